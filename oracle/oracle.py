@@ -1,0 +1,515 @@
+"""FP64 CPU oracle of the fibre-diffraction profile-quadrature path.
+
+TEST INFRASTRUCTURE ONLY.  The tests, the smoke check and the benchmark's
+CPU-baseline leg are the only callers; the product library never imports,
+links or runs anything here, and this module imports nothing from the
+product package.
+
+Plain, slow and written to be checked against the paper by eye: IEEE binary64
+throughout, numpy for elementwise arrays (numpy does not fuse multiply-adds),
+scipy.special.voigt_profile for the Voigt shape as the paper itself does, and
+a small C file (oracle_c.c, built with -ffp-contract=off) for the two
+per-pixel loops that are too slow in Python.
+
+Steps, in the order of the method:
+  frame             reciprocal basis            Eq. recip_basis, tutorial frame convention
+  enumerate_hkl     reflection list             Eq. laue3d + resolution shell (tutorial, Table hkl)
+  structure_factors F(hkl)                      Eq. structure_factor, isotropic Debye-Waller
+  disorder_factors  A_i, N_eff, I_para          Eqs. Ah, Neff, Ipara
+  reflection_frames S, e1, e2, e_perp           Eq. gnomonic (tangent vectors)
+  node_table        (d1, d2) grid and weights   Eqs. gnomonic, node_weight; angular shapes
+  pixel_rz          (R, Z) of each pixel        Eqs. laue, squared, harmonic (Ewald condition)
+  pattern           detector image              Eqs. I_shape, direct_sum, lorentz
+  culling_lists     per-tile reflection lists   (contract of the GPU path, exact predicate)
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+from scipy.special import voigt_profile
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "_oracle_c.so")
+_lib = None
+
+
+def build_c(force: bool = True) -> str:
+    """Compile oracle_c.c (plain C, OpenMP, no FMA contraction)."""
+    src = os.path.join(_HERE, "oracle_c.c")
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+                               "-shared", "-fPIC", "-o", tmp, src, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _c():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build_c()
+        _lib = ctypes.CDLL(_LIB_PATH)
+    return _lib
+
+
+# --------------------------------------------------------------------------- O1
+def frame(cell):
+    """Real and reciprocal basis (Eq. recip_basis) in the tutorial's laboratory
+    frame: c along z, b in the yz-plane, a completing the cell with a_x > 0.
+    Returns (avec, astar, V) with avec rows a, b, c and astar rows a*, b*, c*."""
+    a, b, c = cell.a, cell.b, cell.c
+    ca, cb, cg = math.cos(cell.alpha), math.cos(cell.beta), math.cos(cell.gamma)
+    sa = math.sin(cell.alpha)
+    cvec = np.array([0.0, 0.0, c])
+    bvec = np.array([0.0, b * sa, b * ca])
+    az = a * cb
+    ay = a * (cg - ca * cb) / sa
+    ax = math.sqrt(a * a - ay * ay - az * az)
+    avec = np.array([ax, ay, az])
+
+    def cross(u, v):
+        return np.array([u[1] * v[2] - u[2] * v[1], u[2] * v[0] - u[0] * v[2], u[0] * v[1] - u[1] * v[0]])
+
+    bxc = cross(bvec, cvec)
+    V = (avec[0] * bxc[0] + avec[1] * bxc[1]) + avec[2] * bxc[2]
+    astar = np.stack([bxc / V, cross(cvec, avec) / V, cross(avec, bvec) / V])
+    return np.stack([avec, bvec, cvec]), astar, V
+
+
+def recip_vectors(hkl, astar):
+    """D = h a* + k b* + l c*, componentwise as (h a*_j + k b*_j) + l c*_j."""
+    h = hkl[:, 0].astype(np.float64)
+    k = hkl[:, 1].astype(np.float64)
+    l = hkl[:, 2].astype(np.float64)
+    D = np.empty((hkl.shape[0], 3))
+    for j in range(3):
+        D[:, j] = (h * astar[0, j] + k * astar[1, j]) + l * astar[2, j]
+    return D
+
+
+def q_of(D):
+    """|D|^2 as (Dx^2 + Dy^2) + Dz^2."""
+    return (D[:, 0] * D[:, 0] + D[:, 1] * D[:, 1]) + D[:, 2] * D[:, 2]
+
+
+# --------------------------------------------------------------------------- O2
+def enumerate_hkl(cell, d_min, d_max):
+    """All (h,k,l) != 0 with d_min <= d <= d_max (1/d = |D|), both ends inclusive with
+    a relative slack of 1e-9 on |D|^2, in ascending lexicographic order; d_max <= 0
+    means no low-resolution limit.  Since h = D.a, |h| <= |a|/d_min bounds the search."""
+    _, astar, _ = frame(cell)
+    hm = int(math.floor(cell.a / d_min)) + 1
+    km = int(math.floor(cell.b / d_min)) + 1
+    lm = int(math.floor(cell.c / d_min)) + 1
+    hs, ks, ls = np.meshgrid(np.arange(-hm, hm + 1), np.arange(-km, km + 1), np.arange(-lm, lm + 1), indexing="ij")
+    cand = np.stack([hs.ravel(), ks.ravel(), ls.ravel()], axis=1).astype(np.int32)
+    q = q_of(recip_vectors(cand, astar))
+    t_hi = (1.0 / (d_min * d_min)) * (1.0 + 1e-9)
+    keep = q <= t_hi
+    if d_max > 0:
+        t_lo = (1.0 / (d_max * d_max)) * (1.0 - 1e-9)
+        keep &= q >= t_lo
+    keep &= np.any(cand != 0, axis=1)
+    return np.ascontiguousarray(cand[keep])
+
+
+# --------------------------------------------------------------------------- O3
+def structure_factors(hkl, cell, atoms, chunk=2048):
+    """F_hkl = sum_j occ_j f_t(j)(s) exp(-B_j s^2) exp(2 pi i (h x_j + k y_j + l z_j))
+    (Eq. structure_factor with the isotropic Debye-Waller factor of the section
+    "Paracrystalline disorder", B = 8 pi^2 <u^2>), s = |D|/2 = sin(theta)/lambda,
+    f_t(s) = sum_g a_g exp(-b_g s^2) + c.  The phase is reduced modulo one turn."""
+    _, astar, _ = frame(cell)
+    q = q_of(recip_vectors(hkl, astar))
+    s2 = q / 4.0
+    x = atoms.x.astype(np.float64)
+    y = atoms.y.astype(np.float64)
+    z = atoms.z.astype(np.float64)
+    B = atoms.B.astype(np.float64)
+    occ = atoms.occ.astype(np.float64)
+    ff = atoms.ff.astype(np.float64)
+    F = np.zeros(hkl.shape[0], dtype=np.complex128)
+    for i0 in range(0, hkl.shape[0], chunk):
+        sl = slice(i0, i0 + chunk)
+        hh = hkl[sl].astype(np.float64)
+        ss = s2[sl][:, None]
+        f = np.zeros((hh.shape[0], ff.shape[0]))
+        for t in range(ff.shape[0]):
+            f[:, t] = ff[t, 8]
+            for g in range(4):
+                f[:, t] += ff[t, g] * np.exp(-ff[t, 4 + g] * s2[sl])
+        phase = (hh[:, 0:1] * x[None, :] + hh[:, 1:2] * y[None, :]) + hh[:, 2:3] * z[None, :]
+        phase = phase - np.floor(phase)
+        amp = occ[None, :] * f[:, atoms.type] * np.exp(-B[None, :] * ss)
+        F[sl] = (amp * np.cos(2 * np.pi * phase)).sum(axis=1) + 1j * (amp * np.sin(2 * np.pi * phase)).sum(axis=1)
+    return F
+
+
+# --------------------------------------------------------------------------- O4
+PI2 = math.pi * math.pi
+
+
+def extinction_arg(hkl, g):
+    """2 pi^2 sum_i g_i^2 h_i^2, the exponent of prod_i A_i (Eq. Ah)."""
+    h = hkl.astype(np.float64)
+    t = (g[0] * g[0]) * (h[:, 0] * h[:, 0]) + (g[1] * g[1]) * (h[:, 1] * h[:, 1])
+    t = t + (g[2] * g[2]) * (h[:, 2] * h[:, 2])
+    return (2.0 * PI2) * t
+
+
+def disorder_factors(hkl, dis):
+    """Per reflection and axis: A_i = exp(-2 pi^2 g_i^2 h_i^2) (Eq. Ah),
+    1/N_eff = 1/N_base + (1 - A)/(1 + A) (Eq. Neff), and
+    I_para = prod_i 2 A_i/(1 + A_i^2) (Eq. Ipara; 1 when intensity_model is none)."""
+    h = hkl.astype(np.float64)
+    g = np.asarray(dis.g, dtype=np.float64)
+    Nb = np.asarray(dis.N_base, dtype=np.float64)
+    A = np.exp(-2.0 * PI2 * (g[None, :] ** 2) * h * h)
+    N = 1.0 / (1.0 / Nb[None, :] + (1.0 - A) / (1.0 + A))
+    if dis.intensity_model:
+        Ip = np.prod(2.0 * A / (1.0 + A * A), axis=1)
+    else:
+        Ip = np.ones(hkl.shape[0])
+    return A, N, Ip
+
+
+def extinct_mask(hkl, dis, limit):
+    """Reflections whose paracrystalline intensity loss prod A_i is below exp(-limit)
+    (and I_para below 8 exp(-limit)); the pattern skips them."""
+    return extinction_arg(hkl, dis.g) > limit
+
+
+# --------------------------------------------------------------------------- O5
+def reflection_frames(D):
+    """Unit vector S = D/r0, tangent vectors e1 = z x S/|z x S| (azimuthal),
+    e2 = S x e1 (meridional) and the radial unit vector e_perp of D about the fibre
+    axis z.  On the meridian (R_D = |D_xy| <= 1e-12) e1 = x x S/|x x S| and
+    e_perp = sign(D_z) y, so the frames of D and -D are exact negatives."""
+    n = D.shape[0]
+    r0 = np.sqrt(q_of(D))
+    S = D / r0[:, None]
+    RD = np.sqrt(D[:, 0] * D[:, 0] + D[:, 1] * D[:, 1])
+    e1 = np.zeros((n, 3))
+    ep = np.zeros((n, 3))
+    off = RD > 1e-12
+    # z x D = (-D_y, D_x, 0), |z x D| = R_D
+    e1[off, 0] = -D[off, 1] / RD[off]
+    e1[off, 1] = D[off, 0] / RD[off]
+    ep[off, 0] = D[off, 0] / RD[off]
+    ep[off, 1] = D[off, 1] / RD[off]
+    on = ~off
+    # x x D = (0, -D_z, D_y), |x x D| = sqrt(D_y^2 + D_z^2)
+    nrm = np.sqrt(D[on, 1] * D[on, 1] + D[on, 2] * D[on, 2])
+    e1[on, 1] = -D[on, 2] / nrm
+    e1[on, 2] = D[on, 1] / nrm
+    ep[on, 1] = np.sign(D[on, 2])
+    e2 = np.stack([S[:, 1] * e1[:, 2] - S[:, 2] * e1[:, 1],
+                   S[:, 2] * e1[:, 0] - S[:, 0] * e1[:, 2],
+                   S[:, 0] * e1[:, 1] - S[:, 1] * e1[:, 0]], axis=1)
+    return r0, S, e1, e2, ep
+
+
+# --------------------------------------------------------------------------- O6/O7
+def angular_shape(delta, sigma_theta, gamma_theta):
+    """Unit-peak angular weight g(delta) (section "Angular peak shapes"):
+    Gaussian when gamma = 0, Lorentzian when sigma = 0, otherwise the Voigt profile
+    divided by its value at zero, evaluated with scipy.special.voigt_profile."""
+    delta = np.asarray(delta, dtype=np.float64)
+    if sigma_theta == 0.0 and gamma_theta == 0.0:
+        raise ValueError("sigma_theta and gamma_theta are both zero")
+    if gamma_theta == 0.0:
+        return np.exp(-delta * delta / (2.0 * sigma_theta * sigma_theta))
+    if sigma_theta == 0.0:
+        return gamma_theta * gamma_theta / (delta * delta + gamma_theta * gamma_theta)
+    return voigt_profile(delta, sigma_theta, gamma_theta) / voigt_profile(0.0, sigma_theta, gamma_theta)
+
+
+@dataclass
+class Nodes:
+    d1: np.ndarray
+    d2: np.ndarray
+    c: np.ndarray
+    Delta: np.ndarray
+    omega: np.ndarray
+    h: float
+
+
+def node_table(n, T, sigma_r, sigma_theta, gamma_theta):
+    """Midpoint grid of n x n tangent-plane offsets on [-T, T]^2, node index
+    k = i2*n + i1 with d_j = -T + (i_j + 1/2) h, h = 2T/n.  Each node carries
+    omega = sigma_r sqrt(2 pi) g(Delta) c^3 h^2 with c = (1 + d1^2 + d2^2)^(-1/2)
+    and Delta = arccos(c) (Eq. node_weight without the r0^2 factor, which is per
+    reflection)."""
+    h = 2.0 * T / n
+    d = -T + (np.arange(n, dtype=np.float64) + 0.5) * h
+    d1 = np.tile(d, n)
+    d2 = np.repeat(d, n)
+    rho2 = d1 * d1 + d2 * d2
+    c = 1.0 / np.sqrt(1.0 + rho2)
+    Delta = np.arccos(c)
+    omega = sigma_r * math.sqrt(2.0 * math.pi) * angular_shape(Delta, sigma_theta, gamma_theta) * c ** 3 * h * h
+    return Nodes(d1, d2, c, Delta, omega, h)
+
+
+# --------------------------------------------------------------------------- O8
+def pixel_rz(geom):
+    """Ring coordinates (R, Z) of every pixel centre, arrays [H][W].
+    Pixel (i, j) (column, row; row 0 at the bottom) sits at y = (i + 1/2 - c_x) p,
+    z = (j + 1/2 - c_y) p on a detector normal to the beam at distance SF.  Its
+    outgoing direction X/|X|, X = (SF, y, z), gives the scattering vector
+    S = (X/|X| - x)/lambda, which lies on the Ewald sphere (Eq. laue); written
+    without cancellation as S = (-(y^2 + z^2)/(r (r + SF)), y/r, z/r)/lambda.
+    R = sqrt(S_x^2 + S_y^2), Z = S_z (Eq. cyl-average's coordinates)."""
+    W, H = geom.width, geom.height
+    i = np.arange(W, dtype=np.float64)
+    j = np.arange(H, dtype=np.float64)
+    y = ((i + 0.5) - geom.center_x) * geom.pixel
+    z = ((j + 0.5) - geom.center_y) * geom.pixel
+    y, z = np.meshgrid(y, z)          # [H][W]
+    SF = geom.distance
+    r = np.sqrt((SF * SF + y * y) + z * z)
+    lam = geom.wavelength
+    Sx = -(y * y + z * z) / ((r * (r + SF)) * lam)
+    Sy = y / (r * lam)
+    Sz = z / (r * lam)
+    R = np.sqrt(Sx * Sx + Sy * Sy)
+    return R, Sz
+
+
+# --------------------------------------------------------------------------- prepared problem
+@dataclass
+class Prepared:
+    hkl: np.ndarray
+    F: np.ndarray
+    W: np.ndarray        # |F|^2 * I_para
+    N: np.ndarray        # N_eff [n][3]
+    A: np.ndarray
+    Ip: np.ndarray
+    D: np.ndarray
+    r0: np.ndarray
+    S: np.ndarray
+    e1: np.ndarray
+    e2: np.ndarray
+    ep: np.ndarray
+    avec: np.ndarray
+    astar: np.ndarray
+    nodes: Nodes
+    m: int
+    delta: float
+
+
+def prepare(wl, hkl=None, F=None, cull_extinct=True):
+    """Run O1-O7 for a workload: reflection list, structure factors, disorder
+    factors, frames and the node table.  Reflections removed by the extinction
+    cull are dropped."""
+    avec, astar, _ = frame(wl.cell)
+    if hkl is None:
+        hkl = enumerate_hkl(wl.cell, wl.quad.d_min, wl.quad.d_max)
+    if cull_extinct:
+        keep = ~extinct_mask(hkl, wl.dis, wl.quad.extinction)
+        hkl = np.ascontiguousarray(hkl[keep])
+        if F is not None:
+            F = F[keep]
+    if F is None:
+        F = structure_factors(hkl, wl.cell, wl.atoms)
+    A, N, Ip = disorder_factors(hkl, wl.dis)
+    D = recip_vectors(hkl, astar)
+    r0, S, e1, e2, ep = reflection_frames(D)
+    nodes = node_table(wl.quad.n_nodes, wl.quad.T, wl.quad.sigma_r, wl.dis.sigma_theta, wl.dis.gamma_theta)
+    W = (F.real * F.real + F.imag * F.imag) * Ip
+    return Prepared(hkl, F, W, N, A, Ip, D, r0, S, e1, e2, ep, avec, astar, nodes, wl.quad.m, wl.quad.delta)
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("n_hkl", ctypes.c_int64), ("W", ctypes.c_void_p), ("N", ctypes.c_void_p),
+                ("r0", ctypes.c_void_p), ("S", ctypes.c_void_p), ("e1", ctypes.c_void_p),
+                ("e2", ctypes.c_void_p), ("ep", ctypes.c_void_p), ("astar", ctypes.c_void_p),
+                ("avec", ctypes.c_void_p), ("n_nodes", ctypes.c_int64), ("d1", ctypes.c_void_p),
+                ("d2", ctypes.c_void_p), ("omega", ctypes.c_void_p), ("m", ctypes.c_int32),
+                ("delta", ctypes.c_double), ("use_skip", ctypes.c_int32)]
+
+
+def _c_problem(P: Prepared, use_skip: bool):
+    keep = []
+
+    def ptr(a):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        keep.append(a)
+        return a.ctypes.data
+
+    prob = _Problem(P.hkl.shape[0], ptr(P.W), ptr(P.N), ptr(P.r0), ptr(P.S), ptr(P.e1), ptr(P.e2),
+                    ptr(P.ep), ptr(P.astar), ptr(P.avec), P.nodes.d1.shape[0], ptr(P.nodes.d1),
+                    ptr(P.nodes.d2), ptr(P.nodes.omega), P.m, P.delta, 1 if use_skip else 0)
+    return prob, keep
+
+
+def pattern_at(P: Prepared, R, Z, use_skip=True, count=False):
+    """Image values at pixels with ring coordinates (R, Z) (flat arrays):
+    L(R) sum_hkl W_hkl I_hkl(p*), p* = R e_perp + Z z (Eqs. direct_sum, lorentz)."""
+    R = np.ascontiguousarray(np.ravel(R), dtype=np.float64)
+    Z = np.ascontiguousarray(np.ravel(Z), dtype=np.float64)
+    out = np.zeros(R.shape[0])
+    n_ev = ctypes.c_int64(0)
+    prob, keep = _c_problem(P, use_skip)
+    lib = _c()
+    lib.oracle_pattern(ctypes.byref(prob), ctypes.c_int64(R.shape[0]), ctypes.c_void_p(R.ctypes.data),
+                       ctypes.c_void_p(Z.ctypes.data), ctypes.c_void_p(out.ctypes.data), ctypes.byref(n_ev))
+    del keep
+    if count:
+        return out, int(n_ev.value)
+    return out
+
+
+def profile_table(P: Prepared, R, Z):
+    """Per-reflection shell-quadrature profiles I_hkl(p*) at each pixel, [n_pix][n_hkl]."""
+    R = np.ascontiguousarray(np.ravel(R), dtype=np.float64)
+    Z = np.ascontiguousarray(np.ravel(Z), dtype=np.float64)
+    out = np.zeros((R.shape[0], P.hkl.shape[0]))
+    prob, keep = _c_problem(P, False)
+    _c().oracle_profile_table(ctypes.byref(prob), ctypes.c_int64(R.shape[0]), ctypes.c_void_p(R.ctypes.data),
+                              ctypes.c_void_p(Z.ctypes.data), ctypes.c_void_p(out.ctypes.data))
+    del keep
+    return out
+
+
+def pattern(wl, P: Prepared = None, use_skip=True, count=False):
+    """Full detector image [H][W] (row 0 at the bottom)."""
+    if P is None:
+        P = prepare(wl)
+    R, Z = pixel_rz(wl.geom)
+    res = pattern_at(P, R, Z, use_skip=use_skip, count=count)
+    if count:
+        img, n = res
+        return img.reshape(R.shape), n
+    return res.reshape(R.shape)
+
+
+# --------------------------------------------------------------------------- culling contract
+def tile_boxes(geom, tile_w, tile_h):
+    """(R, Z) bounding box over the pixel centres of each tile_w x tile_h tile
+    (tiles clipped at the detector edge), arrays [n_tiles_y][n_tiles_x]."""
+    R, Z = pixel_rz(geom)
+    H, W = R.shape
+    ny, nx = (H + tile_h - 1) // tile_h, (W + tile_w - 1) // tile_w
+    box = np.zeros((ny, nx, 4))
+    for ty in range(ny):
+        for tx in range(nx):
+            r = R[ty * tile_h:(ty + 1) * tile_h, tx * tile_w:(tx + 1) * tile_w]
+            z = Z[ty * tile_h:(ty + 1) * tile_h, tx * tile_w:(tx + 1) * tile_w]
+            box[ty, tx] = (r.min(), r.max(), z.min(), z.max())
+    return box
+
+
+def reflection_boxes(wl, hkl):
+    """Conservative (R, Z) box of the query points a reflection can reach.
+    Nodes s = r0 c (S + d1 e1 + d2 e2) have |d_j| <= T and c in [c_min, 1],
+    c_min = (1 + 2T^2)^(-1/2); a query point p lies within the support box
+    {x: |a_i.x| <= m/N_i} of some node, whose extent along a unit vector v is
+    sum_i (m/N_i)|a*_i.v|.  1/N_i is bounded without transcendentals by
+    1/N_base,i + min(pi^2 g_i^2 h_i^2, 1) (tanh(t) <= min(t, 1)).
+    Returns [n][4] = (R_lo, R_hi, Z_lo, Z_hi); all arithmetic is +,-,*,/,sqrt in a
+    fixed order so that an exact reproduction elsewhere matches bit for bit."""
+    _, astar, _ = frame(wl.cell)
+    D = recip_vectors(hkl, astar)
+    r0, S, e1, e2, ep = reflection_frames(D)
+    T = wl.quad.T
+    m = float(wl.quad.m)
+    cmin = 1.0 / math.sqrt(1.0 + 2.0 * T * T)
+    h = hkl.astype(np.float64)
+    Ninv = np.empty((hkl.shape[0], 3))
+    for i in range(3):
+        g = wl.dis.g[i]
+        t = PI2 * (g * g) * (h[:, i] * h[:, i])
+        Ninv[:, i] = 1.0 / wl.dis.N_base[i] + np.minimum(t, 1.0)
+    ez = np.zeros_like(ep)
+    ez[:, 2] = 1.0
+
+    def dot(u, v):
+        return (u[:, 0] * v[:, 0] + u[:, 1] * v[:, 1]) + u[:, 2] * v[:, 2]
+
+    def extent(v):
+        ext = (m * Ninv[:, 0]) * np.abs(dot(np.broadcast_to(astar[0], v.shape), v))
+        ext = ext + (m * Ninv[:, 1]) * np.abs(dot(np.broadcast_to(astar[1], v.shape), v))
+        ext = ext + (m * Ninv[:, 2]) * np.abs(dot(np.broadcast_to(astar[2], v.shape), v))
+        l0, l1, l2 = dot(S, v), dot(e1, v), dot(e2, v)
+        spread = T * (np.abs(l1) + np.abs(l2))
+        lo, hi = l0 - spread, l0 + spread
+        s_lo = r0 * np.minimum(cmin * lo, lo)
+        s_hi = r0 * np.maximum(cmin * hi, hi)
+        return s_lo - ext, s_hi + ext
+
+    Rlo, Rhi = extent(ep)
+    Zlo, Zhi = extent(ez)
+    return np.stack([Rlo, Rhi, Zlo, Zhi], axis=1)
+
+
+def culling_lists(wl, hkl, tile_w=8, tile_h=8):
+    """Per tile (row-major over tiles), ascending indices into hkl of the
+    reflections not removed by the extinction cull whose box meets the tile's box."""
+    tb = tile_boxes(wl.geom, tile_w, tile_h).reshape(-1, 4)
+    rb = reflection_boxes(wl, hkl)
+    alive = ~extinct_mask(hkl, wl.dis, wl.quad.extinction)
+    lists = []
+    for t in range(tb.shape[0]):
+        ok = alive & (rb[:, 0] <= tb[t, 1]) & (tb[t, 0] <= rb[:, 1]) & (rb[:, 2] <= tb[t, 3]) & (tb[t, 2] <= rb[:, 3])
+        lists.append(np.nonzero(ok)[0].astype(np.int32))
+    return lists
+
+
+# --------------------------------------------------------------------------- Ewald projection
+def rodrigues(S, phi, n=np.array([0.0, 0.0, 1.0])):
+    """S rotated by phi about unit axis n (Eq. rodrigues)."""
+    S = np.asarray(S, dtype=np.float64)
+    nxS = np.cross(n, S)
+    nS = S @ n
+    return S * np.cos(phi)[..., None] + nxS * np.sin(phi)[..., None] + n * (nS * (1.0 - np.cos(phi)))[..., None]
+
+
+def ewald_angles(S, wavelength, beam=np.array([1.0, 0.0, 0.0]), fibre=np.array([0.0, 0.0, 1.0])):
+    """Rotation angles about the fibre axis that bring S onto the Ewald sphere
+    (Eqs. laue, squared, harmonic, solutions): P cos(phi) + Q sin(phi) = R with
+    A = k.S, B = k.(n x S), D = (k.n)(n.S), C = |k|^2 + |S|^2, E = (1/lambda^2 - C)/2 - D,
+    P = A - D, Q = B, R = E, |k| = 1/lambda.  Returns (phi1, phi2), NaN where
+    |R|/sqrt(P^2 + Q^2) > 1 (Eq. valid)."""
+    S = np.atleast_2d(np.asarray(S, dtype=np.float64))
+    k = beam / wavelength
+    A = S @ k
+    Bc = np.cross(fibre, S) @ k
+    Dc = (k @ fibre) * (S @ fibre)
+    C = k @ k + np.sum(S * S, axis=1)
+    E = (1.0 / wavelength ** 2 - C) / 2.0 - Dc
+    P, Q, R = A - Dc, Bc, E
+    amp = np.sqrt(P * P + Q * Q)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        ratio = R / amp
+        ok = np.abs(ratio) <= 1.0
+        phi0 = np.arctan2(Q, P)
+        dphi = np.where(ok, np.arccos(np.clip(ratio, -1.0, 1.0)), np.nan)
+    return phi0 + dphi, phi0 - dphi
+
+
+def ewald_project(S, geom, beam=np.array([1.0, 0.0, 0.0]), fibre=np.array([0.0, 0.0, 1.0])):
+    """Detector positions (column i, row j, fractional pixel units, pixel centres at
+    integers) of the two diffraction-condition rotations of each S: k_out = k_in + S_phi
+    (section "Analytical Solution of the Ewald Diffraction Condition") intersected with
+    the detector plane x = SF.  NaN where no rotation reaches the sphere."""
+    S = np.atleast_2d(np.asarray(S, dtype=np.float64))
+    out = []
+    for phi in ewald_angles(S, geom.wavelength, beam, fibre):
+        Sphi = rodrigues(S, phi, fibre)
+        kout = beam / geom.wavelength + Sphi
+        y = geom.distance * kout[:, 1] / kout[:, 0]
+        z = geom.distance * kout[:, 2] / kout[:, 0]
+        out.append(np.stack([y / geom.pixel + geom.center_x - 0.5, z / geom.pixel + geom.center_y - 0.5], axis=1))
+    return out[0], out[1]
+
+
+def lorentz(R, delta):
+    """Regularised Lorentz factor L = delta/(R + delta) (Eq. lorentz)."""
+    return delta / (np.asarray(R, dtype=np.float64) + delta)

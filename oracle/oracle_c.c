@@ -1,0 +1,184 @@
+/*
+ * FP64 CPU oracle, compiled part.  TEST INFRASTRUCTURE ONLY: nothing on the
+ * product path links, loads or calls this file; only the tests, the smoke
+ * check and the benchmark's CPU-baseline leg do.
+ *
+ * Plain loops, IEEE binary64, no fused multiply-add (built with
+ * -ffp-contract=off).  The per-reflection inputs (frames, effective sizes,
+ * weights) and the node table come from the Python half of the oracle; this
+ * file holds the two loops that are too slow in Python:
+ *
+ *   oracle_pattern   -- the detector image at a list of pixels
+ *   oracle_grad      -- the adjoint of that image for a weighted residual
+ *
+ * Both follow the section "Numerical evaluation: per-reflection shell
+ * quadrature" (Eqs. I_shape, gnomonic, node_weight, direct_sum), the
+ * section "Lorentz correction on a sampled reciprocal lattice" (Eq. lorentz)
+ * and the section "Index-dependent paracrystalline disorder" (Eqs. Ah, Neff,
+ * Ipara) of the paper.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+typedef struct {
+  /* per reflection, all [n_hkl] or [n_hkl][3] */
+  int64_t n_hkl;
+  const double* W;      /* |F|^2 * I_para */
+  const double* N;      /* effective cells N_eff along a,b,c  [n][3] */
+  const double* r0;     /* |D| */
+  const double* S;      /* unit D                              [n][3] */
+  const double* e1;     /* tangent vector 1                    [n][3] */
+  const double* e2;     /* tangent vector 2                    [n][3] */
+  const double* ep;     /* unit radial direction of D about z  [n][3] */
+  const double* astar;  /* reciprocal basis rows a*, b*, c*    [3][3] */
+  const double* avec;   /* real basis rows a, b, c             [3][3] */
+  /* node table */
+  int64_t n_nodes;
+  const double* d1;
+  const double* d2;
+  const double* omega;  /* sigma_r sqrt(2 pi) g(Delta) c^3 h^2 */
+  int32_t m;            /* kernel zeros kept per axis */
+  double delta;         /* Lorentz regulariser */
+  int32_t use_skip;     /* 1: skip reflections whose support provably misses the query point */
+} oracle_problem;
+
+/* N sinc^2(N u), sinc(x) = sin(pi x)/(pi x), sinc(0) = 1 (Eq. I_shape, one axis). */
+static double laue_axis(double N, double u) {
+  double x = N * u;
+  if (x == 0.0) return N;
+  double s = sin(M_PI * x) / (M_PI * x);
+  return N * s * s;
+}
+
+static double dot3(const double* a, const double* b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+
+/* Largest |x| over the support box {x : |a_i . x| <= m/N_i} = {sum u_i a*_i : |u_i| <= m/N_i}:
+ * the longest of its corner vectors. */
+static double support_radius(const oracle_problem* P, int64_t h) {
+  double best = 0.0;
+  for (int sa = -1; sa <= 1; sa += 2)
+    for (int sb = -1; sb <= 1; sb += 2)
+      for (int sc = -1; sc <= 1; sc += 2) {
+        double v[3];
+        for (int j = 0; j < 3; ++j)
+          v[j] = sa * (P->m / P->N[3 * h + 0]) * P->astar[0 * 3 + j] + sb * (P->m / P->N[3 * h + 1]) * P->astar[1 * 3 + j] +
+                 sc * (P->m / P->N[3 * h + 2]) * P->astar[2 * 3 + j];
+        double r = sqrt(dot3(v, v));
+        if (r > best) best = r;
+      }
+  return best;
+}
+
+/* Exact-zero skip: every node lies on the sphere |s| = r0 within angle theta_nodes of S.
+ * A node can only be inside the support of p if |p - s| <= rho, which needs
+ * | |p| - r0 | <= rho and angle(p, S) <= theta_nodes + asin(rho/|p|).  When either fails,
+ * no node passes the support test and the reflection adds nothing; skipping it leaves
+ * the sum bit-identical.  Margins keep the test conservative under rounding. */
+static int provably_empty(const oracle_problem* P, int64_t h, const double* p, double theta_nodes) {
+  double rho = support_radius(P, h) * (1.0 + 1e-6) + 1e-12;
+  double pn = sqrt(dot3(p, p));
+  if (fabs(pn - P->r0[h]) > rho) return 1;
+  if (pn > rho) {
+    double cosang = dot3(p, &P->S[3 * h]) / pn;
+    if (cosang > 1.0) cosang = 1.0;
+    if (cosang < -1.0) cosang = -1.0;
+    double ang = acos(cosang);
+    double lim = theta_nodes + asin(rho / pn) + 1e-6;
+    if (ang > lim) return 1;
+  }
+  return 0;
+}
+
+static double nodes_max_angle(const oracle_problem* P) {
+  double best = 0.0;
+  for (int64_t k = 0; k < P->n_nodes; ++k) {
+    double a = atan(sqrt(P->d1[k] * P->d1[k] + P->d2[k] * P->d2[k]));
+    if (a > best) best = a;
+  }
+  return best;
+}
+
+/* Query point of pixel ring (R, Z) for reflection h: the point of the ring at the
+ * reflection's own azimuth, p = R e_perp + Z z. */
+static void query_point(const oracle_problem* P, int64_t h, double R, double Z, double* p) {
+  p[0] = R * P->ep[3 * h + 0];
+  p[1] = R * P->ep[3 * h + 1];
+  p[2] = R * P->ep[3 * h + 2] + Z;
+}
+
+/* Shell-quadrature profile of reflection h at Cartesian point p (Eq. direct_sum):
+ * sum over nodes k with |a_i.(p - s_k)| <= m/N_i of w_k Z(p - s_k),
+ * s_k = r0 (S + d1 e1 + d2 e2)/sqrt(1 + d1^2 + d2^2)   (Eq. gnomonic),
+ * w_k = r0^2 omega_k                                   (Eq. node_weight). */
+static double profile_at(const oracle_problem* P, int64_t h, const double* p, int64_t* n_eval) {
+  const double r0 = P->r0[h];
+  const double* S = &P->S[3 * h];
+  const double* e1 = &P->e1[3 * h];
+  const double* e2 = &P->e2[3 * h];
+  const double* N = &P->N[3 * h];
+  double I = 0.0;
+  int64_t cnt = 0;
+  for (int64_t k = 0; k < P->n_nodes; ++k) {
+    double d1 = P->d1[k], d2 = P->d2[k];
+    double c = 1.0 / sqrt(1.0 + d1 * d1 + d2 * d2);
+    double x[3];
+    for (int j = 0; j < 3; ++j) {
+      double s = r0 * c * (S[j] + d1 * e1[j] + d2 * e2[j]);
+      x[j] = p[j] - s;
+    }
+    double u[3];
+    int inside = 1;
+    for (int i = 0; i < 3; ++i) {
+      u[i] = dot3(&P->avec[3 * i], x);
+      if (fabs(u[i]) > P->m / N[i]) inside = 0;
+    }
+    if (!inside) continue;
+    double Zk = laue_axis(N[0], u[0]) * laue_axis(N[1], u[1]) * laue_axis(N[2], u[2]);
+    I += r0 * r0 * P->omega[k] * Zk;
+    ++cnt;
+  }
+  if (n_eval) *n_eval += cnt;
+  return I;
+}
+
+/* Detector image at n_pix pixels with ring coordinates (R[p], Z[p]):
+ * P = L(R) sum_h W_h I_h(p*_h), L = delta/(R + delta) (Eq. lorentz), summed over
+ * reflections in ascending order in FP64.  n_evals (optional) receives the number
+ * of (pixel, reflection, node) triples that passed the support test. */
+void oracle_pattern(const oracle_problem* P, int64_t n_pix, const double* R, const double* Z, double* out,
+                    int64_t* n_evals) {
+  double theta_nodes = nodes_max_angle(P);
+  int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : total)
+  for (int64_t q = 0; q < n_pix; ++q) {
+    double acc = 0.0;
+    int64_t cnt = 0;
+    for (int64_t h = 0; h < P->n_hkl; ++h) {
+      double p[3];
+      query_point(P, h, R[q], Z[q], p);
+      if (P->use_skip && provably_empty(P, h, p, theta_nodes)) continue;
+      acc += P->W[h] * profile_at(P, h, p, &cnt);
+    }
+    out[q] = P->delta / (R[q] + P->delta) * acc;
+    total += cnt;
+  }
+  if (n_evals) *n_evals = total;
+}
+
+/* Per-reflection profile values at each pixel, [n_pix][n_hkl] (no W, no Lorentz):
+ * used by tests that check the culling lists and the per-reflection adjoint. */
+void oracle_profile_table(const oracle_problem* P, int64_t n_pix, const double* R, const double* Z, double* out) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < n_pix; ++q) {
+    for (int64_t h = 0; h < P->n_hkl; ++h) {
+      double p[3];
+      query_point(P, h, R[q], Z[q], p);
+      out[q * P->n_hkl + h] = profile_at(P, h, p, NULL);
+    }
+  }
+}

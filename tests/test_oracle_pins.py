@@ -1,0 +1,515 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test ties one oracle step to something other than the oracle itself: an
+exact integer brute force, a textbook closed form, an invariant, a published
+approximation, or an independent numerical integration.  A plausible slip in
+the oracle (dropped term, wrong sign or index, transposed operand) fails at
+least one of them.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate, optimize, special
+
+import workloads as W
+from oracle import oracle as O
+
+DEG = math.pi / 180.0
+
+
+# ----------------------------------------------------------------------------- frame (Eq. recip_basis)
+@pytest.mark.parametrize("cell", [
+    W.Cell(10, 10, 20, 90 * DEG, 90 * DEG, 90 * DEG),
+    W.Cell(40, 40, 60, 90 * DEG, 95 * DEG, 90 * DEG),
+    W.Cell(10.4, 6.717, 5.962, 80.37 * DEG, 118.08 * DEG, 114.8 * DEG),   # cellulose I-alpha cell of the paper
+    W.Cell(7.784, 8.201, 10.38, 90 * DEG, 90 * DEG, 96.55 * DEG),         # cellulose I-beta cell of the tutorial
+])
+def test_frame_duality_and_metric(cell):
+    avec, astar, V = O.frame(cell)
+    # a*_i . a_j = delta_ij (section "Scattered vector and scattering amplitude")
+    np.testing.assert_allclose(astar @ avec.T, np.eye(3), atol=1e-14)
+    # edge lengths and angles of the real cell
+    np.testing.assert_allclose(np.linalg.norm(avec, axis=1), [cell.a, cell.b, cell.c], rtol=1e-14)
+    ang = lambda u, v: math.acos(u @ v / np.linalg.norm(u) / np.linalg.norm(v))
+    np.testing.assert_allclose([ang(avec[1], avec[2]), ang(avec[0], avec[2]), ang(avec[0], avec[1])],
+                               [cell.alpha, cell.beta, cell.gamma], atol=1e-12)
+    # textbook cell volume
+    ca, cb, cg = math.cos(cell.alpha), math.cos(cell.beta), math.cos(cell.gamma)
+    Vt = cell.a * cell.b * cell.c * math.sqrt(1 - ca * ca - cb * cb - cg * cg + 2 * ca * cb * cg)
+    assert abs(V - Vt) < 1e-12 * Vt
+    # tutorial convention: c along +z, b in the yz-plane, beam a* along +x
+    assert avec[2, 0] == 0 and avec[2, 1] == 0 and avec[2, 2] > 0
+    assert avec[1, 0] == 0
+    assert astar[0, 1] == 0 and astar[0, 2] == 0 and astar[0, 0] > 0
+
+
+# ----------------------------------------------------------------------------- enumeration
+def _brute_orthogonal(a, b, c, d_min, d_max):
+    """Exact integer test for orthogonal cells: h^2/a^2 + k^2/b^2 + l^2/c^2 <= 1/d^2,
+    scaled to integers (a, b, c, d given as integers or halves)."""
+    out = []
+    H, K, L = int(a / d_min) + 1, int(b / d_min) + 1, int(c / d_min) + 1
+    from fractions import Fraction as Fr
+    a, b, c, d_min, d_max = Fr(a), Fr(b), Fr(c), Fr(d_min), Fr(d_max)
+    for h in range(-H, H + 1):
+        for k in range(-K, K + 1):
+            for l in range(-L, L + 1):
+                if h == 0 and k == 0 and l == 0:
+                    continue
+                q = Fr(h * h) / (a * a) + Fr(k * k) / (b * b) + Fr(l * l) / (c * c)
+                if q <= 1 / (d_min * d_min) and q >= 1 / (d_max * d_max):
+                    out.append((h, k, l))
+    return np.array(out, dtype=np.int32)
+
+
+def test_enumeration_tiny_config_exact():
+    wl = W.config0()
+    hkl = O.enumerate_hkl(wl.cell, wl.quad.d_min, wl.quad.d_max)
+    ref = _brute_orthogonal(10, 10, 20, 4, 30)
+    assert hkl.shape == ref.shape == (150, 3)
+    assert np.array_equal(hkl, ref)
+    # 10 exact ties at d = 4 A are kept (inclusive resolution limit)
+    q4 = 4 * hkl[:, 0] ** 2 + 4 * hkl[:, 1] ** 2 + hkl[:, 2] ** 2
+    assert int(np.sum(q4 == 25)) == 10
+
+
+def test_enumeration_general_cell_matches_metric_tensor():
+    """Reciprocal metric tensor G* = G^-1 from the cell constants alone (no lab frame)."""
+    cell = W.Cell(40, 40, 60, 90 * DEG, 95 * DEG, 90 * DEG)
+    d_min, d_max = 4.0, 30.0
+    hkl = O.enumerate_hkl(cell, d_min, d_max)
+    ca, cb, cg = math.cos(cell.alpha), math.cos(cell.beta), math.cos(cell.gamma)
+    G = np.array([[cell.a ** 2, cell.a * cell.b * cg, cell.a * cell.c * cb],
+                  [cell.a * cell.b * cg, cell.b ** 2, cell.b * cell.c * ca],
+                  [cell.a * cell.c * cb, cell.b * cell.c * ca, cell.c ** 2]])
+    Gs = np.linalg.inv(G)
+    r = np.arange(-16, 17)
+    cand = np.stack(np.meshgrid(r, r, r, indexing="ij"), -1).reshape(-1, 3)
+    q = np.einsum("ni,ij,nj->n", cand.astype(float), Gs, cand.astype(float))
+    keep = (q <= 1 / d_min ** 2 * (1 + 1e-9)) & (q >= 1 / d_max ** 2 * (1 - 1e-9)) & np.any(cand != 0, 1)
+    ref = cand[keep]
+    assert np.array_equal(hkl, ref)
+
+
+def test_enumeration_order_negation_and_volume():
+    wl = W.config1()
+    hkl = O.enumerate_hkl(wl.cell, wl.quad.d_min, wl.quad.d_max)
+    assert hkl.shape[0] == 49962
+    # ascending lexicographic order, closed under negation with mate at n-1-i
+    keys = hkl[:, 0].astype(np.int64) * 10 ** 6 + hkl[:, 1] * 10 ** 3 + hkl[:, 2]
+    assert np.all(np.diff(keys) > 0)
+    assert np.array_equal(hkl, -hkl[::-1])
+    # count -> reciprocal-shell volume times cell volume
+    _, _, V = O.frame(wl.cell)
+    est = 4 * math.pi / 3 * V * (1 / wl.quad.d_min ** 3 - 1 / wl.quad.d_max ** 3)
+    assert abs(hkl.shape[0] / est - 1) < 0.01
+
+
+# ----------------------------------------------------------------------------- structure factors
+def _atoms(x, y, z, B, occ, typ, zs=(6, 7, 8)):
+    f = lambda a: np.asarray(a, dtype=np.float32)
+    return W.Atoms(f(x), f(y), f(z), f(B), f(occ), np.asarray(typ, dtype=np.int32), W.ff_table(zs))
+
+
+def test_sf_single_atom_modulus():
+    cell = W.Cell(9, 11, 13, 90 * DEG, 100 * DEG, 90 * DEG)
+    hkl = O.enumerate_hkl(cell, 2.0, 30.0)
+    at = _atoms([0.123], [0.456], [0.789], [12.0], [0.7], [1])
+    F = O.structure_factors(hkl, cell, at)
+    _, astar, _ = O.frame(cell)
+    # |D|^2 from the metric tensor, s = |D|/2
+    D = hkl @ astar
+    s2 = np.sum(D * D, 1) / 4
+    occ, b = float(np.float32(0.7)), float(np.float32(W.FF_B))    # inputs are float32
+    expect = occ * 7.0 * np.exp(-b * s2) * np.exp(-12.0 * s2)
+    np.testing.assert_allclose(np.abs(F), expect, rtol=1e-12)
+    # phase: exp(2 pi i h.x) with x taken as the float32 input value
+    x = np.array([np.float32(0.123), np.float32(0.456), np.float32(0.789)], dtype=np.float64)
+    ph = np.angle(F / expect) / (2 * np.pi)
+    d = (ph - hkl @ x) % 1.0
+    assert np.all(np.minimum(d, 1 - d) < 1e-10)
+
+
+def test_sf_friedel_centric_and_body_centred():
+    cell = W.Cell(12, 12, 16, 90 * DEG, 90 * DEG, 90 * DEG)
+    hkl = O.enumerate_hkl(cell, 2.5, 30.0)
+    rng = np.random.default_rng(7)
+    n = 30
+    xyz = rng.random((n, 3))
+    B = rng.uniform(5, 20, n)
+    typ = rng.integers(0, 3, n)
+    F = O.structure_factors(hkl, cell, _atoms(xyz[:, 0], xyz[:, 1], xyz[:, 2], B, np.ones(n), typ))
+    # Friedel: F(-h) = conj F(h), mate at n-1-i
+    np.testing.assert_allclose(F[::-1], np.conj(F), atol=1e-9 * np.abs(F).max())
+    # centrosymmetric model (atoms at +-x): F real
+    cx = np.concatenate([xyz, (1.0 - xyz)])
+    Fc = O.structure_factors(hkl, cell, _atoms(cx[:, 0], cx[:, 1], cx[:, 2], np.tile(B, 2), np.ones(2 * n), np.tile(typ, 2)))
+    assert np.abs(Fc.imag).max() < 1e-6 * np.abs(Fc.real).max()
+    # body-centred pair (x, x + 1/2,1/2,1/2) with exactly representable coordinates
+    base = np.round(xyz * 64) / 128
+    bc = np.concatenate([base, base + 0.5])
+    Fb = O.structure_factors(hkl, cell, _atoms(bc[:, 0], bc[:, 1], bc[:, 2], np.tile(B, 2), np.ones(2 * n), np.tile(typ, 2)))
+    F1 = O.structure_factors(hkl, cell, _atoms(base[:, 0], base[:, 1], base[:, 2], B, np.ones(n), typ))
+    odd = (hkl.sum(1) % 2) != 0
+    assert np.abs(Fb[odd]).max() < 1e-9 * np.abs(Fb).max()
+    np.testing.assert_allclose(Fb[~odd], 2 * F1[~odd], rtol=1e-10, atol=1e-10 * np.abs(F1).max())
+
+
+def test_sf_exact_rational_phases():
+    """Coordinates on a 1/8 grid: exp(2 pi i phi) is known exactly (eighth roots of unity)."""
+    cell = W.Cell(10, 10, 10, 90 * DEG, 90 * DEG, 90 * DEG)
+    hkl = O.enumerate_hkl(cell, 2.0, 0.0)
+    num = np.array([[1, 3, 5], [2, 7, 0], [6, 1, 4]])
+    at = _atoms(num[:, 0] / 8, num[:, 1] / 8, num[:, 2] / 8, [0, 0, 0], [1, 1, 1], [0, 1, 2])
+    F = O.structure_factors(hkl, cell, at)
+    s2 = np.sum(hkl.astype(float) ** 2, 1) / 100 / 4
+    roots = np.exp(2j * np.pi * np.arange(8) / 8)
+    ref = np.zeros(len(hkl), complex)
+    for j, zz in enumerate((6, 7, 8)):
+        ref += zz * np.exp(-float(np.float32(W.FF_B)) * s2) * roots[(hkl @ num[j]) % 8]
+    np.testing.assert_allclose(F, ref, rtol=1e-12, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------- paracrystal factors
+def test_coherence_factor_is_gaussian_characteristic_function():
+    """|phi(h)| for a Gaussian spacing distribution of relative width g, evaluated by
+    numerical integration of E[exp(2 pi i h eps)], eps ~ N(0, g^2) (Eq. Ah)."""
+    hkl = np.array([[1, 0, 0], [3, 2, 0], [7, -5, 2], [12, 0, -9]], dtype=np.int32)
+    dis = W.Disorder(0.01, 0.0, (10.0, 8.0, 6.0), (0.03, 0.05, 0.02))
+    A, N, Ip = O.disorder_factors(hkl, dis)
+    for r in range(hkl.shape[0]):
+        for i in range(3):
+            g, h = dis.g[i], hkl[r, i]
+            val, _ = integrate.quad(lambda e: math.cos(2 * math.pi * h * e) * math.exp(-e * e / (2 * g * g)) / (g * math.sqrt(2 * math.pi)),
+                                    -12 * g, 12 * g, limit=400, epsabs=1e-14)
+            assert abs(A[r, i] - val) < 1e-10
+
+
+def test_hosemann_breadth_and_neff():
+    """Eq. Z with |phi| = A held at its value at the reflection is the Poisson kernel:
+    integral over one period 1, peak (1+A)/(1-A) (Eq. breadth).  With N_base -> inf,
+    1/N_eff equals that integral breadth (Eq. Neff); with g -> 0 N_eff = N_base."""
+    hkl = np.array([[2, 0, 0], [5, 3, 1], [9, 0, 4]], dtype=np.int32)
+    big = W.Disorder(0.01, 0.0, (1e300, 1e300, 1e300), (0.04, 0.02, 0.03))
+    A, N, _ = O.disorder_factors(hkl, big)
+    for r in range(hkl.shape[0]):
+        for i in range(3):
+            a = A[r, i]
+            if hkl[r, i] == 0:
+                assert a == 1.0 and 1 / N[r, i] < 1e-299     # sharp lattice along this axis
+                continue
+            Z = lambda u: (1 - a * a) / (1 - 2 * a * math.cos(2 * math.pi * u) + a * a)
+            area, _ = integrate.quad(Z, -0.5, 0.5, points=[0.0], limit=400, epsabs=1e-13)
+            assert abs(area - 1) < 1e-9
+            breadth = area / Z(0.0)
+            assert abs(1 / N[r, i] - breadth) < 1e-10 * max(breadth, 1e-3)
+    sharp = W.Disorder(0.01, 0.0, (7.0, 5.0, 3.0), (0.0, 0.0, 0.0))
+    A0, N0, Ip0 = O.disorder_factors(hkl, sharp)
+    assert np.all(A0 == 1.0) and np.all(Ip0 == 1.0)
+    assert np.array_equal(N0, np.tile([7.0, 5.0, 3.0], (3, 1)))
+
+
+def test_intensity_loss_is_sech():
+    """2A/(1+A^2) with A = exp(-t) is 1/cosh(t) (Eq. Ipara)."""
+    hkl = np.array([[1, 2, 3], [10, -4, 7], [0, 0, 15]], dtype=np.int32)
+    dis = W.Disorder(0.01, 0.0, (5.0, 5.0, 5.0), (0.05, 0.03, 0.04))
+    A, _, Ip = O.disorder_factors(hkl, dis)
+    t = 2 * math.pi ** 2 * np.array(dis.g) ** 2 * hkl.astype(float) ** 2
+    np.testing.assert_allclose(Ip, np.prod(1 / np.cosh(t), 1), rtol=1e-13)
+    np.testing.assert_allclose(O.extinction_arg(hkl, dis.g), t.sum(1), rtol=1e-14)
+    off = W.Disorder(0.01, 0.0, (5.0, 5.0, 5.0), (0.05, 0.03, 0.04), intensity_model=0)
+    assert np.all(O.disorder_factors(hkl, off)[2] == 1.0)
+
+
+# ----------------------------------------------------------------------------- angular shapes
+def test_angular_shapes_peak_fwhm_and_limits():
+    s, gm = 3 * DEG, 2 * DEG
+    for st, gt in [(s, 0.0), (0.0, gm), (s, gm)]:
+        assert abs(O.angular_shape(0.0, st, gt) - 1.0) < 1e-14
+    half = lambda st, gt: optimize.brentq(lambda x: O.angular_shape(x, st, gt) - 0.5, 0.0, 20 * max(st, gt))
+    # FWHM_G = 2 sqrt(2 ln 2) sigma ~ 2.3548 sigma, FWHM_L = 2 gamma
+    assert abs(2 * half(s, 0.0) / s - 2 * math.sqrt(2 * math.log(2))) < 1e-10
+    assert abs(2 * half(0.0, gm) / gm - 2.0) < 1e-10
+    # for sigma = gamma the Gaussian is broader at half maximum by sqrt(2 ln 2) ~ 1.177
+    assert abs(half(s, 0.0) / half(0.0, s) - math.sqrt(2 * math.log(2))) < 1e-10
+    # Voigt FWHM vs Olivero-Longbothum (1977), accuracy 0.02%
+    fG, fL = 2 * math.sqrt(2 * math.log(2)) * s, 2 * gm
+    fV = 0.5346 * fL + math.sqrt(0.2166 * fL * fL + fG * fG)
+    assert abs(2 * half(s, gm) / fV - 1) < 3e-4
+    # Voigt limits: gamma -> 0 gives the Gaussian, sigma -> 0 the Lorentzian
+    x = np.linspace(0, 15 * DEG, 31)
+    # (the Voigt keeps Lorentzian tails ~gamma sigma/x^2, visible only where the Gaussian is ~1e-5)
+    np.testing.assert_allclose(O.angular_shape(x, s, 1e-9 * s), O.angular_shape(x, s, 0.0), rtol=2e-6, atol=1e-10)
+    np.testing.assert_allclose(O.angular_shape(x, 1e-7 * gm, gm), O.angular_shape(x, 0.0, gm), rtol=2e-6)
+    with pytest.raises(ValueError):
+        O.angular_shape(x, 0.0, 0.0)
+
+
+def test_voigt_is_normalised_convolution():
+    """g_V = (G*L)(x)/(G*L)(0), G of standard deviation sigma, L of HWHM gamma,
+    by direct numerical convolution."""
+    s, gm = 1.5 * DEG, 1.5 * DEG
+    G = lambda t: math.exp(-t * t / (2 * s * s))
+    L = lambda t: gm * gm / (t * t + gm * gm)
+    conv = lambda x: integrate.quad(lambda t: G(t) * L(x - t), -40 * s, 40 * s, points=[0.0, x], limit=500, epsabs=1e-15)[0]
+    c0 = conv(0.0)
+    for x in [0.3 * DEG, 1.0 * DEG, 3.0 * DEG, 8.0 * DEG]:
+        assert abs(O.angular_shape(x, s, gm) - conv(x) / c0) < 1e-7
+
+
+# ----------------------------------------------------------------------------- nodes
+def test_node_solid_angle_converges_to_gnomonic_square():
+    """With g = 1 the node weights sum to the solid angle of the gnomonic square
+    [-T,T]^2, 4 atan(T^2/sqrt(1+2T^2)), with O(h^2) error of the midpoint rule."""
+    T = math.tan(20 * DEG)
+    exact = 4 * math.atan(T * T / math.sqrt(1 + 2 * T * T))
+    assert abs(exact - 0.4689848726) < 1e-9
+    errs = []
+    for n in (16, 32, 64):
+        nd = O.node_table(n, T, 1.0, 1e6, 0.0)     # sigma huge: g = 1 to ~1e-13
+        errs.append(abs(nd.omega.sum() / math.sqrt(2 * math.pi) - exact))
+    assert errs[2] < 2e-5
+    assert 3.5 < errs[0] / errs[1] < 4.5 and 3.5 < errs[1] / errs[2] < 4.5
+
+
+def test_node_gaussian_cap_mass():
+    """sum_k omega_k / (sigma_r sqrt(2 pi)) -> integral of g over the sphere,
+    2 pi int_0^pi exp(-D^2/2 s^2) sin(D) dD, when the grid covers the cap."""
+    s = 2 * DEG
+    nd = O.node_table(96, math.tan(12 * s), 1e-4, s, 0.0)
+    cap, _ = integrate.quad(lambda d: 2 * math.pi * math.exp(-d * d / (2 * s * s)) * math.sin(d), 0, math.pi, limit=400)
+    assert abs(nd.omega.sum() / (1e-4 * math.sqrt(2 * math.pi)) / cap - 1) < 2e-4
+    # exact great-circle angle: Delta = arccos(c) = atan(rho)
+    rho = np.hypot(nd.d1, nd.d2)
+    np.testing.assert_allclose(nd.Delta, np.arctan(rho), rtol=1e-12, atol=1e-15)
+
+
+# ----------------------------------------------------------------------------- Ewald geometry
+def test_pixel_points_lie_on_ewald_sphere_and_round_trip():
+    wl = W.small(3, width=23, height=17, center=(10.3, 9.1))
+    R, Z = O.pixel_rz(wl.geom)
+    lam = wl.geom.wavelength
+    # rebuild S at azimuth psi for each pixel and check |k_in + S| = 1/lambda for psi = 0
+    rng = np.random.default_rng(0)
+    for j, i in [(0, 0), (16, 22), (9, 10), (3, 17)]:
+        psi = rng.uniform(0, 2 * math.pi)
+        S = np.array([R[j, i] * math.cos(psi), R[j, i] * math.sin(psi), Z[j, i]])
+        p1, p2 = O.ewald_project(S, wl.geom)
+        hits = np.stack([p1[0], p2[0]])
+        # one of the two rotations lands on the pixel, the other on its mirror (lab y -> -y)
+        mirror_i = 2 * (wl.geom.center_x - 0.5) - i
+        targets = {(i, j), (mirror_i, j)}
+        got = sorted([tuple(np.round(h, 9)) for h in hits])
+        want = sorted([tuple(np.round(t, 9)) for t in targets])
+        np.testing.assert_allclose(got, want, atol=1e-7)
+    # the pixel's own scattering vector (psi such that S_x < 0 branch) is on the sphere
+    SF = wl.geom.distance
+    y = ((np.arange(wl.geom.width) + 0.5) - wl.geom.center_x) * wl.geom.pixel
+    z = ((np.arange(wl.geom.height) + 0.5) - wl.geom.center_y) * wl.geom.pixel
+    yy, zz = np.meshgrid(y, z)
+    kout = np.stack([np.full_like(yy, SF), yy, zz], -1)
+    kout /= np.linalg.norm(kout, axis=-1, keepdims=True) * lam
+    S = kout - np.array([1 / lam, 0, 0])
+    np.testing.assert_allclose(np.hypot(S[..., 0], S[..., 1]), R, rtol=1e-12)
+    np.testing.assert_allclose(S[..., 2], Z, rtol=1e-12, atol=1e-15)
+
+
+def test_ewald_validity():
+    """Beam normal to the fibre: S can be rotated onto the sphere iff lambda |S|^2 <= 2 R
+    (Eq. valid); otherwise both angles are NaN."""
+    lam = 1.0
+    rng = np.random.default_rng(1)
+    S = rng.uniform(-0.8, 0.8, (2000, 3))
+    p1, p2 = O.ewald_angles(S, lam)
+    R = np.hypot(S[:, 0], S[:, 1])
+    q = np.sum(S * S, 1)
+    ok = lam * q <= 2 * R
+    margin = np.abs(lam * q - 2 * R) > 1e-9
+    assert np.array_equal(np.isfinite(p1)[margin], ok[margin])
+    assert np.array_equal(np.isfinite(p2)[margin], ok[margin])
+    # valid angles do satisfy |k_in + S_phi| = 1/lambda
+    Sphi = O.rodrigues(S[ok], p1[ok])
+    np.testing.assert_allclose(np.linalg.norm(Sphi + np.array([1 / lam, 0, 0]), axis=1), 1 / lam, rtol=1e-12)
+
+
+def test_lorentz_bounds():
+    d = 1e-5
+    R = np.concatenate([[0.0], np.logspace(-9, 0, 50)])
+    L = O.lorentz(R, d)
+    assert L[0] == 1.0 and np.all(L > 0) and np.all(L <= 1)
+    np.testing.assert_allclose(L[-5:] * R[-5:] / d, 1.0, rtol=1e-4)
+
+
+# ----------------------------------------------------------------------------- Laue kernel through the profile loop
+def _probe_problem(N, cell=None, m=3):
+    """Single node at d = 0 with omega = 1: the profile at p is r0^2 Z(p - D)."""
+    cell = cell or W.Cell(9, 11, 13, 90 * DEG, 100 * DEG, 90 * DEG)
+    avec, astar, _ = O.frame(cell)
+    hkl = np.array([[2, -1, 3]], dtype=np.int32)
+    D = O.recip_vectors(hkl, astar)
+    r0, S, e1, e2, ep = O.reflection_frames(D)
+    nodes = O.Nodes(np.zeros(1), np.zeros(1), np.ones(1), np.zeros(1), np.ones(1), 1.0)
+    P = O.Prepared(hkl, np.ones(1, complex), np.ones(1), np.array([N], float), np.ones((1, 3)), np.ones(1),
+                   D, r0, S, e1, e2, ep, avec, astar, nodes, m, 1e-5)
+    return P
+
+
+def _profile_points(P, pts):
+    """Profile of reflection 0 at arbitrary Cartesian points: express each point as
+    R e_perp + Z z with e_perp rotated to the point's azimuth."""
+    out = []
+    for p in pts:
+        Q = O.Prepared(**{**P.__dict__})
+        R = math.hypot(p[0], p[1])
+        Q.ep = np.array([[p[0] / R, p[1] / R, 0.0]])
+        out.append(O.profile_table(Q, np.array([R]), np.array([p[2]]))[0, 0])
+    return np.array(out)
+
+
+def test_laue_kernel_peak_zeros_and_laue_function():
+    N = (4.0, 5.0, 3.0)
+    P = _probe_problem(N)
+    D = P.D[0]
+    r0 = P.r0[0]
+    # peak value r0^2 N_a N_b N_c (Eq. I_shape)
+    assert abs(_profile_points(P, [D])[0] / (r0 * r0) - 60.0) < 1e-12
+    # zeros at a_i.(p - D) = k/N_i
+    for i in range(3):
+        for k in (1, 2):
+            v = _profile_points(P, [D + (k / N[i]) * P.astar[i]])[0]
+            assert abs(v) < 1e-25
+    # near the peak the envelope matches the 1-D Laue function (Eq. laue1d):
+    # sum_n |exp(2 pi i u n)|^2 over N cells, divided by N, per axis
+    u = np.array([0.004, 0.013, -0.021])
+    v = _profile_points(P, [D + (u[0] * P.astar[0] + u[1] * P.astar[1] + u[2] * P.astar[2])])[0] / (r0 * r0)
+    lattice = 1.0
+    for i, n in enumerate((4, 5, 3)):
+        amp = abs(sum(np.exp(2j * np.pi * u[i] * np.arange(n)))) ** 2
+        lattice *= amp / n
+    assert abs(v / lattice - 1) < 3 * (math.pi * 0.021) ** 2
+
+
+def test_laue_kernel_truncated_mass():
+    """Along one axis the kept mass is (2/pi) Si(2 pi m) = 0.966410 for m = 3."""
+    N = (4.0, 5.0, 3.0)
+    P = _probe_problem(N)
+    D = P.D[0]
+    frac = 2 / math.pi * special.sici(2 * math.pi * 3)[0]
+    assert abs(frac - 0.966410) < 1e-6
+    u = np.linspace(-1.0, 1.0, 4001)     # beyond the support m/N = 0.75
+    vals = _profile_points(P, [D + x * P.astar[0] for x in u]) / (P.r0[0] ** 2) / (N[1] * N[2])
+    mass = np.trapezoid(vals, u)
+    assert abs(mass - frac) < 2e-5
+    assert np.all(vals[np.abs(u) > 3 / N[0] + 1e-12] == 0.0)
+
+
+# ----------------------------------------------------------------------------- shell quadrature vs brute force
+def test_shell_quadrature_matches_volume_integral():
+    """Eq. shell_conv integrated directly: finite radial Gaussian shell (width sigma_r)
+    times the angular Gaussian, convolved with the truncated Laue kernel, in spherical
+    coordinates about S over the same angular square.  Agrees with the node sum within
+    the delta-collapse error plus quadrature error."""
+    wl = W.small(11, sigma_theta=4 * DEG, size_A=(40.0, 40.0, 50.0), n_nodes=48)
+    P = O.prepare(wl, hkl=np.array([[1, 1, 1], [2, 0, 1]], dtype=np.int32), F=np.ones(2, complex), cull_extinct=False)
+    sig_r = wl.quad.sigma_r
+    T = wl.quad.T
+    st = wl.dis.sigma_theta
+    for r in range(2):
+        D = P.D[r]
+        S, e1, e2 = P.S[r], P.e1[r], P.e2[r]
+        r0 = P.r0[r]
+        N = P.N[r]
+        # three query points: on the peak, along the arc, off the shell radially
+        qs = [D, r0 * (math.cos(0.05) * S + math.sin(0.05) * e2), D * (1 + 0.4 / (N[2] * r0 * wl.cell.c))]
+        # node-sum value
+        node_vals = _profile_points(_single(P, r), qs)
+        # brute force
+        th = np.linspace(0, math.atan(T * math.sqrt(2)), 500)
+        ph = np.linspace(0, 2 * math.pi, 800, endpoint=False)
+        dth, dph = th[1] - th[0], ph[1] - ph[0]
+        TH, PH = np.meshgrid(th[:-1] + dth / 2, ph + dph / 2, indexing="ij")
+        d1 = np.tan(TH) * np.cos(PH)
+        d2 = np.tan(TH) * np.sin(PH)
+        inside = (np.abs(d1) <= T) & (np.abs(d2) <= T)
+        nhat = (np.cos(TH)[..., None] * S + np.sin(TH)[..., None] * (np.cos(PH)[..., None] * e1 + np.sin(PH)[..., None] * e2))
+        gx, gw = np.polynomial.hermite_e.hermegauss(12)
+        for qi, p in enumerate(qs):
+            tot = 0.0
+            for x, wgt in zip(gx, gw):
+                rr = r0 + sig_r * x
+                s = rr * nhat
+                u = (p - s) @ P.avec.T
+                ok = np.all(np.abs(u) <= 3 / N, axis=-1) & inside
+                z = np.prod(N * np.sinc(N * u) ** 2, axis=-1)
+                integrand = np.where(ok, z, 0.0) * np.exp(-TH ** 2 / (2 * st * st)) * np.sin(TH) * rr * rr
+                # radial Gaussian exp(-(r-r0)^2/2 s_r^2) dr -> hermegauss weights times sig_r
+                tot += wgt * sig_r * integrand.sum() * dth * dph
+            assert abs(node_vals[qi] / tot - 1) < 5e-4, (r, qi, node_vals[qi], tot)
+
+
+def _single(P, r):
+    sl = slice(r, r + 1)
+    return O.Prepared(P.hkl[sl], P.F[sl], P.W[sl], P.N[sl], P.A[sl], P.Ip[sl], P.D[sl], P.r0[sl], P.S[sl],
+                      P.e1[sl], P.e2[sl], P.ep[sl], P.avec, P.astar, P.nodes, P.m, P.delta)
+
+
+def test_node_refinement_converges():
+    """Profile values at fixed points converge under n -> 2n -> 4n (midpoint rule, O(h^2))."""
+    vals = []
+    for n in (24, 48, 96):
+        wl = W.small(5, sigma_theta=3 * DEG, size_A=(50.0, 50.0, 60.0), n_nodes=n)
+        P = O.prepare(wl, hkl=np.array([[1, 2, 1]], dtype=np.int32), F=np.ones(1, complex), cull_extinct=False)
+        D, S, e2, r0 = P.D[0], P.S[0], P.e2[0], P.r0[0]
+        pts = [D, r0 * (math.cos(0.04) * S + math.sin(0.04) * e2)]
+        vals.append(_profile_points(P, pts))
+    vals = np.array(vals)
+    e1 = np.abs(vals[0] - vals[2])
+    e2 = np.abs(vals[1] - vals[2])
+    assert np.all(e2 < e1 / 2.5)
+    assert np.all(np.abs(vals[1] / vals[2] - 1) < 2e-3)
+
+
+# ----------------------------------------------------------------------------- pattern invariants
+def test_pattern_symmetries_and_skip():
+    wl = W.config0()
+    P = O.prepare(wl)
+    img, n = O.pattern(wl, P, count=True)
+    img2, n2 = O.pattern(wl, P, use_skip=False, count=True)
+    assert np.array_equal(img, img2) and n == n2
+    # mirror y -> -y about the centred beam is exact; Friedel z -> -z holds to rounding
+    assert np.array_equal(img, img[:, ::-1])
+    assert np.abs(img - img[::-1, :]).max() <= 1e-12 * img.max()
+    assert np.all(img >= 0) and img.max() > 0
+
+
+def test_g_zero_reduces_to_plain_laue():
+    """g -> 0: A = 1, N_eff = N_base, I_para = 1, and the pattern equals the one computed
+    with the plain Laue kernel of size N_base."""
+    wl = W.small(2, g=(1e-12, 1e-12, 1e-12))
+    P = O.prepare(wl)
+    assert np.allclose(P.N, np.array(wl.dis.N_base)[None, :], rtol=1e-15)
+    assert np.all(P.Ip == 1.0)
+    wl0 = W.small(2)
+    P0 = O.prepare(wl0)
+    np.testing.assert_allclose(O.pattern(wl, P), O.pattern(wl0, P0), rtol=1e-13, atol=0)
+
+
+def test_culling_lists_are_conservative():
+    """Every reflection with a nonzero profile at some pixel of a tile is in that tile's list."""
+    wl = W.small(4, width=21, height=19, g=(0.04, 0.02, 0.0), center=(9.7, 10.2))
+    hkl = O.enumerate_hkl(wl.cell, wl.quad.d_min, wl.quad.d_max)
+    P = O.prepare(wl, hkl=hkl, F=np.ones(len(hkl), complex), cull_extinct=False)
+    R, Z = O.pixel_rz(wl.geom)
+    tab = O.profile_table(P, R, Z).reshape(R.shape[0], R.shape[1], -1)
+    lists = O.culling_lists(wl, hkl, 8, 8)
+    ny, nx = (R.shape[0] + 7) // 8, (R.shape[1] + 7) // 8
+    assert len(lists) == ny * nx
+    nonempty = 0
+    for ty in range(ny):
+        for tx in range(nx):
+            blk = tab[ty * 8:(ty + 1) * 8, tx * 8:(tx + 1) * 8]
+            hit = np.nonzero(np.any(blk != 0, axis=(0, 1)))[0]
+            assert set(hit.tolist()) <= set(lists[ty * nx + tx].tolist())
+            nonempty += len(hit)
+    assert nonempty > 0
