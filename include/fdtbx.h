@@ -1,0 +1,231 @@
+/*
+ * fdtbx -- fibre-diffraction profile quadrature on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of the hot path of "FDTBX - Computational Tools for Simulation of X-ray
+ * Fiber Diffraction Patterns from Atomic Coordinates": reflection enumeration,
+ * direct structure factors, per-reflection shell quadrature of the broadened
+ * profile at the query points of flat-detector pixels, Lorentz correction, and
+ * the adjoint of that image.
+ *
+ * Conventions (all entry points):
+ *   - Lengths in Angstrom, reciprocal lengths in 1/Angstrom, angles in radians
+ *     (the tutorial passes cell angles in radians); detector distance and pixel
+ *     pitch share one length unit (millimetres in the examples).
+ *   - Laboratory frame of the tutorial's "Unit cell and reciprocal-space frame":
+ *     crystal c along +z (the fibre axis), b in the yz-plane; the beam runs along
+ *     a* = +x, normal to the fibre (the notebook's check |beam . fibre| <= 1e-3
+ *     holds exactly).  Fibre and detector tilt are zero.
+ *   - Detector images are float32 [height][width], row-major, row 0 at the bottom
+ *     (origin='lower'); pixel (i, j) has its centre at
+ *     y = (i + 1/2 - center_x) pixel, z = (j + 1/2 - center_y) pixel.
+ *   - Pointers documented as "device" must be device memory of the current HIP
+ *     device (hipMalloc or a torch CUDA tensor); "host" pointers are ordinary
+ *     memory.  The caller owns every buffer; the library never allocates or frees.
+ *   - Every call is asynchronous on `stream` (a hipStream_t; NULL is the null
+ *     stream) unless it says it synchronises.  Argument checks run on the host
+ *     before any launch; on error nothing is launched and no output is written.
+ *   - Return value 0 on success, a negative FDTBX_ERR_* code otherwise;
+ *     fdtbx_error_string() describes it.  No exceptions cross the ABI.
+ */
+#ifndef FDTBX_H
+#define FDTBX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  FDTBX_OK = 0,
+  FDTBX_ERR_INVALID_ARGUMENT = -1, /* null pointer, non-positive size, widths both zero, NaN, ... */
+  FDTBX_ERR_GEOMETRY = -2,         /* distance/pixel/wavelength <= 0, cell not a valid parallelepiped */
+  FDTBX_ERR_BUFFER_TOO_SMALL = -3, /* an output or workspace capacity is too small; see the call */
+  FDTBX_ERR_HIP = -4,              /* a HIP runtime call failed; fdtbx_last_hip_error() has the code */
+  FDTBX_ERR_UNSUPPORTED = -5       /* a parameter outside what this build implements */
+};
+
+/* Unit cell (tutorial Table "unitcell"). */
+typedef struct fdtbx_cell {
+  double a, b, c;             /* edge lengths, A */
+  double alpha, beta, gamma;  /* angles b^c, a^c, a^b, radians */
+} fdtbx_cell;
+
+/* Flat detector normal to the beam (tutorial Table "experiment", tilt 0). */
+typedef struct fdtbx_geometry {
+  double wavelength;          /* A */
+  double distance;            /* sample-detector distance, same unit as pixel */
+  double pixel;               /* pixel pitch */
+  int32_t width, height;      /* pixels along lab y (horizontal) and lab z (fibre) */
+  double center_x, center_y;  /* beam centre in pixel units (width/2, height/2 puts it between pixels) */
+} fdtbx_geometry;
+
+/* Orientational and lattice disorder (section "Angular peak shapes", tutorial
+ * Table "paracrystal").  sigma_theta: Gaussian standard deviation; gamma_theta:
+ * Lorentzian HWHM; both zero is an error.  N_base: coherent cells along a, b, c
+ * (non-integer allowed).  g: Hosemann relative spacing fluctuation per axis
+ * (Eq. Ah).  intensity_model: 1 applies the intensity loss of Eq. Ipara, 0 omits it. */
+typedef struct fdtbx_disorder {
+  double sigma_theta, gamma_theta;
+  double N_base[3];
+  double g[3];
+  int32_t intensity_model;
+} fdtbx_disorder;
+
+/* Shell quadrature (section "Numerical evaluation: per-reflection shell quadrature"). */
+typedef struct fdtbx_quadrature {
+  int32_t n_nodes;    /* nodes per side of the midpoint (d1, d2) grid, 1..256 */
+  double T;           /* grid half extent in tangent-plane units, 0 < T < 10 */
+  double sigma_r;     /* radial shell width collapsed to its integral sigma_r sqrt(2 pi) */
+  int32_t m;          /* Laue-kernel zeros kept per lattice axis, 1..8 */
+  double delta;       /* Lorentz regulariser of Eq. lorentz, 1/A */
+  double d_min, d_max;/* resolution shell, A; d_max <= 0: no low-resolution limit */
+  double extinction;  /* skip hkl with 2 pi^2 sum_i g_i^2 h_i^2 above this (<= 0: never) */
+} fdtbx_quadrature;
+
+typedef struct fdtbx_model {
+  fdtbx_cell cell;
+  fdtbx_geometry geom;
+  fdtbx_disorder dis;
+  fdtbx_quadrature quad;
+} fdtbx_model;
+
+/* Description of the last error on this thread (static string, never NULL). */
+const char* fdtbx_error_string(int code);
+/* hipError_t of the last FDTBX_ERR_HIP on this thread. */
+int fdtbx_last_hip_error(void);
+
+/* ------------------------------------------------------------------ reflections
+ * fdtbx_hkl_capacity: host only.  Upper bound on the number of reflections of
+ * fdtbx_enumerate_hkl for this cell and d_min (size of the index box
+ * |h| <= floor(a/d_min)+1, likewise k and l, since h = D.a).
+ *
+ * fdtbx_enumerate_hkl: every (h,k,l) != 0 with
+ *   |D|^2 <= (1/d_min^2)(1 + 1e-9)  and  |D|^2 >= (1/d_max^2)(1 - 1e-9) (if d_max > 0),
+ * D = h a* + k b* + l c* (Eq. laue3d, Eq. recip_basis), the resolution shell of the
+ * tutorial's reflection list, in ascending lexicographic order of (h,k,l).  The
+ * list is closed under negation, the mate of entry i being entry n-1-i.  The
+ * predicate is evaluated in IEEE binary64 with a fixed operation order and no
+ * fused multiply-add, so the list is reproducible bit for bit.
+ *   extinction host float64 [4] = (g_a, g_b, g_c, limit) or NULL: also drop reflections
+ *         with 2 pi^2 ((g_a^2 h^2 + g_b^2 k^2) + g_c^2 l^2) > limit, whose paracrystalline
+ *         intensity loss prod_i A_i (Eq. Ah) is below exp(-limit); the kept list is
+ *         still closed under negation and ordered
+ *   hkl   device int32 [cap][3] output
+ *   n_out device int64 [1] output: number of reflections written
+ *   ws    device workspace of at least fdtbx_enumerate_workspace(cell, d_min) bytes */
+int fdtbx_hkl_capacity(const fdtbx_cell* cell, double d_min, int64_t* cap);
+size_t fdtbx_enumerate_workspace(const fdtbx_cell* cell, double d_min);
+int fdtbx_enumerate_hkl(const fdtbx_cell* cell, double d_min, double d_max, const double* extinction,
+                        int32_t* hkl, int64_t cap, int64_t* n_out, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ structure factors
+ * F_hkl = sum_j occ_j f_t(j)(s) exp(-B_j s^2) exp(2 pi i (h x_j + k y_j + l z_j))
+ * (Eq. structure_factor with the isotropic Debye-Waller factor, B = 8 pi^2 <u^2>),
+ * s = |D_hkl|/2 = sin(theta)/lambda, f_t(s) = sum_{g=1..4} a_g exp(-b_g s^2) + c.
+ *   x, y, z  device float32 [n_atoms], fractional coordinates
+ *   B, occ   device float32 [n_atoms]
+ *   type     device int32 [n_atoms], 0 <= type < n_types (not checked on device)
+ *   ff       device float32 [n_types][9] = a1..a4, b1..b4, c; n_types <= 16
+ *   hkl      device int32 [n_hkl][3]
+ *   F        device float32 [n_hkl][2] (re, im) output, may be NULL
+ *   F2       device float32 [n_hkl] output |F|^2, may be NULL
+ *   ws       device workspace of fdtbx_sf_workspace(n_hkl, n_atoms) bytes
+ * Deterministic: fixed summation order, no atomics. */
+size_t fdtbx_sf_workspace(int64_t n_hkl, int64_t n_atoms);
+int fdtbx_structure_factors(const fdtbx_cell* cell, int64_t n_atoms, const float* x, const float* y,
+                            const float* z, const float* B, const float* occ, const int32_t* type,
+                            const float* ff, int32_t n_types, const int32_t* hkl, int64_t n_hkl, float* F,
+                            float* F2, void* ws, size_t ws_bytes, void* stream);
+
+/* ------------------------------------------------------------------ pattern building blocks
+ * Record layouts (device memory, produced and consumed by the library; exposed
+ * so each step can be checked on its own).
+ *
+ * Reflection record, FDTBX_REFL_FLOATS float32 per reflection (see
+ * fdtbx_reflection_prep).  Culling record, FDTBX_CULL_DOUBLES float64 per
+ * reflection:
+ *   [0..3]  R_lo, R_hi, Z_lo, Z_hi    box in (R, Z) of the query points it can reach
+ *   [4..5]  P2_lo, P2_hi              range of |p|^2 (annulus about r0)
+ *   [6..11] n1R, n1Z, rho1, n2R, n2Z, rho2   inward edge normals of the arc wedge and
+ *                                     the support extent along each; rho1 < 0 disables
+ *   [12]    1 if the reflection is kept (not removed by the extinction cull), else 0
+ *   [13..15] reserved (0)
+ * Node record, FDTBX_NODE_FLOATS float32 per node, node k = i2*n + i1:
+ *   [0] c - 1   [1] c d1   [2] c d2   [3] omega   [4] d omega/d sigma_theta
+ *   [5] d omega/d gamma_theta   [6] d1   [7] d2
+ * with c = (1 + d1^2 + d2^2)^(-1/2), d_j = -T + (i_j + 1/2) h, h = 2T/n and
+ * omega = sigma_r sqrt(2 pi) g(Delta) c^3 h^2, Delta = arccos c (Eq. node_weight
+ * without the per-reflection r0^2). */
+#define FDTBX_REFL_FLOATS 48
+#define FDTBX_CULL_DOUBLES 16
+#define FDTBX_NODE_FLOATS 8
+#define FDTBX_TILE 8 /* pixel tiles are FDTBX_TILE x FDTBX_TILE */
+
+/* Node table of the shell quadrature (Eqs. gnomonic, node_weight; angular shape
+ * of section "Angular peak shapes": Gaussian if gamma_theta = 0, Lorentzian if
+ * sigma_theta = 0, otherwise the unit-peak Voigt profile, evaluated on the device
+ * through the Faddeeva function w(z) by Weideman's rational series).
+ *   nodes device float32 [n_nodes^2][FDTBX_NODE_FLOATS] output */
+int fdtbx_node_table(const fdtbx_disorder* dis, const fdtbx_quadrature* quad, float* nodes, void* stream);
+
+/* Per-reflection preparation (Eqs. Ah, Neff, Ipara, gnomonic):
+ *   hkl  device int32 [n_hkl][3];  F2 device float32 [n_hkl] (|F|^2)
+ *   refl device float32 [n_hkl][FDTBX_REFL_FLOATS] output (layout private to the
+ *        profile kernels except: [0] W = |F|^2 I_para, [1..3] N_eff a,b,c, [4] r0)
+ *   cull device float64 [n_hkl][FDTBX_CULL_DOUBLES] output (layout above) */
+int fdtbx_reflection_prep(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F2,
+                          float* refl, double* cull, void* stream);
+
+/* Ring coordinates of every pixel and the (R, Z) boxes of the pixel tiles.
+ *   pix  device float64 [height][width][2] output: (R, Z) of the pixel's Ewald point,
+ *        S = (X/|X| - x)/lambda, X = (distance, y, z) (Eqs. laue, cyl-average)
+ *   tile device float64 [n_tiles][8] output: R_lo, R_hi, Z_lo, Z_hi, P2_lo, P2_hi, 0, 0
+ *        over the pixel centres of each FDTBX_TILE^2 tile, tiles row-major,
+ *        n_tiles = ceil(height/8) * ceil(width/8) */
+int fdtbx_pixel_map(const fdtbx_geometry* geom, double* pix, double* tile, void* stream);
+
+/* Per-tile culling lists: reflection r is listed for tile t iff it is kept and
+ *   R_lo(r) <= R_hi(t), R_lo(t) <= R_hi(r), Z_lo(r) <= Z_hi(t), Z_lo(t) <= Z_hi(r),
+ *   P2_lo(r) <= P2_hi(t), P2_lo(t) <= P2_hi(r), and (if rho1 >= 0)
+ *   max_corner(n1 . p) >= -rho1 and max_corner(n2 . p) >= -rho2 over the tile box corners,
+ * in ascending reflection order.  Exact binary64 comparisons: reproducible bit for bit.
+ *   offsets device int64 [n_tiles + 1] output (CSR row pointers)
+ *   idx     device int32 [cap] output;  n_pairs host int64 output (total pairs)
+ * Synchronises `stream` once to read the pair count.  If it exceeds cap,
+ * returns FDTBX_ERR_BUFFER_TOO_SMALL with *n_pairs set and idx untouched.
+ *   ws      device workspace of fdtbx_cull_workspace(geom, n_hkl) bytes
+ * The tile grid is the one of fdtbx_pixel_map for geom. */
+size_t fdtbx_cull_workspace(const fdtbx_geometry* geom, int64_t n_hkl);
+int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_t n_hkl, const double* cull, int64_t* offsets,
+               int32_t* idx, int64_t cap, int64_t* n_pairs, void* ws, size_t ws_bytes, void* stream);
+
+/* The detector image (Eq. direct_sum per reflection at the pixel's query point
+ * p* = R e_perp + Z z, Eq. I_shape with N -> N_eff, Eq. lorentz):
+ *   image[j][i] = delta/(R_ij + delta) * sum_hkl W_hkl r0^2 sum_k omega_k Z_hkl(p* - s_k)
+ * over nodes with |a_l.(p* - s_k)| <= m/N_l, reflections from the tile lists.
+ *   image device float32 [height][width] output (fully overwritten)
+ *   counts device int64 [1] (may be NULL): if non-NULL, a counting pass runs instead
+ *          of the image pass and adds the number of (pixel, reflection, node) triples
+ *          inside the support to *counts (image untouched). */
+int fdtbx_profile(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
+                  const double* tile, const int64_t* offsets, const int32_t* idx, float* image, int64_t* counts,
+                  void* stream);
+
+/* ------------------------------------------------------------------ one-call pattern
+ * fdtbx_profile_pattern runs reflection_prep, node_table, pixel_map, cull and
+ * profile into a caller workspace laid out by fdtbx_pattern_workspace(model,
+ * n_hkl, pair_cap).  Synchronises once (pair count).  If the culling lists need
+ * more than pair_cap entries it returns FDTBX_ERR_BUFFER_TOO_SMALL and writes
+ * the required count to *pairs_needed (host, may be NULL); on success
+ * *pairs_needed receives the pair count. */
+size_t fdtbx_pattern_workspace(const fdtbx_model* model, int64_t n_hkl, int64_t pair_cap);
+int fdtbx_profile_pattern(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F2,
+                          float* image, int64_t pair_cap, int64_t* pairs_needed, void* ws, size_t ws_bytes,
+                          void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FDTBX_H */

@@ -151,6 +151,24 @@ def structure_factors(hkl, cell, atoms, chunk=2048):
     return F
 
 
+def structure_factors_c(hkl, cell, atoms):
+    """The same sum as structure_factors, as a plain C loop (OpenMP over reflections)
+    for reflection lists too long for numpy."""
+    _, astar, _ = frame(cell)
+    hkl = np.ascontiguousarray(hkl, dtype=np.int32)
+    s2 = np.ascontiguousarray(q_of(recip_vectors(hkl, astar)) / 4.0)
+    cv = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+    x, y, z, B, occ = cv(atoms.x), cv(atoms.y), cv(atoms.z), cv(atoms.B), cv(atoms.occ)
+    typ = np.ascontiguousarray(atoms.type, dtype=np.int32)
+    ff = cv(atoms.ff)
+    re = np.zeros(hkl.shape[0])
+    im = np.zeros(hkl.shape[0])
+    vp = lambda a: ctypes.c_void_p(a.ctypes.data)
+    _c().oracle_structure_factors(ctypes.c_int64(hkl.shape[0]), vp(hkl), vp(s2), ctypes.c_int64(x.shape[0]), vp(x), vp(y),
+                                  vp(z), vp(B), vp(occ), vp(typ), ctypes.c_int32(ff.shape[0]), vp(ff), vp(re), vp(im))
+    return re + 1j * im
+
+
 # --------------------------------------------------------------------------- O4
 PI2 = math.pi * math.pi
 
@@ -391,73 +409,123 @@ def pattern(wl, P: Prepared = None, use_skip=True, count=False):
 
 
 # --------------------------------------------------------------------------- culling contract
-def tile_boxes(geom, tile_w, tile_h):
-    """(R, Z) bounding box over the pixel centres of each tile_w x tile_h tile
-    (tiles clipped at the detector edge), arrays [n_tiles_y][n_tiles_x]."""
+def tile_boxes(geom, tile_w=8, tile_h=8):
+    """Per tile of tile_w x tile_h pixels (clipped at the detector edge), the ranges
+    of R, Z and R^2 + Z^2 over its pixel centres: [n_tiles_y][n_tiles_x][6] =
+    (R_lo, R_hi, Z_lo, Z_hi, P2_lo, P2_hi)."""
     R, Z = pixel_rz(geom)
+    P2 = R * R + Z * Z
     H, W = R.shape
     ny, nx = (H + tile_h - 1) // tile_h, (W + tile_w - 1) // tile_w
-    box = np.zeros((ny, nx, 4))
+    box = np.zeros((ny, nx, 6))
     for ty in range(ny):
         for tx in range(nx):
-            r = R[ty * tile_h:(ty + 1) * tile_h, tx * tile_w:(tx + 1) * tile_w]
-            z = Z[ty * tile_h:(ty + 1) * tile_h, tx * tile_w:(tx + 1) * tile_w]
-            box[ty, tx] = (r.min(), r.max(), z.min(), z.max())
+            sl = (slice(ty * tile_h, (ty + 1) * tile_h), slice(tx * tile_w, (tx + 1) * tile_w))
+            box[ty, tx] = (R[sl].min(), R[sl].max(), Z[sl].min(), Z[sl].max(), P2[sl].min(), P2[sl].max())
     return box
 
 
 def reflection_boxes(wl, hkl):
-    """Conservative (R, Z) box of the query points a reflection can reach.
-    Nodes s = r0 c (S + d1 e1 + d2 e2) have |d_j| <= T and c in [c_min, 1],
-    c_min = (1 + 2T^2)^(-1/2); a query point p lies within the support box
-    {x: |a_i.x| <= m/N_i} of some node, whose extent along a unit vector v is
-    sum_i (m/N_i)|a*_i.v|.  1/N_i is bounded without transcendentals by
-    1/N_base,i + min(pi^2 g_i^2 h_i^2, 1) (tanh(t) <= min(t, 1)).
-    Returns [n][4] = (R_lo, R_hi, Z_lo, Z_hi); all arithmetic is +,-,*,/,sqrt in a
-    fixed order so that an exact reproduction elsewhere matches bit for bit."""
+    """Conservative description of the query points a reflection can reach, as
+    the 13 numbers (R_lo, R_hi, Z_lo, Z_hi, P2_lo, P2_hi, n1R, n1Z, rho1, n2R, n2Z,
+    rho2, alive) per reflection.
+
+    Nodes s = r0 c (S + d1 e1 + d2 e2) have |d_j| <= T and c in [c_min, 1] with
+    c_min = (1 + 2T^2)^(-1/2); a query point p lies in the support box
+    {x : |a_i.x| <= m/N_i} of some node, whose extent along a unit vector v is
+    sum_i (m/N_i)|a*_i.v|, with 1/N_i bounded without transcendentals by
+    1/N_base,i + min(pi^2 g_i^2 h_i^2, 1) (since tanh(t) <= min(t, 1)).  Hence:
+      - (R, Z) box: s.v over the node set, widened by the support extent, v = e_perp, z;
+      - annulus: |s| = r0, so |p| is within sum_i (m/N_i)|a*_i| of r0;
+      - wedge (reflections off the meridian): in the (R, Z) plane every node lies in
+        the cone spanned by S + d2 e2, |d2| <= T, so p lies on the inner side of each
+        edge line up to the support extent along that edge's normal.
+    All arithmetic is +, -, *, /, sqrt in a fixed order (reproducible bit for bit)."""
     _, astar, _ = frame(wl.cell)
     D = recip_vectors(hkl, astar)
     r0, S, e1, e2, ep = reflection_frames(D)
+    RD = np.sqrt(D[:, 0] * D[:, 0] + D[:, 1] * D[:, 1])
+    merid = ~(RD > 1e-12)
     T = wl.quad.T
     m = float(wl.quad.m)
     cmin = 1.0 / math.sqrt(1.0 + 2.0 * T * T)
     h = hkl.astype(np.float64)
-    Ninv = np.empty((hkl.shape[0], 3))
+    n = hkl.shape[0]
+    mN = np.empty((n, 3))
     for i in range(3):
         g = wl.dis.g[i]
         t = PI2 * (g * g) * (h[:, i] * h[:, i])
-        Ninv[:, i] = 1.0 / wl.dis.N_base[i] + np.minimum(t, 1.0)
+        mN[:, i] = m * (1.0 / wl.dis.N_base[i] + np.minimum(t, 1.0))
     ez = np.zeros_like(ep)
     ez[:, 2] = 1.0
 
     def dot(u, v):
         return (u[:, 0] * v[:, 0] + u[:, 1] * v[:, 1]) + u[:, 2] * v[:, 2]
 
-    def extent(v):
-        ext = (m * Ninv[:, 0]) * np.abs(dot(np.broadcast_to(astar[0], v.shape), v))
-        ext = ext + (m * Ninv[:, 1]) * np.abs(dot(np.broadcast_to(astar[1], v.shape), v))
-        ext = ext + (m * Ninv[:, 2]) * np.abs(dot(np.broadcast_to(astar[2], v.shape), v))
+    def ext(v):
+        e = mN[:, 0] * np.abs(dot(np.broadcast_to(astar[0], v.shape), v))
+        e = e + mN[:, 1] * np.abs(dot(np.broadcast_to(astar[1], v.shape), v))
+        e = e + mN[:, 2] * np.abs(dot(np.broadcast_to(astar[2], v.shape), v))
+        return e
+
+    def span(v):
         l0, l1, l2 = dot(S, v), dot(e1, v), dot(e2, v)
         spread = T * (np.abs(l1) + np.abs(l2))
         lo, hi = l0 - spread, l0 + spread
         s_lo = r0 * np.minimum(cmin * lo, lo)
         s_hi = r0 * np.maximum(cmin * hi, hi)
-        return s_lo - ext, s_hi + ext
+        e = ext(v)
+        return s_lo - e, s_hi + e
 
-    Rlo, Rhi = extent(ep)
-    Zlo, Zhi = extent(ez)
-    return np.stack([Rlo, Rhi, Zlo, Zhi], axis=1)
+    out = np.zeros((n, 13))
+    out[:, 0], out[:, 1] = span(ep)
+    out[:, 2], out[:, 3] = span(ez)
+    rho = mN[:, 0] * math.sqrt((astar[0, 0] * astar[0, 0] + astar[0, 1] * astar[0, 1]) + astar[0, 2] * astar[0, 2])
+    rho = rho + mN[:, 1] * math.sqrt((astar[1, 0] * astar[1, 0] + astar[1, 1] * astar[1, 1]) + astar[1, 2] * astar[1, 2])
+    rho = rho + mN[:, 2] * math.sqrt((astar[2, 0] * astar[2, 0] + astar[2, 1] * astar[2, 1]) + astar[2, 2] * astar[2, 2])
+    a_lo, a_hi = r0 - rho, r0 + rho
+    out[:, 4] = np.where(a_lo > 0.0, a_lo * a_lo, 0.0)
+    out[:, 5] = a_hi * a_hi
+    # wedge of the in-plane node directions
+    SR, SZ, e2R, e2Z = dot(S, ep), S[:, 2], dot(e2, ep), e2[:, 2]
+    vmR, vmZ = SR - T * e2R, SZ - T * e2Z
+    vpR, vpZ = SR + T * e2R, SZ + T * e2Z
+    n1R, n1Z = -vmZ, vmR
+    flip = n1R * vpR + n1Z * vpZ < 0.0
+    n1R, n1Z = np.where(flip, -n1R, n1R), np.where(flip, -n1Z, n1Z)
+    n2R, n2Z = -vpZ, vpR
+    flip = n2R * vmR + n2Z * vmZ < 0.0
+    n2R, n2Z = np.where(flip, -n2R, n2R), np.where(flip, -n2Z, n2Z)
+    v1 = np.stack([n1R * ep[:, 0], n1R * ep[:, 1], n1R * ep[:, 2] + n1Z], axis=1)
+    v2 = np.stack([n2R * ep[:, 0], n2R * ep[:, 1], n2R * ep[:, 2] + n2Z], axis=1)
+    out[:, 6], out[:, 7], out[:, 8] = n1R, n1Z, ext(v1)
+    out[:, 9], out[:, 10], out[:, 11] = n2R, n2Z, ext(v2)
+    out[merid, 6:12] = [0.0, 0.0, -1.0, 0.0, 0.0, -1.0]
+    ext_lim = wl.quad.extinction
+    alive = ~((ext_lim > 0) & (extinction_arg(hkl, wl.dis.g) > ext_lim))
+    out[:, 12] = alive.astype(np.float64)
+    return out
 
 
-def culling_lists(wl, hkl, tile_w=8, tile_h=8):
-    """Per tile (row-major over tiles), ascending indices into hkl of the
-    reflections not removed by the extinction cull whose box meets the tile's box."""
-    tb = tile_boxes(wl.geom, tile_w, tile_h).reshape(-1, 4)
+def culling_lists(wl, hkl, tile_w=8, tile_h=8, tiles=None):
+    """Per tile (row-major over tiles, or the given flat tile indices), ascending
+    indices into hkl of the reflections that are alive and pass every test of the
+    reflection's description against the tile's box (the box corners stand in for
+    the tile's pixels in the wedge test)."""
+    tb = tile_boxes(wl.geom, tile_w, tile_h).reshape(-1, 6)
     rb = reflection_boxes(wl, hkl)
-    alive = ~extinct_mask(hkl, wl.dis, wl.quad.extinction)
+    if tiles is None:
+        tiles = range(tb.shape[0])
     lists = []
-    for t in range(tb.shape[0]):
-        ok = alive & (rb[:, 0] <= tb[t, 1]) & (tb[t, 0] <= rb[:, 1]) & (rb[:, 2] <= tb[t, 3]) & (tb[t, 2] <= rb[:, 3])
+    for t in tiles:
+        b = tb[t]
+        ok = rb[:, 12] != 0.0
+        ok &= (rb[:, 0] <= b[1]) & (b[0] <= rb[:, 1]) & (rb[:, 2] <= b[3]) & (b[2] <= rb[:, 3])
+        ok &= (rb[:, 4] <= b[5]) & (b[4] <= rb[:, 5])
+        wedge = rb[:, 8] >= 0.0
+        m1 = np.maximum(rb[:, 6] * b[0], rb[:, 6] * b[1]) + np.maximum(rb[:, 7] * b[2], rb[:, 7] * b[3])
+        m2 = np.maximum(rb[:, 9] * b[0], rb[:, 9] * b[1]) + np.maximum(rb[:, 10] * b[2], rb[:, 10] * b[3])
+        ok &= ~wedge | ((m1 >= -rb[:, 8]) & (m2 >= -rb[:, 11]))
         lists.append(np.nonzero(ok)[0].astype(np.int32))
     return lists
 

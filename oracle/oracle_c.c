@@ -182,3 +182,30 @@ void oracle_profile_table(const oracle_problem* P, int64_t n_pix, const double* 
     }
   }
 }
+
+/* Structure factors (Eq. structure_factor with the isotropic Debye-Waller factor):
+ * F = sum_j occ_j f_t(s) exp(-B_j s^2) (cos 2 pi phi + i sin 2 pi phi), phi = (h x + k y + l z) mod 1,
+ * s^2 = |D|^2/4 given per reflection, f_t(s) = sum_g a_g exp(-b_g s^2) + c from ff[t][9]. */
+void oracle_structure_factors(int64_t n_hkl, const int32_t* hkl, const double* s2, int64_t n_atoms, const double* x,
+                              const double* y, const double* z, const double* B, const double* occ, const int32_t* type,
+                              int32_t n_types, const double* ff, double* F_re, double* F_im) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t r = 0; r < n_hkl; ++r) {
+    double f[64];
+    for (int t = 0; t < n_types && t < 64; ++t) {
+      f[t] = ff[9 * t + 8];
+      for (int g = 0; g < 4; ++g) f[t] += ff[9 * t + g] * exp(-ff[9 * t + 4 + g] * s2[r]);
+    }
+    double h = hkl[3 * r], k = hkl[3 * r + 1], l = hkl[3 * r + 2];
+    double re = 0.0, im = 0.0;
+    for (int64_t j = 0; j < n_atoms; ++j) {
+      double phi = (h * x[j] + k * y[j]) + l * z[j];
+      phi = phi - floor(phi);
+      double amp = occ[j] * f[type[j]] * exp(-B[j] * s2[r]);
+      re += amp * cos(2.0 * M_PI * phi);
+      im += amp * sin(2.0 * M_PI * phi);
+    }
+    F_re[r] = re;
+    F_im[r] = im;
+  }
+}

@@ -1,0 +1,292 @@
+"""ctypes binding of libfdtbx.so.
+
+Argument marshalling only: every step of the path runs in the library's HIP
+kernels.  Device buffers are torch CUDA tensors (torch supplies device memory
+and the current stream); the functions below mirror the C ABI names in
+include/fdtbx.h.  If the library is missing, importing works but every call
+raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libfdtbx.so")
+
+REFL_FLOATS = 48
+CULL_DOUBLES = 16
+NODE_FLOATS = 8
+TILE = 8
+
+ERRORS = {0: "ok", -1: "invalid argument", -2: "geometry", -3: "buffer too small", -4: "hip", -5: "unsupported"}
+
+
+class FdtbxError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fdtbx error {code} ({ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class Cell(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_double), ("b", ctypes.c_double), ("c", ctypes.c_double),
+                ("alpha", ctypes.c_double), ("beta", ctypes.c_double), ("gamma", ctypes.c_double)]
+
+
+class Geometry(ctypes.Structure):
+    _fields_ = [("wavelength", ctypes.c_double), ("distance", ctypes.c_double), ("pixel", ctypes.c_double),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32),
+                ("center_x", ctypes.c_double), ("center_y", ctypes.c_double)]
+
+
+class Disorder(ctypes.Structure):
+    _fields_ = [("sigma_theta", ctypes.c_double), ("gamma_theta", ctypes.c_double),
+                ("N_base", ctypes.c_double * 3), ("g", ctypes.c_double * 3), ("intensity_model", ctypes.c_int32)]
+
+
+class Quadrature(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int32), ("T", ctypes.c_double), ("sigma_r", ctypes.c_double),
+                ("m", ctypes.c_int32), ("delta", ctypes.c_double), ("d_min", ctypes.c_double),
+                ("d_max", ctypes.c_double), ("extinction", ctypes.c_double)]
+
+
+class Model(ctypes.Structure):
+    _fields_ = [("cell", Cell), ("geom", Geometry), ("dis", Disorder), ("quad", Quadrature)]
+
+
+_lib = None
+
+_SIGS = {
+    "fdtbx_error_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "fdtbx_last_hip_error": (ctypes.c_int, []),
+    "fdtbx_hkl_capacity": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p]),
+    "fdtbx_enumerate_workspace": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_double]),
+    "fdtbx_enumerate_hkl": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_double, ctypes.c_double, ctypes.c_void_p,
+                                           ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_size_t, ctypes.c_void_p]),
+    "fdtbx_sf_workspace": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64]),
+    "fdtbx_structure_factors": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64] + [ctypes.c_void_p] * 7 +
+                                [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "fdtbx_node_table": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fdtbx_reflection_prep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fdtbx_pixel_map": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fdtbx_cull_workspace": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64]),
+    "fdtbx_cull": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                  ctypes.c_void_p]),
+    "fdtbx_profile": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 9),
+    "fdtbx_pattern_workspace": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]),
+    "fdtbx_profile_pattern": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                             ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                             ctypes.c_size_t, ctypes.c_void_p]),
+}
+
+
+def exported_symbols():
+    return list(_SIGS.keys())
+
+
+def lib():
+    """Load libfdtbx.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        msg = lib().fdtbx_error_string(rc).decode()
+        raise FdtbxError(rc, msg)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, dtype, name: str):
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+# ----------------------------------------------------------------------------- struct builders
+def make_cell(c) -> Cell:
+    return Cell(c.a, c.b, c.c, c.alpha, c.beta, c.gamma)
+
+
+def make_model(wl) -> Model:
+    g, d, q = wl.geom, wl.dis, wl.quad
+    return Model(make_cell(wl.cell),
+                 Geometry(g.wavelength, g.distance, g.pixel, g.width, g.height, g.center_x, g.center_y),
+                 Disorder(d.sigma_theta, d.gamma_theta, (ctypes.c_double * 3)(*d.N_base),
+                          (ctypes.c_double * 3)(*d.g), d.intensity_model),
+                 Quadrature(q.n_nodes, q.T, q.sigma_r, q.m, q.delta, q.d_min, q.d_max, q.extinction))
+
+
+def tiles_of(width: int, height: int):
+    return (width + TILE - 1) // TILE, (height + TILE - 1) // TILE
+
+
+# ----------------------------------------------------------------------------- entry points
+def hkl_capacity(cell: Cell, d_min: float) -> int:
+    cap = ctypes.c_int64(0)
+    _check(lib().fdtbx_hkl_capacity(ctypes.byref(cell), d_min, ctypes.byref(cap)))
+    return int(cap.value)
+
+
+def enumerate_hkl(cell: Cell, d_min: float, d_max: float, extinction=None, device="cuda") -> torch.Tensor:
+    """fdtbx_enumerate_hkl; returns int32 [n][3] on the device (one synchronisation to read n)."""
+    L = lib()
+    cap = hkl_capacity(cell, d_min)
+    out = torch.empty((cap, 3), dtype=torch.int32, device=device)
+    n = torch.zeros(1, dtype=torch.int64, device=device)
+    wsb = L.fdtbx_enumerate_workspace(ctypes.byref(cell), d_min)
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=device)
+    ext = None
+    if extinction is not None:
+        ext = (ctypes.c_double * 4)(*extinction)
+    _check(L.fdtbx_enumerate_hkl(ctypes.byref(cell), d_min, d_max, ext, _ptr(out), cap, _ptr(n), _ptr(ws), wsb,
+                                 _stream()))
+    return out[: int(n.item())]
+
+
+def structure_factors(cell: Cell, atoms: dict, hkl: torch.Tensor, want_F=True, want_F2=True):
+    """fdtbx_structure_factors.  atoms: dict of device tensors x, y, z, B, occ (float32), type (int32),
+    ff (float32 [n_types][9]).  Returns (F [n][2] or None, F2 [n] or None)."""
+    L = lib()
+    n_hkl = int(hkl.shape[0])
+    n_atoms = int(atoms["x"].shape[0])
+    for k in ("x", "y", "z", "B", "occ", "ff"):
+        _dev(atoms[k], torch.float32, k)
+    _dev(atoms["type"], torch.int32, "type")
+    _dev(hkl, torch.int32, "hkl")
+    dev = hkl.device
+    F = torch.empty((n_hkl, 2), dtype=torch.float32, device=dev) if want_F else None
+    F2 = torch.empty(n_hkl, dtype=torch.float32, device=dev) if want_F2 else None
+    wsb = L.fdtbx_sf_workspace(n_hkl, n_atoms)
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=dev)
+    _check(L.fdtbx_structure_factors(ctypes.byref(cell), n_atoms, _ptr(atoms["x"]), _ptr(atoms["y"]), _ptr(atoms["z"]),
+                                     _ptr(atoms["B"]), _ptr(atoms["occ"]), _ptr(atoms["type"]), _ptr(atoms["ff"]),
+                                     int(atoms["ff"].shape[0]), _ptr(hkl), n_hkl, _ptr(F), _ptr(F2), _ptr(ws), wsb,
+                                     _stream()))
+    return F, F2
+
+
+def node_table(model: Model) -> torch.Tensor:
+    n = model.quad.n_nodes
+    out = torch.empty((n * n, NODE_FLOATS), dtype=torch.float32, device="cuda")
+    _check(lib().fdtbx_node_table(ctypes.byref(model.dis), ctypes.byref(model.quad), _ptr(out), _stream()))
+    return out
+
+
+def reflection_prep(model: Model, hkl: torch.Tensor, F2: torch.Tensor):
+    n = int(hkl.shape[0])
+    _dev(hkl, torch.int32, "hkl")
+    _dev(F2, torch.float32, "F2")
+    refl = torch.empty((n, REFL_FLOATS), dtype=torch.float32, device=hkl.device)
+    cull = torch.empty((n, CULL_DOUBLES), dtype=torch.float64, device=hkl.device)
+    _check(lib().fdtbx_reflection_prep(ctypes.byref(model), _ptr(hkl), n, _ptr(F2), _ptr(refl), _ptr(cull), _stream()))
+    return refl, cull
+
+
+def pixel_map(geom: Geometry):
+    tx, ty = tiles_of(geom.width, geom.height)
+    pix = torch.empty((geom.height, geom.width, 2), dtype=torch.float64, device="cuda")
+    tile = torch.empty((tx * ty, 8), dtype=torch.float64, device="cuda")
+    _check(lib().fdtbx_pixel_map(ctypes.byref(geom), _ptr(pix), _ptr(tile), _stream()))
+    return pix, tile
+
+
+def cull(geom: Geometry, tile: torch.Tensor, cull_rec: torch.Tensor, cap: Optional[int] = None):
+    """fdtbx_cull; returns (offsets int64 [n_tiles+1], idx int32 [n_pairs]).  Retries once with the
+    exact capacity when cap is too small."""
+    L = lib()
+    n_hkl = int(cull_rec.shape[0])
+    n_tiles = int(tile.shape[0])
+    offsets = torch.empty(n_tiles + 1, dtype=torch.int64, device=tile.device)
+    wsb = L.fdtbx_cull_workspace(ctypes.byref(geom), n_hkl)
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=tile.device)
+    if cap is None:
+        cap = 1 << 20
+    for _ in range(2):
+        idx = torch.empty(max(cap, 1), dtype=torch.int32, device=tile.device)
+        n_pairs = ctypes.c_int64(0)
+        rc = L.fdtbx_cull(ctypes.byref(geom), _ptr(tile), n_hkl, _ptr(cull_rec), _ptr(offsets), _ptr(idx), cap,
+                          ctypes.byref(n_pairs), _ptr(ws), wsb, _stream())
+        if rc == -3 and n_pairs.value > cap:
+            cap = int(n_pairs.value)
+            continue
+        _check(rc)
+        return offsets, idx[: int(n_pairs.value)]
+    raise FdtbxError(-3, "culling capacity")
+
+
+def profile(model: Model, refl, nodes, pix, tile, offsets, idx, count=False):
+    """fdtbx_profile: the image [H][W] float32, or (count=True) the number of support-passing evaluations."""
+    g = model.geom
+    if count:
+        c = torch.zeros(1, dtype=torch.int64, device="cuda")
+        _check(lib().fdtbx_profile(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(tile), _ptr(offsets),
+                                   _ptr(idx), None, _ptr(c), _stream()))
+        return int(c.item())
+    img = torch.empty((g.height, g.width), dtype=torch.float32, device="cuda")
+    _check(lib().fdtbx_profile(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(tile), _ptr(offsets),
+                               _ptr(idx), _ptr(img), None, _stream()))
+    return img
+
+
+class PatternPlan:
+    """Workspace holder for fdtbx_profile_pattern; grows its culling capacity on demand."""
+
+    def __init__(self, model: Model, n_hkl: int, pair_cap: int = 1 << 20):
+        self.model = model
+        self.n_hkl = n_hkl
+        self.pair_cap = pair_cap
+        self._alloc()
+
+    def _alloc(self):
+        wsb = lib().fdtbx_pattern_workspace(ctypes.byref(self.model), self.n_hkl, self.pair_cap)
+        if wsb == 0:
+            raise FdtbxError(-1, "fdtbx_pattern_workspace rejected the model")
+        self.ws_bytes = wsb
+        self.ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+
+    def run(self, hkl: torch.Tensor, F2: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        g = self.model.geom
+        if out is None:
+            out = torch.empty((g.height, g.width), dtype=torch.float32, device="cuda")
+        for _ in range(2):
+            need = ctypes.c_int64(0)
+            rc = lib().fdtbx_profile_pattern(ctypes.byref(self.model), _ptr(hkl), self.n_hkl, _ptr(F2), _ptr(out),
+                                             self.pair_cap, ctypes.byref(need), _ptr(self.ws), self.ws_bytes, _stream())
+            if rc == -3 and need.value > self.pair_cap:
+                self.pair_cap = int(need.value * 1.05) + 1024
+                self._alloc()
+                continue
+            _check(rc)
+            self.pairs = int(need.value)
+            return out
+        raise FdtbxError(-3, "pattern workspace")

@@ -1,0 +1,152 @@
+// Host side of the C ABI: argument checks, error reporting, and the one-call
+// pattern entry point that chains the building blocks on one stream.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace fdtbx {
+
+static thread_local const char* g_msg = "no error";
+static thread_local int g_hip = 0;
+
+int fail(int code, const char* msg) {
+  g_msg = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  g_hip = (int)e;
+  g_msg = where;
+  return FDTBX_ERR_HIP;
+}
+
+bool finite_pos(double v) { return isfinite(v) && v > 0.0; }
+
+int check_cell(const fdtbx_cell* c) {
+  if (!c) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null cell");
+  if (!finite_pos(c->a) || !finite_pos(c->b) || !finite_pos(c->c))
+    return fail(FDTBX_ERR_GEOMETRY, "cell edges must be positive and finite");
+  const double angs[3] = {c->alpha, c->beta, c->gamma};
+  for (double a : angs)
+    if (!(isfinite(a) && a > 0.0 && a < M_PI)) return fail(FDTBX_ERR_GEOMETRY, "cell angles must be in (0, pi) radians");
+  double ca = cos(c->alpha), cb = cos(c->beta), cg = cos(c->gamma);
+  if (!(1.0 - ca * ca - cb * cb - cg * cg + 2.0 * ca * cb * cg > 1e-12))
+    return fail(FDTBX_ERR_GEOMETRY, "cell angles do not span a parallelepiped");
+  return FDTBX_OK;
+}
+
+int check_geometry(const fdtbx_geometry* g) {
+  if (!g) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null geometry");
+  if (!finite_pos(g->wavelength) || !finite_pos(g->distance) || !finite_pos(g->pixel))
+    return fail(FDTBX_ERR_GEOMETRY, "wavelength, distance and pixel must be positive and finite");
+  if (g->width < 1 || g->height < 1 || g->width > 65536 || g->height > 65536)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "detector size must be in 1..65536 pixels");
+  if (!isfinite(g->center_x) || !isfinite(g->center_y)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "beam centre not finite");
+  return FDTBX_OK;
+}
+
+int check_model(const fdtbx_model* m) {
+  if (!m) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null model");
+  int rc = check_cell(&m->cell);
+  if (rc) return rc;
+  rc = check_geometry(&m->geom);
+  if (rc) return rc;
+  const fdtbx_disorder& d = m->dis;
+  if (!(isfinite(d.sigma_theta) && d.sigma_theta >= 0) || !(isfinite(d.gamma_theta) && d.gamma_theta >= 0))
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "angular widths must be finite and non-negative");
+  if (d.sigma_theta == 0.0 && d.gamma_theta == 0.0)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "sigma_theta and gamma_theta are both zero");
+  for (int i = 0; i < 3; ++i) {
+    if (!finite_pos(d.N_base[i])) return fail(FDTBX_ERR_INVALID_ARGUMENT, "N_base must be positive and finite");
+    if (!(isfinite(d.g[i]) && d.g[i] >= 0.0 && d.g[i] < 1.0)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "g must be in [0, 1)");
+  }
+  if (d.intensity_model != 0 && d.intensity_model != 1) return fail(FDTBX_ERR_INVALID_ARGUMENT, "intensity_model must be 0 or 1");
+  const fdtbx_quadrature& q = m->quad;
+  if (q.n_nodes < 1 || q.n_nodes > 256) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_nodes must be in 1..256");
+  if (!(q.T > 0.0 && q.T < 10.0)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "T must be in (0, 10)");
+  if (!finite_pos(q.sigma_r)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "sigma_r must be positive");
+  if (q.m < 1 || q.m > 8) return fail(FDTBX_ERR_INVALID_ARGUMENT, "m must be in 1..8");
+  if (!finite_pos(q.delta)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "delta must be positive");
+  if (!finite_pos(q.d_min)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "d_min must be positive");
+  if (isnan(q.d_max) || (q.d_max > 0 && !(q.d_max > q.d_min))) return fail(FDTBX_ERR_INVALID_ARGUMENT, "d_max must exceed d_min");
+  if (!isfinite(q.extinction)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "extinction limit must be finite");
+  return FDTBX_OK;
+}
+
+struct PatternLayout {
+  size_t refl, cull, nodes, pix, tile, offsets, cullws, idx, total;
+};
+
+static PatternLayout layout(const fdtbx_model* m, int64_t n_hkl, int64_t pair_cap) {
+  PatternLayout L;
+  int64_t tiles = ceil_div(m->geom.width, FDTBX_TILE) * ceil_div(m->geom.height, FDTBX_TILE);
+  size_t o = 0;
+  L.refl = o;
+  o += align_up((size_t)n_hkl * FDTBX_REFL_FLOATS * sizeof(float), 256);
+  L.cull = o;
+  o += align_up((size_t)n_hkl * FDTBX_CULL_DOUBLES * sizeof(double), 256);
+  L.nodes = o;
+  o += align_up((size_t)m->quad.n_nodes * m->quad.n_nodes * FDTBX_NODE_FLOATS * sizeof(float), 256);
+  L.pix = o;
+  o += align_up((size_t)m->geom.width * m->geom.height * 2 * sizeof(double), 256);
+  L.tile = o;
+  o += align_up((size_t)tiles * 8 * sizeof(double), 256);
+  L.offsets = o;
+  o += align_up((size_t)(tiles + 1) * sizeof(int64_t), 256);
+  L.cullws = o;
+  o += align_up(fdtbx_cull_workspace(&m->geom, n_hkl), 256);
+  L.idx = o;
+  o += align_up((size_t)(pair_cap > 0 ? pair_cap : 1) * sizeof(int32_t), 256);
+  L.total = o;
+  return L;
+}
+
+}  // namespace fdtbx
+
+using namespace fdtbx;
+
+extern "C" const char* fdtbx_error_string(int code) {
+  if (code == FDTBX_OK) return "ok";
+  return g_msg;
+}
+
+extern "C" int fdtbx_last_hip_error(void) { return g_hip; }
+
+extern "C" size_t fdtbx_pattern_workspace(const fdtbx_model* model, int64_t n_hkl, int64_t pair_cap) {
+  if (!model || check_model(model) || n_hkl <= 0 || pair_cap < 0) return 0;
+  return layout(model, n_hkl, pair_cap).total;
+}
+
+extern "C" int fdtbx_profile_pattern(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F2,
+                                     float* image, int64_t pair_cap, int64_t* pairs_needed, void* ws, size_t ws_bytes,
+                                     void* stream) {
+  if (!model || !hkl || !F2 || !image || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be positive");
+  if (pair_cap < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "pair_cap must be non-negative");
+  int rc = check_model(model);
+  if (rc) return rc;
+  PatternLayout L = layout(model, n_hkl, pair_cap);
+  if (ws_bytes < L.total) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "pattern workspace too small");
+  char* w = (char*)ws;
+  float* refl = (float*)(w + L.refl);
+  double* cull = (double*)(w + L.cull);
+  float* nodes = (float*)(w + L.nodes);
+  double* pix = (double*)(w + L.pix);
+  double* tile = (double*)(w + L.tile);
+  int64_t* offsets = (int64_t*)(w + L.offsets);
+  int32_t* idx = (int32_t*)(w + L.idx);
+  rc = fdtbx_reflection_prep(model, hkl, n_hkl, F2, refl, cull, stream);
+  if (rc) return rc;
+  rc = fdtbx_node_table(&model->dis, &model->quad, nodes, stream);
+  if (rc) return rc;
+  rc = fdtbx_pixel_map(&model->geom, pix, tile, stream);
+  if (rc) return rc;
+  int64_t n_pairs = 0;
+  rc = fdtbx_cull(&model->geom, tile, n_hkl, cull, offsets, idx, pair_cap, &n_pairs, w + L.cullws,
+                  fdtbx_cull_workspace(&model->geom, n_hkl), stream);
+  if (pairs_needed) *pairs_needed = n_pairs;
+  if (rc) return rc;
+  return fdtbx_profile(model, refl, nodes, pix, tile, offsets, idx, image, nullptr, stream);
+}

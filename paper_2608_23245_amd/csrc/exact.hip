@@ -1,0 +1,680 @@
+// Bit-reproducible binary64 steps: cell frame, reflection enumeration, pixel map
+// and tile boxes, per-reflection records, per-tile culling lists.
+//
+// This translation unit is compiled with -ffp-contract=off: every expression is
+// evaluated in IEEE binary64 with correctly rounded +, -, *, /, sqrt in the order
+// written, so the integer results (reflection list, culling lists) do not depend
+// on the compiler's choice of fused multiply-adds.  The float32 records for the
+// profile kernels are derived here too (rounded once from binary64).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace fdtbx {
+
+// ---------------------------------------------------------------- frame (Eq. recip_basis)
+// c = (0,0,c); b = (0, b sin(alpha), b cos(alpha)); a_z = a cos(beta),
+// a_y = a (cos(gamma) - cos(alpha) cos(beta))/sin(alpha), a_x = sqrt(a^2 - a_y^2 - a_z^2);
+// V = a.(b x c); a* = (b x c)/V, b* = (c x a)/V, c* = (a x b)/V.
+__host__ __device__ static inline void cross3(const double* u, const double* v, double* w) {
+  w[0] = u[1] * v[2] - u[2] * v[1];
+  w[1] = u[2] * v[0] - u[0] * v[2];
+  w[2] = u[0] * v[1] - u[1] * v[0];
+}
+
+
+__host__ __device__ static void make_frame(const fdtbx_cell c, Frame* f) {
+  double ca = cos(c.alpha), cb = cos(c.beta), cg = cos(c.gamma), sa = sin(c.alpha);
+  double cv[3] = {0.0, 0.0, c.c};
+  double bv[3] = {0.0, c.b * sa, c.b * ca};
+  double az = c.a * cb;
+  double ay = c.a * (cg - ca * cb) / sa;
+  double ax = sqrt(c.a * c.a - ay * ay - az * az);
+  double av[3] = {ax, ay, az};
+  double bxc[3], cxa[3], axb[3];
+  cross3(bv, cv, bxc);
+  cross3(cv, av, cxa);
+  cross3(av, bv, axb);
+  double V = (av[0] * bxc[0] + av[1] * bxc[1]) + av[2] * bxc[2];
+  for (int j = 0; j < 3; ++j) {
+    f->a[0 * 3 + j] = av[j];
+    f->a[1 * 3 + j] = bv[j];
+    f->a[2 * 3 + j] = cv[j];
+    f->s[0 * 3 + j] = bxc[j] / V;
+    f->s[1 * 3 + j] = cxa[j] / V;
+    f->s[2 * 3 + j] = axb[j] / V;
+  }
+  f->V = V;
+}
+
+// D = h a* + k b* + l c*, componentwise (h a*_j + k b*_j) + l c*_j.
+__device__ static inline void recip(const Frame& f, double h, double k, double l, double* D) {
+  for (int j = 0; j < 3; ++j) D[j] = (h * f.s[0 * 3 + j] + k * f.s[1 * 3 + j]) + l * f.s[2 * 3 + j];
+}
+
+static const double kPi2 = M_PI * M_PI;
+
+// 2 pi^2 ((g_a^2 h^2 + g_b^2 k^2) + g_c^2 l^2): exponent of prod_i A_i (Eq. Ah).
+__device__ static inline double extinction_arg(double ga, double gb, double gc, double h, double k, double l) {
+  double t = (ga * ga) * (h * h) + (gb * gb) * (k * k);
+  t = t + (gc * gc) * (l * l);
+  return (2.0 * kPi2) * t;
+}
+
+// ---------------------------------------------------------------- enumeration
+struct EnumParams {
+  Frame f;
+  int32_t H, K, L;      // box half sizes
+  int64_t n_cand;
+  double t_hi, t_lo;    // thresholds on |D|^2; t_lo < 0 disables
+  double ga, gb, gc, ext_limit;  // ext_limit <= 0 disables the extinction cull
+};
+
+static constexpr int kEnumThreads = 256;
+static constexpr int kEnumPerThread = 4;
+static constexpr int kEnumChunk = kEnumThreads * kEnumPerThread;
+
+__device__ static inline bool enum_keep(const EnumParams& p, int64_t idx, int32_t* hkl) {
+  int64_t nl = 2 * p.L + 1, nk = 2 * p.K + 1;
+  int32_t l = (int32_t)(idx % nl) - p.L;
+  int64_t r = idx / nl;
+  int32_t k = (int32_t)(r % nk) - p.K;
+  int32_t h = (int32_t)(r / nk) - p.H;
+  hkl[0] = h;
+  hkl[1] = k;
+  hkl[2] = l;
+  if (h == 0 && k == 0 && l == 0) return false;
+  double D[3];
+  recip(p.f, (double)h, (double)k, (double)l, D);
+  double q = (D[0] * D[0] + D[1] * D[1]) + D[2] * D[2];
+  if (!(q <= p.t_hi)) return false;
+  if (p.t_lo >= 0.0 && !(q >= p.t_lo)) return false;
+  if (p.ext_limit > 0.0 && extinction_arg(p.ga, p.gb, p.gc, h, k, l) > p.ext_limit) return false;
+  return true;
+}
+
+// Exclusive scan over the block; *total gets the block sum.  blockDim.x is a multiple of 64.
+__device__ static int64_t block_exclusive_scan(int64_t v, int64_t* lds, int64_t* total) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  int64_t x = v;
+  for (int o = 1; o < 64; o <<= 1) {
+    int64_t y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) lds[wid] = x;
+  __syncthreads();
+  int64_t off = 0, tot = 0;
+  for (int w = 0; w < nw; ++w) {
+    int64_t s = lds[w];
+    if (w < wid) off += s;
+    tot += s;
+  }
+  __syncthreads();
+  *total = tot;
+  return off + x - v;
+}
+
+__global__ void __launch_bounds__(kEnumThreads) k_enum_count(EnumParams p, int64_t* block_counts) {
+  __shared__ int64_t lds[kEnumThreads / 64];
+  int64_t base = (int64_t)blockIdx.x * kEnumChunk + (int64_t)threadIdx.x * kEnumPerThread;
+  int64_t c = 0;
+  int32_t hkl[3];
+  for (int i = 0; i < kEnumPerThread; ++i)
+    if (base + i < p.n_cand && enum_keep(p, base + i, hkl)) ++c;
+  int64_t tot;
+  block_exclusive_scan(c, lds, &tot);
+  if (threadIdx.x == 0) block_counts[blockIdx.x] = tot;
+}
+
+// Exclusive scan of n values in place with one block; writes the grand total to *total.
+__global__ void __launch_bounds__(1024) k_scan_inplace(int64_t* v, int64_t n, int64_t* total) {
+  __shared__ int64_t lds[16];
+  __shared__ int64_t carry_s;
+  if (threadIdx.x == 0) carry_s = 0;
+  __syncthreads();
+  for (int64_t b = 0; b < n; b += blockDim.x) {
+    int64_t i = b + threadIdx.x;
+    int64_t x = i < n ? v[i] : 0;
+    int64_t tot;
+    int64_t ex = block_exclusive_scan(x, lds, &tot);
+    int64_t carry = carry_s;
+    if (i < n) v[i] = carry + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry_s = carry + tot;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *total = carry_s;
+}
+
+__global__ void __launch_bounds__(kEnumThreads) k_enum_fill(EnumParams p, const int64_t* block_offsets, int32_t* out) {
+  __shared__ int64_t lds[kEnumThreads / 64];
+  int64_t base = (int64_t)blockIdx.x * kEnumChunk + (int64_t)threadIdx.x * kEnumPerThread;
+  int32_t hkl[kEnumPerThread][3];
+  bool keep[kEnumPerThread];
+  int64_t c = 0;
+  for (int i = 0; i < kEnumPerThread; ++i) {
+    keep[i] = base + i < p.n_cand && enum_keep(p, base + i, hkl[i]);
+    c += keep[i];
+  }
+  int64_t tot;
+  int64_t pos = block_offsets[blockIdx.x] + block_exclusive_scan(c, lds, &tot);
+  for (int i = 0; i < kEnumPerThread; ++i)
+    if (keep[i]) {
+      out[3 * pos + 0] = hkl[i][0];
+      out[3 * pos + 1] = hkl[i][1];
+      out[3 * pos + 2] = hkl[i][2];
+      ++pos;
+    }
+}
+
+static void enum_box(const fdtbx_cell* cell, double d_min, int32_t* H, int32_t* K, int32_t* L) {
+  *H = (int32_t)floor(cell->a / d_min) + 1;
+  *K = (int32_t)floor(cell->b / d_min) + 1;
+  *L = (int32_t)floor(cell->c / d_min) + 1;
+}
+
+}  // namespace fdtbx
+
+using namespace fdtbx;
+
+extern "C" int fdtbx_hkl_capacity(const fdtbx_cell* cell, double d_min, int64_t* cap) {
+  if (!cell || !cap) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null argument");
+  int rc = check_cell(cell);
+  if (rc) return rc;
+  if (!finite_pos(d_min)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "d_min must be positive and finite");
+  if (cell->a / d_min > 4096 || cell->b / d_min > 4096 || cell->c / d_min > 4096)
+    return fail(FDTBX_ERR_UNSUPPORTED, "index box larger than 4096 per axis");
+  int32_t H, K, L;
+  enum_box(cell, d_min, &H, &K, &L);
+  *cap = (int64_t)(2 * H + 1) * (2 * K + 1) * (2 * L + 1);
+  return FDTBX_OK;
+}
+
+extern "C" size_t fdtbx_enumerate_workspace(const fdtbx_cell* cell, double d_min) {
+  int64_t cap = 0;
+  if (fdtbx_hkl_capacity(cell, d_min, &cap)) return 0;
+  return (size_t)(ceil_div(cap, kEnumChunk) + 1) * sizeof(int64_t);
+}
+
+extern "C" int fdtbx_enumerate_hkl(const fdtbx_cell* cell, double d_min, double d_max, const double* extinction,
+                                   int32_t* hkl, int64_t cap, int64_t* n_out, void* ws, size_t ws_bytes,
+                                   void* stream) {
+  int64_t n_cand = 0;
+  int rc = fdtbx_hkl_capacity(cell, d_min, &n_cand);
+  if (rc) return rc;
+  if (!hkl || !n_out || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (isnan(d_max)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "d_max is NaN");
+  if (d_max > 0 && !(d_max > d_min)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "d_max must exceed d_min");
+  if (cap < n_cand) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "hkl capacity below fdtbx_hkl_capacity");
+  if (ws_bytes < fdtbx_enumerate_workspace(cell, d_min)) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "workspace too small");
+  EnumParams p;
+  make_frame(*cell, &p.f);
+  enum_box(cell, d_min, &p.H, &p.K, &p.L);
+  p.n_cand = n_cand;
+  p.t_hi = (1.0 / (d_min * d_min)) * (1.0 + 1e-9);
+  p.t_lo = d_max > 0 ? (1.0 / (d_max * d_max)) * (1.0 - 1e-9) : -1.0;
+  p.ga = p.gb = p.gc = 0.0;
+  p.ext_limit = 0.0;
+  if (extinction) {
+    for (int i = 0; i < 4; ++i)
+      if (!isfinite(extinction[i]) || extinction[i] < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "bad extinction parameters");
+    p.ga = extinction[0];
+    p.gb = extinction[1];
+    p.gc = extinction[2];
+    p.ext_limit = extinction[3];
+  }
+  hipStream_t s = (hipStream_t)stream;
+  int64_t nb = ceil_div(n_cand, kEnumChunk);
+  int64_t* counts = (int64_t*)ws;
+  hipLaunchKernelGGL(k_enum_count, dim3((unsigned)nb), dim3(kEnumThreads), 0, s, p, counts);
+  FDTBX_LAUNCH_CHECK("enumerate count");
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, counts, nb, n_out);
+  FDTBX_LAUNCH_CHECK("enumerate scan");
+  hipLaunchKernelGGL(k_enum_fill, dim3((unsigned)nb), dim3(kEnumThreads), 0, s, p, counts, hkl);
+  FDTBX_LAUNCH_CHECK("enumerate fill");
+  return FDTBX_OK;
+}
+
+namespace fdtbx {
+
+// ---------------------------------------------------------------- pixel map (Eqs. laue, cyl-average)
+struct PixParams {
+  double lam, SF, p, cx, cy;
+  int32_t W, H, tiles_x, tiles_y;
+};
+
+// Ewald point of pixel (i, j): y = ((i + 1/2) - c_x) p, z = ((j + 1/2) - c_y) p,
+// r = |(SF, y, z)|, S = (-(y^2 + z^2)/(r (r + SF)), y/r, z/r)/lambda; R = |S_xy|, Z = S_z.
+__device__ static inline void pixel_ewald(const PixParams& q, int i, int j, double* R, double* Z) {
+  double y = (((double)i + 0.5) - q.cx) * q.p;
+  double z = (((double)j + 0.5) - q.cy) * q.p;
+  double r = sqrt((q.SF * q.SF + y * y) + z * z);
+  double Sx = -(y * y + z * z) / ((r * (r + q.SF)) * q.lam);
+  double Sy = y / (r * q.lam);
+  double Sz = z / (r * q.lam);
+  *R = sqrt(Sx * Sx + Sy * Sy);
+  *Z = Sz;
+}
+
+// One 64-lane wave per FDTBX_TILE x FDTBX_TILE tile: pixel values and the tile's box.
+__global__ void __launch_bounds__(64) k_pixel_map(PixParams q, double* pix, double* tile) {
+  const int t = blockIdx.x;
+  const int tx = t % q.tiles_x, ty = t / q.tiles_x;
+  const int i = tx * FDTBX_TILE + (threadIdx.x % FDTBX_TILE);
+  const int j = ty * FDTBX_TILE + (threadIdx.x / FDTBX_TILE);
+  const bool in = i < q.W && j < q.H;
+  double R = 0, Z = 0, P2 = 0;
+  if (in) {
+    pixel_ewald(q, i, j, &R, &Z);
+    P2 = R * R + Z * Z;
+    pix[2 * ((int64_t)j * q.W + i) + 0] = R;
+    pix[2 * ((int64_t)j * q.W + i) + 1] = Z;
+  }
+  double v[6] = {in ? R : INFINITY, in ? -R : INFINITY, in ? Z : INFINITY, in ? -Z : INFINITY,
+                 in ? P2 : INFINITY, in ? -P2 : INFINITY};
+  for (int o = 32; o >= 1; o >>= 1)
+    for (int c = 0; c < 6; ++c) v[c] = fmin(v[c], __shfl_xor(v[c], o, 64));
+  if (threadIdx.x == 0) {
+    double* b = tile + 8 * (int64_t)t;
+    b[0] = v[0];
+    b[1] = -v[1];
+    b[2] = v[2];
+    b[3] = -v[3];
+    b[4] = v[4];
+    b[5] = -v[5];
+    b[6] = 0.0;
+    b[7] = 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- per-reflection records
+struct PrepParams {
+  Frame f;
+  double Nb[3], g[3];
+  double T, cmin, m, ext_limit;
+  int32_t intensity_model;
+  int64_t n;
+};
+
+__device__ static inline double dotv(const double* u, const double* v) { return (u[0] * v[0] + u[1] * v[1]) + u[2] * v[2]; }
+
+// Culling record (see the header): conservative reach of the reflection's profile in (R, Z).
+// Nodes s = r0 c (S + d1 e1 + d2 e2), |d_j| <= T, c in [cmin, 1]; query points lie in
+// the support box of a node, whose extent along v is sum_i (m/N_i)|a*_i.v| with
+// 1/N_i <= 1/N_base,i + min(pi^2 g_i^2 h_i^2, 1).
+__global__ void __launch_bounds__(256) k_prep(PrepParams p, const int32_t* __restrict__ hkl, const float* __restrict__ F2,
+                                              float* __restrict__ refl, double* __restrict__ cull) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= p.n) return;
+  const double hh[3] = {(double)hkl[3 * r + 0], (double)hkl[3 * r + 1], (double)hkl[3 * r + 2]};
+  double D[3];
+  recip(p.f, hh[0], hh[1], hh[2], D);
+  double q = (D[0] * D[0] + D[1] * D[1]) + D[2] * D[2];
+  double r0 = sqrt(q);
+  double S[3] = {D[0] / r0, D[1] / r0, D[2] / r0};
+  double RD = sqrt(D[0] * D[0] + D[1] * D[1]);
+  double e1[3], ep[3];
+  bool merid = !(RD > 1e-12);
+  if (!merid) {
+    e1[0] = -D[1] / RD;
+    e1[1] = D[0] / RD;
+    e1[2] = 0.0;
+    ep[0] = D[0] / RD;
+    ep[1] = D[1] / RD;
+    ep[2] = 0.0;
+  } else {
+    double nrm = sqrt(D[1] * D[1] + D[2] * D[2]);
+    e1[0] = 0.0;
+    e1[1] = -D[2] / nrm;
+    e1[2] = D[1] / nrm;
+    ep[0] = 0.0;
+    ep[1] = D[2] > 0 ? 1.0 : (D[2] < 0 ? -1.0 : 0.0);
+    ep[2] = 0.0;
+  }
+  double e2[3] = {S[1] * e1[2] - S[2] * e1[1], S[2] * e1[0] - S[0] * e1[2], S[0] * e1[1] - S[1] * e1[0]};
+  const double ez[3] = {0.0, 0.0, 1.0};
+
+  // ---- culling record (exact)
+  double mN[3];
+  for (int i = 0; i < 3; ++i) {
+    double t = (kPi2 * (p.g[i] * p.g[i])) * (hh[i] * hh[i]);
+    mN[i] = p.m * (1.0 / p.Nb[i] + fmin(t, 1.0));
+  }
+  auto ext = [&](const double* v) {
+    double e = (mN[0] * fabs(dotv(&p.f.s[0], v)));
+    e = e + mN[1] * fabs(dotv(&p.f.s[3], v));
+    e = e + mN[2] * fabs(dotv(&p.f.s[6], v));
+    return e;
+  };
+  auto span = [&](const double* v, double* lo_out, double* hi_out) {
+    double l0 = dotv(S, v), l1 = dotv(e1, v), l2 = dotv(e2, v);
+    double spread = p.T * (fabs(l1) + fabs(l2));
+    double lo = l0 - spread, hi = l0 + spread;
+    double s_lo = r0 * fmin(p.cmin * lo, lo);
+    double s_hi = r0 * fmax(p.cmin * hi, hi);
+    double e = ext(v);
+    *lo_out = s_lo - e;
+    *hi_out = s_hi + e;
+  };
+  double* C = cull + FDTBX_CULL_DOUBLES * r;
+  double Rlo, Rhi, Zlo, Zhi;
+  span(ep, &Rlo, &Rhi);
+  span(ez, &Zlo, &Zhi);
+  double rho_all = (mN[0] * sqrt(dotv(&p.f.s[0], &p.f.s[0])));
+  rho_all = rho_all + mN[1] * sqrt(dotv(&p.f.s[3], &p.f.s[3]));
+  rho_all = rho_all + mN[2] * sqrt(dotv(&p.f.s[6], &p.f.s[6]));
+  double a_lo = r0 - rho_all, a_hi = r0 + rho_all;
+  C[0] = Rlo;
+  C[1] = Rhi;
+  C[2] = Zlo;
+  C[3] = Zhi;
+  C[4] = a_lo > 0.0 ? a_lo * a_lo : 0.0;
+  C[5] = a_hi * a_hi;
+  if (!merid) {
+    // wedge spanned in the (R, Z) plane by the in-plane node directions S + d2 e2, |d2| <= T
+    double SR = dotv(S, ep), SZ = S[2], e2R = dotv(e2, ep), e2Z = e2[2];
+    double vmR = SR - p.T * e2R, vmZ = SZ - p.T * e2Z;
+    double vpR = SR + p.T * e2R, vpZ = SZ + p.T * e2Z;
+    double n1R = -vmZ, n1Z = vmR;
+    if (n1R * vpR + n1Z * vpZ < 0.0) {
+      n1R = -n1R;
+      n1Z = -n1Z;
+    }
+    double n2R = -vpZ, n2Z = vpR;
+    if (n2R * vmR + n2Z * vmZ < 0.0) {
+      n2R = -n2R;
+      n2Z = -n2Z;
+    }
+    double v1[3] = {n1R * ep[0], n1R * ep[1], n1R * ep[2] + n1Z};
+    double v2[3] = {n2R * ep[0], n2R * ep[1], n2R * ep[2] + n2Z};
+    C[6] = n1R;
+    C[7] = n1Z;
+    C[8] = ext(v1);
+    C[9] = n2R;
+    C[10] = n2Z;
+    C[11] = ext(v2);
+  } else {
+    C[6] = C[7] = C[9] = C[10] = 0.0;
+    C[8] = C[11] = -1.0;
+  }
+  bool alive = !(p.ext_limit > 0.0 && extinction_arg(p.g[0], p.g[1], p.g[2], hh[0], hh[1], hh[2]) > p.ext_limit);
+  C[12] = alive ? 1.0 : 0.0;
+  C[13] = C[14] = C[15] = 0.0;
+
+  // ---- profile record (float32, from binary64 values)
+  double A[3], N[3], Ip = 1.0;
+  for (int i = 0; i < 3; ++i) {
+    A[i] = exp(-2.0 * kPi2 * (p.g[i] * p.g[i]) * (hh[i] * hh[i]));
+    N[i] = 1.0 / (1.0 / p.Nb[i] + (1.0 - A[i]) / (1.0 + A[i]));
+    if (p.intensity_model) Ip *= 2.0 * A[i] / (1.0 + A[i] * A[i]);
+  }
+  float* o = refl + (int64_t)FDTBX_REFL_FLOATS * r;
+  double f2 = (double)F2[r];
+  double W = f2 * Ip;
+  const double two_pi = 2.0 * M_PI;
+  double tp6 = two_pi * two_pi * two_pi;
+  tp6 = tp6 * tp6;
+  o[RS_W] = (float)W;
+  for (int i = 0; i < 3; ++i) o[RS_N + i] = (float)N[i];
+  o[RS_R0] = (float)r0;
+  o[RS_WK] = (float)(W * r0 * r0 * N[0] * N[1] * N[2] / tp6);
+  for (int i = 0; i < 3; ++i) {
+    const double* ai = &p.f.a[3 * i];
+    o[RS_B + i] = (float)(0.5 * N[i] * r0 * dotv(ai, S));
+    o[RS_G1 + i] = (float)(0.5 * N[i] * r0 * dotv(ai, e1));
+    o[RS_G2 + i] = (float)(0.5 * N[i] * r0 * dotv(ai, e2));
+    o[RS_TR + i] = (float)(0.5 * N[i] * dotv(ai, ep));
+    o[RS_TZ + i] = (float)(0.5 * N[i] * ai[2]);
+  }
+  o[RS_IP] = (float)Ip;
+  double RDp = dotv(D, ep), ZD = D[2];
+  *(double*)(o + RS_RD) = RDp;
+  *(double*)(o + RS_ZD) = ZD;
+  o[RS_CS + 0] = (float)dotv(ep, S);
+  o[RS_CS + 1] = (float)S[2];
+  o[RS_C1 + 0] = (float)dotv(ep, e1);
+  o[RS_C1 + 1] = (float)e1[2];
+  o[RS_C2 + 0] = (float)dotv(ep, e2);
+  o[RS_C2 + 1] = (float)e2[2];
+  const double* vs[3] = {S, e1, e2};
+  for (int v = 0; v < 3; ++v) {
+    double e = 0.0;
+    for (int i = 0; i < 3; ++i) e = e + (p.m / N[i]) * fabs(dotv(&p.f.s[3 * i], vs[v]));
+    o[RS_RHO + v] = (float)e;
+  }
+  for (int i = 0; i < 3; ++i) {
+    o[RS_A + i] = (float)A[i];
+    o[RS_H + i] = (float)hh[i];
+  }
+  o[RS_F2] = (float)f2;
+  for (int k = RS_F2 + 1; k < FDTBX_REFL_FLOATS; ++k) o[k] = 0.0f;
+}
+
+// ---------------------------------------------------------------- culling
+// Superblocks of kSB x kSB tiles prefilter the reflections with the same (monotone)
+// predicate on the union box; the per-tile test then runs only over the superblock's
+// candidates and writes the exact per-tile lists in ascending order.
+static constexpr int kSB = 4;
+
+struct CullParams {
+  int32_t tiles_x, tiles_y, sb_x, sb_y;
+  int64_t n_hkl, n_words;
+};
+
+// The exact predicate of the header.  box = tile box (8 doubles), c = culling record.
+__device__ static inline bool cull_test(const double* box, const double* c) {
+  if (!(c[12] != 0.0)) return false;
+  if (!(c[0] <= box[1] && box[0] <= c[1])) return false;
+  if (!(c[2] <= box[3] && box[2] <= c[3])) return false;
+  if (!(c[4] <= box[5] && box[4] <= c[5])) return false;
+  if (c[8] >= 0.0) {
+    double m1 = fmax(c[6] * box[0], c[6] * box[1]) + fmax(c[7] * box[2], c[7] * box[3]);
+    if (!(m1 >= -c[8])) return false;
+    double m2 = fmax(c[9] * box[0], c[9] * box[1]) + fmax(c[10] * box[2], c[10] * box[3]);
+    if (!(m2 >= -c[11])) return false;
+  }
+  return true;
+}
+
+// Superblock boxes: union of the boxes of its tiles.
+__global__ void k_sb_boxes(CullParams q, const double* __restrict__ tile, double* __restrict__ sb) {
+  int s = blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= q.sb_x * q.sb_y) return;
+  int sx = s % q.sb_x, sy = s / q.sb_x;
+  double b[6] = {INFINITY, -INFINITY, INFINITY, -INFINITY, INFINITY, -INFINITY};
+  for (int dy = 0; dy < kSB; ++dy)
+    for (int dx = 0; dx < kSB; ++dx) {
+      int tx = sx * kSB + dx, ty = sy * kSB + dy;
+      if (tx >= q.tiles_x || ty >= q.tiles_y) continue;
+      const double* t = tile + 8 * ((int64_t)ty * q.tiles_x + tx);
+      for (int c = 0; c < 6; c += 2) {
+        b[c] = fmin(b[c], t[c]);
+        b[c + 1] = fmax(b[c + 1], t[c + 1]);
+      }
+    }
+  for (int c = 0; c < 6; ++c) sb[8 * (int64_t)s + c] = b[c];
+  sb[8 * (int64_t)s + 6] = 0.0;
+  sb[8 * (int64_t)s + 7] = 0.0;
+}
+
+// One wave per 64 reflections; loops over all superblocks and writes one mask word each.
+__global__ void __launch_bounds__(64) k_sb_mask(CullParams q, const double* __restrict__ sb, const double* __restrict__ cull,
+                                                uint64_t* __restrict__ mask) {
+  int64_t w = blockIdx.x;
+  int64_t r = w * 64 + threadIdx.x;
+  double c[13];
+  bool have = r < q.n_hkl;
+  for (int k = 0; k < 13; ++k) c[k] = have ? cull[FDTBX_CULL_DOUBLES * r + k] : 0.0;
+  const int nsb = q.sb_x * q.sb_y;
+  for (int s = 0; s < nsb; ++s) {
+    double box[6];
+    for (int k = 0; k < 6; ++k) box[k] = sb[8 * (int64_t)s + k];
+    bool hit = have && cull_test(box, c);
+    uint64_t m = __ballot(hit);
+    if (threadIdx.x == 0) mask[(int64_t)s * q.n_words + w] = m;
+  }
+}
+
+// One wave per tile, kSB*kSB waves per block (one superblock).  mode 0: count; mode 1: fill.
+template <int MODE>
+__global__ void __launch_bounds__(64 * kSB * kSB) k_tile_lists(CullParams q, const double* __restrict__ tile,
+                                                               const uint64_t* __restrict__ mask,
+                                                               const double* __restrict__ cull, int64_t* __restrict__ counts,
+                                                               int32_t* __restrict__ idx) {
+  const int s = blockIdx.x;
+  const int sx = s % q.sb_x, sy = s / q.sb_x;
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int tx = sx * kSB + (wv % kSB), ty = sy * kSB + (wv / kSB);
+  if (tx >= q.tiles_x || ty >= q.tiles_y) return;  // whole wave leaves; no block barrier below
+  const int64_t t = (int64_t)ty * q.tiles_x + tx;
+  double box[6];
+  for (int k = 0; k < 6; ++k) box[k] = tile[8 * t + k];
+  const uint64_t* mrow = mask + (int64_t)s * q.n_words;
+  int64_t pos = MODE ? counts[t] : 0;
+  int64_t cnt = 0;
+  for (int64_t w0 = 0; w0 < q.n_words; w0 += 64) {
+    uint64_t myword = (w0 + lane < q.n_words) ? mrow[w0 + lane] : 0ull;
+    uint64_t nz = __ballot(myword != 0ull);
+    while (nz) {
+      int src = __builtin_ctzll(nz);
+      nz &= nz - 1;
+      uint64_t word = __shfl(myword, src, 64);
+      int64_t r = (w0 + src) * 64 + lane;
+      bool hit = false;
+      if ((word >> lane) & 1ull) {
+        double c[13];
+        for (int k = 0; k < 13; ++k) c[k] = cull[FDTBX_CULL_DOUBLES * r + k];
+        hit = cull_test(box, c);
+      }
+      uint64_t hm = __ballot(hit);
+      if (MODE) {
+        if (hit) {
+          uint64_t below = lane ? (hm & ((~0ull) >> (64 - lane))) : 0ull;
+          idx[pos + __popcll(below)] = (int32_t)r;
+        }
+        pos += __popcll(hm);
+      } else {
+        cnt += __popcll(hm);
+      }
+    }
+  }
+  if (!MODE && lane == 0) counts[t] = cnt;
+}
+
+}  // namespace fdtbx
+
+using namespace fdtbx;
+
+static void pix_params(const fdtbx_geometry* g, PixParams* q) {
+  q->lam = g->wavelength;
+  q->SF = g->distance;
+  q->p = g->pixel;
+  q->cx = g->center_x;
+  q->cy = g->center_y;
+  q->W = g->width;
+  q->H = g->height;
+  q->tiles_x = (int32_t)ceil_div(g->width, FDTBX_TILE);
+  q->tiles_y = (int32_t)ceil_div(g->height, FDTBX_TILE);
+}
+
+extern "C" int fdtbx_pixel_map(const fdtbx_geometry* geom, double* pix, double* tile, void* stream) {
+  if (!geom || !pix || !tile) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  int rc = check_geometry(geom);
+  if (rc) return rc;
+  PixParams q;
+  pix_params(geom, &q);
+  int64_t n_tiles = (int64_t)q.tiles_x * q.tiles_y;
+  hipLaunchKernelGGL(k_pixel_map, dim3((unsigned)n_tiles), dim3(64), 0, (hipStream_t)stream, q, pix, tile);
+  FDTBX_LAUNCH_CHECK("pixel map");
+  return FDTBX_OK;
+}
+
+extern "C" int fdtbx_reflection_prep(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F2,
+                                     float* refl, double* cull, void* stream) {
+  if (!model || !hkl || !F2 || !refl || !cull) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be positive");
+  int rc = check_model(model);
+  if (rc) return rc;
+  PrepParams p;
+  make_frame(model->cell, &p.f);
+  for (int i = 0; i < 3; ++i) {
+    p.Nb[i] = model->dis.N_base[i];
+    p.g[i] = model->dis.g[i];
+  }
+  p.T = model->quad.T;
+  p.cmin = 1.0 / sqrt(1.0 + 2.0 * p.T * p.T);
+  p.m = (double)model->quad.m;
+  p.ext_limit = model->quad.extinction;
+  p.intensity_model = model->dis.intensity_model;
+  p.n = n_hkl;
+  hipLaunchKernelGGL(k_prep, dim3((unsigned)ceil_div(n_hkl, 256)), dim3(256), 0, (hipStream_t)stream, p, hkl, F2, refl,
+                     cull);
+  FDTBX_LAUNCH_CHECK("reflection prep");
+  return FDTBX_OK;
+}
+
+static void cull_params(const fdtbx_geometry* g, int64_t n_hkl, CullParams* q) {
+  q->tiles_x = (int32_t)ceil_div(g->width, FDTBX_TILE);
+  q->tiles_y = (int32_t)ceil_div(g->height, FDTBX_TILE);
+  q->sb_x = (int32_t)ceil_div(q->tiles_x, kSB);
+  q->sb_y = (int32_t)ceil_div(q->tiles_y, kSB);
+  q->n_hkl = n_hkl;
+  q->n_words = ceil_div(n_hkl, 64);
+}
+
+// Workspace: superblock boxes | masks | tile counts scratch.
+extern "C" size_t fdtbx_cull_workspace(const fdtbx_geometry* geom, int64_t n_hkl) {
+  if (!geom || check_geometry(geom) || n_hkl <= 0) return 0;
+  CullParams q;
+  cull_params(geom, n_hkl, &q);
+  int64_t nsb = (int64_t)q.sb_x * q.sb_y;
+  size_t b = align_up((size_t)nsb * 8 * sizeof(double), 256);
+  b += align_up((size_t)nsb * q.n_words * sizeof(uint64_t), 256);
+  b += align_up(sizeof(int64_t) * 2, 256);
+  return b;
+}
+
+extern "C" int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_t n_hkl, const double* cull,
+                          int64_t* offsets, int32_t* idx, int64_t cap, int64_t* n_pairs, void* ws, size_t ws_bytes,
+                          void* stream) {
+  if (!geom || !tile || !cull || !offsets || !n_pairs || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be positive");
+  if (n_hkl > (int64_t)INT32_MAX) return fail(FDTBX_ERR_UNSUPPORTED, "more than 2^31 reflections");
+  int rc = check_geometry(geom);
+  if (rc) return rc;
+  if (ws_bytes < fdtbx_cull_workspace(geom, n_hkl)) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "cull workspace too small");
+  CullParams q;
+  cull_params(geom, n_hkl, &q);
+  int64_t nsb = (int64_t)q.sb_x * q.sb_y;
+  int64_t n_tiles = (int64_t)q.tiles_x * q.tiles_y;
+  char* w = (char*)ws;
+  double* sb = (double*)w;
+  w += align_up((size_t)nsb * 8 * sizeof(double), 256);
+  uint64_t* mask = (uint64_t*)w;
+  w += align_up((size_t)nsb * q.n_words * sizeof(uint64_t), 256);
+  int64_t* total = (int64_t*)w;
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_sb_boxes, dim3((unsigned)ceil_div(nsb, 256)), dim3(256), 0, s, q, tile, sb);
+  FDTBX_LAUNCH_CHECK("cull superblocks");
+  hipLaunchKernelGGL(k_sb_mask, dim3((unsigned)q.n_words), dim3(64), 0, s, q, sb, cull, mask);
+  FDTBX_LAUNCH_CHECK("cull masks");
+  hipLaunchKernelGGL(k_tile_lists<0>, dim3((unsigned)nsb), dim3(64 * kSB * kSB), 0, s, q, tile, mask, cull, offsets,
+                     (int32_t*)nullptr);
+  FDTBX_LAUNCH_CHECK("cull count");
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, offsets, n_tiles, total);
+  FDTBX_LAUNCH_CHECK("cull scan");
+  int64_t h_total = 0;
+  FDTBX_HIP(hipMemcpyAsync(&h_total, total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  FDTBX_HIP(hipStreamSynchronize(s));
+  *n_pairs = h_total;
+  FDTBX_HIP(hipMemcpyAsync(offsets + n_tiles, total, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  if (h_total > cap || (h_total > 0 && !idx)) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "culling pair capacity too small");
+  if (h_total > 0) {
+    hipLaunchKernelGGL(k_tile_lists<1>, dim3((unsigned)nsb), dim3(64 * kSB * kSB), 0, s, q, tile, mask, cull, offsets,
+                       idx);
+    FDTBX_LAUNCH_CHECK("cull fill");
+  }
+  return FDTBX_OK;
+}

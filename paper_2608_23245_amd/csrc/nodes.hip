@@ -1,0 +1,157 @@
+// Node table of the shell quadrature (Eqs. gnomonic, node_weight) with the unit-peak
+// angular shapes of the section "Angular peak shapes".  Binary64 on the device,
+// stored as float32.  The Voigt shape and its width derivatives go through the
+// Faddeeva function w(z) = exp(-z^2) erfc(-i z), evaluated with Weideman's rational
+// series (J. A. C. Weideman, SIAM J. Numer. Anal. 31 (1994) 1497-1518):
+//   w(z) = 2 p(Z)/(L - i z)^2 + (1/sqrt(pi))/(L - i z),   Z = (L + i z)/(L - i z),
+//   p(Z) = sum_{n=0}^{N-1} a_{n+1} Z^n,  L = sqrt(N/sqrt(2)),
+// where a_n are the Fourier coefficients of f(theta) = exp(-t^2)(L^2 + t^2),
+// t = L tan(theta/2), obtained with the trapezoid rule on 4N points.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace fdtbx {
+
+static constexpr int kWN = 40;  // series length (relative error ~1e-13 for Im z >= 0.1)
+
+struct cplx {
+  double re, im;
+};
+__device__ static inline cplx cmul(cplx a, cplx b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ static inline cplx cdiv(cplx a, cplx b) {
+  double d = b.re * b.re + b.im * b.im;
+  return {(a.re * b.re + a.im * b.im) / d, (a.im * b.re - a.re * b.im) / d};
+}
+
+// a_{n}, n = 1..kWN, into coef[0..kWN-1]; called by threads 0..kWN-1 of a block.
+__device__ static double weideman_coef(int n, double L) {
+  const int M = 2 * kWN, M2 = 2 * M;
+  double sum = 0.0;
+  for (int k = -M + 1; k <= M - 1; ++k) {
+    double th = k * M_PI / M;
+    double t = L * tan(0.5 * th);
+    double f = exp(-t * t) * (L * L + t * t);
+    sum += f * cos(n * th);
+  }
+  return sum / M2;  // the theta = -pi sample has f = 0
+}
+
+__device__ static cplx faddeeva(cplx z, const double* coef, double L) {
+  cplx iz = {-z.im, z.re};
+  cplx den = {L - iz.re, -iz.im};          // L - i z
+  cplx num = {L + iz.re, iz.im};           // L + i z
+  cplx Z = cdiv(num, den);
+  cplx p = {coef[kWN - 1], 0.0};
+  for (int n = kWN - 2; n >= 0; --n) {
+    p = cmul(p, Z);
+    p.re += coef[n];
+  }
+  cplx d2 = cmul(den, den);
+  cplx a = cdiv({2.0 * p.re, 2.0 * p.im}, d2);
+  cplx b = cdiv({1.0 / sqrt(M_PI), 0.0}, den);
+  return {a.re + b.re, a.im + b.im};
+}
+
+// w'(z) = -2 z w(z) + 2 i/sqrt(pi)
+__device__ static inline cplx faddeeva_deriv(cplx z, cplx w) {
+  cplx zw = cmul(z, w);
+  return {-2.0 * zw.re, -2.0 * zw.im + 2.0 / sqrt(M_PI)};
+}
+
+struct NodeParams {
+  int32_t n;
+  double T, h, sigma_r, sig, gam;
+};
+
+// g and its derivatives with respect to sigma_theta and gamma_theta at angle D.
+// gamma = 0: Gaussian value; the gamma derivative is the one-sided derivative of the
+// Voigt at gamma = 0+.  sigma = 0: Lorentzian; its sigma derivative vanishes.
+__device__ static void shape(double D, double s, double g, const double* coef, double L, double* val, double* ds,
+                             double* dg) {
+  if (s == 0.0) {
+    double den = D * D + g * g;
+    *val = g * g / den;
+    *ds = 0.0;
+    *dg = 2.0 * g * D * D / (den * den);
+    return;
+  }
+  const double sq2 = sqrt(2.0);
+  double k = 1.0 / (s * sq2);
+  cplx z = {D * k, g * k};
+  cplx z0 = {0.0, g * k};
+  cplx w = faddeeva(z, coef, L), w0 = faddeeva(z0, coef, L);
+  cplx wp = faddeeva_deriv(z, w), wp0 = faddeeva_deriv(z0, w0);
+  // d z/d sigma = -z/sigma, d z/d gamma = i k
+  double u = w.re, v = w0.re;
+  double du_s = -(wp.re * z.re - wp.im * z.im) / s;
+  double dv_s = -(wp0.re * z0.re - wp0.im * z0.im) / s;
+  double du_g = -wp.im * k;
+  double dv_g = -wp0.im * k;
+  if (g == 0.0) {
+    double t = D / s;
+    *val = exp(-0.5 * t * t);
+    *ds = *val * t * t / s;
+  } else {
+    *val = u / v;
+    *ds = (du_s * v - u * dv_s) / (v * v);
+  }
+  *dg = (du_g * v - u * dv_g) / (v * v);
+}
+
+__global__ void __launch_bounds__(256) k_nodes(NodeParams p, float* __restrict__ out) {
+  __shared__ double coef[kWN];
+  const double L = sqrt(kWN / sqrt(2.0));
+  if (threadIdx.x < kWN && p.sig != 0.0) coef[threadIdx.x] = weideman_coef(threadIdx.x + 1, L);
+  __syncthreads();
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= p.n * p.n) return;
+  int i1 = k % p.n, i2 = k / p.n;
+  double d1 = -p.T + ((double)i1 + 0.5) * p.h;
+  double d2 = -p.T + ((double)i2 + 0.5) * p.h;
+  double rho2 = d1 * d1 + d2 * d2;
+  double sq = sqrt(1.0 + rho2);
+  double c = 1.0 / sq;
+  double cm1 = -rho2 / (sq * (1.0 + sq));
+  double Delta = atan(sqrt(rho2));
+  double g, gs, gg;
+  shape(Delta, p.sig, p.gam, coef, L, &g, &gs, &gg);
+  double base = p.sigma_r * sqrt(2.0 * M_PI) * c * c * c * p.h * p.h;
+  float* o = out + (int64_t)FDTBX_NODE_FLOATS * k;
+  o[0] = (float)cm1;
+  o[1] = (float)(c * d1);
+  o[2] = (float)(c * d2);
+  o[3] = (float)(base * g);
+  o[4] = (float)(base * gs);
+  o[5] = (float)(base * gg);
+  o[6] = (float)d1;
+  o[7] = (float)d2;
+}
+
+}  // namespace fdtbx
+
+using namespace fdtbx;
+
+extern "C" int fdtbx_node_table(const fdtbx_disorder* dis, const fdtbx_quadrature* quad, float* nodes, void* stream) {
+  if (!dis || !quad || !nodes) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (!(quad->n_nodes >= 1 && quad->n_nodes <= 256)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_nodes must be in 1..256");
+  if (!(quad->T > 0 && quad->T < 10)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "T must be in (0, 10)");
+  if (!(quad->sigma_r > 0) || !isfinite(quad->sigma_r)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "sigma_r must be positive");
+  if (!(dis->sigma_theta >= 0) || !(dis->gamma_theta >= 0) || !isfinite(dis->sigma_theta) || !isfinite(dis->gamma_theta))
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "angular widths must be finite and non-negative");
+  if (dis->sigma_theta == 0.0 && dis->gamma_theta == 0.0)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "sigma_theta and gamma_theta are both zero");
+  NodeParams p;
+  p.n = quad->n_nodes;
+  p.T = quad->T;
+  p.h = 2.0 * quad->T / quad->n_nodes;
+  p.sigma_r = quad->sigma_r;
+  p.sig = dis->sigma_theta;
+  p.gam = dis->gamma_theta;
+  int nn = p.n * p.n;
+  hipLaunchKernelGGL(k_nodes, dim3((unsigned)ceil_div(nn, 256)), dim3(256), 0, (hipStream_t)stream, p, nodes);
+  FDTBX_LAUNCH_CHECK("node table");
+  return FDTBX_OK;
+}

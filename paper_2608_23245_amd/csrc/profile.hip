@@ -1,0 +1,193 @@
+// Profile pattern: per pixel, the sum over the reflections of its tile list of
+// W_hkl r0^2 sum_k omega_k Z(p* - s_k) (Eq. direct_sum with Eq. I_shape and
+// N -> N_eff), times the Lorentz factor delta/(R + delta) (Eq. lorentz).
+//
+// Mapping: one 64-lane wave per 8x8 pixel tile, one lane per pixel, pixel sums in
+// registers.  Reflections of the tile list are uniform across the wave (their
+// records come through scalar loads).  For each (tile, reflection) the wave
+// bounds the node window that the tile's query points can reach, builds the
+// per-node offsets for 64 window nodes at a time (one node per lane) into LDS, and
+// then every lane walks those 64 nodes with broadcast LDS reads.
+//
+// Per (pixel, reflection) the lattice coordinates are written relative to D so
+// that nothing of size h_i is cancelled in float32:
+//   y_i = (N_i/2) a_i.(p* - s_k) = alpha_i - kappa_ik,
+//   alpha_i = (N_i/2) [(R - R_D)(a_i.e_perp) + (Z - Z_D) a_i,z]           (per pixel)
+//   kappa_ik = (N_i r0/2) [(c_k - 1) a_i.S + c_k d1 a_i.e1 + c_k d2 a_i.e2] (per node),
+// so that N_i sinc^2(N_i u_i) = N_i sin^2(2 pi y_i)/(2 pi y_i)^2 with the hardware
+// sine taking its argument in turns.  Support: max_i |y_i| <= m/2.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace fdtbx {
+
+struct ProfParams {
+  int32_t W, H, tiles_x, tiles_y;
+  int32_t n;        // nodes per side
+  float T, inv_h;   // grid half extent, 1/spacing
+  float half_m;     // m/2
+  float cmin;       // (1 + 2T^2)^(-1/2)
+  double delta;     // Lorentz regulariser
+};
+
+struct Window {
+  int i1lo, i1hi, i2lo, i2hi;
+};
+
+// Node index range that the query points of a tile box can reach.  A node in the
+// support of p satisfies |s.v - p.v| <= rho_v for v in {S, e1, e2}; s.S = r0 c is in
+// [r0 cmin, r0]; d_j = (s.e_j)/(s.S).  One extra node of margin on each side.
+__device__ static inline bool node_window(const ProfParams& q, const float* rec, float Rlo, float Rhi, float Zlo, float Zhi,
+                                          Window* w) {
+  auto range = [&](float cR, float cZ, float* lo, float* hi) {
+    float a = Rlo * cR, b = Rhi * cR, c = Zlo * cZ, d = Zhi * cZ;
+    *lo = fminf(a, b) + fminf(c, d);
+    *hi = fmaxf(a, b) + fmaxf(c, d);
+  };
+  const float r0 = rec[RS_R0];
+  float sl, sh, l1, h1, l2, h2;
+  range(rec[RS_CS], rec[RS_CS + 1], &sl, &sh);
+  range(rec[RS_C1], rec[RS_C1 + 1], &l1, &h1);
+  range(rec[RS_C2], rec[RS_C2 + 1], &l2, &h2);
+  const float rS = rec[RS_RHO] * 1.0001f, r1 = rec[RS_RHO + 1] * 1.0001f, r2 = rec[RS_RHO + 2] * 1.0001f;
+  float dlo_s = fmaxf(sl - rS, r0 * q.cmin * 0.9999f);
+  float dhi_s = fminf(sh + rS, r0 * 1.0001f);
+  if (!(dlo_s <= dhi_s)) return false;
+  auto bounds = [&](float nl, float nh, float* dlo, float* dhi) {
+    *dlo = nl >= 0.0f ? nl / dhi_s : nl / dlo_s;
+    *dhi = nh >= 0.0f ? nh / dlo_s : nh / dhi_s;
+  };
+  float d1l, d1h, d2l, d2h;
+  bounds(l1 - r1, h1 + r1, &d1l, &d1h);
+  bounds(l2 - r2, h2 + r2, &d2l, &d2h);
+  // node i sits at d = -T + (i + 1/2) h
+  auto lo_idx = [&](float d) { return (int)ceilf((d + q.T) * q.inv_h - 0.5f) - 1; };
+  auto hi_idx = [&](float d) { return (int)floorf((d + q.T) * q.inv_h - 0.5f) + 1; };
+  float big = 2.0f * q.T;
+  d1l = fmaxf(d1l, -big);
+  d2l = fmaxf(d2l, -big);
+  d1h = fminf(d1h, big);
+  d2h = fminf(d2h, big);
+  w->i1lo = max(lo_idx(d1l), 0);
+  w->i1hi = min(hi_idx(d1h), q.n - 1);
+  w->i2lo = max(lo_idx(d2l), 0);
+  w->i2hi = min(hi_idx(d2h), q.n - 1);
+  return w->i1lo <= w->i1hi && w->i2lo <= w->i2hi;
+}
+
+template <bool COUNT>
+__global__ void __launch_bounds__(64) k_profile(ProfParams q, const float* __restrict__ refl, const float* __restrict__ nodes,
+                                                const double* __restrict__ pix, const double* __restrict__ tile,
+                                                const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
+                                                float* __restrict__ image, unsigned long long* __restrict__ counts) {
+  __shared__ float4 nb[64];
+  const int t = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int tx = t % q.tiles_x, ty = t / q.tiles_x;
+  const int i = tx * FDTBX_TILE + (lane % FDTBX_TILE);
+  const int j = ty * FDTBX_TILE + (lane / FDTBX_TILE);
+  const bool in = i < q.W && j < q.H;
+  // lanes outside the detector sit far from every reflection: all supports fail
+  const double R = in ? pix[2 * ((int64_t)j * q.W + i) + 0] : 1.0e30;
+  const double Z = in ? pix[2 * ((int64_t)j * q.W + i) + 1] : 0.0;
+  const float Rlo = (float)tile[8 * (int64_t)t + 0], Rhi = (float)tile[8 * (int64_t)t + 1];
+  const float Zlo = (float)tile[8 * (int64_t)t + 2], Zhi = (float)tile[8 * (int64_t)t + 3];
+  const int64_t p0 = offsets[t], p1 = offsets[t + 1];
+  float acc = 0.0f;
+  unsigned long long cnt = 0;
+  for (int64_t pp = p0; pp < p1; ++pp) {
+    const float* rec = refl + (int64_t)FDTBX_REFL_FLOATS * idx[pp];
+    Window w;
+    if (!node_window(q, rec, Rlo, Rhi, Zlo, Zhi, &w)) continue;
+    const double RD = *(const double*)(rec + RS_RD);
+    const double ZD = *(const double*)(rec + RS_ZD);
+    const float dR = (float)(R - RD), dZ = (float)(Z - ZD);
+    const float al0 = fmaf(rec[RS_TR + 0], dR, rec[RS_TZ + 0] * dZ);
+    const float al1 = fmaf(rec[RS_TR + 1], dR, rec[RS_TZ + 1] * dZ);
+    const float al2 = fmaf(rec[RS_TR + 2], dR, rec[RS_TZ + 2] * dZ);
+    const float B0 = rec[RS_B + 0], B1 = rec[RS_B + 1], B2 = rec[RS_B + 2];
+    const float G10 = rec[RS_G1 + 0], G11 = rec[RS_G1 + 1], G12 = rec[RS_G1 + 2];
+    const float G20 = rec[RS_G2 + 0], G21 = rec[RS_G2 + 1], G22 = rec[RS_G2 + 2];
+    const int nw1 = w.i1hi - w.i1lo + 1;
+    const int nwin = nw1 * (w.i2hi - w.i2lo + 1);
+    float accr = 0.0f;
+    for (int w0 = 0; w0 < nwin; w0 += 64) {
+      const int wi = w0 + lane;
+      float4 e = make_float4(3.0e30f, 3.0e30f, 3.0e30f, 0.0f);
+      if (wi < nwin) {
+        const int i1 = w.i1lo + wi % nw1, i2 = w.i2lo + wi / nw1;
+        const float4 nd = *(const float4*)(nodes + (int64_t)FDTBX_NODE_FLOATS * (i2 * q.n + i1));
+        e.x = fmaf(nd.x, B0, fmaf(nd.y, G10, nd.z * G20));
+        e.y = fmaf(nd.x, B1, fmaf(nd.y, G11, nd.z * G21));
+        e.z = fmaf(nd.x, B2, fmaf(nd.y, G12, nd.z * G22));
+        e.w = nd.w;
+      }
+      __syncthreads();
+      nb[lane] = e;
+      __syncthreads();
+      const int m = nwin - w0 < 64 ? nwin - w0 : 64;
+      for (int jj = 0; jj < m; ++jj) {
+        const float4 nd = nb[jj];
+        float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
+        float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
+        if (mx <= q.half_m) {
+          if (COUNT) {
+            ++cnt;
+          } else {
+            ya = fmaxf(fabsf(ya), 1.0e-6f);
+            yb = fmaxf(fabsf(yb), 1.0e-6f);
+            yc = fmaxf(fabsf(yc), 1.0e-6f);
+            const float num = __builtin_amdgcn_sinf(ya) * __builtin_amdgcn_sinf(yb) * __builtin_amdgcn_sinf(yc);
+            const float rr = num * __builtin_amdgcn_rcpf(ya * yb * yc);
+            accr = fmaf(nd.w, rr * rr, accr);
+          }
+        }
+      }
+    }
+    if (!COUNT) acc = fmaf(rec[RS_WK], accr, acc);
+  }
+  if (COUNT) {
+    for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if (lane == 0 && cnt) atomicAdd(counts, cnt);
+  } else if (in) {
+    image[(int64_t)j * q.W + i] = (float)(q.delta / (R + q.delta)) * acc;
+  }
+}
+
+}  // namespace fdtbx
+
+using namespace fdtbx;
+
+extern "C" int fdtbx_profile(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
+                             const double* tile, const int64_t* offsets, const int32_t* idx, float* image, int64_t* counts,
+                             void* stream) {
+  if (!model || !refl || !nodes || !pix || !tile || !offsets || !idx) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (!counts && !image) return fail(FDTBX_ERR_INVALID_ARGUMENT, "image is NULL");
+  int rc = check_model(model);
+  if (rc) return rc;
+  ProfParams q;
+  q.W = model->geom.width;
+  q.H = model->geom.height;
+  q.tiles_x = (int32_t)ceil_div(q.W, FDTBX_TILE);
+  q.tiles_y = (int32_t)ceil_div(q.H, FDTBX_TILE);
+  q.n = model->quad.n_nodes;
+  q.T = (float)model->quad.T;
+  q.inv_h = (float)(model->quad.n_nodes / (2.0 * model->quad.T));
+  q.half_m = 0.5f * (float)model->quad.m;
+  q.cmin = (float)(1.0 / sqrt(1.0 + 2.0 * model->quad.T * model->quad.T));
+  q.delta = model->quad.delta;
+  int64_t n_tiles = (int64_t)q.tiles_x * q.tiles_y;
+  hipStream_t s = (hipStream_t)stream;
+  if (counts) {
+    hipLaunchKernelGGL(k_profile<true>, dim3((unsigned)n_tiles), dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
+                       image, (unsigned long long*)counts);
+  } else {
+    hipLaunchKernelGGL(k_profile<false>, dim3((unsigned)n_tiles), dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
+                       image, (unsigned long long*)nullptr);
+  }
+  FDTBX_LAUNCH_CHECK("profile");
+  return FDTBX_OK;
+}

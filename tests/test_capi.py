@@ -1,0 +1,87 @@
+"""The C-ABI library loads, exports every symbol include/fdtbx.h declares, and
+rejects bad arguments on the host before any launch (no GPU needed)."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fdtbx.h")
+
+
+def declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(fdtbx_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2608_23245_amd import binding as B
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("library not built (run __graft_entry__.build())")
+    return B.lib()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = declared()
+    assert "fdtbx_profile_pattern" in names and len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_binding_covers_header():
+    from paper_2608_23245_amd import binding as B
+    assert set(declared()) == set(B.exported_symbols())
+
+
+def test_host_argument_checks(lib):
+    from paper_2608_23245_amd import binding as B
+    cell = B.Cell(10, 10, 20, math.pi / 2, math.pi / 2, math.pi / 2)
+    cap = ctypes.c_int64(0)
+    assert lib.fdtbx_hkl_capacity(ctypes.byref(cell), 4.0, ctypes.byref(cap)) == 0
+    assert cap.value == (2 * 3 + 1) * (2 * 3 + 1) * (2 * 6 + 1)
+    assert lib.fdtbx_hkl_capacity(ctypes.byref(cell), 0.0, ctypes.byref(cap)) == -1
+    assert lib.fdtbx_hkl_capacity(ctypes.byref(cell), float("nan"), ctypes.byref(cap)) == -1
+    bad = B.Cell(10, 10, 20, 0.1, 0.1, 3.0)   # angles that span no parallelepiped
+    assert lib.fdtbx_hkl_capacity(ctypes.byref(bad), 4.0, ctypes.byref(cap)) == -2
+    neg = B.Cell(-1, 10, 20, 1.5, 1.5, 1.5)
+    assert lib.fdtbx_hkl_capacity(ctypes.byref(neg), 4.0, ctypes.byref(cap)) == -2
+    # null pointers and sizes are rejected before any device work
+    assert lib.fdtbx_enumerate_hkl(ctypes.byref(cell), 4.0, 30.0, None, None, 10, None, None, 0, None) == -1
+    assert lib.fdtbx_enumerate_hkl(ctypes.byref(cell), 4.0, 3.0, None, ctypes.c_void_p(8), 10 ** 6, ctypes.c_void_p(8),
+                                   ctypes.c_void_p(8), 10 ** 6, None) == -1  # d_max below d_min
+    assert lib.fdtbx_enumerate_hkl(ctypes.byref(cell), 4.0, 30.0, None, ctypes.c_void_p(8), 5, ctypes.c_void_p(8),
+                                   ctypes.c_void_p(8), 10 ** 6, None) == -3  # capacity below the box
+    msg = lib.fdtbx_error_string(-3).decode()
+    assert "capacity" in msg
+    assert lib.fdtbx_sf_workspace(0, 10) == 0
+    assert lib.fdtbx_structure_factors(ctypes.byref(cell), 10, *([None] * 7), 1, None, 10, None, None, None, 0, None) == -1
+
+
+def test_model_checks(lib):
+    import workloads as W
+    from paper_2608_23245_amd import binding as B
+    wl = W.config0()
+    m = B.make_model(wl)
+    assert lib.fdtbx_pattern_workspace(ctypes.byref(m), 150, 1000) > 0
+    for field, val in [("sigma_theta", 0.0)]:
+        m2 = B.make_model(wl)
+        setattr(m2.dis, field, val)
+        m2.dis.gamma_theta = 0.0
+        assert lib.fdtbx_pattern_workspace(ctypes.byref(m2), 150, 1000) == 0
+    m3 = B.make_model(wl)
+    m3.geom.distance = -1.0
+    assert lib.fdtbx_pattern_workspace(ctypes.byref(m3), 150, 1000) == 0
+    m4 = B.make_model(wl)
+    m4.quad.n_nodes = 0
+    assert lib.fdtbx_pattern_workspace(ctypes.byref(m4), 150, 1000) == 0
+    m5 = B.make_model(wl)
+    m5.dis.g[0] = float("nan")
+    assert lib.fdtbx_pattern_workspace(ctypes.byref(m5), 150, 1000) == 0
+    # pattern call with a workspace that is too small is rejected before any launch
+    rc = lib.fdtbx_profile_pattern(ctypes.byref(m), ctypes.c_void_p(8), 150, ctypes.c_void_p(8), ctypes.c_void_p(8), 1000,
+                                   None, ctypes.c_void_p(8), 16, None)
+    assert rc == -3

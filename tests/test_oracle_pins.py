@@ -112,11 +112,12 @@ def _atoms(x, y, z, B, occ, typ, zs=(6, 7, 8)):
     return W.Atoms(f(x), f(y), f(z), f(B), f(occ), np.asarray(typ, dtype=np.int32), W.ff_table(zs))
 
 
-def test_sf_single_atom_modulus():
+@pytest.mark.parametrize("sf", [O.structure_factors, O.structure_factors_c])
+def test_sf_single_atom_modulus(sf):
     cell = W.Cell(9, 11, 13, 90 * DEG, 100 * DEG, 90 * DEG)
     hkl = O.enumerate_hkl(cell, 2.0, 30.0)
     at = _atoms([0.123], [0.456], [0.789], [12.0], [0.7], [1])
-    F = O.structure_factors(hkl, cell, at)
+    F = sf(hkl, cell, at)
     _, astar, _ = O.frame(cell)
     # |D|^2 from the metric tensor, s = |D|/2
     D = hkl @ astar
@@ -131,7 +132,8 @@ def test_sf_single_atom_modulus():
     assert np.all(np.minimum(d, 1 - d) < 1e-10)
 
 
-def test_sf_friedel_centric_and_body_centred():
+@pytest.mark.parametrize("sf", [O.structure_factors, O.structure_factors_c])
+def test_sf_friedel_centric_and_body_centred(sf):
     cell = W.Cell(12, 12, 16, 90 * DEG, 90 * DEG, 90 * DEG)
     hkl = O.enumerate_hkl(cell, 2.5, 30.0)
     rng = np.random.default_rng(7)
@@ -139,30 +141,31 @@ def test_sf_friedel_centric_and_body_centred():
     xyz = rng.random((n, 3))
     B = rng.uniform(5, 20, n)
     typ = rng.integers(0, 3, n)
-    F = O.structure_factors(hkl, cell, _atoms(xyz[:, 0], xyz[:, 1], xyz[:, 2], B, np.ones(n), typ))
+    F = sf(hkl, cell, _atoms(xyz[:, 0], xyz[:, 1], xyz[:, 2], B, np.ones(n), typ))
     # Friedel: F(-h) = conj F(h), mate at n-1-i
     np.testing.assert_allclose(F[::-1], np.conj(F), atol=1e-9 * np.abs(F).max())
     # centrosymmetric model (atoms at +-x): F real
     cx = np.concatenate([xyz, (1.0 - xyz)])
-    Fc = O.structure_factors(hkl, cell, _atoms(cx[:, 0], cx[:, 1], cx[:, 2], np.tile(B, 2), np.ones(2 * n), np.tile(typ, 2)))
+    Fc = sf(hkl, cell, _atoms(cx[:, 0], cx[:, 1], cx[:, 2], np.tile(B, 2), np.ones(2 * n), np.tile(typ, 2)))
     assert np.abs(Fc.imag).max() < 1e-6 * np.abs(Fc.real).max()
     # body-centred pair (x, x + 1/2,1/2,1/2) with exactly representable coordinates
     base = np.round(xyz * 64) / 128
     bc = np.concatenate([base, base + 0.5])
-    Fb = O.structure_factors(hkl, cell, _atoms(bc[:, 0], bc[:, 1], bc[:, 2], np.tile(B, 2), np.ones(2 * n), np.tile(typ, 2)))
-    F1 = O.structure_factors(hkl, cell, _atoms(base[:, 0], base[:, 1], base[:, 2], B, np.ones(n), typ))
+    Fb = sf(hkl, cell, _atoms(bc[:, 0], bc[:, 1], bc[:, 2], np.tile(B, 2), np.ones(2 * n), np.tile(typ, 2)))
+    F1 = sf(hkl, cell, _atoms(base[:, 0], base[:, 1], base[:, 2], B, np.ones(n), typ))
     odd = (hkl.sum(1) % 2) != 0
     assert np.abs(Fb[odd]).max() < 1e-9 * np.abs(Fb).max()
     np.testing.assert_allclose(Fb[~odd], 2 * F1[~odd], rtol=1e-10, atol=1e-10 * np.abs(F1).max())
 
 
-def test_sf_exact_rational_phases():
+@pytest.mark.parametrize("sf", [O.structure_factors, O.structure_factors_c])
+def test_sf_exact_rational_phases(sf):
     """Coordinates on a 1/8 grid: exp(2 pi i phi) is known exactly (eighth roots of unity)."""
     cell = W.Cell(10, 10, 10, 90 * DEG, 90 * DEG, 90 * DEG)
     hkl = O.enumerate_hkl(cell, 2.0, 0.0)
     num = np.array([[1, 3, 5], [2, 7, 0], [6, 1, 4]])
     at = _atoms(num[:, 0] / 8, num[:, 1] / 8, num[:, 2] / 8, [0, 0, 0], [1, 1, 1], [0, 1, 2])
-    F = O.structure_factors(hkl, cell, at)
+    F = sf(hkl, cell, at)
     s2 = np.sum(hkl.astype(float) ** 2, 1) / 100 / 4
     roots = np.exp(2j * np.pi * np.arange(8) / 8)
     ref = np.zeros(len(hkl), complex)
