@@ -1,0 +1,170 @@
+"""Benchmark of the fibre-diffraction profile-quadrature path on one MI355X.
+
+A step is one pass of the whole forward path over the medium workload
+(40x40x60 A cell, beta 95 deg, 5000 atoms, reflections to 2 A, 1024x1024
+detector, Voigt 3 deg eta .5, Hosemann g .03 lateral, 64x64 nodes):
+reflection enumeration, structure factors, reflection preparation, node table,
+pixel map, tile culling and the profile kernel.  Inputs are seeded and
+synthetic and resident in device memory before the timed region.
+
+Prints one JSON line.  value = useful profile evaluations per second of the
+whole step (evaluations = (pixel, reflection, node) triples inside the kernel
+support, counted once by a counting pass of the same kernel).  The roofline
+object refers to the profile kernel, timed with HIP events on the stream it is
+launched on; cpu_baseline is the FP64 oracle on a bounded pixel sample of the
+same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Per useful evaluation, the issue slots of the arithmetic the method needs in
+# this formulation: 3 subtractions (lattice coordinates relative to the node),
+# 1 three-way max and 1 compare (support), 4 multiplies (sine and coordinate
+# products), 1 multiply and 1 square (ratio), 1 fused multiply-add (weighted
+# accumulate) at full rate, plus 3 sines and 1 reciprocal at quarter rate
+# (4 slots each).
+SLOTS_PER_EVAL = 12 + 4 * 4
+# 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = VALU lane issue slots per second.
+PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
+    ap.add_argument("--cpu-pixels", type=int, default=256)
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards by reflections "
+              "across GPUs with one image all-reduce, which this build does not implement.", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2608_23245_amd import atoms_to_device
+    from paper_2608_23245_amd import binding as B
+
+    torch.cuda.set_device(0)
+    wl = W.config1()
+    model = B.make_model(wl)
+    cell = model.cell
+    atoms = atoms_to_device(wl.atoms)
+    ext = (wl.dis.g[0], wl.dis.g[1], wl.dis.g[2], wl.quad.extinction)
+    stream = torch.cuda.current_stream()
+
+    state = {}
+
+    def step(timed_events=None):
+        hkl = B.enumerate_hkl(cell, wl.quad.d_min, wl.quad.d_max, extinction=ext)
+        _, F2 = B.structure_factors(cell, atoms, hkl, want_F=False)
+        refl, cull = B.reflection_prep(model, hkl, F2)
+        nodes = B.node_table(model)
+        pix, tile = B.pixel_map(model.geom)
+        off, idx = B.cull(model.geom, tile, cull, cap=state.get("cap", 1 << 24))
+        state["cap"] = int(idx.shape[0]) + 1024
+        if timed_events is not None:
+            timed_events[0].record(stream)
+        img = B.profile(model, refl, nodes, pix, tile, off, idx)
+        if timed_events is not None:
+            timed_events[1].record(stream)
+        state.update(hkl=hkl, refl=refl, nodes=nodes, pix=pix, tile=tile, off=off, idx=idx, img=img)
+        return img
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    # useful evaluations of one step (counting pass, outside the timed region)
+    n_evals = B.profile(model, state["refl"], state["nodes"], state["pix"], state["tile"], state["off"], state["idx"],
+                        count=True)
+    events = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    prof_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    img = state["img"]
+    assert torch.isfinite(img).all()
+
+    slots = n_evals * SLOTS_PER_EVAL
+    achieved = slots / (prof_ms * 1e-3) / 1e12
+    peak = PEAK_SLOTS / 1e12
+    out = {
+        "metric": "profile-quadrature evals/s & ms/pattern (fwd, fwd+bwd, batched) at stated tol",
+        "value": n_evals / (ms_step * 1e-3),
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": wl.name, "n_hkl": int(state["hkl"].shape[0]), "pixels": wl.geom.width * wl.geom.height,
+                   "nodes": wl.quad.n_nodes ** 2, "culled_pairs": int(state["idx"].shape[0]),
+                   "useful_evals_per_step": int(n_evals), "pass": "forward"},
+        "ms_per_pattern": ms_step,
+        "profile_kernel_ms": prof_ms,
+        "profile_kernel_evals_per_s": n_evals / (prof_ms * 1e-3),
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak,
+                     "traffic": None, "kernel": "k_profile<false>",
+                     "slots_per_eval": SLOTS_PER_EVAL},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(wl, state, args.cpu_pixels)
+    print(json.dumps(out), flush=True)
+
+
+def cpu_baseline(wl, state, n_pix):
+    """The FP64 oracle on a seeded sample of pixels of the same workload (all
+    reflections of their tiles' lists, oracle structure factors), in useful
+    evaluations per second."""
+    import numpy as np
+
+    from oracle import oracle as O
+    img = state["img"].cpu().numpy()
+    H, Wd = img.shape
+    rng = np.random.default_rng(12345)
+    flat = img.ravel()
+    strong = np.nonzero(flat > 1e-2 * flat.max())[0]
+    pick = np.concatenate([rng.choice(strong, n_pix // 2, replace=False), rng.choice(flat.size, n_pix - n_pix // 2,
+                                                                                      replace=False)])
+    hkl = state["hkl"].cpu().numpy()
+    tx_n = (Wd + 7) // 8
+    tiles = sorted({int((p // Wd) // 8 * tx_n + (p % Wd) // 8) for p in pick})
+    sub = np.unique(np.concatenate(O.culling_lists(wl, hkl, tiles=tiles)))
+    F = O.structure_factors_c(hkl[sub], wl.cell, wl.atoms)
+    P = O.prepare(wl, hkl=np.ascontiguousarray(hkl[sub]), F=F, cull_extinct=False)
+    R, Z = O.pixel_rz(wl.geom)
+    t0 = time.perf_counter()
+    vals, n = O.pattern_at(P, R.ravel()[pick], Z.ravel()[pick], count=True)
+    dt = time.perf_counter() - t0
+    ref = vals
+    got = flat[pick].astype(np.float64)
+    rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    return {"value": n / dt, "unit": "evals/s", "cores": O.threads(), "kind": "oracle",
+            "sample": f"{n_pix} seeded pixels of the 1024x1024 image ({n} useful evaluations, {dt:.1f} s), "
+                      f"reflections of their tiles' lists; GPU vs oracle rel-L2 on the sample {rel:.1e}"}
+
+
+if __name__ == "__main__":
+    main()

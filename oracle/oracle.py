@@ -384,6 +384,11 @@ def pattern_at(P: Prepared, R, Z, use_skip=True, count=False):
     return out
 
 
+def threads() -> int:
+    """OpenMP threads of the compiled oracle loops."""
+    return int(_c().oracle_threads())
+
+
 def profile_table(P: Prepared, R, Z):
     """Per-reflection shell-quadrature profiles I_hkl(p*) at each pixel, [n_pix][n_hkl]."""
     R = np.ascontiguousarray(np.ravel(R), dtype=np.float64)

@@ -209,3 +209,7 @@ void oracle_structure_factors(int64_t n_hkl, const int32_t* hkl, const double* s
     F_im[r] = im;
   }
 }
+
+/* Threads the OpenMP loops above use. */
+#include <omp.h>
+int oracle_threads(void) { return omp_get_max_threads(); }

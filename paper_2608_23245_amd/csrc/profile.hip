@@ -30,6 +30,8 @@ struct ProfParams {
   float T, inv_h;   // grid half extent, 1/spacing
   float half_m;     // m/2
   float cmin;       // (1 + 2T^2)^(-1/2)
+  float tiny;       // lower clamp of |y| (sinc(2y) at |y| < tiny differs from 1 by < 7e-12)
+  float margin;     // slack of the tile-level node test, in y units
   double delta;     // Lorentz regulariser
 };
 
@@ -78,12 +80,34 @@ __device__ static inline bool node_window(const ProfParams& q, const float* rec,
   return w->i1lo <= w->i1hi && w->i2lo <= w->i2hi;
 }
 
+// Per-lane evaluation of one queued node: returns omega * (prod_i sin(2 pi y_i)/y_i)^2 if the
+// node is inside this pixel's support, else 0 (and counts it in COUNT mode).
+template <bool COUNT>
+__device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1, float al2, float half_m, float tiny,
+                                          float& accr, unsigned long long& cnt) {
+  float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
+  float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
+  if (mx <= half_m) {
+    if (COUNT) {
+      ++cnt;
+    } else {
+      ya = fmaxf(fabsf(ya), tiny);
+      yb = fmaxf(fabsf(yb), tiny);
+      yc = fmaxf(fabsf(yc), tiny);
+      const float num = __builtin_amdgcn_sinf(ya) * __builtin_amdgcn_sinf(yb) * __builtin_amdgcn_sinf(yc);
+      const float rr = num * __builtin_amdgcn_rcpf(ya * yb * yc);
+      accr = fmaf(nd.w, rr * rr, accr);
+    }
+  }
+}
+
 template <bool COUNT>
 __global__ void __launch_bounds__(64) k_profile(ProfParams q, const float* __restrict__ refl, const float* __restrict__ nodes,
                                                 const double* __restrict__ pix, const double* __restrict__ tile,
                                                 const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
                                                 float* __restrict__ image, unsigned long long* __restrict__ counts) {
-  __shared__ float4 nb[64];
+  // queue of window nodes that can be inside the support of some pixel of the tile
+  __shared__ float4 qn[128];
   const int t = blockIdx.x;
   const int lane = threadIdx.x;
   const int tx = t % q.tiles_x, ty = t / q.tiles_x;
@@ -93,9 +117,11 @@ __global__ void __launch_bounds__(64) k_profile(ProfParams q, const float* __res
   // lanes outside the detector sit far from every reflection: all supports fail
   const double R = in ? pix[2 * ((int64_t)j * q.W + i) + 0] : 1.0e30;
   const double Z = in ? pix[2 * ((int64_t)j * q.W + i) + 1] : 0.0;
-  const float Rlo = (float)tile[8 * (int64_t)t + 0], Rhi = (float)tile[8 * (int64_t)t + 1];
-  const float Zlo = (float)tile[8 * (int64_t)t + 2], Zhi = (float)tile[8 * (int64_t)t + 3];
+  const double bRlo = tile[8 * (int64_t)t + 0], bRhi = tile[8 * (int64_t)t + 1];
+  const double bZlo = tile[8 * (int64_t)t + 2], bZhi = tile[8 * (int64_t)t + 3];
+  const float Rlo = (float)bRlo, Rhi = (float)bRhi, Zlo = (float)bZlo, Zhi = (float)bZhi;
   const int64_t p0 = offsets[t], p1 = offsets[t + 1];
+  const float tiny = q.tiny;
   float acc = 0.0f;
   unsigned long long cnt = 0;
   for (int64_t pp = p0; pp < p1; ++pp) {
@@ -105,18 +131,30 @@ __global__ void __launch_bounds__(64) k_profile(ProfParams q, const float* __res
     const double RD = *(const double*)(rec + RS_RD);
     const double ZD = *(const double*)(rec + RS_ZD);
     const float dR = (float)(R - RD), dZ = (float)(Z - ZD);
-    const float al0 = fmaf(rec[RS_TR + 0], dR, rec[RS_TZ + 0] * dZ);
-    const float al1 = fmaf(rec[RS_TR + 1], dR, rec[RS_TZ + 1] * dZ);
-    const float al2 = fmaf(rec[RS_TR + 2], dR, rec[RS_TZ + 2] * dZ);
+    float tr[3], tz[3], al[3], lo[3], hi[3];
+    // tile range of alpha_i (linear in R, Z: extremes at the box corners), widened by m/2
+    const float dRl = (float)(bRlo - RD), dRh = (float)(bRhi - RD);
+    const float dZl = (float)(bZlo - ZD), dZh = (float)(bZhi - ZD);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      tr[a] = rec[RS_TR + a];
+      tz[a] = rec[RS_TZ + a];
+      al[a] = fmaf(tr[a], dR, tz[a] * dZ);
+      const float r1 = tr[a] * dRl, r2 = tr[a] * dRh, z1 = tz[a] * dZl, z2 = tz[a] * dZh;
+      lo[a] = fminf(r1, r2) + fminf(z1, z2) - q.half_m - q.margin;
+      hi[a] = fmaxf(r1, r2) + fmaxf(z1, z2) + q.half_m + q.margin;
+    }
     const float B0 = rec[RS_B + 0], B1 = rec[RS_B + 1], B2 = rec[RS_B + 2];
     const float G10 = rec[RS_G1 + 0], G11 = rec[RS_G1 + 1], G12 = rec[RS_G1 + 2];
     const float G20 = rec[RS_G2 + 0], G21 = rec[RS_G2 + 1], G22 = rec[RS_G2 + 2];
     const int nw1 = w.i1hi - w.i1lo + 1;
     const int nwin = nw1 * (w.i2hi - w.i2lo + 1);
     float accr = 0.0f;
+    int qlen = 0;  // uniform
     for (int w0 = 0; w0 < nwin; w0 += 64) {
       const int wi = w0 + lane;
-      float4 e = make_float4(3.0e30f, 3.0e30f, 3.0e30f, 0.0f);
+      float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+      bool keep = false;
       if (wi < nwin) {
         const int i1 = w.i1lo + wi % nw1, i2 = w.i2lo + wi / nw1;
         const float4 nd = *(const float4*)(nodes + (int64_t)FDTBX_NODE_FLOATS * (i2 * q.n + i1));
@@ -124,29 +162,25 @@ __global__ void __launch_bounds__(64) k_profile(ProfParams q, const float* __res
         e.y = fmaf(nd.x, B1, fmaf(nd.y, G11, nd.z * G21));
         e.z = fmaf(nd.x, B2, fmaf(nd.y, G12, nd.z * G22));
         e.w = nd.w;
+        keep = e.x >= lo[0] && e.x <= hi[0] && e.y >= lo[1] && e.y <= hi[1] && e.z >= lo[2] && e.z <= hi[2];
       }
+      const unsigned long long b = __ballot(keep);
+      if (keep) {
+        const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
+        qn[pos] = e;
+      }
+      qlen += __popcll(b);
       __syncthreads();
-      nb[lane] = e;
-      __syncthreads();
-      const int m = nwin - w0 < 64 ? nwin - w0 : 64;
-      for (int jj = 0; jj < m; ++jj) {
-        const float4 nd = nb[jj];
-        float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
-        float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
-        if (mx <= q.half_m) {
-          if (COUNT) {
-            ++cnt;
-          } else {
-            ya = fmaxf(fabsf(ya), 1.0e-6f);
-            yb = fmaxf(fabsf(yb), 1.0e-6f);
-            yc = fmaxf(fabsf(yc), 1.0e-6f);
-            const float num = __builtin_amdgcn_sinf(ya) * __builtin_amdgcn_sinf(yb) * __builtin_amdgcn_sinf(yc);
-            const float rr = num * __builtin_amdgcn_rcpf(ya * yb * yc);
-            accr = fmaf(nd.w, rr * rr, accr);
-          }
-        }
+      if (qlen >= 64) {
+        for (int jj = 0; jj < 64; ++jj) eval_node<COUNT>(qn[jj], al[0], al[1], al[2], q.half_m, tiny, accr, cnt);
+        qlen -= 64;
+        __syncthreads();
+        if (lane < qlen) qn[lane] = qn[64 + lane];
+        __syncthreads();
       }
     }
+    for (int jj = 0; jj < qlen; ++jj) eval_node<COUNT>(qn[jj], al[0], al[1], al[2], q.half_m, tiny, accr, cnt);
+    __syncthreads();
     if (!COUNT) acc = fmaf(rec[RS_WK], accr, acc);
   }
   if (COUNT) {
@@ -178,6 +212,8 @@ extern "C" int fdtbx_profile(const fdtbx_model* model, const float* refl, const 
   q.inv_h = (float)(model->quad.n_nodes / (2.0 * model->quad.T));
   q.half_m = 0.5f * (float)model->quad.m;
   q.cmin = (float)(1.0 / sqrt(1.0 + 2.0 * model->quad.T * model->quad.T));
+  q.tiny = 1.0e-6f;
+  q.margin = 1.0e-3f;
   q.delta = model->quad.delta;
   int64_t n_tiles = (int64_t)q.tiles_x * q.tiles_y;
   hipStream_t s = (hipStream_t)stream;
