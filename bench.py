@@ -36,6 +36,25 @@ SLOTS_PER_EVAL = 12 + 4 * 4
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 
 
+def measured_traffic():
+    """HBM bytes per launch of the profile kernel from the committed counter summary,
+    or None when the kernel source has changed since the counters were taken."""
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_2608_23245_amd", "csrc", "profile.hip")
+    summ = os.path.join(ROOT, "profiles", "k_profile_medium_traffic.md")
+    try:
+        text = open(summ).read()
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    except OSError:
+        return None
+    m = re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text)
+    h = re.search(r"profile.hip sha256 prefix at measurement: ([0-9a-f]+)", text)
+    if not m or not h or h.group(1) != sha:
+        return None
+    return float(m.group(1))
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -43,6 +62,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-pixels", type=int, default=256)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="also run one device-to-device copy of this many MiB (reference kernel for the "
+                         "FETCH_SIZE/WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -85,12 +107,17 @@ def main():
         state.update(hkl=hkl, refl=refl, nodes=nodes, pix=pix, tile=tile, off=off, idx=idx, img=img)
         return img
 
+    if args.copy_calibration > 0:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
-    # useful evaluations of one step (counting pass, outside the timed region)
-    n_evals = B.profile(model, state["refl"], state["nodes"], state["pix"], state["tile"], state["off"], state["idx"],
-                        count=True)
     events = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -102,6 +129,9 @@ def main():
     prof_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
     img = state["img"]
     assert torch.isfinite(img).all()
+    # useful evaluations of one step (counting pass of the same kernel, after the timed region)
+    n_evals = B.profile(model, state["refl"], state["nodes"], state["pix"], state["tile"], state["off"], state["idx"],
+                        count=True)
 
     slots = n_evals * SLOTS_PER_EVAL
     achieved = slots / (prof_ms * 1e-3) / 1e12
@@ -126,7 +156,7 @@ def main():
         "profile_kernel_ms": prof_ms,
         "profile_kernel_evals_per_s": n_evals / (prof_ms * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak,
-                     "traffic": None, "kernel": "k_profile<false>",
+                     "traffic": measured_traffic(), "kernel": "k_profile<false>",
                      "slots_per_eval": SLOTS_PER_EVAL},
     }
     if not args.no_cpu:
