@@ -225,6 +225,63 @@ int fdtbx_profile_pattern(const fdtbx_model* model, const int32_t* hkl, int64_t 
                           float* image, int64_t pair_cap, int64_t* pairs_needed, void* ws, size_t ws_bytes,
                           void* stream);
 
+/* ------------------------------------------------------------------ adjoint
+ * Gradients of a scalar L through the image, given G = dL/dimage (float32 [height][width],
+ * device).  The parameters are the atoms (fractional x, y, z, B, occupancy), the angular
+ * widths sigma_theta, gamma_theta, N_base[3] and g[3]; T stays fixed.  Profile values are
+ * recomputed tile by tile, never stored.
+ *
+ * fdtbx_profile_adjoint: per reflection r, over the pixels of the tiles that list r and the
+ * nodes inside the support (same lists, windows and kernel as fdtbx_profile),
+ *   sums[r][0] = sum G L(R) sum_k omega_k Z'_k            Z' = prod_i sinc^2(N_i u_i)
+ *   sums[r][1] = sum G L(R) sum_k (d omega_k/d sigma_theta) Z'_k
+ *   sums[r][2] = sum G L(R) sum_k (d omega_k/d gamma_theta) Z'_k
+ *   sums[r][3+i] = sum G L(R) sum_k omega_k D_ik,  D_ik = d[N_i sinc^2(N_i u_i)]/dN_i prod_{j!=i} sinc^2
+ * each up to the factor (2 pi)^6 folded into the reflection record.  sums: device float64
+ * [n_hkl][6], zeroed by the call, then accumulated with binary64 atomic adds (the result
+ * depends on the order of those adds only below binary64 rounding). */
+int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
+                          const double* tile, const int64_t* offsets, const int32_t* idx, int64_t n_hkl,
+                          const float* grad_image, double* sums, void* stream);
+
+/* fdtbx_adjoint_finish: chain rule per reflection in binary64 (Eqs. Ah, Neff, Ipara):
+ *   dF2[r] = dL/d|F|^2 (device float32 [n_hkl] output, may be NULL)
+ *   d_globals = dL/d(sigma_theta, gamma_theta, N_base a, b, c, g a, b, c) (device float64 [8])
+ * from the sums of fdtbx_profile_adjoint, the reflection records and F (device float32
+ * [n_hkl][2]).  The globals are reduced over reflections in a fixed order.
+ *   ws: device workspace of fdtbx_adjoint_finish_workspace(n_hkl) bytes */
+size_t fdtbx_adjoint_finish_workspace(int64_t n_hkl);
+int fdtbx_adjoint_finish(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* refl,
+                         const double* sums, const float* F, float* dF2, double* d_globals, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* fdtbx_sf_adjoint: gradients of L through |F|^2 with respect to the atoms (Eq.
+ * structure_factor): with t_j = occ_j f(s) exp(-B_j s^2) exp(2 pi i h.x_j),
+ *   dL/dx_j = sum_r dF2_r 2 Re(F_r* 2 pi i h t_j)   (fractional x; y with k, z with l)
+ *   dL/dB_j = sum_r dF2_r 2 Re(-s^2 F_r* t_j),  dL/docc_j = sum_r dF2_r 2 Re(F_r* t_j/occ_j)
+ * Outputs device float32 [n_atoms] each (any may be NULL).  Deterministic (fixed-order
+ * partial sums).  ws: device workspace of fdtbx_sf_adjoint_workspace(n_hkl, n_atoms) bytes. */
+size_t fdtbx_sf_adjoint_workspace(int64_t n_hkl, int64_t n_atoms);
+int fdtbx_sf_adjoint(const fdtbx_cell* cell, int64_t n_atoms, const float* x, const float* y, const float* z,
+                     const float* B, const float* occ, const int32_t* type, const float* ff, int32_t n_types,
+                     const int32_t* hkl, int64_t n_hkl, const float* F, const float* dF2, float* d_x, float* d_y,
+                     float* d_z, float* d_B, float* d_occ, void* ws, size_t ws_bytes, void* stream);
+
+/* fdtbx_pattern_backward: the three steps above after a successful fdtbx_profile_pattern
+ * call with the same model, hkl, n_hkl and pair_cap, whose workspace fwd_ws still holds the
+ * reflection records, node table, pixel map and culling lists.  F: the structure factors
+ * whose |F|^2 the forward used.  Atom arrays as in fdtbx_structure_factors; gradient
+ * outputs as in fdtbx_sf_adjoint (all five NULL skips the atom adjoint); d_globals as in
+ * fdtbx_adjoint_finish; dF2 optional.  ws: device workspace of
+ * fdtbx_backward_workspace(n_hkl, n_atoms) bytes. */
+size_t fdtbx_backward_workspace(int64_t n_hkl, int64_t n_atoms);
+int fdtbx_pattern_backward(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F,
+                           const float* grad_image, const void* fwd_ws, size_t fwd_ws_bytes, int64_t pair_cap,
+                           int64_t n_atoms, const float* x, const float* y, const float* z, const float* B,
+                           const float* occ, const int32_t* type, const float* ff, int32_t n_types, float* d_x,
+                           float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals, float* dF2, void* ws,
+                           size_t ws_bytes, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

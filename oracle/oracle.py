@@ -413,6 +413,119 @@ def pattern(wl, P: Prepared = None, use_skip=True, count=False):
     return res.reshape(R.shape)
 
 
+# --------------------------------------------------------------------------- adjoint
+def angular_shape_derivs(delta, sigma_theta, gamma_theta):
+    """d g/d sigma_theta and d g/d gamma_theta of the unit-peak angular weight, by
+    Richardson-extrapolated central differences of angular_shape (forward differences at a
+    width that is zero, where the Gaussian or Lorentzian branch is the boundary value)."""
+    delta = np.asarray(delta, dtype=np.float64)
+
+    def d_dwidth(which):
+        base = sigma_theta if which == 0 else gamma_theta
+        scale = max(sigma_theta, gamma_theta)
+
+        def g(v):
+            return angular_shape(delta, v, gamma_theta) if which == 0 else angular_shape(delta, sigma_theta, v)
+
+        if base > 0.0:
+            def D(h):
+                return (g(base + h) - g(base - h)) / (2.0 * h)
+            h = 1e-3 * base
+            return (4.0 * D(h / 2) - D(h)) / 3.0
+        # one-sided at zero width: second-order forward difference
+        h = 1e-6 * scale
+        return (-3.0 * g(0.0) + 4.0 * g(h) - g(2.0 * h)) / (2.0 * h)
+
+    return d_dwidth(0), d_dwidth(1)
+
+
+def node_weight_derivs(nodes: Nodes, sigma_r, sigma_theta, gamma_theta):
+    """d omega/d sigma_theta and d omega/d gamma_theta (Eq. node_weight, T held fixed)."""
+    dgs, dgg = angular_shape_derivs(nodes.Delta, sigma_theta, gamma_theta)
+    base = sigma_r * math.sqrt(2.0 * math.pi) * nodes.c ** 3 * nodes.h * nodes.h
+    return base * dgs, base * dgg
+
+
+def grad_sums(P: Prepared, domega_ds, domega_dg, R, Z, G, use_skip=True):
+    """Per reflection: [dL/dW, sum W-free terms for sigma, gamma, N_a, N_b, N_c] of
+    L = sum_q G_q P_q over the pixels listed by (R, Z, G) (see oracle_grad_sums)."""
+    R = np.ascontiguousarray(np.ravel(R), dtype=np.float64)
+    Z = np.ascontiguousarray(np.ravel(Z), dtype=np.float64)
+    G = np.ascontiguousarray(np.ravel(G), dtype=np.float64)
+    ds = np.ascontiguousarray(domega_ds, dtype=np.float64)
+    dg = np.ascontiguousarray(domega_dg, dtype=np.float64)
+    out = np.zeros((P.hkl.shape[0], 6))
+    prob, keep = _c_problem(P, use_skip)
+    vp = lambda a: ctypes.c_void_p(a.ctypes.data)
+    _c().oracle_grad_sums(ctypes.byref(prob), vp(ds), vp(dg), ctypes.c_int64(R.shape[0]), vp(R), vp(Z), vp(G), vp(out))
+    del keep
+    return out
+
+
+def sf_adjoint(hkl, cell, atoms, F, dF2):
+    """Gradients of L through |F|^2 with dL/d|F|^2 = dF2 per reflection, for each atom:
+    d|F|^2/dx_j = 2 Re(F* dF/dx_j), dF/dx_j = 2 pi i h t_j (fractional x; likewise y with k,
+    z with l), dF/dB_j = -s^2 t_j, dF/docc_j = t_j/occ_j, t_j = occ_j f_j(s) exp(-B_j s^2)
+    exp(2 pi i (h x_j + k y_j + l z_j)) (Eq. structure_factor)."""
+    _, astar, _ = frame(cell)
+    s2 = q_of(recip_vectors(hkl, astar)) / 4.0
+    x, y, z = (atoms.x.astype(np.float64), atoms.y.astype(np.float64), atoms.z.astype(np.float64))
+    B, occ, ff = atoms.B.astype(np.float64), atoms.occ.astype(np.float64), atoms.ff.astype(np.float64)
+    n = x.shape[0]
+    out = {k: np.zeros(n) for k in ("x", "y", "z", "B", "occ")}
+    for i0 in range(0, hkl.shape[0], 1024):
+        sl = slice(i0, i0 + 1024)
+        hh = hkl[sl].astype(np.float64)
+        f = np.zeros((hh.shape[0], ff.shape[0]))
+        for t in range(ff.shape[0]):
+            f[:, t] = ff[t, 8]
+            for g in range(4):
+                f[:, t] += ff[t, g] * np.exp(-ff[t, 4 + g] * s2[sl])
+        phase = (hh[:, 0:1] * x[None, :] + hh[:, 1:2] * y[None, :]) + hh[:, 2:3] * z[None, :]
+        phase = phase - np.floor(phase)
+        t_over_occ = f[:, atoms.type] * np.exp(-B[None, :] * s2[sl][:, None]) * np.exp(2j * np.pi * phase)
+        Fc = np.conj(F[sl])[:, None]
+        w = dF2[sl][:, None]
+        prod = Fc * t_over_occ             # F* t_j / occ_j
+        out["x"] += np.sum(w * 2.0 * np.real(2j * np.pi * hh[:, 0:1] * prod), axis=0) * occ
+        out["y"] += np.sum(w * 2.0 * np.real(2j * np.pi * hh[:, 1:2] * prod), axis=0) * occ
+        out["z"] += np.sum(w * 2.0 * np.real(2j * np.pi * hh[:, 2:3] * prod), axis=0) * occ
+        out["B"] += np.sum(w * 2.0 * np.real(-s2[sl][:, None] * prod), axis=0) * occ
+        out["occ"] += np.sum(w * 2.0 * np.real(prod), axis=0)
+    return out
+
+
+def gradients(wl, P: Prepared, G, R=None, Z=None, use_skip=True):
+    """Gradients of L = sum_pixels G * image with respect to the atoms (fractional x, y, z,
+    B, occupancy) and the globals sigma_theta, gamma_theta, N_base (3), g (3), with T held
+    fixed.  Chain: W = |F|^2 I_para, N_eff from Eq. Neff, I_para from Eq. Ipara,
+    A_i = exp(-2 pi^2 g_i^2 h_i^2) (Eq. Ah)."""
+    if R is None:
+        R, Z = pixel_rz(wl.geom)
+    nd = P.nodes
+    ds, dg = node_weight_derivs(nd, wl.quad.sigma_r, wl.dis.sigma_theta, wl.dis.gamma_theta)
+    sums = grad_sums(P, ds, dg, R, Z, G, use_skip=use_skip)
+    dW = sums[:, 0]
+    d_sigma = float(np.sum(P.W * sums[:, 1]))
+    d_gamma = float(np.sum(P.W * sums[:, 2]))
+    dN = P.W[:, None] * sums[:, 3:6]                       # dL/dN_eff per reflection and axis
+    Nb = np.asarray(wl.dis.N_base, dtype=np.float64)
+    d_Nbase = np.sum(dN * P.N ** 2 / Nb[None, :] ** 2, axis=0)
+    F2 = P.F.real ** 2 + P.F.imag ** 2
+    dIp = dW * F2
+    A = P.A
+    dN_dA = 2.0 * P.N ** 2 / (1.0 + A) ** 2
+    dA = dN * dN_dA
+    if wl.dis.intensity_model:
+        dA = dA + (dIp * P.Ip)[:, None] * (1.0 - A * A) / (A * (1.0 + A * A))
+    g = np.asarray(wl.dis.g, dtype=np.float64)
+    h2 = P.hkl.astype(np.float64) ** 2
+    d_g = np.sum(dA * (-4.0 * PI2 * g[None, :] * h2 * A), axis=0)
+    atom = sf_adjoint(P.hkl, wl.cell, wl.atoms, P.F, dW * P.Ip)
+    return {"atoms": atom, "sigma_theta": d_sigma, "gamma_theta": d_gamma, "N_base": d_Nbase, "g": d_g,
+            "dW": dW, "sums": sums}
+
+
 # --------------------------------------------------------------------------- culling contract
 def tile_boxes(geom, tile_w=8, tile_h=8):
     """Per tile of tile_w x tile_h pixels (clipped at the detector edge), the ranges

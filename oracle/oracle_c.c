@@ -183,6 +183,70 @@ void oracle_profile_table(const oracle_problem* P, int64_t n_pix, const double* 
   }
 }
 
+/* d/dN [N sinc^2(N u)] = sin(2 pi N u)/(pi u N) - sin^2(pi N u)/(pi^2 u^2 N^2); at u = 0 it is 1. */
+static double laue_axis_dN(double N, double u) {
+  if (u == 0.0) return 1.0;
+  double s = sin(M_PI * N * u);
+  return sin(2.0 * M_PI * N * u) / (M_PI * u * N) - s * s / (M_PI * M_PI * u * u * N * N);
+}
+
+/* Adjoint sums of the image for a pixel weight G (dL/dP at each listed pixel).  For every
+ * reflection h, over the listed pixels q and the nodes k inside the support at p*_qh:
+ *   out[h][0] = sum_q G_q L(R_q) r0^2 sum_k omega_k Z_k              (= dL/dW_h)
+ *   out[h][1] = sum_q G_q L(R_q) r0^2 sum_k domega_k/dsigma Z_k
+ *   out[h][2] = sum_q G_q L(R_q) r0^2 sum_k domega_k/dgamma Z_k
+ *   out[h][3+i] = sum_q G_q L(R_q) r0^2 sum_k omega_k dZ_k/dN_i     (i = a, b, c)
+ * with Z_k = prod_i N_i sinc^2(N_i u_i) (Eq. I_shape).  The support boundary moves with N_i
+ * but Z has a double zero there, so it adds nothing. */
+void oracle_grad_sums(const oracle_problem* P, const double* domega_ds, const double* domega_dg, int64_t n_pix,
+                      const double* R, const double* Z, const double* G, double* out) {
+  double theta_nodes = nodes_max_angle(P);
+#pragma omp parallel for schedule(dynamic, 4)
+  for (int64_t h = 0; h < P->n_hkl; ++h) {
+    const double r0 = P->r0[h];
+    const double* S = &P->S[3 * h];
+    const double* e1 = &P->e1[3 * h];
+    const double* e2 = &P->e2[3 * h];
+    const double* N = &P->N[3 * h];
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t q = 0; q < n_pix; ++q) {
+      if (G[q] == 0.0) continue;
+      double p[3];
+      query_point(P, h, R[q], Z[q], p);
+      if (P->use_skip && provably_empty(P, h, p, theta_nodes)) continue;
+      double wq = G[q] * (P->delta / (R[q] + P->delta)) * r0 * r0;
+      double a[6] = {0, 0, 0, 0, 0, 0};
+      for (int64_t k = 0; k < P->n_nodes; ++k) {
+        double d1 = P->d1[k], d2 = P->d2[k];
+        double c = 1.0 / sqrt(1.0 + d1 * d1 + d2 * d2);
+        double x[3];
+        for (int j = 0; j < 3; ++j) x[j] = p[j] - r0 * c * (S[j] + d1 * e1[j] + d2 * e2[j]);
+        double u[3];
+        int inside = 1;
+        for (int i = 0; i < 3; ++i) {
+          u[i] = dot3(&P->avec[3 * i], x);
+          if (fabs(u[i]) > P->m / N[i]) inside = 0;
+        }
+        if (!inside) continue;
+        double f[3], df[3];
+        for (int i = 0; i < 3; ++i) {
+          f[i] = laue_axis(N[i], u[i]);
+          df[i] = laue_axis_dN(N[i], u[i]);
+        }
+        double Zk = f[0] * f[1] * f[2];
+        a[0] += P->omega[k] * Zk;
+        a[1] += domega_ds[k] * Zk;
+        a[2] += domega_dg[k] * Zk;
+        a[3] += P->omega[k] * df[0] * f[1] * f[2];
+        a[4] += P->omega[k] * f[0] * df[1] * f[2];
+        a[5] += P->omega[k] * f[0] * f[1] * df[2];
+      }
+      for (int i = 0; i < 6; ++i) acc[i] += wq * a[i];
+    }
+    for (int i = 0; i < 6; ++i) out[6 * h + i] = acc[i];
+  }
+}
+
 /* Structure factors (Eq. structure_factor with the isotropic Debye-Waller factor):
  * F = sum_j occ_j f_t(s) exp(-B_j s^2) (cos 2 pi phi + i sin 2 pi phi), phi = (h x + k y + l z) mod 1,
  * s^2 = |D|^2/4 given per reflection, f_t(s) = sum_g a_g exp(-b_g s^2) + c from ff[t][9]. */

@@ -84,6 +84,20 @@ _SIGS = {
     "fdtbx_profile_pattern": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_size_t, ctypes.c_void_p]),
+    "fdtbx_profile_adjoint": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                                                      ctypes.c_void_p]),
+    "fdtbx_adjoint_finish_workspace": (ctypes.c_size_t, [ctypes.c_int64]),
+    "fdtbx_adjoint_finish": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64] + [ctypes.c_void_p] * 6 +
+                             [ctypes.c_size_t, ctypes.c_void_p]),
+    "fdtbx_sf_adjoint_workspace": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64]),
+    "fdtbx_sf_adjoint": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64] + [ctypes.c_void_p] * 7 +
+                         [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64] + [ctypes.c_void_p] * 8 +
+                         [ctypes.c_size_t, ctypes.c_void_p]),
+    "fdtbx_backward_workspace": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64]),
+    "fdtbx_pattern_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64,
+                                              ctypes.c_int64] + [ctypes.c_void_p] * 7 + [ctypes.c_int32] +
+                               [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
 }
 
 
@@ -290,3 +304,73 @@ class PatternPlan:
             self.pairs = int(need.value)
             return out
         raise FdtbxError(-3, "pattern workspace")
+
+
+# ----------------------------------------------------------------------------- adjoint
+GLOBAL_NAMES = ("sigma_theta", "gamma_theta", "N_base_a", "N_base_b", "N_base_c", "g_a", "g_b", "g_c")
+
+
+def profile_adjoint(model: Model, refl, nodes, pix, tile, offsets, idx, grad_image: torch.Tensor) -> torch.Tensor:
+    """fdtbx_profile_adjoint: per-reflection sums float64 [n_hkl][6]."""
+    n = int(refl.shape[0])
+    _dev(grad_image, torch.float32, "grad_image")
+    sums = torch.empty((n, 6), dtype=torch.float64, device=refl.device)
+    _check(lib().fdtbx_profile_adjoint(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(tile), _ptr(offsets),
+                                       _ptr(idx), n, _ptr(grad_image), _ptr(sums), _stream()))
+    return sums
+
+
+def adjoint_finish(model: Model, hkl, refl, sums, F):
+    """fdtbx_adjoint_finish: (dF2 float32 [n], d_globals float64 [8])."""
+    L = lib()
+    n = int(hkl.shape[0])
+    dF2 = torch.empty(n, dtype=torch.float32, device=hkl.device)
+    glob = torch.empty(8, dtype=torch.float64, device=hkl.device)
+    wsb = L.fdtbx_adjoint_finish_workspace(n)
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=hkl.device)
+    _check(L.fdtbx_adjoint_finish(ctypes.byref(model), _ptr(hkl), n, _ptr(refl), _ptr(sums), _ptr(F), _ptr(dF2), _ptr(glob),
+                                  _ptr(ws), wsb, _stream()))
+    return dF2, glob
+
+
+def sf_adjoint(cell: Cell, atoms: dict, hkl, F, dF2):
+    """fdtbx_sf_adjoint: dict of float32 [n_atoms] gradients x, y, z (fractional), B, occ."""
+    L = lib()
+    n_hkl = int(hkl.shape[0])
+    n_atoms = int(atoms["x"].shape[0])
+    dev = hkl.device
+    out = {k: torch.empty(n_atoms, dtype=torch.float32, device=dev) for k in ("x", "y", "z", "B", "occ")}
+    wsb = L.fdtbx_sf_adjoint_workspace(n_hkl, n_atoms)
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=dev)
+    _check(L.fdtbx_sf_adjoint(ctypes.byref(cell), n_atoms, _ptr(atoms["x"]), _ptr(atoms["y"]), _ptr(atoms["z"]),
+                              _ptr(atoms["B"]), _ptr(atoms["occ"]), _ptr(atoms["type"]), _ptr(atoms["ff"]),
+                              int(atoms["ff"].shape[0]), _ptr(hkl), n_hkl, _ptr(F), _ptr(dF2), _ptr(out["x"]),
+                              _ptr(out["y"]), _ptr(out["z"]), _ptr(out["B"]), _ptr(out["occ"]), _ptr(ws), wsb,
+                              _stream()))
+    return out
+
+
+def pattern_backward(plan: "PatternPlan", hkl, F, grad_image, atoms: Optional[dict]):
+    """fdtbx_pattern_backward after plan.run(hkl, |F|^2): (atom gradients dict or None,
+    d_globals float64 [8], dF2 float32 [n_hkl])."""
+    L = lib()
+    n_hkl = plan.n_hkl
+    dev = hkl.device
+    n_atoms = int(atoms["x"].shape[0]) if atoms is not None else 0
+    wsb = L.fdtbx_backward_workspace(n_hkl, n_atoms)
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=dev)
+    glob = torch.empty(8, dtype=torch.float64, device=dev)
+    dF2 = torch.empty(n_hkl, dtype=torch.float32, device=dev)
+    out = None
+    a = [None] * 7
+    d = [None] * 5
+    nt = 1
+    if atoms is not None:
+        out = {k: torch.empty(n_atoms, dtype=torch.float32, device=dev) for k in ("x", "y", "z", "B", "occ")}
+        a = [_ptr(atoms[k]) for k in ("x", "y", "z", "B", "occ", "type", "ff")]
+        d = [_ptr(out[k]) for k in ("x", "y", "z", "B", "occ")]
+        nt = int(atoms["ff"].shape[0])
+    _check(L.fdtbx_pattern_backward(ctypes.byref(plan.model), _ptr(hkl), n_hkl, _ptr(F), _ptr(grad_image), _ptr(plan.ws),
+                                    plan.ws_bytes, plan.pair_cap, n_atoms, *a, nt, *d, _ptr(glob), _ptr(dF2), _ptr(ws),
+                                    wsb, _stream()))
+    return out, glob, dF2

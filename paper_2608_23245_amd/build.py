@@ -22,6 +22,7 @@ SOURCES = {
     "nodes.hip": [],
     "sf.hip": [],
     "profile.hip": [],
+    "adjoint.hip": [],
     "capi.hip": [],
 }
 

@@ -1,0 +1,452 @@
+// Adjoint of the detector image for a pixel weight G = dL/dimage.
+//
+// k_profile_adj walks the same tile lists, node windows and tile-level node queue as
+// the forward kernel and, per pixel lane inside the support, accumulates
+//   z  = g omega Z',  s = g domega/dsigma Z',  y = g domega/dgamma Z',  n_i = g omega D_i
+// with g = G L(R) of the pixel, Z' = prod_j S_j^2 and, for N_i sinc^2(N_i u_i) written in
+// y_i = N_i u_i/2 and S_j = sin(2 pi y_j)/y_j = 2 pi sinc(2 y_j),
+//   d/dN_i [N_i sinc^2(N_i u_i)] = sinc(x)(2 cos(pi x) - sinc(x)),  x = 2 y_i,
+// so that D_i = S_i (4 pi cos(2 pi y_i) - S_i) prod_{j != i} S_j^2 carries the same
+// 1/(2 pi)^6 and N factors as Z' (Eq. I_shape with N -> N_eff).  Per (tile, reflection)
+// the six lane sums are reduced over the wave and added in binary64 to the reflection's
+// sums.  Profile values are recomputed, never stored.
+//
+// k_adj_finish applies the chain rule per reflection in binary64:
+//   dL/dW = K z,  W = |F|^2 I_para,  K = r0^2 N_a N_b N_c/(2 pi)^6
+//   dL/dsigma_theta += W K s,  dL/dgamma_theta += W K y
+//   dL/dN_eff,i = W K n_i / N_i,  dN_eff/dN_base = N_eff^2/N_base^2            (Eq. Neff)
+//   dN_eff/dA = 2 N_eff^2/(1 + A)^2,  dI_para/dA_i = I_para (1 - A^2)/(A (1 + A^2)) (Eq. Ipara)
+//   dA/dg = -4 pi^2 g h^2 A                                                    (Eq. Ah)
+// and reduces the eight global gradients over reflections in a fixed order.
+//
+// k_sf_adj_* carry dL/d|F|^2 back to the atoms (Eq. structure_factor):
+//   d|F|^2/dx_j = -4 pi h occ_j Im(F* t_j/occ_j) (likewise y with k, z with l),
+//   d|F|^2/dB_j = -2 s^2 occ_j Re(F* t_j/occ_j),  d|F|^2/docc_j = 2 Re(F* t_j/occ_j).
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "internal.h"
+#include "profile_common.h"
+
+namespace fdtbx {
+
+__device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, float al0, float al1, float al2, float gp,
+                                              float half_m, float tiny, float* acc) {
+  float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
+  float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
+  if (mx <= half_m) {
+    ya = fmaxf(fabsf(ya), tiny);
+    yb = fmaxf(fabsf(yb), tiny);
+    yc = fmaxf(fabsf(yc), tiny);
+    const float sa = __builtin_amdgcn_sinf(ya), sb = __builtin_amdgcn_sinf(yb), sc = __builtin_amdgcn_sinf(yc);
+    const float ca = __builtin_amdgcn_cosf(ya), cb = __builtin_amdgcn_cosf(yb), cc = __builtin_amdgcn_cosf(yc);
+    const float yab = ya * yb;
+    const float inv = __builtin_amdgcn_rcpf(yab * yc);
+    const float Sa = sa * (inv * (yb * yc));
+    const float Sb = sb * (inv * (ya * yc));
+    const float Sc = sc * (inv * yab);
+    const float Pa = Sa * Sa, Pb = Sb * Sb, Pc = Sc * Sc;
+    const float Pab = Pa * Pb;
+    const float P = Pab * Pc;
+    const float t = gp * P;
+    acc[0] = fmaf(nd.w, t, acc[0]);
+    acc[1] = fmaf(dw.x, t, acc[1]);
+    acc[2] = fmaf(dw.y, t, acc[2]);
+    const float four_pi = 12.566370614359172f;
+    const float t2 = gp * nd.w;
+    acc[3] = fmaf(t2, Sa * fmaf(four_pi, ca, -Sa) * (Pb * Pc), acc[3]);
+    acc[4] = fmaf(t2, Sb * fmaf(four_pi, cb, -Sb) * (Pa * Pc), acc[4]);
+    acc[5] = fmaf(t2, Sc * fmaf(four_pi, cc, -Sc) * Pab, acc[5]);
+  }
+}
+
+__global__ void __launch_bounds__(64) k_profile_adj(ProfParams q, const float* __restrict__ refl, const float* __restrict__ nodes,
+                                                    const double* __restrict__ pix, const double* __restrict__ tile,
+                                                    const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
+                                                    const float* __restrict__ grad_image, double* __restrict__ sums) {
+  __shared__ float4 qn[128];
+  __shared__ float2 qd[128];
+  const int t = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int tx = t % q.tiles_x, ty = t / q.tiles_x;
+  const int i = tx * FDTBX_TILE + (lane % FDTBX_TILE);
+  const int j = ty * FDTBX_TILE + (lane / FDTBX_TILE);
+  const bool in = i < q.W && j < q.H;
+  const double R = in ? pix[2 * ((int64_t)j * q.W + i) + 0] : 1.0e30;
+  const double Z = in ? pix[2 * ((int64_t)j * q.W + i) + 1] : 0.0;
+  const float gp = in ? grad_image[(int64_t)j * q.W + i] * (float)(q.delta / (R + q.delta)) : 0.0f;
+  const double bRlo = tile[8 * (int64_t)t + 0], bRhi = tile[8 * (int64_t)t + 1];
+  const double bZlo = tile[8 * (int64_t)t + 2], bZhi = tile[8 * (int64_t)t + 3];
+  const float Rlo = (float)bRlo, Rhi = (float)bRhi, Zlo = (float)bZlo, Zhi = (float)bZhi;
+  const int64_t p0 = offsets[t], p1 = offsets[t + 1];
+  // a tile whose pixels all carry zero weight adds nothing
+  if (__ballot(gp != 0.0f) == 0ull) return;
+  for (int64_t pp = p0; pp < p1; ++pp) {
+    const int32_t r = idx[pp];
+    const float* rec = refl + (int64_t)FDTBX_REFL_FLOATS * r;
+    Window w;
+    if (!node_window(q, rec, Rlo, Rhi, Zlo, Zhi, &w)) continue;
+    const double RD = *(const double*)(rec + RS_RD);
+    const double ZD = *(const double*)(rec + RS_ZD);
+    const float dR = (float)(R - RD), dZ = (float)(Z - ZD);
+    float al[3], lo[3], hi[3];
+    const float dRl = (float)(bRlo - RD), dRh = (float)(bRhi - RD);
+    const float dZl = (float)(bZlo - ZD), dZh = (float)(bZhi - ZD);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float tr = rec[RS_TR + a], tz = rec[RS_TZ + a];
+      al[a] = fmaf(tr, dR, tz * dZ);
+      const float r1 = tr * dRl, r2 = tr * dRh, z1 = tz * dZl, z2 = tz * dZh;
+      lo[a] = fminf(r1, r2) + fminf(z1, z2) - q.half_m - q.margin;
+      hi[a] = fmaxf(r1, r2) + fmaxf(z1, z2) + q.half_m + q.margin;
+    }
+    const float B0 = rec[RS_B + 0], B1 = rec[RS_B + 1], B2 = rec[RS_B + 2];
+    const float G10 = rec[RS_G1 + 0], G11 = rec[RS_G1 + 1], G12 = rec[RS_G1 + 2];
+    const float G20 = rec[RS_G2 + 0], G21 = rec[RS_G2 + 1], G22 = rec[RS_G2 + 2];
+    const int nw1 = w.i1hi - w.i1lo + 1;
+    const int nwin = nw1 * (w.i2hi - w.i2lo + 1);
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int qlen = 0;
+    for (int w0 = 0; w0 < nwin; w0 += 64) {
+      const int wi = w0 + lane;
+      float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+      float2 ed = make_float2(0.f, 0.f);
+      bool keep = false;
+      if (wi < nwin) {
+        const int i1 = w.i1lo + wi % nw1, i2 = w.i2lo + wi / nw1;
+        const float* np_ = nodes + (int64_t)FDTBX_NODE_FLOATS * (i2 * q.n + i1);
+        const float4 nd = *(const float4*)np_;
+        const float2 nd2 = *(const float2*)(np_ + 4);
+        e.x = fmaf(nd.x, B0, fmaf(nd.y, G10, nd.z * G20));
+        e.y = fmaf(nd.x, B1, fmaf(nd.y, G11, nd.z * G21));
+        e.z = fmaf(nd.x, B2, fmaf(nd.y, G12, nd.z * G22));
+        e.w = nd.w;
+        ed = nd2;
+        keep = e.x >= lo[0] && e.x <= hi[0] && e.y >= lo[1] && e.y <= hi[1] && e.z >= lo[2] && e.z <= hi[2];
+      }
+      const unsigned long long b = __ballot(keep);
+      if (keep) {
+        const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
+        qn[pos] = e;
+        qd[pos] = ed;
+      }
+      qlen += __popcll(b);
+      __syncthreads();
+      if (qlen >= 64) {
+        for (int jj = 0; jj < 64; ++jj) eval_node_adj(qn[jj], qd[jj], al[0], al[1], al[2], gp, q.half_m, q.tiny, acc);
+        qlen -= 64;
+        __syncthreads();
+        if (lane < qlen) {
+          qn[lane] = qn[64 + lane];
+          qd[lane] = qd[64 + lane];
+        }
+        __syncthreads();
+      }
+    }
+    for (int jj = 0; jj < qlen; ++jj) eval_node_adj(qn[jj], qd[jj], al[0], al[1], al[2], gp, q.half_m, q.tiny, acc);
+    __syncthreads();
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      float v = acc[c];
+      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+      acc[c] = v;
+      any |= v != 0.0f;
+    }
+    if (lane == 0 && any) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) unsafeAtomicAdd(&sums[6 * (int64_t)r + c], (double)acc[c]);
+    }
+  }
+}
+
+__global__ void k_zero_f64(double* __restrict__ v, int64_t n) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) v[k] = 0.0;
+}
+
+// ---------------------------------------------------------------- chain rule per reflection
+struct FinishParams {
+  double Nb[3], g[3];
+  int32_t intensity_model;
+  int64_t n;
+};
+
+static constexpr int kFinThreads = 256;
+
+// Block sum of 8 doubles per thread into part[block][8] (fixed tree order).
+__device__ static void block_sum8(double v[8], double* part) {
+  __shared__ double red[kFinThreads / 64][8];
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int c = 0; c < 8; ++c) {
+    double x = v[c];
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    if (lane == 0) red[wid][c] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < 8) {
+    double x = 0.0;
+    for (int w = 0; w < kFinThreads / 64; ++w) x += red[w][threadIdx.x];
+    part[8 * (int64_t)blockIdx.x + threadIdx.x] = x;
+  }
+}
+
+__global__ void __launch_bounds__(kFinThreads) k_adj_finish(FinishParams p, const int32_t* __restrict__ hkl,
+                                                            const float* __restrict__ refl, const double* __restrict__ sums,
+                                                            const float* __restrict__ F, float* __restrict__ dF2,
+                                                            double* __restrict__ part) {
+  const int64_t r = (int64_t)blockIdx.x * kFinThreads + threadIdx.x;
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (r < p.n) {
+    const double pi2 = M_PI * M_PI;
+    double A[3], N[3], Ip = 1.0, h2[3];
+    for (int i = 0; i < 3; ++i) {
+      double h = (double)hkl[3 * r + i];
+      h2[i] = h * h;
+      A[i] = exp(-2.0 * pi2 * p.g[i] * p.g[i] * h2[i]);
+      N[i] = 1.0 / (1.0 / p.Nb[i] + (1.0 - A[i]) / (1.0 + A[i]));
+      if (p.intensity_model) Ip *= 2.0 * A[i] / (1.0 + A[i] * A[i]);
+    }
+    const double fr = F[2 * r], fi = F[2 * r + 1];
+    const double f2 = fr * fr + fi * fi;
+    const double W = f2 * Ip;
+    const double K = (double)refl[(int64_t)FDTBX_REFL_FLOATS * r + RS_K];
+    const double* sr = sums + 6 * r;
+    const double dW = K * sr[0];
+    if (dF2) dF2[r] = (float)(dW * Ip);
+    const double WK = W * K;
+    v[0] = WK * sr[1];
+    v[1] = WK * sr[2];
+    const double dIp = dW * f2;
+    for (int i = 0; i < 3; ++i) {
+      const double dN = WK * sr[3 + i] / N[i];
+      v[2 + i] = dN * N[i] * N[i] / (p.Nb[i] * p.Nb[i]);
+      double dA = dN * 2.0 * N[i] * N[i] / ((1.0 + A[i]) * (1.0 + A[i]));
+      if (p.intensity_model) dA += dIp * Ip * (1.0 - A[i] * A[i]) / (A[i] * (1.0 + A[i] * A[i]));
+      v[5 + i] = dA * (-4.0 * pi2 * p.g[i] * h2[i] * A[i]);
+    }
+  }
+  block_sum8(v, part);
+}
+
+__global__ void k_sum_parts(const double* __restrict__ part, int64_t nb, double* __restrict__ out) {
+  const int c = threadIdx.x;
+  if (c >= 8) return;
+  double x = 0.0;
+  for (int64_t b = 0; b < nb; ++b) x += part[8 * b + c];
+  out[c] = x;
+}
+
+// ---------------------------------------------------------------- atoms
+static constexpr int kSAThreads = 256;
+static constexpr int kSAMaxTypes = 16;
+static constexpr int kReflPerChunkMax = 2048;
+
+struct SAParams {
+  double as[9];
+  int64_t n_hkl, n_atoms, chunk;
+  int32_t n_types, n_chunks;
+};
+
+struct ReflLds {
+  int h, k, l;
+  float s2, cre, cim;
+};
+
+__global__ void __launch_bounds__(kSAThreads) k_sf_adj_partial(SAParams p, const float* __restrict__ x, const float* __restrict__ y,
+                                                               const float* __restrict__ z, const float* __restrict__ B,
+                                                               const int32_t* __restrict__ type, const float* __restrict__ ff,
+                                                               const int32_t* __restrict__ hkl, const float* __restrict__ F,
+                                                               const float* __restrict__ dF2, double* __restrict__ part) {
+  __shared__ ReflLds rl[kSAThreads];
+  __shared__ float ft[kSAThreads][kSAMaxTypes + 1];
+  const int64_t a = (int64_t)blockIdx.x * kSAThreads + threadIdx.x;
+  const bool have = a < p.n_atoms;
+  const double ax = have ? x[a] : 0.0, ay = have ? y[a] : 0.0, az = have ? z[a] : 0.0;
+  int ta = have ? type[a] : 0;
+  ta = ta < 0 ? 0 : (ta >= p.n_types ? p.n_types - 1 : ta);
+  const float nBl2e = have ? -B[a] * 1.4426950408889634f : 0.0f;
+  const int64_t r0 = (int64_t)blockIdx.y * p.chunk;
+  const int64_t r1 = r0 + p.chunk < p.n_hkl ? r0 + p.chunk : p.n_hkl;
+  double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // h Im, k Im, l Im, s^2 Re, Re (binary64: sums cancel strongly)
+  for (int64_t g0 = r0; g0 < r1; g0 += kSAThreads) {
+    __syncthreads();
+    const int64_t r = g0 + threadIdx.x;
+    if (r < r1) {
+      const double h = hkl[3 * r], k = hkl[3 * r + 1], l = hkl[3 * r + 2];
+      double D[3];
+      for (int j = 0; j < 3; ++j) D[j] = (h * p.as[j] + k * p.as[3 + j]) + l * p.as[6 + j];
+      const double s2 = 0.25 * ((D[0] * D[0] + D[1] * D[1]) + D[2] * D[2]);
+      const float w = dF2[r];
+      rl[threadIdx.x] = {(int)h, (int)k, (int)l, (float)s2, w * F[2 * r], -w * F[2 * r + 1]};
+      for (int t = 0; t < p.n_types; ++t) {
+        const float* c = ff + 9 * t;
+        double f = c[8];
+        for (int q = 0; q < 4; ++q) f += (double)c[q] * exp(-(double)c[4 + q] * s2);
+        ft[threadIdx.x][t] = (float)f;
+      }
+    }
+    __syncthreads();
+    const int cnt = (int)((r1 - g0) < kSAThreads ? (r1 - g0) : kSAThreads);
+    if (have) {
+      for (int i = 0; i < cnt; ++i) {
+        const ReflLds q = rl[i];
+        const double ph = fma((double)q.h, ax, fma((double)q.k, ay, (double)q.l * az));
+        const float fr = (float)(ph - floor(ph));
+        const float amp = ft[i][ta] * __builtin_amdgcn_exp2f(nBl2e * q.s2);
+        const float cs = __builtin_amdgcn_cosf(fr), sn = __builtin_amdgcn_sinf(fr);
+        // C t/occ with C = dF2 F*: real and imaginary parts
+        const float re = amp * (q.cre * cs - q.cim * sn);
+        const float im = amp * (q.cre * sn + q.cim * cs);
+        g[0] = fma((double)q.h, (double)im, g[0]);
+        g[1] = fma((double)q.k, (double)im, g[1]);
+        g[2] = fma((double)q.l, (double)im, g[2]);
+        g[3] = fma((double)q.s2, (double)re, g[3]);
+        g[4] += (double)re;
+      }
+    }
+  }
+  if (have)
+    for (int c = 0; c < 5; ++c) part[((int64_t)blockIdx.y * 5 + c) * p.n_atoms + a] = g[c];
+}
+
+__global__ void k_sf_adj_final(int64_t n_atoms, int32_t n_chunks, const double* __restrict__ part, const float* __restrict__ occ,
+                               float* dx, float* dy, float* dz, float* dB, float* docc) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n_atoms) return;
+  double s[5] = {0, 0, 0, 0, 0};
+  for (int c = 0; c < n_chunks; ++c)
+    for (int k = 0; k < 5; ++k) s[k] += part[((int64_t)c * 5 + k) * n_atoms + a];
+  const double o = occ[a];
+  const double fpi = 4.0 * M_PI;
+  if (dx) dx[a] = (float)(-fpi * o * s[0]);
+  if (dy) dy[a] = (float)(-fpi * o * s[1]);
+  if (dz) dz[a] = (float)(-fpi * o * s[2]);
+  if (dB) dB[a] = (float)(-2.0 * o * s[3]);
+  if (docc) docc[a] = (float)(2.0 * s[4]);
+}
+
+static void sa_split(int64_t n_hkl, int64_t n_atoms, int32_t* n_chunks, int64_t* chunk) {
+  int64_t nb = ceil_div(n_atoms, kSAThreads);
+  int64_t want = ceil_div(4096, nb);
+  int64_t need = ceil_div(n_hkl, kReflPerChunkMax);
+  int64_t nc = want > need ? want : need;
+  int64_t maxc = ceil_div(n_hkl, 64);
+  if (nc > maxc) nc = maxc;
+  if (nc < 1) nc = 1;
+  *chunk = ceil_div(n_hkl, nc);
+  *n_chunks = (int32_t)ceil_div(n_hkl, *chunk);
+}
+
+static void recip_basis(const fdtbx_cell* cell, double* as) {
+  double ca = cos(cell->alpha), cb = cos(cell->beta), cg = cos(cell->gamma), sa = sin(cell->alpha);
+  double cv[3] = {0.0, 0.0, cell->c};
+  double bv[3] = {0.0, cell->b * sa, cell->b * ca};
+  double az = cell->a * cb, ay = cell->a * (cg - ca * cb) / sa;
+  double av[3] = {sqrt(cell->a * cell->a - ay * ay - az * az), ay, az};
+  auto cross = [](const double* u, const double* v, double* w) {
+    w[0] = u[1] * v[2] - u[2] * v[1];
+    w[1] = u[2] * v[0] - u[0] * v[2];
+    w[2] = u[0] * v[1] - u[1] * v[0];
+  };
+  double bxc[3], cxa[3], axb[3];
+  cross(bv, cv, bxc);
+  cross(cv, av, cxa);
+  cross(av, bv, axb);
+  double V = (av[0] * bxc[0] + av[1] * bxc[1]) + av[2] * bxc[2];
+  for (int j = 0; j < 3; ++j) {
+    as[j] = bxc[j] / V;
+    as[3 + j] = cxa[j] / V;
+    as[6 + j] = axb[j] / V;
+  }
+}
+
+}  // namespace fdtbx
+
+using namespace fdtbx;
+
+extern "C" int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
+                                     const double* tile, const int64_t* offsets, const int32_t* idx, int64_t n_hkl,
+                                     const float* grad_image, double* sums, void* stream) {
+  if (!model || !refl || !nodes || !pix || !tile || !offsets || !idx || !grad_image || !sums)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be positive");
+  int rc = check_model(model);
+  if (rc) return rc;
+  ProfParams q;
+  prof_params(model, &q);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(6 * n_hkl, 256)), dim3(256), 0, s, sums, 6 * n_hkl);
+  FDTBX_LAUNCH_CHECK("adjoint zero");
+  int64_t n_tiles = (int64_t)q.tiles_x * q.tiles_y;
+  hipLaunchKernelGGL(k_profile_adj, dim3((unsigned)n_tiles), dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx, grad_image,
+                     sums);
+  FDTBX_LAUNCH_CHECK("profile adjoint");
+  return FDTBX_OK;
+}
+
+extern "C" size_t fdtbx_adjoint_finish_workspace(int64_t n_hkl) {
+  if (n_hkl <= 0) return 0;
+  return (size_t)ceil_div(n_hkl, kFinThreads) * 8 * sizeof(double);
+}
+
+extern "C" int fdtbx_adjoint_finish(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* refl,
+                                    const double* sums, const float* F, float* dF2, double* d_globals, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  if (!model || !hkl || !refl || !sums || !F || !d_globals || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be positive");
+  int rc = check_model(model);
+  if (rc) return rc;
+  if (ws_bytes < fdtbx_adjoint_finish_workspace(n_hkl)) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "finish workspace too small");
+  FinishParams p;
+  for (int i = 0; i < 3; ++i) {
+    p.Nb[i] = model->dis.N_base[i];
+    p.g[i] = model->dis.g[i];
+  }
+  p.intensity_model = model->dis.intensity_model;
+  p.n = n_hkl;
+  int64_t nb = ceil_div(n_hkl, kFinThreads);
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_adj_finish, dim3((unsigned)nb), dim3(kFinThreads), 0, s, p, hkl, refl, sums, F, dF2, (double*)ws);
+  FDTBX_LAUNCH_CHECK("adjoint finish");
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, (const double*)ws, nb, d_globals);
+  FDTBX_LAUNCH_CHECK("adjoint globals");
+  return FDTBX_OK;
+}
+
+extern "C" size_t fdtbx_sf_adjoint_workspace(int64_t n_hkl, int64_t n_atoms) {
+  if (n_hkl <= 0 || n_atoms <= 0) return 0;
+  int32_t nc;
+  int64_t chunk;
+  sa_split(n_hkl, n_atoms, &nc, &chunk);
+  return (size_t)nc * 5 * n_atoms * sizeof(double);
+}
+
+extern "C" int fdtbx_sf_adjoint(const fdtbx_cell* cell, int64_t n_atoms, const float* x, const float* y, const float* z,
+                                const float* B, const float* occ, const int32_t* type, const float* ff, int32_t n_types,
+                                const int32_t* hkl, int64_t n_hkl, const float* F, const float* dF2, float* d_x, float* d_y,
+                                float* d_z, float* d_B, float* d_occ, void* ws, size_t ws_bytes, void* stream) {
+  if (!cell || !x || !y || !z || !B || !occ || !type || !ff || !hkl || !F || !dF2 || !ws)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_atoms <= 0 || n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_atoms and n_hkl must be positive");
+  if (n_types < 1 || n_types > kSAMaxTypes) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_types must be in 1..16");
+  int rc = check_cell(cell);
+  if (rc) return rc;
+  if (ws_bytes < fdtbx_sf_adjoint_workspace(n_hkl, n_atoms)) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "sf adjoint workspace");
+  SAParams p;
+  recip_basis(cell, p.as);
+  p.n_hkl = n_hkl;
+  p.n_atoms = n_atoms;
+  p.n_types = n_types;
+  sa_split(n_hkl, n_atoms, &p.n_chunks, &p.chunk);
+  hipStream_t s = (hipStream_t)stream;
+  double* part = (double*)ws;
+  dim3 grid((unsigned)ceil_div(n_atoms, kSAThreads), (unsigned)p.n_chunks);
+  hipLaunchKernelGGL(k_sf_adj_partial, grid, dim3(kSAThreads), 0, s, p, x, y, z, B, type, ff, hkl, F, dF2, part);
+  FDTBX_LAUNCH_CHECK("sf adjoint");
+  hipLaunchKernelGGL(k_sf_adj_final, dim3((unsigned)ceil_div(n_atoms, 256)), dim3(256), 0, s, n_atoms, p.n_chunks, part, occ, d_x,
+                     d_y, d_z, d_B, d_occ);
+  FDTBX_LAUNCH_CHECK("sf adjoint reduce");
+  return FDTBX_OK;
+}

@@ -150,3 +150,52 @@ extern "C" int fdtbx_profile_pattern(const fdtbx_model* model, const int32_t* hk
   if (rc) return rc;
   return fdtbx_profile(model, refl, nodes, pix, tile, offsets, idx, image, nullptr, stream);
 }
+
+extern "C" size_t fdtbx_backward_workspace(int64_t n_hkl, int64_t n_atoms) {
+  if (n_hkl <= 0) return 0;
+  size_t b = align_up((size_t)n_hkl * 6 * sizeof(double), 256);
+  b += align_up(fdtbx_adjoint_finish_workspace(n_hkl), 256);
+  b += align_up((size_t)n_hkl * sizeof(float), 256);
+  if (n_atoms > 0) b += align_up(fdtbx_sf_adjoint_workspace(n_hkl, n_atoms), 256);
+  return b;
+}
+
+extern "C" int fdtbx_pattern_backward(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F,
+                                      const float* grad_image, const void* fwd_ws, size_t fwd_ws_bytes, int64_t pair_cap,
+                                      int64_t n_atoms, const float* x, const float* y, const float* z, const float* B,
+                                      const float* occ, const int32_t* type, const float* ff, int32_t n_types, float* d_x,
+                                      float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals, float* dF2,
+                                      void* ws, size_t ws_bytes, void* stream) {
+  if (!model || !hkl || !F || !grad_image || !fwd_ws || !d_globals || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl <= 0 || pair_cap < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "bad sizes");
+  int rc = check_model(model);
+  if (rc) return rc;
+  const bool atoms = d_x || d_y || d_z || d_B || d_occ;
+  if (atoms && (n_atoms <= 0 || !x || !y || !z || !B || !occ || !type || !ff))
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "atom arrays required for atom gradients");
+  PatternLayout L = layout(model, n_hkl, pair_cap);
+  if (fwd_ws_bytes < L.total) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "forward workspace smaller than the layout for pair_cap");
+  if (ws_bytes < fdtbx_backward_workspace(n_hkl, atoms ? n_atoms : 0)) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "backward workspace too small");
+  const char* fw = (const char*)fwd_ws;
+  const float* refl = (const float*)(fw + L.refl);
+  const float* nodes = (const float*)(fw + L.nodes);
+  const double* pix = (const double*)(fw + L.pix);
+  const double* tile = (const double*)(fw + L.tile);
+  const int64_t* offsets = (const int64_t*)(fw + L.offsets);
+  const int32_t* idx = (const int32_t*)(fw + L.idx);
+  char* w = (char*)ws;
+  double* sums = (double*)w;
+  w += align_up((size_t)n_hkl * 6 * sizeof(double), 256);
+  void* fin = w;
+  size_t fin_bytes = fdtbx_adjoint_finish_workspace(n_hkl);
+  w += align_up(fin_bytes, 256);
+  float* g2 = dF2 ? dF2 : (float*)w;
+  w += align_up((size_t)n_hkl * sizeof(float), 256);
+  rc = fdtbx_profile_adjoint(model, refl, nodes, pix, tile, offsets, idx, n_hkl, grad_image, sums, stream);
+  if (rc) return rc;
+  rc = fdtbx_adjoint_finish(model, hkl, n_hkl, refl, sums, F, g2, d_globals, fin, fin_bytes, stream);
+  if (rc) return rc;
+  if (!atoms) return FDTBX_OK;
+  return fdtbx_sf_adjoint(&model->cell, n_atoms, x, y, z, B, occ, type, ff, n_types, hkl, n_hkl, F, g2, d_x, d_y, d_z, d_B,
+                          d_occ, w, fdtbx_sf_adjoint_workspace(n_hkl, n_atoms), stream);
+}

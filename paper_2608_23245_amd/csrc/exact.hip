@@ -420,6 +420,7 @@ __global__ void __launch_bounds__(256) k_prep(PrepParams p, const int32_t* __res
   for (int i = 0; i < 3; ++i) o[RS_N + i] = (float)N[i];
   o[RS_R0] = (float)r0;
   o[RS_WK] = (float)(W * r0 * r0 * N[0] * N[1] * N[2] / tp6);
+  o[RS_K] = (float)(r0 * r0 * N[0] * N[1] * N[2] / tp6);
   for (int i = 0; i < 3; ++i) {
     const double* ai = &p.f.a[3 * i];
     o[RS_B + i] = (float)(0.5 * N[i] * r0 * dotv(ai, S));
@@ -449,7 +450,7 @@ __global__ void __launch_bounds__(256) k_prep(PrepParams p, const int32_t* __res
     o[RS_H + i] = (float)hh[i];
   }
   o[RS_F2] = (float)f2;
-  for (int k = RS_F2 + 1; k < FDTBX_REFL_FLOATS; ++k) o[k] = 0.0f;
+  for (int k = RS_K + 1; k < FDTBX_REFL_FLOATS; ++k) o[k] = 0.0f;
 }
 
 // ---------------------------------------------------------------- culling

@@ -51,6 +51,7 @@ enum ReflSlot {
   RS_A = 35,       // coherence factors A_i (35..37)
   RS_H = 38,       // h, k, l as floats (38..40)
   RS_F2 = 41,      // |F|^2
+  RS_K = 42,       // r0^2 N_a N_b N_c / (2 pi)^6, so that RS_WK = W * RS_K
 };
 
 // Cell frame in the laboratory convention: rows of avec are a, b, c; rows of

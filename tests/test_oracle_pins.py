@@ -516,3 +516,81 @@ def test_culling_lists_are_conservative():
             assert set(hit.tolist()) <= set(lists[ty * nx + tx].tolist())
             nonempty += len(hit)
     assert nonempty > 0
+
+
+# ----------------------------------------------------------------------------- adjoint vs finite differences
+def _fd_problem(sigma_theta, gamma_theta, g=(0.03, 0.02, 0.01), intensity_model=1, seed=31):
+    wl = W.small(seed, n_atoms=6, width=14, height=12, sigma_theta=sigma_theta, gamma_theta=gamma_theta, g=g,
+                 n_nodes=14, d_min=4.5, center=(6.2, 5.7))
+    wl.dis.intensity_model = intensity_model
+    a = wl.atoms
+    f64 = lambda v: np.asarray(v, dtype=np.float64).copy()
+    wl.atoms = W.Atoms(f64(a.x), f64(a.y), f64(a.z), f64(a.B), f64(a.occ) * 0.9, a.type.copy(), a.ff.astype(np.float64))
+    hkl = O.enumerate_hkl(wl.cell, wl.quad.d_min, wl.quad.d_max)
+    G = np.random.default_rng(seed).normal(size=(wl.geom.height, wl.geom.width))
+    return wl, hkl, G
+
+
+def _loss(wl, hkl, G):
+    P = O.prepare(wl, hkl=hkl, cull_extinct=False)
+    return float(np.sum(G * O.pattern(wl, P, use_skip=False)))
+
+
+@pytest.mark.parametrize("st,gt", [(3 * DEG, 2 * DEG), (4 * DEG, 0.0), (0.0, 3 * DEG)])
+def test_oracle_gradients_match_finite_differences(st, gt):
+    """L = sum G * image; the oracle's adjoint against FP64 central differences of its own
+    forward for every global parameter and every atom field."""
+    import copy
+    wl, hkl, G = _fd_problem(st, gt)
+    P = O.prepare(wl, hkl=hkl, cull_extinct=False)
+    gr = O.gradients(wl, P, G, use_skip=False)
+
+    def fd(mut, h):
+        w1, w2 = copy.deepcopy(wl), copy.deepcopy(wl)
+        mut(w1, +h)
+        mut(w2, -h)
+        return (_loss(w1, hkl, G) - _loss(w2, hkl, G)) / (2 * h)
+
+    checks = []
+    if st > 0:
+        checks.append(("sigma", gr["sigma_theta"], fd(lambda w, h: setattr(w.dis, "sigma_theta", w.dis.sigma_theta + h), 1e-7)))
+    if gt > 0:
+        checks.append(("gamma", gr["gamma_theta"], fd(lambda w, h: setattr(w.dis, "gamma_theta", w.dis.gamma_theta + h), 1e-7)))
+    for i in range(3):
+        def mN(w, h, i=i):
+            nb = list(w.dis.N_base)
+            nb[i] += h
+            w.dis.N_base = tuple(nb)
+        checks.append((f"N{i}", gr["N_base"][i], fd(mN, 1e-5)))
+
+        def mg(w, h, i=i):
+            gg = list(w.dis.g)
+            gg[i] += h
+            w.dis.g = tuple(gg)
+        checks.append((f"g{i}", gr["g"][i], fd(mg, 1e-6)))
+    for j in range(wl.atoms.n):
+        for field, h in (("x", 1e-6), ("y", 1e-6), ("z", 1e-6), ("B", 1e-4), ("occ", 1e-5)):
+            def ma(w, hh, field=field, j=j):
+                getattr(w.atoms, field)[j] += hh
+            checks.append((f"{field}{j}", gr["atoms"][field][j], fd(ma, h)))
+    scale = max(abs(c[2]) for c in checks)
+    for name, an, num in checks:
+        assert abs(an - num) <= 1e-6 * scale + 1e-5 * abs(num), (name, an, num)
+
+
+def test_oracle_intensity_model_none_and_dot_product():
+    """intensity_model 0 drops the I_para term of the g gradient; the adjoint is linear in G."""
+    wl, hkl, G = _fd_problem(3 * DEG, 1 * DEG, intensity_model=0)
+    P = O.prepare(wl, hkl=hkl, cull_extinct=False)
+    g1 = O.gradients(wl, P, G, use_skip=False)
+    g2 = O.gradients(wl, P, 2.0 * G, use_skip=False)
+    np.testing.assert_allclose(g2["g"], 2.0 * g1["g"], rtol=1e-12)
+    # <J v, G> = <v, J^T G> for v along sigma: directional FD of the image
+    import copy
+    h = 1e-7
+    w1, w2 = copy.deepcopy(wl), copy.deepcopy(wl)
+    w1.dis.sigma_theta += h
+    w2.dis.sigma_theta -= h
+    Jv = (O.pattern(w1, O.prepare(w1, hkl=hkl, cull_extinct=False), use_skip=False)
+          - O.pattern(w2, O.prepare(w2, hkl=hkl, cull_extinct=False), use_skip=False)) / (2 * h)
+    assert abs(np.sum(Jv * G) - g1["sigma_theta"]) <= 1e-6 * abs(g1["sigma_theta"])
