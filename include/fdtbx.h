@@ -282,6 +282,71 @@ int fdtbx_pattern_backward(const fdtbx_model* model, const int32_t* hkl, int64_t
                            float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals, float* dF2, void* ws,
                            size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------ batched models
+ * Many models of different cells, atom counts, reflection lists and detectors in one
+ * launch per step.  Each model's static data (reflection list, pixel map, tile boxes,
+ * culling lists, scattering-factor table) is built beforehand with the single-model
+ * entry points above and concatenated; fdtbx_batch_entry records where each model's
+ * part starts.  Offsets count elements of the respective arrays (reflections, atoms,
+ * pixels, tiles, CSR row pointers, culling-list entries, nodes, scattering-factor rows).
+ * Every model keeps its own detector, quadrature and disorder parameters; the kernels
+ * read them from the device copy of the entries, so sigma_theta, gamma_theta, N_base and
+ * g can change between steps (fdtbx_batch_set_globals) without a host round trip.  The
+ * culling lists stay those built at set-up.
+ *
+ * Work tables (device int64, built by the caller): entries pack (model << 40) | first index.
+ *   refl_blocks: blocks of 256 reflections, model-major (all blocks of a model adjacent);
+ *   model_rb[n_models+1]: first refl_blocks entry of each model;
+ *   atom_blocks: blocks of 256 atoms;  node_blocks: blocks of 256 nodes;
+ *   tile_items: (model, tile) pairs in the order the persistent kernels take them
+ *               (longest culling list first balances the tail). */
+typedef struct fdtbx_batch_entry {
+  fdtbx_model model;
+  double frame[19];     /* filled by fdtbx_batch_entry_init: rows a, b, c; rows a*, b*, c*; V */
+  int64_t atom_off, n_atoms;
+  int64_t hkl_off, n_hkl;
+  int64_t pix_off;      /* first pixel of this model's image and pixel map */
+  int64_t tile_off;     /* first tile box */
+  int64_t rowptr_off;   /* first of this model's n_tiles + 1 CSR row pointers */
+  int64_t pair_off;     /* first culling-list entry; the row pointers are relative to it */
+  int64_t node_off;     /* first node record (n_nodes^2 of them) */
+  int64_t ff_off;       /* first scattering-factor row */
+  int32_t n_types, n_tiles;
+} fdtbx_batch_entry;
+
+/* Host: validate the model and fill e->model and e->frame (offsets are the caller's). */
+int fdtbx_batch_entry_init(const fdtbx_model* model, fdtbx_batch_entry* e);
+/* sizeof(fdtbx_batch_entry), for bindings that mirror the struct. */
+size_t fdtbx_batch_entry_size(void);
+
+/* Device: entries[m].model.dis <- globals[m][0..7] = (sigma_theta, gamma_theta, N_base[3], g[3]). */
+int fdtbx_batch_set_globals(fdtbx_batch_entry* entries, int32_t n_models, const double* globals, void* stream);
+
+/* Forward step for all models: structure factors F [sum n_hkl][2] and F2, reflection
+ * records, node tables, and the images (float32, each [height][width] at pix_off).
+ * counter: device int64 [2] scratch for the persistent kernel's work queue. */
+int fdtbx_batch_forward(const fdtbx_batch_entry* entries, int32_t n_models, const int64_t* refl_blocks, int64_t n_rb,
+                        const int64_t* node_blocks, int64_t n_nb, const int64_t* tile_items, int64_t n_items,
+                        const int32_t* hkl, const float* x, const float* y, const float* z, const float* B,
+                        const float* occ, const int32_t* type, const float* ff, const double* pix, const double* tile,
+                        const int64_t* rowptr, const int32_t* idx, float* F, float* F2, float* refl, float* nodes,
+                        float* image, int64_t* counter, void* stream);
+
+/* Backward step for all models, after fdtbx_batch_forward with the same inputs:
+ * grad_image (float32, laid out as the images) -> atom gradients (float32 [sum n_atoms]
+ * each), d_globals (float64 [n_models][8]) and dF2 (float32 [sum n_hkl]).  sums: device
+ * float64 [n_hkl_total][6] scratch (n_hkl_total = sum of n_hkl); part: device float64
+ * [n_rb][8] scratch.  Neither call allocates, copies to the host or synchronises, so a
+ * caller can capture them (with fdtbx_batch_set_globals) in a HIP graph. */
+int fdtbx_batch_backward(const fdtbx_batch_entry* entries, int32_t n_models, const int64_t* refl_blocks, int64_t n_rb,
+                         const int64_t* model_rb, const int64_t* atom_blocks, int64_t n_ab, const int64_t* tile_items,
+                         int64_t n_items, int64_t n_hkl_total, const int32_t* hkl, const float* x, const float* y, const float* z,
+                         const float* B, const float* occ, const int32_t* type, const float* ff, const double* pix,
+                         const double* tile, const int64_t* rowptr, const int32_t* idx, const float* F,
+                         const float* refl, const float* nodes, const float* grad_image, double* sums, double* part,
+                         float* dF2, float* d_x, float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals,
+                         int64_t* counter, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

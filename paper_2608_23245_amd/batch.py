@@ -1,0 +1,215 @@
+"""Batched models: many workloads of different cells, atom counts, reflection lists
+and detectors, stepped together by fdtbx_batch_forward / fdtbx_batch_backward.
+
+Set-up runs the single-model entry points once per model (reflection list with the
+extinction cull of its initial g, pixel map, tile boxes, culling lists) and
+concatenates the results; the per-model descriptors (fdtbx_batch_entry) live in
+device memory, so the refinable parameters of every model can be updated in place
+(set_globals) between steps.  The step itself allocates nothing, copies nothing to
+the host and never synchronises, so it can be captured in a HIP graph
+(``GraphStep``).
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+RB = 256  # reflections / atoms / nodes per block of the work tables
+
+
+def _pack(model: int, first: int) -> int:
+    return (model << 40) | first
+
+
+class BatchEngine:
+    def __init__(self, workloads: List, device="cuda"):
+        L = B.lib()
+        if L.fdtbx_batch_entry_size() != ctypes.sizeof(B.BatchEntry):
+            raise RuntimeError("fdtbx_batch_entry layout differs between the library and the binding")
+        self.workloads = workloads
+        self.n = n = len(workloads)
+        self.device = device
+        self.models = [B.make_model(wl) for wl in workloads]
+        ents = (B.BatchEntry * n)()
+        hkls, pixs, tiles, rowptrs, idxs = [], [], [], [], []
+        ax, ay, az, aB, aocc, atype, ffs = [], [], [], [], [], [], []
+        self.shapes = []
+        off = dict(atom=0, hkl=0, pix=0, tile=0, rowptr=0, pair=0, node=0, ff=0)
+        refl_blocks, model_rb, atom_blocks, node_blocks, items, costs = [], [], [], [], [], []
+        self.list_len = []
+        for m, (wl, mod) in enumerate(zip(workloads, self.models)):
+            e = ents[m]
+            B._check(L.fdtbx_batch_entry_init(ctypes.byref(mod), ctypes.byref(e)))
+            ext = (wl.dis.g[0], wl.dis.g[1], wl.dis.g[2], wl.quad.extinction) if wl.quad.extinction > 0 else None
+            hkl = B.enumerate_hkl(mod.cell, wl.quad.d_min, wl.quad.d_max, extinction=ext, device=device)
+            n_hkl = int(hkl.shape[0])
+            if n_hkl == 0:
+                raise ValueError(f"model {m} has no reflections")
+            pix, tile = B.pixel_map(mod.geom)
+            _, cull = B.reflection_prep(mod, hkl, torch.ones(n_hkl, dtype=torch.float32, device=device))
+            rowptr, idx = B.cull(mod.geom, tile, cull)
+            n_tiles = int(tile.shape[0])
+            a = wl.atoms
+            e.atom_off, e.n_atoms = off["atom"], a.n
+            e.hkl_off, e.n_hkl = off["hkl"], n_hkl
+            e.pix_off = off["pix"]
+            e.tile_off = off["tile"]
+            e.rowptr_off = off["rowptr"]
+            e.pair_off = off["pair"]
+            e.node_off = off["node"]
+            e.ff_off = off["ff"]
+            e.n_types = int(a.ff.shape[0])
+            e.n_tiles = n_tiles
+            model_rb.append(len(refl_blocks))
+            refl_blocks += [_pack(m, r) for r in range(0, n_hkl, RB)]
+            atom_blocks += [_pack(m, r) for r in range(0, a.n, RB)]
+            node_blocks += [_pack(m, r) for r in range(0, wl.quad.n_nodes ** 2, RB)]
+            lens = (rowptr[1:] - rowptr[:-1]).cpu().numpy()
+            items += [_pack(m, t) for t in range(n_tiles)]
+            costs.append(lens)
+            self.list_len.append(int(idx.shape[0]))
+            hkls.append(hkl)
+            pixs.append(pix.reshape(-1, 2))
+            tiles.append(tile)
+            rowptrs.append(rowptr)
+            idxs.append(idx)
+            ax.append(a.x), ay.append(a.y), az.append(a.z), aB.append(a.B), aocc.append(a.occ)
+            atype.append(a.type), ffs.append(a.ff)
+            self.shapes.append((wl.geom.height, wl.geom.width))
+            off["atom"] += a.n
+            off["hkl"] += n_hkl
+            off["pix"] += wl.geom.width * wl.geom.height
+            off["tile"] += n_tiles
+            off["rowptr"] += n_tiles + 1
+            off["pair"] += int(idx.shape[0])
+            off["node"] += wl.quad.n_nodes ** 2
+            off["ff"] += int(a.ff.shape[0])
+        model_rb.append(len(refl_blocks))
+        self.totals = dict(off)
+        dev = lambda arr, dt: torch.as_tensor(np.ascontiguousarray(arr), dtype=dt).to(device)
+        self.hkl = torch.cat(hkls).contiguous()
+        self.pix = torch.cat(pixs).contiguous()
+        self.tile = torch.cat(tiles).contiguous()
+        self.rowptr = torch.cat(rowptrs).contiguous()
+        self.idx = torch.cat(idxs).contiguous() if off["pair"] > 0 else torch.zeros(1, dtype=torch.int32, device=device)
+        self.atoms = {"x": dev(np.concatenate(ax), torch.float32), "y": dev(np.concatenate(ay), torch.float32),
+                      "z": dev(np.concatenate(az), torch.float32), "B": dev(np.concatenate(aB), torch.float32),
+                      "occ": dev(np.concatenate(aocc), torch.float32), "type": dev(np.concatenate(atype), torch.int32),
+                      "ff": dev(np.concatenate(ffs), torch.float32)}
+        # longest culling list first: the persistent kernels take items in this order
+        cost = np.concatenate(costs)
+        order = np.argsort(-cost, kind="stable")
+        self.items = dev(np.asarray(items, dtype=np.int64)[order], torch.int64)
+        self.refl_blocks = dev(np.asarray(refl_blocks, dtype=np.int64), torch.int64)
+        self.model_rb = dev(np.asarray(model_rb, dtype=np.int64), torch.int64)
+        self.atom_blocks = dev(np.asarray(atom_blocks, dtype=np.int64), torch.int64)
+        self.node_blocks = dev(np.asarray(node_blocks, dtype=np.int64), torch.int64)
+        raw = bytes(ctypes.string_at(ctypes.addressof(ents), ctypes.sizeof(ents)))
+        self.entries = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
+        self._host_entries = ents
+        H = off["hkl"]
+        self.F = torch.empty((H, 2), dtype=torch.float32, device=device)
+        self.F2 = torch.empty(H, dtype=torch.float32, device=device)
+        self.refl = torch.empty((H, B.REFL_FLOATS), dtype=torch.float32, device=device)
+        self.nodes = torch.empty((off["node"], B.NODE_FLOATS), dtype=torch.float32, device=device)
+        self.image = torch.empty(off["pix"], dtype=torch.float32, device=device)
+        self.counter = torch.zeros(2, dtype=torch.int64, device=device)
+        self.sums = torch.empty((H, 6), dtype=torch.float64, device=device)
+        self.part = torch.empty((max(len(refl_blocks), 1), 8), dtype=torch.float64, device=device)
+        self.dF2 = torch.empty(H, dtype=torch.float32, device=device)
+        self.grads = {k: torch.empty(off["atom"], dtype=torch.float32, device=device) for k in ("x", "y", "z", "B", "occ")}
+        self.d_globals = torch.empty((n, 8), dtype=torch.float64, device=device)
+        pix_off = [0]
+        for h, w in self.shapes:
+            pix_off.append(pix_off[-1] + h * w)
+        self.pix_off = pix_off
+        self.hkl_off = [ents[m].hkl_off for m in range(n)] + [H]
+        self.atom_off = [ents[m].atom_off for m in range(n)] + [off["atom"]]
+
+    # ------------------------------------------------------------------ views
+    def image_of(self, m: int) -> torch.Tensor:
+        h, w = self.shapes[m]
+        return self.image[self.pix_off[m]:self.pix_off[m + 1]].view(h, w)
+
+    def globals(self) -> torch.Tensor:
+        g = [[wl.dis.sigma_theta, wl.dis.gamma_theta, *wl.dis.N_base, *wl.dis.g] for wl in self.workloads]
+        return torch.tensor(g, dtype=torch.float64, device=self.device)
+
+    # ------------------------------------------------------------------ step
+    def set_globals(self, glob: torch.Tensor):
+        glob = glob.to(self.device, torch.float64).contiguous()
+        B._check(B.lib().fdtbx_batch_set_globals(B._ptr(self.entries), self.n, B._ptr(glob), B._stream()))
+
+    def forward(self) -> torch.Tensor:
+        a = self.atoms
+        B._check(B.lib().fdtbx_batch_forward(
+            B._ptr(self.entries), self.n, B._ptr(self.refl_blocks), int(self.refl_blocks.shape[0]),
+            B._ptr(self.node_blocks), int(self.node_blocks.shape[0]), B._ptr(self.items), int(self.items.shape[0]),
+            B._ptr(self.hkl), B._ptr(a["x"]), B._ptr(a["y"]), B._ptr(a["z"]), B._ptr(a["B"]), B._ptr(a["occ"]),
+            B._ptr(a["type"]), B._ptr(a["ff"]), B._ptr(self.pix), B._ptr(self.tile), B._ptr(self.rowptr),
+            B._ptr(self.idx), B._ptr(self.F), B._ptr(self.F2), B._ptr(self.refl), B._ptr(self.nodes),
+            B._ptr(self.image), B._ptr(self.counter), B._stream()))
+        return self.image
+
+    def backward(self, grad_image: torch.Tensor, atoms: bool = True):
+        a = self.atoms
+        g = self.grads
+        d = [B._ptr(g[k]) if atoms else None for k in ("x", "y", "z", "B", "occ")]
+        B._check(B.lib().fdtbx_batch_backward(
+            B._ptr(self.entries), self.n, B._ptr(self.refl_blocks), int(self.refl_blocks.shape[0]),
+            B._ptr(self.model_rb), B._ptr(self.atom_blocks), int(self.atom_blocks.shape[0]), B._ptr(self.items),
+            int(self.items.shape[0]), int(self.totals["hkl"]), B._ptr(self.hkl), B._ptr(a["x"]), B._ptr(a["y"]),
+            B._ptr(a["z"]), B._ptr(a["B"]), B._ptr(a["occ"]), B._ptr(a["type"]), B._ptr(a["ff"]), B._ptr(self.pix),
+            B._ptr(self.tile), B._ptr(self.rowptr), B._ptr(self.idx), B._ptr(self.F), B._ptr(self.refl),
+            B._ptr(self.nodes), B._ptr(grad_image), B._ptr(self.sums), B._ptr(self.part), B._ptr(self.dF2), *d,
+            B._ptr(self.d_globals), B._ptr(self.counter), B._stream()))
+        return g, self.d_globals
+
+
+class GraphStep:
+    """One refinement step of every model captured in a HIP graph: forward, pixel weights of
+    the weighted residual, G = 2 w (I - T) with w = 1/(T + 1e-3 max T), and backward.  The
+    targets and their weights are fixed inputs; replay() recomputes images and gradients
+    for the parameters currently in the engine (set_globals / atom tensors updated in
+    place).  The graph holds no memset nodes: every scratch buffer is cleared by a kernel."""
+
+    def __init__(self, engine: BatchEngine, target: torch.Tensor):
+        self.engine = engine
+        self.target = target.contiguous()
+        w = torch.empty_like(self.target)
+        for m in range(engine.n):
+            s = slice(engine.pix_off[m], engine.pix_off[m + 1])
+            t = self.target[s]
+            w[s] = 1.0 / (t + 1e-3 * t.max())
+        self.weight = w
+        self.G = torch.empty_like(self.target)
+        self.graph = None
+
+    def _body(self):
+        img = self.engine.forward()
+        torch.sub(img, self.target, out=self.G)
+        self.G.mul_(self.weight).mul_(2.0)
+        self.engine.backward(self.G)
+
+    def eager(self):
+        self._body()
+
+    def capture(self):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self._body()  # warm-up outside the graph
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        self.graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self.graph):
+            self._body()
+        torch.cuda.synchronize()
+
+    def replay(self):
+        self.graph.replay()

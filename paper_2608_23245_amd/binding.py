@@ -57,6 +57,14 @@ class Model(ctypes.Structure):
     _fields_ = [("cell", Cell), ("geom", Geometry), ("dis", Disorder), ("quad", Quadrature)]
 
 
+class BatchEntry(ctypes.Structure):
+    _fields_ = [("model", Model), ("frame", ctypes.c_double * 19), ("atom_off", ctypes.c_int64),
+                ("n_atoms", ctypes.c_int64), ("hkl_off", ctypes.c_int64), ("n_hkl", ctypes.c_int64),
+                ("pix_off", ctypes.c_int64), ("tile_off", ctypes.c_int64), ("rowptr_off", ctypes.c_int64),
+                ("pair_off", ctypes.c_int64), ("node_off", ctypes.c_int64), ("ff_off", ctypes.c_int64),
+                ("n_types", ctypes.c_int32), ("n_tiles", ctypes.c_int32)]
+
+
 _lib = None
 
 _SIGS = {
@@ -98,6 +106,15 @@ _SIGS = {
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64,
                                               ctypes.c_int64] + [ctypes.c_void_p] * 7 + [ctypes.c_int32] +
                                [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "fdtbx_batch_entry_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "fdtbx_batch_entry_size": (ctypes.c_size_t, []),
+    "fdtbx_batch_set_globals": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "fdtbx_batch_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                           ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64] +
+                            [ctypes.c_void_p] * 18 + [ctypes.c_void_p]),
+    "fdtbx_batch_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                            ctypes.c_int64, ctypes.c_int64] + [ctypes.c_void_p] * 26 + [ctypes.c_void_p]),
 }
 
 

@@ -28,38 +28,9 @@
 
 #include "internal.h"
 #include "profile_common.h"
+#include "adjoint_tile.h"
 
 namespace fdtbx {
-
-__device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, float al0, float al1, float al2, float gp,
-                                              float half_m, float tiny, float* acc) {
-  float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
-  float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
-  if (mx <= half_m) {
-    ya = fmaxf(fabsf(ya), tiny);
-    yb = fmaxf(fabsf(yb), tiny);
-    yc = fmaxf(fabsf(yc), tiny);
-    const float sa = __builtin_amdgcn_sinf(ya), sb = __builtin_amdgcn_sinf(yb), sc = __builtin_amdgcn_sinf(yc);
-    const float ca = __builtin_amdgcn_cosf(ya), cb = __builtin_amdgcn_cosf(yb), cc = __builtin_amdgcn_cosf(yc);
-    const float yab = ya * yb;
-    const float inv = __builtin_amdgcn_rcpf(yab * yc);
-    const float Sa = sa * (inv * (yb * yc));
-    const float Sb = sb * (inv * (ya * yc));
-    const float Sc = sc * (inv * yab);
-    const float Pa = Sa * Sa, Pb = Sb * Sb, Pc = Sc * Sc;
-    const float Pab = Pa * Pb;
-    const float P = Pab * Pc;
-    const float t = gp * P;
-    acc[0] = fmaf(nd.w, t, acc[0]);
-    acc[1] = fmaf(dw.x, t, acc[1]);
-    acc[2] = fmaf(dw.y, t, acc[2]);
-    const float four_pi = 12.566370614359172f;
-    const float t2 = gp * nd.w;
-    acc[3] = fmaf(t2, Sa * fmaf(four_pi, ca, -Sa) * (Pb * Pc), acc[3]);
-    acc[4] = fmaf(t2, Sb * fmaf(four_pi, cb, -Sb) * (Pa * Pc), acc[4]);
-    acc[5] = fmaf(t2, Sc * fmaf(four_pi, cc, -Sc) * Pab, acc[5]);
-  }
-}
 
 __global__ void __launch_bounds__(64) k_profile_adj(ProfParams q, const float* __restrict__ refl, const float* __restrict__ nodes,
                                                     const double* __restrict__ pix, const double* __restrict__ tile,
@@ -67,98 +38,7 @@ __global__ void __launch_bounds__(64) k_profile_adj(ProfParams q, const float* _
                                                     const float* __restrict__ grad_image, double* __restrict__ sums) {
   __shared__ float4 qn[128];
   __shared__ float2 qd[128];
-  const int t = blockIdx.x;
-  const int lane = threadIdx.x;
-  const int tx = t % q.tiles_x, ty = t / q.tiles_x;
-  const int i = tx * FDTBX_TILE + (lane % FDTBX_TILE);
-  const int j = ty * FDTBX_TILE + (lane / FDTBX_TILE);
-  const bool in = i < q.W && j < q.H;
-  const double R = in ? pix[2 * ((int64_t)j * q.W + i) + 0] : 1.0e30;
-  const double Z = in ? pix[2 * ((int64_t)j * q.W + i) + 1] : 0.0;
-  const float gp = in ? grad_image[(int64_t)j * q.W + i] * (float)(q.delta / (R + q.delta)) : 0.0f;
-  const double bRlo = tile[8 * (int64_t)t + 0], bRhi = tile[8 * (int64_t)t + 1];
-  const double bZlo = tile[8 * (int64_t)t + 2], bZhi = tile[8 * (int64_t)t + 3];
-  const float Rlo = (float)bRlo, Rhi = (float)bRhi, Zlo = (float)bZlo, Zhi = (float)bZhi;
-  const int64_t p0 = offsets[t], p1 = offsets[t + 1];
-  // a tile whose pixels all carry zero weight adds nothing
-  if (__ballot(gp != 0.0f) == 0ull) return;
-  for (int64_t pp = p0; pp < p1; ++pp) {
-    const int32_t r = idx[pp];
-    const float* rec = refl + (int64_t)FDTBX_REFL_FLOATS * r;
-    Window w;
-    if (!node_window(q, rec, Rlo, Rhi, Zlo, Zhi, &w)) continue;
-    const double RD = *(const double*)(rec + RS_RD);
-    const double ZD = *(const double*)(rec + RS_ZD);
-    const float dR = (float)(R - RD), dZ = (float)(Z - ZD);
-    float al[3], lo[3], hi[3];
-    const float dRl = (float)(bRlo - RD), dRh = (float)(bRhi - RD);
-    const float dZl = (float)(bZlo - ZD), dZh = (float)(bZhi - ZD);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float tr = rec[RS_TR + a], tz = rec[RS_TZ + a];
-      al[a] = fmaf(tr, dR, tz * dZ);
-      const float r1 = tr * dRl, r2 = tr * dRh, z1 = tz * dZl, z2 = tz * dZh;
-      lo[a] = fminf(r1, r2) + fminf(z1, z2) - q.half_m - q.margin;
-      hi[a] = fmaxf(r1, r2) + fmaxf(z1, z2) + q.half_m + q.margin;
-    }
-    const float B0 = rec[RS_B + 0], B1 = rec[RS_B + 1], B2 = rec[RS_B + 2];
-    const float G10 = rec[RS_G1 + 0], G11 = rec[RS_G1 + 1], G12 = rec[RS_G1 + 2];
-    const float G20 = rec[RS_G2 + 0], G21 = rec[RS_G2 + 1], G22 = rec[RS_G2 + 2];
-    const int nw1 = w.i1hi - w.i1lo + 1;
-    const int nwin = nw1 * (w.i2hi - w.i2lo + 1);
-    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    int qlen = 0;
-    for (int w0 = 0; w0 < nwin; w0 += 64) {
-      const int wi = w0 + lane;
-      float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
-      float2 ed = make_float2(0.f, 0.f);
-      bool keep = false;
-      if (wi < nwin) {
-        const int i1 = w.i1lo + wi % nw1, i2 = w.i2lo + wi / nw1;
-        const float* np_ = nodes + (int64_t)FDTBX_NODE_FLOATS * (i2 * q.n + i1);
-        const float4 nd = *(const float4*)np_;
-        const float2 nd2 = *(const float2*)(np_ + 4);
-        e.x = fmaf(nd.x, B0, fmaf(nd.y, G10, nd.z * G20));
-        e.y = fmaf(nd.x, B1, fmaf(nd.y, G11, nd.z * G21));
-        e.z = fmaf(nd.x, B2, fmaf(nd.y, G12, nd.z * G22));
-        e.w = nd.w;
-        ed = nd2;
-        keep = e.x >= lo[0] && e.x <= hi[0] && e.y >= lo[1] && e.y <= hi[1] && e.z >= lo[2] && e.z <= hi[2];
-      }
-      const unsigned long long b = __ballot(keep);
-      if (keep) {
-        const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
-        qn[pos] = e;
-        qd[pos] = ed;
-      }
-      qlen += __popcll(b);
-      __syncthreads();
-      if (qlen >= 64) {
-        for (int jj = 0; jj < 64; ++jj) eval_node_adj(qn[jj], qd[jj], al[0], al[1], al[2], gp, q.half_m, q.tiny, acc);
-        qlen -= 64;
-        __syncthreads();
-        if (lane < qlen) {
-          qn[lane] = qn[64 + lane];
-          qd[lane] = qd[64 + lane];
-        }
-        __syncthreads();
-      }
-    }
-    for (int jj = 0; jj < qlen; ++jj) eval_node_adj(qn[jj], qd[jj], al[0], al[1], al[2], gp, q.half_m, q.tiny, acc);
-    __syncthreads();
-    bool any = false;
-#pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      float v = acc[c];
-      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-      acc[c] = v;
-      any |= v != 0.0f;
-    }
-    if (lane == 0 && any) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) unsafeAtomicAdd(&sums[6 * (int64_t)r + c], (double)acc[c]);
-    }
-  }
+  adjoint_tile(q, refl, nodes, pix, tile, offsets, idx, grad_image, sums, blockIdx.x, qn, qd);
 }
 
 __global__ void k_zero_f64(double* __restrict__ v, int64_t n) {
@@ -192,6 +72,38 @@ __device__ static void block_sum8(double v[8], double* part) {
   }
 }
 
+// Chain rule for one reflection (binary64).  Returns dL/d|F|^2 and adds the eight global
+// contributions to v.
+__device__ static double finish_one(const FinishParams& p, const int32_t* hk, const float* rec, const double* sr,
+                                    const float* Fr, double v[8]) {
+  const double pi2 = M_PI * M_PI;
+  double A[3], N[3], Ip = 1.0, h2[3];
+  for (int i = 0; i < 3; ++i) {
+    double h = (double)hk[i];
+    h2[i] = h * h;
+    A[i] = exp(-2.0 * pi2 * p.g[i] * p.g[i] * h2[i]);
+    N[i] = 1.0 / (1.0 / p.Nb[i] + (1.0 - A[i]) / (1.0 + A[i]));
+    if (p.intensity_model) Ip *= 2.0 * A[i] / (1.0 + A[i] * A[i]);
+  }
+  const double fr = Fr[0], fi = Fr[1];
+  const double f2 = fr * fr + fi * fi;
+  const double W = f2 * Ip;
+  const double K = (double)rec[RS_K];
+  const double dW = K * sr[0];
+  const double WK = W * K;
+  v[0] += WK * sr[1];
+  v[1] += WK * sr[2];
+  const double dIp = dW * f2;
+  for (int i = 0; i < 3; ++i) {
+    const double dN = WK * sr[3 + i] / N[i];
+    v[2 + i] += dN * N[i] * N[i] / (p.Nb[i] * p.Nb[i]);
+    double dA = dN * 2.0 * N[i] * N[i] / ((1.0 + A[i]) * (1.0 + A[i]));
+    if (p.intensity_model) dA += dIp * Ip * (1.0 - A[i] * A[i]) / (A[i] * (1.0 + A[i] * A[i]));
+    v[5 + i] += dA * (-4.0 * pi2 * p.g[i] * h2[i] * A[i]);
+  }
+  return dW * Ip;
+}
+
 __global__ void __launch_bounds__(kFinThreads) k_adj_finish(FinishParams p, const int32_t* __restrict__ hkl,
                                                             const float* __restrict__ refl, const double* __restrict__ sums,
                                                             const float* __restrict__ F, float* __restrict__ dF2,
@@ -199,33 +111,8 @@ __global__ void __launch_bounds__(kFinThreads) k_adj_finish(FinishParams p, cons
   const int64_t r = (int64_t)blockIdx.x * kFinThreads + threadIdx.x;
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (r < p.n) {
-    const double pi2 = M_PI * M_PI;
-    double A[3], N[3], Ip = 1.0, h2[3];
-    for (int i = 0; i < 3; ++i) {
-      double h = (double)hkl[3 * r + i];
-      h2[i] = h * h;
-      A[i] = exp(-2.0 * pi2 * p.g[i] * p.g[i] * h2[i]);
-      N[i] = 1.0 / (1.0 / p.Nb[i] + (1.0 - A[i]) / (1.0 + A[i]));
-      if (p.intensity_model) Ip *= 2.0 * A[i] / (1.0 + A[i] * A[i]);
-    }
-    const double fr = F[2 * r], fi = F[2 * r + 1];
-    const double f2 = fr * fr + fi * fi;
-    const double W = f2 * Ip;
-    const double K = (double)refl[(int64_t)FDTBX_REFL_FLOATS * r + RS_K];
-    const double* sr = sums + 6 * r;
-    const double dW = K * sr[0];
-    if (dF2) dF2[r] = (float)(dW * Ip);
-    const double WK = W * K;
-    v[0] = WK * sr[1];
-    v[1] = WK * sr[2];
-    const double dIp = dW * f2;
-    for (int i = 0; i < 3; ++i) {
-      const double dN = WK * sr[3 + i] / N[i];
-      v[2 + i] = dN * N[i] * N[i] / (p.Nb[i] * p.Nb[i]);
-      double dA = dN * 2.0 * N[i] * N[i] / ((1.0 + A[i]) * (1.0 + A[i]));
-      if (p.intensity_model) dA += dIp * Ip * (1.0 - A[i] * A[i]) / (A[i] * (1.0 + A[i] * A[i]));
-      v[5 + i] = dA * (-4.0 * pi2 * p.g[i] * h2[i] * A[i]);
-    }
+    const double d = finish_one(p, hkl + 3 * r, refl + (int64_t)FDTBX_REFL_FLOATS * r, sums + 6 * r, F + 2 * r, v);
+    if (dF2) dF2[r] = (float)d;
   }
   block_sum8(v, part);
 }
@@ -362,9 +249,201 @@ static void recip_basis(const fdtbx_cell* cell, double* as) {
   }
 }
 
+// ---------------------------------------------------------------- batched models
+__global__ void __launch_bounds__(64) k_b_profile_adj(const fdtbx_batch_entry* __restrict__ ent, const int64_t* __restrict__ items,
+                                                      int64_t n_items, const float* __restrict__ refl,
+                                                      const float* __restrict__ nodes, const double* __restrict__ pix,
+                                                      const double* __restrict__ tile, const int64_t* __restrict__ rowptr,
+                                                      const int32_t* __restrict__ idx, const float* __restrict__ grad_image,
+                                                      double* __restrict__ sums, unsigned long long* __restrict__ counter) {
+  __shared__ float4 qn[128];
+  __shared__ float2 qd[128];
+  for (;;) {
+    unsigned long long mine = 0;
+    if (threadIdx.x == 0) mine = atomicAdd(counter, 1ull);
+    const int64_t it = (int64_t)__shfl(mine, 0, 64);
+    if (it >= n_items) break;
+    const int64_t packed = items[it];
+    const int m = (int)(packed >> 40);
+    const int t = (int)(packed & ((1ll << 40) - 1));
+    const fdtbx_batch_entry& e = ent[m];
+    ProfParams q;
+    prof_params(&e.model, &q);
+    adjoint_tile(q, refl + (int64_t)FDTBX_REFL_FLOATS * e.hkl_off, nodes + (int64_t)FDTBX_NODE_FLOATS * e.node_off,
+                 pix + 2 * e.pix_off, tile + 8 * e.tile_off, rowptr + e.rowptr_off, idx + e.pair_off,
+                 grad_image + e.pix_off, sums + 6 * e.hkl_off, t, qn, qd);
+  }
+}
+
+__device__ static void finish_params_of(const fdtbx_batch_entry& e, FinishParams* p) {
+  for (int i = 0; i < 3; ++i) {
+    p->Nb[i] = e.model.dis.N_base[i];
+    p->g[i] = e.model.dis.g[i];
+  }
+  p->intensity_model = e.model.dis.intensity_model;
+  p->n = e.n_hkl;
+}
+
+__global__ void __launch_bounds__(kFinThreads) k_b_finish(const fdtbx_batch_entry* __restrict__ ent, const int64_t* __restrict__ blocks,
+                                                          const int32_t* __restrict__ hkl, const float* __restrict__ refl,
+                                                          const double* __restrict__ sums, const float* __restrict__ F,
+                                                          float* __restrict__ dF2, double* __restrict__ part) {
+  const int64_t item = blocks[blockIdx.x];
+  const int m = (int)(item >> 40);
+  const fdtbx_batch_entry& e = ent[m];
+  const int64_t r = (item & ((1ll << 40) - 1)) + threadIdx.x;
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (r < e.n_hkl) {
+    FinishParams p;
+    finish_params_of(e, &p);
+    const int64_t g = e.hkl_off + r;
+    dF2[g] = (float)finish_one(p, hkl + 3 * g, refl + (int64_t)FDTBX_REFL_FLOATS * g, sums + 6 * g, F + 2 * g, v);
+  }
+  block_sum8(v, part);
+}
+
+// d_globals[m] = sum of the model's block partials, in block order.
+__global__ void k_b_globals(int32_t n_models, const int64_t* __restrict__ model_rb, const double* __restrict__ part,
+                            double* __restrict__ out) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_models) return;
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int64_t b = model_rb[m]; b < model_rb[m + 1]; ++b)
+    for (int c = 0; c < 8; ++c) v[c] += part[8 * b + c];
+  for (int c = 0; c < 8; ++c) out[8 * (int64_t)m + c] = v[c];
+}
+
+// One thread per atom of one model; loops over all of the model's reflections.
+__global__ void __launch_bounds__(kSAThreads) k_b_sf_adj(const fdtbx_batch_entry* __restrict__ ent, const int64_t* __restrict__ blocks,
+                                                         const float* __restrict__ x, const float* __restrict__ y,
+                                                         const float* __restrict__ z, const float* __restrict__ B,
+                                                         const float* __restrict__ occ, const int32_t* __restrict__ type,
+                                                         const float* __restrict__ ff, const int32_t* __restrict__ hkl,
+                                                         const float* __restrict__ F, const float* __restrict__ dF2,
+                                                         float* d_x, float* d_y, float* d_z, float* d_B, float* d_occ) {
+  __shared__ ReflLds rl[kSAThreads];
+  __shared__ float ft[kSAThreads][kSAMaxTypes + 1];
+  const int64_t item = blocks[blockIdx.x];
+  const int m = (int)(item >> 40);
+  const fdtbx_batch_entry& e = ent[m];
+  const int64_t al = (item & ((1ll << 40) - 1)) + threadIdx.x;
+  const bool have = al < e.n_atoms;
+  const int64_t a = e.atom_off + al;
+  const int n_types = e.n_types;
+  const float* ffm = ff + 9 * e.ff_off;
+  const double ax = have ? x[a] : 0.0, ay = have ? y[a] : 0.0, az = have ? z[a] : 0.0;
+  int ta = have ? type[a] : 0;
+  ta = ta < 0 ? 0 : (ta >= n_types ? n_types - 1 : ta);
+  const float nBl2e = have ? -B[a] * 1.4426950408889634f : 0.0f;
+  const int64_t r0 = e.hkl_off, r1 = e.hkl_off + e.n_hkl;
+  double g[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t g0 = r0; g0 < r1; g0 += kSAThreads) {
+    __syncthreads();
+    const int64_t r = g0 + threadIdx.x;
+    if (r < r1) {
+      const double h = hkl[3 * r], k = hkl[3 * r + 1], l = hkl[3 * r + 2];
+      double D[3];
+      for (int j = 0; j < 3; ++j) D[j] = (h * e.frame[9 + j] + k * e.frame[12 + j]) + l * e.frame[15 + j];
+      const double s2 = 0.25 * ((D[0] * D[0] + D[1] * D[1]) + D[2] * D[2]);
+      const float w = dF2[r];
+      rl[threadIdx.x] = {(int)h, (int)k, (int)l, (float)s2, w * F[2 * r], -w * F[2 * r + 1]};
+      for (int t = 0; t < n_types; ++t) {
+        const float* c = ffm + 9 * t;
+        double f = c[8];
+        for (int q = 0; q < 4; ++q) f += (double)c[q] * exp(-(double)c[4 + q] * s2);
+        ft[threadIdx.x][t] = (float)f;
+      }
+    }
+    __syncthreads();
+    const int cnt = (int)((r1 - g0) < kSAThreads ? (r1 - g0) : kSAThreads);
+    if (have) {
+      for (int i = 0; i < cnt; ++i) {
+        const ReflLds q = rl[i];
+        const double ph = fma((double)q.h, ax, fma((double)q.k, ay, (double)q.l * az));
+        const float fr = (float)(ph - floor(ph));
+        const float amp = ft[i][ta] * __builtin_amdgcn_exp2f(nBl2e * q.s2);
+        const float cs = __builtin_amdgcn_cosf(fr), sn = __builtin_amdgcn_sinf(fr);
+        const float re = amp * (q.cre * cs - q.cim * sn);
+        const float im = amp * (q.cre * sn + q.cim * cs);
+        g[0] = fma((double)q.h, (double)im, g[0]);
+        g[1] = fma((double)q.k, (double)im, g[1]);
+        g[2] = fma((double)q.l, (double)im, g[2]);
+        g[3] = fma((double)q.s2, (double)re, g[3]);
+        g[4] += (double)re;
+      }
+    }
+  }
+  if (have) {
+    const double o = occ[a];
+    const double fpi = 4.0 * M_PI;
+    if (d_x) d_x[a] = (float)(-fpi * o * g[0]);
+    if (d_y) d_y[a] = (float)(-fpi * o * g[1]);
+    if (d_z) d_z[a] = (float)(-fpi * o * g[2]);
+    if (d_B) d_B[a] = (float)(-2.0 * o * g[3]);
+    if (d_occ) d_occ[a] = (float)(2.0 * g[4]);
+  }
+}
+
+__global__ void k_b_set_globals(fdtbx_batch_entry* __restrict__ ent, int32_t n_models, const double* __restrict__ glob) {
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= n_models) return;
+  fdtbx_disorder& d = ent[m].model.dis;
+  d.sigma_theta = glob[8 * (int64_t)m + 0];
+  d.gamma_theta = glob[8 * (int64_t)m + 1];
+  for (int i = 0; i < 3; ++i) {
+    d.N_base[i] = glob[8 * (int64_t)m + 2 + i];
+    d.g[i] = glob[8 * (int64_t)m + 5 + i];
+  }
+}
+
+static constexpr unsigned kPersistentBlocksAdj = 8192;
+
 }  // namespace fdtbx
 
 using namespace fdtbx;
+
+extern "C" int fdtbx_batch_set_globals(fdtbx_batch_entry* entries, int32_t n_models, const double* globals, void* stream) {
+  if (!entries || !globals || n_models <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "bad arguments");
+  hipLaunchKernelGGL(k_b_set_globals, dim3((unsigned)ceil_div(n_models, 64)), dim3(64), 0, (hipStream_t)stream, entries,
+                     n_models, globals);
+  FDTBX_LAUNCH_CHECK("batch set globals");
+  return FDTBX_OK;
+}
+
+namespace fdtbx {
+int launch_batch_backward(const fdtbx_batch_entry* ent, int32_t n_models, const int64_t* refl_blocks, int64_t n_rb,
+                          const int64_t* model_rb, const int64_t* atom_blocks, int64_t n_ab, const int64_t* items,
+                          int64_t n_items, int64_t n_hkl_total, const int32_t* hkl, const float* x, const float* y,
+                          const float* z, const float* B, const float* occ, const int32_t* type, const float* ff,
+                          const double* pix, const double* tile, const int64_t* rowptr, const int32_t* idx, const float* F,
+                          const float* refl, const float* nodes, const float* grad_image, double* sums, double* part,
+                          float* dF2, float* d_x, float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals,
+                          int64_t* counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(6 * n_hkl_total, 256)), dim3(256), 0, s, sums, 6 * n_hkl_total);
+  FDTBX_LAUNCH_CHECK("batch adjoint zero");
+  hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, (double*)counter, (int64_t)1);
+  FDTBX_LAUNCH_CHECK("batch adjoint counter");
+  if (n_items > 0) {
+    unsigned nb = n_items < (int64_t)kPersistentBlocksAdj ? (unsigned)n_items : kPersistentBlocksAdj;
+    hipLaunchKernelGGL(k_b_profile_adj, dim3(nb), dim3(64), 0, s, ent, items, n_items, refl, nodes, pix, tile, rowptr, idx,
+                       grad_image, sums, (unsigned long long*)counter);
+    FDTBX_LAUNCH_CHECK("batch profile adjoint");
+  }
+  if (n_rb > 0) {
+    hipLaunchKernelGGL(k_b_finish, dim3((unsigned)n_rb), dim3(kFinThreads), 0, s, ent, refl_blocks, hkl, refl, sums, F, dF2,
+                       part);
+    FDTBX_LAUNCH_CHECK("batch adjoint finish");
+  }
+  hipLaunchKernelGGL(k_b_globals, dim3((unsigned)ceil_div(n_models, 64)), dim3(64), 0, s, n_models, model_rb, part, d_globals);
+  FDTBX_LAUNCH_CHECK("batch adjoint globals");
+  if (n_ab > 0 && (d_x || d_y || d_z || d_B || d_occ)) {
+    hipLaunchKernelGGL(k_b_sf_adj, dim3((unsigned)n_ab), dim3(kSAThreads), 0, s, ent, atom_blocks, x, y, z, B, occ, type, ff, hkl,
+                       F, dF2, d_x, d_y, d_z, d_B, d_occ);
+    FDTBX_LAUNCH_CHECK("batch sf adjoint");
+  }
+  return FDTBX_OK;
+}
+}  // namespace fdtbx
 
 extern "C" int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
                                      const double* tile, const int64_t* offsets, const int32_t* idx, int64_t n_hkl,

@@ -1,0 +1,138 @@
+// Per-tile body of the adjoint profile kernel, shared by the single-model and the
+// batched launches (see adjoint.hip for the quantities it accumulates).
+#pragma once
+
+#include "profile_common.h"
+
+namespace fdtbx {
+
+__device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, float al0, float al1, float al2, float gp,
+                                              float half_m, float tiny, float* acc) {
+  float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
+  float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
+  if (mx <= half_m) {
+    ya = fmaxf(fabsf(ya), tiny);
+    yb = fmaxf(fabsf(yb), tiny);
+    yc = fmaxf(fabsf(yc), tiny);
+    const float sa = __builtin_amdgcn_sinf(ya), sb = __builtin_amdgcn_sinf(yb), sc = __builtin_amdgcn_sinf(yc);
+    const float ca = __builtin_amdgcn_cosf(ya), cb = __builtin_amdgcn_cosf(yb), cc = __builtin_amdgcn_cosf(yc);
+    const float yab = ya * yb;
+    const float inv = __builtin_amdgcn_rcpf(yab * yc);
+    const float Sa = sa * (inv * (yb * yc));
+    const float Sb = sb * (inv * (ya * yc));
+    const float Sc = sc * (inv * yab);
+    const float Pa = Sa * Sa, Pb = Sb * Sb, Pc = Sc * Sc;
+    const float Pab = Pa * Pb;
+    const float P = Pab * Pc;
+    const float t = gp * P;
+    acc[0] = fmaf(nd.w, t, acc[0]);
+    acc[1] = fmaf(dw.x, t, acc[1]);
+    acc[2] = fmaf(dw.y, t, acc[2]);
+    const float four_pi = 12.566370614359172f;
+    const float t2 = gp * nd.w;
+    acc[3] = fmaf(t2, Sa * fmaf(four_pi, ca, -Sa) * (Pb * Pc), acc[3]);
+    acc[4] = fmaf(t2, Sb * fmaf(four_pi, cb, -Sb) * (Pa * Pc), acc[4]);
+    acc[5] = fmaf(t2, Sc * fmaf(four_pi, cc, -Sc) * Pab, acc[5]);
+  }
+}
+
+// One 8x8 tile t of one model, walked by one 64-lane wave.  qn, qd: LDS queue of 128 entries.
+__device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* __restrict__ refl, const float* __restrict__ nodes,
+                                             const double* __restrict__ pix, const double* __restrict__ tile,
+                                             const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
+                                             const float* __restrict__ grad_image, double* __restrict__ sums, const int t,
+                                             float4* qn, float2* qd) {
+  const int lane = threadIdx.x & 63;
+  const int tx = t % q.tiles_x, ty = t / q.tiles_x;
+  const int i = tx * FDTBX_TILE + (lane % FDTBX_TILE);
+  const int j = ty * FDTBX_TILE + (lane / FDTBX_TILE);
+  const bool in = i < q.W && j < q.H;
+  const double R = in ? pix[2 * ((int64_t)j * q.W + i) + 0] : 1.0e30;
+  const double Z = in ? pix[2 * ((int64_t)j * q.W + i) + 1] : 0.0;
+  const float gp = in ? grad_image[(int64_t)j * q.W + i] * (float)(q.delta / (R + q.delta)) : 0.0f;
+  const double bRlo = tile[8 * (int64_t)t + 0], bRhi = tile[8 * (int64_t)t + 1];
+  const double bZlo = tile[8 * (int64_t)t + 2], bZhi = tile[8 * (int64_t)t + 3];
+  const float Rlo = (float)bRlo, Rhi = (float)bRhi, Zlo = (float)bZlo, Zhi = (float)bZhi;
+  const int64_t p0 = offsets[t], p1 = offsets[t + 1];
+  // a tile whose pixels all carry zero weight adds nothing
+  if (__ballot(gp != 0.0f) == 0ull) return;
+  for (int64_t pp = p0; pp < p1; ++pp) {
+    const int32_t r = idx[pp];
+    const float* rec = refl + (int64_t)FDTBX_REFL_FLOATS * r;
+    Window w;
+    if (!node_window(q, rec, Rlo, Rhi, Zlo, Zhi, &w)) continue;
+    const double RD = *(const double*)(rec + RS_RD);
+    const double ZD = *(const double*)(rec + RS_ZD);
+    const float dR = (float)(R - RD), dZ = (float)(Z - ZD);
+    float al[3], lo[3], hi[3];
+    const float dRl = (float)(bRlo - RD), dRh = (float)(bRhi - RD);
+    const float dZl = (float)(bZlo - ZD), dZh = (float)(bZhi - ZD);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float tr = rec[RS_TR + a], tz = rec[RS_TZ + a];
+      al[a] = fmaf(tr, dR, tz * dZ);
+      const float r1 = tr * dRl, r2 = tr * dRh, z1 = tz * dZl, z2 = tz * dZh;
+      lo[a] = fminf(r1, r2) + fminf(z1, z2) - q.half_m - q.margin;
+      hi[a] = fmaxf(r1, r2) + fmaxf(z1, z2) + q.half_m + q.margin;
+    }
+    const float B0 = rec[RS_B + 0], B1 = rec[RS_B + 1], B2 = rec[RS_B + 2];
+    const float G10 = rec[RS_G1 + 0], G11 = rec[RS_G1 + 1], G12 = rec[RS_G1 + 2];
+    const float G20 = rec[RS_G2 + 0], G21 = rec[RS_G2 + 1], G22 = rec[RS_G2 + 2];
+    const int nw1 = w.i1hi - w.i1lo + 1;
+    const int nwin = nw1 * (w.i2hi - w.i2lo + 1);
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    int qlen = 0;
+    for (int w0 = 0; w0 < nwin; w0 += 64) {
+      const int wi = w0 + lane;
+      float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+      float2 ed = make_float2(0.f, 0.f);
+      bool keep = false;
+      if (wi < nwin) {
+        const int i1 = w.i1lo + wi % nw1, i2 = w.i2lo + wi / nw1;
+        const float* np_ = nodes + (int64_t)FDTBX_NODE_FLOATS * (i2 * q.n + i1);
+        const float4 nd = *(const float4*)np_;
+        const float2 nd2 = *(const float2*)(np_ + 4);
+        e.x = fmaf(nd.x, B0, fmaf(nd.y, G10, nd.z * G20));
+        e.y = fmaf(nd.x, B1, fmaf(nd.y, G11, nd.z * G21));
+        e.z = fmaf(nd.x, B2, fmaf(nd.y, G12, nd.z * G22));
+        e.w = nd.w;
+        ed = nd2;
+        keep = e.x >= lo[0] && e.x <= hi[0] && e.y >= lo[1] && e.y <= hi[1] && e.z >= lo[2] && e.z <= hi[2];
+      }
+      const unsigned long long b = __ballot(keep);
+      if (keep) {
+        const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
+        qn[pos] = e;
+        qd[pos] = ed;
+      }
+      qlen += __popcll(b);
+      __syncthreads();
+      if (qlen >= 64) {
+        for (int jj = 0; jj < 64; ++jj) eval_node_adj(qn[jj], qd[jj], al[0], al[1], al[2], gp, q.half_m, q.tiny, acc);
+        qlen -= 64;
+        __syncthreads();
+        if (lane < qlen) {
+          qn[lane] = qn[64 + lane];
+          qd[lane] = qd[64 + lane];
+        }
+        __syncthreads();
+      }
+    }
+    for (int jj = 0; jj < qlen; ++jj) eval_node_adj(qn[jj], qd[jj], al[0], al[1], al[2], gp, q.half_m, q.tiny, acc);
+    __syncthreads();
+    bool any = false;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+      float v = acc[c];
+      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+      acc[c] = v;
+      any |= v != 0.0f;
+    }
+    if (lane == 0 && any) {
+#pragma unroll
+      for (int c = 0; c < 6; ++c) unsafeAtomicAdd(&sums[6 * (int64_t)r + c], (double)acc[c]);
+    }
+  }
+}
+
+}  // namespace fdtbx

@@ -199,3 +199,44 @@ extern "C" int fdtbx_pattern_backward(const fdtbx_model* model, const int32_t* h
   return fdtbx_sf_adjoint(&model->cell, n_atoms, x, y, z, B, occ, type, ff, n_types, hkl, n_hkl, F, g2, d_x, d_y, d_z, d_B,
                           d_occ, w, fdtbx_sf_adjoint_workspace(n_hkl, n_atoms), stream);
 }
+
+extern "C" int fdtbx_batch_forward(const fdtbx_batch_entry* entries, int32_t n_models, const int64_t* refl_blocks, int64_t n_rb,
+                                   const int64_t* node_blocks, int64_t n_nb, const int64_t* tile_items, int64_t n_items,
+                                   const int32_t* hkl, const float* x, const float* y, const float* z, const float* B,
+                                   const float* occ, const int32_t* type, const float* ff, const double* pix,
+                                   const double* tile, const int64_t* rowptr, const int32_t* idx, float* F, float* F2,
+                                   float* refl, float* nodes, float* image, int64_t* counter, void* stream) {
+  if (!entries || n_models <= 0 || n_rb < 0 || n_nb < 0 || n_items < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "bad sizes");
+  if (!refl_blocks || !node_blocks || !tile_items || !hkl || !x || !y || !z || !B || !occ || !type || !ff || !pix || !tile ||
+      !rowptr || !idx || !F || !F2 || !refl || !nodes || !image || !counter)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  int rc = launch_batch_sf(entries, refl_blocks, n_rb, x, y, z, B, occ, type, ff, hkl, F, F2, s);
+  if (rc) return rc;
+  rc = launch_batch_prep(entries, refl_blocks, n_rb, hkl, F2, refl, s);
+  if (rc) return rc;
+  rc = launch_batch_nodes(entries, node_blocks, n_nb, nodes, s);
+  if (rc) return rc;
+  return launch_batch_profile(entries, tile_items, n_items, refl, nodes, pix, tile, rowptr, idx, image, counter, s);
+}
+
+extern "C" int fdtbx_batch_backward(const fdtbx_batch_entry* entries, int32_t n_models, const int64_t* refl_blocks, int64_t n_rb,
+                                    const int64_t* model_rb, const int64_t* atom_blocks, int64_t n_ab, const int64_t* tile_items,
+                                    int64_t n_items, int64_t n_hkl_total, const int32_t* hkl, const float* x, const float* y,
+                                    const float* z, const float* B, const float* occ, const int32_t* type, const float* ff,
+                                    const double* pix, const double* tile, const int64_t* rowptr, const int32_t* idx,
+                                    const float* F, const float* refl, const float* nodes, const float* grad_image,
+                                    double* sums, double* part, float* dF2, float* d_x, float* d_y, float* d_z, float* d_B,
+                                    float* d_occ, double* d_globals, int64_t* counter, void* stream) {
+  if (!entries || n_models <= 0 || n_rb < 0 || n_ab < 0 || n_items < 0 || n_hkl_total < 0)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "bad sizes");
+  if (!refl_blocks || !model_rb || !atom_blocks || !tile_items || !hkl || !x || !y || !z || !B || !occ || !type || !ff ||
+      !pix || !tile || !rowptr || !idx || !F || !refl || !nodes || !grad_image || !sums || !part || !dF2 || !d_globals ||
+      !counter)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  return launch_batch_backward(entries, n_models, refl_blocks, n_rb, model_rb, atom_blocks, n_ab, tile_items, n_items,
+                               n_hkl_total, hkl, x, y, z, B, occ, type, ff, pix, tile, rowptr, idx, F, refl, nodes, grad_image,
+                               sums, part, dF2, d_x, d_y, d_z, d_B, d_occ, d_globals, counter, (hipStream_t)stream);
+}
+
+extern "C" size_t fdtbx_batch_entry_size(void) { return sizeof(fdtbx_batch_entry); }

@@ -300,24 +300,29 @@ struct PrepParams {
 
 __device__ static inline double dotv(const double* u, const double* v) { return (u[0] * v[0] + u[1] * v[1]) + u[2] * v[2]; }
 
-// Culling record (see the header): conservative reach of the reflection's profile in (R, Z).
-// Nodes s = r0 c (S + d1 e1 + d2 e2), |d_j| <= T, c in [cmin, 1]; query points lie in
-// the support box of a node, whose extent along v is sum_i (m/N_i)|a*_i.v| with
-// 1/N_i <= 1/N_base,i + min(pi^2 g_i^2 h_i^2, 1).
-__global__ void __launch_bounds__(256) k_prep(PrepParams p, const int32_t* __restrict__ hkl, const float* __restrict__ F2,
-                                              float* __restrict__ refl, double* __restrict__ cull) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= p.n) return;
-  const double hh[3] = {(double)hkl[3 * r + 0], (double)hkl[3 * r + 1], (double)hkl[3 * r + 2]};
-  double D[3];
-  recip(p.f, hh[0], hh[1], hh[2], D);
+struct ReflFrame {
+  double D[3], r0, S[3], e1[3], e2[3], ep[3];
+  bool merid;
+};
+
+// Frame of one reflection (Eq. gnomonic's tangent vectors): S = D/r0, e1 = z x S/|z x S|,
+// e2 = S x e1, e_perp = radial unit vector of D about z; on the meridian e1 = x x S/|x x S|
+// and e_perp = sign(D_z) y.
+__device__ static void refl_frame(const Frame& f, const double* hh, ReflFrame* F) {
+  double* D = F->D;
+  recip(f, hh[0], hh[1], hh[2], D);
   double q = (D[0] * D[0] + D[1] * D[1]) + D[2] * D[2];
   double r0 = sqrt(q);
-  double S[3] = {D[0] / r0, D[1] / r0, D[2] / r0};
+  F->r0 = r0;
+  double* S = F->S;
+  S[0] = D[0] / r0;
+  S[1] = D[1] / r0;
+  S[2] = D[2] / r0;
   double RD = sqrt(D[0] * D[0] + D[1] * D[1]);
-  double e1[3], ep[3];
-  bool merid = !(RD > 1e-12);
-  if (!merid) {
+  double* e1 = F->e1;
+  double* ep = F->ep;
+  F->merid = !(RD > 1e-12);
+  if (!F->merid) {
     e1[0] = -D[1] / RD;
     e1[1] = D[0] / RD;
     e1[2] = 0.0;
@@ -333,10 +338,23 @@ __global__ void __launch_bounds__(256) k_prep(PrepParams p, const int32_t* __res
     ep[1] = D[2] > 0 ? 1.0 : (D[2] < 0 ? -1.0 : 0.0);
     ep[2] = 0.0;
   }
-  double e2[3] = {S[1] * e1[2] - S[2] * e1[1], S[2] * e1[0] - S[0] * e1[2], S[0] * e1[1] - S[1] * e1[0]};
-  const double ez[3] = {0.0, 0.0, 1.0};
+  double* e2 = F->e2;
+  e2[0] = S[1] * e1[2] - S[2] * e1[1];
+  e2[1] = S[2] * e1[0] - S[0] * e1[2];
+  e2[2] = S[0] * e1[1] - S[1] * e1[0];
+}
 
-  // ---- culling record (exact)
+// Culling record (see the header): conservative reach of the reflection's profile in (R, Z).
+// Nodes s = r0 c (S + d1 e1 + d2 e2), |d_j| <= T, c in [cmin, 1]; query points lie in
+// the support box of a node, whose extent along v is sum_i (m/N_i)|a*_i.v| with
+// 1/N_i <= 1/N_base,i + min(pi^2 g_i^2 h_i^2, 1).
+__device__ static void cull_record(const PrepParams& p, const double* hh, const ReflFrame& F, double* C) {
+  const double* S = F.S;
+  const double* e1 = F.e1;
+  const double* e2 = F.e2;
+  const double* ep = F.ep;
+  const double r0 = F.r0;
+  const double ez[3] = {0.0, 0.0, 1.0};
   double mN[3];
   for (int i = 0; i < 3; ++i) {
     double t = (kPi2 * (p.g[i] * p.g[i])) * (hh[i] * hh[i]);
@@ -358,7 +376,6 @@ __global__ void __launch_bounds__(256) k_prep(PrepParams p, const int32_t* __res
     *lo_out = s_lo - e;
     *hi_out = s_hi + e;
   };
-  double* C = cull + FDTBX_CULL_DOUBLES * r;
   double Rlo, Rhi, Zlo, Zhi;
   span(ep, &Rlo, &Rhi);
   span(ez, &Zlo, &Zhi);
@@ -372,7 +389,7 @@ __global__ void __launch_bounds__(256) k_prep(PrepParams p, const int32_t* __res
   C[3] = Zhi;
   C[4] = a_lo > 0.0 ? a_lo * a_lo : 0.0;
   C[5] = a_hi * a_hi;
-  if (!merid) {
+  if (!F.merid) {
     // wedge spanned in the (R, Z) plane by the in-plane node directions S + d2 e2, |d2| <= T
     double SR = dotv(S, ep), SZ = S[2], e2R = dotv(e2, ep), e2Z = e2[2];
     double vmR = SR - p.T * e2R, vmZ = SZ - p.T * e2Z;
@@ -402,16 +419,22 @@ __global__ void __launch_bounds__(256) k_prep(PrepParams p, const int32_t* __res
   bool alive = !(p.ext_limit > 0.0 && extinction_arg(p.g[0], p.g[1], p.g[2], hh[0], hh[1], hh[2]) > p.ext_limit);
   C[12] = alive ? 1.0 : 0.0;
   C[13] = C[14] = C[15] = 0.0;
+}
 
-  // ---- profile record (float32, from binary64 values)
+// Profile record (float32, from binary64 values; layout of ReflSlot).
+__device__ static void profile_record(const PrepParams& p, const double* hh, const ReflFrame& F, double f2, float* o) {
+  const double* S = F.S;
+  const double* e1 = F.e1;
+  const double* e2 = F.e2;
+  const double* ep = F.ep;
+  const double* D = F.D;
+  const double r0 = F.r0;
   double A[3], N[3], Ip = 1.0;
   for (int i = 0; i < 3; ++i) {
     A[i] = exp(-2.0 * kPi2 * (p.g[i] * p.g[i]) * (hh[i] * hh[i]));
     N[i] = 1.0 / (1.0 / p.Nb[i] + (1.0 - A[i]) / (1.0 + A[i]));
     if (p.intensity_model) Ip *= 2.0 * A[i] / (1.0 + A[i] * A[i]);
   }
-  float* o = refl + (int64_t)FDTBX_REFL_FLOATS * r;
-  double f2 = (double)F2[r];
   double W = f2 * Ip;
   const double two_pi = 2.0 * M_PI;
   double tp6 = two_pi * two_pi * two_pi;
@@ -451,6 +474,53 @@ __global__ void __launch_bounds__(256) k_prep(PrepParams p, const int32_t* __res
   }
   o[RS_F2] = (float)f2;
   for (int k = RS_K + 1; k < FDTBX_REFL_FLOATS; ++k) o[k] = 0.0f;
+}
+
+__global__ void __launch_bounds__(256) k_prep(PrepParams p, const int32_t* __restrict__ hkl, const float* __restrict__ F2,
+                                              float* __restrict__ refl, double* __restrict__ cull) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= p.n) return;
+  const double hh[3] = {(double)hkl[3 * r + 0], (double)hkl[3 * r + 1], (double)hkl[3 * r + 2]};
+  ReflFrame F;
+  refl_frame(p.f, hh, &F);
+  cull_record(p, hh, F, cull + FDTBX_CULL_DOUBLES * r);
+  profile_record(p, hh, F, (double)F2[r], refl + (int64_t)FDTBX_REFL_FLOATS * r);
+}
+
+// Batched models: block b of refl_blocks covers reflections [first, first + 256) of one model.
+__device__ static void prep_params_of(const fdtbx_batch_entry& e, PrepParams* p) {
+  for (int k = 0; k < 9; ++k) {
+    p->f.a[k] = e.frame[k];
+    p->f.s[k] = e.frame[9 + k];
+  }
+  p->f.V = e.frame[18];
+  for (int i = 0; i < 3; ++i) {
+    p->Nb[i] = e.model.dis.N_base[i];
+    p->g[i] = e.model.dis.g[i];
+  }
+  p->T = e.model.quad.T;
+  p->cmin = 1.0 / sqrt(1.0 + 2.0 * p->T * p->T);
+  p->m = (double)e.model.quad.m;
+  p->ext_limit = e.model.quad.extinction;
+  p->intensity_model = e.model.dis.intensity_model;
+  p->n = e.n_hkl;
+}
+
+__global__ void __launch_bounds__(256) k_b_prep(const fdtbx_batch_entry* __restrict__ ent, const int64_t* __restrict__ blocks,
+                                                const int32_t* __restrict__ hkl, const float* __restrict__ F2,
+                                                float* __restrict__ refl) {
+  const int64_t item = blocks[blockIdx.x];
+  const int m = (int)(item >> 40);
+  const int64_t r = (item & ((1ll << 40) - 1)) + threadIdx.x;
+  const fdtbx_batch_entry& e = ent[m];
+  if (r >= e.n_hkl) return;
+  PrepParams p;
+  prep_params_of(e, &p);
+  const int64_t g = e.hkl_off + r;
+  const double hh[3] = {(double)hkl[3 * g + 0], (double)hkl[3 * g + 1], (double)hkl[3 * g + 2]};
+  ReflFrame F;
+  refl_frame(p.f, hh, &F);
+  profile_record(p, hh, F, (double)F2[g], refl + (int64_t)FDTBX_REFL_FLOATS * g);
 }
 
 // ---------------------------------------------------------------- culling
@@ -679,3 +749,28 @@ extern "C" int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_
   }
   return FDTBX_OK;
 }
+
+extern "C" int fdtbx_batch_entry_init(const fdtbx_model* model, fdtbx_batch_entry* e) {
+  if (!model || !e) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  int rc = check_model(model);
+  if (rc) return rc;
+  e->model = *model;
+  Frame f;
+  make_frame(model->cell, &f);
+  for (int k = 0; k < 9; ++k) {
+    e->frame[k] = f.a[k];
+    e->frame[9 + k] = f.s[k];
+  }
+  e->frame[18] = f.V;
+  return FDTBX_OK;
+}
+
+namespace fdtbx {
+int launch_batch_prep(const fdtbx_batch_entry* ent, const int64_t* blocks, int64_t n_rb, const int32_t* hkl, const float* F2,
+                      float* refl, hipStream_t s) {
+  if (n_rb <= 0) return FDTBX_OK;
+  hipLaunchKernelGGL(k_b_prep, dim3((unsigned)n_rb), dim3(256), 0, s, ent, blocks, hkl, F2, refl);
+  FDTBX_LAUNCH_CHECK("batch prep");
+  return FDTBX_OK;
+}
+}  // namespace fdtbx

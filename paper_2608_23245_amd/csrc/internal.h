@@ -54,6 +54,25 @@ enum ReflSlot {
   RS_K = 42,       // r0^2 N_a N_b N_c / (2 pi)^6, so that RS_WK = W * RS_K
 };
 
+// Batched launchers (one per translation unit that owns the kernels).
+int launch_batch_sf(const fdtbx_batch_entry* ent, const int64_t* blocks, int64_t n_rb, const float* x, const float* y,
+                    const float* z, const float* B, const float* occ, const int32_t* type, const float* ff, const int32_t* hkl,
+                    float* F, float* F2, hipStream_t s);
+int launch_batch_prep(const fdtbx_batch_entry* ent, const int64_t* blocks, int64_t n_rb, const int32_t* hkl, const float* F2,
+                      float* refl, hipStream_t s);
+int launch_batch_nodes(const fdtbx_batch_entry* ent, const int64_t* blocks, int64_t n_nb, float* nodes, hipStream_t s);
+int launch_batch_profile(const fdtbx_batch_entry* ent, const int64_t* items, int64_t n_items, const float* refl,
+                         const float* nodes, const double* pix, const double* tile, const int64_t* rowptr, const int32_t* idx,
+                         float* image, int64_t* counter, hipStream_t s);
+int launch_batch_backward(const fdtbx_batch_entry* ent, int32_t n_models, const int64_t* refl_blocks, int64_t n_rb,
+                          const int64_t* model_rb, const int64_t* atom_blocks, int64_t n_ab, const int64_t* items,
+                          int64_t n_items, int64_t n_hkl_total, const int32_t* hkl, const float* x, const float* y,
+                          const float* z, const float* B, const float* occ, const int32_t* type, const float* ff,
+                          const double* pix, const double* tile, const int64_t* rowptr, const int32_t* idx, const float* F,
+                          const float* refl, const float* nodes, const float* grad_image, double* sums, double* part,
+                          float* dF2, float* d_x, float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals,
+                          int64_t* counter, hipStream_t s);
+
 // Cell frame in the laboratory convention: rows of avec are a, b, c; rows of
 // astar are a*, b*, c*.  Binary64, operation order fixed (compiled without
 // contraction in the exact translation unit).

@@ -101,13 +101,7 @@ __device__ static void shape(double D, double s, double g, const double* coef, d
   *dg = (du_g * v - u * dv_g) / (v * v);
 }
 
-__global__ void __launch_bounds__(256) k_nodes(NodeParams p, float* __restrict__ out) {
-  __shared__ double coef[kWN];
-  const double L = sqrt(kWN / sqrt(2.0));
-  if (threadIdx.x < kWN && p.sig != 0.0) coef[threadIdx.x] = weideman_coef(threadIdx.x + 1, L);
-  __syncthreads();
-  int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= p.n * p.n) return;
+__device__ static void node_record(const NodeParams& p, int k, const double* coef, double L, float* o) {
   int i1 = k % p.n, i2 = k / p.n;
   double d1 = -p.T + ((double)i1 + 0.5) * p.h;
   double d2 = -p.T + ((double)i2 + 0.5) * p.h;
@@ -119,7 +113,6 @@ __global__ void __launch_bounds__(256) k_nodes(NodeParams p, float* __restrict__
   double g, gs, gg;
   shape(Delta, p.sig, p.gam, coef, L, &g, &gs, &gg);
   double base = p.sigma_r * sqrt(2.0 * M_PI) * c * c * c * p.h * p.h;
-  float* o = out + (int64_t)FDTBX_NODE_FLOATS * k;
   o[0] = (float)cm1;
   o[1] = (float)(c * d1);
   o[2] = (float)(c * d2);
@@ -128,6 +121,45 @@ __global__ void __launch_bounds__(256) k_nodes(NodeParams p, float* __restrict__
   o[5] = (float)(base * gg);
   o[6] = (float)d1;
   o[7] = (float)d2;
+}
+
+__global__ void __launch_bounds__(256) k_nodes(NodeParams p, float* __restrict__ out) {
+  __shared__ double coef[kWN];
+  const double L = sqrt(kWN / sqrt(2.0));
+  if (threadIdx.x < kWN && p.sig != 0.0) coef[threadIdx.x] = weideman_coef(threadIdx.x + 1, L);
+  __syncthreads();
+  int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= p.n * p.n) return;
+  node_record(p, k, coef, L, out + (int64_t)FDTBX_NODE_FLOATS * k);
+}
+
+// Batched models: block b of node_blocks covers nodes [first, first + 256) of one model.
+__global__ void __launch_bounds__(256) k_b_nodes(const fdtbx_batch_entry* __restrict__ ent, const int64_t* __restrict__ blocks,
+                                                 float* __restrict__ out) {
+  __shared__ double coef[kWN];
+  const int64_t item = blocks[blockIdx.x];
+  const int m = (int)(item >> 40);
+  const int k = (int)(item & ((1ll << 40) - 1)) + threadIdx.x;
+  const fdtbx_batch_entry& e = ent[m];
+  NodeParams p;
+  p.n = e.model.quad.n_nodes;
+  p.T = e.model.quad.T;
+  p.h = 2.0 * p.T / p.n;
+  p.sigma_r = e.model.quad.sigma_r;
+  p.sig = e.model.dis.sigma_theta;
+  p.gam = e.model.dis.gamma_theta;
+  const double L = sqrt(kWN / sqrt(2.0));
+  if (threadIdx.x < kWN && p.sig != 0.0) coef[threadIdx.x] = weideman_coef(threadIdx.x + 1, L);
+  __syncthreads();
+  if (k >= p.n * p.n) return;
+  node_record(p, k, coef, L, out + (int64_t)FDTBX_NODE_FLOATS * (e.node_off + k));
+}
+
+int launch_batch_nodes(const fdtbx_batch_entry* ent, const int64_t* blocks, int64_t n_nb, float* nodes, hipStream_t s) {
+  if (n_nb <= 0) return FDTBX_OK;
+  hipLaunchKernelGGL(k_b_nodes, dim3((unsigned)n_nb), dim3(256), 0, s, ent, blocks, nodes);
+  FDTBX_LAUNCH_CHECK("batch nodes");
+  return FDTBX_OK;
 }
 
 }  // namespace fdtbx

@@ -66,11 +66,11 @@ __device__ static inline bool node_window(const ProfParams& q, const float* rec,
   return w->i1lo <= w->i1hi && w->i2lo <= w->i2hi;
 }
 
-inline void prof_params(const fdtbx_model* model, ProfParams* q) {
+__host__ __device__ inline void prof_params(const fdtbx_model* model, ProfParams* q) {
   q->W = model->geom.width;
   q->H = model->geom.height;
-  q->tiles_x = (int32_t)ceil_div(q->W, FDTBX_TILE);
-  q->tiles_y = (int32_t)ceil_div(q->H, FDTBX_TILE);
+  q->tiles_x = (q->W + FDTBX_TILE - 1) / FDTBX_TILE;
+  q->tiles_y = (q->H + FDTBX_TILE - 1) / FDTBX_TILE;
   q->n = model->quad.n_nodes;
   q->T = (float)model->quad.T;
   q->inv_h = (float)(model->quad.n_nodes / (2.0 * model->quad.T));

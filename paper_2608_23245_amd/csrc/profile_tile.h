@@ -1,0 +1,119 @@
+// Per-tile body of the forward profile kernel, shared by the single-model and the
+// batched launches.
+#pragma once
+
+#include "profile_common.h"
+
+namespace fdtbx {
+
+// Per-lane evaluation of one queued node: returns omega * (prod_i sin(2 pi y_i)/y_i)^2 if the
+// node is inside this pixel's support, else 0 (and counts it in COUNT mode).
+template <bool COUNT>
+__device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1, float al2, float half_m, float tiny,
+                                          float& accr, unsigned long long& cnt) {
+  float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
+  float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
+  if (mx <= half_m) {
+    if (COUNT) {
+      ++cnt;
+    } else {
+      ya = fmaxf(fabsf(ya), tiny);
+      yb = fmaxf(fabsf(yb), tiny);
+      yc = fmaxf(fabsf(yc), tiny);
+      const float num = __builtin_amdgcn_sinf(ya) * __builtin_amdgcn_sinf(yb) * __builtin_amdgcn_sinf(yc);
+      const float rr = num * __builtin_amdgcn_rcpf(ya * yb * yc);
+      accr = fmaf(nd.w, rr * rr, accr);
+    }
+  }
+}
+
+// One 8x8 tile t of one model, walked by one 64-lane wave.  qn: LDS queue of 128 entries.
+template <bool COUNT>
+__device__ __forceinline__ void profile_tile(const ProfParams& q, const float* __restrict__ refl,
+                                             const float* __restrict__ nodes, const double* __restrict__ pix,
+                                             const double* __restrict__ tile, const int64_t* __restrict__ offsets,
+                                             const int32_t* __restrict__ idx, float* __restrict__ image,
+                                             unsigned long long* __restrict__ counts, const int t, float4* qn) {
+  const int lane = threadIdx.x & 63;
+  const int tx = t % q.tiles_x, ty = t / q.tiles_x;
+  const int i = tx * FDTBX_TILE + (lane % FDTBX_TILE);
+  const int j = ty * FDTBX_TILE + (lane / FDTBX_TILE);
+  const bool in = i < q.W && j < q.H;
+  // lanes outside the detector sit far from every reflection: all supports fail
+  const double R = in ? pix[2 * ((int64_t)j * q.W + i) + 0] : 1.0e30;
+  const double Z = in ? pix[2 * ((int64_t)j * q.W + i) + 1] : 0.0;
+  const double bRlo = tile[8 * (int64_t)t + 0], bRhi = tile[8 * (int64_t)t + 1];
+  const double bZlo = tile[8 * (int64_t)t + 2], bZhi = tile[8 * (int64_t)t + 3];
+  const float Rlo = (float)bRlo, Rhi = (float)bRhi, Zlo = (float)bZlo, Zhi = (float)bZhi;
+  const int64_t p0 = offsets[t], p1 = offsets[t + 1];
+  const float tiny = q.tiny;
+  float acc = 0.0f;
+  unsigned long long cnt = 0;
+  for (int64_t pp = p0; pp < p1; ++pp) {
+    const float* rec = refl + (int64_t)FDTBX_REFL_FLOATS * idx[pp];
+    Window w;
+    if (!node_window(q, rec, Rlo, Rhi, Zlo, Zhi, &w)) continue;
+    const double RD = *(const double*)(rec + RS_RD);
+    const double ZD = *(const double*)(rec + RS_ZD);
+    const float dR = (float)(R - RD), dZ = (float)(Z - ZD);
+    float tr[3], tz[3], al[3], lo[3], hi[3];
+    // tile range of alpha_i (linear in R, Z: extremes at the box corners), widened by m/2
+    const float dRl = (float)(bRlo - RD), dRh = (float)(bRhi - RD);
+    const float dZl = (float)(bZlo - ZD), dZh = (float)(bZhi - ZD);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      tr[a] = rec[RS_TR + a];
+      tz[a] = rec[RS_TZ + a];
+      al[a] = fmaf(tr[a], dR, tz[a] * dZ);
+      const float r1 = tr[a] * dRl, r2 = tr[a] * dRh, z1 = tz[a] * dZl, z2 = tz[a] * dZh;
+      lo[a] = fminf(r1, r2) + fminf(z1, z2) - q.half_m - q.margin;
+      hi[a] = fmaxf(r1, r2) + fmaxf(z1, z2) + q.half_m + q.margin;
+    }
+    const float B0 = rec[RS_B + 0], B1 = rec[RS_B + 1], B2 = rec[RS_B + 2];
+    const float G10 = rec[RS_G1 + 0], G11 = rec[RS_G1 + 1], G12 = rec[RS_G1 + 2];
+    const float G20 = rec[RS_G2 + 0], G21 = rec[RS_G2 + 1], G22 = rec[RS_G2 + 2];
+    const int nw1 = w.i1hi - w.i1lo + 1;
+    const int nwin = nw1 * (w.i2hi - w.i2lo + 1);
+    float accr = 0.0f;
+    int qlen = 0;  // uniform
+    for (int w0 = 0; w0 < nwin; w0 += 64) {
+      const int wi = w0 + lane;
+      float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+      bool keep = false;
+      if (wi < nwin) {
+        const int i1 = w.i1lo + wi % nw1, i2 = w.i2lo + wi / nw1;
+        const float4 nd = *(const float4*)(nodes + (int64_t)FDTBX_NODE_FLOATS * (i2 * q.n + i1));
+        e.x = fmaf(nd.x, B0, fmaf(nd.y, G10, nd.z * G20));
+        e.y = fmaf(nd.x, B1, fmaf(nd.y, G11, nd.z * G21));
+        e.z = fmaf(nd.x, B2, fmaf(nd.y, G12, nd.z * G22));
+        e.w = nd.w;
+        keep = e.x >= lo[0] && e.x <= hi[0] && e.y >= lo[1] && e.y <= hi[1] && e.z >= lo[2] && e.z <= hi[2];
+      }
+      const unsigned long long b = __ballot(keep);
+      if (keep) {
+        const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
+        qn[pos] = e;
+      }
+      qlen += __popcll(b);
+      __syncthreads();
+      if (qlen >= 64) {
+        for (int jj = 0; jj < 64; ++jj) eval_node<COUNT>(qn[jj], al[0], al[1], al[2], q.half_m, tiny, accr, cnt);
+        qlen -= 64;
+        __syncthreads();
+        if (lane < qlen) qn[lane] = qn[64 + lane];
+        __syncthreads();
+      }
+    }
+    for (int jj = 0; jj < qlen; ++jj) eval_node<COUNT>(qn[jj], al[0], al[1], al[2], q.half_m, tiny, accr, cnt);
+    __syncthreads();
+    if (!COUNT) acc = fmaf(rec[RS_WK], accr, acc);
+  }
+  if (COUNT) {
+    for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if (lane == 0 && cnt) atomicAdd(counts, cnt);
+  } else if (in) {
+    image[(int64_t)j * q.W + i] = (float)(q.delta / (R + q.delta)) * acc;
+  }
+}
+
+}  // namespace fdtbx

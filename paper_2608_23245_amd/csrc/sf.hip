@@ -103,6 +103,84 @@ __global__ void k_sf_final(int64_t n_hkl, int32_t n_chunks, const float2* __rest
   if (F2) F2[r] = (float)(re * re + im * im);
 }
 
+// Batched models: block b of refl_blocks covers reflections [first, first + 256) of one
+// model and loops over all of that model's atoms (binary64 accumulation, no partials).
+__global__ void __launch_bounds__(kSFThreads) k_b_sf(const fdtbx_batch_entry* __restrict__ ent, const int64_t* __restrict__ blocks,
+                                                     const float* __restrict__ x, const float* __restrict__ y,
+                                                     const float* __restrict__ z, const float* __restrict__ B,
+                                                     const float* __restrict__ occ, const int32_t* __restrict__ type,
+                                                     const float* __restrict__ ff, const int32_t* __restrict__ hkl,
+                                                     float* __restrict__ F, float* __restrict__ F2) {
+  __shared__ AtomLds at[kSFThreads];
+  __shared__ float ftab[kMaxTypes][kSFThreads];
+  const int64_t item = blocks[blockIdx.x];
+  const int m = (int)(item >> 40);
+  const fdtbx_batch_entry& e = ent[m];
+  const int64_t r = (item & ((1ll << 40) - 1)) + threadIdx.x;
+  const bool have = r < e.n_hkl;
+  const int64_t g = e.hkl_off + r;
+  const int n_types = e.n_types;
+  const float* ffm = ff + 9 * e.ff_off;
+  double h = 0, k = 0, l = 0;
+  float s2 = 0.0f;
+  if (have) {
+    h = hkl[3 * g + 0];
+    k = hkl[3 * g + 1];
+    l = hkl[3 * g + 2];
+    double D[3];
+    for (int j = 0; j < 3; ++j) D[j] = (h * e.frame[9 + j] + k * e.frame[12 + j]) + l * e.frame[15 + j];
+    double q = (D[0] * D[0] + D[1] * D[1]) + D[2] * D[2];
+    double s2d = 0.25 * q;
+    s2 = (float)s2d;
+    for (int t = 0; t < n_types; ++t) {
+      const float* c = ffm + 9 * t;
+      double f = c[8];
+      for (int q2 = 0; q2 < 4; ++q2) f += (double)c[q2] * exp(-(double)c[4 + q2] * s2d);
+      ftab[t][threadIdx.x] = (float)f;
+    }
+  }
+  const int64_t a0 = e.atom_off, a1 = e.atom_off + e.n_atoms;
+  double re = 0.0, im = 0.0;
+  const float log2e = 1.4426950408889634f;
+  for (int64_t g0 = a0; g0 < a1; g0 += kSFThreads) {
+    __syncthreads();
+    const int64_t j = g0 + threadIdx.x;
+    if (j < a1) {
+      int t = type[j];
+      t = t < 0 ? 0 : (t >= n_types ? n_types - 1 : t);
+      at[threadIdx.x] = {x[j], y[j], z[j], -B[j] * log2e, occ[j], t};
+    }
+    __syncthreads();
+    const int cnt = (int)((a1 - g0) < kSFThreads ? (a1 - g0) : kSFThreads);
+    if (have) {
+      for (int i = 0; i < cnt; ++i) {
+        const AtomLds a = at[i];
+        double ph = fma(h, (double)a.x, fma(k, (double)a.y, l * (double)a.z));
+        float frac = (float)(ph - floor(ph));
+        float amp = a.occ * ftab[a.type][threadIdx.x] * __builtin_amdgcn_exp2f(a.nBl2e * s2);
+        re = fma((double)amp, (double)__builtin_amdgcn_cosf(frac), re);
+        im = fma((double)amp, (double)__builtin_amdgcn_sinf(frac), im);
+      }
+    }
+  }
+  if (have) {
+    if (F) {
+      F[2 * g + 0] = (float)re;
+      F[2 * g + 1] = (float)im;
+    }
+    if (F2) F2[g] = (float)(re * re + im * im);
+  }
+}
+
+int launch_batch_sf(const fdtbx_batch_entry* ent, const int64_t* blocks, int64_t n_rb, const float* x, const float* y,
+                    const float* z, const float* B, const float* occ, const int32_t* type, const float* ff, const int32_t* hkl,
+                    float* F, float* F2, hipStream_t s) {
+  if (n_rb <= 0) return FDTBX_OK;
+  hipLaunchKernelGGL(k_b_sf, dim3((unsigned)n_rb), dim3(kSFThreads), 0, s, ent, blocks, x, y, z, B, occ, type, ff, hkl, F, F2);
+  FDTBX_LAUNCH_CHECK("batch structure factors");
+  return FDTBX_OK;
+}
+
 static void sf_split(int64_t n_hkl, int64_t n_atoms, int32_t* n_chunks, int64_t* chunk) {
   int64_t nb = ceil_div(n_hkl, kSFThreads);
   int64_t want = ceil_div(4096, nb);                       // fill the chip with >= 4096 blocks
