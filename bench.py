@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
     ap.add_argument("--cpu-pixels", type=int, default=256)
+    ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-model leg")
+    ap.add_argument("--batch-models", type=int, default=256)
+    ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="also run one device-to-device copy of this many MiB (reference kernel for the "
                          "FETCH_SIZE/WRITE_SIZE counters)")
@@ -161,7 +165,146 @@ def main():
     }
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(wl, state, args.cpu_pixels)
+    del state
+    torch.cuda.empty_cache()
+    if not args.no_bwd:
+        out["fwd_bwd"] = bench_fwd_bwd(args)
+        torch.cuda.empty_cache()
+    if not args.no_batch:
+        out["batched"] = bench_batched(args)
     print(json.dumps(out), flush=True)
+
+
+def bench_fwd_bwd(args):
+    """Refinement step on the medium model: structure factors, pattern, pixel weights of the
+    weighted residual against a target image, and the hand-written adjoint down to the atom
+    and global gradients.  The target is the image of the perturbed target model."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2608_23245_amd import autograd as AG
+    from paper_2608_23245_amd import binding as B
+
+    gw = W.config3()
+    eng_t = AG.PatternEngine(gw.target)
+    ta = gw.target.atoms
+    at_t = eng_t.atoms(*(torch.as_tensor(v) for v in (ta.x, ta.y, ta.z, ta.B, ta.occ)))
+    _, F2t = B.structure_factors(eng_t.cell, at_t, eng_t.hkl)
+    target = eng_t.plan.run(eng_t.hkl, F2t).clone()
+    del eng_t, at_t, F2t
+    torch.cuda.empty_cache()
+    eng = AG.PatternEngine(gw.model)
+    a = gw.model.atoms
+    atoms = eng.atoms(*(torch.as_tensor(v) for v in (a.x, a.y, a.z, a.B, a.occ)))
+    w = 1.0 / (target + 1e-3 * target.max())
+    stream = torch.cuda.current_stream()
+    res = {}
+
+    def step(ev=None):
+        F, F2 = B.structure_factors(eng.cell, atoms, eng.hkl)
+        img = eng.plan.run(eng.hkl, F2)
+        G = (2.0 * w * (img - target)).contiguous()
+        if ev is not None:
+            ev[0].record(stream)
+        out, glob, _ = B.pattern_backward(eng.plan, eng.hkl, F, G, atoms)
+        if ev is not None:
+            ev[1].record(stream)
+        res.update(img=img, G=G, glob=glob)
+
+    for _ in range(max(args.warmup, 1)):
+        step()
+    torch.cuda.synchronize()
+    evs = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        step(evs[k])
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    bwd_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    loss = float((w * (res["img"] - target) ** 2).sum().item())
+    assert np.isfinite(loss) and torch.isfinite(res["glob"]).all()
+    return {"workload": "refinement: medium model vs perturbed target (xyz N(0,0.1 A), B x1.2, sigma 3.5 deg, g .035), "
+                        "loss sum w (I - T)^2, w = 1/(T + 1e-3 max T)",
+            "ms_per_step": ms, "backward_ms": bwd_ms, "forward_ms": ms - bwd_ms, "loss": loss,
+            "steps": args.steps, "pass": "forward + adjoint (atoms xyz/B/occ, sigma, gamma, N_base, g)"}
+
+
+def bench_batched(args):
+    """Batched refinement step (forward + adjoint of every model) captured in one HIP graph,
+    against the plain single-model forward of each model run one after the other."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2608_23245_amd import binding as B
+    from paper_2608_23245_amd.batch import BatchEngine, GraphStep
+
+    wls = W.config4(n_models=args.batch_models)
+    t0 = time.perf_counter()
+    be = BatchEngine(wls)
+    torch.cuda.synchronize()
+    setup_s = time.perf_counter() - t0
+    glob = be.globals()
+    tglob = glob.clone()
+    tglob[:, 0] *= 1.1
+    be.set_globals(tglob)
+    target = be.forward().clone()
+    be.set_globals(glob)
+    # useful evaluations: counting pass of the single-model kernel on each model's part of the batch
+    be.forward()
+    torch.cuda.synchronize()
+    n_evals = 0
+    for m, mod in enumerate(be.models):
+        e = be._host_entries[m]
+        refl = be.refl[e.hkl_off:e.hkl_off + e.n_hkl]
+        nodes = be.nodes[e.node_off:e.node_off + wls[m].quad.n_nodes ** 2]
+        pix = be.pix[e.pix_off:e.pix_off + wls[m].geom.width * wls[m].geom.height]
+        tile = be.tile[e.tile_off:e.tile_off + e.n_tiles]
+        rowptr = be.rowptr[e.rowptr_off:e.rowptr_off + e.n_tiles + 1]
+        idx = be.idx[e.pair_off:e.pair_off + max(be.list_len[m], 1)]
+        n_evals += B.profile(mod, refl, nodes, pix, tile, rowptr, idx, count=True)
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    be.forward()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fwd_ms = e0.elapsed_time(e1)
+    step = GraphStep(be, target)
+    step.capture()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.batch_steps):
+        step.replay()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.batch_steps
+    assert torch.isfinite(be.d_globals).all()
+    del step
+    # plain single-model forwards, one after the other (each with its own culling)
+    from paper_2608_23245_amd import Pipeline
+    torch.cuda.synchronize()
+    single_ms = 0.0
+    for wl in wls:
+        pipe = Pipeline(wl)
+        _, F2 = pipe.structure_factors()
+        pipe.pattern(F2)              # sizes the plan's culling capacity
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, F2 = pipe.structure_factors()
+        pipe.pattern(F2)
+        torch.cuda.synchronize()
+        single_ms += (time.perf_counter() - t0) * 1e3
+        del pipe
+    return {"workload": f"{len(wls)} ragged models (edges U(10,80) A, 500-20000 atoms, 256^2-1024^2 px, "
+                        "Voigt sigma U(1,8) deg, eta U(0,1), g U(0,.06), d_min U(2,3) A, 32x32 nodes)",
+            "n_models": len(wls), "n_hkl": int(be.totals["hkl"]), "pixels": int(be.totals["pix"]),
+            "culled_pairs": int(be.totals["pair"]), "useful_evals_per_forward": int(n_evals),
+            "setup_s": setup_s, "graph_ms_per_step": ms, "graph_steps": args.batch_steps,
+            "batched_forward_ms": fwd_ms, "batched_forward_evals_per_s": n_evals / (fwd_ms * 1e-3),
+            "sum_single_forward_ms": single_ms,
+            "forward_speedup_vs_single": single_ms / fwd_ms,
+            "pass": "one HIP graph: batched forward + pixel weights + batched adjoint of all models"}
 
 
 def cpu_baseline(wl, state, n_pix):
