@@ -11,9 +11,9 @@ __device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, 
   float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
   float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
   if (mx <= half_m) {
-    ya = fmaxf(fabsf(ya), tiny);
-    yb = fmaxf(fabsf(yb), tiny);
-    yc = fmaxf(fabsf(yc), tiny);
+    ya = fabsf(ya) + tiny;
+    yb = fabsf(yb) + tiny;
+    yc = fabsf(yc) + tiny;
     const float sa = __builtin_amdgcn_sinf(ya), sb = __builtin_amdgcn_sinf(yb), sc = __builtin_amdgcn_sinf(yc);
     const float ca = __builtin_amdgcn_cosf(ya), cb = __builtin_amdgcn_cosf(yb), cc = __builtin_amdgcn_cosf(yc);
     const float yab = ya * yb;
@@ -33,6 +33,20 @@ __device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, 
     acc[3] = fmaf(t2, Sa * fmaf(four_pi, ca, -Sa) * (Pb * Pc), acc[3]);
     acc[4] = fmaf(t2, Sb * fmaf(four_pi, cb, -Sb) * (Pa * Pc), acc[4]);
     acc[5] = fmaf(t2, Sc * fmaf(four_pi, cc, -Sc) * Pab, acc[5]);
+  }
+}
+
+// Every lane walks the first cnt queue entries, reading entry jj + 1 before evaluating jj.
+__device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* qd, int cnt, const float* al, float gp,
+                                               float half_m, float tiny, float* acc) {
+  float4 nxt = qn[0];
+  float2 nxt2 = qd[0];
+  for (int jj = 0; jj < cnt; ++jj) {
+    const float4 cur = nxt;
+    const float2 cur2 = nxt2;
+    nxt = qn[jj + 1];
+    nxt2 = qd[jj + 1];
+    eval_node_adj(cur, cur2, al[0], al[1], al[2], gp, half_m, tiny, acc);
   }
 }
 
@@ -80,6 +94,7 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
     const float G20 = rec[RS_G2 + 0], G21 = rec[RS_G2 + 1], G22 = rec[RS_G2 + 2];
     const int nw1 = w.i1hi - w.i1lo + 1;
     const int nwin = nw1 * (w.i2hi - w.i2lo + 1);
+    const float inv_nw1 = 1.0f / (float)nw1;
     float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int qlen = 0;
     for (int w0 = 0; w0 < nwin; w0 += 64) {
@@ -88,7 +103,9 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
       float2 ed = make_float2(0.f, 0.f);
       bool keep = false;
       if (wi < nwin) {
-        const int i1 = w.i1lo + wi % nw1, i2 = w.i2lo + wi / nw1;
+        int d1, d2;
+        window_node(wi, nw1, inv_nw1, &d1, &d2);
+        const int i1 = w.i1lo + d1, i2 = w.i2lo + d2;
         const float* np_ = nodes + (int64_t)FDTBX_NODE_FLOATS * (i2 * q.n + i1);
         const float4 nd = *(const float4*)np_;
         const float2 nd2 = *(const float2*)(np_ + 4);
@@ -108,7 +125,7 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
       qlen += __popcll(b);
       __syncthreads();
       if (qlen >= 64) {
-        for (int jj = 0; jj < 64; ++jj) eval_node_adj(qn[jj], qd[jj], al[0], al[1], al[2], gp, q.half_m, q.tiny, acc);
+        walk_queue_adj(qn, qd, 64, al, gp, q.half_m, q.tiny, acc);
         qlen -= 64;
         __syncthreads();
         if (lane < qlen) {
@@ -118,7 +135,7 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
         __syncthreads();
       }
     }
-    for (int jj = 0; jj < qlen; ++jj) eval_node_adj(qn[jj], qd[jj], al[0], al[1], al[2], gp, q.half_m, q.tiny, acc);
+    walk_queue_adj(qn, qd, qlen, al, gp, q.half_m, q.tiny, acc);
     __syncthreads();
     bool any = false;
 #pragma unroll

@@ -16,7 +16,7 @@ struct ProfParams {
   float T, inv_h;   // grid half extent, 1/spacing
   float half_m;     // m/2
   float cmin;       // (1 + 2T^2)^(-1/2)
-  float tiny;       // lower clamp of |y| (sinc(2y) at |y| < tiny differs from 1 by < 7e-12)
+  float tiny;       // added to |y|: keeps sin(2 pi y)/y finite at y = 0, exact in float32 for |y| > 1e-5
   float margin;     // slack of the tile-level node test, in y units
   double delta;     // Lorentz regulariser
 };
@@ -27,7 +27,8 @@ struct Window {
 
 // Node index range that the query points of a tile box can reach.  A node in the
 // support of p satisfies |s.v - p.v| <= rho_v for v in {S, e1, e2}; s.S = r0 c is in
-// [r0 cmin, r0]; d_j = (s.e_j)/(s.S).  One extra node of margin on each side.
+// [r0 cmin, r0]; d_j = (s.e_j)/(s.S).  One extra node of margin on each side absorbs the
+// float32 rounding of these bounds (hardware reciprocals included).
 __device__ static inline bool node_window(const ProfParams& q, const float* rec, float Rlo, float Rhi, float Zlo, float Zhi,
                                           Window* w) {
   auto range = [&](float cR, float cZ, float* lo, float* hi) {
@@ -44,9 +45,10 @@ __device__ static inline bool node_window(const ProfParams& q, const float* rec,
   float dlo_s = fmaxf(sl - rS, r0 * q.cmin * 0.9999f);
   float dhi_s = fminf(sh + rS, r0 * 1.0001f);
   if (!(dlo_s <= dhi_s)) return false;
+  const float inv_lo = __builtin_amdgcn_rcpf(dlo_s), inv_hi = __builtin_amdgcn_rcpf(dhi_s);
   auto bounds = [&](float nl, float nh, float* dlo, float* dhi) {
-    *dlo = nl >= 0.0f ? nl / dhi_s : nl / dlo_s;
-    *dhi = nh >= 0.0f ? nh / dlo_s : nh / dhi_s;
+    *dlo = nl * (nl >= 0.0f ? inv_hi : inv_lo);
+    *dhi = nh * (nh >= 0.0f ? inv_lo : inv_hi);
   };
   float d1l, d1h, d2l, d2h;
   bounds(l1 - r1, h1 + r1, &d1l, &d1h);
@@ -66,6 +68,22 @@ __device__ static inline bool node_window(const ProfParams& q, const float* rec,
   return w->i1lo <= w->i1hi && w->i2lo <= w->i2hi;
 }
 
+// Window node wi -> (i1, i2) for a window nw1 nodes wide, through a float reciprocal
+// (exact integers below 2^24) with a one-step correction instead of an integer division.
+__device__ static inline void window_node(int wi, int nw1, float inv_nw1, int* i1, int* i2) {
+  int q2 = (int)((float)wi * inv_nw1);
+  int q1 = wi - q2 * nw1;
+  if (q1 < 0) {
+    q2 -= 1;
+    q1 += nw1;
+  } else if (q1 >= nw1) {
+    q2 += 1;
+    q1 -= nw1;
+  }
+  *i1 = q1;
+  *i2 = q2;
+}
+
 __host__ __device__ inline void prof_params(const fdtbx_model* model, ProfParams* q) {
   q->W = model->geom.width;
   q->H = model->geom.height;
@@ -76,7 +94,7 @@ __host__ __device__ inline void prof_params(const fdtbx_model* model, ProfParams
   q->inv_h = (float)(model->quad.n_nodes / (2.0 * model->quad.T));
   q->half_m = 0.5f * (float)model->quad.m;
   q->cmin = (float)(1.0 / sqrt(1.0 + 2.0 * model->quad.T * model->quad.T));
-  q->tiny = 1.0e-6f;
+  q->tiny = 1.0e-12f;
   q->margin = 1.0e-3f;
   q->delta = model->quad.delta;
 }

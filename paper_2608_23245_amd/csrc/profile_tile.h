@@ -17,9 +17,9 @@ __device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1,
     if (COUNT) {
       ++cnt;
     } else {
-      ya = fmaxf(fabsf(ya), tiny);
-      yb = fmaxf(fabsf(yb), tiny);
-      yc = fmaxf(fabsf(yc), tiny);
+      ya = fabsf(ya) + tiny;
+      yb = fabsf(yb) + tiny;
+      yc = fabsf(yc) + tiny;
       const float num = __builtin_amdgcn_sinf(ya) * __builtin_amdgcn_sinf(yb) * __builtin_amdgcn_sinf(yc);
       const float rr = num * __builtin_amdgcn_rcpf(ya * yb * yc);
       accr = fmaf(nd.w, rr * rr, accr);
@@ -28,6 +28,19 @@ __device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1,
 }
 
 // One 8x8 tile t of one model, walked by one 64-lane wave.  qn: LDS queue of 128 entries.
+// Every lane walks the first cnt queue entries; the read of entry jj + 1 is issued before
+// entry jj is evaluated (the buffer holds 128 entries, cnt <= 64, so it stays in bounds).
+template <bool COUNT>
+__device__ __forceinline__ void walk_queue(const float4* qn, int cnt, const float* al, float half_m, float tiny, float& accr,
+                                           unsigned long long& cnt_eval) {
+  float4 nxt = qn[0];
+  for (int jj = 0; jj < cnt; ++jj) {
+    const float4 cur = nxt;
+    nxt = qn[jj + 1];
+    eval_node<COUNT>(cur, al[0], al[1], al[2], half_m, tiny, accr, cnt_eval);
+  }
+}
+
 template <bool COUNT>
 __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* __restrict__ refl,
                                              const float* __restrict__ nodes, const double* __restrict__ pix,
@@ -74,6 +87,7 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
     const float G20 = rec[RS_G2 + 0], G21 = rec[RS_G2 + 1], G22 = rec[RS_G2 + 2];
     const int nw1 = w.i1hi - w.i1lo + 1;
     const int nwin = nw1 * (w.i2hi - w.i2lo + 1);
+    const float inv_nw1 = 1.0f / (float)nw1;
     float accr = 0.0f;
     int qlen = 0;  // uniform
     for (int w0 = 0; w0 < nwin; w0 += 64) {
@@ -81,7 +95,9 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
       float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
       bool keep = false;
       if (wi < nwin) {
-        const int i1 = w.i1lo + wi % nw1, i2 = w.i2lo + wi / nw1;
+        int d1, d2;
+        window_node(wi, nw1, inv_nw1, &d1, &d2);
+        const int i1 = w.i1lo + d1, i2 = w.i2lo + d2;
         const float4 nd = *(const float4*)(nodes + (int64_t)FDTBX_NODE_FLOATS * (i2 * q.n + i1));
         e.x = fmaf(nd.x, B0, fmaf(nd.y, G10, nd.z * G20));
         e.y = fmaf(nd.x, B1, fmaf(nd.y, G11, nd.z * G21));
@@ -97,14 +113,14 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
       qlen += __popcll(b);
       __syncthreads();
       if (qlen >= 64) {
-        for (int jj = 0; jj < 64; ++jj) eval_node<COUNT>(qn[jj], al[0], al[1], al[2], q.half_m, tiny, accr, cnt);
+        walk_queue<COUNT>(qn, 64, al, q.half_m, tiny, accr, cnt);
         qlen -= 64;
         __syncthreads();
         if (lane < qlen) qn[lane] = qn[64 + lane];
         __syncthreads();
       }
     }
-    for (int jj = 0; jj < qlen; ++jj) eval_node<COUNT>(qn[jj], al[0], al[1], al[2], q.half_m, tiny, accr, cnt);
+    walk_queue<COUNT>(qn, qlen, al, q.half_m, tiny, accr, cnt);
     __syncthreads();
     if (!COUNT) acc = fmaf(rec[RS_WK], accr, acc);
   }
