@@ -36,20 +36,33 @@ SLOTS_PER_EVAL = 12 + 4 * 4
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 
 
+def log(msg):
+    """Progress line on stderr (the JSON result is the only line on stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def profile_source_sha():
+    """sha256 prefix over the sources the forward profile kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("profile.hip", "profile_tile.h", "profile_common.h"):
+        with open(os.path.join(ROOT, "paper_2608_23245_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
 def measured_traffic():
     """HBM bytes per launch of the profile kernel from the committed counter summary,
     or None when the kernel source has changed since the counters were taken."""
-    import hashlib
     import re
-    src = os.path.join(ROOT, "paper_2608_23245_amd", "csrc", "profile.hip")
     summ = os.path.join(ROOT, "profiles", "k_profile_medium_traffic.md")
     try:
         text = open(summ).read()
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+        sha = profile_source_sha()
     except OSError:
         return None
     m = re.search(r"traffic_bytes_per_launch: ([0-9.eE+]+)", text)
-    h = re.search(r"profile.hip sha256 prefix at measurement: ([0-9a-f]+)", text)
+    h = re.search(r"profile kernel sources sha256 prefix at measurement: ([0-9a-f]+)", text)
     if not m or not h or h.group(1) != sha:
         return None
     return float(m.group(1))
@@ -119,9 +132,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    log(f"forward: {wl.name}, {args.warmup} warm-up steps")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    log(f"forward: {args.steps} timed steps")
     events = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(args.steps)]
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -137,6 +152,7 @@ def main():
     n_evals = B.profile(model, state["refl"], state["nodes"], state["pix"], state["tile"], state["off"], state["idx"],
                         count=True)
 
+    log(f"forward: {ms_step:.1f} ms/step, profile kernel {prof_ms:.1f} ms, {n_evals:.4e} useful evaluations")
     slots = n_evals * SLOTS_PER_EVAL
     achieved = slots / (prof_ms * 1e-3) / 1e12
     peak = PEAK_SLOTS / 1e12
@@ -164,13 +180,16 @@ def main():
                      "slots_per_eval": SLOTS_PER_EVAL},
     }
     if not args.no_cpu:
+        log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, state, args.cpu_pixels)
     del state
     torch.cuda.empty_cache()
     if not args.no_bwd:
+        log("forward + adjoint")
         out["fwd_bwd"] = bench_fwd_bwd(args)
         torch.cuda.empty_cache()
     if not args.no_batch:
+        log(f"batched: {args.batch_models} models")
         out["batched"] = bench_batched(args)
     print(json.dumps(out), flush=True)
 
@@ -245,6 +264,7 @@ def bench_batched(args):
     be = BatchEngine(wls)
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
+    log(f"batched: set-up {setup_s:.1f} s, {be.totals['pair']} culled pairs")
     glob = be.globals()
     tglob = glob.clone()
     tglob[:, 0] *= 1.1
@@ -271,9 +291,11 @@ def bench_batched(args):
     e1.record(stream)
     torch.cuda.synchronize()
     fwd_ms = e0.elapsed_time(e1)
+    log(f"batched: forward {fwd_ms:.1f} ms; capturing the refinement step")
     step = GraphStep(be, target)
     step.capture()
     torch.cuda.synchronize()
+    log(f"batched: {args.batch_steps} graph replays")
     t0 = time.perf_counter()
     for _ in range(args.batch_steps):
         step.replay()
@@ -285,7 +307,10 @@ def bench_batched(args):
     from paper_2608_23245_amd import Pipeline
     torch.cuda.synchronize()
     single_ms = 0.0
-    for wl in wls:
+    log(f"batched: graph step {ms:.1f} ms; single-model forwards")
+    for m, wl in enumerate(wls):
+        if m % 64 == 63:
+            log(f"batched: single-model forwards {m + 1}/{len(wls)}")
         pipe = Pipeline(wl)
         _, F2 = pipe.structure_factors()
         pipe.pattern(F2)              # sizes the plan's culling capacity
