@@ -29,9 +29,11 @@ sys.path.insert(0, ROOT)
 # this formulation: 3 subtractions (lattice coordinates relative to the node),
 # 1 three-way max and 1 compare (support), 4 multiplies (sine and coordinate
 # products), 1 multiply and 1 square (ratio), 1 fused multiply-add (weighted
-# accumulate) at full rate, plus 3 sines and 1 reciprocal at quarter rate
-# (4 slots each).
-SLOTS_PER_EVAL = 12 + 4 * 4
+# accumulate) at full rate, plus 3 sines and 1 reciprocal, which gfx950 issues
+# at half rate (2 slots each; a throughput kernel of independent v_sin_f32 or
+# v_rcp_f32 chains reaches half the v_fma_f32 rate).
+TRANS_SLOTS = 2
+SLOTS_PER_EVAL = 12 + 4 * TRANS_SLOTS
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = VALU lane issue slots per second.
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 
@@ -278,7 +280,7 @@ def bench_batched(args):
     for m, mod in enumerate(be.models):
         e = be._host_entries[m]
         refl = be.refl[e.hkl_off:e.hkl_off + e.n_hkl]
-        nodes = be.nodes[e.node_off:e.node_off + wls[m].quad.n_nodes ** 2]
+        nodes = be.nodes[e.node_off:e.node_off + B.node_rows(wls[m].quad.n_nodes)]
         pix = be.pix[e.pix_off:e.pix_off + wls[m].geom.width * wls[m].geom.height]
         tile = be.tile[e.tile_off:e.tile_off + e.n_tiles]
         rowptr = be.rowptr[e.rowptr_off:e.rowptr_off + e.n_tiles + 1]

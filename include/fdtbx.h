@@ -157,17 +157,31 @@ int fdtbx_structure_factors(const fdtbx_cell* cell, int64_t n_atoms, const float
  *   [5] d omega/d gamma_theta   [6] d1   [7] d2
  * with c = (1 + d1^2 + d2^2)^(-1/2), d_j = -T + (i_j + 1/2) h, h = 2T/n and
  * omega = sigma_r sqrt(2 pi) g(Delta) c^3 h^2, Delta = arccos c (Eq. node_weight
- * without the per-reflection r0^2). */
+ * without the per-reflection r0^2).
+ * The n^2 node records are followed by nb^2 block records, nb = ceil(n/FDTBX_NODE_BLOCK),
+ * block b = b2*nb + b1 covering the nodes with i_j in [b_j B, b_j B + B) (B = FDTBX_NODE_BLOCK)
+ * that exist:
+ *   [0..2] centre c_j of the block's float32 values of (c - 1, c d1, c d2)
+ *   [3]    max_j |c_j| + r_j
+ *   [4..6] half-widths r_j, rounded up so every node value v_j satisfies |v_j - c_j| <= r_j
+ *   [7]    0
+ * The profile kernels test blocks before nodes; the records are derived data, not part
+ * of the quadrature. */
 #define FDTBX_REFL_FLOATS 48
 #define FDTBX_CULL_DOUBLES 16
 #define FDTBX_NODE_FLOATS 8
+#define FDTBX_NODE_BLOCK 4
 #define FDTBX_TILE 8 /* pixel tiles are FDTBX_TILE x FDTBX_TILE */
+
+/* Rows of FDTBX_NODE_FLOATS float32 in the node table of n_nodes per side:
+ * n_nodes^2 + ceil(n_nodes/FDTBX_NODE_BLOCK)^2; 0 if n_nodes is outside 1..256. */
+int64_t fdtbx_node_rows(int32_t n_nodes);
 
 /* Node table of the shell quadrature (Eqs. gnomonic, node_weight; angular shape
  * of section "Angular peak shapes": Gaussian if gamma_theta = 0, Lorentzian if
  * sigma_theta = 0, otherwise the unit-peak Voigt profile, evaluated on the device
  * through the Faddeeva function w(z) by Weideman's rational series).
- *   nodes device float32 [n_nodes^2][FDTBX_NODE_FLOATS] output */
+ *   nodes device float32 [fdtbx_node_rows(n_nodes)][FDTBX_NODE_FLOATS] output */
 int fdtbx_node_table(const fdtbx_disorder* dis, const fdtbx_quadrature* quad, float* nodes, void* stream);
 
 /* Per-reflection preparation (Eqs. Ah, Neff, Ipara, gnomonic):
@@ -297,7 +311,8 @@ int fdtbx_pattern_backward(const fdtbx_model* model, const int32_t* hkl, int64_t
  * Work tables (device int64, built by the caller): entries pack (model << 40) | first index.
  *   refl_blocks: blocks of 256 reflections, model-major (all blocks of a model adjacent);
  *   model_rb[n_models+1]: first refl_blocks entry of each model;
- *   atom_blocks: blocks of 256 atoms;  node_blocks: blocks of 256 nodes;
+ *   atom_blocks: blocks of 256 atoms;  node_blocks: blocks of 256 node-table rows
+ *               (fdtbx_node_rows(n_nodes) rows per model: node and block records);
  *   tile_items: (model, tile) pairs in the order the persistent kernels take them
  *               (longest culling list first balances the tail). */
 typedef struct fdtbx_batch_entry {
@@ -309,7 +324,7 @@ typedef struct fdtbx_batch_entry {
   int64_t tile_off;     /* first tile box */
   int64_t rowptr_off;   /* first of this model's n_tiles + 1 CSR row pointers */
   int64_t pair_off;     /* first culling-list entry; the row pointers are relative to it */
-  int64_t node_off;     /* first node record (n_nodes^2 of them) */
+  int64_t node_off;     /* first row of this model's node table (fdtbx_node_rows(n_nodes) rows) */
   int64_t ff_off;       /* first scattering-factor row */
   int32_t n_types, n_tiles;
 } fdtbx_batch_entry;

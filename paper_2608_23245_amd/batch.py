@@ -19,7 +19,7 @@ import torch
 
 from . import binding as B
 
-RB = 256  # reflections / atoms / nodes per block of the work tables
+RB = 256  # reflections / atoms / node-table rows per block of the work tables
 
 
 def _pack(model: int, first: int) -> int:
@@ -68,7 +68,8 @@ class BatchEngine:
             model_rb.append(len(refl_blocks))
             refl_blocks += [_pack(m, r) for r in range(0, n_hkl, RB)]
             atom_blocks += [_pack(m, r) for r in range(0, a.n, RB)]
-            node_blocks += [_pack(m, r) for r in range(0, wl.quad.n_nodes ** 2, RB)]
+            n_rows = B.node_rows(wl.quad.n_nodes)
+            node_blocks += [_pack(m, r) for r in range(0, n_rows, RB)]
             lens = (rowptr[1:] - rowptr[:-1]).cpu().numpy()
             items += [_pack(m, t) for t in range(n_tiles)]
             costs.append(lens)
@@ -87,7 +88,7 @@ class BatchEngine:
             off["tile"] += n_tiles
             off["rowptr"] += n_tiles + 1
             off["pair"] += int(idx.shape[0])
-            off["node"] += wl.quad.n_nodes ** 2
+            off["node"] += n_rows
             off["ff"] += int(a.ff.shape[0])
         model_rb.append(len(refl_blocks))
         self.totals = dict(off)

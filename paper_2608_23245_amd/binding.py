@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "_lib", "libfdtbx.so")
 REFL_FLOATS = 48
 CULL_DOUBLES = 16
 NODE_FLOATS = 8
+NODE_BLOCK = 4
 TILE = 8
 
 ERRORS = {0: "ok", -1: "invalid argument", -2: "geometry", -3: "buffer too small", -4: "hip", -5: "unsupported"}
@@ -79,6 +80,7 @@ _SIGS = {
     "fdtbx_structure_factors": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64] + [ctypes.c_void_p] * 7 +
                                 [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                  ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "fdtbx_node_rows": (ctypes.c_int64, [ctypes.c_int32]),
     "fdtbx_node_table": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdtbx_reflection_prep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
@@ -226,9 +228,17 @@ def structure_factors(cell: Cell, atoms: dict, hkl: torch.Tensor, want_F=True, w
     return F, F2
 
 
+def node_rows(n_nodes: int) -> int:
+    """Rows of the node table: n^2 node records followed by the node-block records."""
+    rows = int(lib().fdtbx_node_rows(int(n_nodes)))
+    if rows <= 0:
+        raise FdtbxError(-1, f"n_nodes {n_nodes} outside 1..256")
+    return rows
+
+
 def node_table(model: Model) -> torch.Tensor:
-    n = model.quad.n_nodes
-    out = torch.empty((n * n, NODE_FLOATS), dtype=torch.float32, device="cuda")
+    """Node table [node_rows(n)][NODE_FLOATS]; the first n^2 rows are the node records."""
+    out = torch.empty((node_rows(model.quad.n_nodes), NODE_FLOATS), dtype=torch.float32, device="cuda")
     _check(lib().fdtbx_node_table(ctypes.byref(model.dis), ctypes.byref(model.quad), _ptr(out), _stream()))
     return out
 

@@ -38,7 +38,8 @@ __global__ void __launch_bounds__(64) k_profile_adj(ProfParams q, const float* _
                                                     const float* __restrict__ grad_image, double* __restrict__ sums) {
   __shared__ float4 qn[128];
   __shared__ float2 qd[128];
-  adjoint_tile(q, refl, nodes, pix, tile, offsets, idx, grad_image, sums, blockIdx.x, qn, qd);
+  __shared__ int bq[64];
+  adjoint_tile(q, refl, nodes, pix, tile, offsets, idx, grad_image, sums, blockIdx.x, qn, qd, bq);
 }
 
 __global__ void k_zero_f64(double* __restrict__ v, int64_t n) {
@@ -258,10 +259,9 @@ __global__ void __launch_bounds__(64) k_b_profile_adj(const fdtbx_batch_entry* _
                                                       double* __restrict__ sums, unsigned long long* __restrict__ counter) {
   __shared__ float4 qn[128];
   __shared__ float2 qd[128];
+  __shared__ int bq[64];
   for (;;) {
-    unsigned long long mine = 0;
-    if (threadIdx.x == 0) mine = atomicAdd(counter, 1ull);
-    const int64_t it = (int64_t)__shfl(mine, 0, 64);
+    const int64_t it = next_item(counter);
     if (it >= n_items) break;
     const int64_t packed = items[it];
     const int m = (int)(packed >> 40);
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(64) k_b_profile_adj(const fdtbx_batch_entry* _
     prof_params(&e.model, &q);
     adjoint_tile(q, refl + (int64_t)FDTBX_REFL_FLOATS * e.hkl_off, nodes + (int64_t)FDTBX_NODE_FLOATS * e.node_off,
                  pix + 2 * e.pix_off, tile + 8 * e.tile_off, rowptr + e.rowptr_off, idx + e.pair_off,
-                 grad_image + e.pix_off, sums + 6 * e.hkl_off, t, qn, qd);
+                 grad_image + e.pix_off, sums + 6 * e.hkl_off, t, qn, qd, bq);
   }
 }
 

@@ -37,8 +37,12 @@ __device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, 
 }
 
 // Every lane walks the first cnt queue entries, reading entry jj + 1 before evaluating jj.
+// The queue addresses go through threadIdx.y (always 0) so that they stay in vector
+// registers and the unrolled reads use instruction offsets.
 __device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* qd, int cnt, const float* al, float gp,
                                                float half_m, float tiny, float* acc) {
+  qn += threadIdx.y;
+  qd += threadIdx.y;
   float4 nxt = qn[0];
   float2 nxt2 = qd[0];
   for (int jj = 0; jj < cnt; ++jj) {
@@ -50,12 +54,13 @@ __device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* q
   }
 }
 
-// One 8x8 tile t of one model, walked by one 64-lane wave.  qn, qd: LDS queue of 128 entries.
+// One 8x8 tile t of one model, walked by one 64-lane wave.  qn, qd: LDS queue of 128 entries;
+// bq: LDS scratch of 64 ints for the block test.
 __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* __restrict__ refl, const float* __restrict__ nodes,
                                              const double* __restrict__ pix, const double* __restrict__ tile,
                                              const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
                                              const float* __restrict__ grad_image, double* __restrict__ sums, const int t,
-                                             float4* qn, float2* qd) {
+                                             float4* qn, float2* qd, int* bq) {
   const int lane = threadIdx.x & 63;
   const int tx = t % q.tiles_x, ty = t / q.tiles_x;
   const int i = tx * FDTBX_TILE + (lane % FDTBX_TILE);
@@ -89,38 +94,21 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
       lo[a] = fminf(r1, r2) + fminf(z1, z2) - q.half_m - q.margin;
       hi[a] = fmaxf(r1, r2) + fmaxf(z1, z2) + q.half_m + q.margin;
     }
-    const float B0 = rec[RS_B + 0], B1 = rec[RS_B + 1], B2 = rec[RS_B + 2];
-    const float G10 = rec[RS_G1 + 0], G11 = rec[RS_G1 + 1], G12 = rec[RS_G1 + 2];
-    const float G20 = rec[RS_G2 + 0], G21 = rec[RS_G2 + 1], G22 = rec[RS_G2 + 2];
-    const int nw1 = w.i1hi - w.i1lo + 1;
-    const int nwin = nw1 * (w.i2hi - w.i2lo + 1);
-    const float inv_nw1 = 1.0f / (float)nw1;
+    float Bv[3], G1[3], G2[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Bv[a] = rec[RS_B + a];
+      G1[a] = rec[RS_G1 + a];
+      G2[a] = rec[RS_G2 + a];
+    }
     float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int qlen = 0;
-    for (int w0 = 0; w0 < nwin; w0 += 64) {
-      const int wi = w0 + lane;
-      float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
-      float2 ed = make_float2(0.f, 0.f);
-      bool keep = false;
-      if (wi < nwin) {
-        int d1, d2;
-        window_node(wi, nw1, inv_nw1, &d1, &d2);
-        const int i1 = w.i1lo + d1, i2 = w.i2lo + d2;
-        const float* np_ = nodes + (int64_t)FDTBX_NODE_FLOATS * (i2 * q.n + i1);
-        const float4 nd = *(const float4*)np_;
-        const float2 nd2 = *(const float2*)(np_ + 4);
-        e.x = fmaf(nd.x, B0, fmaf(nd.y, G10, nd.z * G20));
-        e.y = fmaf(nd.x, B1, fmaf(nd.y, G11, nd.z * G21));
-        e.z = fmaf(nd.x, B2, fmaf(nd.y, G12, nd.z * G22));
-        e.w = nd.w;
-        ed = nd2;
-        keep = e.x >= lo[0] && e.x <= hi[0] && e.y >= lo[1] && e.y <= hi[1] && e.z >= lo[2] && e.z <= hi[2];
-      }
+    scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int k, float4 e) {
       const unsigned long long b = __ballot(keep);
       if (keep) {
         const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
         qn[pos] = e;
-        qd[pos] = ed;
+        qd[pos] = *(const float2*)(nodes + (int64_t)FDTBX_NODE_FLOATS * k + 4);
       }
       qlen += __popcll(b);
       __syncthreads();
@@ -134,7 +122,7 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
         }
         __syncthreads();
       }
-    }
+    });
     walk_queue_adj(qn, qd, qlen, al, gp, q.half_m, q.tiny, acc);
     __syncthreads();
     bool any = false;

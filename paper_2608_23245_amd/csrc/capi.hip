@@ -88,7 +88,7 @@ static PatternLayout layout(const fdtbx_model* m, int64_t n_hkl, int64_t pair_ca
   L.cull = o;
   o += align_up((size_t)n_hkl * FDTBX_CULL_DOUBLES * sizeof(double), 256);
   L.nodes = o;
-  o += align_up((size_t)m->quad.n_nodes * m->quad.n_nodes * FDTBX_NODE_FLOATS * sizeof(float), 256);
+  o += align_up((size_t)node_rows(m->quad.n_nodes) * FDTBX_NODE_FLOATS * sizeof(float), 256);
   L.pix = o;
   o += align_up((size_t)m->geom.width * m->geom.height * 2 * sizeof(double), 256);
   L.tile = o;

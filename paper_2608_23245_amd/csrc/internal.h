@@ -29,6 +29,21 @@ int check_model(const fdtbx_model* m);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+// Node-table rows for n nodes per side: node records, then block records.
+__host__ __device__ inline int64_t node_rows(int64_t n) {
+  const int64_t nb = (n + FDTBX_NODE_BLOCK - 1) / FDTBX_NODE_BLOCK;
+  return n * n + nb * nb;
+}
+
+// Next item of a persistent launch: lane 0 takes it from the counter and the wave reads
+// lane 0's value into scalar registers (so everything indexed by it is loaded as uniform).
+__device__ inline int64_t next_item(unsigned long long* counter) {
+  unsigned long long mine = 0;
+  if ((threadIdx.x & 63) == 0) mine = atomicAdd(counter, 1ull);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)mine);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(mine >> 32));
+  return (int64_t)(((unsigned long long)hi << 32) | lo);
+}
 
 // Reflection record slots (float32, FDTBX_REFL_FLOATS per reflection).
 enum ReflSlot {

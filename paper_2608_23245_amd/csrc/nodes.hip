@@ -101,21 +101,67 @@ __device__ static void shape(double D, double s, double g, const double* coef, d
   *dg = (du_g * v - u * dv_g) / (v * v);
 }
 
+// Position of node (i1, i2) on the unit sphere about the origin of the tangent frame:
+// (c - 1, c d1, c d2), with c - 1 written without cancellation.
+__device__ static void node_xyz(const NodeParams& p, int i1, int i2, double* d1o, double* d2o, double* co, float* v) {
+  const double d1 = -p.T + ((double)i1 + 0.5) * p.h;
+  const double d2 = -p.T + ((double)i2 + 0.5) * p.h;
+  const double rho2 = d1 * d1 + d2 * d2;
+  const double sq = sqrt(1.0 + rho2);
+  const double c = 1.0 / sq;
+  v[0] = (float)(-rho2 / (sq * (1.0 + sq)));
+  v[1] = (float)(c * d1);
+  v[2] = (float)(c * d2);
+  *d1o = d1;
+  *d2o = d2;
+  *co = c;
+}
+
+// Block record b (layout in fdtbx.h): centre and rounded-up half-width of the float32
+// node coordinates of the block.
+__device__ static void block_record(const NodeParams& p, int b, float* o) {
+  const int nb = (p.n + FDTBX_NODE_BLOCK - 1) / FDTBX_NODE_BLOCK;
+  const int b1 = b % nb, b2 = b / nb;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int s2 = 0; s2 < FDTBX_NODE_BLOCK; ++s2)
+    for (int s1 = 0; s1 < FDTBX_NODE_BLOCK; ++s1) {
+      const int i1 = b1 * FDTBX_NODE_BLOCK + s1, i2 = b2 * FDTBX_NODE_BLOCK + s2;
+      if (i1 >= p.n || i2 >= p.n) continue;
+      double d1, d2, c;
+      float v[3];
+      node_xyz(p, i1, i2, &d1, &d2, &c, v);
+      for (int j = 0; j < 3; ++j) {
+        lo[j] = fmin(lo[j], (double)v[j]);
+        hi[j] = fmax(hi[j], (double)v[j]);
+      }
+    }
+  double mag = 0.0;
+  for (int j = 0; j < 3; ++j) {
+    const float cf = (float)(0.5 * (lo[j] + hi[j]));
+    const double r = fmax(hi[j] - (double)cf, (double)cf - lo[j]);  // exact: differences of nearby floats
+    float rf = (float)r;
+    if ((double)rf < r) rf = nextafterf(rf, INFINITY);
+    o[j] = cf;
+    o[4 + j] = rf;
+    mag = fmax(mag, fabs((double)cf) + (double)rf);
+  }
+  o[3] = (float)mag * 1.0000002f;
+  o[7] = 0.0f;
+}
+
 __device__ static void node_record(const NodeParams& p, int k, const double* coef, double L, float* o) {
   int i1 = k % p.n, i2 = k / p.n;
-  double d1 = -p.T + ((double)i1 + 0.5) * p.h;
-  double d2 = -p.T + ((double)i2 + 0.5) * p.h;
+  double d1, d2, c;
+  float v[3];
+  node_xyz(p, i1, i2, &d1, &d2, &c, v);
   double rho2 = d1 * d1 + d2 * d2;
-  double sq = sqrt(1.0 + rho2);
-  double c = 1.0 / sq;
-  double cm1 = -rho2 / (sq * (1.0 + sq));
   double Delta = atan(sqrt(rho2));
   double g, gs, gg;
   shape(Delta, p.sig, p.gam, coef, L, &g, &gs, &gg);
   double base = p.sigma_r * sqrt(2.0 * M_PI) * c * c * c * p.h * p.h;
-  o[0] = (float)cm1;
-  o[1] = (float)(c * d1);
-  o[2] = (float)(c * d2);
+  o[0] = v[0];
+  o[1] = v[1];
+  o[2] = v[2];
   o[3] = (float)(base * g);
   o[4] = (float)(base * gs);
   o[5] = (float)(base * gg);
@@ -129,8 +175,10 @@ __global__ void __launch_bounds__(256) k_nodes(NodeParams p, float* __restrict__
   if (threadIdx.x < kWN && p.sig != 0.0) coef[threadIdx.x] = weideman_coef(threadIdx.x + 1, L);
   __syncthreads();
   int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= p.n * p.n) return;
-  node_record(p, k, coef, L, out + (int64_t)FDTBX_NODE_FLOATS * k);
+  if (k < p.n * p.n)
+    node_record(p, k, coef, L, out + (int64_t)FDTBX_NODE_FLOATS * k);
+  else if (k < node_rows(p.n))
+    block_record(p, k - p.n * p.n, out + (int64_t)FDTBX_NODE_FLOATS * k);
 }
 
 // Batched models: block b of node_blocks covers nodes [first, first + 256) of one model.
@@ -151,8 +199,11 @@ __global__ void __launch_bounds__(256) k_b_nodes(const fdtbx_batch_entry* __rest
   const double L = sqrt(kWN / sqrt(2.0));
   if (threadIdx.x < kWN && p.sig != 0.0) coef[threadIdx.x] = weideman_coef(threadIdx.x + 1, L);
   __syncthreads();
-  if (k >= p.n * p.n) return;
-  node_record(p, k, coef, L, out + (int64_t)FDTBX_NODE_FLOATS * (e.node_off + k));
+  float* o = out + (int64_t)FDTBX_NODE_FLOATS * (e.node_off + k);
+  if (k < p.n * p.n)
+    node_record(p, k, coef, L, o);
+  else if (k < node_rows(p.n))
+    block_record(p, k - p.n * p.n, o);
 }
 
 int launch_batch_nodes(const fdtbx_batch_entry* ent, const int64_t* blocks, int64_t n_nb, float* nodes, hipStream_t s) {
@@ -165,6 +216,11 @@ int launch_batch_nodes(const fdtbx_batch_entry* ent, const int64_t* blocks, int6
 }  // namespace fdtbx
 
 using namespace fdtbx;
+
+extern "C" int64_t fdtbx_node_rows(int32_t n_nodes) {
+  if (n_nodes < 1 || n_nodes > 256) return 0;
+  return node_rows(n_nodes);
+}
 
 extern "C" int fdtbx_node_table(const fdtbx_disorder* dis, const fdtbx_quadrature* quad, float* nodes, void* stream) {
   if (!dis || !quad || !nodes) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
@@ -182,8 +238,8 @@ extern "C" int fdtbx_node_table(const fdtbx_disorder* dis, const fdtbx_quadratur
   p.sigma_r = quad->sigma_r;
   p.sig = dis->sigma_theta;
   p.gam = dis->gamma_theta;
-  int nn = p.n * p.n;
-  hipLaunchKernelGGL(k_nodes, dim3((unsigned)ceil_div(nn, 256)), dim3(256), 0, (hipStream_t)stream, p, nodes);
+  const int64_t rows = node_rows(p.n);
+  hipLaunchKernelGGL(k_nodes, dim3((unsigned)ceil_div(rows, 256)), dim3(256), 0, (hipStream_t)stream, p, nodes);
   FDTBX_LAUNCH_CHECK("node table");
   return FDTBX_OK;
 }

@@ -33,7 +33,8 @@ __global__ void __launch_bounds__(64) k_profile(ProfParams q, const float* __res
                                                 float* __restrict__ image, unsigned long long* __restrict__ counts) {
   // queue of window nodes that can be inside the support of some pixel of the tile
   __shared__ float4 qn[128];
-  profile_tile<COUNT>(q, refl, nodes, pix, tile, offsets, idx, image, counts, blockIdx.x, qn);
+  __shared__ int bq[64];
+  profile_tile<COUNT>(q, refl, nodes, pix, tile, offsets, idx, image, counts, blockIdx.x, qn, bq);
 }
 
 // Batched models, persistent: every wave takes (model, tile) items from a shared counter
@@ -45,10 +46,9 @@ __global__ void __launch_bounds__(64) k_b_profile(const fdtbx_batch_entry* __res
                                                   const int32_t* __restrict__ idx, float* __restrict__ image,
                                                   unsigned long long* __restrict__ counter) {
   __shared__ float4 qn[128];
+  __shared__ int bq[64];
   for (;;) {
-    unsigned long long mine = 0;
-    if (threadIdx.x == 0) mine = atomicAdd(counter, 1ull);
-    const int64_t it = (int64_t)__shfl(mine, 0, 64);
+    const int64_t it = next_item(counter);
     if (it >= n_items) break;
     const int64_t packed = items[it];
     const int m = (int)(packed >> 40);
@@ -58,7 +58,7 @@ __global__ void __launch_bounds__(64) k_b_profile(const fdtbx_batch_entry* __res
     prof_params(&e.model, &q);
     profile_tile<false>(q, refl + (int64_t)FDTBX_REFL_FLOATS * e.hkl_off, nodes + (int64_t)FDTBX_NODE_FLOATS * e.node_off,
                         pix + 2 * e.pix_off, tile + 8 * e.tile_off, rowptr + e.rowptr_off, idx + e.pair_off,
-                        image + e.pix_off, nullptr, t, qn);
+                        image + e.pix_off, nullptr, t, qn, bq);
   }
 }
 

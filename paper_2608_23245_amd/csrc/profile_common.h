@@ -84,6 +84,113 @@ __device__ static inline void window_node(int wi, int nw1, float inv_nw1, int* i
   *i2 = q2;
 }
 
+// Windows of at most this many nodes are scanned node by node; larger ones first test
+// the FDTBX_NODE_BLOCK^2 node blocks that overlap them.
+constexpr int kPlainScanMax = 192;
+
+// Candidate nodes of one (tile, reflection) pair: the nodes k of window w whose offsets
+// e_a = B_a (c - 1) + G1_a c d1 + G2_a c d2 lie in [lo_a, hi_a] for a = 0, 1, 2.  Calls
+// sink(keep, k, e) on every lane of the wave with uniform control flow, 64 candidates a
+// call, where keep marks a candidate, k is its node index and e = (e_0, e_1, e_2, omega).
+// The candidates are the same on both paths; the order in which they are offered differs.
+// bq: LDS scratch of 64 ints.
+template <class Sink>
+__device__ __forceinline__ void scan_window(const ProfParams& q, const float* __restrict__ nodes, const Window& w,
+                                            const float* Bv, const float* G1, const float* G2, const float* lo,
+                                            const float* hi, int* bq, Sink&& sink) {
+  const int lane = threadIdx.x & 63;
+  auto node_e = [&](int k, float4* e) {
+    const float4 nd = *(const float4*)(nodes + (int64_t)FDTBX_NODE_FLOATS * k);
+    e->x = fmaf(nd.x, Bv[0], fmaf(nd.y, G1[0], nd.z * G2[0]));
+    e->y = fmaf(nd.x, Bv[1], fmaf(nd.y, G1[1], nd.z * G2[1]));
+    e->z = fmaf(nd.x, Bv[2], fmaf(nd.y, G1[2], nd.z * G2[2]));
+    e->w = nd.w;
+    return e->x >= lo[0] && e->x <= hi[0] && e->y >= lo[1] && e->y <= hi[1] && e->z >= lo[2] && e->z <= hi[2];
+  };
+  const int nw1 = w.i1hi - w.i1lo + 1;
+  const int nwin = nw1 * (w.i2hi - w.i2lo + 1);
+  if (nwin <= kPlainScanMax) {
+    const float inv_nw1 = 1.0f / (float)nw1;
+    for (int w0 = 0; w0 < nwin; w0 += 64) {
+      const int wi = w0 + lane;
+      float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+      bool keep = false;
+      int k = 0;
+      if (wi < nwin) {
+        int d1, d2;
+        window_node(wi, nw1, inv_nw1, &d1, &d2);
+        k = (w.i2lo + d2) * q.n + (w.i1lo + d1);
+        keep = node_e(k, &e);
+      }
+      sink(keep, k, e);
+    }
+    return;
+  }
+  // Block test: a block record holds the centre c_j and half-width r_j of the block's
+  // node coordinates (every node value lies in c_j +- r_j exactly) and mag = max_j |c_j| + r_j.
+  // The block is kept if [E(c) - E(r) - slack, E(c) + E(r) + slack] meets [lo, hi], with E
+  // the map above (absolute coefficients for r); the slack covers the float32 rounding of
+  // these sums and of the node test (a few units in the last place of sum |coef| mag).
+  const float* blocks = nodes + (int64_t)FDTBX_NODE_FLOATS * q.n * q.n;
+  const int nbs = (q.n + FDTBX_NODE_BLOCK - 1) / FDTBX_NODE_BLOCK;
+  const int b1lo = w.i1lo / FDTBX_NODE_BLOCK, b1hi = w.i1hi / FDTBX_NODE_BLOCK;
+  const int b2lo = w.i2lo / FDTBX_NODE_BLOCK, b2hi = w.i2hi / FDTBX_NODE_BLOCK;
+  const int nb1 = b1hi - b1lo + 1;
+  const int nbw = nb1 * (b2hi - b2lo + 1);
+  const float inv_nb1 = 1.0f / (float)nb1;
+  float aB[3], aG1[3], aG2[3], sl[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    aB[a] = fabsf(Bv[a]);
+    aG1[a] = fabsf(G1[a]);
+    aG2[a] = fabsf(G2[a]);
+    sl[a] = 4.0e-6f * (aB[a] + aG1[a] + aG2[a]);
+  }
+  constexpr int kBB = FDTBX_NODE_BLOCK * FDTBX_NODE_BLOCK;
+  constexpr int kPer = 64 / kBB;  // blocks expanded per pass
+  for (int c0 = 0; c0 < nbw; c0 += 64) {
+    const int bi = c0 + lane;
+    bool keep = false;
+    int bid = 0;
+    if (bi < nbw) {
+      int d1, d2;
+      window_node(bi, nb1, inv_nb1, &d1, &d2);
+      bid = (b2lo + d2) * nbs + (b1lo + d1);
+      const float4 cm = *(const float4*)(blocks + (int64_t)FDTBX_NODE_FLOATS * bid);
+      const float4 rr = *(const float4*)(blocks + (int64_t)FDTBX_NODE_FLOATS * bid + 4);
+      keep = true;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const float ec = fmaf(cm.x, Bv[a], fmaf(cm.y, G1[a], cm.z * G2[a]));
+        const float er = fmaf(sl[a], cm.w, fmaf(rr.x, aB[a], fmaf(rr.y, aG1[a], rr.z * aG2[a])));
+        keep = keep && ec - er <= hi[a] && ec + er >= lo[a];
+      }
+    }
+    const unsigned long long b = __ballot(keep);
+    const int nk = __popcll(b);
+    if (keep) bq[(int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u))] = bid;
+    __syncthreads();
+    for (int k0 = 0; k0 < nk; k0 += kPer) {
+      const int kk = k0 + lane / kBB;
+      float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
+      bool keepn = false;
+      int k = 0;
+      if (kk < nk) {
+        const int bb = bq[kk];
+        const int sub = lane % kBB;
+        const int i1 = (bb % nbs) * FDTBX_NODE_BLOCK + sub % FDTBX_NODE_BLOCK;
+        const int i2 = (bb / nbs) * FDTBX_NODE_BLOCK + sub / FDTBX_NODE_BLOCK;
+        if (i1 >= w.i1lo && i1 <= w.i1hi && i2 >= w.i2lo && i2 <= w.i2hi) {
+          k = i2 * q.n + i1;
+          keepn = node_e(k, &e);
+        }
+      }
+      sink(keepn, k, e);
+    }
+    __syncthreads();
+  }
+}
+
 __host__ __device__ inline void prof_params(const fdtbx_model* model, ProfParams* q) {
   q->W = model->geom.width;
   q->H = model->geom.height;

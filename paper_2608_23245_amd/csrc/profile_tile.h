@@ -27,12 +27,17 @@ __device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1,
   }
 }
 
-// One 8x8 tile t of one model, walked by one 64-lane wave.  qn: LDS queue of 128 entries.
+// One 8x8 tile t of one model, walked by one 64-lane wave.  qn: LDS queue of 128 entries;
+// bq: LDS scratch of 64 ints for the block test.
 // Every lane walks the first cnt queue entries; the read of entry jj + 1 is issued before
 // entry jj is evaluated (the buffer holds 128 entries, cnt <= 64, so it stays in bounds).
+// The queue is addressed from threadIdx.y (always 0: the launches are one-dimensional), which
+// keeps its address in a vector register; the unrolled reads then use instruction offsets
+// instead of moving a scalar loop counter into a vector register for every entry.
 template <bool COUNT>
 __device__ __forceinline__ void walk_queue(const float4* qn, int cnt, const float* al, float half_m, float tiny, float& accr,
                                            unsigned long long& cnt_eval) {
+  qn += threadIdx.y;
   float4 nxt = qn[0];
   for (int jj = 0; jj < cnt; ++jj) {
     const float4 cur = nxt;
@@ -46,7 +51,7 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
                                              const float* __restrict__ nodes, const double* __restrict__ pix,
                                              const double* __restrict__ tile, const int64_t* __restrict__ offsets,
                                              const int32_t* __restrict__ idx, float* __restrict__ image,
-                                             unsigned long long* __restrict__ counts, const int t, float4* qn) {
+                                             unsigned long long* __restrict__ counts, const int t, float4* qn, int* bq) {
   const int lane = threadIdx.x & 63;
   const int tx = t % q.tiles_x, ty = t / q.tiles_x;
   const int i = tx * FDTBX_TILE + (lane % FDTBX_TILE);
@@ -69,42 +74,29 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
     const double RD = *(const double*)(rec + RS_RD);
     const double ZD = *(const double*)(rec + RS_ZD);
     const float dR = (float)(R - RD), dZ = (float)(Z - ZD);
-    float tr[3], tz[3], al[3], lo[3], hi[3];
+    float al[3], lo[3], hi[3];
     // tile range of alpha_i (linear in R, Z: extremes at the box corners), widened by m/2
     const float dRl = (float)(bRlo - RD), dRh = (float)(bRhi - RD);
     const float dZl = (float)(bZlo - ZD), dZh = (float)(bZhi - ZD);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      tr[a] = rec[RS_TR + a];
-      tz[a] = rec[RS_TZ + a];
-      al[a] = fmaf(tr[a], dR, tz[a] * dZ);
-      const float r1 = tr[a] * dRl, r2 = tr[a] * dRh, z1 = tz[a] * dZl, z2 = tz[a] * dZh;
+      const float tr = rec[RS_TR + a], tz = rec[RS_TZ + a];
+      al[a] = fmaf(tr, dR, tz * dZ);
+      const float r1 = tr * dRl, r2 = tr * dRh, z1 = tz * dZl, z2 = tz * dZh;
       lo[a] = fminf(r1, r2) + fminf(z1, z2) - q.half_m - q.margin;
       hi[a] = fmaxf(r1, r2) + fmaxf(z1, z2) + q.half_m + q.margin;
     }
-    const float B0 = rec[RS_B + 0], B1 = rec[RS_B + 1], B2 = rec[RS_B + 2];
-    const float G10 = rec[RS_G1 + 0], G11 = rec[RS_G1 + 1], G12 = rec[RS_G1 + 2];
-    const float G20 = rec[RS_G2 + 0], G21 = rec[RS_G2 + 1], G22 = rec[RS_G2 + 2];
-    const int nw1 = w.i1hi - w.i1lo + 1;
-    const int nwin = nw1 * (w.i2hi - w.i2lo + 1);
-    const float inv_nw1 = 1.0f / (float)nw1;
+    float Bv[3], G1[3], G2[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Bv[a] = rec[RS_B + a];
+      G1[a] = rec[RS_G1 + a];
+      G2[a] = rec[RS_G2 + a];
+    }
     float accr = 0.0f;
     int qlen = 0;  // uniform
-    for (int w0 = 0; w0 < nwin; w0 += 64) {
-      const int wi = w0 + lane;
-      float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
-      bool keep = false;
-      if (wi < nwin) {
-        int d1, d2;
-        window_node(wi, nw1, inv_nw1, &d1, &d2);
-        const int i1 = w.i1lo + d1, i2 = w.i2lo + d2;
-        const float4 nd = *(const float4*)(nodes + (int64_t)FDTBX_NODE_FLOATS * (i2 * q.n + i1));
-        e.x = fmaf(nd.x, B0, fmaf(nd.y, G10, nd.z * G20));
-        e.y = fmaf(nd.x, B1, fmaf(nd.y, G11, nd.z * G21));
-        e.z = fmaf(nd.x, B2, fmaf(nd.y, G12, nd.z * G22));
-        e.w = nd.w;
-        keep = e.x >= lo[0] && e.x <= hi[0] && e.y >= lo[1] && e.y <= hi[1] && e.z >= lo[2] && e.z <= hi[2];
-      }
+    // candidates go to the LDS queue; every 64 queued nodes are walked by all lanes
+    scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int, float4 e) {
       const unsigned long long b = __ballot(keep);
       if (keep) {
         const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
@@ -119,7 +111,7 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
         if (lane < qlen) qn[lane] = qn[64 + lane];
         __syncthreads();
       }
-    }
+    });
     walk_queue<COUNT>(qn, qlen, al, q.half_m, tiny, accr, cnt);
     __syncthreads();
     if (!COUNT) acc = fmaf(rec[RS_WK], accr, acc);

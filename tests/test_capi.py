@@ -85,3 +85,12 @@ def test_model_checks(lib):
     rc = lib.fdtbx_profile_pattern(ctypes.byref(m), ctypes.c_void_p(8), 150, ctypes.c_void_p(8), ctypes.c_void_p(8), 1000,
                                    None, ctypes.c_void_p(8), 16, None)
     assert rc == -3
+
+
+def test_node_rows(lib):
+    """Node table size: n^2 node records plus ceil(n/4)^2 block records; 0 outside 1..256."""
+    from paper_2608_23245_amd import binding as B
+    assert B.NODE_BLOCK == 4
+    for n, rows in ((1, 2), (4, 17), (10, 109), (64, 4096 + 256), (96, 9216 + 576), (256, 65536 + 4096)):
+        assert lib.fdtbx_node_rows(n) == rows == B.node_rows(n)
+    assert lib.fdtbx_node_rows(0) == 0 and lib.fdtbx_node_rows(257) == 0

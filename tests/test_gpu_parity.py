@@ -147,7 +147,9 @@ def test_node_table(case):
     say(f"node table {case}")
     wl = {"g0": W.config0(), "l1": W.config2(), "v1": W.config1(),
           "wide": W.small(5, sigma_theta=0.5 * DEG, gamma_theta=6 * DEG, n_nodes=100)}[case]
-    nodes = B.node_table(B.make_model(wl)).cpu().numpy().astype(np.float64)
+    n = wl.quad.n_nodes
+    table = B.node_table(B.make_model(wl)).cpu().numpy().astype(np.float64)
+    nodes = table[:n * n]
     nd = O.node_table(wl.quad.n_nodes, wl.quad.T, wl.quad.sigma_r, wl.dis.sigma_theta, wl.dis.gamma_theta)
     np.testing.assert_allclose(nodes[:, 0], nd.c - 1.0, rtol=2e-7, atol=1e-9)
     np.testing.assert_allclose(nodes[:, 1], nd.c * nd.d1, rtol=2e-7, atol=1e-9)
@@ -155,6 +157,26 @@ def test_node_table(case):
     np.testing.assert_allclose(nodes[:, 3], nd.omega, rtol=1e-6, atol=1e-7 * nd.omega.max())
     np.testing.assert_allclose(nodes[:, 6], nd.d1, rtol=2e-7, atol=1e-9)
     np.testing.assert_allclose(nodes[:, 7], nd.d2, rtol=2e-7, atol=1e-9)
+    check_block_records(table, n)
+
+
+def check_block_records(table, n):
+    """Block records after the n^2 node records: every node value of a block lies in
+    centre +- half-width exactly (float32 values compared in float64), the half-width is
+    the tight one up to one float32 ulp, and mag bounds |centre| + half-width."""
+    nb = (n + B.NODE_BLOCK - 1) // B.NODE_BLOCK
+    assert table.shape[0] == n * n + nb * nb == B.node_rows(n)
+    xyz = table[:n * n, :3].reshape(n, n, 3)          # [i2][i1]
+    blk = table[n * n:].reshape(nb, nb, 8)
+    for b2 in range(nb):
+        for b1 in range(nb):
+            v = xyz[b2 * B.NODE_BLOCK:(b2 + 1) * B.NODE_BLOCK, b1 * B.NODE_BLOCK:(b1 + 1) * B.NODE_BLOCK].reshape(-1, 3)
+            c, r = blk[b2, b1, 0:3], blk[b2, b1, 4:7]
+            assert np.all(np.abs(v - c) <= r), (b1, b2)
+            tight = np.max(np.abs(v - c), axis=0)
+            assert np.all(r <= tight + np.spacing(np.float32(np.maximum(r, 1e-30))).astype(np.float64)), (b1, b2)
+            assert blk[b2, b1, 3] >= np.max(np.abs(c) + r)
+            assert blk[b2, b1, 7] == 0.0
 
 
 @pytest.mark.parametrize("name", list(SMALL) + ["config0", "config1"])
