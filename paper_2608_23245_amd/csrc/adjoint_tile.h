@@ -75,32 +75,32 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
   const int64_t p0 = offsets[t], p1 = offsets[t + 1];
   // a tile whose pixels all carry zero weight adds nothing
   if (__ballot(gp != 0.0f) == 0ull) return;
+  // the next pair's reflection index is read one iteration ahead
+  int32_t r_next = p0 < p1 ? idx[p0] : 0;
   for (int64_t pp = p0; pp < p1; ++pp) {
-    const int32_t r = idx[pp];
-    const float* rec = refl + (int64_t)FDTBX_REFL_FLOATS * r;
-    Window w;
-    if (!node_window(q, rec, Rlo, Rhi, Zlo, Zhi, &w)) continue;
-    const double RD = *(const double*)(rec + RS_RD);
-    const double ZD = *(const double*)(rec + RS_ZD);
+    const int32_t r = r_next;
+    r_next = idx[pp + 1 < p1 ? pp + 1 : pp];
+    PairRec f;
+    load_pair(refl + (int64_t)FDTBX_REFL_FLOATS * r, f);
+    const double RD = f.at_f64(RS_RD);
+    const double ZD = f.at_f64(RS_ZD);
     const float dR = (float)(R - RD), dZ = (float)(Z - ZD);
-    float al[3], lo[3], hi[3];
+    float al[3], lo[3], hi[3], Bv[3], G1[3], G2[3];
     const float dRl = (float)(bRlo - RD), dRh = (float)(bRhi - RD);
     const float dZl = (float)(bZlo - ZD), dZh = (float)(bZhi - ZD);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const float tr = rec[RS_TR + a], tz = rec[RS_TZ + a];
+      const float tr = f.at(RS_TR + a), tz = f.at(RS_TZ + a);
       al[a] = fmaf(tr, dR, tz * dZ);
       const float r1 = tr * dRl, r2 = tr * dRh, z1 = tz * dZl, z2 = tz * dZh;
       lo[a] = fminf(r1, r2) + fminf(z1, z2) - q.half_m - q.margin;
       hi[a] = fmaxf(r1, r2) + fmaxf(z1, z2) + q.half_m + q.margin;
+      Bv[a] = f.at(RS_B + a);
+      G1[a] = f.at(RS_G1 + a);
+      G2[a] = f.at(RS_G2 + a);
     }
-    float Bv[3], G1[3], G2[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      Bv[a] = rec[RS_B + a];
-      G1[a] = rec[RS_G1 + a];
-      G2[a] = rec[RS_G2 + a];
-    }
+    Window w;
+    if (!node_window(q, f, Rlo, Rhi, Zlo, Zhi, &w)) continue;
     float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int qlen = 0;
     scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int k, float4 e) {

@@ -25,23 +25,53 @@ struct Window {
   int i1lo, i1hi, i2lo, i2hi;
 };
 
+// Record slots 4..35 of one reflection (everything a (tile, reflection) pair reads), loaded
+// with one batch of 16-byte loads so that a pair waits for memory once.
+struct PairRec {
+  float v[32];
+  __device__ float at(int slot) const { return v[slot - 4]; }
+  __device__ double at_f64(int slot) const {
+    return __hiloint2double(__float_as_int(v[slot - 3]), __float_as_int(v[slot - 4]));
+  }
+};
+
+__device__ __forceinline__ void load_pair(const float* __restrict__ rec, PairRec& f) {
+  const float4* r4 = (const float4*)(rec + 4);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const float4 x = r4[k];
+    f.v[4 * k + 0] = x.x;
+    f.v[4 * k + 1] = x.y;
+    f.v[4 * k + 2] = x.z;
+    f.v[4 * k + 3] = x.w;
+  }
+  // An empty statement that reads the fields: it keeps the compiler from sinking some of
+  // the loads below the window test, so that the pair waits for memory once, not three times.
+  asm volatile("" ::"s"(f.v[0]), "s"(f.v[1]), "s"(f.v[2]), "s"(f.v[3]), "s"(f.v[4]), "s"(f.v[5]), "s"(f.v[6]),
+               "s"(f.v[7]), "s"(f.v[8]), "s"(f.v[9]), "s"(f.v[10]), "s"(f.v[11]), "s"(f.v[12]), "s"(f.v[13]),
+               "s"(f.v[14]), "s"(f.v[15]));
+  asm volatile("" ::"s"(f.v[16]), "s"(f.v[17]), "s"(f.v[18]), "s"(f.v[19]), "s"(f.v[20]), "s"(f.v[21]),
+               "s"(f.v[22]), "s"(f.v[23]), "s"(f.v[24]), "s"(f.v[25]), "s"(f.v[26]), "s"(f.v[27]), "s"(f.v[28]),
+               "s"(f.v[29]), "s"(f.v[30]));
+}
+
 // Node index range that the query points of a tile box can reach.  A node in the
 // support of p satisfies |s.v - p.v| <= rho_v for v in {S, e1, e2}; s.S = r0 c is in
 // [r0 cmin, r0]; d_j = (s.e_j)/(s.S).  One extra node of margin on each side absorbs the
 // float32 rounding of these bounds (hardware reciprocals included).
-__device__ static inline bool node_window(const ProfParams& q, const float* rec, float Rlo, float Rhi, float Zlo, float Zhi,
+__device__ static inline bool node_window(const ProfParams& q, const PairRec& rec, float Rlo, float Rhi, float Zlo, float Zhi,
                                           Window* w) {
   auto range = [&](float cR, float cZ, float* lo, float* hi) {
     float a = Rlo * cR, b = Rhi * cR, c = Zlo * cZ, d = Zhi * cZ;
     *lo = fminf(a, b) + fminf(c, d);
     *hi = fmaxf(a, b) + fmaxf(c, d);
   };
-  const float r0 = rec[RS_R0];
+  const float r0 = rec.at(RS_R0);
   float sl, sh, l1, h1, l2, h2;
-  range(rec[RS_CS], rec[RS_CS + 1], &sl, &sh);
-  range(rec[RS_C1], rec[RS_C1 + 1], &l1, &h1);
-  range(rec[RS_C2], rec[RS_C2 + 1], &l2, &h2);
-  const float rS = rec[RS_RHO] * 1.0001f, r1 = rec[RS_RHO + 1] * 1.0001f, r2 = rec[RS_RHO + 2] * 1.0001f;
+  range(rec.at(RS_CS), rec.at(RS_CS + 1), &sl, &sh);
+  range(rec.at(RS_C1), rec.at(RS_C1 + 1), &l1, &h1);
+  range(rec.at(RS_C2), rec.at(RS_C2 + 1), &l2, &h2);
+  const float rS = rec.at(RS_RHO) * 1.0001f, r1 = rec.at(RS_RHO + 1) * 1.0001f, r2 = rec.at(RS_RHO + 2) * 1.0001f;
   float dlo_s = fmaxf(sl - rS, r0 * q.cmin * 0.9999f);
   float dhi_s = fminf(sh + rS, r0 * 1.0001f);
   if (!(dlo_s <= dhi_s)) return false;
