@@ -283,7 +283,11 @@ def pixel_rz(geom):
     outgoing direction X/|X|, X = (SF, y, z), gives the scattering vector
     S = (X/|X| - x)/lambda, which lies on the Ewald sphere (Eq. laue); written
     without cancellation as S = (-(y^2 + z^2)/(r (r + SF)), y/r, z/r)/lambda.
-    R = sqrt(S_x^2 + S_y^2), Z = S_z (Eq. cyl-average's coordinates)."""
+    (R, Z) are the cylindrical coordinates of S about the fibre axis n (Eq.
+    cyl-average's coordinates): Z = S.n, R = |S - Z n|.  The fibre axis is z tilted
+    by geom.tilt about the lab y axis (the detector horizontal), n = (sin t, 0, cos t);
+    with m = (cos t, 0, -sin t), R = sqrt((S.m)^2 + S_y^2).  At tilt 0 this is
+    R = sqrt(S_x^2 + S_y^2), Z = S_z."""
     W, H = geom.width, geom.height
     i = np.arange(W, dtype=np.float64)
     j = np.arange(H, dtype=np.float64)
@@ -296,8 +300,12 @@ def pixel_rz(geom):
     Sx = -(y * y + z * z) / ((r * (r + SF)) * lam)
     Sy = y / (r * lam)
     Sz = z / (r * lam)
-    R = np.sqrt(Sx * Sx + Sy * Sy)
-    return R, Sz
+    tilt = float(getattr(geom, "tilt", 0.0))
+    st, ct = math.sin(tilt), math.cos(tilt)
+    Z = Sx * st + Sz * ct
+    Sm = Sx * ct - Sz * st
+    R = np.sqrt(Sm * Sm + Sy * Sy)
+    return R, Z
 
 
 # --------------------------------------------------------------------------- prepared problem

@@ -318,6 +318,40 @@ def test_pixel_points_lie_on_ewald_sphere_and_round_trip():
     np.testing.assert_allclose(S[..., 2], Z, rtol=1e-12, atol=1e-15)
 
 
+@pytest.mark.parametrize("tilt_deg", [22.0, -35.0, 60.0])
+def test_tilted_fibre_round_trip(tilt_deg):
+    """Fibre tilted toward the beam (k_in . n != 0, so the D term of Eq. harmonic is
+    nonzero): every point of the ring of a pixel's (R, Z) about the tilted axis, rotated
+    into the diffraction condition by Eqs. harmonic/solutions and projected onto the
+    detector, lands on the pixel or on its mirror (lab y -> -y)."""
+    t = tilt_deg * DEG
+    wl = W.small(4, width=29, height=23, center=(12.3, 8.6), tilt=t)
+    n = np.array([math.sin(t), 0.0, math.cos(t)])
+    m = np.array([math.cos(t), 0.0, -math.sin(t)])
+    y = np.array([0.0, 1.0, 0.0])
+    R, Z = O.pixel_rz(wl.geom)
+    rng = np.random.default_rng(7)
+    for j, i in [(0, 0), (22, 28), (11, 12), (5, 20), (17, 3)]:
+        psi = rng.uniform(0, 2 * math.pi)
+        S = R[j, i] * (math.cos(psi) * m + math.sin(psi) * y) + Z[j, i] * n
+        p1, p2 = O.ewald_project(S, wl.geom, fibre=n)
+        hits = np.stack([p1[0], p2[0]])
+        mirror_i = 2 * (wl.geom.center_x - 0.5) - i
+        got = sorted([tuple(np.round(h, 9)) for h in hits])
+        want = sorted([tuple(np.round(v, 9)) for v in {(i, j), (mirror_i, j)}])
+        np.testing.assert_allclose(got, want, atol=1e-7)
+    # tilt 0 leaves the map unchanged; a tilt mixes S_x into Z, so Z is no longer odd in z
+    R0, Z0 = O.pixel_rz(W.small(4, width=29, height=23, center=(12.3, 8.6)).geom)
+    assert not np.allclose(Z, Z0)
+    assert np.all(R >= 0)
+    # the tilt is a rotation about lab y: the pattern of a centred beam keeps its exact
+    # mirror y -> -y and loses the up/down (Friedel) symmetry
+    wc = W.small(6, width=20, height=18, n_nodes=10, tilt=t)
+    img = O.pattern(wc, O.prepare(wc))
+    assert img.max() > 0 and np.array_equal(img, img[:, ::-1])
+    assert np.abs(img - img[::-1, :]).max() > 1e-3 * img.max()
+
+
 def test_ewald_validity():
     """Beam normal to the fibre: S can be rotated onto the sphere iff lambda |S|^2 <= 2 R
     (Eq. valid); otherwise both angles are NaN."""

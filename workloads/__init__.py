@@ -57,6 +57,7 @@ class Geometry:
     height: int            # pixels along the detector vertical (lab z, fibre)
     center_x: float        # beam centre, pixel units
     center_y: float
+    tilt: float = 0.0      # fibre axis tilted by this angle (rad) about lab y, toward +x
 
 
 @dataclasses.dataclass
@@ -256,7 +257,7 @@ def small(seed: int, n_atoms: int = 24, width: int = 24, height: int = 20,
           cell: Optional[Cell] = None, sigma_theta: float = 4 * DEG, gamma_theta: float = 0.0,
           g=(0.0, 0.0, 0.0), n_nodes: int = 12, d_min: float = 5.0,
           size_A=(60.0, 60.0, 80.0), distance: float = 60.0, pixel: float = 0.8,
-          center=None) -> Workload:
+          center=None, tilt: float = 0.0) -> Workload:
     """Tiny seeded workload for oracle pins and parity edge cases (ragged detector
     sizes, off-centre beams, skewed cells)."""
     rng = np.random.default_rng(seed)
@@ -268,6 +269,6 @@ def small(seed: int, n_atoms: int = 24, width: int = 24, height: int = 20,
     N = (size_A[0] / cell.a, size_A[1] / cell.b, size_A[2] / cell.c)
     return Workload(
         f"small seed {seed}", cell,
-        Geometry(1.0, distance, pixel, width, height, float(center[0]), float(center[1])),
+        Geometry(1.0, distance, pixel, width, height, float(center[0]), float(center[1]), float(tilt)),
         Disorder(sigma_theta, gamma_theta, N, tuple(g)),
         Quadrature(n_nodes, extent_T(sigma_theta, gamma_theta), d_min=d_min), atoms)
