@@ -18,6 +18,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -79,6 +80,7 @@ def parse():
     ap.add_argument("--cpu-pixels", type=int, default=256)
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-model leg")
+    ap.add_argument("--no-tilt", action="store_true", help="skip the tilted-fibre forward leg")
     ap.add_argument("--batch-models", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -87,27 +89,22 @@ def parse():
     return ap.parse_args()
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards by reflections "
-              "across GPUs with one image all-reduce, which this build does not implement.", file=sys.stderr)
-        sys.exit(2)
+def forward_leg(wl, steps, warmup):
+    """Times the whole forward step (enumeration, structure factors, reflection prep, node
+    table, pixel map, culling, profile kernel) on workload wl.  Returns the wall time per
+    step, the profile kernel's mean HIP-event time, the useful evaluations of one step
+    (counting pass after the timed region) and the buffers of the last step."""
     import numpy as np
     import torch
 
-    import workloads as W
     from paper_2608_23245_amd import atoms_to_device
     from paper_2608_23245_amd import binding as B
 
-    torch.cuda.set_device(0)
-    wl = W.config1()
     model = B.make_model(wl)
     cell = model.cell
     atoms = atoms_to_device(wl.atoms)
     ext = (wl.dis.g[0], wl.dis.g[1], wl.dis.g[2], wl.quad.extinction)
     stream = torch.cuda.current_stream()
-
     state = {}
 
     def step(timed_events=None):
@@ -126,6 +123,49 @@ def main():
         state.update(hkl=hkl, refl=refl, nodes=nodes, pix=pix, tile=tile, off=off, idx=idx, img=img)
         return img
 
+    log(f"forward: {wl.name}, {warmup} warm-up steps")
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"forward: {steps} timed steps")
+    events = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        step(events[k])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / steps
+    prof_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
+    img = state["img"]
+    assert torch.isfinite(img).all()
+    n_evals = B.profile(model, state["refl"], state["nodes"], state["pix"], state["tile"], state["off"], state["idx"],
+                        count=True)
+    return ms_step, prof_ms, n_evals, state
+
+
+def bench_tilted(args):
+    """The medium forward step with the fibre tilted 22 degrees toward the beam."""
+    import workloads as W
+    wl = W.with_tilt(W.config1(), math.radians(22.0))
+    ms_step, prof_ms, n_evals, state = forward_leg(wl, max(1, min(args.steps, 3)), 1)
+    return {"workload": wl.name, "culled_pairs": int(state["idx"].shape[0]), "useful_evals_per_step": int(n_evals),
+            "ms_per_pattern": ms_step, "profile_kernel_ms": prof_ms, "evals_per_s": n_evals / (ms_step * 1e-3),
+            "profile_kernel_evals_per_s": n_evals / (prof_ms * 1e-3), "pass": "forward"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the path shards by reflections "
+              "across GPUs with one image all-reduce, which this build does not implement.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    wl = W.config1()
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -134,26 +174,7 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    log(f"forward: {wl.name}, {args.warmup} warm-up steps")
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    log(f"forward: {args.steps} timed steps")
-    events = [[torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)] for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        step(events[k])
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    prof_ms = float(np.mean([a.elapsed_time(b) for a, b in events]))
-    img = state["img"]
-    assert torch.isfinite(img).all()
-    # useful evaluations of one step (counting pass of the same kernel, after the timed region)
-    n_evals = B.profile(model, state["refl"], state["nodes"], state["pix"], state["tile"], state["off"], state["idx"],
-                        count=True)
-
+    ms_step, prof_ms, n_evals, state = forward_leg(wl, args.steps, args.warmup)
     log(f"forward: {ms_step:.1f} ms/step, profile kernel {prof_ms:.1f} ms, {n_evals:.4e} useful evaluations")
     slots = n_evals * SLOTS_PER_EVAL
     achieved = slots / (prof_ms * 1e-3) / 1e12
@@ -186,6 +207,10 @@ def main():
         out["cpu_baseline"] = cpu_baseline(wl, state, args.cpu_pixels)
     del state
     torch.cuda.empty_cache()
+    if not args.no_tilt:
+        log("forward, tilted fibre")
+        out["tilted"] = bench_tilted(args)
+        torch.cuda.empty_cache()
     if not args.no_bwd:
         log("forward + adjoint")
         out["fwd_bwd"] = bench_fwd_bwd(args)

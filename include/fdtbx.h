@@ -52,13 +52,18 @@ typedef struct fdtbx_cell {
   double alpha, beta, gamma;  /* angles b^c, a^c, a^b, radians */
 } fdtbx_cell;
 
-/* Flat detector normal to the beam (tutorial Table "experiment", tilt 0). */
+/* Flat detector normal to the beam along lab x (tutorial Table "experiment").  The
+ * fibre axis is lab z tilted by `tilt` about lab y (the detector horizontal) toward +x,
+ * n = (sin tilt, 0, cos tilt); tilt 0 is the fibre normal to the beam.  A tilted fibre
+ * makes the D term of Eq. harmonic nonzero; the pixel ring coordinates become
+ * Z = S.n, R = |S - Z n| (see fdtbx_pixel_map). */
 typedef struct fdtbx_geometry {
   double wavelength;          /* A */
   double distance;            /* sample-detector distance, same unit as pixel */
   double pixel;               /* pixel pitch */
-  int32_t width, height;      /* pixels along lab y (horizontal) and lab z (fibre) */
+  int32_t width, height;      /* pixels along lab y (horizontal) and lab z (vertical) */
   double center_x, center_y;  /* beam centre in pixel units (width/2, height/2 puts it between pixels) */
+  double tilt;                /* fibre tilt, radians, |tilt| < pi/2 */
 } fdtbx_geometry;
 
 /* Orientational and lattice disorder (section "Angular peak shapes", tutorial
@@ -193,8 +198,11 @@ int fdtbx_reflection_prep(const fdtbx_model* model, const int32_t* hkl, int64_t 
                           float* refl, double* cull, void* stream);
 
 /* Ring coordinates of every pixel and the (R, Z) boxes of the pixel tiles.
- *   pix  device float64 [height][width][2] output: (R, Z) of the pixel's Ewald point,
- *        S = (X/|X| - x)/lambda, X = (distance, y, z) (Eqs. laue, cyl-average)
+ *   pix  device float64 [height][width][2] output: (R, Z) of the pixel's Ewald point
+ *        S = (X/|X| - x)/lambda, X = (distance, y, z) (Eqs. laue, cyl-average), about the
+ *        fibre axis n: Z = S_x sin(tilt) + S_z cos(tilt),
+ *        R = sqrt((S_x cos(tilt) - S_z sin(tilt))^2 + S_y^2), binary64 without fused
+ *        multiply-adds, sin and cos of the host's C library
  *   tile device float64 [n_tiles][8] output: R_lo, R_hi, Z_lo, Z_hi, P2_lo, P2_hi, 0, 0
  *        over the pixel centres of each FDTBX_TILE^2 tile, tiles row-major,
  *        n_tiles = ceil(height/8) * ceil(width/8) */

@@ -40,7 +40,7 @@ class Cell(ctypes.Structure):
 class Geometry(ctypes.Structure):
     _fields_ = [("wavelength", ctypes.c_double), ("distance", ctypes.c_double), ("pixel", ctypes.c_double),
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32),
-                ("center_x", ctypes.c_double), ("center_y", ctypes.c_double)]
+                ("center_x", ctypes.c_double), ("center_y", ctypes.c_double), ("tilt", ctypes.c_double)]
 
 
 class Disorder(ctypes.Structure):
@@ -173,7 +173,8 @@ def make_cell(c) -> Cell:
 def make_model(wl) -> Model:
     g, d, q = wl.geom, wl.dis, wl.quad
     return Model(make_cell(wl.cell),
-                 Geometry(g.wavelength, g.distance, g.pixel, g.width, g.height, g.center_x, g.center_y),
+                 Geometry(g.wavelength, g.distance, g.pixel, g.width, g.height, g.center_x, g.center_y,
+                          float(getattr(g, "tilt", 0.0))),
                  Disorder(d.sigma_theta, d.gamma_theta, (ctypes.c_double * 3)(*d.N_base),
                           (ctypes.c_double * 3)(*d.g), d.intensity_model),
                  Quadrature(q.n_nodes, q.T, q.sigma_r, q.m, q.delta, q.d_min, q.d_max, q.extinction))

@@ -44,6 +44,7 @@ int check_geometry(const fdtbx_geometry* g) {
   if (g->width < 1 || g->height < 1 || g->width > 65536 || g->height > 65536)
     return fail(FDTBX_ERR_INVALID_ARGUMENT, "detector size must be in 1..65536 pixels");
   if (!isfinite(g->center_x) || !isfinite(g->center_y)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "beam centre not finite");
+  if (!(fabs(g->tilt) < 0.5 * M_PI)) return fail(FDTBX_ERR_GEOMETRY, "fibre tilt must be finite with |tilt| < pi/2");
   return FDTBX_OK;
 }
 

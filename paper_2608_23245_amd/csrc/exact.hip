@@ -242,11 +242,14 @@ namespace fdtbx {
 // ---------------------------------------------------------------- pixel map (Eqs. laue, cyl-average)
 struct PixParams {
   double lam, SF, p, cx, cy;
+  double st, ct;  // sine and cosine of the fibre tilt
   int32_t W, H, tiles_x, tiles_y;
 };
 
 // Ewald point of pixel (i, j): y = ((i + 1/2) - c_x) p, z = ((j + 1/2) - c_y) p,
-// r = |(SF, y, z)|, S = (-(y^2 + z^2)/(r (r + SF)), y/r, z/r)/lambda; R = |S_xy|, Z = S_z.
+// r = |(SF, y, z)|, S = (-(y^2 + z^2)/(r (r + SF)), y/r, z/r)/lambda; cylindrical
+// coordinates about the fibre axis n = (sin t, 0, cos t): Z = S.n and R = |S - Z n|,
+// written with m = (cos t, 0, -sin t) as R = sqrt((S.m)^2 + S_y^2).
 __device__ static inline void pixel_ewald(const PixParams& q, int i, int j, double* R, double* Z) {
   double y = (((double)i + 0.5) - q.cx) * q.p;
   double z = (((double)j + 0.5) - q.cy) * q.p;
@@ -254,8 +257,9 @@ __device__ static inline void pixel_ewald(const PixParams& q, int i, int j, doub
   double Sx = -(y * y + z * z) / ((r * (r + q.SF)) * q.lam);
   double Sy = y / (r * q.lam);
   double Sz = z / (r * q.lam);
-  *R = sqrt(Sx * Sx + Sy * Sy);
-  *Z = Sz;
+  double Sm = Sx * q.ct - Sz * q.st;
+  *R = sqrt(Sm * Sm + Sy * Sy);
+  *Z = Sx * q.st + Sz * q.ct;
 }
 
 // One 64-lane wave per FDTBX_TILE x FDTBX_TILE tile: pixel values and the tile's box.
@@ -644,6 +648,8 @@ static void pix_params(const fdtbx_geometry* g, PixParams* q) {
   q->p = g->pixel;
   q->cx = g->center_x;
   q->cy = g->center_y;
+  q->st = sin(g->tilt);
+  q->ct = cos(g->tilt);
   q->W = g->width;
   q->H = g->height;
   q->tiles_x = (int32_t)ceil_div(g->width, FDTBX_TILE);

@@ -81,6 +81,11 @@ def test_model_checks(lib):
     m5 = B.make_model(wl)
     m5.dis.g[0] = float("nan")
     assert lib.fdtbx_pattern_workspace(ctypes.byref(m5), 150, 1000) == 0
+    for tilt, ok in ((0.3, True), (-1.5, True), (1.6, False), (float("nan"), False)):
+        m6 = B.make_model(wl)
+        m6.geom.tilt = tilt
+        assert (lib.fdtbx_pattern_workspace(ctypes.byref(m6), 150, 1000) > 0) == ok, tilt
+    assert lib.fdtbx_pixel_map(ctypes.byref(m6.geom), ctypes.c_void_p(8), ctypes.c_void_p(8), None) == -2
     # pattern call with a workspace that is too small is rejected before any launch
     rc = lib.fdtbx_profile_pattern(ctypes.byref(m), ctypes.c_void_p(8), 150, ctypes.c_void_p(8), ctypes.c_void_p(8), 1000,
                                    None, ctypes.c_void_p(8), 16, None)

@@ -57,6 +57,8 @@ CASES = {
                       g=(0.01, 0.04, 0.0)),
     "no_intensity_model": dict(seed=45, width=16, height=16, sigma_theta=3 * DEG, gamma_theta=1 * DEG,
                                g=(0.03, 0.03, 0.0)),
+    "tilted": dict(seed=46, width=18, height=20, sigma_theta=2 * DEG, gamma_theta=1 * DEG, g=(0.02, 0.02, 0.0),
+                   tilt=30 * DEG),
 }
 
 

@@ -57,6 +57,9 @@ SMALL = {
     "lorentz": dict(seed=24, width=17, height=33, sigma_theta=0.0, gamma_theta=2.5 * DEG),
     "tiny_det": dict(seed=25, width=1, height=3, center=(-8.0, 1.5)),
     "wide_nodes": dict(seed=26, width=16, height=16, n_nodes=40, d_min=4.0),
+    "tilted": dict(seed=27, width=26, height=22, center=(13.0, 9.4), tilt=22 * DEG, sigma_theta=2 * DEG,
+                   gamma_theta=1 * DEG),
+    "tilted_back": dict(seed=28, width=19, height=25, tilt=-40 * DEG, g=(0.03, 0.03, 0.0)),
 }
 
 
@@ -280,6 +283,15 @@ def _sampled(wl, n_pix, seed):
     P = O.prepare(wl, hkl=np.ascontiguousarray(hkl[sub]), F=F, cull_extinct=False)
     vals = O.pattern_at(P, R.ravel()[pick], Z.ravel()[pick])
     return flat[pick], vals
+
+
+def test_pattern_tilted_medium_sampled():
+    """The medium workload with its fibre tilted by 22 degrees toward the beam (the tilt of
+    the paper's A-DNA example), full size, oracle at sampled pixels."""
+    wl = W.with_tilt(W.config1(), 22 * DEG)
+    say("pattern medium, fibre tilt 22 deg, 48 sampled pixels")
+    got, ref = _sampled(wl, 48, seed=11)
+    check_pattern(got, ref, "medium tilted sampled")
 
 
 @pytest.mark.parametrize("cfg,n_pix", [(1, 48), (2, 16)])

@@ -272,3 +272,9 @@ def small(seed: int, n_atoms: int = 24, width: int = 24, height: int = 20,
         Geometry(1.0, distance, pixel, width, height, float(center[0]), float(center[1]), float(tilt)),
         Disorder(sigma_theta, gamma_theta, N, tuple(g)),
         Quadrature(n_nodes, extent_T(sigma_theta, gamma_theta), d_min=d_min), atoms)
+
+
+def with_tilt(wl: Workload, tilt: float) -> Workload:
+    """The same workload with its fibre axis tilted by `tilt` (rad) toward the beam."""
+    return dataclasses.replace(wl, name=f"{wl.name}, fibre tilt {math.degrees(tilt):.0f} deg",
+                               geom=dataclasses.replace(wl.geom, tilt=float(tilt)))
