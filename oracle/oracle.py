@@ -197,6 +197,42 @@ def disorder_factors(hkl, dis):
     return A, N, Ip
 
 
+def axis_damping(hkl, cell, B_axis):
+    """Axis-dependent Debye-Waller damping of section "Paracrystalline disorder",
+    D(S) = exp(-1/4 sum_i B_i (S.a_i/|a_i|)^2), evaluated at S = D_hkl."""
+    avec, astar, _ = frame(cell)
+    S = recip_vectors(hkl, astar)
+    ex = np.zeros(hkl.shape[0])
+    for i in range(3):
+        ahat = avec[i] / np.linalg.norm(avec[i])
+        ex = ex + B_axis[i] * (S @ ahat) ** 2
+    return np.exp(-0.25 * ex)
+
+
+def axis_profile(lineshape, N, u):
+    """Per-axis peak of integral breadth 1/N (unit integral per lattice period, peak N),
+    in the form selected by lineshape:
+      0 Laue:     N sinc^2(N u)                                  (Eq. I_shape with N -> N_eff)
+      1 Gaussian: N exp(-pi N^2 u^2)                             (matched integral breadth)
+      2 Hosemann: (1 - A^2)/(1 - 2 A cos(2 pi u) + A^2), A = max(0, (N - 1)/(N + 1)),
+                  Eq. Z with its breadth (1 - A)/(1 + A) (Eq. breadth) equal to 1/N."""
+    N = np.asarray(N, dtype=np.float64)
+    u = np.asarray(u, dtype=np.float64)
+    if lineshape == 0:
+        return N * np.sinc(N * u) ** 2
+    if lineshape == 1:
+        return N * np.exp(-math.pi * N * N * u * u)
+    A = np.maximum(0.0, (N - 1.0) / (N + 1.0))
+    return (1.0 - A * A) / (1.0 - 2.0 * A * np.cos(2.0 * math.pi * u) + A * A)
+
+
+def support_half(lineshape, m, N):
+    """Support half-width in u = a_i.(p - s) per axis: m/N (Laue, Gaussian) or half a
+    lattice period (Hosemann, whose factor is periodic in u)."""
+    N = np.asarray(N, dtype=np.float64)
+    return np.full_like(N, 0.5) if lineshape == 2 else m / N
+
+
 def extinct_mask(hkl, dis, limit):
     """Reflections whose paracrystalline intensity loss prod A_i is below exp(-limit)
     (and I_para below 8 exp(-limit)); the pattern skips them."""
@@ -313,7 +349,7 @@ def pixel_rz(geom):
 class Prepared:
     hkl: np.ndarray
     F: np.ndarray
-    W: np.ndarray        # |F|^2 * I_para
+    W: np.ndarray        # |F|^2 * I_para * axis damping
     N: np.ndarray        # N_eff [n][3]
     A: np.ndarray
     Ip: np.ndarray
@@ -328,6 +364,8 @@ class Prepared:
     nodes: Nodes
     m: int
     delta: float
+    Dw: np.ndarray = None     # axis damping D(D_hkl)
+    lineshape: int = 0
 
 
 def prepare(wl, hkl=None, F=None, cull_extinct=True):
@@ -348,8 +386,10 @@ def prepare(wl, hkl=None, F=None, cull_extinct=True):
     D = recip_vectors(hkl, astar)
     r0, S, e1, e2, ep = reflection_frames(D)
     nodes = node_table(wl.quad.n_nodes, wl.quad.T, wl.quad.sigma_r, wl.dis.sigma_theta, wl.dis.gamma_theta)
-    W = (F.real * F.real + F.imag * F.imag) * Ip
-    return Prepared(hkl, F, W, N, A, Ip, D, r0, S, e1, e2, ep, avec, astar, nodes, wl.quad.m, wl.quad.delta)
+    Dw = axis_damping(hkl, wl.cell, getattr(wl.dis, "B_axis", (0.0, 0.0, 0.0)))
+    W = (F.real * F.real + F.imag * F.imag) * Ip * Dw
+    return Prepared(hkl, F, W, N, A, Ip, D, r0, S, e1, e2, ep, avec, astar, nodes, wl.quad.m, wl.quad.delta, Dw,
+                    int(getattr(wl.dis, "lineshape", 0)))
 
 
 class _Problem(ctypes.Structure):
@@ -358,7 +398,7 @@ class _Problem(ctypes.Structure):
                 ("e2", ctypes.c_void_p), ("ep", ctypes.c_void_p), ("astar", ctypes.c_void_p),
                 ("avec", ctypes.c_void_p), ("n_nodes", ctypes.c_int64), ("d1", ctypes.c_void_p),
                 ("d2", ctypes.c_void_p), ("omega", ctypes.c_void_p), ("m", ctypes.c_int32),
-                ("delta", ctypes.c_double), ("use_skip", ctypes.c_int32)]
+                ("delta", ctypes.c_double), ("use_skip", ctypes.c_int32), ("lineshape", ctypes.c_int32)]
 
 
 def _c_problem(P: Prepared, use_skip: bool):
@@ -371,7 +411,7 @@ def _c_problem(P: Prepared, use_skip: bool):
 
     prob = _Problem(P.hkl.shape[0], ptr(P.W), ptr(P.N), ptr(P.r0), ptr(P.S), ptr(P.e1), ptr(P.e2),
                     ptr(P.ep), ptr(P.astar), ptr(P.avec), P.nodes.d1.shape[0], ptr(P.nodes.d1),
-                    ptr(P.nodes.d2), ptr(P.nodes.omega), P.m, P.delta, 1 if use_skip else 0)
+                    ptr(P.nodes.d2), ptr(P.nodes.omega), P.m, P.delta, 1 if use_skip else 0, P.lineshape)
     return prob, keep
 
 
@@ -505,9 +545,10 @@ def sf_adjoint(hkl, cell, atoms, F, dF2):
 
 def gradients(wl, P: Prepared, G, R=None, Z=None, use_skip=True):
     """Gradients of L = sum_pixels G * image with respect to the atoms (fractional x, y, z,
-    B, occupancy) and the globals sigma_theta, gamma_theta, N_base (3), g (3), with T held
-    fixed.  Chain: W = |F|^2 I_para, N_eff from Eq. Neff, I_para from Eq. Ipara,
-    A_i = exp(-2 pi^2 g_i^2 h_i^2) (Eq. Ah)."""
+    B, occupancy) and the globals sigma_theta, gamma_theta, N_base (3), g (3), B_axis (3),
+    with T held fixed.  Chain: W = |F|^2 I_para D, N_eff from Eq. Neff, I_para from Eq.
+    Ipara, A_i = exp(-2 pi^2 g_i^2 h_i^2) (Eq. Ah), D the axis damping; the lineshape's
+    dependence on N_eff enters through the per-reflection sums."""
     if R is None:
         R, Z = pixel_rz(wl.geom)
     nd = P.nodes
@@ -520,7 +561,8 @@ def gradients(wl, P: Prepared, G, R=None, Z=None, use_skip=True):
     Nb = np.asarray(wl.dis.N_base, dtype=np.float64)
     d_Nbase = np.sum(dN * P.N ** 2 / Nb[None, :] ** 2, axis=0)
     F2 = P.F.real ** 2 + P.F.imag ** 2
-    dIp = dW * F2
+    Dw = P.Dw if P.Dw is not None else np.ones_like(F2)
+    dIp = dW * F2 * Dw
     A = P.A
     dN_dA = 2.0 * P.N ** 2 / (1.0 + A) ** 2
     dA = dN * dN_dA
@@ -529,9 +571,15 @@ def gradients(wl, P: Prepared, G, R=None, Z=None, use_skip=True):
     g = np.asarray(wl.dis.g, dtype=np.float64)
     h2 = P.hkl.astype(np.float64) ** 2
     d_g = np.sum(dA * (-4.0 * PI2 * g[None, :] * h2 * A), axis=0)
-    atom = sf_adjoint(P.hkl, wl.cell, wl.atoms, P.F, dW * P.Ip)
+    # axis damping: dW/dB_i = -W (S.a_i/|a_i|)^2 / 4
+    avec = P.avec
+    d_B = np.zeros(3)
+    for i in range(3):
+        ahat = avec[i] / np.linalg.norm(avec[i])
+        d_B[i] = np.sum(dW * P.W * (-0.25) * (P.D @ ahat) ** 2)
+    atom = sf_adjoint(P.hkl, wl.cell, wl.atoms, P.F, dW * P.Ip * Dw)
     return {"atoms": atom, "sigma_theta": d_sigma, "gamma_theta": d_gamma, "N_base": d_Nbase, "g": d_g,
-            "dW": dW, "sums": sums}
+            "B_axis": d_B, "dW": dW, "sums": sums}
 
 
 # --------------------------------------------------------------------------- culling contract
@@ -558,9 +606,10 @@ def reflection_boxes(wl, hkl):
 
     Nodes s = r0 c (S + d1 e1 + d2 e2) have |d_j| <= T and c in [c_min, 1] with
     c_min = (1 + 2T^2)^(-1/2); a query point p lies in the support box
-    {x : |a_i.x| <= m/N_i} of some node, whose extent along a unit vector v is
-    sum_i (m/N_i)|a*_i.v|, with 1/N_i bounded without transcendentals by
-    1/N_base,i + min(pi^2 g_i^2 h_i^2, 1) (since tanh(t) <= min(t, 1)).  Hence:
+    {x : |a_i.x| <= w_i} of some node, whose extent along a unit vector v is
+    sum_i w_i |a*_i.v|.  For the Laue and Gaussian lineshapes w_i = m/N_i, with 1/N_i
+    bounded without transcendentals by 1/N_base,i + min(pi^2 g_i^2 h_i^2, 1) (since
+    tanh(t) <= min(t, 1)); for the Hosemann lineshape w_i = 1/2.  Hence:
       - (R, Z) box: s.v over the node set, widened by the support extent, v = e_perp, z;
       - annulus: |s| = r0, so |p| is within sum_i (m/N_i)|a*_i| of r0;
       - wedge (reflections off the meridian): in the (R, Z) plane every node lies in
@@ -582,6 +631,8 @@ def reflection_boxes(wl, hkl):
         g = wl.dis.g[i]
         t = PI2 * (g * g) * (h[:, i] * h[:, i])
         mN[:, i] = m * (1.0 / wl.dis.N_base[i] + np.minimum(t, 1.0))
+    if getattr(wl.dis, "lineshape", 0) == 2:
+        mN[:] = 0.5
     ez = np.zeros_like(ep)
     ez[:, 2] = 1.0
 

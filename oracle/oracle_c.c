@@ -12,7 +12,8 @@
  *   oracle_grad      -- the adjoint of that image for a weighted residual
  *
  * Both follow the section "Numerical evaluation: per-reflection shell
- * quadrature" (Eqs. I_shape, gnomonic, node_weight, direct_sum), the
+ * quadrature" (Eqs. I_shape, gnomonic, node_weight, direct_sum; Eqs. Z and
+ * breadth for the Hosemann lineshape), the
  * section "Lorentz correction on a sampled reciprocal lattice" (Eq. lorentz)
  * and the section "Index-dependent paracrystalline disorder" (Eqs. Ah, Neff,
  * Ipara) of the paper.
@@ -45,6 +46,7 @@ typedef struct {
   int32_t m;            /* kernel zeros kept per axis */
   double delta;         /* Lorentz regulariser */
   int32_t use_skip;     /* 1: skip reflections whose support provably misses the query point */
+  int32_t lineshape;    /* per-axis peak form: 0 Laue, 1 Gaussian, 2 Hosemann */
 } oracle_problem;
 
 /* N sinc^2(N u), sinc(x) = sin(pi x)/(pi x), sinc(0) = 1 (Eq. I_shape, one axis). */
@@ -55,19 +57,37 @@ static double laue_axis(double N, double u) {
   return N * s * s;
 }
 
+/* Coefficient of Hosemann's factor (Eq. Z) whose integral breadth (1 - A)/(1 + A)
+ * (Eq. breadth) equals 1/N; 0 when N <= 1 (no narrower peak exists). */
+static double hosemann_A(double N) { return N > 1.0 ? (N - 1.0) / (N + 1.0) : 0.0; }
+
+/* Per-axis peak of integral breadth 1/N, unit integral per period, peak N:
+ * Laue N sinc^2(N u) (Eq. I_shape), Gaussian N exp(-pi N^2 u^2), or Hosemann
+ * (1 - A^2)/(1 - 2 A cos(2 pi u) + A^2) (Eq. Z). */
+static double axis_profile(int lineshape, double N, double u) {
+  if (lineshape == 0) return laue_axis(N, u);
+  if (lineshape == 1) return N * exp(-M_PI * N * N * u * u);
+  double A = hosemann_A(N);
+  return (1.0 - A * A) / (1.0 - 2.0 * A * cos(2.0 * M_PI * u) + A * A);
+}
+
+/* Support half-width in u: m/N (Laue, Gaussian) or half a lattice period (Hosemann). */
+static double support_half(const oracle_problem* P, double N) { return P->lineshape == 2 ? 0.5 : P->m / N; }
+
 static double dot3(const double* a, const double* b) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
 
-/* Largest |x| over the support box {x : |a_i . x| <= m/N_i} = {sum u_i a*_i : |u_i| <= m/N_i}:
+/* Largest |x| over the support box {x : |a_i . x| <= w_i} = {sum u_i a*_i : |u_i| <= w_i}:
  * the longest of its corner vectors. */
 static double support_radius(const oracle_problem* P, int64_t h) {
   double best = 0.0;
+  const double w0 = support_half(P, P->N[3 * h + 0]), w1 = support_half(P, P->N[3 * h + 1]);
+  const double w2 = support_half(P, P->N[3 * h + 2]);
   for (int sa = -1; sa <= 1; sa += 2)
     for (int sb = -1; sb <= 1; sb += 2)
       for (int sc = -1; sc <= 1; sc += 2) {
         double v[3];
         for (int j = 0; j < 3; ++j)
-          v[j] = sa * (P->m / P->N[3 * h + 0]) * P->astar[0 * 3 + j] + sb * (P->m / P->N[3 * h + 1]) * P->astar[1 * 3 + j] +
-                 sc * (P->m / P->N[3 * h + 2]) * P->astar[2 * 3 + j];
+          v[j] = sa * w0 * P->astar[0 * 3 + j] + sb * w1 * P->astar[1 * 3 + j] + sc * w2 * P->astar[2 * 3 + j];
         double r = sqrt(dot3(v, v));
         if (r > best) best = r;
       }
@@ -135,10 +155,11 @@ static double profile_at(const oracle_problem* P, int64_t h, const double* p, in
     int inside = 1;
     for (int i = 0; i < 3; ++i) {
       u[i] = dot3(&P->avec[3 * i], x);
-      if (fabs(u[i]) > P->m / N[i]) inside = 0;
+      if (fabs(u[i]) > support_half(P, N[i])) inside = 0;
     }
     if (!inside) continue;
-    double Zk = laue_axis(N[0], u[0]) * laue_axis(N[1], u[1]) * laue_axis(N[2], u[2]);
+    double Zk = axis_profile(P->lineshape, N[0], u[0]) * axis_profile(P->lineshape, N[1], u[1]) *
+                axis_profile(P->lineshape, N[2], u[2]);
     I += r0 * r0 * P->omega[k] * Zk;
     ++cnt;
   }
@@ -190,14 +211,28 @@ static double laue_axis_dN(double N, double u) {
   return sin(2.0 * M_PI * N * u) / (M_PI * u * N) - s * s / (M_PI * M_PI * u * u * N * N);
 }
 
+/* d/dN of axis_profile at fixed u.  Gaussian: exp(-pi N^2 u^2)(1 - 2 pi N^2 u^2).
+ * Hosemann: (dA/dN) [2 cos(2 pi u)(1 + A^2) - 4 A]/(1 - 2 A cos(2 pi u) + A^2)^2 with
+ * dA/dN = 2/(N + 1)^2 for N > 1 and 0 below (where A is held at 0). */
+static double axis_profile_dN(int lineshape, double N, double u) {
+  if (lineshape == 0) return laue_axis_dN(N, u);
+  if (lineshape == 1) return exp(-M_PI * N * N * u * u) * (1.0 - 2.0 * M_PI * N * N * u * u);
+  if (!(N > 1.0)) return 0.0;
+  double A = hosemann_A(N);
+  double c = cos(2.0 * M_PI * u);
+  double den = 1.0 - 2.0 * A * c + A * A;
+  return 2.0 / ((N + 1.0) * (N + 1.0)) * (2.0 * c * (1.0 + A * A) - 4.0 * A) / (den * den);
+}
+
 /* Adjoint sums of the image for a pixel weight G (dL/dP at each listed pixel).  For every
  * reflection h, over the listed pixels q and the nodes k inside the support at p*_qh:
  *   out[h][0] = sum_q G_q L(R_q) r0^2 sum_k omega_k Z_k              (= dL/dW_h)
  *   out[h][1] = sum_q G_q L(R_q) r0^2 sum_k domega_k/dsigma Z_k
  *   out[h][2] = sum_q G_q L(R_q) r0^2 sum_k domega_k/dgamma Z_k
  *   out[h][3+i] = sum_q G_q L(R_q) r0^2 sum_k omega_k dZ_k/dN_i     (i = a, b, c)
- * with Z_k = prod_i N_i sinc^2(N_i u_i) (Eq. I_shape).  The support boundary moves with N_i
- * but Z has a double zero there, so it adds nothing. */
+ * with Z_k = prod_i f(N_i, u_i), f the per-axis profile of the lineshape.  For the Laue form
+ * the support boundary moves with N_i but Z has a double zero there, so it adds nothing; the
+ * Gaussian is below 1e-12 of its peak there; the Hosemann support (half a period) is fixed. */
 void oracle_grad_sums(const oracle_problem* P, const double* domega_ds, const double* domega_dg, int64_t n_pix,
                       const double* R, const double* Z, const double* G, double* out) {
   double theta_nodes = nodes_max_angle(P);
@@ -225,13 +260,13 @@ void oracle_grad_sums(const oracle_problem* P, const double* domega_ds, const do
         int inside = 1;
         for (int i = 0; i < 3; ++i) {
           u[i] = dot3(&P->avec[3 * i], x);
-          if (fabs(u[i]) > P->m / N[i]) inside = 0;
+          if (fabs(u[i]) > support_half(P, N[i])) inside = 0;
         }
         if (!inside) continue;
         double f[3], df[3];
         for (int i = 0; i < 3; ++i) {
-          f[i] = laue_axis(N[i], u[i]);
-          df[i] = laue_axis_dN(N[i], u[i]);
+          f[i] = axis_profile(P->lineshape, N[i], u[i]);
+          df[i] = axis_profile_dN(P->lineshape, N[i], u[i]);
         }
         double Zk = f[0] * f[1] * f[2];
         a[0] += P->omega[k] * Zk;

@@ -213,6 +213,82 @@ def test_hosemann_breadth_and_neff():
     assert np.array_equal(N0, np.tile([7.0, 5.0, 3.0], (3, 1)))
 
 
+@pytest.mark.parametrize("N", [0.8, 1.7, 3.75, 8.0, 25.0])
+def test_axis_profiles_peak_integral_breadth(N):
+    """Every lineshape is a per-axis peak of height N_eff, unit integral per lattice period
+    and integral breadth 1/N_eff (Eq. breadth for the Hosemann form; the Laue form's mass
+    is the Dirichlet integral, the Gaussian's the Gaussian integral)."""
+    f = lambda ls, u: float(O.axis_profile(ls, N, u))
+    # Laue: peak N, integral over the line 1 (sinc^2 integrates to 1)
+    assert f(0, 0.0) == pytest.approx(N, rel=1e-15)
+    lim = 400.0 / N
+    mass = sum(integrate.quad(lambda u: f(0, u), a, a + 1.0 / N, limit=200)[0] for a in np.arange(-lim, lim, 1.0 / N))
+    assert mass == pytest.approx(1.0, abs=2.0 / (math.pi ** 2 * 400.0))
+    # Gaussian of matched integral breadth
+    assert f(1, 0.0) == pytest.approx(N, rel=1e-15)
+    assert integrate.quad(lambda u: f(1, u), -np.inf, np.inf)[0] == pytest.approx(1.0, rel=1e-10)
+    # Hosemann: one period integrates to 1; peak (1 + A)/(1 - A) = N when N > 1, flat otherwise
+    per = integrate.quad(lambda u: f(2, u), -0.5, 0.5, limit=200)[0]
+    assert per == pytest.approx(1.0, rel=1e-10)
+    assert f(2, 0.0) == pytest.approx(max(N, 1.0), rel=1e-12)
+    assert f(2, 0.3) == pytest.approx(f(2, 1.3), rel=1e-12) and f(2, 0.3) == pytest.approx(f(2, -0.3), rel=1e-12)
+
+
+def test_hosemann_profile_is_poisson_kernel():
+    """Eq. Z is the Poisson kernel: (1 - A^2)/(1 - 2A cos t + A^2) = 1 + 2 sum_k A^k cos(k t)."""
+    u = np.linspace(-0.5, 0.5, 41)
+    for N in (1.5, 4.0, 12.0):
+        A = (N - 1.0) / (N + 1.0)
+        series = 1.0 + 2.0 * sum(A ** k * np.cos(2.0 * math.pi * k * u) for k in range(1, 2000))
+        np.testing.assert_allclose(O.axis_profile(2, N, u), series, rtol=1e-10)
+
+
+def test_axis_profile_n_derivatives_match_fd():
+    """d/dN of each per-axis profile at fixed u (used by the adjoint) against central
+    differences of axis_profile, through the compiled oracle's derivative routine."""
+    wl = W.small(32, n_atoms=4, width=10, height=9, sigma_theta=3 * DEG, g=(0.02, 0.0, 0.01), n_nodes=10, d_min=5.0)
+    for ls in (0, 1, 2):
+        wl2 = W.with_disorder(wl, lineshape=ls)
+        hkl = O.enumerate_hkl(wl2.cell, wl2.quad.d_min, wl2.quad.d_max)
+        P = O.prepare(wl2, hkl=hkl, cull_extinct=False)
+        R, Z = O.pixel_rz(wl2.geom)
+        G = np.random.default_rng(ls).normal(size=R.shape)
+        ds, dg = O.node_weight_derivs(P.nodes, wl2.quad.sigma_r, wl2.dis.sigma_theta, wl2.dis.gamma_theta)
+        sums = O.grad_sums(P, ds, dg, R, Z, G, use_skip=False)
+        # sums[:, 3 + i] = sum G L r0^2 omega dZ/dN_i: compare with (S(N + h) - S(N - h))/2h of sums[:, 0]
+        for i in range(3):
+            h = 1e-5
+            Pp, Pm = O.prepare(wl2, hkl=hkl, cull_extinct=False), O.prepare(wl2, hkl=hkl, cull_extinct=False)
+            Pp.N = P.N.copy()
+            Pm.N = P.N.copy()
+            Pp.N[:, i] += h
+            Pm.N[:, i] -= h
+            fd = (O.grad_sums(Pp, ds, dg, R, Z, G, use_skip=False)[:, 0] -
+                  O.grad_sums(Pm, ds, dg, R, Z, G, use_skip=False)[:, 0]) / (2 * h)
+            scale = np.abs(fd).max()
+            assert scale > 0
+            np.testing.assert_allclose(sums[:, 3 + i], fd, atol=2e-6 * scale, rtol=1e-5)
+
+
+def test_axis_damping():
+    """D(S) = exp(-1/4 sum B_i (S.a_i/|a_i|)^2): S.a_i = h_i for S = D_hkl, so the exponent is
+    sum B_i h_i^2/|a_i|^2 / 4; equal B on an orthogonal cell gives the isotropic form
+    exp(-2 pi^2 <u^2> S^2) with B = 8 pi^2 <u^2>."""
+    skew = W.Cell(9.0, 11.0, 13.0, 80 * DEG, 100 * DEG, 110 * DEG)
+    hkl = O.enumerate_hkl(skew, 3.0, 30.0)
+    B = (3.0, 7.0, 11.0)
+    lens = (skew.a, skew.b, skew.c)
+    want = np.exp(-0.25 * sum(B[i] * hkl[:, i].astype(np.float64) ** 2 / lens[i] ** 2 for i in range(3)))
+    np.testing.assert_allclose(O.axis_damping(hkl, skew, B), want, rtol=1e-13)
+    ortho = W.Cell(9.0, 11.0, 13.0, 90 * DEG, 90 * DEG, 90 * DEG)
+    hkl = O.enumerate_hkl(ortho, 3.0, 30.0)
+    S2 = O.q_of(O.recip_vectors(hkl, O.frame(ortho)[1]))
+    u2 = 0.07
+    np.testing.assert_allclose(O.axis_damping(hkl, ortho, (8 * math.pi ** 2 * u2,) * 3),
+                               np.exp(-2 * math.pi ** 2 * u2 * S2), rtol=1e-13)
+    assert np.all(O.axis_damping(hkl, ortho, (0.0, 0.0, 0.0)) == 1.0)
+
+
 def test_intensity_loss_is_sech():
     """2A/(1+A^2) with A = exp(-t) is 1/cosh(t) (Eq. Ipara)."""
     hkl = np.array([[1, 2, 3], [10, -4, 7], [0, 0, 15]], dtype=np.int32)
@@ -604,6 +680,45 @@ def test_oracle_gradients_match_finite_differences(st, gt):
         checks.append((f"g{i}", gr["g"][i], fd(mg, 1e-6)))
     for j in range(wl.atoms.n):
         for field, h in (("x", 1e-6), ("y", 1e-6), ("z", 1e-6), ("B", 1e-4), ("occ", 1e-5)):
+            def ma(w, hh, field=field, j=j):
+                getattr(w.atoms, field)[j] += hh
+            checks.append((f"{field}{j}", gr["atoms"][field][j], fd(ma, h)))
+    scale = max(abs(c[2]) for c in checks)
+    for name, an, num in checks:
+        assert abs(an - num) <= 1e-6 * scale + 1e-5 * abs(num), (name, an, num)
+
+
+@pytest.mark.parametrize("lineshape", [1, 2])
+def test_oracle_gradients_lineshapes_and_damping_fd(lineshape):
+    """Gaussian and Hosemann lineshapes with axis damping: the oracle's adjoint for the
+    globals (sigma, N_base, g, B_axis) and a few atom fields against central differences."""
+    import copy
+    wl, hkl, G = _fd_problem(3 * DEG, 1 * DEG)
+    wl.dis.lineshape = lineshape
+    wl.dis.B_axis = (4.0, 9.0, 2.5)
+    P = O.prepare(wl, hkl=hkl, cull_extinct=False)
+    gr = O.gradients(wl, P, G, use_skip=False)
+
+    def fd(mut, h):
+        w1, w2 = copy.deepcopy(wl), copy.deepcopy(wl)
+        mut(w1, +h)
+        mut(w2, -h)
+        return (_loss(w1, hkl, G) - _loss(w2, hkl, G)) / (2 * h)
+
+    def tup(name, i):
+        def mut(w, h):
+            v = list(getattr(w.dis, name))
+            v[i] += h
+            setattr(w.dis, name, tuple(v))
+        return mut
+
+    checks = [("sigma", gr["sigma_theta"], fd(lambda w, h: setattr(w.dis, "sigma_theta", w.dis.sigma_theta + h), 1e-7))]
+    for i in range(3):
+        checks.append((f"N{i}", gr["N_base"][i], fd(tup("N_base", i), 1e-5)))
+        checks.append((f"g{i}", gr["g"][i], fd(tup("g", i), 1e-6)))
+        checks.append((f"B{i}", gr["B_axis"][i], fd(tup("B_axis", i), 1e-4)))
+    for j in range(2):
+        for field, h in (("x", 1e-6), ("B", 1e-4), ("occ", 1e-5)):
             def ma(w, hh, field=field, j=j):
                 getattr(w.atoms, field)[j] += hh
             checks.append((f"{field}{j}", gr["atoms"][field][j], fd(ma, h)))

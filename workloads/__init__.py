@@ -67,6 +67,8 @@ class Disorder:
     N_base: tuple          # coherent cells along a, b, c
     g: tuple               # Hosemann g along a, b, c
     intensity_model: int = 1   # 1 = Hosemann intensity loss, 0 = none
+    lineshape: int = 0         # per-axis peak form: 0 Laue (sinc^2), 1 Gaussian, 2 Hosemann
+    B_axis: tuple = (0.0, 0.0, 0.0)  # axis-dependent Debye-Waller damping B_a, B_b, B_c (A^2)
 
 
 @dataclasses.dataclass
@@ -272,6 +274,14 @@ def small(seed: int, n_atoms: int = 24, width: int = 24, height: int = 20,
         Geometry(1.0, distance, pixel, width, height, float(center[0]), float(center[1]), float(tilt)),
         Disorder(sigma_theta, gamma_theta, N, tuple(g)),
         Quadrature(n_nodes, extent_T(sigma_theta, gamma_theta), d_min=d_min), atoms)
+
+
+LINESHAPES = {"laue": 0, "gaussian": 1, "hosemann": 2}
+
+
+def with_disorder(wl: Workload, **changes) -> Workload:
+    """The same workload with some disorder fields replaced (lineshape, B_axis, ...)."""
+    return dataclasses.replace(wl, dis=dataclasses.replace(wl.dis, **changes))
 
 
 def with_tilt(wl: Workload, tilt: float) -> Workload:
