@@ -81,6 +81,7 @@ def parse():
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-model leg")
     ap.add_argument("--no-tilt", action="store_true", help="skip the tilted-fibre forward leg")
+    ap.add_argument("--no-lineshapes", action="store_true", help="skip the Gaussian/Hosemann lineshape legs")
     ap.add_argument("--batch-models", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -154,6 +155,30 @@ def bench_tilted(args):
             "profile_kernel_evals_per_s": n_evals / (prof_ms * 1e-3), "pass": "forward"}
 
 
+# Issue slots per useful evaluation of the other lineshapes (same accounting as above):
+# Gaussian: 3 subtractions, max3, compare, sum of squares (3), scale (1), accumulate (1)
+# and one half-rate exp2; Hosemann: 3 subtractions, max3, compare, 3 denominators, 2
+# products, accumulate and three half-rate cosines and one reciprocal.
+SLOTS_PER_EVAL_LS = {"gaussian": 10 + 1 * TRANS_SLOTS, "hosemann": 11 + 4 * TRANS_SLOTS}
+
+
+def bench_lineshapes(args):
+    """The medium forward step with the Gaussian and the Hosemann lineshapes and the
+    tutorial's axis damping B = (10, 10, 10) A^2."""
+    import workloads as W
+    out = {}
+    for name, code in (("gaussian", 1), ("hosemann", 2)):
+        wl = W.with_disorder(W.config1(), lineshape=code, B_axis=(10.0, 10.0, 10.0))
+        ms_step, prof_ms, n_evals, state = forward_leg(wl, max(1, min(args.steps, 3)), 1)
+        ach = n_evals * SLOTS_PER_EVAL_LS[name] / (prof_ms * 1e-3)
+        out[name] = {"ms_per_pattern": ms_step, "profile_kernel_ms": prof_ms, "useful_evals_per_step": int(n_evals),
+                     "evals_per_s": n_evals / (ms_step * 1e-3), "profile_kernel_evals_per_s": n_evals / (prof_ms * 1e-3),
+                     "slots_per_eval": SLOTS_PER_EVAL_LS[name], "issue_frac": ach / PEAK_SLOTS}
+        del state
+    out["workload"] = "medium (as value), lineshape varied, axis damping B = (10, 10, 10) A^2"
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -210,6 +235,10 @@ def main():
     if not args.no_tilt:
         log("forward, tilted fibre")
         out["tilted"] = bench_tilted(args)
+        torch.cuda.empty_cache()
+    if not args.no_lineshapes:
+        log("forward, Gaussian and Hosemann lineshapes")
+        out["lineshapes"] = bench_lineshapes(args)
         torch.cuda.empty_cache()
     if not args.no_bwd:
         log("forward + adjoint")

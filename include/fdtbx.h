@@ -70,13 +70,31 @@ typedef struct fdtbx_geometry {
  * Table "paracrystal").  sigma_theta: Gaussian standard deviation; gamma_theta:
  * Lorentzian HWHM; both zero is an error.  N_base: coherent cells along a, b, c
  * (non-integer allowed).  g: Hosemann relative spacing fluctuation per axis
- * (Eq. Ah).  intensity_model: 1 applies the intensity loss of Eq. Ipara, 0 omits it. */
+ * (Eq. Ah).  intensity_model: 1 applies the intensity loss of Eq. Ipara, 0 omits it.
+ * lineshape: per-axis peak of integral breadth 1/N_eff (Eq. Neff), unit integral per
+ * lattice period and height N_eff, in u = a_i.(p - s):
+ *   FDTBX_LINESHAPE_LAUE      N sinc^2(N u) (Eq. I_shape with N -> N_eff), support |u| <= m/N
+ *   FDTBX_LINESHAPE_GAUSSIAN  N exp(-pi N^2 u^2) (matched integral breadth), support |u| <= m/N
+ *   FDTBX_LINESHAPE_HOSEMANN  (1 - A^2)/(1 - 2 A cos(2 pi u) + A^2), A = max(0, (N-1)/(N+1))
+ *                             (Eq. Z with breadth (1-A)/(1+A) = 1/N, Eq. breadth), support
+ *                             |u| <= 1/2 (one lattice period; m unused)
+ * B_axis: axis-dependent Debye-Waller damping (section "Paracrystalline disorder"), a factor
+ * exp(-1/4 sum_i B_i (S.a_i/|a_i|)^2) on each reflection's intensity at S = D_hkl, A^2. */
+#define FDTBX_LINESHAPE_LAUE 0
+#define FDTBX_LINESHAPE_GAUSSIAN 1
+#define FDTBX_LINESHAPE_HOSEMANN 2
 typedef struct fdtbx_disorder {
   double sigma_theta, gamma_theta;
   double N_base[3];
   double g[3];
   int32_t intensity_model;
+  int32_t lineshape;
+  double B_axis[3];
 } fdtbx_disorder;
+
+/* Refinable globals of a model, in this order, for the gradient and update calls:
+ * sigma_theta, gamma_theta, N_base a, b, c, g a, b, c, B_axis a, b, c. */
+#define FDTBX_N_GLOBALS 11
 
 /* Shell quadrature (section "Numerical evaluation: per-reflection shell quadrature"). */
 typedef struct fdtbx_quadrature {
@@ -155,6 +173,9 @@ int fdtbx_structure_factors(const fdtbx_cell* cell, int64_t n_atoms, const float
  *   [4..5]  P2_lo, P2_hi              range of |p|^2 (annulus about r0)
  *   [6..11] n1R, n1Z, rho1, n2R, n2Z, rho2   inward edge normals of the arc wedge and
  *                                     the support extent along each; rho1 < 0 disables
+ * The support extents use the per-axis half-widths w_i of the lineshape's support in u:
+ * 1/2 for the Hosemann lineshape, else m/N_eff,i bounded above (no transcendental) by
+ * m (1/N_base,i + min(pi^2 g_i^2 h_i^2, 1)).
  *   [12]    1 if the reflection is kept (not removed by the extinction cull), else 0
  *   [13..15] reserved (0)
  * Node record, FDTBX_NODE_FLOATS float32 per node, node k = i2*n + i1:
@@ -189,10 +210,10 @@ int64_t fdtbx_node_rows(int32_t n_nodes);
  *   nodes device float32 [fdtbx_node_rows(n_nodes)][FDTBX_NODE_FLOATS] output */
 int fdtbx_node_table(const fdtbx_disorder* dis, const fdtbx_quadrature* quad, float* nodes, void* stream);
 
-/* Per-reflection preparation (Eqs. Ah, Neff, Ipara, gnomonic):
+/* Per-reflection preparation (Eqs. Ah, Neff, Ipara, gnomonic; axis damping D):
  *   hkl  device int32 [n_hkl][3];  F2 device float32 [n_hkl] (|F|^2)
  *   refl device float32 [n_hkl][FDTBX_REFL_FLOATS] output (layout private to the
- *        profile kernels except: [0] W = |F|^2 I_para, [1..3] N_eff a,b,c, [4] r0)
+ *        profile kernels except: [0] W = |F|^2 I_para D, [1..3] N_eff a,b,c, [4] r0)
  *   cull device float64 [n_hkl][FDTBX_CULL_DOUBLES] output (layout above) */
 int fdtbx_reflection_prep(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F2,
                           float* refl, double* cull, void* stream);
@@ -224,9 +245,10 @@ int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_t n_hkl, co
                int32_t* idx, int64_t cap, int64_t* n_pairs, void* ws, size_t ws_bytes, void* stream);
 
 /* The detector image (Eq. direct_sum per reflection at the pixel's query point
- * p* = R e_perp + Z z, Eq. I_shape with N -> N_eff, Eq. lorentz):
+ * p* = R e_perp + Z z, Eq. lorentz):
  *   image[j][i] = delta/(R_ij + delta) * sum_hkl W_hkl r0^2 sum_k omega_k Z_hkl(p* - s_k)
- * over nodes with |a_l.(p* - s_k)| <= m/N_l, reflections from the tile lists.
+ * with Z_hkl = prod_l f(N_l, a_l.(p* - s_k)), f the per-axis profile of the model's lineshape
+ * (fdtbx_disorder), over nodes inside its support, reflections from the tile lists.
  *   image device float32 [height][width] output (fully overwritten)
  *   counts device int64 [1] (may be NULL): if non-NULL, a counting pass runs instead
  *          of the image pass and adds the number of (pixel, reflection, node) triples
@@ -249,26 +271,28 @@ int fdtbx_profile_pattern(const fdtbx_model* model, const int32_t* hkl, int64_t 
 
 /* ------------------------------------------------------------------ adjoint
  * Gradients of a scalar L through the image, given G = dL/dimage (float32 [height][width],
- * device).  The parameters are the atoms (fractional x, y, z, B, occupancy), the angular
- * widths sigma_theta, gamma_theta, N_base[3] and g[3]; T stays fixed.  Profile values are
- * recomputed tile by tile, never stored.
+ * device).  The parameters are the atoms (fractional x, y, z, B, occupancy) and the
+ * FDTBX_N_GLOBALS globals; T stays fixed.  Profile values are recomputed tile by tile,
+ * never stored.
  *
  * fdtbx_profile_adjoint: per reflection r, over the pixels of the tiles that list r and the
- * nodes inside the support (same lists, windows and kernel as fdtbx_profile),
- *   sums[r][0] = sum G L(R) sum_k omega_k Z'_k            Z' = prod_i sinc^2(N_i u_i)
+ * nodes inside the support (same lists, windows and kernel as fdtbx_profile), with
+ * Z_k = C_r Z'_k the profile product of the lineshape and C_r = K_r/r0^2 the per-reflection
+ * constant folded into the record:
+ *   sums[r][0] = sum G L(R) sum_k omega_k Z'_k
  *   sums[r][1] = sum G L(R) sum_k (d omega_k/d sigma_theta) Z'_k
  *   sums[r][2] = sum G L(R) sum_k (d omega_k/d gamma_theta) Z'_k
- *   sums[r][3+i] = sum G L(R) sum_k omega_k D_ik,  D_ik = d[N_i sinc^2(N_i u_i)]/dN_i prod_{j!=i} sinc^2
- * each up to the factor (2 pi)^6 folded into the reflection record.  sums: device float64
- * [n_hkl][6], zeroed by the call, then accumulated with binary64 atomic adds (the result
- * depends on the order of those adds only below binary64 rounding). */
+ *   sums[r][3+i] = sum G L(R) sum_k omega_k N_i (dZ_k/dN_i)/C_r   (u held fixed)
+ * sums: device float64 [n_hkl][6], zeroed by the call, then accumulated with binary64 atomic
+ * adds (the result depends on the order of those adds only below binary64 rounding). */
 int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
                           const double* tile, const int64_t* offsets, const int32_t* idx, int64_t n_hkl,
                           const float* grad_image, double* sums, void* stream);
 
-/* fdtbx_adjoint_finish: chain rule per reflection in binary64 (Eqs. Ah, Neff, Ipara):
+/* fdtbx_adjoint_finish: chain rule per reflection in binary64 (Eqs. Ah, Neff, Ipara, axis
+ * damping):
  *   dF2[r] = dL/d|F|^2 (device float32 [n_hkl] output, may be NULL)
- *   d_globals = dL/d(sigma_theta, gamma_theta, N_base a, b, c, g a, b, c) (device float64 [8])
+ *   d_globals = dL/d(the FDTBX_N_GLOBALS globals) (device float64 [FDTBX_N_GLOBALS])
  * from the sums of fdtbx_profile_adjoint, the reflection records and F (device float32
  * [n_hkl][2]).  The globals are reduced over reflections in a fixed order.
  *   ws: device workspace of fdtbx_adjoint_finish_workspace(n_hkl) bytes */
@@ -312,8 +336,9 @@ int fdtbx_pattern_backward(const fdtbx_model* model, const int32_t* hkl, int64_t
  * part starts.  Offsets count elements of the respective arrays (reflections, atoms,
  * pixels, tiles, CSR row pointers, culling-list entries, nodes, scattering-factor rows).
  * Every model keeps its own detector, quadrature and disorder parameters; the kernels
- * read them from the device copy of the entries, so sigma_theta, gamma_theta, N_base and
- * g can change between steps (fdtbx_batch_set_globals) without a host round trip.  The
+ * read them from the device copy of the entries, so the globals (sigma_theta, gamma_theta,
+ * N_base, g, B_axis) can change between steps (fdtbx_batch_set_globals) without a host
+ * round trip.  The
  * culling lists stay those built at set-up.
  *
  * Work tables (device int64, built by the caller): entries pack (model << 40) | first index.
@@ -342,7 +367,7 @@ int fdtbx_batch_entry_init(const fdtbx_model* model, fdtbx_batch_entry* e);
 /* sizeof(fdtbx_batch_entry), for bindings that mirror the struct. */
 size_t fdtbx_batch_entry_size(void);
 
-/* Device: entries[m].model.dis <- globals[m][0..7] = (sigma_theta, gamma_theta, N_base[3], g[3]). */
+/* Device: entries[m].model.dis <- globals[m][0..FDTBX_N_GLOBALS-1] (order of FDTBX_N_GLOBALS). */
 int fdtbx_batch_set_globals(fdtbx_batch_entry* entries, int32_t n_models, const double* globals, void* stream);
 
 /* Forward step for all models: structure factors F [sum n_hkl][2] and F2, reflection
@@ -357,9 +382,9 @@ int fdtbx_batch_forward(const fdtbx_batch_entry* entries, int32_t n_models, cons
 
 /* Backward step for all models, after fdtbx_batch_forward with the same inputs:
  * grad_image (float32, laid out as the images) -> atom gradients (float32 [sum n_atoms]
- * each), d_globals (float64 [n_models][8]) and dF2 (float32 [sum n_hkl]).  sums: device
+ * each), d_globals (float64 [n_models][FDTBX_N_GLOBALS]) and dF2 (float32 [sum n_hkl]).  sums: device
  * float64 [n_hkl_total][6] scratch (n_hkl_total = sum of n_hkl); part: device float64
- * [n_rb][8] scratch.  Neither call allocates, copies to the host or synchronises, so a
+ * [n_rb][FDTBX_N_GLOBALS] scratch.  Neither call allocates, copies to the host or synchronises, so a
  * caller can capture them (with fdtbx_batch_set_globals) in a HIP graph. */
 int fdtbx_batch_backward(const fdtbx_batch_entry* entries, int32_t n_models, const int64_t* refl_blocks, int64_t n_rb,
                          const int64_t* model_rb, const int64_t* atom_blocks, int64_t n_ab, const int64_t* tile_items,

@@ -3,13 +3,13 @@
 ``PatternFunction`` maps (fractional x, y, z, B, occupancy, globals) to the
 detector image through libfdtbx (structure factors, then the profile pattern)
 and back through fdtbx_pattern_backward.  globals is a float64 tensor of the
-eight parameters (sigma_theta, gamma_theta, N_base a/b/c, g a/b/c); the node
-grid extent T stays fixed.
+eleven parameters (sigma_theta, gamma_theta, N_base a/b/c, g a/b/c, B_axis a/b/c);
+the node grid extent T stays fixed.
 
 ``FibreModel`` holds refinement parameters in physical units (Cartesian
 coordinates in A, B, occupancy, total angular width sigma and Lorentzian fraction
-eta, crystallite sizes in A, Hosemann g) and converts them with torch ops, so that
-autograd supplies those chain rules.
+eta, crystallite sizes in A, Hosemann g, axis damping B_axis) and converts them
+with torch ops, so that autograd supplies those chain rules.
 """
 from __future__ import annotations
 
@@ -47,10 +47,11 @@ class PatternEngine:
         for i in range(3):
             d.N_base[i] = float(g[2 + i])
             d.g[i] = float(g[5 + i])
+            d.B_axis[i] = float(g[8 + i])
 
     def globals_of(self, wl=None) -> torch.Tensor:
         d = (wl or self.wl).dis
-        return torch.tensor([d.sigma_theta, d.gamma_theta, *d.N_base, *d.g], dtype=torch.float64)
+        return torch.tensor([d.sigma_theta, d.gamma_theta, *d.N_base, *d.g, *d.B_axis], dtype=torch.float64)
 
     def atoms(self, x, y, z, Bf, occ) -> dict:
         c = lambda t: t.detach().to(self.device, torch.float32).contiguous()
@@ -104,7 +105,7 @@ def real_basis(cell) -> np.ndarray:
 
 class FibreModel(torch.nn.Module):
     """Parameters: xyz (Cartesian, A) [n][3], B [n], occ [n], sigma (rad), eta, size (A) [3],
-    g [3].  forward() returns the detector image."""
+    g [3], B_axis (A^2) [3].  forward() returns the detector image."""
 
     def __init__(self, wl, engine: Optional[PatternEngine] = None, device="cuda"):
         super().__init__()
@@ -124,12 +125,13 @@ class FibreModel(torch.nn.Module):
         self.size = torch.nn.Parameter(torch.tensor([wl.dis.N_base[i] * [wl.cell.a, wl.cell.b, wl.cell.c][i]
                                                      for i in range(3)], dtype=torch.float64))
         self.g = torch.nn.Parameter(torch.tensor(list(wl.dis.g), dtype=torch.float64))
+        self.B_axis = torch.nn.Parameter(torch.tensor(list(wl.dis.B_axis), dtype=torch.float64))
 
     def globals(self):
         st = (1.0 - self.eta) * self.sigma
         gt = self.eta * self.sigma
         Nb = self.size / self.edges
-        return torch.cat([st.reshape(1), gt.reshape(1), Nb, self.g])
+        return torch.cat([st.reshape(1), gt.reshape(1), Nb, self.g, self.B_axis])
 
     def forward(self):
         frac = self.xyz @ self.basis_inv

@@ -121,10 +121,10 @@ class BatchEngine:
         self.image = torch.empty(off["pix"], dtype=torch.float32, device=device)
         self.counter = torch.zeros(2, dtype=torch.int64, device=device)
         self.sums = torch.empty((H, 6), dtype=torch.float64, device=device)
-        self.part = torch.empty((max(len(refl_blocks), 1), 8), dtype=torch.float64, device=device)
+        self.part = torch.empty((max(len(refl_blocks), 1), B.N_GLOBALS), dtype=torch.float64, device=device)
         self.dF2 = torch.empty(H, dtype=torch.float32, device=device)
         self.grads = {k: torch.empty(off["atom"], dtype=torch.float32, device=device) for k in ("x", "y", "z", "B", "occ")}
-        self.d_globals = torch.empty((n, 8), dtype=torch.float64, device=device)
+        self.d_globals = torch.empty((n, B.N_GLOBALS), dtype=torch.float64, device=device)
         pix_off = [0]
         for h, w in self.shapes:
             pix_off.append(pix_off[-1] + h * w)
@@ -138,7 +138,7 @@ class BatchEngine:
         return self.image[self.pix_off[m]:self.pix_off[m + 1]].view(h, w)
 
     def globals(self) -> torch.Tensor:
-        g = [[wl.dis.sigma_theta, wl.dis.gamma_theta, *wl.dis.N_base, *wl.dis.g] for wl in self.workloads]
+        g = [[wl.dis.sigma_theta, wl.dis.gamma_theta, *wl.dis.N_base, *wl.dis.g, *wl.dis.B_axis] for wl in self.workloads]
         return torch.tensor(g, dtype=torch.float64, device=self.device)
 
     # ------------------------------------------------------------------ step

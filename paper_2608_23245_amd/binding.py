@@ -45,7 +45,8 @@ class Geometry(ctypes.Structure):
 
 class Disorder(ctypes.Structure):
     _fields_ = [("sigma_theta", ctypes.c_double), ("gamma_theta", ctypes.c_double),
-                ("N_base", ctypes.c_double * 3), ("g", ctypes.c_double * 3), ("intensity_model", ctypes.c_int32)]
+                ("N_base", ctypes.c_double * 3), ("g", ctypes.c_double * 3), ("intensity_model", ctypes.c_int32),
+                ("lineshape", ctypes.c_int32), ("B_axis", ctypes.c_double * 3)]
 
 
 class Quadrature(ctypes.Structure):
@@ -176,7 +177,8 @@ def make_model(wl) -> Model:
                  Geometry(g.wavelength, g.distance, g.pixel, g.width, g.height, g.center_x, g.center_y,
                           float(getattr(g, "tilt", 0.0))),
                  Disorder(d.sigma_theta, d.gamma_theta, (ctypes.c_double * 3)(*d.N_base),
-                          (ctypes.c_double * 3)(*d.g), d.intensity_model),
+                          (ctypes.c_double * 3)(*d.g), d.intensity_model, int(getattr(d, "lineshape", 0)),
+                          (ctypes.c_double * 3)(*getattr(d, "B_axis", (0.0, 0.0, 0.0)))),
                  Quadrature(q.n_nodes, q.T, q.sigma_r, q.m, q.delta, q.d_min, q.d_max, q.extinction))
 
 
@@ -335,7 +337,10 @@ class PatternPlan:
 
 
 # ----------------------------------------------------------------------------- adjoint
-GLOBAL_NAMES = ("sigma_theta", "gamma_theta", "N_base_a", "N_base_b", "N_base_c", "g_a", "g_b", "g_c")
+GLOBAL_NAMES = ("sigma_theta", "gamma_theta", "N_base_a", "N_base_b", "N_base_c", "g_a", "g_b", "g_c",
+                "B_a", "B_b", "B_c")
+N_GLOBALS = len(GLOBAL_NAMES)
+LINESHAPES = {"laue": 0, "gaussian": 1, "hosemann": 2}
 
 
 def profile_adjoint(model: Model, refl, nodes, pix, tile, offsets, idx, grad_image: torch.Tensor) -> torch.Tensor:
@@ -349,11 +354,11 @@ def profile_adjoint(model: Model, refl, nodes, pix, tile, offsets, idx, grad_ima
 
 
 def adjoint_finish(model: Model, hkl, refl, sums, F):
-    """fdtbx_adjoint_finish: (dF2 float32 [n], d_globals float64 [8])."""
+    """fdtbx_adjoint_finish: (dF2 float32 [n], d_globals float64 [N_GLOBALS])."""
     L = lib()
     n = int(hkl.shape[0])
     dF2 = torch.empty(n, dtype=torch.float32, device=hkl.device)
-    glob = torch.empty(8, dtype=torch.float64, device=hkl.device)
+    glob = torch.empty(N_GLOBALS, dtype=torch.float64, device=hkl.device)
     wsb = L.fdtbx_adjoint_finish_workspace(n)
     ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=hkl.device)
     _check(L.fdtbx_adjoint_finish(ctypes.byref(model), _ptr(hkl), n, _ptr(refl), _ptr(sums), _ptr(F), _ptr(dF2), _ptr(glob),
@@ -380,14 +385,14 @@ def sf_adjoint(cell: Cell, atoms: dict, hkl, F, dF2):
 
 def pattern_backward(plan: "PatternPlan", hkl, F, grad_image, atoms: Optional[dict]):
     """fdtbx_pattern_backward after plan.run(hkl, |F|^2): (atom gradients dict or None,
-    d_globals float64 [8], dF2 float32 [n_hkl])."""
+    d_globals float64 [N_GLOBALS], dF2 float32 [n_hkl])."""
     L = lib()
     n_hkl = plan.n_hkl
     dev = hkl.device
     n_atoms = int(atoms["x"].shape[0]) if atoms is not None else 0
     wsb = L.fdtbx_backward_workspace(n_hkl, n_atoms)
     ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=dev)
-    glob = torch.empty(8, dtype=torch.float64, device=dev)
+    glob = torch.empty(N_GLOBALS, dtype=torch.float64, device=dev)
     dF2 = torch.empty(n_hkl, dtype=torch.float32, device=dev)
     out = None
     a = [None] * 7

@@ -3,21 +3,21 @@
 // k_profile_adj walks the same tile lists, node windows and tile-level node queue as
 // the forward kernel and, per pixel lane inside the support, accumulates
 //   z  = g omega Z',  s = g domega/dsigma Z',  y = g domega/dgamma Z',  n_i = g omega D_i
-// with g = G L(R) of the pixel, Z' = prod_j S_j^2 and, for N_i sinc^2(N_i u_i) written in
-// y_i = N_i u_i/2 and S_j = sin(2 pi y_j)/y_j = 2 pi sinc(2 y_j),
-//   d/dN_i [N_i sinc^2(N_i u_i)] = sinc(x)(2 cos(pi x) - sinc(x)),  x = 2 y_i,
-// so that D_i = S_i (4 pi cos(2 pi y_i) - S_i) prod_{j != i} S_j^2 carries the same
-// 1/(2 pi)^6 and N factors as Z' (Eq. I_shape with N -> N_eff).  Per (tile, reflection)
-// the six lane sums are reduced over the wave and added in binary64 to the reflection's
-// sums.  Profile values are recomputed, never stored.
+// with g = G L(R) of the pixel, Z = C Z' the lineshape's profile product (C its
+// per-reflection constant) and D_i = N_i (dZ/dN_i)/C at fixed u (eval_node_adj gives D_i
+// for each lineshape; for the Laue form, with y_i = N_i u_i/2 and S_j = sin(2 pi y_j)/y_j,
+// D_i = S_i (4 pi cos(2 pi y_i) - S_i) prod_{j != i} S_j^2).  Per (tile, reflection) the six
+// lane sums are reduced over the wave and added in binary64 to the reflection's sums.
+// Profile values are recomputed, never stored.
 //
 // k_adj_finish applies the chain rule per reflection in binary64:
-//   dL/dW = K z,  W = |F|^2 I_para,  K = r0^2 N_a N_b N_c/(2 pi)^6
+//   dL/dW = K z,  W = |F|^2 I_para D,  K = r0^2 C
 //   dL/dsigma_theta += W K s,  dL/dgamma_theta += W K y
 //   dL/dN_eff,i = W K n_i / N_i,  dN_eff/dN_base = N_eff^2/N_base^2            (Eq. Neff)
 //   dN_eff/dA = 2 N_eff^2/(1 + A)^2,  dI_para/dA_i = I_para (1 - A^2)/(A (1 + A^2)) (Eq. Ipara)
 //   dA/dg = -4 pi^2 g h^2 A                                                    (Eq. Ah)
-// and reduces the eight global gradients over reflections in a fixed order.
+//   D = exp(-1/4 sum_i B_i h_i^2/|a_i|^2),  dW/dB_i = -W h_i^2/(4 |a_i|^2)   (axis damping)
+// and reduces the FDTBX_N_GLOBALS global gradients over reflections in a fixed order.
 //
 // k_sf_adj_* carry dL/d|F|^2 back to the atoms (Eq. structure_factor):
 //   d|F|^2/dx_j = -4 pi h occ_j Im(F* t_j/occ_j) (likewise y with k, z with l),
@@ -32,6 +32,7 @@
 
 namespace fdtbx {
 
+template <int LS>
 __global__ void __launch_bounds__(64) k_profile_adj(ProfParams q, const float* __restrict__ refl, const float* __restrict__ nodes,
                                                     const double* __restrict__ pix, const double* __restrict__ tile,
                                                     const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
@@ -39,7 +40,7 @@ __global__ void __launch_bounds__(64) k_profile_adj(ProfParams q, const float* _
   __shared__ float4 qn[128];
   __shared__ float2 qd[128];
   __shared__ int bq[64];
-  adjoint_tile(q, refl, nodes, pix, tile, offsets, idx, grad_image, sums, blockIdx.x, qn, qd, bq);
+  adjoint_tile<LS>(q, refl, nodes, pix, tile, offsets, idx, grad_image, sums, blockIdx.x, qn, qd, bq);
 }
 
 __global__ void k_zero_f64(double* __restrict__ v, int64_t n) {
@@ -50,59 +51,65 @@ __global__ void k_zero_f64(double* __restrict__ v, int64_t n) {
 // ---------------------------------------------------------------- chain rule per reflection
 struct FinishParams {
   double Nb[3], g[3];
+  double Bax[3], ia2[3];  // axis damping B_i and 1/|a_i|^2
   int32_t intensity_model;
   int64_t n;
 };
 
+constexpr int kNG = FDTBX_N_GLOBALS;
+
 static constexpr int kFinThreads = 256;
 
-// Block sum of 8 doubles per thread into part[block][8] (fixed tree order).
-__device__ static void block_sum8(double v[8], double* part) {
-  __shared__ double red[kFinThreads / 64][8];
+// Block sum of kNG doubles per thread into part[block][kNG] (fixed tree order).
+__device__ static void block_sum(double v[kNG], double* part) {
+  __shared__ double red[kFinThreads / 64][kNG];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  for (int c = 0; c < 8; ++c) {
+  for (int c = 0; c < kNG; ++c) {
     double x = v[c];
     for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
     if (lane == 0) red[wid][c] = x;
   }
   __syncthreads();
-  if (threadIdx.x < 8) {
+  if (threadIdx.x < kNG) {
     double x = 0.0;
     for (int w = 0; w < kFinThreads / 64; ++w) x += red[w][threadIdx.x];
-    part[8 * (int64_t)blockIdx.x + threadIdx.x] = x;
+    part[kNG * (int64_t)blockIdx.x + threadIdx.x] = x;
   }
 }
 
-// Chain rule for one reflection (binary64).  Returns dL/d|F|^2 and adds the eight global
+// Chain rule for one reflection (binary64).  Returns dL/d|F|^2 and adds the kNG global
 // contributions to v.
 __device__ static double finish_one(const FinishParams& p, const int32_t* hk, const float* rec, const double* sr,
-                                    const float* Fr, double v[8]) {
+                                    const float* Fr, double v[kNG]) {
   const double pi2 = M_PI * M_PI;
-  double A[3], N[3], Ip = 1.0, h2[3];
+  double A[3], N[3], Ip = 1.0, h2[3], Dx = 0.0;
   for (int i = 0; i < 3; ++i) {
     double h = (double)hk[i];
     h2[i] = h * h;
     A[i] = exp(-2.0 * pi2 * p.g[i] * p.g[i] * h2[i]);
     N[i] = 1.0 / (1.0 / p.Nb[i] + (1.0 - A[i]) / (1.0 + A[i]));
     if (p.intensity_model) Ip *= 2.0 * A[i] / (1.0 + A[i] * A[i]);
+    Dx += p.Bax[i] * h2[i] * p.ia2[i];
   }
+  const double Dw = exp(-0.25 * Dx);
   const double fr = Fr[0], fi = Fr[1];
   const double f2 = fr * fr + fi * fi;
-  const double W = f2 * Ip;
+  const double W = f2 * Ip * Dw;
   const double K = (double)rec[RS_K];
   const double dW = K * sr[0];
   const double WK = W * K;
   v[0] += WK * sr[1];
   v[1] += WK * sr[2];
-  const double dIp = dW * f2;
+  const double dIp = dW * f2 * Dw;
   for (int i = 0; i < 3; ++i) {
     const double dN = WK * sr[3 + i] / N[i];
     v[2 + i] += dN * N[i] * N[i] / (p.Nb[i] * p.Nb[i]);
     double dA = dN * 2.0 * N[i] * N[i] / ((1.0 + A[i]) * (1.0 + A[i]));
     if (p.intensity_model) dA += dIp * Ip * (1.0 - A[i] * A[i]) / (A[i] * (1.0 + A[i] * A[i]));
     v[5 + i] += dA * (-4.0 * pi2 * p.g[i] * h2[i] * A[i]);
+    v[8 + i] += dW * W * (-0.25 * h2[i] * p.ia2[i]);
   }
-  return dW * Ip;
+  return dW * Ip * Dw;
 }
 
 __global__ void __launch_bounds__(kFinThreads) k_adj_finish(FinishParams p, const int32_t* __restrict__ hkl,
@@ -110,19 +117,19 @@ __global__ void __launch_bounds__(kFinThreads) k_adj_finish(FinishParams p, cons
                                                             const float* __restrict__ F, float* __restrict__ dF2,
                                                             double* __restrict__ part) {
   const int64_t r = (int64_t)blockIdx.x * kFinThreads + threadIdx.x;
-  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double v[kNG] = {};
   if (r < p.n) {
     const double d = finish_one(p, hkl + 3 * r, refl + (int64_t)FDTBX_REFL_FLOATS * r, sums + 6 * r, F + 2 * r, v);
     if (dF2) dF2[r] = (float)d;
   }
-  block_sum8(v, part);
+  block_sum(v, part);
 }
 
 __global__ void k_sum_parts(const double* __restrict__ part, int64_t nb, double* __restrict__ out) {
   const int c = threadIdx.x;
-  if (c >= 8) return;
+  if (c >= kNG) return;
   double x = 0.0;
-  for (int64_t b = 0; b < nb; ++b) x += part[8 * b + c];
+  for (int64_t b = 0; b < nb; ++b) x += part[kNG * b + c];
   out[c] = x;
 }
 
@@ -269,9 +276,24 @@ __global__ void __launch_bounds__(64) k_b_profile_adj(const fdtbx_batch_entry* _
     const fdtbx_batch_entry& e = ent[m];
     ProfParams q;
     prof_params(&e.model, &q);
-    adjoint_tile(q, refl + (int64_t)FDTBX_REFL_FLOATS * e.hkl_off, nodes + (int64_t)FDTBX_NODE_FLOATS * e.node_off,
-                 pix + 2 * e.pix_off, tile + 8 * e.tile_off, rowptr + e.rowptr_off, idx + e.pair_off,
-                 grad_image + e.pix_off, sums + 6 * e.hkl_off, t, qn, qd, bq);
+    const float* rf = refl + (int64_t)FDTBX_REFL_FLOATS * e.hkl_off;
+    const float* nd = nodes + (int64_t)FDTBX_NODE_FLOATS * e.node_off;
+    const double* px = pix + 2 * e.pix_off;
+    const double* tb = tile + 8 * e.tile_off;
+    const int64_t* rp = rowptr + e.rowptr_off;
+    const int32_t* ix = idx + e.pair_off;
+    const float* gi = grad_image + e.pix_off;
+    double* sm = sums + 6 * e.hkl_off;
+    switch (q.lineshape) {  // uniform across the wave
+      case FDTBX_LINESHAPE_GAUSSIAN:
+        adjoint_tile<FDTBX_LINESHAPE_GAUSSIAN>(q, rf, nd, px, tb, rp, ix, gi, sm, t, qn, qd, bq);
+        break;
+      case FDTBX_LINESHAPE_HOSEMANN:
+        adjoint_tile<FDTBX_LINESHAPE_HOSEMANN>(q, rf, nd, px, tb, rp, ix, gi, sm, t, qn, qd, bq);
+        break;
+      default:
+        adjoint_tile<FDTBX_LINESHAPE_LAUE>(q, rf, nd, px, tb, rp, ix, gi, sm, t, qn, qd, bq);
+    }
   }
 }
 
@@ -279,7 +301,10 @@ __device__ static void finish_params_of(const fdtbx_batch_entry& e, FinishParams
   for (int i = 0; i < 3; ++i) {
     p->Nb[i] = e.model.dis.N_base[i];
     p->g[i] = e.model.dis.g[i];
+    p->Bax[i] = e.model.dis.B_axis[i];
   }
+  const double len[3] = {e.model.cell.a, e.model.cell.b, e.model.cell.c};
+  for (int i = 0; i < 3; ++i) p->ia2[i] = 1.0 / (len[i] * len[i]);
   p->intensity_model = e.model.dis.intensity_model;
   p->n = e.n_hkl;
 }
@@ -292,14 +317,14 @@ __global__ void __launch_bounds__(kFinThreads) k_b_finish(const fdtbx_batch_entr
   const int m = (int)(item >> 40);
   const fdtbx_batch_entry& e = ent[m];
   const int64_t r = (item & ((1ll << 40) - 1)) + threadIdx.x;
-  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double v[kNG] = {};
   if (r < e.n_hkl) {
     FinishParams p;
     finish_params_of(e, &p);
     const int64_t g = e.hkl_off + r;
     dF2[g] = (float)finish_one(p, hkl + 3 * g, refl + (int64_t)FDTBX_REFL_FLOATS * g, sums + 6 * g, F + 2 * g, v);
   }
-  block_sum8(v, part);
+  block_sum(v, part);
 }
 
 // d_globals[m] = sum of the model's block partials, in block order.
@@ -307,10 +332,10 @@ __global__ void k_b_globals(int32_t n_models, const int64_t* __restrict__ model_
                             double* __restrict__ out) {
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_models) return;
-  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  double v[kNG] = {};
   for (int64_t b = model_rb[m]; b < model_rb[m + 1]; ++b)
-    for (int c = 0; c < 8; ++c) v[c] += part[8 * b + c];
-  for (int c = 0; c < 8; ++c) out[8 * (int64_t)m + c] = v[c];
+    for (int c = 0; c < kNG; ++c) v[c] += part[kNG * b + c];
+  for (int c = 0; c < kNG; ++c) out[kNG * (int64_t)m + c] = v[c];
 }
 
 // One thread per atom of one model; loops over all of the model's reflections.
@@ -388,11 +413,13 @@ __global__ void k_b_set_globals(fdtbx_batch_entry* __restrict__ ent, int32_t n_m
   const int m = blockIdx.x * blockDim.x + threadIdx.x;
   if (m >= n_models) return;
   fdtbx_disorder& d = ent[m].model.dis;
-  d.sigma_theta = glob[8 * (int64_t)m + 0];
-  d.gamma_theta = glob[8 * (int64_t)m + 1];
+  const double* gl = glob + kNG * (int64_t)m;
+  d.sigma_theta = gl[0];
+  d.gamma_theta = gl[1];
   for (int i = 0; i < 3; ++i) {
-    d.N_base[i] = glob[8 * (int64_t)m + 2 + i];
-    d.g[i] = glob[8 * (int64_t)m + 5 + i];
+    d.N_base[i] = gl[2 + i];
+    d.g[i] = gl[5 + i];
+    d.B_axis[i] = gl[8 + i];
   }
 }
 
@@ -458,16 +485,23 @@ extern "C" int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(6 * n_hkl, 256)), dim3(256), 0, s, sums, 6 * n_hkl);
   FDTBX_LAUNCH_CHECK("adjoint zero");
-  int64_t n_tiles = (int64_t)q.tiles_x * q.tiles_y;
-  hipLaunchKernelGGL(k_profile_adj, dim3((unsigned)n_tiles), dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx, grad_image,
-                     sums);
+  const dim3 grid((unsigned)((int64_t)q.tiles_x * q.tiles_y));
+  if (q.lineshape == FDTBX_LINESHAPE_GAUSSIAN)
+    hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_GAUSSIAN>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
+                       grad_image, sums);
+  else if (q.lineshape == FDTBX_LINESHAPE_HOSEMANN)
+    hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_HOSEMANN>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
+                       grad_image, sums);
+  else
+    hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
+                       grad_image, sums);
   FDTBX_LAUNCH_CHECK("profile adjoint");
   return FDTBX_OK;
 }
 
 extern "C" size_t fdtbx_adjoint_finish_workspace(int64_t n_hkl) {
   if (n_hkl <= 0) return 0;
-  return (size_t)ceil_div(n_hkl, kFinThreads) * 8 * sizeof(double);
+  return (size_t)ceil_div(n_hkl, kFinThreads) * kNG * sizeof(double);
 }
 
 extern "C" int fdtbx_adjoint_finish(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* refl,
@@ -479,9 +513,12 @@ extern "C" int fdtbx_adjoint_finish(const fdtbx_model* model, const int32_t* hkl
   if (rc) return rc;
   if (ws_bytes < fdtbx_adjoint_finish_workspace(n_hkl)) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "finish workspace too small");
   FinishParams p;
+  const double len[3] = {model->cell.a, model->cell.b, model->cell.c};
   for (int i = 0; i < 3; ++i) {
     p.Nb[i] = model->dis.N_base[i];
     p.g[i] = model->dis.g[i];
+    p.Bax[i] = model->dis.B_axis[i];
+    p.ia2[i] = 1.0 / (len[i] * len[i]);
   }
   p.intensity_model = model->dis.intensity_model;
   p.n = n_hkl;

@@ -3,44 +3,85 @@
 #pragma once
 
 #include "profile_common.h"
+#include "profile_tile.h"
 
 namespace fdtbx {
 
+// Adjoint of eval_node for one queued node (nd = kappa, omega; dw = d omega/d sigma,
+// d omega/d gamma), weighted by gp = G L(R) of the lane's pixel.  With Z' the lineshape's
+// profile product as in eval_node:
+//   acc[0] += gp omega Z',  acc[1] += gp dw.x Z',  acc[2] += gp dw.y Z',
+//   acc[3+i] += gp omega N_i (dZ/dN_i)/C   (the profile's N-derivative at fixed u, C its
+//                                           per-reflection constant; see the header).
+// Laue:     S_i (4 pi cos(2 pi y_i) - S_i) prod_{j!=i} S_j^2 with S_i = sin(2 pi y_i)/y_i.
+// Gaussian: Z' (1 - 8 pi y_i^2).
+// Hosemann: Z' (c_i (1 + A_i^2) - 2 A_i)/den_i with c_i = cos(2 pi y_i) (0 where A_i is held at 0).
+template <int LS>
 __device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, float al0, float al1, float al2, float gp,
-                                              float half_m, float tiny, float* acc) {
+                                              float half_m, float tiny, const HoseK& hk, float* acc) {
   float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
   float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
   if (mx <= half_m) {
-    ya = fabsf(ya) + tiny;
-    yb = fabsf(yb) + tiny;
-    yc = fabsf(yc) + tiny;
-    const float sa = __builtin_amdgcn_sinf(ya), sb = __builtin_amdgcn_sinf(yb), sc = __builtin_amdgcn_sinf(yc);
-    const float ca = __builtin_amdgcn_cosf(ya), cb = __builtin_amdgcn_cosf(yb), cc = __builtin_amdgcn_cosf(yc);
-    const float yab = ya * yb;
-    const float inv = __builtin_amdgcn_rcpf(yab * yc);
-    const float Sa = sa * (inv * (yb * yc));
-    const float Sb = sb * (inv * (ya * yc));
-    const float Sc = sc * (inv * yab);
-    const float Pa = Sa * Sa, Pb = Sb * Sb, Pc = Sc * Sc;
-    const float Pab = Pa * Pb;
-    const float P = Pab * Pc;
-    const float t = gp * P;
-    acc[0] = fmaf(nd.w, t, acc[0]);
-    acc[1] = fmaf(dw.x, t, acc[1]);
-    acc[2] = fmaf(dw.y, t, acc[2]);
-    const float four_pi = 12.566370614359172f;
-    const float t2 = gp * nd.w;
-    acc[3] = fmaf(t2, Sa * fmaf(four_pi, ca, -Sa) * (Pb * Pc), acc[3]);
-    acc[4] = fmaf(t2, Sb * fmaf(four_pi, cb, -Sb) * (Pa * Pc), acc[4]);
-    acc[5] = fmaf(t2, Sc * fmaf(four_pi, cc, -Sc) * Pab, acc[5]);
+    if (LS == FDTBX_LINESHAPE_GAUSSIAN) {
+      const float P = __builtin_amdgcn_exp2f(kGauss * fmaf(ya, ya, fmaf(yb, yb, yc * yc)));
+      const float t = gp * P;
+      acc[0] = fmaf(nd.w, t, acc[0]);
+      acc[1] = fmaf(dw.x, t, acc[1]);
+      acc[2] = fmaf(dw.y, t, acc[2]);
+      const float t2 = nd.w * t;
+      const float m8pi = -25.132741228718345f;
+      acc[3] = fmaf(t2, fmaf(m8pi, ya * ya, 1.0f), acc[3]);
+      acc[4] = fmaf(t2, fmaf(m8pi, yb * yb, 1.0f), acc[4]);
+      acc[5] = fmaf(t2, fmaf(m8pi, yc * yc, 1.0f), acc[5]);
+    } else if (LS == FDTBX_LINESHAPE_HOSEMANN) {
+      const float ca = __builtin_amdgcn_cosf(ya), cb = __builtin_amdgcn_cosf(yb), cc = __builtin_amdgcn_cosf(yc);
+      const float da = fmaf(-hk.c1[0], ca, hk.c0[0]);
+      const float db = fmaf(-hk.c1[1], cb, hk.c0[1]);
+      const float dc = fmaf(-hk.c1[2], cc, hk.c0[2]);
+      const float dab = da * db;
+      const float P = __builtin_amdgcn_rcpf(dab * dc);
+      const float t = gp * P;
+      acc[0] = fmaf(nd.w, t, acc[0]);
+      acc[1] = fmaf(dw.x, t, acc[1]);
+      acc[2] = fmaf(dw.y, t, acc[2]);
+      // 1/den_a = P db dc, ...
+      const float t2 = nd.w * t * P;
+      acc[3] = fmaf(t2 * (db * dc), fmaf(ca, hk.e0[0], -hk.e1[0]), acc[3]);
+      acc[4] = fmaf(t2 * (da * dc), fmaf(cb, hk.e0[1], -hk.e1[1]), acc[4]);
+      acc[5] = fmaf(t2 * dab, fmaf(cc, hk.e0[2], -hk.e1[2]), acc[5]);
+    } else {
+      ya = fabsf(ya) + tiny;
+      yb = fabsf(yb) + tiny;
+      yc = fabsf(yc) + tiny;
+      const float sa = __builtin_amdgcn_sinf(ya), sb = __builtin_amdgcn_sinf(yb), sc = __builtin_amdgcn_sinf(yc);
+      const float ca = __builtin_amdgcn_cosf(ya), cb = __builtin_amdgcn_cosf(yb), cc = __builtin_amdgcn_cosf(yc);
+      const float yab = ya * yb;
+      const float inv = __builtin_amdgcn_rcpf(yab * yc);
+      const float Sa = sa * (inv * (yb * yc));
+      const float Sb = sb * (inv * (ya * yc));
+      const float Sc = sc * (inv * yab);
+      const float Pa = Sa * Sa, Pb = Sb * Sb, Pc = Sc * Sc;
+      const float Pab = Pa * Pb;
+      const float P = Pab * Pc;
+      const float t = gp * P;
+      acc[0] = fmaf(nd.w, t, acc[0]);
+      acc[1] = fmaf(dw.x, t, acc[1]);
+      acc[2] = fmaf(dw.y, t, acc[2]);
+      const float four_pi = 12.566370614359172f;
+      const float t2 = gp * nd.w;
+      acc[3] = fmaf(t2, Sa * fmaf(four_pi, ca, -Sa) * (Pb * Pc), acc[3]);
+      acc[4] = fmaf(t2, Sb * fmaf(four_pi, cb, -Sb) * (Pa * Pc), acc[4]);
+      acc[5] = fmaf(t2, Sc * fmaf(four_pi, cc, -Sc) * Pab, acc[5]);
+    }
   }
 }
 
 // Every lane walks the first cnt queue entries, reading entry jj + 1 before evaluating jj.
 // The queue addresses go through threadIdx.y (always 0) so that they stay in vector
 // registers and the unrolled reads use instruction offsets.
+template <int LS>
 __device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* qd, int cnt, const float* al, float gp,
-                                               float half_m, float tiny, float* acc) {
+                                               float half_m, float tiny, const HoseK& hk, float* acc) {
   qn += threadIdx.y;
   qd += threadIdx.y;
   float4 nxt = qn[0];
@@ -50,12 +91,13 @@ __device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* q
     const float2 cur2 = nxt2;
     nxt = qn[jj + 1];
     nxt2 = qd[jj + 1];
-    eval_node_adj(cur, cur2, al[0], al[1], al[2], gp, half_m, tiny, acc);
+    eval_node_adj<LS>(cur, cur2, al[0], al[1], al[2], gp, half_m, tiny, hk, acc);
   }
 }
 
 // One 8x8 tile t of one model, walked by one 64-lane wave.  qn, qd: LDS queue of 128 entries;
 // bq: LDS scratch of 64 ints for the block test.
+template <int LS>
 __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* __restrict__ refl, const float* __restrict__ nodes,
                                              const double* __restrict__ pix, const double* __restrict__ tile,
                                              const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
@@ -101,6 +143,8 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
     }
     Window w;
     if (!node_window(q, f, Rlo, Rhi, Zlo, Zhi, &w)) continue;
+    HoseK hk = {};
+    if (LS == FDTBX_LINESHAPE_HOSEMANN) hose_constants(refl + (int64_t)FDTBX_REFL_FLOATS * r, hk);
     float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     int qlen = 0;
     scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int k, float4 e) {
@@ -113,7 +157,7 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
       qlen += __popcll(b);
       __syncthreads();
       if (qlen >= 64) {
-        walk_queue_adj(qn, qd, 64, al, gp, q.half_m, q.tiny, acc);
+        walk_queue_adj<LS>(qn, qd, 64, al, gp, q.half_m, q.tiny, hk, acc);
         qlen -= 64;
         __syncthreads();
         if (lane < qlen) {
@@ -123,7 +167,7 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
         __syncthreads();
       }
     });
-    walk_queue_adj(qn, qd, qlen, al, gp, q.half_m, q.tiny, acc);
+    walk_queue_adj<LS>(qn, qd, qlen, al, gp, q.half_m, q.tiny, hk, acc);
     __syncthreads();
     bool any = false;
 #pragma unroll

@@ -64,6 +64,10 @@ int check_model(const fdtbx_model* m) {
     if (!(isfinite(d.g[i]) && d.g[i] >= 0.0 && d.g[i] < 1.0)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "g must be in [0, 1)");
   }
   if (d.intensity_model != 0 && d.intensity_model != 1) return fail(FDTBX_ERR_INVALID_ARGUMENT, "intensity_model must be 0 or 1");
+  if (d.lineshape < FDTBX_LINESHAPE_LAUE || d.lineshape > FDTBX_LINESHAPE_HOSEMANN)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "lineshape must be FDTBX_LINESHAPE_LAUE, _GAUSSIAN or _HOSEMANN");
+  for (int i = 0; i < 3; ++i)
+    if (!isfinite(d.B_axis[i])) return fail(FDTBX_ERR_INVALID_ARGUMENT, "B_axis must be finite");
   const fdtbx_quadrature& q = m->quad;
   if (q.n_nodes < 1 || q.n_nodes > 256) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_nodes must be in 1..256");
   if (!(q.T > 0.0 && q.T < 10.0)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "T must be in (0, 10)");

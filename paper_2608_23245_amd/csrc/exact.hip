@@ -297,8 +297,9 @@ __global__ void __launch_bounds__(64) k_pixel_map(PixParams q, double* pix, doub
 struct PrepParams {
   Frame f;
   double Nb[3], g[3];
+  double Bax[3];     // axis damping B_i
   double T, cmin, m, ext_limit;
-  int32_t intensity_model;
+  int32_t intensity_model, lineshape;
   int64_t n;
 };
 
@@ -350,8 +351,8 @@ __device__ static void refl_frame(const Frame& f, const double* hh, ReflFrame* F
 
 // Culling record (see the header): conservative reach of the reflection's profile in (R, Z).
 // Nodes s = r0 c (S + d1 e1 + d2 e2), |d_j| <= T, c in [cmin, 1]; query points lie in
-// the support box of a node, whose extent along v is sum_i (m/N_i)|a*_i.v| with
-// 1/N_i <= 1/N_base,i + min(pi^2 g_i^2 h_i^2, 1).
+// the support box of a node, whose extent along v is sum_i w_i |a*_i.v| with w_i = 1/2
+// (Hosemann lineshape) or w_i = m/N_i, 1/N_i <= 1/N_base,i + min(pi^2 g_i^2 h_i^2, 1).
 __device__ static void cull_record(const PrepParams& p, const double* hh, const ReflFrame& F, double* C) {
   const double* S = F.S;
   const double* e1 = F.e1;
@@ -362,7 +363,7 @@ __device__ static void cull_record(const PrepParams& p, const double* hh, const 
   double mN[3];
   for (int i = 0; i < 3; ++i) {
     double t = (kPi2 * (p.g[i] * p.g[i])) * (hh[i] * hh[i]);
-    mN[i] = p.m * (1.0 / p.Nb[i] + fmin(t, 1.0));
+    mN[i] = p.lineshape == FDTBX_LINESHAPE_HOSEMANN ? 0.5 : p.m * (1.0 / p.Nb[i] + fmin(t, 1.0));
   }
   auto ext = [&](const double* v) {
     double e = (mN[0] * fabs(dotv(&p.f.s[0], v)));
@@ -433,28 +434,40 @@ __device__ static void profile_record(const PrepParams& p, const double* hh, con
   const double* ep = F.ep;
   const double* D = F.D;
   const double r0 = F.r0;
-  double A[3], N[3], Ip = 1.0;
+  double A[3], N[3], Ip = 1.0, Dx = 0.0;
   for (int i = 0; i < 3; ++i) {
     A[i] = exp(-2.0 * kPi2 * (p.g[i] * p.g[i]) * (hh[i] * hh[i]));
     N[i] = 1.0 / (1.0 / p.Nb[i] + (1.0 - A[i]) / (1.0 + A[i]));
     if (p.intensity_model) Ip *= 2.0 * A[i] / (1.0 + A[i] * A[i]);
+    // axis damping: S.a_i/|a_i| = h_i/|a_i| at S = D_hkl
+    const double* ai = &p.f.a[3 * i];
+    Dx += p.Bax[i] * (hh[i] * hh[i]) / dotv(ai, ai);
   }
-  double W = f2 * Ip;
-  const double two_pi = 2.0 * M_PI;
-  double tp6 = two_pi * two_pi * two_pi;
-  tp6 = tp6 * tp6;
+  double W = f2 * Ip * exp(-0.25 * Dx);
+  // lineshape: per-reflection constant C and per-axis scale of y (see lineshape_half)
+  double C = 1.0, sc[3], AH[3] = {0.0, 0.0, 0.0};
+  for (int i = 0; i < 3; ++i) {
+    if (p.lineshape == FDTBX_LINESHAPE_HOSEMANN) {
+      AH[i] = N[i] > 1.0 ? (N[i] - 1.0) / (N[i] + 1.0) : 0.0;
+      C *= 1.0 - AH[i] * AH[i];
+      sc[i] = 1.0;
+    } else {
+      C *= p.lineshape == FDTBX_LINESHAPE_GAUSSIAN ? N[i] : N[i] / (4.0 * kPi2);
+      sc[i] = 0.5 * N[i];
+    }
+  }
   o[RS_W] = (float)W;
   for (int i = 0; i < 3; ++i) o[RS_N + i] = (float)N[i];
   o[RS_R0] = (float)r0;
-  o[RS_WK] = (float)(W * r0 * r0 * N[0] * N[1] * N[2] / tp6);
-  o[RS_K] = (float)(r0 * r0 * N[0] * N[1] * N[2] / tp6);
+  o[RS_WK] = (float)(W * r0 * r0 * C);
+  o[RS_K] = (float)(r0 * r0 * C);
   for (int i = 0; i < 3; ++i) {
     const double* ai = &p.f.a[3 * i];
-    o[RS_B + i] = (float)(0.5 * N[i] * r0 * dotv(ai, S));
-    o[RS_G1 + i] = (float)(0.5 * N[i] * r0 * dotv(ai, e1));
-    o[RS_G2 + i] = (float)(0.5 * N[i] * r0 * dotv(ai, e2));
-    o[RS_TR + i] = (float)(0.5 * N[i] * dotv(ai, ep));
-    o[RS_TZ + i] = (float)(0.5 * N[i] * ai[2]);
+    o[RS_B + i] = (float)(sc[i] * r0 * dotv(ai, S));
+    o[RS_G1 + i] = (float)(sc[i] * r0 * dotv(ai, e1));
+    o[RS_G2 + i] = (float)(sc[i] * r0 * dotv(ai, e2));
+    o[RS_TR + i] = (float)(sc[i] * dotv(ai, ep));
+    o[RS_TZ + i] = (float)(sc[i] * ai[2]);
   }
   o[RS_IP] = (float)Ip;
   double RDp = dotv(D, ep), ZD = D[2];
@@ -469,7 +482,10 @@ __device__ static void profile_record(const PrepParams& p, const double* hh, con
   const double* vs[3] = {S, e1, e2};
   for (int v = 0; v < 3; ++v) {
     double e = 0.0;
-    for (int i = 0; i < 3; ++i) e = e + (p.m / N[i]) * fabs(dotv(&p.f.s[3 * i], vs[v]));
+    for (int i = 0; i < 3; ++i) {
+      const double w = p.lineshape == FDTBX_LINESHAPE_HOSEMANN ? 0.5 : p.m / N[i];
+      e = e + w * fabs(dotv(&p.f.s[3 * i], vs[v]));
+    }
     o[RS_RHO + v] = (float)e;
   }
   for (int i = 0; i < 3; ++i) {
@@ -478,6 +494,7 @@ __device__ static void profile_record(const PrepParams& p, const double* hh, con
   }
   o[RS_F2] = (float)f2;
   for (int k = RS_K + 1; k < FDTBX_REFL_FLOATS; ++k) o[k] = 0.0f;
+  for (int i = 0; i < 3; ++i) o[RS_AH + i] = (float)AH[i];
 }
 
 __global__ void __launch_bounds__(256) k_prep(PrepParams p, const int32_t* __restrict__ hkl, const float* __restrict__ F2,
@@ -507,6 +524,8 @@ __device__ static void prep_params_of(const fdtbx_batch_entry& e, PrepParams* p)
   p->m = (double)e.model.quad.m;
   p->ext_limit = e.model.quad.extinction;
   p->intensity_model = e.model.dis.intensity_model;
+  p->lineshape = e.model.dis.lineshape;
+  for (int i = 0; i < 3; ++i) p->Bax[i] = e.model.dis.B_axis[i];
   p->n = e.n_hkl;
 }
 
@@ -685,6 +704,8 @@ extern "C" int fdtbx_reflection_prep(const fdtbx_model* model, const int32_t* hk
   p.m = (double)model->quad.m;
   p.ext_limit = model->quad.extinction;
   p.intensity_model = model->dis.intensity_model;
+  p.lineshape = model->dis.lineshape;
+  for (int i = 0; i < 3; ++i) p.Bax[i] = model->dis.B_axis[i];
   p.n = n_hkl;
   hipLaunchKernelGGL(k_prep, dim3((unsigned)ceil_div(n_hkl, 256)), dim3(256), 0, (hipStream_t)stream, p, hkl, F2, refl,
                      cull);

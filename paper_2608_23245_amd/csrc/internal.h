@@ -66,8 +66,18 @@ enum ReflSlot {
   RS_A = 35,       // coherence factors A_i (35..37)
   RS_H = 38,       // h, k, l as floats (38..40)
   RS_F2 = 41,      // |F|^2
-  RS_K = 42,       // r0^2 N_a N_b N_c / (2 pi)^6, so that RS_WK = W * RS_K
+  RS_K = 42,       // r0^2 C with C the lineshape's constant (Laue prod N/(2 pi)^6, Gaussian
+                   // prod N, Hosemann prod (1 - A'^2)), so that RS_WK = W * RS_K
+  RS_AH = 44,      // Hosemann lineshape: A'_i = max(0, (N_i - 1)/(N_i + 1)) (44..46)
 };
+
+// Per-axis scale of the lattice offsets y_i in the record (y_i = scale_i a_i.(p - s)) and
+// the support half-width in y: N_i/2 and m/2 for the Laue and Gaussian lineshapes (the
+// sines and the Gaussian take y in turns of half the Laue argument), 1 and 1/2 for the
+// Hosemann lineshape (y = u, one lattice period).
+__host__ __device__ inline double lineshape_half(int32_t lineshape, int32_t m) {
+  return lineshape == FDTBX_LINESHAPE_HOSEMANN ? 0.5 : 0.5 * (double)m;
+}
 
 // Batched launchers (one per translation unit that owns the kernels).
 int launch_batch_sf(const fdtbx_batch_entry* ent, const int64_t* blocks, int64_t n_rb, const float* x, const float* y,

@@ -1,6 +1,7 @@
 // Profile pattern: per pixel, the sum over the reflections of its tile list of
-// W_hkl r0^2 sum_k omega_k Z(p* - s_k) (Eq. direct_sum with Eq. I_shape and
-// N -> N_eff), times the Lorentz factor delta/(R + delta) (Eq. lorentz).
+// W_hkl r0^2 sum_k omega_k Z(p* - s_k) (Eq. direct_sum with the lineshape's per-axis
+// profile: Eq. I_shape with N -> N_eff, or its Gaussian or Hosemann (Eq. Z) form of the
+// same integral breadth), times the Lorentz factor delta/(R + delta) (Eq. lorentz).
 //
 // Mapping: one 64-lane wave per 8x8 pixel tile, one lane per pixel, pixel sums in
 // registers.  Reflections of the tile list are uniform across the wave (their
@@ -15,7 +16,9 @@
 //   alpha_i = (N_i/2) [(R - R_D)(a_i.e_perp) + (Z - Z_D) a_i,z]           (per pixel)
 //   kappa_ik = (N_i r0/2) [(c_k - 1) a_i.S + c_k d1 a_i.e1 + c_k d2 a_i.e2] (per node),
 // so that N_i sinc^2(N_i u_i) = N_i sin^2(2 pi y_i)/(2 pi y_i)^2 with the hardware
-// sine taking its argument in turns.  Support: max_i |y_i| <= m/2.
+// sine taking its argument in turns.  Support: max_i |y_i| <= m/2.  The Gaussian
+// lineshape uses the same y (N exp(-pi N^2 u^2) = N exp(-4 pi y^2)); the Hosemann one
+// writes the record with scale 1 instead of N_i/2 (y_i = u_i, support |y_i| <= 1/2).
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -26,7 +29,8 @@
 
 namespace fdtbx {
 
-template <bool COUNT>
+// COUNT: counting pass (support test only, the same for every lineshape); LS: lineshape.
+template <bool COUNT, int LS>
 __global__ void __launch_bounds__(64) k_profile(ProfParams q, const float* __restrict__ refl, const float* __restrict__ nodes,
                                                 const double* __restrict__ pix, const double* __restrict__ tile,
                                                 const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
@@ -34,7 +38,7 @@ __global__ void __launch_bounds__(64) k_profile(ProfParams q, const float* __res
   // queue of window nodes that can be inside the support of some pixel of the tile
   __shared__ float4 qn[128];
   __shared__ int bq[64];
-  profile_tile<COUNT>(q, refl, nodes, pix, tile, offsets, idx, image, counts, blockIdx.x, qn, bq);
+  profile_tile<COUNT, LS>(q, refl, nodes, pix, tile, offsets, idx, image, counts, blockIdx.x, qn, bq);
 }
 
 // Batched models, persistent: every wave takes (model, tile) items from a shared counter
@@ -56,9 +60,23 @@ __global__ void __launch_bounds__(64) k_b_profile(const fdtbx_batch_entry* __res
     const fdtbx_batch_entry& e = ent[m];
     ProfParams q;
     prof_params(&e.model, &q);
-    profile_tile<false>(q, refl + (int64_t)FDTBX_REFL_FLOATS * e.hkl_off, nodes + (int64_t)FDTBX_NODE_FLOATS * e.node_off,
-                        pix + 2 * e.pix_off, tile + 8 * e.tile_off, rowptr + e.rowptr_off, idx + e.pair_off,
-                        image + e.pix_off, nullptr, t, qn, bq);
+    const float* rf = refl + (int64_t)FDTBX_REFL_FLOATS * e.hkl_off;
+    const float* nd = nodes + (int64_t)FDTBX_NODE_FLOATS * e.node_off;
+    const double* px = pix + 2 * e.pix_off;
+    const double* tb = tile + 8 * e.tile_off;
+    const int64_t* rp = rowptr + e.rowptr_off;
+    const int32_t* ix = idx + e.pair_off;
+    float* im = image + e.pix_off;
+    switch (q.lineshape) {  // uniform across the wave
+      case FDTBX_LINESHAPE_GAUSSIAN:
+        profile_tile<false, FDTBX_LINESHAPE_GAUSSIAN>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
+        break;
+      case FDTBX_LINESHAPE_HOSEMANN:
+        profile_tile<false, FDTBX_LINESHAPE_HOSEMANN>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
+        break;
+      default:
+        profile_tile<false, FDTBX_LINESHAPE_LAUE>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
+    }
   }
 }
 
@@ -96,12 +114,19 @@ extern "C" int fdtbx_profile(const fdtbx_model* model, const float* refl, const 
   prof_params(model, &q);
   int64_t n_tiles = (int64_t)q.tiles_x * q.tiles_y;
   hipStream_t s = (hipStream_t)stream;
+  const dim3 grid((unsigned)n_tiles);
   if (counts) {
-    hipLaunchKernelGGL(k_profile<true>, dim3((unsigned)n_tiles), dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
+    hipLaunchKernelGGL((k_profile<true, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
                        image, (unsigned long long*)counts);
+  } else if (q.lineshape == FDTBX_LINESHAPE_GAUSSIAN) {
+    hipLaunchKernelGGL((k_profile<false, FDTBX_LINESHAPE_GAUSSIAN>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets,
+                       idx, image, (unsigned long long*)nullptr);
+  } else if (q.lineshape == FDTBX_LINESHAPE_HOSEMANN) {
+    hipLaunchKernelGGL((k_profile<false, FDTBX_LINESHAPE_HOSEMANN>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets,
+                       idx, image, (unsigned long long*)nullptr);
   } else {
-    hipLaunchKernelGGL(k_profile<false>, dim3((unsigned)n_tiles), dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
-                       image, (unsigned long long*)nullptr);
+    hipLaunchKernelGGL((k_profile<false, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets,
+                       idx, image, (unsigned long long*)nullptr);
   }
   FDTBX_LAUNCH_CHECK("profile");
   return FDTBX_OK;

@@ -12,9 +12,10 @@ namespace fdtbx {
 
 struct ProfParams {
   int32_t W, H, tiles_x, tiles_y;
+  int32_t lineshape;
   int32_t n;        // nodes per side
   float T, inv_h;   // grid half extent, 1/spacing
-  float half_m;     // m/2
+  float half_m;     // support half-width in y (lineshape_half)
   float cmin;       // (1 + 2T^2)^(-1/2)
   float tiny;       // added to |y|: keeps sin(2 pi y)/y finite at y = 0, exact in float32 for |y| > 1e-5
   float margin;     // slack of the tile-level node test, in y units
@@ -229,7 +230,8 @@ __host__ __device__ inline void prof_params(const fdtbx_model* model, ProfParams
   q->n = model->quad.n_nodes;
   q->T = (float)model->quad.T;
   q->inv_h = (float)(model->quad.n_nodes / (2.0 * model->quad.T));
-  q->half_m = 0.5f * (float)model->quad.m;
+  q->lineshape = model->dis.lineshape;
+  q->half_m = (float)lineshape_half(model->dis.lineshape, model->quad.m);
   q->cmin = (float)(1.0 / sqrt(1.0 + 2.0 * model->quad.T * model->quad.T));
   q->tiny = 1.0e-12f;
   q->margin = 1.0e-3f;

@@ -6,16 +6,51 @@
 
 namespace fdtbx {
 
-// Per-lane evaluation of one queued node: returns omega * (prod_i sin(2 pi y_i)/y_i)^2 if the
-// node is inside this pixel's support, else 0 (and counts it in COUNT mode).
-template <bool COUNT>
+// Per-pair constants of the Hosemann lineshape: den_i = c0_i - c1_i cos(2 pi y_i) with
+// c0 = 1 + A'^2, c1 = 2 A'; e0, e1: the same times 0 or 1 (0 where A' is held at 0), for the
+// N-derivative of the adjoint.
+struct HoseK {
+  float c0[3], c1[3], e0[3], e1[3];
+};
+
+__device__ __forceinline__ void hose_constants(const float* rec, HoseK& h) {
+  const float4 a = *(const float4*)(rec + RS_AH);
+  const float A[3] = {a.x, a.y, a.z};
+#pragma unroll
+  for (int i = 0; i < 3; ++i) {
+    h.c0[i] = fmaf(A[i], A[i], 1.0f);
+    h.c1[i] = 2.0f * A[i];
+    const float q = A[i] > 0.0f ? 1.0f : 0.0f;
+    h.e0[i] = q * h.c0[i];
+    h.e1[i] = q * h.c1[i];
+  }
+}
+
+// exp(-4 pi s) = exp2(kGauss s)
+constexpr float kGauss = -18.129440567308775f;
+
+// Per-lane evaluation of one queued node: returns omega times the lineshape's profile
+// product (without its per-reflection constant) if the node is inside this pixel's support,
+// else 0 (and counts it in COUNT mode).
+//   Laue:     (prod_i sin(2 pi y_i)/y_i)^2      (y_i = N_i u_i/2)
+//   Gaussian: exp(-4 pi sum_i y_i^2)            (y_i = N_i u_i/2)
+//   Hosemann: 1/prod_i (c0_i - c1_i cos(2 pi y_i))   (y_i = u_i)
+template <bool COUNT, int LS>
 __device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1, float al2, float half_m, float tiny,
-                                          float& accr, unsigned long long& cnt) {
+                                          const HoseK& hk, float& accr, unsigned long long& cnt) {
   float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
   float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
   if (mx <= half_m) {
     if (COUNT) {
       ++cnt;
+    } else if (LS == FDTBX_LINESHAPE_GAUSSIAN) {
+      const float s2 = fmaf(ya, ya, fmaf(yb, yb, yc * yc));
+      accr = fmaf(nd.w, __builtin_amdgcn_exp2f(kGauss * s2), accr);
+    } else if (LS == FDTBX_LINESHAPE_HOSEMANN) {
+      const float da = fmaf(-hk.c1[0], __builtin_amdgcn_cosf(ya), hk.c0[0]);
+      const float db = fmaf(-hk.c1[1], __builtin_amdgcn_cosf(yb), hk.c0[1]);
+      const float dc = fmaf(-hk.c1[2], __builtin_amdgcn_cosf(yc), hk.c0[2]);
+      accr = fmaf(nd.w, __builtin_amdgcn_rcpf(da * db * dc), accr);
     } else {
       ya = fabsf(ya) + tiny;
       yb = fabsf(yb) + tiny;
@@ -34,19 +69,19 @@ __device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1,
 // The queue is addressed from threadIdx.y (always 0: the launches are one-dimensional), which
 // keeps its address in a vector register; the unrolled reads then use instruction offsets
 // instead of moving a scalar loop counter into a vector register for every entry.
-template <bool COUNT>
-__device__ __forceinline__ void walk_queue(const float4* qn, int cnt, const float* al, float half_m, float tiny, float& accr,
-                                           unsigned long long& cnt_eval) {
+template <bool COUNT, int LS>
+__device__ __forceinline__ void walk_queue(const float4* qn, int cnt, const float* al, float half_m, float tiny,
+                                           const HoseK& hk, float& accr, unsigned long long& cnt_eval) {
   qn += threadIdx.y;
   float4 nxt = qn[0];
   for (int jj = 0; jj < cnt; ++jj) {
     const float4 cur = nxt;
     nxt = qn[jj + 1];
-    eval_node<COUNT>(cur, al[0], al[1], al[2], half_m, tiny, accr, cnt_eval);
+    eval_node<COUNT, LS>(cur, al[0], al[1], al[2], half_m, tiny, hk, accr, cnt_eval);
   }
 }
 
-template <bool COUNT>
+template <bool COUNT, int LS>
 __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* __restrict__ refl,
                                              const float* __restrict__ nodes, const double* __restrict__ pix,
                                              const double* __restrict__ tile, const int64_t* __restrict__ offsets,
@@ -94,6 +129,8 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
     }
     Window w;
     if (!node_window(q, f, Rlo, Rhi, Zlo, Zhi, &w)) continue;
+    HoseK hk = {};
+    if (LS == FDTBX_LINESHAPE_HOSEMANN && !COUNT) hose_constants(refl + (int64_t)FDTBX_REFL_FLOATS * r, hk);
     float accr = 0.0f;
     int qlen = 0;  // uniform
     // candidates go to the LDS queue; every 64 queued nodes are walked by all lanes
@@ -106,14 +143,14 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
       qlen += __popcll(b);
       __syncthreads();
       if (qlen >= 64) {
-        walk_queue<COUNT>(qn, 64, al, q.half_m, tiny, accr, cnt);
+        walk_queue<COUNT, LS>(qn, 64, al, q.half_m, tiny, hk, accr, cnt);
         qlen -= 64;
         __syncthreads();
         if (lane < qlen) qn[lane] = qn[64 + lane];
         __syncthreads();
       }
     });
-    walk_queue<COUNT>(qn, qlen, al, q.half_m, tiny, accr, cnt);
+    walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, tiny, hk, accr, cnt);
     __syncthreads();
     if (!COUNT) acc = fmaf(f.at(RS_WK), accr, acc);
   }

@@ -99,3 +99,21 @@ def test_node_rows(lib):
     for n, rows in ((1, 2), (4, 17), (10, 109), (64, 4096 + 256), (96, 9216 + 576), (256, 65536 + 4096)):
         assert lib.fdtbx_node_rows(n) == rows == B.node_rows(n)
     assert lib.fdtbx_node_rows(0) == 0 and lib.fdtbx_node_rows(257) == 0
+
+
+def test_struct_layouts_match_binding(lib):
+    """The ctypes mirrors of the ABI structs have the library's sizes, and host checks
+    reject a lineshape outside the three defined and a non-finite damping."""
+    import workloads as W
+    from paper_2608_23245_amd import binding as B
+    assert lib.fdtbx_batch_entry_size() == ctypes.sizeof(B.BatchEntry)
+    assert B.N_GLOBALS == 11 and B.LINESHAPES == W.LINESHAPES
+    wl = W.config0()
+    for ls, ok in ((0, True), (1, True), (2, True), (3, False), (-1, False)):
+        m = B.make_model(wl)
+        m.dis.lineshape = ls
+        assert (lib.fdtbx_pattern_workspace(ctypes.byref(m), 150, 1000) > 0) == ok, ls
+    m = B.make_model(wl)
+    m.dis.B_axis[1] = float("inf")
+    assert lib.fdtbx_pattern_workspace(ctypes.byref(m), 150, 1000) == 0
+

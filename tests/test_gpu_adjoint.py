@@ -59,6 +59,12 @@ CASES = {
                                g=(0.03, 0.03, 0.0)),
     "tilted": dict(seed=46, width=18, height=20, sigma_theta=2 * DEG, gamma_theta=1 * DEG, g=(0.02, 0.02, 0.0),
                    tilt=30 * DEG),
+    "gaussian_damped": dict(seed=47, width=18, height=16, sigma_theta=2 * DEG, gamma_theta=1 * DEG, g=(0.02, 0.03, 0.01),
+                            lineshape=1, B_axis=(4.0, 9.0, 2.5)),
+    "hosemann_damped": dict(seed=48, width=17, height=19, sigma_theta=3 * DEG, gamma_theta=0.0, g=(0.03, 0.02, 0.01),
+                            lineshape=2, B_axis=(6.0, 1.0, 3.0)),
+    "hosemann_small_n": dict(seed=49, width=16, height=16, sigma_theta=2 * DEG, gamma_theta=2 * DEG, g=(0.1, 0.02, 0.0),
+                             lineshape=2, size_A=(12.0, 60.0, 50.0)),
 }
 
 
@@ -76,7 +82,7 @@ def test_adjoint_small_vs_oracle(name):
     for k in ("x", "y", "z", "B", "occ"):
         check_group(k, ga[k], ref["atoms"][k])
     names = B.GLOBAL_NAMES
-    refg = [ref["sigma_theta"], ref["gamma_theta"], *ref["N_base"], *ref["g"]]
+    refg = [ref["sigma_theta"], ref["gamma_theta"], *ref["N_base"], *ref["g"], *ref["B_axis"]]
     for i, n in enumerate(names):
         if ("g_" in n and wl.dis.g[i - 5] == 0.0):
             continue  # dA/dg vanishes at g = 0 on both sides; compared below as zero
@@ -113,7 +119,7 @@ def test_adjoint_medium_model_on_a_detector_crop():
     ref = O.gradients(wl, P, G)
     for k in ("x", "y", "z", "B", "occ"):
         check_group(k, ga[k], ref["atoms"][k])
-    refg = [ref["sigma_theta"], ref["gamma_theta"], *ref["N_base"], *ref["g"]]
+    refg = [ref["sigma_theta"], ref["gamma_theta"], *ref["N_base"], *ref["g"], *ref["B_axis"]]
     for i, n in enumerate(B.GLOBAL_NAMES):
         if n == "g_c":
             continue  # g_c = 0 in this model
@@ -187,3 +193,4 @@ def test_autograd_module_chain_rule():
     edges = np.array([wl.cell.a, wl.cell.b, wl.cell.c])
     check_group("size", model.size.grad.numpy(), ref["N_base"] / edges)
     check_group("g_ab", model.g.grad.numpy()[:2], ref["g"][:2])
+    check_group("B_axis", model.B_axis.grad.numpy(), ref["B_axis"])

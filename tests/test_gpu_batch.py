@@ -36,10 +36,11 @@ def small_batch():
         W.small(62, n_atoms=15, width=17, height=29, sigma_theta=0.0, gamma_theta=2 * DEG, n_nodes=20,
                 cell=W.Cell(8.0, 12.0, 10.0, 90 * DEG, 104 * DEG, 90 * DEG), center=(5.2, 14.7)),
         W.small(63, n_atoms=60, width=32, height=32, sigma_theta=4 * DEG, gamma_theta=0.0, g=(0.03, 0.0, 0.01),
-                n_nodes=16, d_min=4.0),
+                n_nodes=16, d_min=4.0, lineshape=1, B_axis=(3.0, 5.0, 1.0)),
         W.small(64, n_atoms=25, width=9, height=40, sigma_theta=2 * DEG, gamma_theta=2 * DEG, center=(-6.0, 20.0)),
         W.small(65, n_atoms=33, width=27, height=11, sigma_theta=5 * DEG, gamma_theta=0.5 * DEG, n_nodes=10,
-                cell=W.Cell(11.0, 9.5, 12.5, 95 * DEG, 90 * DEG, 100 * DEG)),
+                cell=W.Cell(11.0, 9.5, 12.5, 95 * DEG, 90 * DEG, 100 * DEG), lineshape=2, g=(0.02, 0.01, 0.0),
+                tilt=15 * DEG),
     ]
 
 
@@ -109,15 +110,16 @@ def test_batch_set_globals_in_place():
     glob[0, 0] *= 1.3          # sigma_theta of model 0
     glob[2, 5] = 0.02          # g_a of model 2
     glob[3, 3] *= 0.8          # N_base_b of model 3
+    glob[4, 9] = 4.0           # B_b of model 4
     be.set_globals(glob)
     be.forward()
     torch.cuda.synchronize()
     import copy
-    for m in (0, 2, 3):
+    for m in (0, 2, 3, 4):
         wl = copy.deepcopy(wls[m])
         g = glob[m].cpu().tolist()
         wl.dis.sigma_theta, wl.dis.gamma_theta = g[0], g[1]
-        wl.dis.N_base, wl.dis.g = tuple(g[2:5]), tuple(g[5:8])
+        wl.dis.N_base, wl.dis.g, wl.dis.B_axis = tuple(g[2:5]), tuple(g[5:8]), tuple(g[8:11])
         # the batch keeps its reflection list (extinction cull of the initial g)
         eng = AG.PatternEngine(wls[m])
         eng.set_globals(g)

@@ -60,6 +60,12 @@ SMALL = {
     "tilted": dict(seed=27, width=26, height=22, center=(13.0, 9.4), tilt=22 * DEG, sigma_theta=2 * DEG,
                    gamma_theta=1 * DEG),
     "tilted_back": dict(seed=28, width=19, height=25, tilt=-40 * DEG, g=(0.03, 0.03, 0.0)),
+    "gaussian_damped": dict(seed=29, width=22, height=20, sigma_theta=2 * DEG, gamma_theta=1 * DEG,
+                            g=(0.03, 0.02, 0.01), lineshape=1, B_axis=(4.0, 9.0, 2.5)),
+    "hosemann": dict(seed=30, width=23, height=21, sigma_theta=3 * DEG, g=(0.03, 0.02, 0.01), lineshape=2),
+    "hosemann_small_n": dict(seed=31, width=18, height=18, sigma_theta=2 * DEG, gamma_theta=2 * DEG,
+                             g=(0.1, 0.02, 0.0), lineshape=2, size_A=(12.0, 60.0, 50.0), B_axis=(2.0, 2.0, 8.0)),
+    "no_intensity_model": dict(seed=32, width=20, height=17, g=(0.04, 0.04, 0.0), intensity_model=0),
 }
 
 
@@ -292,6 +298,16 @@ def test_pattern_tilted_medium_sampled():
     say("pattern medium, fibre tilt 22 deg, 48 sampled pixels")
     got, ref = _sampled(wl, 48, seed=11)
     check_pattern(got, ref, "medium tilted sampled")
+
+
+@pytest.mark.parametrize("lineshape", ["gaussian", "hosemann"])
+def test_pattern_lineshapes_medium_sampled(lineshape):
+    """The medium workload with the Gaussian or Hosemann lineshape and axis damping
+    B = (10, 10, 10) A^2 (the tutorial's values), full size, oracle at sampled pixels."""
+    wl = W.with_disorder(W.config1(), lineshape=W.LINESHAPES[lineshape], B_axis=(10.0, 10.0, 10.0))
+    say(f"pattern medium, {lineshape} lineshape, damping, 48 sampled pixels")
+    got, ref = _sampled(wl, 48, seed=12)
+    check_pattern(got, ref, f"medium {lineshape} sampled")
 
 
 @pytest.mark.parametrize("cfg,n_pix", [(1, 48), (2, 16)])

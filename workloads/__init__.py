@@ -259,7 +259,8 @@ def small(seed: int, n_atoms: int = 24, width: int = 24, height: int = 20,
           cell: Optional[Cell] = None, sigma_theta: float = 4 * DEG, gamma_theta: float = 0.0,
           g=(0.0, 0.0, 0.0), n_nodes: int = 12, d_min: float = 5.0,
           size_A=(60.0, 60.0, 80.0), distance: float = 60.0, pixel: float = 0.8,
-          center=None, tilt: float = 0.0) -> Workload:
+          center=None, tilt: float = 0.0, lineshape: int = 0, B_axis=(0.0, 0.0, 0.0),
+          intensity_model: int = 1) -> Workload:
     """Tiny seeded workload for oracle pins and parity edge cases (ragged detector
     sizes, off-centre beams, skewed cells)."""
     rng = np.random.default_rng(seed)
@@ -272,7 +273,7 @@ def small(seed: int, n_atoms: int = 24, width: int = 24, height: int = 20,
     return Workload(
         f"small seed {seed}", cell,
         Geometry(1.0, distance, pixel, width, height, float(center[0]), float(center[1]), float(tilt)),
-        Disorder(sigma_theta, gamma_theta, N, tuple(g)),
+        Disorder(sigma_theta, gamma_theta, N, tuple(g), intensity_model, lineshape, tuple(B_axis)),
         Quadrature(n_nodes, extent_T(sigma_theta, gamma_theta), d_min=d_min), atoms)
 
 
