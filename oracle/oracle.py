@@ -582,7 +582,89 @@ def gradients(wl, P: Prepared, G, R=None, Z=None, use_skip=True):
             "B_axis": d_B, "dW": dW, "sums": sums}
 
 
+# --------------------------------------------------------------------------- forward splat
+class _SplatParams(ctypes.Structure):
+    _fields_ = [("lambda_", ctypes.c_double), ("SF", ctypes.c_double), ("pixel", ctypes.c_double),
+                ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("st", ctypes.c_double), ("ct", ctypes.c_double),
+                ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("n_r", ctypes.c_int32), ("n_s", ctypes.c_int32),
+                ("dr", ctypes.c_void_p), ("Ts", ctypes.c_void_p)]
+
+
+def splat_extents(wl, hkl):
+    """Per reflection, the sampling box of the forward splat: radial half-extent dr and
+    tangent-plane half-extent Ts.  dr = sum_i w_i |a*_i| is the corner radius of the support
+    box, with w_i the culling contract's bound on the support half-width (m/N_i bounded
+    without transcendentals, or 1/2 for the Hosemann lineshape); Ts = min(T + 2 dr/r0, 10)
+    widens the node patch by the support.  +, -, *, /, sqrt only, in a fixed order."""
+    _, astar, _ = frame(wl.cell)
+    D = recip_vectors(hkl, astar)
+    r0 = np.sqrt((D[:, 0] * D[:, 0] + D[:, 1] * D[:, 1]) + D[:, 2] * D[:, 2])
+    rb_w = _support_bounds(wl, hkl)
+    dr = rb_w[:, 0] * math.sqrt((astar[0, 0] * astar[0, 0] + astar[0, 1] * astar[0, 1]) + astar[0, 2] * astar[0, 2])
+    dr = dr + rb_w[:, 1] * math.sqrt((astar[1, 0] * astar[1, 0] + astar[1, 1] * astar[1, 1]) + astar[1, 2] * astar[1, 2])
+    dr = dr + rb_w[:, 2] * math.sqrt((astar[2, 0] * astar[2, 0] + astar[2, 1] * astar[2, 1]) + astar[2, 2] * astar[2, 2])
+    Ts = np.minimum(wl.quad.T + 2.0 * dr / r0, 10.0)
+    return dr, Ts
+
+
+def splat(wl, P: Prepared, n_r, n_s, count=False):
+    """Deterministic forward splat of every reflection of P onto the detector (see
+    oracle_splat): image [H][W] of sum over samples of W I(S) L(R_S) dV, deposited at both
+    diffraction-condition rotations of each sample."""
+    g = wl.geom
+    dr, Ts = splat_extents(wl, P.hkl)
+    dr = np.ascontiguousarray(dr)
+    Ts = np.ascontiguousarray(Ts)
+    tilt = float(getattr(g, "tilt", 0.0))
+    sp = _SplatParams(g.wavelength, g.distance, g.pixel, g.center_x, g.center_y, math.sin(tilt), math.cos(tilt),
+                      g.width, g.height, int(n_r), int(n_s), dr.ctypes.data, Ts.ctypes.data)
+    img = np.zeros(g.width * g.height)
+    n_ev = ctypes.c_int64(0)
+    prob, keep = _c_problem(P, False)
+    _c().oracle_splat(ctypes.byref(prob), ctypes.byref(sp), ctypes.c_void_p(img.ctypes.data), ctypes.byref(n_ev))
+    del keep
+    img = img.reshape(g.height, g.width)
+    return (img, int(n_ev.value)) if count else img
+
+
+def splat_project(S, geom):
+    """Detector pixels (column, row; fractional, pixel centres at integer + 1/2 from the
+    pixel's lower edge) of the two diffraction-condition rotations of fibre-frame points S,
+    by the algebraic form used by the splat (see oracle_splat); NaN where none exists."""
+    S = np.atleast_2d(np.asarray(S, dtype=np.float64))
+    tilt = float(getattr(geom, "tilt", 0.0))
+    st, ct = math.sin(tilt), math.cos(tilt)
+    q = (S[:, 0] * S[:, 0] + S[:, 1] * S[:, 1]) + S[:, 2] * S[:, 2]
+    sx = -(geom.wavelength * q) / 2.0
+    sz = (S[:, 2] - sx * st) / ct
+    sy2 = (q - sx * sx) - sz * sz
+    with np.errstate(invalid="ignore"):
+        sy = np.where(sy2 >= 0.0, np.sqrt(sy2), np.nan)
+    kx = 1.0 / geom.wavelength + sx
+    out = []
+    for sgn in (1.0, -1.0):
+        y = geom.distance * (sgn * sy) / kx
+        z = geom.distance * sz / kx
+        out.append(np.stack([y / geom.pixel + geom.center_x, z / geom.pixel + geom.center_y], axis=1))
+    return out[0], out[1]
+
+
 # --------------------------------------------------------------------------- culling contract
+def _support_bounds(wl, hkl):
+    """Per reflection and axis, the culling contract's upper bound on the support half-width
+    in u: m (1/N_base + min(pi^2 g^2 h^2, 1)), or 1/2 for the Hosemann lineshape."""
+    h = hkl.astype(np.float64)
+    m = float(wl.quad.m)
+    mN = np.empty((hkl.shape[0], 3))
+    for i in range(3):
+        g = wl.dis.g[i]
+        t = PI2 * (g * g) * (h[:, i] * h[:, i])
+        mN[:, i] = m * (1.0 / wl.dis.N_base[i] + np.minimum(t, 1.0))
+    if getattr(wl.dis, "lineshape", 0) == 2:
+        mN[:] = 0.5
+    return mN
+
+
 def tile_boxes(geom, tile_w=8, tile_h=8):
     """Per tile of tile_w x tile_h pixels (clipped at the detector edge), the ranges
     of R, Z and R^2 + Z^2 over its pixel centres: [n_tiles_y][n_tiles_x][6] =
@@ -624,15 +706,8 @@ def reflection_boxes(wl, hkl):
     T = wl.quad.T
     m = float(wl.quad.m)
     cmin = 1.0 / math.sqrt(1.0 + 2.0 * T * T)
-    h = hkl.astype(np.float64)
     n = hkl.shape[0]
-    mN = np.empty((n, 3))
-    for i in range(3):
-        g = wl.dis.g[i]
-        t = PI2 * (g * g) * (h[:, i] * h[:, i])
-        mN[:, i] = m * (1.0 / wl.dis.N_base[i] + np.minimum(t, 1.0))
-    if getattr(wl.dis, "lineshape", 0) == 2:
-        mN[:] = 0.5
+    mN = _support_bounds(wl, hkl)
     ez = np.zeros_like(ep)
     ez[:, 2] = 1.0
 

@@ -10,6 +10,7 @@
  *
  *   oracle_pattern   -- the detector image at a list of pixels
  *   oracle_grad      -- the adjoint of that image for a weighted residual
+ *   oracle_splat     -- the forward splat of sampled shell points onto the detector
  *
  * Both follow the section "Numerical evaluation: per-reflection shell
  * quadrature" (Eqs. I_shape, gnomonic, node_weight, direct_sum; Eqs. Z and
@@ -21,6 +22,7 @@
 #include <math.h>
 #include <stdint.h>
 #include <stddef.h>
+#include <stdlib.h>
 
 #ifndef M_PI
 #define M_PI 3.14159265358979323846
@@ -307,6 +309,101 @@ void oracle_structure_factors(int64_t n_hkl, const int32_t* hkl, const double* s
     F_re[r] = re;
     F_im[r] = im;
   }
+}
+
+/* Deterministic forward splat (section "Numerical evaluation: per-reflection shell quadrature":
+ * each reflection is sampled on its shell in (r, d1, d2) and every sample is projected onto
+ * the detector; section "Lorentz correction on a sampled reciprocal lattice"; section
+ * "Analytical Solution of the Ewald Diffraction Condition").  For reflection h, samples
+ *   r_a  = r0 - dr + (a + 1/2)(2 dr/n_r),            a = 0..n_r-1
+ *   d_b  = -Ts + (b + 1/2)(2 Ts/n_s),                 b = 0..n_s-1 (both tangent axes)
+ *   S    = (r c) ((S0 + d1 e1) + d2 e2),  c = 1/sqrt((1 + d1 d1) + d2 d2)   (Eq. gnomonic)
+ *   dV   = r^2 (2 dr/n_r) c^3 (2 Ts/n_s)^2
+ *   w    = W_h I_h(S) L(R_S) dV,  L = delta/(R_S + delta)  (Eqs. direct_sum, lorentz)
+ * with dr and Ts per reflection (sp_dr, sp_Ts) and R_S = |S_xy|, Z_S = S_z about the fibre.
+ * Both rotations about the fibre axis that bring S onto the Ewald sphere (Eqs. harmonic,
+ * solutions) receive w: in the laboratory, with the fibre axis n = (sin t, 0, cos t) and
+ * k_in = x/lambda, those are the points with cylindrical coordinates (R_S, Z_S) about n on
+ * the sphere:  S_x = -lambda |S|^2/2,  S_z = (Z_S - S_x sin t)/cos t,
+ * S_y = +-sqrt(|S|^2 - S_x^2 - S_z^2) (none if negative); k_out = (1/lambda + S_x, S_y, S_z)
+ * meets the detector plane at y = SF k_y/k_x, z = SF k_z/k_x (k_x > 0), in pixel
+ * (floor(y/p + c_x), floor(z/p + c_y)).  Binary64, no fused multiply-add. */
+typedef struct {
+  double lambda, SF, pixel, cx, cy, st, ct;
+  int32_t width, height;
+  int32_t n_r, n_s;
+  const double* dr;   /* [n_hkl] radial half-extent */
+  const double* Ts;   /* [n_hkl] tangent-plane half-extent */
+} oracle_splat_params;
+
+/* One sample's two detector pixels (index j*W + i, or -1 when the projection misses). */
+static void splat_pixels(const oracle_splat_params* sp, const double* S, int64_t* out) {
+  out[0] = out[1] = -1;
+  double q = (S[0] * S[0] + S[1] * S[1]) + S[2] * S[2];
+  double RS2 = S[0] * S[0] + S[1] * S[1];
+  double ZS = S[2];
+  (void)RS2;
+  double sx = -(sp->lambda * q) / 2.0;
+  double sz = (ZS - sx * sp->st) / sp->ct;
+  double sy2 = (q - sx * sx) - sz * sz;
+  if (!(sy2 >= 0.0)) return;
+  double sy = sqrt(sy2);
+  double kx = 1.0 / sp->lambda + sx;
+  if (!(kx > 0.0)) return;
+  for (int b = 0; b < 2; ++b) {
+    double ky = b == 0 ? sy : -sy;
+    double y = sp->SF * ky / kx, z = sp->SF * sz / kx;
+    double fi = floor(y / sp->pixel + sp->cx), fj = floor(z / sp->pixel + sp->cy);
+    if (fi >= 0.0 && fi < (double)sp->width && fj >= 0.0 && fj < (double)sp->height)
+      out[b] = (int64_t)fj * sp->width + (int64_t)fi;
+  }
+}
+
+/* image[height*width] (zeroed by the caller) += the deposits of every sample of every
+ * reflection; n_evals (optional) receives the (sample, node) pairs inside the support. */
+void oracle_splat(const oracle_problem* P, const oracle_splat_params* sp, double* image, int64_t* n_evals) {
+  int64_t npix = (int64_t)sp->width * sp->height;
+  int64_t total = 0;
+#pragma omp parallel reduction(+ : total)
+  {
+    double* local = (double*)calloc((size_t)npix, sizeof(double));
+#pragma omp for schedule(dynamic, 1)
+    for (int64_t h = 0; h < P->n_hkl; ++h) {
+      const double r0 = P->r0[h];
+      const double* S0 = &P->S[3 * h];
+      const double* e1 = &P->e1[3 * h];
+      const double* e2 = &P->e2[3 * h];
+      const double dr = sp->dr[h], Ts = sp->Ts[h];
+      const double hr = 2.0 * dr / sp->n_r, hs = 2.0 * Ts / sp->n_s;
+      for (int a = 0; a < sp->n_r; ++a) {
+        double r = (r0 - dr) + (a + 0.5) * hr;
+        for (int b2 = 0; b2 < sp->n_s; ++b2) {
+          double d2 = -Ts + (b2 + 0.5) * hs;
+          for (int b1 = 0; b1 < sp->n_s; ++b1) {
+            double d1 = -Ts + (b1 + 0.5) * hs;
+            double c = 1.0 / sqrt((1.0 + d1 * d1) + d2 * d2);
+            double S[3];
+            for (int j = 0; j < 3; ++j) S[j] = (r * c) * ((S0[j] + d1 * e1[j]) + d2 * e2[j]);
+            int64_t px[2];
+            splat_pixels(sp, S, px);
+            int64_t cnt = 0;
+            double I = profile_at(P, h, S, &cnt);
+            total += cnt;
+            if (px[0] < 0 && px[1] < 0) continue;
+            double RS = sqrt(S[0] * S[0] + S[1] * S[1]);
+            double dV = ((r * r) * hr) * ((c * c) * c) * (hs * hs);
+            double w = P->W[h] * I * (P->delta / (RS + P->delta)) * dV;
+            for (int k = 0; k < 2; ++k)
+              if (px[k] >= 0) local[px[k]] += w;
+          }
+        }
+      }
+    }
+#pragma omp critical
+    for (int64_t q = 0; q < npix; ++q) image[q] += local[q];
+    free(local);
+  }
+  if (n_evals) *n_evals = total;
 }
 
 /* Threads the OpenMP loops above use. */

@@ -428,6 +428,67 @@ def test_tilted_fibre_round_trip(tilt_deg):
     assert np.abs(img - img[::-1, :]).max() > 1e-3 * img.max()
 
 
+@pytest.mark.parametrize("tilt_deg", [0.0, 22.0, -35.0])
+def test_splat_projection_matches_ewald_solution(tilt_deg):
+    """The forward splat's algebraic projection (S_x = -lambda |S|^2/2, S.n = Z_S, S_y from
+    |S|) lands where Eqs. harmonic/solutions (rotation about the tilted fibre axis, then
+    k_out = k_in + S_phi onto the detector) put the point, for both rotations."""
+    t = tilt_deg * DEG
+    wl = W.small(4, width=60, height=50, center=(31.3, 22.6), tilt=t)
+    n = np.array([math.sin(t), 0.0, math.cos(t)])
+    m = np.array([math.cos(t), 0.0, -math.sin(t)])
+    R, Z = O.pixel_rz(wl.geom)
+    rng = np.random.default_rng(3)
+    pts = []
+    for _ in range(40):
+        j, i = rng.integers(0, 50), rng.integers(0, 60)
+        psi = rng.uniform(0, 2 * math.pi)
+        pts.append((R[j, i] * math.cos(psi), R[j, i] * math.sin(psi), Z[j, i]))     # fibre frame
+    S = np.array(pts)
+    a1, a2 = O.splat_project(S, wl.geom)
+    lab = np.array([np.hypot(s[0], s[1]) * m + s[2] * n for s in S])               # same (R, Z) about n
+    e1, e2 = O.ewald_project(lab, wl.geom, fibre=n)
+    for k in range(S.shape[0]):
+        got = sorted([tuple(np.round(a1[k] - 0.5, 9)), tuple(np.round(a2[k] - 0.5, 9))])
+        want = sorted([tuple(np.round(e1[k], 9)), tuple(np.round(e2[k], 9))])
+        np.testing.assert_allclose(got, want, atol=1e-7)
+
+
+@pytest.mark.parametrize("lineshape", [0, 1])
+def test_splat_mass_converges_to_closed_form(lineshape):
+    """With L = 1 (delta -> infinity) the splatted weight of one reflection integrates its
+    profile over reciprocal space, twice (both rotations): 2 W r0^2 sum_k omega_k prod_i m_i / V,
+    m_i the per-axis mass inside the support ((2/pi) Si(2 pi m) for Laue, erf(m sqrt(pi)) for
+    the Gaussian).  The midpoint sampling converges to it as the grid refines."""
+    wl = W.small(40, n_atoms=8, width=400, height=400, sigma_theta=1.5 * DEG, gamma_theta=0.0, n_nodes=12,
+                 d_min=3.0, size_A=(60.0, 60.0, 80.0), lineshape=lineshape)
+    wl.quad.delta = 1e6
+    P = O.prepare(wl, hkl=np.array([[1, 1, 1]], dtype=np.int32), F=np.ones(1, complex), cull_extinct=False)
+    V = O.frame(wl.cell)[2]
+    m = wl.quad.m
+    mass = ((2 / math.pi) * special.sici(2 * math.pi * m)[0]) ** 3 if lineshape == 0 else special.erf(m * math.sqrt(math.pi)) ** 3
+    want = 2.0 * P.W[0] * P.r0[0] ** 2 * P.nodes.omega.sum() * mass / V
+    coarse = O.splat(wl, P, 16, 96).sum() / want
+    fine = O.splat(wl, P, 32, 192).sum() / want
+    assert abs(fine - 1.0) < 5e-4 and abs(fine - 1.0) < abs(coarse - 1.0) / 20
+
+
+def test_splat_symmetry_and_counts():
+    """Centred beam, untilted fibre: the splat is mirror-symmetric bit for bit; every deposit
+    of a sample of reflection h lands on a pixel whose ring coordinates are those of the sample."""
+    wl = W.config0()
+    P = O.prepare(wl)
+    img, n = O.splat(wl, P, 4, 16, count=True)
+    assert img.max() > 0 and n > 0 and np.array_equal(img, img[:, ::-1])
+    R, Z = O.pixel_rz(wl.geom)
+    S = np.array([[0.05, 0.07, 0.1], [0.11, -0.02, -0.04]])
+    for a in O.splat_project(S, wl.geom):
+        i, j = np.floor(a[:, 0]).astype(int), np.floor(a[:, 1]).astype(int)
+        RS, ZS = np.hypot(S[:, 0], S[:, 1]), S[:, 2]
+        pitch = wl.geom.pixel / wl.geom.distance / wl.geom.wavelength
+        assert np.all(np.abs(R[j, i] - RS) < pitch) and np.all(np.abs(Z[j, i] - ZS) < pitch)
+
+
 def test_ewald_validity():
     """Beam normal to the fibre: S can be rotated onto the sphere iff lambda |S|^2 <= 2 R
     (Eq. valid); otherwise both angles are NaN."""
