@@ -82,6 +82,7 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-model leg")
     ap.add_argument("--no-tilt", action="store_true", help="skip the tilted-fibre forward leg")
     ap.add_argument("--no-lineshapes", action="store_true", help="skip the Gaussian/Hosemann lineshape legs")
+    ap.add_argument("--no-splat", action="store_true", help="skip the forward-splat leg")
     ap.add_argument("--batch-models", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -179,6 +180,43 @@ def bench_lineshapes(args):
     return out
 
 
+def bench_splat(args, n_r=8, n_s=64):
+    """Deterministic forward splat of the medium workload: n_r x n_s^2 shell samples per
+    reflection, each evaluated by the direct sum and deposited at both diffraction-condition
+    rotations."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2608_23245_amd import atoms_to_device
+    from paper_2608_23245_amd import binding as B
+
+    wl = W.config1()
+    model = B.make_model(wl)
+    ext = (wl.dis.g[0], wl.dis.g[1], wl.dis.g[2], wl.quad.extinction)
+    hkl = B.enumerate_hkl(model.cell, wl.quad.d_min, wl.quad.d_max, extinction=ext)
+    _, F2 = B.structure_factors(model.cell, atoms_to_device(wl.atoms), hkl, want_F=False)
+    refl, _ = B.reflection_prep(model, hkl, F2)
+    nodes = B.node_table(model)
+    B.splat(model, hkl, refl, nodes, n_r, n_s)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(2)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        img = B.splat(model, hkl, refl, nodes, n_r, n_s)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    assert torch.isfinite(img).all() and img.max().item() > 0
+    n_evals = B.splat(model, hkl, refl, nodes, n_r, n_s, count=True)
+    samples = int(hkl.shape[0]) * n_r * n_s * n_s
+    return {"workload": f"medium, {n_r} x {n_s}^2 samples per reflection", "n_hkl": int(hkl.shape[0]),
+            "samples": samples, "useful_evals": int(n_evals), "splat_ms": ms, "samples_per_s": samples / (ms * 1e-3),
+            "evals_per_s": n_evals / (ms * 1e-3), "evals_per_sample": n_evals / samples,
+            "pass": "forward splat (binary64 sample geometry and projection, float32 direct sum)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -239,6 +277,10 @@ def main():
     if not args.no_lineshapes:
         log("forward, Gaussian and Hosemann lineshapes")
         out["lineshapes"] = bench_lineshapes(args)
+        torch.cuda.empty_cache()
+    if not args.no_splat:
+        log("forward splat")
+        out["splat"] = bench_splat(args)
         torch.cuda.empty_cache()
     if not args.no_bwd:
         log("forward + adjoint")

@@ -257,6 +257,31 @@ int fdtbx_profile(const fdtbx_model* model, const float* refl, const float* node
                   const double* tile, const int64_t* offsets, const int32_t* idx, float* image, int64_t* counts,
                   void* stream);
 
+/* Deterministic forward splat (the paper's projection path, sampled on a fixed grid
+ * instead of at random; sections "Numerical evaluation: per-reflection shell quadrature",
+ * "Lorentz correction on a sampled reciprocal lattice", "Analytical Solution of the Ewald
+ * Diffraction Condition").  For each reflection h (fibre frame, radius r0, tangent frame
+ * S0, e1, e2) and each sample
+ *   r_a = r0 - dr + (a + 1/2) 2dr/n_r,  d_b = -Ts + (b + 1/2) 2Ts/n_s  (a < n_r; b < n_s per axis)
+ *   S = (r c)((S0 + d1 e1) + d2 e2),  c = 1/sqrt((1 + d1^2) + d2^2)           (Eq. gnomonic)
+ * with dr = sum_i w_i |a*_i| (w_i: the culling contract's support half-width bounds) and
+ * Ts = min(T + 2 dr/r0, 10), the weight
+ *   W_h I_h(S) delta/(R_S + delta) r^2 (2dr/n_r) c^3 (2Ts/n_s)^2,  I_h(S) = r0^2 sum_k omega_k Z(S - s_k)
+ * is added to the pixels of both rotations about the fibre axis that put S on the Ewald
+ * sphere (Eqs. harmonic, solutions; tilt as in fdtbx_geometry): S_x = -lambda |S|^2/2,
+ * S.n = S_z(fibre), S_y = +-sqrt(|S|^2 - S_x^2 - S_z^2), k_out = (1/lambda + S_x, S_y, S_z),
+ * pixel (floor(y/pixel + center_x), floor(z/pixel + center_y)) of y = distance k_y/k_x,
+ * z = distance k_z/k_x (k_x > 0, on the detector).  Sample positions and pixels are
+ * binary64 without fused multiply-adds, reproducible bit for bit; the weights are float32
+ * accumulated with atomic adds (order-dependent in the last bits).
+ *   hkl   device int32 [n_hkl][3]; refl, nodes: from fdtbx_reflection_prep, fdtbx_node_table
+ *   n_r 1..1024, n_s 1..4096; n_hkl * n_r < 2^31
+ *   image device float32 [height][width] output (zeroed by the call)
+ *   counts device int64 [1] (may be NULL): if non-NULL, counts the (sample, node) pairs inside
+ *          the support instead (image untouched). */
+int fdtbx_splat(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* refl, const float* nodes,
+                int32_t n_r, int32_t n_s, float* image, int64_t* counts, void* stream);
+
 /* ------------------------------------------------------------------ one-call pattern
  * fdtbx_profile_pattern runs reflection_prep, node_table, pixel_map, cull and
  * profile into a caller workspace laid out by fdtbx_pattern_workspace(model,

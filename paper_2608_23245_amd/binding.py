@@ -91,6 +91,8 @@ _SIGS = {
                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                   ctypes.c_void_p]),
     "fdtbx_profile": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 9),
+    "fdtbx_splat": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdtbx_pattern_workspace": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]),
     "fdtbx_profile_pattern": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
@@ -299,6 +301,22 @@ def profile(model: Model, refl, nodes, pix, tile, offsets, idx, count=False):
     img = torch.empty((g.height, g.width), dtype=torch.float32, device="cuda")
     _check(lib().fdtbx_profile(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(tile), _ptr(offsets),
                                _ptr(idx), _ptr(img), None, _stream()))
+    return img
+
+
+def splat(model: Model, hkl, refl, nodes, n_r: int, n_s: int, count=False):
+    """fdtbx_splat: the forward-splat image [H][W] float32, or (count=True) the number of
+    (sample, node) pairs inside the support."""
+    g = model.geom
+    n = int(hkl.shape[0])
+    if count:
+        c = torch.zeros(1, dtype=torch.int64, device="cuda")
+        _check(lib().fdtbx_splat(ctypes.byref(model), _ptr(hkl), n, _ptr(refl), _ptr(nodes), int(n_r), int(n_s), None,
+                                 _ptr(c), _stream()))
+        return int(c.item())
+    img = torch.empty((g.height, g.width), dtype=torch.float32, device="cuda")
+    _check(lib().fdtbx_splat(ctypes.byref(model), _ptr(hkl), n, _ptr(refl), _ptr(nodes), int(n_r), int(n_s), _ptr(img),
+                             None, _stream()))
     return img
 
 

@@ -2,8 +2,9 @@
 
 Every translation unit is compiled for gfx950 only, with packed-FP32 code
 generation disabled.  exact.hip (enumeration, pixel map, culling records and
-lists) is compiled without floating-point contraction so that its binary64
-predicates are evaluated exactly as written.
+lists) and splat.hip (sample positions and their detector pixels) are compiled
+without floating-point contraction so that their binary64 predicates are
+evaluated exactly as written.
 """
 from __future__ import annotations
 
@@ -23,6 +24,7 @@ SOURCES = {
     "sf.hip": [],
     "profile.hip": [],
     "adjoint.hip": [],
+    "splat.hip": ["-ffp-contract=off"],
     "capi.hip": [],
 }
 

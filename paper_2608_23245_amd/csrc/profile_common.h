@@ -56,23 +56,14 @@ __device__ __forceinline__ void load_pair(const float* __restrict__ rec, PairRec
                "s"(f.v[29]), "s"(f.v[30]));
 }
 
-// Node index range that the query points of a tile box can reach.  A node in the
-// support of p satisfies |s.v - p.v| <= rho_v for v in {S, e1, e2}; s.S = r0 c is in
-// [r0 cmin, r0]; d_j = (s.e_j)/(s.S).  One extra node of margin on each side absorbs the
-// float32 rounding of these bounds (hardware reciprocals included).
-__device__ static inline bool node_window(const ProfParams& q, const PairRec& rec, float Rlo, float Rhi, float Zlo, float Zhi,
-                                          Window* w) {
-  auto range = [&](float cR, float cZ, float* lo, float* hi) {
-    float a = Rlo * cR, b = Rhi * cR, c = Zlo * cZ, d = Zhi * cZ;
-    *lo = fminf(a, b) + fminf(c, d);
-    *hi = fmaxf(a, b) + fmaxf(c, d);
-  };
-  const float r0 = rec.at(RS_R0);
-  float sl, sh, l1, h1, l2, h2;
-  range(rec.at(RS_CS), rec.at(RS_CS + 1), &sl, &sh);
-  range(rec.at(RS_C1), rec.at(RS_C1 + 1), &l1, &h1);
-  range(rec.at(RS_C2), rec.at(RS_C2 + 1), &l2, &h2);
-  const float rS = rec.at(RS_RHO) * 1.0001f, r1 = rec.at(RS_RHO + 1) * 1.0001f, r2 = rec.at(RS_RHO + 2) * 1.0001f;
+// Node index range that query points p with p.S in [sl, sh], p.e1 in [l1, h1] and
+// p.e2 in [l2, h2] can reach.  A node in the support of p satisfies |s.v - p.v| <= rho_v
+// for v in {S, e1, e2} (rho_v: support extents); s.S = r0 c is in [r0 cmin, r0];
+// d_j = (s.e_j)/(s.S).  One extra node of margin on each side absorbs the float32 rounding
+// of these bounds (hardware reciprocals included).
+__device__ static inline bool node_window_ranges(const ProfParams& q, float r0, float sl, float sh, float l1, float h1,
+                                                 float l2, float h2, float rhoS, float rho1, float rho2, Window* w) {
+  const float rS = rhoS * 1.0001f, r1 = rho1 * 1.0001f, r2 = rho2 * 1.0001f;
   float dlo_s = fmaxf(sl - rS, r0 * q.cmin * 0.9999f);
   float dhi_s = fminf(sh + rS, r0 * 1.0001f);
   if (!(dlo_s <= dhi_s)) return false;
@@ -97,6 +88,23 @@ __device__ static inline bool node_window(const ProfParams& q, const PairRec& re
   w->i2lo = max(lo_idx(d2l), 0);
   w->i2hi = min(hi_idx(d2h), q.n - 1);
   return w->i1lo <= w->i1hi && w->i2lo <= w->i2hi;
+}
+
+// Node window of a tile box in (R, Z): the query points p = R e_perp + Z z have
+// p.v = R (e_perp.v) + Z v_z, extreme at the box corners.
+__device__ static inline bool node_window(const ProfParams& q, const PairRec& rec, float Rlo, float Rhi, float Zlo, float Zhi,
+                                          Window* w) {
+  auto range = [&](float cR, float cZ, float* lo, float* hi) {
+    float a = Rlo * cR, b = Rhi * cR, c = Zlo * cZ, d = Zhi * cZ;
+    *lo = fminf(a, b) + fminf(c, d);
+    *hi = fmaxf(a, b) + fmaxf(c, d);
+  };
+  float sl, sh, l1, h1, l2, h2;
+  range(rec.at(RS_CS), rec.at(RS_CS + 1), &sl, &sh);
+  range(rec.at(RS_C1), rec.at(RS_C1 + 1), &l1, &h1);
+  range(rec.at(RS_C2), rec.at(RS_C2 + 1), &l2, &h2);
+  return node_window_ranges(q, rec.at(RS_R0), sl, sh, l1, h1, l2, h2, rec.at(RS_RHO), rec.at(RS_RHO + 1),
+                            rec.at(RS_RHO + 2), w);
 }
 
 // Window node wi -> (i1, i2) for a window nw1 nodes wide, through a float reciprocal
