@@ -649,6 +649,54 @@ def splat_project(S, geom):
     return out[0], out[1]
 
 
+# --------------------------------------------------------------------------- cylindrical average
+def cyl_at(P: Prepared, R, Z, arc, use_skip=True, count=False):
+    """Exact cylindrical average (Eq. cyl-average) of the pattern at pixels with ring
+    coordinates (R, Z), by the periodic trapezoid rule over the ring with arc step `arc`
+    (see oracle_cyl)."""
+    R = np.ascontiguousarray(np.ravel(R), dtype=np.float64)
+    Z = np.ascontiguousarray(np.ravel(Z), dtype=np.float64)
+    out = np.zeros(R.shape[0])
+    n_ev = ctypes.c_int64(0)
+    prob, keep = _c_problem(P, use_skip)
+    _c().oracle_cyl(ctypes.byref(prob), ctypes.c_int64(R.shape[0]), ctypes.c_void_p(R.ctypes.data),
+                    ctypes.c_void_p(Z.ctypes.data), ctypes.c_double(arc), ctypes.c_void_p(out.ctypes.data),
+                    ctypes.byref(n_ev))
+    del keep
+    return (out, int(n_ev.value)) if count else out
+
+
+def cyl_boxes(wl, hkl):
+    """Culling description for the cylindrical average, in the layout of reflection_boxes:
+    every query point that a ring point at any azimuth can reach lies in the ball of radius
+    rho_B = 2 r0 sqrt((1 - c_min)/2) + rho about D (the nodes lie within the great-circle
+    angle arccos(c_min) of S; rho = sum_i w_i |a*_i| bounds the support), so its ring
+    coordinates satisfy |R - R_D| <= rho_B and |Z - Z_D| <= rho_B, and |p| is within rho of
+    r0.  No wedge.  +, -, *, /, sqrt only."""
+    _, astar, _ = frame(wl.cell)
+    D = recip_vectors(hkl, astar)
+    r0 = np.sqrt((D[:, 0] * D[:, 0] + D[:, 1] * D[:, 1]) + D[:, 2] * D[:, 2])
+    RD = np.sqrt(D[:, 0] * D[:, 0] + D[:, 1] * D[:, 1])
+    T = wl.quad.T
+    cmin = 1.0 / math.sqrt(1.0 + 2.0 * T * T)
+    w = _support_bounds(wl, hkl)
+    rho = w[:, 0] * math.sqrt((astar[0, 0] * astar[0, 0] + astar[0, 1] * astar[0, 1]) + astar[0, 2] * astar[0, 2])
+    rho = rho + w[:, 1] * math.sqrt((astar[1, 0] * astar[1, 0] + astar[1, 1] * astar[1, 1]) + astar[1, 2] * astar[1, 2])
+    rho = rho + w[:, 2] * math.sqrt((astar[2, 0] * astar[2, 0] + astar[2, 1] * astar[2, 1]) + astar[2, 2] * astar[2, 2])
+    rB = (2.0 * r0) * math.sqrt((1.0 - cmin) / 2.0) + rho
+    out = np.zeros((hkl.shape[0], 13))
+    out[:, 0], out[:, 1] = RD - rB, RD + rB
+    out[:, 2], out[:, 3] = D[:, 2] - rB, D[:, 2] + rB
+    a_lo, a_hi = r0 - rho, r0 + rho
+    out[:, 4] = np.where(a_lo > 0.0, a_lo * a_lo, 0.0)
+    out[:, 5] = a_hi * a_hi
+    out[:, 6:12] = [0.0, 0.0, -1.0, 0.0, 0.0, -1.0]
+    ext_lim = wl.quad.extinction
+    alive = ~((ext_lim > 0) & (extinction_arg(hkl, wl.dis.g) > ext_lim))
+    out[:, 12] = alive.astype(np.float64)
+    return out
+
+
 # --------------------------------------------------------------------------- culling contract
 def _support_bounds(wl, hkl):
     """Per reflection and axis, the culling contract's upper bound on the support half-width
@@ -759,13 +807,13 @@ def reflection_boxes(wl, hkl):
     return out
 
 
-def culling_lists(wl, hkl, tile_w=8, tile_h=8, tiles=None):
+def culling_lists(wl, hkl, tile_w=8, tile_h=8, tiles=None, boxes=None):
     """Per tile (row-major over tiles, or the given flat tile indices), ascending
     indices into hkl of the reflections that are alive and pass every test of the
-    reflection's description against the tile's box (the box corners stand in for
-    the tile's pixels in the wedge test)."""
+    reflection's description (reflection_boxes, or the given boxes) against the tile's box
+    (the box corners stand in for the tile's pixels in the wedge test)."""
     tb = tile_boxes(wl.geom, tile_w, tile_h).reshape(-1, 6)
-    rb = reflection_boxes(wl, hkl)
+    rb = reflection_boxes(wl, hkl) if boxes is None else boxes
     if tiles is None:
         tiles = range(tb.shape[0])
     lists = []

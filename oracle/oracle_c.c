@@ -11,6 +11,7 @@
  *   oracle_pattern   -- the detector image at a list of pixels
  *   oracle_grad      -- the adjoint of that image for a weighted residual
  *   oracle_splat     -- the forward splat of sampled shell points onto the detector
+ *   oracle_cyl       -- the exact cylindrical average at a list of pixels
  *
  * Both follow the section "Numerical evaluation: per-reflection shell
  * quadrature" (Eqs. I_shape, gnomonic, node_weight, direct_sum; Eqs. Z and
@@ -402,6 +403,39 @@ void oracle_splat(const oracle_problem* P, const oracle_splat_params* sp, double
 #pragma omp critical
     for (int64_t q = 0; q < npix; ++q) image[q] += local[q];
     free(local);
+  }
+  if (n_evals) *n_evals = total;
+}
+
+/* Exact cylindrical average (Eq. cyl-average) at n_pix pixels with ring coordinates (R, Z):
+ *   out[q] = sum_h W_h (1/2 pi) sum_j dphi I_h(p_h(phi_j)),
+ *   p_h(phi) = R cos(phi) e_perp + R sin(phi) e_az + Z z,  e_az = z x e_perp,
+ * with the periodic trapezoid rule phi_j = j dphi, dphi = 2 pi/n, n = max(8, ceil(2 pi R/arc)),
+ * j = -floor(n/2) .. ceil(n/2) - 1 (every point of the ring once, phi = 0 at the reflection's
+ * own azimuth).  No Lorentz factor: the ring average is the rotation average itself. */
+void oracle_cyl(const oracle_problem* P, int64_t n_pix, const double* R, const double* Z, double arc, double* out,
+                int64_t* n_evals) {
+  double theta_nodes = nodes_max_angle(P);
+  int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : total)
+  for (int64_t q = 0; q < n_pix; ++q) {
+    double nf = ceil(2.0 * M_PI * R[q] / arc);
+    int64_t n = nf < 8.0 ? 8 : (int64_t)nf;
+    double dphi = 2.0 * M_PI / (double)n;
+    double acc = 0.0;
+    int64_t cnt = 0;
+    for (int64_t j = -(n / 2); j < n - n / 2; ++j) {
+      double phi = (double)j * dphi;
+      double cp = cos(phi), sp = sin(phi);
+      for (int64_t h = 0; h < P->n_hkl; ++h) {
+        const double* ep = &P->ep[3 * h];
+        double p[3] = {R[q] * cp * ep[0] - R[q] * sp * ep[1], R[q] * cp * ep[1] + R[q] * sp * ep[0], Z[q]};
+        if (P->use_skip && provably_empty(P, h, p, theta_nodes)) continue;
+        acc += P->W[h] * profile_at(P, h, p, &cnt);
+      }
+    }
+    out[q] = acc * dphi / (2.0 * M_PI);
+    total += cnt;
   }
   if (n_evals) *n_evals = total;
 }

@@ -489,6 +489,52 @@ def test_splat_symmetry_and_counts():
         assert np.all(np.abs(R[j, i] - RS) < pitch) and np.all(np.abs(Z[j, i] - ZS) < pitch)
 
 
+def test_cyl_single_node_ring_integral():
+    """Eq. cyl-average for a one-node shell (the node at D) of an orthogonal cell: with D
+    in the x-z plane the ring offset is (R cos phi - R_D, R sin phi, Z - Z_D), so the ring
+    average is W r0^2 omega f_c (1/2 pi) int f_a(a R cos phi - h) f_b(b R sin phi) dphi,
+    computed here by adaptive quadrature; the oracle's trapezoid rule converges to it."""
+    wl = W.small(50, n_atoms=4, width=10, height=10, sigma_theta=2 * DEG, n_nodes=1, size_A=(60.0, 66.0, 78.0))
+    P = O.prepare(wl, hkl=np.array([[2, 0, 1]], dtype=np.int32), F=np.ones(1, complex), cull_extinct=False)
+    a, b, c = wl.cell.a, wl.cell.b, wl.cell.c
+    N, m = P.N[0], wl.quad.m
+    R, Z = 2 / a + 0.004, 1 / c + 0.003
+
+    def f(i, u):
+        return float(O.axis_profile(0, N[i], u)) if abs(u) <= m / N[i] else 0.0
+
+    ring = integrate.quad(lambda ph: f(0, a * R * math.cos(ph) - 2) * f(1, b * R * math.sin(ph)), -0.5, 0.5,
+                          limit=500, epsabs=0, epsrel=1e-12)[0]
+    want = P.W[0] * P.r0[0] ** 2 * P.nodes.omega[0] * f(2, c * Z - 1) * ring / (2 * math.pi)
+    for arc, tol in ((5e-4, 1e-6), (1e-4, 1e-8)):
+        got = O.cyl_at(P, np.array([R]), np.array([Z]), arc, use_skip=False)[0]
+        assert abs(got / want - 1) < tol, (arc, got, want)
+    # the exact skip leaves the sum unchanged
+    assert O.cyl_at(P, np.array([R]), np.array([Z]), 5e-4) == O.cyl_at(P, np.array([R]), np.array([Z]), 5e-4, use_skip=False)
+
+
+def test_cyl_culling_is_conservative():
+    """Every reflection whose ring average is nonzero at some pixel of a tile is in that tile's
+    list under the cylindrical culling description."""
+    wl = W.small(51, n_atoms=6, width=40, height=30, sigma_theta=1.5 * DEG, n_nodes=10, d_min=4.5, g=(0.02, 0.02, 0.0),
+                 pixel=1.6)
+    hkl = O.enumerate_hkl(wl.cell, wl.quad.d_min, wl.quad.d_max)
+    P = O.prepare(wl, hkl=hkl, F=np.ones(hkl.shape[0], complex), cull_extinct=False)
+    lists = O.culling_lists(wl, hkl, boxes=O.cyl_boxes(wl, hkl))
+    R, Z = O.pixel_rz(wl.geom)
+    H, Wd = R.shape
+    tx_n = (Wd + 7) // 8
+    missed = 0
+    for r in range(hkl.shape[0]):
+        Pr = _single(P, r)
+        vals = O.cyl_at(Pr, R, Z, 2e-3, use_skip=False).reshape(H, Wd)
+        for j, i in zip(*np.nonzero(vals)):
+            t = (j // 8) * tx_n + i // 8
+            missed += r not in set(lists[t].tolist())
+    assert missed == 0
+    assert sum(len(x) for x in lists) < hkl.shape[0] * len(lists)   # the description does cull
+
+
 def test_ewald_validity():
     """Beam normal to the fibre: S can be rotated onto the sphere iff lambda |S|^2 <= 2 R
     (Eq. valid); otherwise both angles are NaN."""
