@@ -282,6 +282,26 @@ int fdtbx_profile(const fdtbx_model* model, const float* refl, const float* node
 int fdtbx_splat(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* refl, const float* nodes,
                 int32_t n_r, int32_t n_s, float* image, int64_t* counts, void* stream);
 
+/* Exact cylindrical average (Eq. cyl-average) instead of the single-azimuth gather:
+ *   image[j][i] = sum_h W_h (1/2 pi) sum_k dphi I_h(p_h(phi_k)),
+ *   p_h(phi) = R cos(phi) e_perp + R sin(phi) e_az + Z z  (e_az = z x e_perp; (R, Z) of the pixel),
+ * periodic trapezoid rule phi_k = k dphi, dphi = 2 pi/n, n = max(8, ceil(2 pi R/arc)),
+ * k = -floor(n/2) .. ceil(n/2) - 1; no Lorentz factor (the ring average is the rotation
+ * average).  I_h as in fdtbx_profile (lineshape included).
+ *   offsets, idx: culling lists built by fdtbx_cull from fdtbx_cyl_records (the gather's lists
+ *                 do not cover ring points off each reflection's azimuth)
+ *   arc: ring step, 1/A, in [1e-5, 1)
+ *   image, counts: as in fdtbx_profile (counts: (pixel, ring point, node) triples) */
+int fdtbx_profile_cyl(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
+                      const int64_t* offsets, const int32_t* idx, double arc, float* image, int64_t* counts, void* stream);
+
+/* Culling records (layout of fdtbx_reflection_prep's) for fdtbx_profile_cyl: with rho the
+ * support corner radius sum_i w_i |a*_i| and rho_B = 2 r0 sqrt((1 - c_min)/2) + rho,
+ * [0..3] = R_D -+ rho_B, D_z -+ rho_B, [4..5] = (max(r0 - rho, 0))^2, (r0 + rho)^2, wedge
+ * disabled, [12] alive; binary64 +, -, *, /, sqrt only.
+ *   cull device float64 [n_hkl][FDTBX_CULL_DOUBLES] output */
+int fdtbx_cyl_records(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, double* cull, void* stream);
+
 /* ------------------------------------------------------------------ one-call pattern
  * fdtbx_profile_pattern runs reflection_prep, node_table, pixel_map, cull and
  * profile into a caller workspace laid out by fdtbx_pattern_workspace(model,

@@ -91,6 +91,9 @@ _SIGS = {
                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                   ctypes.c_void_p]),
     "fdtbx_profile": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 9),
+    "fdtbx_profile_cyl": (ctypes.c_int, [ctypes.c_void_p] * 6 + [ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                                                   ctypes.c_void_p]),
+    "fdtbx_cyl_records": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "fdtbx_splat": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdtbx_pattern_workspace": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]),
@@ -301,6 +304,29 @@ def profile(model: Model, refl, nodes, pix, tile, offsets, idx, count=False):
     img = torch.empty((g.height, g.width), dtype=torch.float32, device="cuda")
     _check(lib().fdtbx_profile(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(tile), _ptr(offsets),
                                _ptr(idx), _ptr(img), None, _stream()))
+    return img
+
+
+def cyl_records(model: Model, hkl) -> torch.Tensor:
+    """fdtbx_cyl_records: culling records float64 [n][CULL_DOUBLES] for the cylindrical average."""
+    n = int(hkl.shape[0])
+    out = torch.empty((n, CULL_DOUBLES), dtype=torch.float64, device=hkl.device)
+    _check(lib().fdtbx_cyl_records(ctypes.byref(model), _ptr(hkl), n, _ptr(out), _stream()))
+    return out
+
+
+def profile_cyl(model: Model, refl, nodes, pix, offsets, idx, arc: float, count=False):
+    """fdtbx_profile_cyl: the cylindrically averaged image [H][W] float32, or (count=True) the
+    number of support-passing evaluations."""
+    g = model.geom
+    if count:
+        c = torch.zeros(1, dtype=torch.int64, device="cuda")
+        _check(lib().fdtbx_profile_cyl(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(offsets), _ptr(idx),
+                                       float(arc), None, _ptr(c), _stream()))
+        return int(c.item())
+    img = torch.empty((g.height, g.width), dtype=torch.float32, device="cuda")
+    _check(lib().fdtbx_profile_cyl(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(offsets), _ptr(idx),
+                                   float(arc), _ptr(img), None, _stream()))
     return img
 
 

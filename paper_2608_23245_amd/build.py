@@ -2,8 +2,8 @@
 
 Every translation unit is compiled for gfx950 only, with packed-FP32 code
 generation disabled.  exact.hip (enumeration, pixel map, culling records and
-lists) and splat.hip (sample positions and their detector pixels) are compiled
-without floating-point contraction so that their binary64 predicates are
+lists), splat.hip (sample positions and their detector pixels) and cyl.hip (ring
+quadrature sizes) are compiled without floating-point contraction so that their binary64 predicates are
 evaluated exactly as written.
 """
 from __future__ import annotations
@@ -25,6 +25,7 @@ SOURCES = {
     "profile.hip": [],
     "adjoint.hip": [],
     "splat.hip": ["-ffp-contract=off"],
+    "cyl.hip": ["-ffp-contract=off"],
     "capi.hip": [],
 }
 

@@ -1,0 +1,223 @@
+// Exact cylindrical average of the pattern (Eq. cyl-average): per pixel with ring
+// coordinates (R, Z),
+//   image = sum_h W_h (1/2 pi) sum_j dphi I_h(p_h(phi_j)),
+//   p_h(phi) = R cos(phi) e_perp + R sin(phi) e_az + Z z,   e_az = z x e_perp,
+// by the periodic trapezoid rule phi_j = j dphi, dphi = 2 pi/n, n = max(8, ceil(2 pi R/arc)),
+// j = -floor(n/2) .. ceil(n/2) - 1, with I_h the shell quadrature of Eq. direct_sum.  Unlike the
+// profile kernel (one query point per pixel at each reflection's own azimuth, weighted by the
+// Lorentz factor of Eq. lorentz), every point of the ring is visited; no Lorentz factor enters.
+//
+// Mapping: one 64-lane wave per 8x8 pixel tile over the tile's list under the cylindrical
+// culling description (fdtbx_cyl_records).  Per (tile, reflection) each lane bounds the part
+// of its ring that can reach the reflection's support (the ball of radius rho_B about D) and
+// the wave steps a shared index j over the union of those ranges; at each j the 64 ring
+// points are treated like the splat's samples: node window from their coordinates, the node
+// queue of the profile kernel, and one evaluation per lane.  cos and sin of j dphi come from
+// a binary64 rotation recurrence per lane.
+#include <hip/hip_runtime.h>
+
+#include <math.h>
+
+#include "internal.h"
+#include "profile_common.h"
+#include "profile_tile.h"
+
+namespace fdtbx {
+
+struct CylParams {
+  ProfParams q;
+  double arc;
+};
+
+__device__ static inline float wmin(float v) {
+  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ static inline float wmax(float v) {
+  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ static inline int wmin_i(int v) {
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ static inline int wmax_i(int v) {
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+template <bool COUNT, int LS>
+__global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict__ refl, const float* __restrict__ nodes,
+                                            const double* __restrict__ pix, const int64_t* __restrict__ offsets,
+                                            const int32_t* __restrict__ idx, float* __restrict__ image,
+                                            unsigned long long* __restrict__ counts) {
+  __shared__ float4 qn[128];
+  __shared__ int bq[64];
+  const ProfParams& q = p.q;
+  const int lane = threadIdx.x & 63;
+  const int t = blockIdx.x;
+  const int tx = t % q.tiles_x, ty = t / q.tiles_x;
+  const int pi_ = tx * FDTBX_TILE + (lane % FDTBX_TILE);
+  const int pj = ty * FDTBX_TILE + (lane / FDTBX_TILE);
+  const bool in = pi_ < q.W && pj < q.H;
+  const double R = in ? pix[2 * ((int64_t)pj * q.W + pi_) + 0] : 0.0;
+  const double Z = in ? pix[2 * ((int64_t)pj * q.W + pi_) + 1] : 0.0;
+  // periodic trapezoid rule over this pixel's ring
+  const double nf = ceil(2.0 * M_PI * R / p.arc);
+  const int n = nf < 8.0 ? 8 : (int)nf;
+  const double dphi = 2.0 * M_PI / (double)n;
+  const int ring_lo = -(n / 2), ring_hi = n - n / 2 - 1;
+  const double cd = cos(dphi), sd = sin(dphi);
+  const int64_t p0 = offsets[t], p1 = offsets[t + 1];
+  float acc = 0.0f;
+  unsigned long long cnt = 0;
+  int32_t r_next = p0 < p1 ? idx[p0] : 0;
+  for (int64_t pp = p0; pp < p1; ++pp) {
+    const int32_t r = r_next;
+    r_next = idx[pp + 1 < p1 ? pp + 1 : pp];
+    const float* rec = refl + (int64_t)FDTBX_REFL_FLOATS * r;
+    PairRec f;
+    load_pair(rec, f);
+    const float4 x1 = *(const float4*)(rec + 36);
+    const float az[3] = {f.at(RS_AZ), x1.x, x1.y};
+    const float ta[3] = {x1.z, x1.w, rec[RS_TA + 2]};
+    const double RD = f.at_f64(RS_RD), ZD = f.at_f64(RS_ZD);
+    float Bv[3], G1[3], G2[3], tr[3], tz[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      Bv[a] = f.at(RS_B + a);
+      G1[a] = f.at(RS_G1 + a);
+      G2[a] = f.at(RS_G2 + a);
+      tr[a] = f.at(RS_TR + a);
+      tz[a] = f.at(RS_TZ + a);
+    }
+    // ring points within rho_B of D: |p(phi) - D|^2 = R^2 + R_D^2 + (Z - Z_D)^2 - 2 R R_D cos(phi)
+    const float rS = f.at(RS_RHO), r1 = f.at(RS_RHO + 1), r2 = f.at(RS_RHO + 2);
+    const float r0 = f.at(RS_R0);
+    const double rhoB = ((double)(2.0f * r0 * sqrtf(0.5f * (1.0f - q.cmin))) + (double)sqrtf(rS * rS + r1 * r1 + r2 * r2)) *
+                            1.001 + 1.0e-7;
+    int jl = 1, jh = 0;  // empty
+    if (in) {
+      const double dz = Z - ZD;
+      const double num = ((R * R + RD * RD) + dz * dz) - rhoB * rhoB;
+      const double den = 2.0 * R * RD;
+      if (!(den > 0.0)) {
+        if (num <= 0.0) {
+          jl = ring_lo;
+          jh = ring_hi;
+        }
+      } else {
+        const double cmin = num / den;
+        if (cmin <= -1.0) {
+          jl = ring_lo;
+          jh = ring_hi;
+        } else if (cmin < 1.0) {
+          const int jm = (int)floor(acos(cmin) / dphi) + 1;
+          jl = max(ring_lo, -jm);
+          jh = min(ring_hi, jm);
+        }
+      }
+    }
+    const bool has = jl <= jh;
+    const int J0 = wmin_i(has ? jl : 0x7fffffff), J1 = wmax_i(has ? jh : -0x7fffffff);
+    if (J0 > J1) continue;
+    HoseK hk = {};
+    if (LS == FDTBX_LINESHAPE_HOSEMANN && !COUNT) hose_constants(rec, hk);
+    double cj = cos((double)J0 * dphi), sj = sin((double)J0 * dphi);
+    float accp = 0.0f;
+    for (int jj = J0; jj <= J1; ++jj) {
+      const bool act = has && jj >= jl && jj <= jh;
+      const double X = R * cj - RD, Y = R * sj;
+      const float fX = (float)X, fY = (float)Y, fZ = (float)(Z - ZD);
+      float al[3], lo[3], hi[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        al[a] = act ? fmaf(tr[a], fX, fmaf(ta[a], fY, tz[a] * fZ)) : 1.0e30f;
+        lo[a] = wmin(act ? al[a] : INFINITY) - q.half_m - q.margin;
+        hi[a] = wmax(act ? al[a] : -INFINITY) + q.half_m + q.margin;
+      }
+      // the ring point's coordinates along S, e1, e2
+      const float Rc = (float)(R * cj), Rs = (float)(R * sj), fz = (float)Z;
+      const float pS = fmaf(Rc, f.at(RS_CS), fmaf(Rs, az[0], fz * f.at(RS_CS + 1)));
+      const float p1v = fmaf(Rc, f.at(RS_C1), fmaf(Rs, az[1], fz * f.at(RS_C1 + 1)));
+      const float p2v = fmaf(Rc, f.at(RS_C2), fmaf(Rs, az[2], fz * f.at(RS_C2 + 1)));
+      const float sl = wmin(act ? pS : INFINITY), sh = wmax(act ? pS : -INFINITY);
+      const float l1 = wmin(act ? p1v : INFINITY), h1 = wmax(act ? p1v : -INFINITY);
+      const float l2 = wmin(act ? p2v : INFINITY), h2 = wmax(act ? p2v : -INFINITY);
+      Window w;
+      if (node_window_ranges(q, r0, sl, sh, l1, h1, l2, h2, rS, r1, r2, &w)) {
+        float accr = 0.0f;
+        int qlen = 0;  // uniform
+        scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int, float4 e) {
+          const unsigned long long bal = __ballot(keep);
+          if (keep) {
+            const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
+            qn[pos] = e;
+          }
+          qlen += __popcll(bal);
+          __syncthreads();
+          if (qlen >= 64) {
+            walk_queue<COUNT, LS>(qn, 64, al, q.half_m, q.tiny, hk, accr, cnt);
+            qlen -= 64;
+            __syncthreads();
+            if (lane < qlen) qn[lane] = qn[64 + lane];
+            __syncthreads();
+          }
+        });
+        walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, q.tiny, hk, accr, cnt);
+        __syncthreads();
+        accp += accr;
+      }
+      const double cn = cj * cd - sj * sd;
+      sj = sj * cd + cj * sd;
+      cj = cn;
+    }
+    acc = fmaf(f.at(RS_WK), accp, acc);
+  }
+  if (COUNT) {
+    for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if (lane == 0 && cnt) atomicAdd(counts, cnt);
+  } else if (in) {
+    image[(int64_t)pj * q.W + pi_] = acc * (float)(dphi / (2.0 * M_PI));
+  }
+}
+
+__global__ void k_zero_count(unsigned long long* c) {
+  if (threadIdx.x == 0) *c = 0ull;
+}
+
+}  // namespace fdtbx
+
+using namespace fdtbx;
+
+extern "C" int fdtbx_profile_cyl(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
+                                 const int64_t* offsets, const int32_t* idx, double arc, float* image, int64_t* counts,
+                                 void* stream) {
+  if (!model || !refl || !nodes || !pix || !offsets || !idx) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (!counts && !image) return fail(FDTBX_ERR_INVALID_ARGUMENT, "image is NULL");
+  int rc = check_model(model);
+  if (rc) return rc;
+  if (!(arc >= 1.0e-5 && arc < 1.0)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "arc must be in [1e-5, 1) 1/A");
+  CylParams p;
+  prof_params(model, &p.q);
+  p.arc = arc;
+  const int64_t n_tiles = (int64_t)p.q.tiles_x * p.q.tiles_y;
+  hipStream_t s = (hipStream_t)stream;
+  const dim3 grid((unsigned)n_tiles);
+  unsigned long long* cp = (unsigned long long*)counts;
+  if (counts) {
+    hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, cp);
+    FDTBX_LAUNCH_CHECK("cylindrical average counter");
+    hipLaunchKernelGGL((k_cyl<true, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, p, refl, nodes, pix, offsets, idx, image, cp);
+  } else if (p.q.lineshape == FDTBX_LINESHAPE_GAUSSIAN) {
+    hipLaunchKernelGGL((k_cyl<false, FDTBX_LINESHAPE_GAUSSIAN>), grid, dim3(64), 0, s, p, refl, nodes, pix, offsets, idx, image,
+                       cp);
+  } else if (p.q.lineshape == FDTBX_LINESHAPE_HOSEMANN) {
+    hipLaunchKernelGGL((k_cyl<false, FDTBX_LINESHAPE_HOSEMANN>), grid, dim3(64), 0, s, p, refl, nodes, pix, offsets, idx, image,
+                       cp);
+  } else {
+    hipLaunchKernelGGL((k_cyl<false, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, p, refl, nodes, pix, offsets, idx, image, cp);
+  }
+  FDTBX_LAUNCH_CHECK("cylindrical average");
+  return FDTBX_OK;
+}

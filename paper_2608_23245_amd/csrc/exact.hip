@@ -393,8 +393,11 @@ __device__ static void profile_record(const PrepParams& p, const double* hh, con
     o[RS_RHO + v] = (float)e;
   }
   for (int i = 0; i < 3; ++i) {
-    o[RS_A + i] = (float)A[i];
-    o[RS_H + i] = (float)hh[i];
+    // ring direction at the reflection's azimuth, for query points off that azimuth
+    const double az[3] = {-ep[1], ep[0], 0.0};
+    const double* vv[3] = {S, e1, e2};
+    o[RS_AZ + i] = (float)dotv(az, vv[i]);
+    o[RS_TA + i] = (float)(sc[i] * dotv(&p.f.a[3 * i], az));
   }
   o[RS_F2] = (float)f2;
   for (int k = RS_K + 1; k < FDTBX_REFL_FLOATS; ++k) o[k] = 0.0f;
@@ -410,6 +413,39 @@ __global__ void __launch_bounds__(256) k_prep(PrepParams p, const int32_t* __res
   refl_frame(p.f, hh, &F);
   cull_record(p, hh, F, cull + FDTBX_CULL_DOUBLES * r);
   profile_record(p, hh, F, (double)F2[r], refl + (int64_t)FDTBX_REFL_FLOATS * r);
+}
+
+// Culling record for the cylindrical average (layout of the culling record): the ball of
+// radius rho_B = 2 r0 sqrt((1 - cmin)/2) + rho about D holds every point a ring point at any
+// azimuth can reach (nodes within arccos(cmin) of S, support corner radius rho), so
+// |R - R_D| <= rho_B, |Z - Z_D| <= rho_B and | |p| - r0 | <= rho; the wedge is disabled.
+__global__ void __launch_bounds__(256) k_cyl_records(PrepParams p, const int32_t* __restrict__ hkl, double* __restrict__ cull) {
+  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= p.n) return;
+  const double hh[3] = {(double)hkl[3 * r + 0], (double)hkl[3 * r + 1], (double)hkl[3 * r + 2]};
+  double D[3];
+  recip(p.f, hh[0], hh[1], hh[2], D);
+  const double r0 = sqrt((D[0] * D[0] + D[1] * D[1]) + D[2] * D[2]);
+  const double RD = sqrt(D[0] * D[0] + D[1] * D[1]);
+  double w[3];
+  support_bounds(p.lineshape, p.m, p.Nb, p.g, hh, w);
+  double rho = w[0] * sqrt(dotv(&p.f.s[0], &p.f.s[0]));
+  rho = rho + w[1] * sqrt(dotv(&p.f.s[3], &p.f.s[3]));
+  rho = rho + w[2] * sqrt(dotv(&p.f.s[6], &p.f.s[6]));
+  const double rB = (2.0 * r0) * sqrt((1.0 - p.cmin) / 2.0) + rho;
+  double* C = cull + FDTBX_CULL_DOUBLES * r;
+  C[0] = RD - rB;
+  C[1] = RD + rB;
+  C[2] = D[2] - rB;
+  C[3] = D[2] + rB;
+  const double a_lo = r0 - rho, a_hi = r0 + rho;
+  C[4] = a_lo > 0.0 ? a_lo * a_lo : 0.0;
+  C[5] = a_hi * a_hi;
+  C[6] = C[7] = C[9] = C[10] = 0.0;
+  C[8] = C[11] = -1.0;
+  const bool alive = !(p.ext_limit > 0.0 && extinction_arg(p.g[0], p.g[1], p.g[2], hh[0], hh[1], hh[2]) > p.ext_limit);
+  C[12] = alive ? 1.0 : 0.0;
+  C[13] = C[14] = C[15] = 0.0;
 }
 
 // Batched models: block b of refl_blocks covers reflections [first, first + 256) of one model.
@@ -614,6 +650,28 @@ extern "C" int fdtbx_reflection_prep(const fdtbx_model* model, const int32_t* hk
   hipLaunchKernelGGL(k_prep, dim3((unsigned)ceil_div(n_hkl, 256)), dim3(256), 0, (hipStream_t)stream, p, hkl, F2, refl,
                      cull);
   FDTBX_LAUNCH_CHECK("reflection prep");
+  return FDTBX_OK;
+}
+
+extern "C" int fdtbx_cyl_records(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, double* cull, void* stream) {
+  if (!model || !hkl || !cull) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be positive");
+  int rc = check_model(model);
+  if (rc) return rc;
+  PrepParams p;
+  make_frame(model->cell, &p.f);
+  for (int i = 0; i < 3; ++i) {
+    p.Nb[i] = model->dis.N_base[i];
+    p.g[i] = model->dis.g[i];
+  }
+  p.T = model->quad.T;
+  p.cmin = 1.0 / sqrt(1.0 + 2.0 * p.T * p.T);
+  p.m = (double)model->quad.m;
+  p.ext_limit = model->quad.extinction;
+  p.lineshape = model->dis.lineshape;
+  p.n = n_hkl;
+  hipLaunchKernelGGL(k_cyl_records, dim3((unsigned)ceil_div(n_hkl, 256)), dim3(256), 0, (hipStream_t)stream, p, hkl, cull);
+  FDTBX_LAUNCH_CHECK("cylindrical culling records");
   return FDTBX_OK;
 }
 

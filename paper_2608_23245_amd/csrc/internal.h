@@ -63,8 +63,8 @@ enum ReflSlot {
   RS_C1 = 28,      // (e_perp.e1, e1_z)
   RS_C2 = 30,      // (e_perp.e2, e2_z)
   RS_RHO = 32,     // support extent along S, e1, e2: sum_i (m/N_i)|a*_i.v|  (32..34)
-  RS_A = 35,       // coherence factors A_i (35..37)
-  RS_H = 38,       // h, k, l as floats (38..40)
+  RS_AZ = 35,      // e_az.S, e_az.e1, e_az.e2 with e_az = z x e_perp (35..37)
+  RS_TA = 38,      // scale_i (a_i.e_az), the lattice offset along the ring direction (38..40)
   RS_F2 = 41,      // |F|^2
   RS_K = 42,       // r0^2 C with C the lineshape's constant (Laue prod N/(2 pi)^6, Gaussian
                    // prod N, Hosemann prod (1 - A'^2)), so that RS_WK = W * RS_K

@@ -1,0 +1,151 @@
+"""Parity of the exact cylindrical average (fdtbx_cyl_records, fdtbx_cull, fdtbx_profile_cyl,
+through the C ABI) with the FP64 oracle's periodic trapezoid rule over each pixel's ring on
+the same ring grid: culling lists bit-exact, images to the pattern tolerances (relative
+L2 <= 1e-4, per-pixel <= 1e-3 over pixels above 1e-3 of the maximum), and the number of
+support-passing (pixel, ring point, node) evaluations equal up to float32 boundary flips."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2608_23245_amd import binding as B  # noqa: E402
+
+DEG = math.pi / 180
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _hkl(wl):
+    hkl = O.enumerate_hkl(wl.cell, wl.quad.d_min, wl.quad.d_max)
+    return np.ascontiguousarray(hkl[~O.extinct_mask(hkl, wl.dis, wl.quad.extinction)])
+
+
+def gpu_cyl(wl, hkl, arc, count=True):
+    model = B.make_model(wl)
+    h = torch.from_numpy(np.ascontiguousarray(hkl, dtype=np.int32)).cuda()
+    F = O.structure_factors_c(hkl, wl.cell, wl.atoms)
+    F2 = torch.as_tensor((F.real ** 2 + F.imag ** 2).astype(np.float32)).cuda()
+    refl, _ = B.reflection_prep(model, h, F2)
+    cull = B.cyl_records(model, h)
+    nodes = B.node_table(model)
+    pix, tile = B.pixel_map(model.geom)
+    off, idx = B.cull(model.geom, tile, cull)
+    img = B.profile_cyl(model, refl, nodes, pix, off, idx, arc).cpu().numpy().astype(np.float64)
+    cnt = B.profile_cyl(model, refl, nodes, pix, off, idx, arc, count=True) if count else None
+    return img, cnt, F, cull.cpu().numpy(), off.cpu().numpy(), idx.cpu().numpy()
+
+
+def check(img, ref, tag):
+    assert ref.max() > 0, f"{tag}: empty reference"
+    r = float(np.linalg.norm(img - ref) / np.linalg.norm(ref))
+    big = ref > 1e-3 * ref.max()
+    px = float(np.max(np.abs(img[big] - ref[big]) / ref[big]))
+    say(f"{tag}: rel-L2 {r:.2e}, per-pixel {px:.2e} over {int(big.sum())} px")
+    assert r <= 1e-4 and px <= 1e-3, (tag, r, px)
+
+
+def pitch(wl):
+    g = wl.geom
+    return g.pixel / g.distance / g.wavelength
+
+
+CASES = {
+    "config0": (None, 2e-3),
+    "voigt": (dict(seed=81, width=24, height=20, sigma_theta=3 * DEG, gamma_theta=1 * DEG, g=(0.02, 0.02, 0.0)), 2e-3),
+    "wide_ragged": (dict(seed=82, width=41, height=29, sigma_theta=1.5 * DEG, pixel=1.6, g=(0.02, 0.02, 0.0)), 1e-3),
+    "tilted": (dict(seed=83, width=36, height=34, sigma_theta=2 * DEG, gamma_theta=1 * DEG, g=(0.02, 0.02, 0.0),
+                    tilt=22 * DEG, center=(17.4, 15.2)), 2e-3),
+    "gaussian_damped": (dict(seed=84, width=30, height=26, sigma_theta=3 * DEG, lineshape=1, B_axis=(4.0, 9.0, 2.5)), 2e-3),
+    "hosemann": (dict(seed=85, width=28, height=30, sigma_theta=2 * DEG, gamma_theta=0.5 * DEG, lineshape=2,
+                      g=(0.03, 0.02, 0.01)), 2e-3),
+    "few_nodes_fine_arc": (dict(seed=86, width=21, height=19, sigma_theta=4 * DEG, n_nodes=10), 5e-4),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_cyl_vs_oracle(name):
+    kw, arc = CASES[name]
+    wl = W.config0() if kw is None else W.small(**kw)
+    say(f"cylindrical average {name}: arc {arc}")
+    hkl = _hkl(wl)
+    img, cnt, F, cull, off, idx = gpu_cyl(wl, hkl, arc)
+    boxes = O.cyl_boxes(wl, hkl)
+    assert np.array_equal(cull[:, :13], boxes)
+    lists = O.culling_lists(wl, hkl, boxes=boxes)
+    for t, lst in enumerate(lists):
+        assert np.array_equal(idx[off[t]:off[t + 1]], lst), t
+    P = O.prepare(wl, hkl=hkl, F=F, cull_extinct=False)
+    R, Z = O.pixel_rz(wl.geom)
+    ref, n_ref = O.cyl_at(P, R, Z, arc, count=True)
+    check(img, ref.reshape(img.shape), name)
+    say(f"  evaluations: GPU {cnt}, oracle {n_ref}")
+    assert abs(cnt - n_ref) <= 1e-4 * n_ref + 2
+
+
+def test_cyl_is_the_azimuthal_mean_of_a_tilt_free_pattern_symmetry():
+    """Without tilt the ring average is even in the detector x about the beam centre and in
+    the equator, like the gather pattern."""
+    wl = W.config0()
+    img, _, _, _, _, _ = gpu_cyl(wl, _hkl(wl), 2e-3, count=False)
+    assert np.abs(img - img[:, ::-1]).max() <= 1e-5 * img.max()
+    assert np.abs(img - img[::-1, :]).max() <= 1e-5 * img.max()
+
+
+def test_cyl_medium_reflection_subset_sampled_pixels():
+    """The medium workload at full detector size for 300 of its reflections (seeded pick),
+    with the ring step equal to the pixel pitch in reciprocal space; the oracle at sampled
+    pixels, lists bit-exact on their tiles."""
+    wl = W.config1()
+    arc = pitch(wl)
+    hkl = _hkl(wl)
+    pick_h = np.sort(np.random.default_rng(12).choice(hkl.shape[0], 300, replace=False))
+    hkl = np.ascontiguousarray(hkl[pick_h])
+    say(f"cylindrical average medium, 300 reflections, arc {arc:.3e}")
+    img, _, F, cull, off, idx = gpu_cyl(wl, hkl, arc, count=False)
+    H, Wd = img.shape
+    rng = np.random.default_rng(11)
+    flat = img.ravel()
+    strong = np.nonzero(flat > 1e-2 * flat.max())[0]
+    pick = np.concatenate([rng.choice(strong, 40, replace=False), rng.choice(flat.size, 40, replace=False),
+                           [int(np.argmax(flat))]])
+    tx_n = (Wd + 7) // 8
+    tiles = sorted({int((p // Wd) // 8 * tx_n + (p % Wd) // 8) for p in pick})
+    boxes = O.cyl_boxes(wl, hkl)
+    assert np.array_equal(cull[:, :13], boxes)
+    lists = O.culling_lists(wl, hkl, tiles=tiles, boxes=boxes)
+    for t, lst in zip(tiles, lists):
+        assert np.array_equal(idx[off[t]:off[t + 1]], lst), t
+    P = O.prepare(wl, hkl=hkl, F=F, cull_extinct=False)
+    R, Z = O.pixel_rz(wl.geom)
+    vals = O.cyl_at(P, R.ravel()[pick], Z.ravel()[pick], arc)
+    got = flat[pick].astype(np.float64)
+    big = vals > 1e-3 * vals.max()
+    err = np.abs(got[big] - vals[big]) / vals[big]
+    say(f"  per-pixel max rel err {err.max():.2e} over {int(big.sum())} pixels")
+    assert err.max() <= 1e-3
+    small = ~big
+    assert np.all(np.abs(got[small] - vals[small]) <= 1e-6 * vals.max())
+
+
+def test_cyl_argument_checks():
+    wl = W.config0()
+    model = B.make_model(wl)
+    z = torch.zeros(16, dtype=torch.float32, device="cuda")
+    o = torch.zeros(16, dtype=torch.int64, device="cuda")
+    i = torch.zeros(16, dtype=torch.int32, device="cuda")
+    for arc in (0.0, 1e-7, 1.0, float("nan")):
+        with pytest.raises(B.FdtbxError):
+            B.profile_cyl(model, z, z, z, o, i, arc)
