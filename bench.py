@@ -83,6 +83,7 @@ def parse():
     ap.add_argument("--no-tilt", action="store_true", help="skip the tilted-fibre forward leg")
     ap.add_argument("--no-lineshapes", action="store_true", help="skip the Gaussian/Hosemann lineshape legs")
     ap.add_argument("--no-splat", action="store_true", help="skip the forward-splat leg")
+    ap.add_argument("--no-cyl", action="store_true", help="skip the exact cylindrical-average leg")
     ap.add_argument("--batch-models", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -217,6 +218,54 @@ def bench_splat(args, n_r=8, n_s=64):
             "pass": "forward splat (binary64 sample geometry and projection, float32 direct sum)"}
 
 
+def bench_cyl(args, n_sub=300):
+    """Exact cylindrical average (periodic trapezoid rule over each pixel's ring, ring step
+    equal to the pixel pitch in reciprocal space) over the medium detector for a seeded
+    subset of the medium workload's reflections: every ring point within reach of a
+    reflection's support is evaluated, several hundred times the gather's evaluations per
+    reflection, so the full reflection list would take minutes per pattern."""
+    import numpy as np
+    import torch
+
+    import workloads as W
+    from paper_2608_23245_amd import atoms_to_device
+    from paper_2608_23245_amd import binding as B
+
+    wl = W.config1()
+    g = wl.geom
+    arc = g.pixel / g.distance / g.wavelength
+    model = B.make_model(wl)
+    ext = (wl.dis.g[0], wl.dis.g[1], wl.dis.g[2], wl.quad.extinction)
+    hkl_all = B.enumerate_hkl(model.cell, wl.quad.d_min, wl.quad.d_max, extinction=ext)
+    pick = np.sort(np.random.default_rng(12).choice(int(hkl_all.shape[0]), n_sub, replace=False))
+    hkl = hkl_all[torch.from_numpy(pick).cuda()].contiguous()
+    _, F2 = B.structure_factors(model.cell, atoms_to_device(wl.atoms), hkl, want_F=False)
+    refl, _ = B.reflection_prep(model, hkl, F2)
+    cull = B.cyl_records(model, hkl)
+    nodes = B.node_table(model)
+    pix, tile = B.pixel_map(model.geom)
+    off, idx = B.cull(model.geom, tile, cull)
+    B.profile_cyl(model, refl, nodes, pix, off, idx, arc)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(2)]
+    for e0, e1 in evs:
+        e0.record(stream)
+        img = B.profile_cyl(model, refl, nodes, pix, off, idx, arc)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
+    assert torch.isfinite(img).all() and img.max().item() > 0
+    n_evals = B.profile_cyl(model, refl, nodes, pix, off, idx, arc, count=True)
+    achieved = n_evals * SLOTS_PER_EVAL / (ms * 1e-3) / 1e12
+    return {"workload": f"medium detector, {n_sub} of its reflections (seeded pick), ring step {arc:.4g} 1/A",
+            "n_hkl": n_sub, "pairs": int(idx.shape[0]), "useful_evals": int(n_evals), "cyl_ms": ms,
+            "evals_per_s": n_evals / (ms * 1e-3), "kernel": "k_cyl<false, 0>",
+            "slots": {"achieved": achieved, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
+                      "frac": achieved / (PEAK_SLOTS / 1e12)},
+            "pass": "exact cylindrical average (float32 evaluation, binary64 ring geometry)"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -278,6 +327,9 @@ def main():
         log("forward, Gaussian and Hosemann lineshapes")
         out["lineshapes"] = bench_lineshapes(args)
         torch.cuda.empty_cache()
+    if not args.no_cyl:
+        log("cylindrical average leg")
+        out["cyl"] = bench_cyl(args)
     if not args.no_splat:
         log("forward splat")
         out["splat"] = bench_splat(args)
