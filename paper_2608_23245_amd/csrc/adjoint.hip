@@ -40,7 +40,9 @@ __global__ void __launch_bounds__(64) k_profile_adj(ProfParams q, const float* _
   __shared__ float4 qn[128];
   __shared__ float2 qd[128];
   __shared__ int bq[64];
-  adjoint_tile<LS>(q, refl, nodes, pix, tile, offsets, idx, grad_image, sums, blockIdx.x, qn, qd, bq);
+  const int t = tile_of_block(q, blockIdx.x);
+  if (t < 0) return;
+  adjoint_tile<LS>(q, refl, nodes, pix, tile, offsets, idx, grad_image, sums, t, qn, qd, bq);
 }
 
 __global__ void k_zero_f64(double* __restrict__ v, int64_t n) {
@@ -485,7 +487,7 @@ extern "C" int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(6 * n_hkl, 256)), dim3(256), 0, s, sums, 6 * n_hkl);
   FDTBX_LAUNCH_CHECK("adjoint zero");
-  const dim3 grid((unsigned)((int64_t)q.tiles_x * q.tiles_y));
+  const dim3 grid((unsigned)tile_grid(q));
   if (q.lineshape == FDTBX_LINESHAPE_GAUSSIAN)
     hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_GAUSSIAN>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
                        grad_image, sums);

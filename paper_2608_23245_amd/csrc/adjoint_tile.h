@@ -155,20 +155,20 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
         qd[pos] = *(const float2*)(nodes + (int64_t)FDTBX_NODE_FLOATS * k + 4);
       }
       qlen += __popcll(b);
-      __syncthreads();
+      wave_sync();
       if (qlen >= 64) {
         walk_queue_adj<LS>(qn, qd, 64, al, gp, q.half_m, q.tiny, hk, acc);
         qlen -= 64;
-        __syncthreads();
+        wave_sync();
         if (lane < qlen) {
           qn[lane] = qn[64 + lane];
           qd[lane] = qd[64 + lane];
         }
-        __syncthreads();
+        wave_sync();
       }
     });
     walk_queue_adj<LS>(qn, qd, qlen, al, gp, q.half_m, q.tiny, hk, acc);
-    __syncthreads();
+    wave_sync();
     bool any = false;
 #pragma unroll
     for (int c = 0; c < 6; ++c) {

@@ -55,7 +55,8 @@ __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict
   __shared__ int bq[64];
   const ProfParams& q = p.q;
   const int lane = threadIdx.x & 63;
-  const int t = blockIdx.x;
+  const int t = tile_of_block(q, blockIdx.x);
+  if (t < 0) return;
   const int tx = t % q.tiles_x, ty = t / q.tiles_x;
   const int pi_ = tx * FDTBX_TILE + (lane % FDTBX_TILE);
   const int pj = ty * FDTBX_TILE + (lane / FDTBX_TILE);
@@ -155,17 +156,17 @@ __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict
             qn[pos] = e;
           }
           qlen += __popcll(bal);
-          __syncthreads();
+          wave_sync();
           if (qlen >= 64) {
             walk_queue<COUNT, LS>(qn, 64, al, q.half_m, q.tiny, hk, accr, cnt);
             qlen -= 64;
-            __syncthreads();
+            wave_sync();
             if (lane < qlen) qn[lane] = qn[64 + lane];
-            __syncthreads();
+            wave_sync();
           }
         });
         walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, q.tiny, hk, accr, cnt);
-        __syncthreads();
+        wave_sync();
         accp += accr;
       }
       const double cn = cj * cd - sj * sd;
@@ -201,9 +202,11 @@ extern "C" int fdtbx_profile_cyl(const fdtbx_model* model, const float* refl, co
   CylParams p;
   prof_params(model, &p.q);
   p.arc = arc;
-  const int64_t n_tiles = (int64_t)p.q.tiles_x * p.q.tiles_y;
+  // plain tile order: the ring work of a few reflections concentrates on a few superblocks,
+  // and the grouped order would pile it onto few XCDs
+  p.q.sbw = 0;
   hipStream_t s = (hipStream_t)stream;
-  const dim3 grid((unsigned)n_tiles);
+  const dim3 grid((unsigned)tile_grid(p.q));
   unsigned long long* cp = (unsigned long long*)counts;
   if (counts) {
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, cp);

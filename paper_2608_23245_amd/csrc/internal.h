@@ -45,6 +45,15 @@ __device__ inline int64_t next_item(unsigned long long* counter) {
   return (int64_t)(((unsigned long long)hi << 32) | lo);
 }
 
+// Orders one wave's LDS accesses before and after this point (what __syncthreads does for a
+// one-wave workgroup) without a workgroup barrier, so that several independent waves can
+// share a workgroup.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
 // Reflection record slots (float32, FDTBX_REFL_FLOATS per reflection).
 enum ReflSlot {
   RS_W = 0,        // |F|^2 I_para

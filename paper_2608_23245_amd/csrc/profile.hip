@@ -38,7 +38,9 @@ __global__ void __launch_bounds__(64) k_profile(ProfParams q, const float* __res
   // queue of window nodes that can be inside the support of some pixel of the tile
   __shared__ float4 qn[128];
   __shared__ int bq[64];
-  profile_tile<COUNT, LS>(q, refl, nodes, pix, tile, offsets, idx, image, counts, blockIdx.x, qn, bq);
+  const int t = tile_of_block(q, blockIdx.x);
+  if (t < 0) return;
+  profile_tile<COUNT, LS>(q, refl, nodes, pix, tile, offsets, idx, image, counts, t, qn, bq);
 }
 
 // Batched models, persistent: every wave takes (model, tile) items from a shared counter
@@ -112,9 +114,8 @@ extern "C" int fdtbx_profile(const fdtbx_model* model, const float* refl, const 
   if (rc) return rc;
   ProfParams q;
   prof_params(model, &q);
-  int64_t n_tiles = (int64_t)q.tiles_x * q.tiles_y;
   hipStream_t s = (hipStream_t)stream;
-  const dim3 grid((unsigned)n_tiles);
+  const dim3 grid((unsigned)tile_grid(q));
   if (counts) {
     hipLaunchKernelGGL((k_profile<true, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
                        image, (unsigned long long*)counts);

@@ -20,7 +20,36 @@ struct ProfParams {
   float tiny;       // added to |y|: keeps sin(2 pi y)/y finite at y = 0, exact in float32 for |y| > 1e-5
   float margin;     // slack of the tile-level node test, in y units
   double delta;     // Lorentz regulariser
+  int32_t sbw;      // superblocks per tile row in the XCD-aware tile order; 0: plain order
 };
+
+// Tile order of the per-tile launches.  Workgroups are dealt to the 8 XCDs in round-robin
+// order and each XCD has its own L2.  Neighbouring tiles share most of their reflections,
+// so the tiles are grouped into kSuper x kSuper superblocks whose tiles run on one XCD in
+// consecutive dispatch slots, consecutive superblocks going to different XCDs (which keeps
+// the XCDs' loads balanced).  Used when there are at least 8 superblocks per XCD.
+constexpr int kXcds = 8, kSuper = 8;
+
+__host__ __device__ inline int32_t superblocks_per_row(int32_t tiles_x, int32_t tiles_y) {
+  const int64_t sbw = (tiles_x + kSuper - 1) / kSuper, sbh = (tiles_y + kSuper - 1) / kSuper;
+  return sbw * sbh >= 8 * kXcds ? (int32_t)sbw : 0;
+}
+
+// Workgroups of a per-tile launch (the padded superblock grid, or one per tile).
+__host__ __device__ inline int64_t tile_grid(const ProfParams& q) {
+  if (q.sbw == 0) return (int64_t)q.tiles_x * q.tiles_y;
+  const int64_t nsb = (int64_t)q.sbw * ((q.tiles_y + kSuper - 1) / kSuper);
+  return (int64_t)kXcds * kSuper * kSuper * ((nsb + kXcds - 1) / kXcds);
+}
+
+// Tile of workgroup b, or -1 for a padding workgroup (past the detector).
+__device__ inline int tile_of_block(const ProfParams& q, int b) {
+  if (q.sbw == 0) return b;
+  const int x = b % kXcds, k = b / kXcds;
+  const int sb = (k / (kSuper * kSuper)) * kXcds + x, i = k % (kSuper * kSuper);
+  const int tx = (sb % q.sbw) * kSuper + i % kSuper, ty = (sb / q.sbw) * kSuper + i / kSuper;
+  return tx < q.tiles_x && ty < q.tiles_y ? ty * q.tiles_x + tx : -1;
+}
 
 struct Window {
   int i1lo, i1hi, i2lo, i2hi;
@@ -107,8 +136,9 @@ __device__ static inline bool node_window(const ProfParams& q, const PairRec& re
                             rec.at(RS_RHO + 2), w);
 }
 
-// Window node wi -> (i1, i2) for a window nw1 nodes wide, through a float reciprocal
-// (exact integers below 2^24) with a one-step correction instead of an integer division.
+// Window node wi -> (i1, i2) for a window nw1 nodes wide, through an approximate float
+// reciprocal (integers below 2^24; the quotient is off by at most one) with a one-step
+// correction instead of an integer division.
 __device__ static inline void window_node(int wi, int nw1, float inv_nw1, int* i1, int* i2) {
   int q2 = (int)((float)wi * inv_nw1);
   int q1 = wi - q2 * nw1;
@@ -149,7 +179,7 @@ __device__ __forceinline__ void scan_window(const ProfParams& q, const float* __
   const int nw1 = w.i1hi - w.i1lo + 1;
   const int nwin = nw1 * (w.i2hi - w.i2lo + 1);
   if (nwin <= kPlainScanMax) {
-    const float inv_nw1 = 1.0f / (float)nw1;
+    const float inv_nw1 = __builtin_amdgcn_rcpf((float)nw1);
     for (int w0 = 0; w0 < nwin; w0 += 64) {
       const int wi = w0 + lane;
       float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -176,7 +206,7 @@ __device__ __forceinline__ void scan_window(const ProfParams& q, const float* __
   const int b2lo = w.i2lo / FDTBX_NODE_BLOCK, b2hi = w.i2hi / FDTBX_NODE_BLOCK;
   const int nb1 = b1hi - b1lo + 1;
   const int nbw = nb1 * (b2hi - b2lo + 1);
-  const float inv_nb1 = 1.0f / (float)nb1;
+  const float inv_nb1 = __builtin_amdgcn_rcpf((float)nb1);
   float aB[3], aG1[3], aG2[3], sl[3];
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
@@ -190,11 +220,12 @@ __device__ __forceinline__ void scan_window(const ProfParams& q, const float* __
   for (int c0 = 0; c0 < nbw; c0 += 64) {
     const int bi = c0 + lane;
     bool keep = false;
-    int bid = 0;
+    int base = 0;  // first node of the block: i1 in the low 16 bits, i2 in the high 16 bits
     if (bi < nbw) {
       int d1, d2;
       window_node(bi, nb1, inv_nb1, &d1, &d2);
-      bid = (b2lo + d2) * nbs + (b1lo + d1);
+      const int bid = (b2lo + d2) * nbs + (b1lo + d1);
+      base = ((b1lo + d1) * FDTBX_NODE_BLOCK) | (((b2lo + d2) * FDTBX_NODE_BLOCK) << 16);
       const float4 cm = *(const float4*)(blocks + (int64_t)FDTBX_NODE_FLOATS * bid);
       const float4 rr = *(const float4*)(blocks + (int64_t)FDTBX_NODE_FLOATS * bid + 4);
       keep = true;
@@ -207,8 +238,8 @@ __device__ __forceinline__ void scan_window(const ProfParams& q, const float* __
     }
     const unsigned long long b = __ballot(keep);
     const int nk = __popcll(b);
-    if (keep) bq[(int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u))] = bid;
-    __syncthreads();
+    if (keep) bq[(int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u))] = base;
+    wave_sync();
     for (int k0 = 0; k0 < nk; k0 += kPer) {
       const int kk = k0 + lane / kBB;
       float4 e = make_float4(0.f, 0.f, 0.f, 0.f);
@@ -217,8 +248,8 @@ __device__ __forceinline__ void scan_window(const ProfParams& q, const float* __
       if (kk < nk) {
         const int bb = bq[kk];
         const int sub = lane % kBB;
-        const int i1 = (bb % nbs) * FDTBX_NODE_BLOCK + sub % FDTBX_NODE_BLOCK;
-        const int i2 = (bb / nbs) * FDTBX_NODE_BLOCK + sub / FDTBX_NODE_BLOCK;
+        const int i1 = (bb & 0xffff) + sub % FDTBX_NODE_BLOCK;
+        const int i2 = (bb >> 16) + sub / FDTBX_NODE_BLOCK;
         if (i1 >= w.i1lo && i1 <= w.i1hi && i2 >= w.i2lo && i2 <= w.i2hi) {
           k = i2 * q.n + i1;
           keepn = node_e(k, &e);
@@ -226,7 +257,7 @@ __device__ __forceinline__ void scan_window(const ProfParams& q, const float* __
       }
       sink(keepn, k, e);
     }
-    __syncthreads();
+    wave_sync();
   }
 }
 
@@ -244,6 +275,7 @@ __host__ __device__ inline void prof_params(const fdtbx_model* model, ProfParams
   q->tiny = 1.0e-12f;
   q->margin = 1.0e-3f;
   q->delta = model->quad.delta;
+  q->sbw = superblocks_per_row(q->tiles_x, q->tiles_y);
 }
 
 }  // namespace fdtbx

@@ -141,17 +141,17 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
         qn[pos] = e;
       }
       qlen += __popcll(b);
-      __syncthreads();
+      wave_sync();
       if (qlen >= 64) {
         walk_queue<COUNT, LS>(qn, 64, al, q.half_m, tiny, hk, accr, cnt);
         qlen -= 64;
-        __syncthreads();
+        wave_sync();
         if (lane < qlen) qn[lane] = qn[64 + lane];
-        __syncthreads();
+        wave_sync();
       }
     });
     walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, tiny, hk, accr, cnt);
-    __syncthreads();
+    wave_sync();
     if (!COUNT) acc = fmaf(f.at(RS_WK), accr, acc);
   }
   if (COUNT) {

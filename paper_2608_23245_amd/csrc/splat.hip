@@ -143,17 +143,17 @@ __global__ void __launch_bounds__(64) k_splat(SplatParams p, const int32_t* __re
           qn[pos] = e;
         }
         qlen += __popcll(bal);
-        __syncthreads();
+        wave_sync();
         if (qlen >= 64) {
           walk_queue<COUNT, LS>(qn, 64, al, q.half_m, q.tiny, hk, accr, cnt);
           qlen -= 64;
-          __syncthreads();
+          wave_sync();
           if (lane < qlen) qn[lane] = qn[64 + lane];
-          __syncthreads();
+          wave_sync();
         }
       });
       walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, q.tiny, hk, accr, cnt);
-      __syncthreads();
+      wave_sync();
     }
     if (!COUNT && in && accr != 0.0f) {
       int64_t px[2];
