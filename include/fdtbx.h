@@ -14,7 +14,8 @@
  *   - Laboratory frame of the tutorial's "Unit cell and reciprocal-space frame":
  *     crystal c along +z (the fibre axis), b in the yz-plane; the beam runs along
  *     a* = +x, normal to the fibre (the notebook's check |beam . fibre| <= 1e-3
- *     holds exactly).  Fibre and detector tilt are zero.
+ *     holds exactly).  The fibre may be tilted toward the beam (fdtbx_geometry.tilt);
+ *     the detector stays normal to the beam.
  *   - Detector images are float32 [height][width], row-major, row 0 at the bottom
  *     (origin='lower'); pixel (i, j) has its centre at
  *     y = (i + 1/2 - center_x) pixel, z = (j + 1/2 - center_y) pixel.
@@ -24,6 +25,9 @@
  *   - Every call is asynchronous on `stream` (a hipStream_t; NULL is the null
  *     stream) unless it says it synchronises.  Argument checks run on the host
  *     before any launch; on error nothing is launched and no output is written.
+ *   - Empty inputs are valid: with n_hkl = 0 images come out zero, culling lists
+ *     empty and gradients zero, and the per-reflection pointers may be NULL; with
+ *     n_atoms = 0 the structure factors are zero and the atom pointers may be NULL.
  *   - Return value 0 on success, a negative FDTBX_ERR_* code otherwise;
  *     fdtbx_error_string() describes it.  No exceptions cross the ABI.
  */
@@ -39,7 +43,7 @@ extern "C" {
 
 enum {
   FDTBX_OK = 0,
-  FDTBX_ERR_INVALID_ARGUMENT = -1, /* null pointer, non-positive size, widths both zero, NaN, ... */
+  FDTBX_ERR_INVALID_ARGUMENT = -1, /* null pointer, negative size, widths both zero, NaN, ... */
   FDTBX_ERR_GEOMETRY = -2,         /* distance/pixel/wavelength <= 0, cell not a valid parallelepiped */
   FDTBX_ERR_BUFFER_TOO_SMALL = -3, /* an output or workspace capacity is too small; see the call */
   FDTBX_ERR_HIP = -4,              /* a HIP runtime call failed; fdtbx_last_hip_error() has the code */

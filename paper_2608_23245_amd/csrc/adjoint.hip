@@ -477,11 +477,13 @@ int launch_batch_backward(const fdtbx_batch_entry* ent, int32_t n_models, const 
 extern "C" int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
                                      const double* tile, const int64_t* offsets, const int32_t* idx, int64_t n_hkl,
                                      const float* grad_image, double* sums, void* stream) {
-  if (!model || !refl || !nodes || !pix || !tile || !offsets || !idx || !grad_image || !sums)
-    return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
-  if (n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be positive");
+  if (!model) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be non-negative");
   int rc = check_model(model);
   if (rc) return rc;
+  if (n_hkl == 0) return FDTBX_OK;  // no reflections: nothing to sum
+  if (!refl || !nodes || !pix || !tile || !offsets || !idx || !grad_image || !sums)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
   ProfParams q;
   prof_params(model, &q);
   hipStream_t s = (hipStream_t)stream;
@@ -509,10 +511,12 @@ extern "C" size_t fdtbx_adjoint_finish_workspace(int64_t n_hkl) {
 extern "C" int fdtbx_adjoint_finish(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* refl,
                                     const double* sums, const float* F, float* dF2, double* d_globals, void* ws,
                                     size_t ws_bytes, void* stream) {
-  if (!model || !hkl || !refl || !sums || !F || !d_globals || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
-  if (n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be positive");
+  if (!model || !d_globals) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be non-negative");
   int rc = check_model(model);
   if (rc) return rc;
+  if (n_hkl == 0) return fill(d_globals, (int64_t)kNG, 0.0, (hipStream_t)stream);
+  if (!hkl || !refl || !sums || !F || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
   if (ws_bytes < fdtbx_adjoint_finish_workspace(n_hkl)) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "finish workspace too small");
   FinishParams p;
   const double len[3] = {model->cell.a, model->cell.b, model->cell.c};
@@ -545,9 +549,20 @@ extern "C" int fdtbx_sf_adjoint(const fdtbx_cell* cell, int64_t n_atoms, const f
                                 const float* B, const float* occ, const int32_t* type, const float* ff, int32_t n_types,
                                 const int32_t* hkl, int64_t n_hkl, const float* F, const float* dF2, float* d_x, float* d_y,
                                 float* d_z, float* d_B, float* d_occ, void* ws, size_t ws_bytes, void* stream) {
-  if (!cell || !x || !y || !z || !B || !occ || !type || !ff || !hkl || !F || !dF2 || !ws)
+  if (!cell) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_atoms < 0 || n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_atoms and n_hkl must be non-negative");
+  if (n_atoms == 0) return FDTBX_OK;
+  if (n_hkl == 0) {  // no reflections: every atom gradient is zero
+    hipStream_t s0 = (hipStream_t)stream;
+    float* const outs[5] = {d_x, d_y, d_z, d_B, d_occ};
+    for (float* o : outs) {
+      const int r0 = fill(o, n_atoms, 0.0f, s0);
+      if (r0) return r0;
+    }
+    return FDTBX_OK;
+  }
+  if (!x || !y || !z || !B || !occ || !type || !ff || !hkl || !F || !dF2 || !ws)
     return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
-  if (n_atoms <= 0 || n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_atoms and n_hkl must be positive");
   if (n_types < 1 || n_types > kSAMaxTypes) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_types must be in 1..16");
   int rc = check_cell(cell);
   if (rc) return rc;

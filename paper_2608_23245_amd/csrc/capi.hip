@@ -120,18 +120,19 @@ extern "C" const char* fdtbx_error_string(int code) {
 extern "C" int fdtbx_last_hip_error(void) { return g_hip; }
 
 extern "C" size_t fdtbx_pattern_workspace(const fdtbx_model* model, int64_t n_hkl, int64_t pair_cap) {
-  if (!model || check_model(model) || n_hkl <= 0 || pair_cap < 0) return 0;
+  if (!model || check_model(model) || n_hkl < 0 || pair_cap < 0) return 0;
   return layout(model, n_hkl, pair_cap).total;
 }
 
 extern "C" int fdtbx_profile_pattern(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F2,
                                      float* image, int64_t pair_cap, int64_t* pairs_needed, void* ws, size_t ws_bytes,
                                      void* stream) {
-  if (!model || !hkl || !F2 || !image || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
-  if (n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be positive");
+  if (!model || !image || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be non-negative");
   if (pair_cap < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "pair_cap must be non-negative");
   int rc = check_model(model);
   if (rc) return rc;
+  if (n_hkl > 0 && (!hkl || !F2)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
   PatternLayout L = layout(model, n_hkl, pair_cap);
   if (ws_bytes < L.total) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "pattern workspace too small");
   char* w = (char*)ws;
@@ -157,7 +158,8 @@ extern "C" int fdtbx_profile_pattern(const fdtbx_model* model, const int32_t* hk
 }
 
 extern "C" size_t fdtbx_backward_workspace(int64_t n_hkl, int64_t n_atoms) {
-  if (n_hkl <= 0) return 0;
+  if (n_hkl < 0) return 0;
+  if (n_hkl == 0) return 256;  // nothing is used; a non-zero size keeps callers' allocations valid
   size_t b = align_up((size_t)n_hkl * 6 * sizeof(double), 256);
   b += align_up(fdtbx_adjoint_finish_workspace(n_hkl), 256);
   b += align_up((size_t)n_hkl * sizeof(float), 256);
@@ -171,11 +173,23 @@ extern "C" int fdtbx_pattern_backward(const fdtbx_model* model, const int32_t* h
                                       const float* occ, const int32_t* type, const float* ff, int32_t n_types, float* d_x,
                                       float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals, float* dF2,
                                       void* ws, size_t ws_bytes, void* stream) {
-  if (!model || !hkl || !F || !grad_image || !fwd_ws || !d_globals || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
-  if (n_hkl <= 0 || pair_cap < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "bad sizes");
+  if (!model || !grad_image || !fwd_ws || !d_globals || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl < 0 || pair_cap < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "bad sizes");
   int rc = check_model(model);
   if (rc) return rc;
   const bool atoms = d_x || d_y || d_z || d_B || d_occ;
+  if (n_hkl == 0) {  // no reflections: every gradient is zero
+    hipStream_t s0 = (hipStream_t)stream;
+    rc = fill(d_globals, (int64_t)FDTBX_N_GLOBALS, 0.0, s0);
+    if (rc || !atoms) return rc;
+    float* const outs[5] = {d_x, d_y, d_z, d_B, d_occ};
+    for (float* o : outs) {
+      rc = fill(o, n_atoms, 0.0f, s0);
+      if (rc) return rc;
+    }
+    return FDTBX_OK;
+  }
+  if (!hkl || !F) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
   if (atoms && (n_atoms <= 0 || !x || !y || !z || !B || !occ || !type || !ff))
     return fail(FDTBX_ERR_INVALID_ARGUMENT, "atom arrays required for atom gradients");
   PatternLayout L = layout(model, n_hkl, pair_cap);

@@ -629,10 +629,12 @@ extern "C" int fdtbx_pixel_map(const fdtbx_geometry* geom, double* pix, double* 
 
 extern "C" int fdtbx_reflection_prep(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F2,
                                      float* refl, double* cull, void* stream) {
-  if (!model || !hkl || !F2 || !refl || !cull) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
-  if (n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be positive");
+  if (!model) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be non-negative");
   int rc = check_model(model);
   if (rc) return rc;
+  if (n_hkl == 0) return FDTBX_OK;
+  if (!hkl || !F2 || !refl || !cull) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
   PrepParams p;
   make_frame(model->cell, &p.f);
   for (int i = 0; i < 3; ++i) {
@@ -654,10 +656,12 @@ extern "C" int fdtbx_reflection_prep(const fdtbx_model* model, const int32_t* hk
 }
 
 extern "C" int fdtbx_cyl_records(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, double* cull, void* stream) {
-  if (!model || !hkl || !cull) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
-  if (n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be positive");
+  if (!model) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be non-negative");
   int rc = check_model(model);
   if (rc) return rc;
+  if (n_hkl == 0) return FDTBX_OK;
+  if (!hkl || !cull) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
   PrepParams p;
   make_frame(model->cell, &p.f);
   for (int i = 0; i < 3; ++i) {
@@ -699,11 +703,17 @@ extern "C" size_t fdtbx_cull_workspace(const fdtbx_geometry* geom, int64_t n_hkl
 extern "C" int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_t n_hkl, const double* cull,
                           int64_t* offsets, int32_t* idx, int64_t cap, int64_t* n_pairs, void* ws, size_t ws_bytes,
                           void* stream) {
-  if (!geom || !tile || !cull || !offsets || !n_pairs || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
-  if (n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be positive");
+  if (!geom || !tile || !offsets || !n_pairs) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be non-negative");
   if (n_hkl > (int64_t)INT32_MAX) return fail(FDTBX_ERR_UNSUPPORTED, "more than 2^31 reflections");
   int rc = check_geometry(geom);
   if (rc) return rc;
+  if (n_hkl == 0) {  // every list empty
+    *n_pairs = 0;
+    return fill(offsets, ceil_div(geom->width, FDTBX_TILE) * ceil_div(geom->height, FDTBX_TILE) + 1, (int64_t)0,
+                (hipStream_t)stream);
+  }
+  if (!cull || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
   if (ws_bytes < fdtbx_cull_workspace(geom, n_hkl)) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "cull workspace too small");
   CullParams q;
   cull_params(geom, n_hkl, &q);

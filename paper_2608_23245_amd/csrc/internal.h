@@ -29,6 +29,20 @@ int check_model(const fdtbx_model* m);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// v[0..n) = x, by a kernel (hipMemsetAsync nodes do not belong in captured graphs).
+template <class T>
+__global__ void k_fill(T* __restrict__ v, int64_t n, T x) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) v[i] = x;
+}
+template <class T>
+inline int fill(T* v, int64_t n, T x, hipStream_t s) {
+  if (n <= 0 || !v) return FDTBX_OK;
+  hipLaunchKernelGGL(k_fill<T>, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, s, v, n, x);
+  FDTBX_LAUNCH_CHECK("fill");
+  return FDTBX_OK;
+}
 // Node-table rows for n nodes per side: node records, then block records.
 __host__ __device__ inline int64_t node_rows(int64_t n) {
   const int64_t nb = (n + FDTBX_NODE_BLOCK - 1) / FDTBX_NODE_BLOCK;

@@ -209,10 +209,16 @@ extern "C" int fdtbx_structure_factors(const fdtbx_cell* cell, int64_t n_atoms, 
                                        const float* z, const float* B, const float* occ, const int32_t* type,
                                        const float* ff, int32_t n_types, const int32_t* hkl, int64_t n_hkl, float* F,
                                        float* F2, void* ws, size_t ws_bytes, void* stream) {
-  if (!cell || !x || !y || !z || !B || !occ || !type || !ff || !hkl || !ws)
-    return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (!cell) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_atoms < 0 || n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_atoms and n_hkl must be non-negative");
+  if (n_hkl == 0) return FDTBX_OK;
   if (!F && !F2) return fail(FDTBX_ERR_INVALID_ARGUMENT, "F and F2 both NULL");
-  if (n_atoms <= 0 || n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_atoms and n_hkl must be positive");
+  if (n_atoms == 0) {  // no atoms: F = 0
+    int r0 = fill(F, 2 * n_hkl, 0.0f, (hipStream_t)stream);
+    if (r0) return r0;
+    return fill(F2, n_hkl, 0.0f, (hipStream_t)stream);
+  }
+  if (!x || !y || !z || !B || !occ || !type || !ff || !hkl || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
   if (n_types < 1 || n_types > kMaxTypes) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_types must be in 1..16");
   if (n_hkl > (int64_t)0x7fffffff * kSFThreads) return fail(FDTBX_ERR_UNSUPPORTED, "too many reflections");
   int rc = check_cell(cell);

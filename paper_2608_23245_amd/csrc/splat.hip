@@ -183,9 +183,10 @@ using namespace fdtbx;
 
 extern "C" int fdtbx_splat(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* refl, const float* nodes,
                            int32_t n_r, int32_t n_s, float* image, int64_t* counts, void* stream) {
-  if (!model || !hkl || !refl || !nodes) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (!model || !nodes) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
   if (!counts && !image) return fail(FDTBX_ERR_INVALID_ARGUMENT, "image is NULL");
-  if (n_hkl <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be positive");
+  if (n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be non-negative");
+  if (n_hkl > 0 && (!hkl || !refl)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
   if (n_r < 1 || n_r > 1024 || n_s < 1 || n_s > 4096) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_r must be in 1..1024, n_s in 1..4096");
   if ((int64_t)n_hkl * n_r > 0x7fffffffll) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl * n_r exceeds the launch grid");
   int rc = check_model(model);
@@ -219,6 +220,7 @@ extern "C" int fdtbx_splat(const fdtbx_model* model, const int32_t* hkl, int64_t
   hipLaunchKernelGGL(k_zero_splat, dim3((unsigned)ceil_div(npix, 256)), dim3(256), 0, s, img, npix,
                      (unsigned long long*)counts);
   FDTBX_LAUNCH_CHECK("splat zero");
+  if (n_hkl == 0) return FDTBX_OK;
   const dim3 grid((unsigned)(n_hkl * n_r));
   unsigned long long* cp = (unsigned long long*)counts;
   if (counts)

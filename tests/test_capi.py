@@ -92,6 +92,25 @@ def test_model_checks(lib):
     assert rc == -3
 
 
+def test_empty_inputs_are_valid_calls(lib):
+    """n_hkl = 0 (an empty shell) and n_atoms = 0 are valid: the calls below return before
+    any device work, with NULL per-reflection (or per-atom) pointers."""
+    import workloads as W
+    from paper_2608_23245_amd import binding as B
+    m = B.make_model(W.config0())
+    cell = m.cell
+    assert lib.fdtbx_pattern_workspace(ctypes.byref(m), 0, 1000) > 0
+    assert lib.fdtbx_pattern_workspace(ctypes.byref(m), -1, 1000) == 0
+    assert lib.fdtbx_backward_workspace(0, 10) > 0
+    assert lib.fdtbx_reflection_prep(ctypes.byref(m), None, 0, None, None, None, None) == 0
+    assert lib.fdtbx_reflection_prep(ctypes.byref(m), None, -1, None, None, None, None) == -1
+    assert lib.fdtbx_cyl_records(ctypes.byref(m), None, 0, None, None) == 0
+    assert lib.fdtbx_structure_factors(ctypes.byref(cell), 10, *([None] * 7), 1, None, 0, None, None, None, 0, None) == 0
+    assert lib.fdtbx_profile_adjoint(ctypes.byref(m), *([None] * 6), 0, None, None, None) == 0
+    assert lib.fdtbx_sf_adjoint(ctypes.byref(cell), 0, *([None] * 7), 1, None, 5, *([None] * 7), None, 0, None) == 0
+    assert lib.fdtbx_structure_factors(ctypes.byref(cell), -1, *([None] * 7), 1, None, 5, None, None, None, 0, None) == -1
+
+
 def test_node_rows(lib):
     """Node table size: n^2 node records plus ceil(n/4)^2 block records; 0 outside 1..256."""
     from paper_2608_23245_amd import binding as B
