@@ -111,75 +111,79 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
   const double R = in ? pix[2 * ((int64_t)j * q.W + i) + 0] : 1.0e30;
   const double Z = in ? pix[2 * ((int64_t)j * q.W + i) + 1] : 0.0;
   const float gp = in ? grad_image[(int64_t)j * q.W + i] * (float)(q.delta / (R + q.delta)) : 0.0f;
-  const double bRlo = tile[8 * (int64_t)t + 0], bRhi = tile[8 * (int64_t)t + 1];
-  const double bZlo = tile[8 * (int64_t)t + 2], bZhi = tile[8 * (int64_t)t + 3];
-  const float Rlo = (float)bRlo, Rhi = (float)bRhi, Zlo = (float)bZlo, Zhi = (float)bZhi;
+  const TileBox box = {tile[8 * (int64_t)t + 0], tile[8 * (int64_t)t + 1], tile[8 * (int64_t)t + 2],
+                       tile[8 * (int64_t)t + 3]};
   const int64_t p0 = offsets[t], p1 = offsets[t + 1];
   // a tile whose pixels all carry zero weight adds nothing
   if (__ballot(gp != 0.0f) == 0ull) return;
-  // the next pair's reflection index is read one iteration ahead
-  int32_t r_next = p0 < p1 ? idx[p0] : 0;
-  for (int64_t pp = p0; pp < p1; ++pp) {
-    const int32_t r = r_next;
-    r_next = idx[pp + 1 < p1 ? pp + 1 : pp];
-    PairRec f;
-    load_pair(refl + (int64_t)FDTBX_REFL_FLOATS * r, f);
-    const double RD = f.at_f64(RS_RD);
-    const double ZD = f.at_f64(RS_ZD);
-    const float dR = (float)(R - RD), dZ = (float)(Z - ZD);
-    float al[3], lo[3], hi[3], Bv[3], G1[3], G2[3];
-    const float dRl = (float)(bRlo - RD), dRh = (float)(bRhi - RD);
-    const float dZl = (float)(bZlo - ZD), dZh = (float)(bZhi - ZD);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const float tr = f.at(RS_TR + a), tz = f.at(RS_TZ + a);
-      al[a] = fmaf(tr, dR, tz * dZ);
-      const float r1 = tr * dRl, r2 = tr * dRh, z1 = tz * dZl, z2 = tz * dZh;
-      lo[a] = fminf(r1, r2) + fminf(z1, z2) - q.half_m - q.margin;
-      hi[a] = fmaxf(r1, r2) + fmaxf(z1, z2) + q.half_m + q.margin;
-      Bv[a] = f.at(RS_B + a);
-      G1[a] = f.at(RS_G1 + a);
-      G2[a] = f.at(RS_G2 + a);
+  // 64 pairs at a time, set up lane-parallel as in the forward tile loop
+  for (int64_t base = p0; base < p1; base += 64) {
+    int32_t rl = 0;
+    int w01 = 0, w23 = 0;
+    float lol[3] = {0.f, 0.f, 0.f}, hil[3] = {0.f, 0.f, 0.f};
+    bool ok = false;
+    if (base + lane < p1) {
+      rl = idx[base + lane];
+      ok = pair_setup(q, refl + (int64_t)FDTBX_REFL_FLOATS * rl, box, &w01, &w23, lol, hil);
     }
-    Window w;
-    if (!node_window(q, f, Rlo, Rhi, Zlo, Zhi, &w)) continue;
-    HoseK hk = {};
-    if (LS == FDTBX_LINESHAPE_HOSEMANN) hose_constants(refl + (int64_t)FDTBX_REFL_FLOATS * r, hk);
-    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    int qlen = 0;
-    scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int k, float4 e) {
-      const unsigned long long b = __ballot(keep);
-      if (keep) {
-        const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
-        qn[pos] = e;
-        qd[pos] = *(const float2*)(nodes + (int64_t)FDTBX_NODE_FLOATS * k + 4);
+    unsigned long long todo = __ballot(ok);
+    while (todo) {
+      const int src = (int)__builtin_ctzll(todo);
+      todo &= todo - 1;
+      const int32_t r = lane_int(rl, src);
+      const int a01 = lane_int(w01, src), a23 = lane_int(w23, src);
+      const Window w = {a01 & 0xffff, a01 >> 16, a23 & 0xffff, a23 >> 16};
+      float al[3], lo[3], hi[3], Bv[3], G1[3], G2[3];
+      PairRec f;
+      load_pair(refl + (int64_t)FDTBX_REFL_FLOATS * r, f);
+      const float dR = (float)(R - f.at_f64(RS_RD)), dZ = (float)(Z - f.at_f64(RS_ZD));
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        al[a] = fmaf(f.at(RS_TR + a), dR, f.at(RS_TZ + a) * dZ);
+        lo[a] = lane_float(lol[a], src);
+        hi[a] = lane_float(hil[a], src);
+        Bv[a] = f.at(RS_B + a);
+        G1[a] = f.at(RS_G1 + a);
+        G2[a] = f.at(RS_G2 + a);
       }
-      qlen += __popcll(b);
-      wave_sync();
-      if (qlen >= 64) {
-        walk_queue_adj<LS>(qn, qd, 64, al, gp, q.half_m, q.tiny, hk, acc);
-        qlen -= 64;
-        wave_sync();
-        if (lane < qlen) {
-          qn[lane] = qn[64 + lane];
-          qd[lane] = qd[64 + lane];
+      HoseK hk = {};
+      if (LS == FDTBX_LINESHAPE_HOSEMANN) hose_constants(refl + (int64_t)FDTBX_REFL_FLOATS * r, hk);
+      float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      int qlen = 0;
+      scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int k, float4 e) {
+        const unsigned long long b = __ballot(keep);
+        if (keep) {
+          const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
+          qn[pos] = e;
+          qd[pos] = *(const float2*)(nodes + (int64_t)FDTBX_NODE_FLOATS * k + 4);
         }
+        qlen += __popcll(b);
         wave_sync();
+        if (qlen >= 64) {
+          walk_queue_adj<LS>(qn, qd, 64, al, gp, q.half_m, q.tiny, hk, acc);
+          qlen -= 64;
+          wave_sync();
+          if (lane < qlen) {
+            qn[lane] = qn[64 + lane];
+            qd[lane] = qd[64 + lane];
+          }
+          wave_sync();
+        }
+      });
+      walk_queue_adj<LS>(qn, qd, qlen, al, gp, q.half_m, q.tiny, hk, acc);
+      wave_sync();
+      bool any = false;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) {
+        float v = acc[c];
+        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        acc[c] = v;
+        any |= v != 0.0f;
       }
-    });
-    walk_queue_adj<LS>(qn, qd, qlen, al, gp, q.half_m, q.tiny, hk, acc);
-    wave_sync();
-    bool any = false;
+      if (lane == 0 && any) {
 #pragma unroll
-    for (int c = 0; c < 6; ++c) {
-      float v = acc[c];
-      for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-      acc[c] = v;
-      any |= v != 0.0f;
-    }
-    if (lane == 0 && any) {
-#pragma unroll
-      for (int c = 0; c < 6; ++c) unsafeAtomicAdd(&sums[6 * (int64_t)r + c], (double)acc[c]);
+        for (int c = 0; c < 6; ++c) unsafeAtomicAdd(&sums[6 * (int64_t)r + c], (double)acc[c]);
+      }
     }
   }
 }

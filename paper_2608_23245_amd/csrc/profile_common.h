@@ -119,21 +119,58 @@ __device__ static inline bool node_window_ranges(const ProfParams& q, float r0, 
   return w->i1lo <= w->i1hi && w->i2lo <= w->i2hi;
 }
 
-// Node window of a tile box in (R, Z): the query points p = R e_perp + Z z have
-// p.v = R (e_perp.v) + Z v_z, extreme at the box corners.
-__device__ static inline bool node_window(const ProfParams& q, const PairRec& rec, float Rlo, float Rhi, float Zlo, float Zhi,
-                                          Window* w) {
-  auto range = [&](float cR, float cZ, float* lo, float* hi) {
-    float a = Rlo * cR, b = Rhi * cR, c = Zlo * cZ, d = Zhi * cZ;
-    *lo = fminf(a, b) + fminf(c, d);
-    *hi = fmaxf(a, b) + fmaxf(c, d);
+// Per-pair set-up of the forward and adjoint tile loops, done lane-parallel (each lane one
+// pair of the tile's list, so that this uniform per-pair arithmetic costs a 64th of a wave
+// instruction per pair): the pair's node window, packed as two ints (low and high 16 bits:
+// first and last index along d1, then along d2; the query points p = R e_perp + Z z of the
+// tile's (R, Z) box have p.v = R (e_perp.v) + Z v_z, extreme at the box corners), and the
+// tile's alpha box, the ranges of
+// alpha_i over the tile's (R, Z) box (linear in R, Z: extremes at the corners) widened by the
+// support half-width and the margin.  Returns false if the window is empty.
+struct TileBox {
+  double Rlo, Rhi, Zlo, Zhi;
+};
+
+__device__ static inline bool pair_setup(const ProfParams& q, const float* __restrict__ rec, const TileBox& b, int* w01,
+                                         int* w23, float* lo, float* hi) {
+  const float4 x0 = *(const float4*)(rec + 4);
+  const float4 x3 = *(const float4*)(rec + 12);
+  const float4 x4 = *(const float4*)(rec + 16);
+  const float4 x5 = *(const float4*)(rec + 20);
+  const float4 x6 = *(const float4*)(rec + 24);
+  const float4 x7 = *(const float4*)(rec + 28);
+  const float4 x8 = *(const float4*)(rec + 32);
+  const float tr[3] = {x3.w, x4.x, x4.y}, tz[3] = {x4.z, x4.w, x5.x};
+  const double RD = __hiloint2double(__float_as_int(x5.w), __float_as_int(x5.z));
+  const double ZD = __hiloint2double(__float_as_int(x6.y), __float_as_int(x6.x));
+  const float dRl = (float)(b.Rlo - RD), dRh = (float)(b.Rhi - RD);
+  const float dZl = (float)(b.Zlo - ZD), dZh = (float)(b.Zhi - ZD);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float r1 = tr[a] * dRl, r2 = tr[a] * dRh, z1 = tz[a] * dZl, z2 = tz[a] * dZh;
+    lo[a] = fminf(r1, r2) + fminf(z1, z2) - q.half_m - q.margin;
+    hi[a] = fmaxf(r1, r2) + fmaxf(z1, z2) + q.half_m + q.margin;
+  }
+  const float Rlo = (float)b.Rlo, Rhi = (float)b.Rhi, Zlo = (float)b.Zlo, Zhi = (float)b.Zhi;
+  auto range = [&](float cR, float cZ, float* l, float* h) {
+    const float a = Rlo * cR, bb = Rhi * cR, c = Zlo * cZ, d = Zhi * cZ;
+    *l = fminf(a, bb) + fminf(c, d);
+    *h = fmaxf(a, bb) + fmaxf(c, d);
   };
   float sl, sh, l1, h1, l2, h2;
-  range(rec.at(RS_CS), rec.at(RS_CS + 1), &sl, &sh);
-  range(rec.at(RS_C1), rec.at(RS_C1 + 1), &l1, &h1);
-  range(rec.at(RS_C2), rec.at(RS_C2 + 1), &l2, &h2);
-  return node_window_ranges(q, rec.at(RS_R0), sl, sh, l1, h1, l2, h2, rec.at(RS_RHO), rec.at(RS_RHO + 1),
-                            rec.at(RS_RHO + 2), w);
+  range(x6.z, x6.w, &sl, &sh);
+  range(x7.x, x7.y, &l1, &h1);
+  range(x7.z, x7.w, &l2, &h2);
+  Window w;
+  if (!node_window_ranges(q, x0.x, sl, sh, l1, h1, l2, h2, x8.x, x8.y, x8.z, &w)) return false;
+  *w01 = w.i1lo | (w.i1hi << 16);
+  *w23 = w.i2lo | (w.i2hi << 16);
+  return true;
+}
+
+__device__ __forceinline__ int lane_int(int v, int src) { return __builtin_amdgcn_readlane(v, src); }
+__device__ __forceinline__ float lane_float(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
 // Window node wi -> (i1, i2) for a window nw1 nodes wide, through an approximate float
