@@ -176,7 +176,7 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
         float v = acc[c];
-        for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+        v = wave_sum(v);
         acc[c] = v;
         any |= v != 0.0f;
       }

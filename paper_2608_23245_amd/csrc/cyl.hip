@@ -29,23 +29,6 @@ struct CylParams {
   double arc;
 };
 
-__device__ static inline float wmin(float v) {
-  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ static inline float wmax(float v) {
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ static inline int wmin_i(int v) {
-  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ static inline int wmax_i(int v) {
-  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
 template <bool COUNT, int LS>
 __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict__ refl, const float* __restrict__ nodes,
                                             const double* __restrict__ pix, const int64_t* __restrict__ offsets,
@@ -120,7 +103,7 @@ __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict
       }
     }
     const bool has = jl <= jh;
-    const int J0 = wmin_i(has ? jl : 0x7fffffff), J1 = wmax_i(has ? jh : -0x7fffffff);
+    const int J0 = wave_min_i32(has ? jl : 0x7fffffff), J1 = wave_max_i32(has ? jh : -0x7fffffff);
     if (J0 > J1) continue;
     HoseK hk = {};
     if (LS == FDTBX_LINESHAPE_HOSEMANN && !COUNT) hose_constants(rec, hk);
@@ -134,17 +117,17 @@ __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         al[a] = act ? fmaf(tr[a], fX, fmaf(ta[a], fY, tz[a] * fZ)) : 1.0e30f;
-        lo[a] = wmin(act ? al[a] : INFINITY) - q.half_m - q.margin;
-        hi[a] = wmax(act ? al[a] : -INFINITY) + q.half_m + q.margin;
+        lo[a] = wave_min(act ? al[a] : INFINITY) - q.half_m - q.margin;
+        hi[a] = wave_max(act ? al[a] : -INFINITY) + q.half_m + q.margin;
       }
       // the ring point's coordinates along S, e1, e2
       const float Rc = (float)(R * cj), Rs = (float)(R * sj), fz = (float)Z;
       const float pS = fmaf(Rc, f.at(RS_CS), fmaf(Rs, az[0], fz * f.at(RS_CS + 1)));
       const float p1v = fmaf(Rc, f.at(RS_C1), fmaf(Rs, az[1], fz * f.at(RS_C1 + 1)));
       const float p2v = fmaf(Rc, f.at(RS_C2), fmaf(Rs, az[2], fz * f.at(RS_C2 + 1)));
-      const float sl = wmin(act ? pS : INFINITY), sh = wmax(act ? pS : -INFINITY);
-      const float l1 = wmin(act ? p1v : INFINITY), h1 = wmax(act ? p1v : -INFINITY);
-      const float l2 = wmin(act ? p2v : INFINITY), h2 = wmax(act ? p2v : -INFINITY);
+      const float sl = wave_min(act ? pS : INFINITY), sh = wave_max(act ? pS : -INFINITY);
+      const float l1 = wave_min(act ? p1v : INFINITY), h1 = wave_max(act ? p1v : -INFINITY);
+      const float l2 = wave_min(act ? p2v : INFINITY), h2 = wave_max(act ? p2v : -INFINITY);
       Window w;
       if (node_window_ranges(q, r0, sl, sh, l1, h1, l2, h2, rS, r1, r2, &w)) {
         float accr = 0.0f;

@@ -68,6 +68,56 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
 }
 
+// Wave-wide reductions (all 64 lanes active) through DPP row shifts and row broadcasts
+// instead of LDS permutes: shifts by 1, 2, 4, 8 leave each row's total in its lane 15, the
+// broadcasts of lanes 15 and 31 then combine the rows, and lane 63 holds the result, which is
+// read into a scalar register (uniform).  Lanes whose source lies outside their row combine
+// with the operation's identity.  Float minima and maxima run on an order-preserving integer
+// image of the bits (x ^ 0x7fffffff for negative x), so each step is one integer min or max
+// with its DPP operand.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_i32(int old, int v) {
+  return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_f32(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWS, 0xf, true));
+}
+__device__ __forceinline__ int float_order(float f) {
+  const int b = __float_as_int(f);
+  return b ^ ((b >> 31) & 0x7fffffff);
+}
+__device__ __forceinline__ float order_float(int k) { return __int_as_float(k ^ ((k >> 31) & 0x7fffffff)); }
+__device__ __forceinline__ int wave_min_i32(int v) {
+  v = min(v, dpp_i32<0x111, 0xf>(INT32_MAX, v));
+  v = min(v, dpp_i32<0x112, 0xf>(INT32_MAX, v));
+  v = min(v, dpp_i32<0x114, 0xf>(INT32_MAX, v));
+  v = min(v, dpp_i32<0x118, 0xf>(INT32_MAX, v));
+  v = min(v, dpp_i32<0x142, 0xa>(INT32_MAX, v));
+  v = min(v, dpp_i32<0x143, 0xc>(INT32_MAX, v));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ int wave_max_i32(int v) {
+  v = max(v, dpp_i32<0x111, 0xf>(INT32_MIN, v));
+  v = max(v, dpp_i32<0x112, 0xf>(INT32_MIN, v));
+  v = max(v, dpp_i32<0x114, 0xf>(INT32_MIN, v));
+  v = max(v, dpp_i32<0x118, 0xf>(INT32_MIN, v));
+  v = max(v, dpp_i32<0x142, 0xa>(INT32_MIN, v));
+  v = max(v, dpp_i32<0x143, 0xc>(INT32_MIN, v));
+  return __builtin_amdgcn_readlane(v, 63);
+}
+__device__ __forceinline__ float wave_min(float v) { return order_float(wave_min_i32(float_order(v))); }
+__device__ __forceinline__ float wave_max(float v) { return order_float(wave_max_i32(float_order(v))); }
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_f32<0x111, 0xf>(v);
+  v += dpp_f32<0x112, 0xf>(v);
+  v += dpp_f32<0x114, 0xf>(v);
+  v += dpp_f32<0x118, 0xf>(v);
+  v += dpp_f32<0x142, 0xa>(v);
+  v += dpp_f32<0x143, 0xc>(v);
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
+}
+
 // Reflection record slots (float32, FDTBX_REFL_FLOATS per reflection).
 enum ReflSlot {
   RS_W = 0,        // |F|^2 I_para

@@ -61,14 +61,6 @@ __device__ static inline void splat_pixels(const SplatParams& p, const double* S
   }
 }
 
-__device__ static inline float wave_min(float v) {
-  for (int o = 32; o >= 1; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ static inline float wave_max(float v) {
-  for (int o = 32; o >= 1; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
-  return v;
-}
 
 template <bool COUNT, int LS>
 __global__ void __launch_bounds__(64) k_splat(SplatParams p, const int32_t* __restrict__ hkl, const float* __restrict__ refl,
