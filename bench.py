@@ -311,7 +311,7 @@ def main():
         "profile_kernel_ms": prof_ms,
         "profile_kernel_evals_per_s": n_evals / (prof_ms * 1e-3),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(), "kernel": "k_profile<false, 0>",
+                     "traffic": measured_traffic(), "kernel": "k_profile<false, 0>", "sources_sha": profile_source_sha(),
                      "slots_per_eval": SLOTS_PER_EVAL},
     }
     if not args.no_cpu:
