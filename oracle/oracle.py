@@ -630,7 +630,9 @@ def splat(wl, P: Prepared, n_r, n_s, count=False):
 def splat_project(S, geom):
     """Detector pixels (column, row; fractional, pixel centres at integer + 1/2 from the
     pixel's lower edge) of the two diffraction-condition rotations of fibre-frame points S,
-    by the algebraic form used by the splat (see oracle_splat); NaN where none exists."""
+    by the algebraic form used by the splat (see oracle_splat); both coordinates NaN where
+    no rotation satisfies the condition (Eq. valid) or the diffracted ray runs away from the
+    detector (k_x <= 0, which oracle_splat skips as well)."""
     S = np.atleast_2d(np.asarray(S, dtype=np.float64))
     tilt = float(getattr(geom, "tilt", 0.0))
     st, ct = math.sin(tilt), math.cos(tilt)
@@ -641,11 +643,14 @@ def splat_project(S, geom):
     with np.errstate(invalid="ignore"):
         sy = np.where(sy2 >= 0.0, np.sqrt(sy2), np.nan)
     kx = 1.0 / geom.wavelength + sx
+    bad = ~(sy2 >= 0.0) | ~(kx > 0.0)
     out = []
     for sgn in (1.0, -1.0):
         y = geom.distance * (sgn * sy) / kx
         z = geom.distance * sz / kx
-        out.append(np.stack([y / geom.pixel + geom.center_x, z / geom.pixel + geom.center_y], axis=1))
+        o = np.stack([y / geom.pixel + geom.center_x, z / geom.pixel + geom.center_y], axis=1)
+        o[bad] = np.nan
+        out.append(o)
     return out[0], out[1]
 
 
@@ -664,6 +669,19 @@ def cyl_at(P: Prepared, R, Z, arc, use_skip=True, count=False):
                     ctypes.byref(n_ev))
     del keep
     return (out, int(n_ev.value)) if count else out
+
+
+def profile_points(P: Prepared, ridx, points):
+    """W_h I_h(p) for reflection ridx[k] at Cartesian points[k] (Eq. direct_sum, one
+    reflection's term of the pattern sum before the Lorentz factor; see oracle_profile_points)."""
+    ridx = np.ascontiguousarray(np.ravel(ridx), dtype=np.int32)
+    pts = np.ascontiguousarray(np.reshape(points, (-1, 3)), dtype=np.float64)
+    out = np.zeros(pts.shape[0])
+    prob, keep = _c_problem(P, False)
+    _c().oracle_profile_points(ctypes.byref(prob), ctypes.c_int64(pts.shape[0]), ctypes.c_void_p(ridx.ctypes.data),
+                               ctypes.c_void_p(pts.ctypes.data), ctypes.c_void_p(out.ctypes.data))
+    del keep
+    return out
 
 
 def cyl_boxes(wl, hkl):

@@ -207,6 +207,13 @@ void oracle_profile_table(const oracle_problem* P, int64_t n_pix, const double* 
   }
 }
 
+/* W_h I_h(p) at arbitrary points: out[k] = W[h] profile_at(h, points[k]), h = ridx[k]
+ * (the term of reflection h in Eq. direct_sum's pattern sum, before the Lorentz factor). */
+void oracle_profile_points(const oracle_problem* P, int64_t n, const int32_t* ridx, const double* points, double* out) {
+#pragma omp parallel for schedule(dynamic, 64)
+  for (int64_t k = 0; k < n; ++k) out[k] = P->W[ridx[k]] * profile_at(P, ridx[k], &points[3 * k], NULL);
+}
+
 /* d/dN [N sinc^2(N u)] = sin(2 pi N u)/(pi u N) - sin^2(pi N u)/(pi^2 u^2 N^2); at u = 0 it is 1. */
 static double laue_axis_dN(double N, double u) {
   if (u == 0.0) return 1.0;

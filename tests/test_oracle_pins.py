@@ -850,3 +850,40 @@ def test_oracle_intensity_model_none_and_dot_product():
     Jv = (O.pattern(w1, O.prepare(w1, hkl=hkl, cull_extinct=False), use_skip=False)
           - O.pattern(w2, O.prepare(w2, hkl=hkl, cull_extinct=False), use_skip=False)) / (2 * h)
     assert abs(np.sum(Jv * G) - g1["sigma_theta"]) <= 1e-6 * abs(g1["sigma_theta"])
+
+
+def test_profile_points_single_node_closed_form():
+    """With one node the shell quadrature is the node at D alone: at p = D + sum_i u_i a*_i
+    (so that a_i.(p - D) = u_i) the term of Eq. direct_sum is W r0^2 omega prod_i N_i sinc^2(N_i u_i)
+    inside the support |u_i| <= m/N_i and zero outside (sinc from numpy)."""
+    wl = W.small(52, n_atoms=5, n_nodes=1, size_A=(45.0, 55.0, 65.0), sigma_theta=2 * DEG)
+    P = O.prepare(wl, hkl=np.array([[1, 2, 1], [0, 0, 2], [-2, 1, 0]], np.int32), cull_extinct=False)
+    rng = np.random.default_rng(3)
+    ridx, pts, want = [], [], []
+    for r in range(3):
+        N = P.N[r]
+        for _ in range(40):
+            u = rng.uniform(-2.0 * wl.quad.m, 2.0 * wl.quad.m, 3) / N
+            ridx.append(r)
+            pts.append(P.D[r] + u @ P.astar)
+            inside = np.all(np.abs(u) <= wl.quad.m / N)
+            want.append(P.W[r] * P.r0[r] ** 2 * P.nodes.omega[0] * np.prod(N * np.sinc(N * u) ** 2) if inside else 0.0)
+    got = O.profile_points(P, np.array(ridx), np.array(pts))
+    assert np.count_nonzero(want) > 10 and np.count_nonzero(np.array(want) == 0.0) > 10
+    np.testing.assert_allclose(got, want, rtol=1e-10, atol=0.0)
+
+
+def test_profile_points_sum_to_the_pattern():
+    """Each pixel of the pattern is L(R) times the sum over reflections of their terms at the
+    pixel's query points p*_h = R e_perp,h + Z z (Eqs. direct_sum, lorentz)."""
+    wl = W.small(53, width=9, height=7, sigma_theta=3 * DEG, gamma_theta=1 * DEG, g=(0.02, 0.02, 0.0))
+    P = O.prepare(wl)
+    R, Z = O.pixel_rz(wl.geom)
+    R, Z = R.ravel()[::5], Z.ravel()[::5]
+    n_h = P.hkl.shape[0]
+    pts = (R[:, None, None] * P.ep[None, :, :] + Z[:, None, None] * np.array([0.0, 0.0, 1.0])).reshape(-1, 3)
+    vals = O.profile_points(P, np.tile(np.arange(n_h), R.size), pts).reshape(R.size, n_h)
+    L = P.delta / (R + P.delta)
+    ref = O.pattern_at(P, R, Z, use_skip=False)
+    assert ref.max() > 0
+    np.testing.assert_allclose(L * vals.sum(1), ref, rtol=1e-11, atol=1e-14 * ref.max())
