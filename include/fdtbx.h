@@ -306,6 +306,36 @@ int fdtbx_profile_cyl(const fdtbx_model* model, const float* refl, const float* 
  *   cull device float64 [n_hkl][FDTBX_CULL_DOUBLES] output */
 int fdtbx_cyl_records(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, double* cull, void* stream);
 
+/* ------------------------------------------------------------------ test-facing points */
+/* The term of one reflection in the sum of Eq. direct_sum at arbitrary reciprocal points:
+ *   out[k] = W_h r0^2 sum_nodes omega Z(p_k - s_node),  h = ridx[k],
+ * i.e. the pattern's summand at p_k before the Lorentz factor (Eq. lorentz), with Z the
+ * model's lineshape and the support test of fdtbx_profile.  One thread per point.
+ *   hkl     device int32 [n_hkl][3] (the list refl was prepared from)
+ *   refl    device float32 [n_hkl][FDTBX_REFL_FLOATS] (fdtbx_reflection_prep)
+ *   nodes   device node table of the model (fdtbx_node_table)
+ *   ridx    device int32 [n]: reflection of each point (index into hkl)
+ *   points  device float64 [n][3]: Cartesian points of the laboratory frame, 1/A
+ *   out     device float32 [n] output
+ * n = 0 is valid (nothing is read or written). */
+int fdtbx_profile_points(const fdtbx_model* model, const int32_t* hkl, const float* refl, const float* nodes,
+                         const int32_t* ridx, const double* points, int64_t n, float* out, void* stream);
+
+/* Forward Ewald projection (section "Analytical Solution of the Ewald Diffraction
+ * Condition"): the detector positions of the two rotations about the (tilted) fibre axis n that
+ * bring the point S onto the Ewald sphere (Eqs. harmonic, solutions).  S is given in the fibre
+ * frame: S_z along n and (S_x, S_y) normal to it, so that only sqrt(S_x^2 + S_y^2) and S_z
+ * matter (with no tilt this is the laboratory frame).  The projection is written
+ * algebraically: the rotated S has S_x = -lambda |S|^2/2, S.n = Z_S and
+ * S_y = +-sqrt(|S|^2 - S_x^2 - S_z^2); k_out = x/lambda + S meets the detector at
+ * y = distance k_y/k_x, z = distance k_z/k_x.
+ *   S    device float64 [n][3], 1/A
+ *   out  device float64 [n][4]: (column, row) of the +S_y rotation, then of the -S_y one, as
+ *        fractional pixel coordinates (pixel (i, j) covers [i, i+1) x [j, j+1)); all four NaN
+ *        where no rotation satisfies the condition (Eq. valid) or k_x <= 0.
+ * Binary64 without fused multiply-adds. */
+int fdtbx_ewald_project(const fdtbx_geometry* geom, const double* S, int64_t n, double* out, void* stream);
+
 /* ------------------------------------------------------------------ one-call pattern
  * fdtbx_profile_pattern runs reflection_prep, node_table, pixel_map, cull and
  * profile into a caller workspace laid out by fdtbx_pattern_workspace(model,

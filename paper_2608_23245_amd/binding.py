@@ -94,6 +94,8 @@ _SIGS = {
     "fdtbx_profile_cyl": (ctypes.c_int, [ctypes.c_void_p] * 6 + [ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                                                    ctypes.c_void_p]),
     "fdtbx_cyl_records": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "fdtbx_profile_points": (ctypes.c_int, [ctypes.c_void_p] * 6 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
+    "fdtbx_ewald_project": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "fdtbx_splat": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                    ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdtbx_pattern_workspace": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_int64]),
@@ -328,6 +330,26 @@ def profile_cyl(model: Model, refl, nodes, pix, offsets, idx, arc: float, count=
     _check(lib().fdtbx_profile_cyl(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(offsets), _ptr(idx),
                                    float(arc), _ptr(img), None, _stream()))
     return img
+
+
+def profile_points(model: Model, hkl, refl, nodes, ridx, points) -> torch.Tensor:
+    """fdtbx_profile_points: W_h I_h(p) float32 [n] for reflection ridx[k] at points[k]."""
+    n = int(points.shape[0])
+    _dev(ridx, torch.int32, "ridx")
+    _dev(points, torch.float64, "points")
+    out = torch.empty(n, dtype=torch.float32, device=points.device)
+    _check(lib().fdtbx_profile_points(ctypes.byref(model), _ptr(hkl), _ptr(refl), _ptr(nodes), _ptr(ridx), _ptr(points), n,
+                                      _ptr(out), _stream()))
+    return out
+
+
+def ewald_project(geom: Geometry, S) -> torch.Tensor:
+    """fdtbx_ewald_project: float64 [n][4] detector positions of both rotations (NaN if none)."""
+    n = int(S.shape[0])
+    _dev(S, torch.float64, "S")
+    out = torch.empty((n, 4), dtype=torch.float64, device=S.device)
+    _check(lib().fdtbx_ewald_project(ctypes.byref(geom), _ptr(S), n, _ptr(out), _stream()))
+    return out
 
 
 def splat(model: Model, hkl, refl, nodes, n_r: int, n_s: int, count=False):

@@ -2,8 +2,9 @@
 
 Every translation unit is compiled for gfx950 only, with packed-FP32 code
 generation disabled.  exact.hip (enumeration, pixel map, culling records and
-lists), splat.hip (sample positions and their detector pixels) and cyl.hip (ring
-quadrature sizes) are compiled without floating-point contraction so that their binary64 predicates are
+lists), splat.hip (sample positions and their detector pixels), cyl.hip (ring
+quadrature sizes) and points.hip (the Ewald projection) are compiled without
+floating-point contraction so that their binary64 predicates are
 evaluated exactly as written.
 """
 from __future__ import annotations
@@ -26,6 +27,7 @@ SOURCES = {
     "adjoint.hip": [],
     "splat.hip": ["-ffp-contract=off"],
     "cyl.hip": ["-ffp-contract=off"],
+    "points.hip": ["-ffp-contract=off"],
     "capi.hip": [],
 }
 

@@ -74,11 +74,13 @@ __device__ __forceinline__ void walk_queue(const float4* qn, int cnt, const floa
                                            const HoseK& hk, float& accr, unsigned long long& cnt_eval) {
   qn += threadIdx.y;
   float4 nxt = qn[0];
+  float part = 0.0f;  // a block sum of at most 64 terms, added once: keeps long sums accurate
   for (int jj = 0; jj < cnt; ++jj) {
     const float4 cur = nxt;
     nxt = qn[jj + 1];
-    eval_node<COUNT, LS>(cur, al[0], al[1], al[2], half_m, tiny, hk, accr, cnt_eval);
+    eval_node<COUNT, LS>(cur, al[0], al[1], al[2], half_m, tiny, hk, part, cnt_eval);
   }
+  accr += part;
 }
 
 template <bool COUNT, int LS>

@@ -1,0 +1,118 @@
+"""Parity of the test-facing entry points (fdtbx_profile_points, fdtbx_ewald_project, through
+the C ABI) with the oracle: the per-reflection term of Eq. direct_sum at arbitrary points to
+the pattern tolerances, and the algebraic Ewald projection to binary64 rounding (NaN where
+Eq. valid fails)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2608_23245_amd import binding as B  # noqa: E402
+
+DEG = math.pi / 180
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+CASES = {
+    "voigt": dict(seed=91, sigma_theta=3 * DEG, gamma_theta=1 * DEG, g=(0.02, 0.02, 0.0)),
+    "gaussian_damped": dict(seed=92, sigma_theta=2 * DEG, lineshape=1, B_axis=(4.0, 9.0, 2.5)),
+    "hosemann": dict(seed=93, sigma_theta=2 * DEG, gamma_theta=0.5 * DEG, lineshape=2, g=(0.03, 0.02, 0.01)),
+    "tilted_skew": dict(seed=94, sigma_theta=2 * DEG, gamma_theta=1 * DEG, tilt=22 * DEG,
+                        cell=W.Cell(9.5, 12.0, 14.0, 80 * DEG, 100 * DEG, 110 * DEG)),
+}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_profile_points_vs_oracle(name):
+    wl = W.small(**CASES[name], width=16, height=14, n_nodes=16)
+    say(f"profile points {name}")
+    hkl = O.enumerate_hkl(wl.cell, wl.quad.d_min, wl.quad.d_max)
+    hkl = np.ascontiguousarray(hkl[~O.extinct_mask(hkl, wl.dis, wl.quad.extinction)])
+    F = O.structure_factors_c(hkl, wl.cell, wl.atoms)
+    P = O.prepare(wl, hkl=hkl, F=F, cull_extinct=False)
+    rng = np.random.default_rng(CASES[name]["seed"])
+    half = 0.5 if wl.dis.lineshape == 2 else wl.quad.m
+    ridx, pts = [], []
+    for r in rng.choice(hkl.shape[0], min(40, hkl.shape[0]), replace=False):
+        u = rng.uniform(-1.2, 1.2, (24, 3)) * (half / P.N[r])
+        pts.append(P.D[r] + u @ P.astar)
+        # and points on the shell at the reflection's azimuth (what the pattern evaluates)
+        ang = rng.uniform(-0.2, 0.2, 8)
+        rr = P.r0[r] * (1.0 + rng.uniform(-0.01, 0.01, 8))
+        Sd = P.S[r][None, :] * np.cos(ang)[:, None] + P.e2[r][None, :] * np.sin(ang)[:, None]
+        pts.append(rr[:, None] * Sd)
+        ridx += [r] * 32
+    ridx = np.array(ridx, np.int32)
+    pts = np.concatenate(pts)
+    model = B.make_model(wl)
+    h = torch.from_numpy(hkl).cuda()
+    F2 = torch.as_tensor((F.real ** 2 + F.imag ** 2).astype(np.float32)).cuda()
+    refl, _ = B.reflection_prep(model, h, F2)
+    nodes = B.node_table(model)
+    got = B.profile_points(model, h, refl, nodes, torch.from_numpy(ridx).cuda(),
+                           torch.from_numpy(np.ascontiguousarray(pts)).cuda()).cpu().numpy().astype(np.float64)
+    ref = O.profile_points(P, ridx, pts)
+    assert ref.max() > 0 and np.count_nonzero(ref) > 100
+    r_l2 = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    big = ref > 1e-3 * ref.max()
+    px = float(np.max(np.abs(got[big] - ref[big]) / ref[big]))
+    say(f"  {pts.shape[0]} points: rel-L2 {r_l2:.2e}, max rel {px:.2e} over {int(big.sum())}")
+    assert r_l2 <= 1e-4 and px <= 1e-3
+    assert np.all(np.abs(got[~big]) <= 2e-3 * ref.max())
+
+
+@pytest.mark.parametrize("tilt", [0.0, 22 * DEG, -35 * DEG])
+def test_ewald_project_vs_oracle(tilt):
+    wl = W.small(95, width=64, height=48, tilt=tilt, center=(30.3, 21.7))
+    say(f"ewald projection, tilt {math.degrees(tilt):.0f} deg")
+    rng = np.random.default_rng(7)
+    S = rng.uniform(-0.9, 0.9, (20000, 3))
+    S[:5] = 0.0
+    got = B.ewald_project(B.make_model(wl).geom, torch.from_numpy(S).cuda()).cpu().numpy()
+    p1, p2 = O.splat_project(S, wl.geom)
+    ref = np.concatenate([p1, p2], axis=1)
+    nan_g, nan_r = np.isnan(got), np.isnan(ref)
+    assert np.array_equal(nan_g, nan_r)
+    ok = ~nan_r
+    assert ok.sum() > 1000 and nan_r.sum() > 1000
+    err = np.abs(got[ok] - ref[ok])
+    say(f"  {int(ok.all(1).sum())} projected, {int(nan_r.all(1).sum())} invalid, max |diff| {err.max():.2e} px")
+    assert err.max() <= 1e-9 * max(1.0, np.abs(ref[ok]).max())
+    # the algebraic projection lands where the paper's rotation angles about the fibre axis
+    # put the point (Eqs. harmonic, solutions; the oracle's route, pixel centres at integers)
+    n = np.array([math.sin(tilt), 0.0, math.cos(tilt)])
+    m = np.array([math.cos(tilt), 0.0, -math.sin(tilt)])
+    sel = np.nonzero(ok.all(1))[0]
+    sel = sel[sel >= 5][:300]   # S = 0 (the direct beam) has no defined rotation angle
+    lab = np.hypot(S[sel, 0], S[sel, 1])[:, None] * m[None, :] + S[sel, 2][:, None] * n[None, :]
+    e1, e2 = O.ewald_project(lab, wl.geom, fibre=n)
+    for k, i in enumerate(sel):
+        want = sorted([tuple(e1[k]), tuple(e2[k])])
+        mine = sorted([tuple(got[i, 0:2] - 0.5), tuple(got[i, 2:4] - 0.5)])
+        np.testing.assert_allclose(mine, want, rtol=0, atol=1e-6)
+
+
+def test_points_argument_checks():
+    wl = W.config0()
+    model = B.make_model(wl)
+    z = torch.zeros((4, 3), dtype=torch.float64, device="cuda")
+    with pytest.raises(ValueError):
+        B.ewald_project(model.geom, z.float())
+    L = B.lib()
+    assert L.fdtbx_ewald_project(B.ctypes.byref(model.geom), None, 0, None, None) == 0
+    assert L.fdtbx_ewald_project(B.ctypes.byref(model.geom), None, -1, None, None) == -1
+    assert L.fdtbx_profile_points(B.ctypes.byref(model), *([None] * 5), 0, None, None) == 0
