@@ -161,6 +161,11 @@ def bench_tilted(args):
 # Gaussian: 3 subtractions, max3, compare, sum of squares (3), scale (1), accumulate (1)
 # and one half-rate exp2; Hosemann: 3 subtractions, max3, compare, 3 denominators, 2
 # products, accumulate and three half-rate cosines and one reciprocal.
+# issue slots per useful evaluation of the adjoint kernel (k_profile_adj, Laue), the |y| + tiny
+# guards not credited as in the forward: 39 full-rate operations (support test 5, the product
+# of the y 2, the three sinc factors 8, their squares and product 5, G P and the three weighted
+# sums 4, the three d/dN_i terms 15) and 3 sin + 3 cos + 1 rcp
+ADJ_SLOTS_PER_EVAL = 39 + 7 * TRANS_SLOTS
 SLOTS_PER_EVAL_LS = {"gaussian": 10 + 1 * TRANS_SLOTS, "hosemann": 11 + 4 * TRANS_SLOTS}
 
 
@@ -393,9 +398,32 @@ def bench_fwd_bwd(args):
     bwd_ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     loss = float((w * (res["img"] - target) ** 2).sum().item())
     assert np.isfinite(loss) and torch.isfinite(res["glob"]).all()
+    # the profile adjoint kernel alone, on the same pattern and pixel weights, against its
+    # evaluations (the forward's support-passing triples: tiles it skips carry no weight)
+    model = eng.plan.model
+    _, F2 = B.structure_factors(eng.cell, atoms, eng.hkl)
+    refl, cull = B.reflection_prep(model, eng.hkl, F2)
+    nodes = B.node_table(model)
+    pix, tile = B.pixel_map(model.geom)
+    off, idx = B.cull(model.geom, tile, cull)
+    G = res["G"]
+    B.profile_adjoint(model, refl, nodes, pix, tile, off, idx, G)
+    torch.cuda.synchronize()
+    aev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(2)]
+    for e0, e1 in aev:
+        e0.record(stream)
+        B.profile_adjoint(model, refl, nodes, pix, tile, off, idx, G)
+        e1.record(stream)
+    torch.cuda.synchronize()
+    adj_ms = float(np.mean([a.elapsed_time(b) for a, b in aev]))
+    n_evals = B.profile(model, refl, nodes, pix, tile, off, idx, count=True)
+    achieved = n_evals * ADJ_SLOTS_PER_EVAL / (adj_ms * 1e-3) / 1e12
     return {"workload": "refinement: medium model vs perturbed target (xyz N(0,0.1 A), B x1.2, sigma 3.5 deg, g .035), "
                         "loss sum w (I - T)^2, w = 1/(T + 1e-3 max T)",
             "ms_per_step": ms, "backward_ms": bwd_ms, "forward_ms": ms - bwd_ms, "loss": loss,
+            "profile_adjoint_ms": adj_ms, "useful_evals": int(n_evals), "kernel": "k_profile_adj<0>",
+            "slots": {"achieved": achieved, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
+                      "frac": achieved / (PEAK_SLOTS / 1e12), "slots_per_eval": ADJ_SLOTS_PER_EVAL},
             "steps": args.steps, "pass": "forward + adjoint (atoms xyz/B/occ, sigma, gamma, N_base, g)"}
 
 

@@ -10,10 +10,10 @@
 // Mapping: one 64-lane wave per 8x8 pixel tile over the tile's list under the cylindrical
 // culling description (fdtbx_cyl_records).  Per (tile, reflection) each lane bounds the part
 // of its ring that can reach the reflection's support (the ball of radius rho_B about D) and
-// the wave steps a shared index j over the union of those ranges; at each j the 64 ring
-// points are treated like the splat's samples: node window from their coordinates, the node
-// queue of the profile kernel, and one evaluation per lane.  cos and sin of j dphi come from
-// a binary64 rotation recurrence per lane.
+// the wave steps a shared index j over the union of those ranges, kJB indices at a time; the
+// 64 x kJB ring points of a step are treated like the splat's samples: node window from their
+// coordinates, the node queue of the profile kernel, and kJB evaluations per lane and queued
+// node.  cos and sin of j dphi come from a binary64 rotation recurrence per lane.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -28,6 +28,25 @@ struct CylParams {
   ProfParams q;
   double arc;
 };
+
+// Ring indices evaluated together: they share the node window, queue and walk.
+constexpr int kJB = 8;
+
+// The queue walk of walk_queue, each entry evaluated at the lane's kJB ring points.
+template <bool COUNT, int LS>
+__device__ __forceinline__ void walk_ring(const float4* qn, int cnt, const float (*al)[3], float half_m, float tiny,
+                                          const HoseK& hk, float& accr, unsigned long long& cnt_eval) {
+  qn += threadIdx.y;
+  float4 nxt = qn[0];
+  float part = 0.0f;
+  for (int jj = 0; jj < cnt; ++jj) {
+    const float4 cur = nxt;
+    nxt = qn[jj + 1];
+#pragma unroll
+    for (int u = 0; u < kJB; ++u) eval_node<COUNT, LS>(cur, al[u][0], al[u][1], al[u][2], half_m, tiny, hk, part, cnt_eval);
+  }
+  accr += part;
+}
 
 template <bool COUNT, int LS>
 __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict__ refl, const float* __restrict__ nodes,
@@ -108,26 +127,45 @@ __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict
     HoseK hk = {};
     if (LS == FDTBX_LINESHAPE_HOSEMANN && !COUNT) hose_constants(rec, hk);
     double cj = cos((double)J0 * dphi), sj = sin((double)J0 * dphi);
+    const float fZ = (float)(Z - ZD), fz = (float)Z;
     float accp = 0.0f;
-    for (int jj = J0; jj <= J1; ++jj) {
-      const bool act = has && jj >= jl && jj <= jh;
-      const double X = R * cj - RD, Y = R * sj;
-      const float fX = (float)X, fY = (float)Y, fZ = (float)(Z - ZD);
-      float al[3], lo[3], hi[3];
+    // kJB consecutive ring indices share one node window, queue and walk
+    for (int jb = J0; jb <= J1; jb += kJB) {
+      float al[kJB][3];
+      float amin[3] = {INFINITY, INFINITY, INFINITY}, amax[3] = {-INFINITY, -INFINITY, -INFINITY};
+      float pmin[3] = {INFINITY, INFINITY, INFINITY}, pmax[3] = {-INFINITY, -INFINITY, -INFINITY};
+#pragma unroll
+      for (int u = 0; u < kJB; ++u) {
+        const int jj = jb + u;
+        const bool act = has && jj >= jl && jj <= jh;
+        const float fX = (float)(R * cj - RD), fY = (float)(R * sj);
+        // the ring point's coordinates along S, e1, e2
+        const float Rc = (float)(R * cj), Rs = (float)(R * sj);
+        const float pv[3] = {fmaf(Rc, f.at(RS_CS), fmaf(Rs, az[0], fz * f.at(RS_CS + 1))),
+                             fmaf(Rc, f.at(RS_C1), fmaf(Rs, az[1], fz * f.at(RS_C1 + 1))),
+                             fmaf(Rc, f.at(RS_C2), fmaf(Rs, az[2], fz * f.at(RS_C2 + 1)))};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float v = fmaf(tr[a], fX, fmaf(ta[a], fY, tz[a] * fZ));
+          al[u][a] = act ? v : 1.0e30f;
+          amin[a] = act ? fminf(amin[a], v) : amin[a];
+          amax[a] = act ? fmaxf(amax[a], v) : amax[a];
+          pmin[a] = act ? fminf(pmin[a], pv[a]) : pmin[a];
+          pmax[a] = act ? fmaxf(pmax[a], pv[a]) : pmax[a];
+        }
+        const double cn = cj * cd - sj * sd;
+        sj = sj * cd + cj * sd;
+        cj = cn;
+      }
+      float lo[3], hi[3];
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
-        al[a] = act ? fmaf(tr[a], fX, fmaf(ta[a], fY, tz[a] * fZ)) : 1.0e30f;
-        lo[a] = wave_min(act ? al[a] : INFINITY) - q.half_m - q.margin;
-        hi[a] = wave_max(act ? al[a] : -INFINITY) + q.half_m + q.margin;
+        lo[a] = wave_min(amin[a]) - q.half_m - q.margin;
+        hi[a] = wave_max(amax[a]) + q.half_m + q.margin;
       }
-      // the ring point's coordinates along S, e1, e2
-      const float Rc = (float)(R * cj), Rs = (float)(R * sj), fz = (float)Z;
-      const float pS = fmaf(Rc, f.at(RS_CS), fmaf(Rs, az[0], fz * f.at(RS_CS + 1)));
-      const float p1v = fmaf(Rc, f.at(RS_C1), fmaf(Rs, az[1], fz * f.at(RS_C1 + 1)));
-      const float p2v = fmaf(Rc, f.at(RS_C2), fmaf(Rs, az[2], fz * f.at(RS_C2 + 1)));
-      const float sl = wave_min(act ? pS : INFINITY), sh = wave_max(act ? pS : -INFINITY);
-      const float l1 = wave_min(act ? p1v : INFINITY), h1 = wave_max(act ? p1v : -INFINITY);
-      const float l2 = wave_min(act ? p2v : INFINITY), h2 = wave_max(act ? p2v : -INFINITY);
+      const float sl = wave_min(pmin[0]), sh = wave_max(pmax[0]);
+      const float l1 = wave_min(pmin[1]), h1 = wave_max(pmax[1]);
+      const float l2 = wave_min(pmin[2]), h2 = wave_max(pmax[2]);
       Window w;
       if (node_window_ranges(q, r0, sl, sh, l1, h1, l2, h2, rS, r1, r2, &w)) {
         float accr = 0.0f;
@@ -141,20 +179,17 @@ __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict
           qlen += __popcll(bal);
           wave_sync();
           if (qlen >= 64) {
-            walk_queue<COUNT, LS>(qn, 64, al, q.half_m, q.tiny, hk, accr, cnt);
+            walk_ring<COUNT, LS>(qn, 64, al, q.half_m, q.tiny, hk, accr, cnt);
             qlen -= 64;
             wave_sync();
             if (lane < qlen) qn[lane] = qn[64 + lane];
             wave_sync();
           }
         });
-        walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, q.tiny, hk, accr, cnt);
+        walk_ring<COUNT, LS>(qn, qlen, al, q.half_m, q.tiny, hk, accr, cnt);
         wave_sync();
         accp += accr;
       }
-      const double cn = cj * cd - sj * sd;
-      sj = sj * cd + cj * sd;
-      cj = cn;
     }
     acc = fmaf(f.at(RS_WK), accp, acc);
   }
