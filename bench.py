@@ -118,12 +118,13 @@ def forward_leg(wl, steps, warmup):
         pix, tile = B.pixel_map(model.geom)
         off, idx = B.cull(model.geom, tile, cull, cap=state.get("cap", 1 << 24))
         state["cap"] = int(idx.shape[0]) + 1024
+        order = B.tile_order(model.geom, off)
         if timed_events is not None:
             timed_events[0].record(stream)
-        img = B.profile(model, refl, nodes, pix, tile, off, idx)
+        img = B.profile(model, refl, nodes, pix, tile, off, idx, order=order)
         if timed_events is not None:
             timed_events[1].record(stream)
-        state.update(hkl=hkl, refl=refl, nodes=nodes, pix=pix, tile=tile, off=off, idx=idx, img=img)
+        state.update(hkl=hkl, refl=refl, nodes=nodes, pix=pix, tile=tile, off=off, idx=idx, order=order, img=img)
         return img
 
     log(f"forward: {wl.name}, {warmup} warm-up steps")
@@ -143,7 +144,7 @@ def forward_leg(wl, steps, warmup):
     img = state["img"]
     assert torch.isfinite(img).all()
     n_evals = B.profile(model, state["refl"], state["nodes"], state["pix"], state["tile"], state["off"], state["idx"],
-                        count=True)
+                        count=True, order=state["order"])
     return ms_step, prof_ms, n_evals, state
 
 
@@ -250,18 +251,19 @@ def bench_cyl(args, n_sub=300):
     nodes = B.node_table(model)
     pix, tile = B.pixel_map(model.geom)
     off, idx = B.cull(model.geom, tile, cull)
-    B.profile_cyl(model, refl, nodes, pix, off, idx, arc)
+    order = B.tile_order(model.geom, off)
+    B.profile_cyl(model, refl, nodes, pix, off, idx, arc, order=order)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(2)]
     for e0, e1 in evs:
         e0.record(stream)
-        img = B.profile_cyl(model, refl, nodes, pix, off, idx, arc)
+        img = B.profile_cyl(model, refl, nodes, pix, off, idx, arc, order=order)
         e1.record(stream)
     torch.cuda.synchronize()
     ms = float(np.mean([a.elapsed_time(b) for a, b in evs]))
     assert torch.isfinite(img).all() and img.max().item() > 0
-    n_evals = B.profile_cyl(model, refl, nodes, pix, off, idx, arc, count=True)
+    n_evals = B.profile_cyl(model, refl, nodes, pix, off, idx, arc, count=True, order=order)
     achieved = n_evals * SLOTS_PER_EVAL / (ms * 1e-3) / 1e12
     return {"workload": f"medium detector, {n_sub} of its reflections (seeded pick), ring step {arc:.4g} 1/A",
             "n_hkl": n_sub, "pairs": int(idx.shape[0]), "useful_evals": int(n_evals), "cyl_ms": ms,
@@ -406,13 +408,14 @@ def bench_fwd_bwd(args):
     nodes = B.node_table(model)
     pix, tile = B.pixel_map(model.geom)
     off, idx = B.cull(model.geom, tile, cull)
+    order = B.tile_order(model.geom, off)
     G = res["G"]
-    B.profile_adjoint(model, refl, nodes, pix, tile, off, idx, G)
+    B.profile_adjoint(model, refl, nodes, pix, tile, off, idx, G, order=order)
     torch.cuda.synchronize()
     aev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(2)]
     for e0, e1 in aev:
         e0.record(stream)
-        B.profile_adjoint(model, refl, nodes, pix, tile, off, idx, G)
+        B.profile_adjoint(model, refl, nodes, pix, tile, off, idx, G, order=order)
         e1.record(stream)
     torch.cuda.synchronize()
     adj_ms = float(np.mean([a.elapsed_time(b) for a, b in aev]))

@@ -248,18 +248,38 @@ size_t fdtbx_cull_workspace(const fdtbx_geometry* geom, int64_t n_hkl);
 int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_t n_hkl, const double* cull, int64_t* offsets,
                int32_t* idx, int64_t cap, int64_t* n_pairs, void* ws, size_t ws_bytes, void* stream);
 
+/* Launch order of the per-tile kernels (fdtbx_profile, fdtbx_profile_adjoint,
+ * fdtbx_profile_cyl) for a set of culling lists: the tile each workgroup processes, -1 for
+ * padding.  Workgroups are dealt to the 8 XCDs round-robin; tiles are grouped into
+ * superblocks of 8 x 8 tiles (single tiles when the detector has fewer than 64
+ * superblocks) that run on one XCD in consecutive dispatch slots.  When the launch holds
+ * fewer than 8 rounds of workgroups per slot (16 per compute unit of the current device),
+ * the superblocks run by decreasing length of their longest list and the tiles of a
+ * superblock by decreasing list length (the long tiles start first); otherwise in index
+ * order.  Performance only: every tile is listed once, and the images do not depend on
+ * the order.
+ *   offsets device int64 [n_tiles + 1] from fdtbx_cull
+ *   order   device int32 [fdtbx_tile_order_size(geom)] output
+ *   ws      device workspace of fdtbx_tile_order_workspace(geom) bytes */
+int64_t fdtbx_tile_order_size(const fdtbx_geometry* geom);
+size_t fdtbx_tile_order_workspace(const fdtbx_geometry* geom);
+int fdtbx_tile_order(const fdtbx_geometry* geom, const int64_t* offsets, int32_t* order, void* ws, size_t ws_bytes,
+                     void* stream);
+
 /* The detector image (Eq. direct_sum per reflection at the pixel's query point
  * p* = R e_perp + Z z, Eq. lorentz):
  *   image[j][i] = delta/(R_ij + delta) * sum_hkl W_hkl r0^2 sum_k omega_k Z_hkl(p* - s_k)
  * with Z_hkl = prod_l f(N_l, a_l.(p* - s_k)), f the per-axis profile of the model's lineshape
  * (fdtbx_disorder), over nodes inside its support, reflections from the tile lists.
+ *   order  device int32 [fdtbx_tile_order_size(geom)] from fdtbx_tile_order, or NULL (tiles
+ *          in a fixed spatial order)
  *   image device float32 [height][width] output (fully overwritten)
  *   counts device int64 [1] (may be NULL): if non-NULL, a counting pass runs instead
  *          of the image pass and adds the number of (pixel, reflection, node) triples
  *          inside the support to *counts (image untouched). */
 int fdtbx_profile(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
-                  const double* tile, const int64_t* offsets, const int32_t* idx, float* image, int64_t* counts,
-                  void* stream);
+                  const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order, float* image,
+                  int64_t* counts, void* stream);
 
 /* Deterministic forward splat (the paper's projection path, sampled on a fixed grid
  * instead of at random; sections "Numerical evaluation: per-reflection shell quadrature",
@@ -294,10 +314,12 @@ int fdtbx_splat(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, con
  * average).  I_h as in fdtbx_profile (lineshape included).
  *   offsets, idx: culling lists built by fdtbx_cull from fdtbx_cyl_records (the gather's lists
  *                 do not cover ring points off each reflection's azimuth)
+ *   order: fdtbx_tile_order of those lists, or NULL (tiles in index order)
  *   arc: ring step, 1/A, in [1e-5, 1)
  *   image, counts: as in fdtbx_profile (counts: (pixel, ring point, node) triples) */
 int fdtbx_profile_cyl(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
-                      const int64_t* offsets, const int32_t* idx, double arc, float* image, int64_t* counts, void* stream);
+                      const int64_t* offsets, const int32_t* idx, const int32_t* order, double arc, float* image,
+                      int64_t* counts, void* stream);
 
 /* Culling records (layout of fdtbx_reflection_prep's) for fdtbx_profile_cyl: with rho the
  * support corner radius sum_i w_i |a*_i| and rho_B = 2 r0 sqrt((1 - c_min)/2) + rho,
@@ -363,10 +385,11 @@ int fdtbx_profile_pattern(const fdtbx_model* model, const int32_t* hkl, int64_t 
  *   sums[r][2] = sum G L(R) sum_k (d omega_k/d gamma_theta) Z'_k
  *   sums[r][3+i] = sum G L(R) sum_k omega_k N_i (dZ_k/dN_i)/C_r   (u held fixed)
  * sums: device float64 [n_hkl][6], zeroed by the call, then accumulated with binary64 atomic
- * adds (the result depends on the order of those adds only below binary64 rounding). */
+ * adds (the result depends on the order of those adds only below binary64 rounding).
+ * order: as in fdtbx_profile. */
 int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
-                          const double* tile, const int64_t* offsets, const int32_t* idx, int64_t n_hkl,
-                          const float* grad_image, double* sums, void* stream);
+                          const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
+                          int64_t n_hkl, const float* grad_image, double* sums, void* stream);
 
 /* fdtbx_adjoint_finish: chain rule per reflection in binary64 (Eqs. Ah, Neff, Ipara, axis
  * damping):

@@ -90,8 +90,11 @@ _SIGS = {
     "fdtbx_cull": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                   ctypes.c_void_p]),
-    "fdtbx_profile": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 9),
-    "fdtbx_profile_cyl": (ctypes.c_int, [ctypes.c_void_p] * 6 + [ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+    "fdtbx_profile": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 10),
+    "fdtbx_tile_order_size": (ctypes.c_int64, [ctypes.c_void_p]),
+    "fdtbx_tile_order_workspace": (ctypes.c_size_t, [ctypes.c_void_p]),
+    "fdtbx_tile_order": (ctypes.c_int, [ctypes.c_void_p] * 4 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "fdtbx_profile_cyl": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                                                    ctypes.c_void_p]),
     "fdtbx_cyl_records": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
     "fdtbx_profile_points": (ctypes.c_int, [ctypes.c_void_p] * 6 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p]),
@@ -102,7 +105,7 @@ _SIGS = {
     "fdtbx_profile_pattern": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_size_t, ctypes.c_void_p]),
-    "fdtbx_profile_adjoint": (ctypes.c_int, [ctypes.c_void_p] * 7 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+    "fdtbx_profile_adjoint": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                                                       ctypes.c_void_p]),
     "fdtbx_adjoint_finish_workspace": (ctypes.c_size_t, [ctypes.c_int64]),
     "fdtbx_adjoint_finish": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64] + [ctypes.c_void_p] * 6 +
@@ -295,17 +298,32 @@ def cull(geom: Geometry, tile: torch.Tensor, cull_rec: torch.Tensor, cap: Option
     raise FdtbxError(-3, "culling capacity")
 
 
-def profile(model: Model, refl, nodes, pix, tile, offsets, idx, count=False):
-    """fdtbx_profile: the image [H][W] float32, or (count=True) the number of support-passing evaluations."""
+def tile_order(geom: Geometry, offsets: torch.Tensor) -> torch.Tensor:
+    """fdtbx_tile_order: launch order (int32, -1 for padding) of the per-tile kernels."""
+    L = lib()
+    n = int(L.fdtbx_tile_order_size(ctypes.byref(geom)))
+    if n <= 0:
+        raise FdtbxError(-1, "fdtbx_tile_order_size rejected the geometry")
+    _dev(offsets, torch.int64, "offsets")
+    order = torch.empty(n, dtype=torch.int32, device=offsets.device)
+    wsb = L.fdtbx_tile_order_workspace(ctypes.byref(geom))
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=offsets.device)
+    _check(L.fdtbx_tile_order(ctypes.byref(geom), _ptr(offsets), _ptr(order), _ptr(ws), wsb, _stream()))
+    return order
+
+
+def profile(model: Model, refl, nodes, pix, tile, offsets, idx, count=False, order=None):
+    """fdtbx_profile: the image [H][W] float32, or (count=True) the number of support-passing
+    evaluations.  order: fdtbx_tile_order of the lists, or None."""
     g = model.geom
     if count:
         c = torch.zeros(1, dtype=torch.int64, device="cuda")
         _check(lib().fdtbx_profile(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(tile), _ptr(offsets),
-                                   _ptr(idx), None, _ptr(c), _stream()))
+                                   _ptr(idx), _ptr(order), None, _ptr(c), _stream()))
         return int(c.item())
     img = torch.empty((g.height, g.width), dtype=torch.float32, device="cuda")
     _check(lib().fdtbx_profile(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(tile), _ptr(offsets),
-                               _ptr(idx), _ptr(img), None, _stream()))
+                               _ptr(idx), _ptr(order), _ptr(img), None, _stream()))
     return img
 
 
@@ -317,18 +335,18 @@ def cyl_records(model: Model, hkl) -> torch.Tensor:
     return out
 
 
-def profile_cyl(model: Model, refl, nodes, pix, offsets, idx, arc: float, count=False):
+def profile_cyl(model: Model, refl, nodes, pix, offsets, idx, arc: float, count=False, order=None):
     """fdtbx_profile_cyl: the cylindrically averaged image [H][W] float32, or (count=True) the
-    number of support-passing evaluations."""
+    number of support-passing evaluations.  order: fdtbx_tile_order of the lists, or None."""
     g = model.geom
     if count:
         c = torch.zeros(1, dtype=torch.int64, device="cuda")
         _check(lib().fdtbx_profile_cyl(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(offsets), _ptr(idx),
-                                       float(arc), None, _ptr(c), _stream()))
+                                       _ptr(order), float(arc), None, _ptr(c), _stream()))
         return int(c.item())
     img = torch.empty((g.height, g.width), dtype=torch.float32, device="cuda")
     _check(lib().fdtbx_profile_cyl(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(offsets), _ptr(idx),
-                                   float(arc), _ptr(img), None, _stream()))
+                                   _ptr(order), float(arc), _ptr(img), None, _stream()))
     return img
 
 
@@ -409,13 +427,13 @@ N_GLOBALS = len(GLOBAL_NAMES)
 LINESHAPES = {"laue": 0, "gaussian": 1, "hosemann": 2}
 
 
-def profile_adjoint(model: Model, refl, nodes, pix, tile, offsets, idx, grad_image: torch.Tensor) -> torch.Tensor:
+def profile_adjoint(model: Model, refl, nodes, pix, tile, offsets, idx, grad_image: torch.Tensor, order=None) -> torch.Tensor:
     """fdtbx_profile_adjoint: per-reflection sums float64 [n_hkl][6]."""
     n = int(refl.shape[0])
     _dev(grad_image, torch.float32, "grad_image")
     sums = torch.empty((n, 6), dtype=torch.float64, device=refl.device)
     _check(lib().fdtbx_profile_adjoint(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(tile), _ptr(offsets),
-                                       _ptr(idx), n, _ptr(grad_image), _ptr(sums), _stream()))
+                                       _ptr(idx), _ptr(order), n, _ptr(grad_image), _ptr(sums), _stream()))
     return sums
 
 

@@ -28,6 +28,7 @@ SOURCES = {
     "splat.hip": ["-ffp-contract=off"],
     "cyl.hip": ["-ffp-contract=off"],
     "points.hip": ["-ffp-contract=off"],
+    "order.hip": [],
     "capi.hip": [],
 }
 

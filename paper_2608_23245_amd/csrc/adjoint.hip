@@ -36,11 +36,12 @@ template <int LS>
 __global__ void __launch_bounds__(64) k_profile_adj(ProfParams q, const float* __restrict__ refl, const float* __restrict__ nodes,
                                                     const double* __restrict__ pix, const double* __restrict__ tile,
                                                     const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
-                                                    const float* __restrict__ grad_image, double* __restrict__ sums) {
+                                                    const float* __restrict__ grad_image, double* __restrict__ sums,
+                                                    const int32_t* __restrict__ order) {
   __shared__ float4 qn[128];
   __shared__ float2 qd[128];
   __shared__ int bq[64];
-  const int t = tile_of_block(q, blockIdx.x);
+  const int t = order ? order[blockIdx.x] : tile_of_block(q, blockIdx.x);
   if (t < 0) return;
   adjoint_tile<LS>(q, refl, nodes, pix, tile, offsets, idx, grad_image, sums, t, qn, qd, bq);
 }
@@ -475,8 +476,8 @@ int launch_batch_backward(const fdtbx_batch_entry* ent, int32_t n_models, const 
 }  // namespace fdtbx
 
 extern "C" int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
-                                     const double* tile, const int64_t* offsets, const int32_t* idx, int64_t n_hkl,
-                                     const float* grad_image, double* sums, void* stream) {
+                                     const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
+                                     int64_t n_hkl, const float* grad_image, double* sums, void* stream) {
   if (!model) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
   if (n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be non-negative");
   int rc = check_model(model);
@@ -489,16 +490,16 @@ extern "C" int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(6 * n_hkl, 256)), dim3(256), 0, s, sums, 6 * n_hkl);
   FDTBX_LAUNCH_CHECK("adjoint zero");
-  const dim3 grid((unsigned)tile_grid(q));
+  const dim3 grid((unsigned)(order ? order_grid(q.tiles_x, q.tiles_y) : tile_grid(q)));
   if (q.lineshape == FDTBX_LINESHAPE_GAUSSIAN)
     hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_GAUSSIAN>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
-                       grad_image, sums);
+                       grad_image, sums, order);
   else if (q.lineshape == FDTBX_LINESHAPE_HOSEMANN)
     hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_HOSEMANN>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
-                       grad_image, sums);
+                       grad_image, sums, order);
   else
     hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
-                       grad_image, sums);
+                       grad_image, sums, order);
   FDTBX_LAUNCH_CHECK("profile adjoint");
   return FDTBX_OK;
 }

@@ -81,7 +81,7 @@ int check_model(const fdtbx_model* m) {
 }
 
 struct PatternLayout {
-  size_t refl, cull, nodes, pix, tile, offsets, cullws, idx, total;
+  size_t refl, cull, nodes, pix, tile, offsets, cullws, order, orderws, idx, total;
 };
 
 static PatternLayout layout(const fdtbx_model* m, int64_t n_hkl, int64_t pair_cap) {
@@ -102,6 +102,10 @@ static PatternLayout layout(const fdtbx_model* m, int64_t n_hkl, int64_t pair_ca
   o += align_up((size_t)(tiles + 1) * sizeof(int64_t), 256);
   L.cullws = o;
   o += align_up(fdtbx_cull_workspace(&m->geom, n_hkl), 256);
+  L.order = o;
+  o += align_up((size_t)fdtbx_tile_order_size(&m->geom) * sizeof(int32_t), 256);
+  L.orderws = o;
+  o += align_up(fdtbx_tile_order_workspace(&m->geom), 256);
   L.idx = o;
   o += align_up((size_t)(pair_cap > 0 ? pair_cap : 1) * sizeof(int32_t), 256);
   L.total = o;
@@ -143,6 +147,7 @@ extern "C" int fdtbx_profile_pattern(const fdtbx_model* model, const int32_t* hk
   double* tile = (double*)(w + L.tile);
   int64_t* offsets = (int64_t*)(w + L.offsets);
   int32_t* idx = (int32_t*)(w + L.idx);
+  int32_t* order = (int32_t*)(w + L.order);
   rc = fdtbx_reflection_prep(model, hkl, n_hkl, F2, refl, cull, stream);
   if (rc) return rc;
   rc = fdtbx_node_table(&model->dis, &model->quad, nodes, stream);
@@ -154,7 +159,9 @@ extern "C" int fdtbx_profile_pattern(const fdtbx_model* model, const int32_t* hk
                   fdtbx_cull_workspace(&model->geom, n_hkl), stream);
   if (pairs_needed) *pairs_needed = n_pairs;
   if (rc) return rc;
-  return fdtbx_profile(model, refl, nodes, pix, tile, offsets, idx, image, nullptr, stream);
+  rc = fdtbx_tile_order(&model->geom, offsets, order, w + L.orderws, fdtbx_tile_order_workspace(&model->geom), stream);
+  if (rc) return rc;
+  return fdtbx_profile(model, refl, nodes, pix, tile, offsets, idx, order, image, nullptr, stream);
 }
 
 extern "C" size_t fdtbx_backward_workspace(int64_t n_hkl, int64_t n_atoms) {
@@ -202,6 +209,7 @@ extern "C" int fdtbx_pattern_backward(const fdtbx_model* model, const int32_t* h
   const double* tile = (const double*)(fw + L.tile);
   const int64_t* offsets = (const int64_t*)(fw + L.offsets);
   const int32_t* idx = (const int32_t*)(fw + L.idx);
+  const int32_t* order = (const int32_t*)(fw + L.order);
   char* w = (char*)ws;
   double* sums = (double*)w;
   w += align_up((size_t)n_hkl * 6 * sizeof(double), 256);
@@ -210,7 +218,7 @@ extern "C" int fdtbx_pattern_backward(const fdtbx_model* model, const int32_t* h
   w += align_up(fin_bytes, 256);
   float* g2 = dF2 ? dF2 : (float*)w;
   w += align_up((size_t)n_hkl * sizeof(float), 256);
-  rc = fdtbx_profile_adjoint(model, refl, nodes, pix, tile, offsets, idx, n_hkl, grad_image, sums, stream);
+  rc = fdtbx_profile_adjoint(model, refl, nodes, pix, tile, offsets, idx, order, n_hkl, grad_image, sums, stream);
   if (rc) return rc;
   rc = fdtbx_adjoint_finish(model, hkl, n_hkl, refl, sums, F, g2, d_globals, fin, fin_bytes, stream);
   if (rc) return rc;

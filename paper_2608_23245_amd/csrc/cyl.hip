@@ -52,12 +52,12 @@ template <bool COUNT, int LS>
 __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict__ refl, const float* __restrict__ nodes,
                                             const double* __restrict__ pix, const int64_t* __restrict__ offsets,
                                             const int32_t* __restrict__ idx, float* __restrict__ image,
-                                            unsigned long long* __restrict__ counts) {
+                                            unsigned long long* __restrict__ counts, const int32_t* __restrict__ order) {
   __shared__ float4 qn[128];
   __shared__ int bq[64];
   const ProfParams& q = p.q;
   const int lane = threadIdx.x & 63;
-  const int t = tile_of_block(q, blockIdx.x);
+  const int t = order ? order[blockIdx.x] : tile_of_block(q, blockIdx.x);
   if (t < 0) return;
   const int tx = t % q.tiles_x, ty = t / q.tiles_x;
   const int pi_ = tx * FDTBX_TILE + (lane % FDTBX_TILE);
@@ -210,8 +210,8 @@ __global__ void k_zero_count(unsigned long long* c) {
 using namespace fdtbx;
 
 extern "C" int fdtbx_profile_cyl(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
-                                 const int64_t* offsets, const int32_t* idx, double arc, float* image, int64_t* counts,
-                                 void* stream) {
+                                 const int64_t* offsets, const int32_t* idx, const int32_t* order, double arc, float* image,
+                                 int64_t* counts, void* stream) {
   if (!model || !refl || !nodes || !pix || !offsets || !idx) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
   if (!counts && !image) return fail(FDTBX_ERR_INVALID_ARGUMENT, "image is NULL");
   int rc = check_model(model);
@@ -220,24 +220,26 @@ extern "C" int fdtbx_profile_cyl(const fdtbx_model* model, const float* refl, co
   CylParams p;
   prof_params(model, &p.q);
   p.arc = arc;
-  // plain tile order: the ring work of a few reflections concentrates on a few superblocks,
-  // and the grouped order would pile it onto few XCDs
+  // without an order: the plain tile order (the ring work of a few reflections concentrates on
+  // a few superblocks, which the spatially grouped order would pile onto few XCDs)
   p.q.sbw = 0;
   hipStream_t s = (hipStream_t)stream;
-  const dim3 grid((unsigned)tile_grid(p.q));
+  const dim3 grid((unsigned)(order ? order_grid(p.q.tiles_x, p.q.tiles_y) : tile_grid(p.q)));
   unsigned long long* cp = (unsigned long long*)counts;
   if (counts) {
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, cp);
     FDTBX_LAUNCH_CHECK("cylindrical average counter");
-    hipLaunchKernelGGL((k_cyl<true, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, p, refl, nodes, pix, offsets, idx, image, cp);
+    hipLaunchKernelGGL((k_cyl<true, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, p, refl, nodes, pix, offsets, idx, image, cp,
+                       order);
   } else if (p.q.lineshape == FDTBX_LINESHAPE_GAUSSIAN) {
     hipLaunchKernelGGL((k_cyl<false, FDTBX_LINESHAPE_GAUSSIAN>), grid, dim3(64), 0, s, p, refl, nodes, pix, offsets, idx, image,
-                       cp);
+                       cp, order);
   } else if (p.q.lineshape == FDTBX_LINESHAPE_HOSEMANN) {
     hipLaunchKernelGGL((k_cyl<false, FDTBX_LINESHAPE_HOSEMANN>), grid, dim3(64), 0, s, p, refl, nodes, pix, offsets, idx, image,
-                       cp);
+                       cp, order);
   } else {
-    hipLaunchKernelGGL((k_cyl<false, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, p, refl, nodes, pix, offsets, idx, image, cp);
+    hipLaunchKernelGGL((k_cyl<false, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, p, refl, nodes, pix, offsets, idx, image, cp,
+                       order);
   }
   FDTBX_LAUNCH_CHECK("cylindrical average");
   return FDTBX_OK;

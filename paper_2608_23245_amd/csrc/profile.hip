@@ -34,11 +34,12 @@ template <bool COUNT, int LS>
 __global__ void __launch_bounds__(64) k_profile(ProfParams q, const float* __restrict__ refl, const float* __restrict__ nodes,
                                                 const double* __restrict__ pix, const double* __restrict__ tile,
                                                 const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
-                                                float* __restrict__ image, unsigned long long* __restrict__ counts) {
+                                                float* __restrict__ image, unsigned long long* __restrict__ counts,
+                                                const int32_t* __restrict__ order) {
   // queue of window nodes that can be inside the support of some pixel of the tile
   __shared__ float4 qn[128];
   __shared__ int bq[64];
-  const int t = tile_of_block(q, blockIdx.x);
+  const int t = order ? order[blockIdx.x] : tile_of_block(q, blockIdx.x);
   if (t < 0) return;
   profile_tile<COUNT, LS>(q, refl, nodes, pix, tile, offsets, idx, image, counts, t, qn, bq);
 }
@@ -106,8 +107,8 @@ int launch_batch_profile(const fdtbx_batch_entry* ent, const int64_t* items, int
 using namespace fdtbx;
 
 extern "C" int fdtbx_profile(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
-                             const double* tile, const int64_t* offsets, const int32_t* idx, float* image, int64_t* counts,
-                             void* stream) {
+                             const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
+                             float* image, int64_t* counts, void* stream) {
   if (!model || !refl || !nodes || !pix || !tile || !offsets || !idx) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
   if (!counts && !image) return fail(FDTBX_ERR_INVALID_ARGUMENT, "image is NULL");
   int rc = check_model(model);
@@ -115,19 +116,20 @@ extern "C" int fdtbx_profile(const fdtbx_model* model, const float* refl, const 
   ProfParams q;
   prof_params(model, &q);
   hipStream_t s = (hipStream_t)stream;
-  const dim3 grid((unsigned)tile_grid(q));
+  const dim3 grid((unsigned)(order ? order_grid(q.tiles_x, q.tiles_y) : tile_grid(q)));
+  unsigned long long* const nc = nullptr;
   if (counts) {
     hipLaunchKernelGGL((k_profile<true, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
-                       image, (unsigned long long*)counts);
+                       image, (unsigned long long*)counts, order);
   } else if (q.lineshape == FDTBX_LINESHAPE_GAUSSIAN) {
     hipLaunchKernelGGL((k_profile<false, FDTBX_LINESHAPE_GAUSSIAN>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets,
-                       idx, image, (unsigned long long*)nullptr);
+                       idx, image, nc, order);
   } else if (q.lineshape == FDTBX_LINESHAPE_HOSEMANN) {
     hipLaunchKernelGGL((k_profile<false, FDTBX_LINESHAPE_HOSEMANN>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets,
-                       idx, image, (unsigned long long*)nullptr);
+                       idx, image, nc, order);
   } else {
     hipLaunchKernelGGL((k_profile<false, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets,
-                       idx, image, (unsigned long long*)nullptr);
+                       idx, image, nc, order);
   }
   FDTBX_LAUNCH_CHECK("profile");
   return FDTBX_OK;

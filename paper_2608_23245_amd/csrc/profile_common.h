@@ -42,6 +42,17 @@ __host__ __device__ inline int64_t tile_grid(const ProfParams& q) {
   return (int64_t)kXcds * kSuper * kSuper * ((nsb + kXcds - 1) / kXcds);
 }
 
+// Superblock side of the launch orders of fdtbx_tile_order: kSuper when the detector has
+// at least 8 superblocks per XCD, else single tiles; and the workgroups of such a launch.
+__host__ __device__ inline int32_t order_super(int32_t tiles_x, int32_t tiles_y) {
+  return superblocks_per_row(tiles_x, tiles_y) ? kSuper : 1;
+}
+__host__ __device__ inline int64_t order_grid(int32_t tiles_x, int32_t tiles_y) {
+  const int64_t S = order_super(tiles_x, tiles_y);
+  const int64_t nsb = ((tiles_x + S - 1) / S) * ((tiles_y + S - 1) / S);
+  return (int64_t)kXcds * S * S * ((nsb + kXcds - 1) / kXcds);
+}
+
 // Tile of workgroup b, or -1 for a padding workgroup (past the detector).
 __device__ inline int tile_of_block(const ProfParams& q, int b) {
   if (q.sbw == 0) return b;

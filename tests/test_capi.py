@@ -106,7 +106,7 @@ def test_empty_inputs_are_valid_calls(lib):
     assert lib.fdtbx_reflection_prep(ctypes.byref(m), None, -1, None, None, None, None) == -1
     assert lib.fdtbx_cyl_records(ctypes.byref(m), None, 0, None, None) == 0
     assert lib.fdtbx_structure_factors(ctypes.byref(cell), 10, *([None] * 7), 1, None, 0, None, None, None, 0, None) == 0
-    assert lib.fdtbx_profile_adjoint(ctypes.byref(m), *([None] * 6), 0, None, None, None) == 0
+    assert lib.fdtbx_profile_adjoint(ctypes.byref(m), *([None] * 7), 0, None, None, None) == 0
     assert lib.fdtbx_sf_adjoint(ctypes.byref(cell), 0, *([None] * 7), 1, None, 5, *([None] * 7), None, 0, None) == 0
     assert lib.fdtbx_structure_factors(ctypes.byref(cell), -1, *([None] * 7), 1, None, 5, None, None, None, 0, None) == -1
 

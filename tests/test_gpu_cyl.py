@@ -43,8 +43,12 @@ def gpu_cyl(wl, hkl, arc, count=True):
     nodes = B.node_table(model)
     pix, tile = B.pixel_map(model.geom)
     off, idx = B.cull(model.geom, tile, cull)
-    img = B.profile_cyl(model, refl, nodes, pix, off, idx, arc).cpu().numpy().astype(np.float64)
-    cnt = B.profile_cyl(model, refl, nodes, pix, off, idx, arc, count=True) if count else None
+    img_t = B.profile_cyl(model, refl, nodes, pix, off, idx, arc)
+    order = B.tile_order(model.geom, off)
+    # the launch order is performance only: the same image with it
+    assert torch.equal(B.profile_cyl(model, refl, nodes, pix, off, idx, arc, order=order), img_t)
+    img = img_t.cpu().numpy().astype(np.float64)
+    cnt = B.profile_cyl(model, refl, nodes, pix, off, idx, arc, count=True, order=order) if count else None
     return img, cnt, F, cull.cpu().numpy(), off.cpu().numpy(), idx.cpu().numpy()
 
 

@@ -316,3 +316,39 @@ def test_pattern_full_size_sampled(cfg, n_pix):
     say(f"pattern config {cfg}, {n_pix} sampled pixels")
     got, ref = _sampled(wl, n_pix, seed=cfg)
     check_pattern(got, ref, f"config{cfg} sampled")
+
+
+@pytest.mark.parametrize("name", ["ragged", "tilted", "config0", "config1"])
+def test_tile_order_is_a_schedule_and_leaves_results_unchanged(name):
+    """fdtbx_tile_order lists every tile once (the rest is padding), and the per-tile kernels
+    give the same image (bit for bit), the same counts and the same adjoint sums (up to the
+    order of binary64 atomic adds) with it as without it."""
+    wl = W.config0() if name == "config0" else W.config1() if name == "config1" else W.small(**SMALL[name])
+    say(f"tile order {name}")
+    pipe = Pipeline(wl)
+    model = pipe.model
+    _, F2 = pipe.structure_factors()
+    refl, cull = B.reflection_prep(model, pipe.hkl, F2)
+    nodes = B.node_table(model)
+    pix, tile = B.pixel_map(model.geom)
+    off, idx = B.cull(model.geom, tile, cull)
+    order = B.tile_order(model.geom, off)
+    o = order.cpu().numpy()
+    n_tiles = tile.shape[0]
+    assert np.array_equal(np.sort(o[o >= 0]), np.arange(n_tiles))
+    img0 = B.profile(model, refl, nodes, pix, tile, off, idx)
+    img1 = B.profile(model, refl, nodes, pix, tile, off, idx, order=order)
+    torch.cuda.synchronize()
+    assert torch.equal(img0, img1)
+    assert B.profile(model, refl, nodes, pix, tile, off, idx, count=True) == \
+        B.profile(model, refl, nodes, pix, tile, off, idx, count=True, order=order)
+    G = torch.as_tensor(np.random.default_rng(3).normal(size=img0.shape), dtype=torch.float32).cuda()
+    s0 = B.profile_adjoint(model, refl, nodes, pix, tile, off, idx, G).cpu().numpy()
+    s1 = B.profile_adjoint(model, refl, nodes, pix, tile, off, idx, G, order=order).cpu().numpy()
+    np.testing.assert_allclose(s1, s0, rtol=1e-9, atol=1e-12 * np.abs(s0).max())
+    if name == "config1":
+        # few rounds of workgroups: the longest lists start first
+        lens = np.diff(off.cpu().numpy())
+        first, last = lens[o[o >= 0][:512]], lens[o[o >= 0][-512:]]
+        say(f"  list length of the first 512 tiles {first.mean():.0f}, of the last 512 {last.mean():.0f}")
+        assert first.mean() > 2 * last.mean()
