@@ -30,10 +30,12 @@ sys.path.insert(0, ROOT)
 # this formulation: 3 subtractions (lattice coordinates relative to the node),
 # 1 three-way max and 1 compare (support), 4 multiplies (sine and coordinate
 # products), 1 multiply and 1 square (ratio), 1 fused multiply-add (weighted
-# accumulate) at full rate, plus 3 sines and 1 reciprocal, which gfx950 issues
-# at half rate (2 slots each; a throughput kernel of independent v_sin_f32 or
-# v_rcp_f32 chains reaches half the v_fma_f32 rate).
-TRANS_SLOTS = 2
+# accumulate), plus 3 sines and 1 reciprocal.  A transcendental takes one issue
+# slot: a stream of nothing but v_sin_f32 or v_rcp_f32 runs at half the v_fma_f32
+# rate, but mixed with other arithmetic (here one per four) it runs beside it; the
+# profile kernel's counters show one VALU instruction issued per SIMD cycle with the
+# transcendentals counted once.
+TRANS_SLOTS = 1
 SLOTS_PER_EVAL = 12 + 4 * TRANS_SLOTS
 # 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = VALU lane issue slots per second.
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
@@ -160,8 +162,8 @@ def bench_tilted(args):
 
 # Issue slots per useful evaluation of the other lineshapes (same accounting as above):
 # Gaussian: 3 subtractions, max3, compare, sum of squares (3), scale (1), accumulate (1)
-# and one half-rate exp2; Hosemann: 3 subtractions, max3, compare, 3 denominators, 2
-# products, accumulate and three half-rate cosines and one reciprocal.
+# and one exp2; Hosemann: 3 subtractions, max3, compare, 3 denominators, 2 products,
+# accumulate and three cosines and one reciprocal.
 # issue slots per useful evaluation of the adjoint kernel (k_profile_adj, Laue), the |y| + tiny
 # guards not credited as in the forward: 39 full-rate operations (support test 5, the product
 # of the y 2, the three sinc factors 8, their squares and product 5, G P and the three weighted
