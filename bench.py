@@ -17,6 +17,7 @@ same workload.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import math
 import os
@@ -86,6 +87,8 @@ def parse():
     ap.add_argument("--no-lineshapes", action="store_true", help="skip the Gaussian/Hosemann lineshape legs")
     ap.add_argument("--no-splat", action="store_true", help="skip the forward-splat leg")
     ap.add_argument("--no-cyl", action="store_true", help="skip the exact cylindrical-average leg")
+    ap.add_argument("--tile-w", type=int, default=0, choices=(0, 2, 4, 8, 16, 32),
+                    help="pixel-tile width of the medium forward (0: chosen by the tile tuner)")
     ap.add_argument("--batch-models", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -148,6 +151,32 @@ def forward_leg(wl, steps, warmup):
     n_evals = B.profile(model, state["refl"], state["nodes"], state["pix"], state["tile"], state["off"], state["idx"],
                         count=True, order=state["order"])
     return ms_step, prof_ms, n_evals, state
+
+
+def tune_tiles(wl):
+    """Tile shape of workload wl chosen by the tuner (set-up, outside every timed region)."""
+    import dataclasses
+
+    import torch
+
+    from paper_2608_23245_amd import atoms_to_device
+    from paper_2608_23245_amd import binding as B
+    from paper_2608_23245_amd.autotune import TileTuner
+
+    t0 = time.perf_counter()
+    model = B.make_model(wl)
+    ext = (wl.dis.g[0], wl.dis.g[1], wl.dis.g[2], wl.quad.extinction)
+    hkl = B.enumerate_hkl(model.cell, wl.quad.d_min, wl.quad.d_max, extinction=ext)
+    _, F2 = B.structure_factors(model.cell, atoms_to_device(wl.atoms), hkl, want_F=False)
+    refl, cull = B.reflection_prep(model, hkl, F2)
+    tuner = TileTuner()
+    tw = tuner.choose(model, refl, B.node_table(model), cull)
+    times = tuner.cached(model, int(hkl.shape[0]))[1]
+    torch.cuda.synchronize()
+    info = {"tile": f"{tw}x{64 // tw}", "profile_ms": {f"{c}x{64 // c}": round(v, 3) for c, v in times.items()},
+            "tuned": True, "tuning_s": time.perf_counter() - t0}
+    log(f"tile tuner: {info['profile_ms']} -> {info['tile']}")
+    return dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, tile_w=tw)), info
 
 
 def bench_tilted(args):
@@ -295,6 +324,11 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.tile_w:
+        wl = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, tile_w=args.tile_w))
+        tiles = {"tile": f"{args.tile_w}x{64 // args.tile_w}", "tuned": False}
+    else:
+        wl, tiles = tune_tiles(wl)
     ms_step, prof_ms, n_evals, state = forward_leg(wl, args.steps, args.warmup)
     log(f"forward: {ms_step:.1f} ms/step, profile kernel {prof_ms:.1f} ms, {n_evals:.4e} useful evaluations")
     slots = n_evals * SLOTS_PER_EVAL
@@ -314,11 +348,13 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "n_hkl": int(state["hkl"].shape[0]), "pixels": wl.geom.width * wl.geom.height,
+                   "tile": tiles["tile"],
                    "nodes": wl.quad.n_nodes ** 2, "culled_pairs": int(state["idx"].shape[0]),
                    "useful_evals_per_step": int(n_evals), "pass": "forward"},
         "ms_per_pattern": ms_step,
         "profile_kernel_ms": prof_ms,
         "profile_kernel_evals_per_s": n_evals / (prof_ms * 1e-3),
+        "tile_tuning": tiles,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak,
                      "traffic": measured_traffic(), "kernel": "k_profile<false, 0>", "sources_sha": profile_source_sha(),
                      "slots_per_eval": SLOTS_PER_EVAL},
@@ -434,20 +470,26 @@ def bench_fwd_bwd(args):
 
 def bench_batched(args):
     """Batched refinement step (forward + adjoint of every model) captured in one HIP graph,
-    against the plain single-model forward of each model run one after the other."""
+    against the plain single-model forward of each model run one after the other.  Set-up
+    (not timed) picks the batch's pixel-tile shape by timing its forward in each candidate
+    shape (autotune.tune_batch)."""
     import numpy as np
     import torch
 
     import workloads as W
     from paper_2608_23245_amd import binding as B
-    from paper_2608_23245_amd.batch import BatchEngine, GraphStep
+    from paper_2608_23245_amd.autotune import tune_batch
+    from paper_2608_23245_amd.batch import GraphStep
 
     wls = W.config4(n_models=args.batch_models)
     t0 = time.perf_counter()
-    be = BatchEngine(wls)
+    be, tile_ms = tune_batch(wls, candidates=(8, 16, 4))
     torch.cuda.synchronize()
     setup_s = time.perf_counter() - t0
-    log(f"batched: set-up {setup_s:.1f} s, {be.totals['pair']} culled pairs")
+    shapes = {f"{c}x{64 // c}": be.tile_w.count(c) for c in sorted(set(be.tile_w))}
+    tile_ms = {f"{c}x{64 // c}": round(v, 1) for c, v in tile_ms.items()}
+    log(f"batched: set-up {setup_s:.1f} s (batched forward per tile shape {tile_ms} ms -> {shapes}), "
+        f"{be.totals['pair']} culled pairs")
     glob = be.globals()
     tglob = glob.clone()
     tglob[:, 0] *= 1.1
@@ -508,7 +550,7 @@ def bench_batched(args):
                         "Voigt sigma U(1,8) deg, eta U(0,1), g U(0,.06), d_min U(2,3) A, 32x32 nodes)",
             "n_models": len(wls), "n_hkl": int(be.totals["hkl"]), "pixels": int(be.totals["pix"]),
             "culled_pairs": int(be.totals["pair"]), "useful_evals_per_forward": int(n_evals),
-            "setup_s": setup_s, "graph_ms_per_step": ms, "graph_steps": args.batch_steps,
+            "setup_s": setup_s, "tile_shapes": shapes, "tile_tuning_forward_ms": tile_ms, "graph_ms_per_step": ms, "graph_steps": args.batch_steps,
             "batched_forward_ms": fwd_ms, "batched_forward_evals_per_s": n_evals / (fwd_ms * 1e-3),
             "sum_single_forward_ms": single_ms,
             "forward_speedup_vs_single": single_ms / fwd_ms,

@@ -68,6 +68,8 @@ typedef struct fdtbx_geometry {
   int32_t width, height;      /* pixels along lab y (horizontal) and lab z (vertical) */
   double center_x, center_y;  /* beam centre in pixel units (width/2, height/2 puts it between pixels) */
   double tilt;                /* fibre tilt, radians, |tilt| < pi/2 */
+  int32_t tile_w;             /* pixel tile width: 2, 4, 8, 16 or 32 (0 means FDTBX_TILE); a tile
+                                 is tile_w x (64 / tile_w) pixels, one 64-lane wave */
 } fdtbx_geometry;
 
 /* Orientational and lattice disorder (section "Angular peak shapes", tutorial
@@ -201,7 +203,12 @@ int fdtbx_structure_factors(const fdtbx_cell* cell, int64_t n_atoms, const float
 #define FDTBX_CULL_DOUBLES 16
 #define FDTBX_NODE_FLOATS 8
 #define FDTBX_NODE_BLOCK 4
-#define FDTBX_TILE 8 /* pixel tiles are FDTBX_TILE x FDTBX_TILE */
+#define FDTBX_TILE 8 /* default pixel tile width (fdtbx_geometry.tile_w = 0): 8 x 8 tiles */
+
+/* Host: the pixel-tile grid of a geometry, tiles_x = ceil(width / tile_w) columns and
+ * tiles_y = ceil(height / (64 / tile_w)) rows; tile t covers columns (t % tiles_x) tile_w
+ * onward and rows (t / tiles_x) (64 / tile_w) onward. */
+int fdtbx_tile_grid(const fdtbx_geometry* geom, int32_t* tiles_x, int32_t* tiles_y);
 
 /* Rows of FDTBX_NODE_FLOATS float32 in the node table of n_nodes per side:
  * n_nodes^2 + ceil(n_nodes/FDTBX_NODE_BLOCK)^2; 0 if n_nodes is outside 1..256. */
@@ -229,8 +236,8 @@ int fdtbx_reflection_prep(const fdtbx_model* model, const int32_t* hkl, int64_t 
  *        R = sqrt((S_x cos(tilt) - S_z sin(tilt))^2 + S_y^2), binary64 without fused
  *        multiply-adds, sin and cos of the host's C library
  *   tile device float64 [n_tiles][8] output: R_lo, R_hi, Z_lo, Z_hi, P2_lo, P2_hi, 0, 0
- *        over the pixel centres of each FDTBX_TILE^2 tile, tiles row-major,
- *        n_tiles = ceil(height/8) * ceil(width/8) */
+ *        over the pixel centres of each tile, tiles row-major (fdtbx_tile_grid),
+ *        n_tiles = tiles_x * tiles_y */
 int fdtbx_pixel_map(const fdtbx_geometry* geom, double* pix, double* tile, void* stream);
 
 /* Per-tile culling lists: reflection r is listed for tile t iff it is kept and

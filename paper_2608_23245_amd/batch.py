@@ -8,6 +8,9 @@ device memory, so the refinable parameters of every model can be updated in plac
 (set_globals) between steps.  The step itself allocates nothing, copies nothing to
 the host and never synchronises, so it can be captured in a HIP graph
 (``GraphStep``).
+
+Each model's tiles run in its own shape (its geometry's tile_w); ``autotune.tune_batch``
+picks the shape of a whole batch by timing the batched forward in each candidate shape.
 """
 from __future__ import annotations
 
@@ -42,16 +45,18 @@ class BatchEngine:
         off = dict(atom=0, hkl=0, pix=0, tile=0, rowptr=0, pair=0, node=0, ff=0)
         refl_blocks, model_rb, atom_blocks, node_blocks, items, costs = [], [], [], [], [], []
         self.list_len = []
+        self.tile_w = []
         for m, (wl, mod) in enumerate(zip(workloads, self.models)):
             e = ents[m]
-            B._check(L.fdtbx_batch_entry_init(ctypes.byref(mod), ctypes.byref(e)))
             ext = (wl.dis.g[0], wl.dis.g[1], wl.dis.g[2], wl.quad.extinction) if wl.quad.extinction > 0 else None
             hkl = B.enumerate_hkl(mod.cell, wl.quad.d_min, wl.quad.d_max, extinction=ext, device=device)
             n_hkl = int(hkl.shape[0])
             if n_hkl == 0:
                 raise ValueError(f"model {m} has no reflections")
-            pix, tile = B.pixel_map(mod.geom)
             _, cull = B.reflection_prep(mod, hkl, torch.ones(n_hkl, dtype=torch.float32, device=device))
+            self.tile_w.append(mod.geom.tile_w or B.TILE)
+            B._check(L.fdtbx_batch_entry_init(ctypes.byref(mod), ctypes.byref(e)))
+            pix, tile = B.pixel_map(mod.geom)
             rowptr, idx = B.cull(mod.geom, tile, cull)
             n_tiles = int(tile.shape[0])
             a = wl.atoms

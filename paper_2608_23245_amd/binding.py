@@ -40,7 +40,8 @@ class Cell(ctypes.Structure):
 class Geometry(ctypes.Structure):
     _fields_ = [("wavelength", ctypes.c_double), ("distance", ctypes.c_double), ("pixel", ctypes.c_double),
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32),
-                ("center_x", ctypes.c_double), ("center_y", ctypes.c_double), ("tilt", ctypes.c_double)]
+                ("center_x", ctypes.c_double), ("center_y", ctypes.c_double), ("tilt", ctypes.c_double),
+                ("tile_w", ctypes.c_int32)]
 
 
 class Disorder(ctypes.Structure):
@@ -86,6 +87,7 @@ _SIGS = {
     "fdtbx_reflection_prep": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdtbx_pixel_map": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fdtbx_tile_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdtbx_cull_workspace": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64]),
     "fdtbx_cull": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
@@ -185,15 +187,18 @@ def make_model(wl) -> Model:
     g, d, q = wl.geom, wl.dis, wl.quad
     return Model(make_cell(wl.cell),
                  Geometry(g.wavelength, g.distance, g.pixel, g.width, g.height, g.center_x, g.center_y,
-                          float(getattr(g, "tilt", 0.0))),
+                          float(getattr(g, "tilt", 0.0)), int(getattr(g, "tile_w", 0))),
                  Disorder(d.sigma_theta, d.gamma_theta, (ctypes.c_double * 3)(*d.N_base),
                           (ctypes.c_double * 3)(*d.g), d.intensity_model, int(getattr(d, "lineshape", 0)),
                           (ctypes.c_double * 3)(*getattr(d, "B_axis", (0.0, 0.0, 0.0)))),
                  Quadrature(q.n_nodes, q.T, q.sigma_r, q.m, q.delta, q.d_min, q.d_max, q.extinction))
 
 
-def tiles_of(width: int, height: int):
-    return (width + TILE - 1) // TILE, (height + TILE - 1) // TILE
+def tile_grid(geom: Geometry):
+    """fdtbx_tile_grid: (tiles_x, tiles_y) of the geometry's pixel tiles."""
+    tx, ty = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().fdtbx_tile_grid(ctypes.byref(geom), ctypes.byref(tx), ctypes.byref(ty)))
+    return int(tx.value), int(ty.value)
 
 
 # ----------------------------------------------------------------------------- entry points
@@ -267,7 +272,7 @@ def reflection_prep(model: Model, hkl: torch.Tensor, F2: torch.Tensor):
 
 
 def pixel_map(geom: Geometry):
-    tx, ty = tiles_of(geom.width, geom.height)
+    tx, ty = tile_grid(geom)
     pix = torch.empty((geom.height, geom.width, 2), dtype=torch.float64, device="cuda")
     tile = torch.empty((tx * ty, 8), dtype=torch.float64, device="cuda")
     _check(lib().fdtbx_pixel_map(ctypes.byref(geom), _ptr(pix), _ptr(tile), _stream()))

@@ -105,8 +105,8 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
                                              float4* qn, float2* qd, int* bq) {
   const int lane = threadIdx.x & 63;
   const int tx = t % q.tiles_x, ty = t / q.tiles_x;
-  const int i = tx * FDTBX_TILE + (lane % FDTBX_TILE);
-  const int j = ty * FDTBX_TILE + (lane / FDTBX_TILE);
+  const int i = (tx << q.tlg) + (lane & ((1 << q.tlg) - 1));
+  const int j = ty * (64 >> q.tlg) + (lane >> q.tlg);
   const bool in = i < q.W && j < q.H;
   const double R = in ? pix[2 * ((int64_t)j * q.W + i) + 0] : 1.0e30;
   const double Z = in ? pix[2 * ((int64_t)j * q.W + i) + 1] : 0.0;

@@ -45,6 +45,9 @@ int check_geometry(const fdtbx_geometry* g) {
     return fail(FDTBX_ERR_INVALID_ARGUMENT, "detector size must be in 1..65536 pixels");
   if (!isfinite(g->center_x) || !isfinite(g->center_y)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "beam centre not finite");
   if (!(fabs(g->tilt) < 0.5 * M_PI)) return fail(FDTBX_ERR_GEOMETRY, "fibre tilt must be finite with |tilt| < pi/2");
+  const int32_t tw = g->tile_w;
+  if (!(tw == 0 || tw == 2 || tw == 4 || tw == 8 || tw == 16 || tw == 32))
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "tile_w must be 0, 2, 4, 8, 16 or 32");
   return FDTBX_OK;
 }
 
@@ -86,7 +89,7 @@ struct PatternLayout {
 
 static PatternLayout layout(const fdtbx_model* m, int64_t n_hkl, int64_t pair_cap) {
   PatternLayout L;
-  int64_t tiles = ceil_div(m->geom.width, FDTBX_TILE) * ceil_div(m->geom.height, FDTBX_TILE);
+  int64_t tiles = (int64_t)tiles_x_of(&m->geom) * tiles_y_of(&m->geom);
   size_t o = 0;
   L.refl = o;
   o += align_up((size_t)n_hkl * FDTBX_REFL_FLOATS * sizeof(float), 256);
@@ -122,6 +125,15 @@ extern "C" const char* fdtbx_error_string(int code) {
 }
 
 extern "C" int fdtbx_last_hip_error(void) { return g_hip; }
+
+extern "C" int fdtbx_tile_grid(const fdtbx_geometry* geom, int32_t* tiles_x, int32_t* tiles_y) {
+  if (!geom || !tiles_x || !tiles_y) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  int rc = check_geometry(geom);
+  if (rc) return rc;
+  *tiles_x = tiles_x_of(geom);
+  *tiles_y = tiles_y_of(geom);
+  return FDTBX_OK;
+}
 
 extern "C" size_t fdtbx_pattern_workspace(const fdtbx_model* model, int64_t n_hkl, int64_t pair_cap) {
   if (!model || check_model(model) || n_hkl < 0 || pair_cap < 0) return 0;

@@ -60,8 +60,8 @@ __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict
   const int t = order ? order[blockIdx.x] : tile_of_block(q, blockIdx.x);
   if (t < 0) return;
   const int tx = t % q.tiles_x, ty = t / q.tiles_x;
-  const int pi_ = tx * FDTBX_TILE + (lane % FDTBX_TILE);
-  const int pj = ty * FDTBX_TILE + (lane / FDTBX_TILE);
+  const int pi_ = (tx << q.tlg) + (lane & ((1 << q.tlg) - 1));
+  const int pj = ty * (64 >> q.tlg) + (lane >> q.tlg);
   const bool in = pi_ < q.W && pj < q.H;
   const double R = in ? pix[2 * ((int64_t)pj * q.W + pi_) + 0] : 0.0;
   const double Z = in ? pix[2 * ((int64_t)pj * q.W + pi_) + 1] : 0.0;

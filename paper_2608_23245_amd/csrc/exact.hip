@@ -195,7 +195,7 @@ namespace fdtbx {
 struct PixParams {
   double lam, SF, p, cx, cy;
   double st, ct;  // sine and cosine of the fibre tilt
-  int32_t W, H, tiles_x, tiles_y;
+  int32_t W, H, tiles_x, tiles_y, tlg;
 };
 
 // Ewald point of pixel (i, j): y = ((i + 1/2) - c_x) p, z = ((j + 1/2) - c_y) p,
@@ -214,12 +214,12 @@ __device__ static inline void pixel_ewald(const PixParams& q, int i, int j, doub
   *Z = Sx * q.st + Sz * q.ct;
 }
 
-// One 64-lane wave per FDTBX_TILE x FDTBX_TILE tile: pixel values and the tile's box.
+// One 64-lane wave per tile of 2^tlg x 64 >> tlg pixels: pixel values and the tile's box.
 __global__ void __launch_bounds__(64) k_pixel_map(PixParams q, double* pix, double* tile) {
   const int t = blockIdx.x;
   const int tx = t % q.tiles_x, ty = t / q.tiles_x;
-  const int i = tx * FDTBX_TILE + (threadIdx.x % FDTBX_TILE);
-  const int j = ty * FDTBX_TILE + (threadIdx.x / FDTBX_TILE);
+  const int i = (tx << q.tlg) + (threadIdx.x & ((1 << q.tlg) - 1));
+  const int j = ty * (64 >> q.tlg) + (threadIdx.x >> q.tlg);
   const bool in = i < q.W && j < q.H;
   double R = 0, Z = 0, P2 = 0;
   if (in) {
@@ -611,8 +611,9 @@ static void pix_params(const fdtbx_geometry* g, PixParams* q) {
   q->ct = cos(g->tilt);
   q->W = g->width;
   q->H = g->height;
-  q->tiles_x = (int32_t)ceil_div(g->width, FDTBX_TILE);
-  q->tiles_y = (int32_t)ceil_div(g->height, FDTBX_TILE);
+  q->tiles_x = tiles_x_of(g);
+  q->tiles_y = tiles_y_of(g);
+  q->tlg = tile_lg(g);
 }
 
 extern "C" int fdtbx_pixel_map(const fdtbx_geometry* geom, double* pix, double* tile, void* stream) {
@@ -680,8 +681,8 @@ extern "C" int fdtbx_cyl_records(const fdtbx_model* model, const int32_t* hkl, i
 }
 
 static void cull_params(const fdtbx_geometry* g, int64_t n_hkl, CullParams* q) {
-  q->tiles_x = (int32_t)ceil_div(g->width, FDTBX_TILE);
-  q->tiles_y = (int32_t)ceil_div(g->height, FDTBX_TILE);
+  q->tiles_x = tiles_x_of(g);
+  q->tiles_y = tiles_y_of(g);
   q->sb_x = (int32_t)ceil_div(q->tiles_x, kSB);
   q->sb_y = (int32_t)ceil_div(q->tiles_y, kSB);
   q->n_hkl = n_hkl;
@@ -710,7 +711,7 @@ extern "C" int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_
   if (rc) return rc;
   if (n_hkl == 0) {  // every list empty
     *n_pairs = 0;
-    return fill(offsets, ceil_div(geom->width, FDTBX_TILE) * ceil_div(geom->height, FDTBX_TILE) + 1, (int64_t)0,
+    return fill(offsets, (int64_t)tiles_x_of(geom) * tiles_y_of(geom) + 1, (int64_t)0,
                 (hipStream_t)stream);
   }
   if (!cull || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");

@@ -28,6 +28,11 @@ int check_geometry(const fdtbx_geometry* g);
 int check_model(const fdtbx_model* m);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Pixel tiles of a checked geometry: 2^tile_lg columns by 64 >> tile_lg rows.
+inline int tile_lg(const fdtbx_geometry* g) { return __builtin_ctz((unsigned)(g->tile_w ? g->tile_w : FDTBX_TILE)); }
+inline int32_t tiles_x_of(const fdtbx_geometry* g) { return (int32_t)ceil_div(g->width, 1 << tile_lg(g)); }
+inline int32_t tiles_y_of(const fdtbx_geometry* g) { return (int32_t)ceil_div(g->height, 64 >> tile_lg(g)); }
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // v[0..n) = x, by a kernel (hipMemsetAsync nodes do not belong in captured graphs).

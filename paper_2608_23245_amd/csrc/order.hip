@@ -79,8 +79,8 @@ __global__ void __launch_bounds__(256) k_order_fill(OrderParams p, int64_t n_blo
 }
 
 static void order_params(const fdtbx_geometry* g, OrderParams* p) {
-  p->tiles_x = (int32_t)ceil_div(g->width, FDTBX_TILE);
-  p->tiles_y = (int32_t)ceil_div(g->height, FDTBX_TILE);
+  p->tiles_x = tiles_x_of(g);
+  p->tiles_y = tiles_y_of(g);
   p->S = order_super(p->tiles_x, p->tiles_y);
   p->sbw = (int32_t)ceil_div(p->tiles_x, p->S);
   p->sbh = (int32_t)ceil_div(p->tiles_y, p->S);
@@ -93,7 +93,7 @@ using namespace fdtbx;
 
 extern "C" int64_t fdtbx_tile_order_size(const fdtbx_geometry* geom) {
   if (!geom || check_geometry(geom)) return 0;
-  return order_grid((int32_t)ceil_div(geom->width, FDTBX_TILE), (int32_t)ceil_div(geom->height, FDTBX_TILE));
+  return order_grid(tiles_x_of(geom), tiles_y_of(geom));
 }
 
 extern "C" size_t fdtbx_tile_order_workspace(const fdtbx_geometry* geom) {

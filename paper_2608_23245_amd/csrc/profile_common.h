@@ -12,6 +12,7 @@ namespace fdtbx {
 
 struct ProfParams {
   int32_t W, H, tiles_x, tiles_y;
+  int32_t tlg;      // tiles are 2^tlg pixels wide and 64 >> tlg high
   int32_t lineshape;
   int32_t n;        // nodes per side
   float T, inv_h;   // grid half extent, 1/spacing
@@ -312,8 +313,10 @@ __device__ __forceinline__ void scan_window(const ProfParams& q, const float* __
 __host__ __device__ inline void prof_params(const fdtbx_model* model, ProfParams* q) {
   q->W = model->geom.width;
   q->H = model->geom.height;
-  q->tiles_x = (q->W + FDTBX_TILE - 1) / FDTBX_TILE;
-  q->tiles_y = (q->H + FDTBX_TILE - 1) / FDTBX_TILE;
+  const int tw = model->geom.tile_w ? model->geom.tile_w : FDTBX_TILE, th = 64 / tw;
+  q->tlg = __builtin_ctz((unsigned)tw);
+  q->tiles_x = (q->W + tw - 1) / tw;
+  q->tiles_y = (q->H + th - 1) / th;
   q->n = model->quad.n_nodes;
   q->T = (float)model->quad.T;
   q->inv_h = (float)(model->quad.n_nodes / (2.0 * model->quad.T));

@@ -136,3 +136,17 @@ def test_struct_layouts_match_binding(lib):
     m.dis.B_axis[1] = float("inf")
     assert lib.fdtbx_pattern_workspace(ctypes.byref(m), 150, 1000) == 0
 
+
+
+def test_tile_grid(lib):
+    from paper_2608_23245_amd import binding as B
+    g = B.Geometry(1.0, 100.0, 0.1, 37, 23, 18.5, 11.5, 0.0, 0)
+    tx, ty = ctypes.c_int32(0), ctypes.c_int32(0)
+    for tw, want in [(0, (5, 3)), (2, (19, 1)), (4, (10, 2)), (8, (5, 3)), (16, (3, 6)), (32, (2, 12))]:
+        g.tile_w = tw
+        assert lib.fdtbx_tile_grid(ctypes.byref(g), ctypes.byref(tx), ctypes.byref(ty)) == 0
+        assert (tx.value, ty.value) == want, tw
+    for bad in (1, 3, 6, 64, -8):
+        g.tile_w = bad
+        assert lib.fdtbx_tile_grid(ctypes.byref(g), ctypes.byref(tx), ctypes.byref(ty)) == -1
+        assert "tile_w" in lib.fdtbx_error_string(-1).decode()

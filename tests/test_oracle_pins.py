@@ -715,24 +715,27 @@ def test_g_zero_reduces_to_plain_laue():
     np.testing.assert_allclose(O.pattern(wl, P), O.pattern(wl0, P0), rtol=1e-13, atol=0)
 
 
-def test_culling_lists_are_conservative():
-    """Every reflection with a nonzero profile at some pixel of a tile is in that tile's list."""
-    wl = W.small(4, width=21, height=19, g=(0.04, 0.02, 0.0), center=(9.7, 10.2))
+@pytest.mark.parametrize("tw,th", [(8, 8), (4, 16), (16, 4), (2, 32), (32, 2)])
+def test_culling_lists_are_conservative(tw, th):
+    """Every reflection with a nonzero profile at some pixel of a tile is in that tile's list,
+    for tiles of every shape the GPU launches take."""
+    wl = W.small(4, width=37, height=19, g=(0.04, 0.02, 0.0), center=(17.7, 10.2))
     hkl = O.enumerate_hkl(wl.cell, wl.quad.d_min, wl.quad.d_max)
     P = O.prepare(wl, hkl=hkl, F=np.ones(len(hkl), complex), cull_extinct=False)
     R, Z = O.pixel_rz(wl.geom)
     tab = O.profile_table(P, R, Z).reshape(R.shape[0], R.shape[1], -1)
-    lists = O.culling_lists(wl, hkl, 8, 8)
-    ny, nx = (R.shape[0] + 7) // 8, (R.shape[1] + 7) // 8
+    lists = O.culling_lists(wl, hkl, tw, th)
+    ny, nx = (R.shape[0] + th - 1) // th, (R.shape[1] + tw - 1) // tw
     assert len(lists) == ny * nx
-    nonempty = 0
+    nonempty, listed = 0, 0
     for ty in range(ny):
         for tx in range(nx):
-            blk = tab[ty * 8:(ty + 1) * 8, tx * 8:(tx + 1) * 8]
+            blk = tab[ty * th:(ty + 1) * th, tx * tw:(tx + 1) * tw]
             hit = np.nonzero(np.any(blk != 0, axis=(0, 1)))[0]
             assert set(hit.tolist()) <= set(lists[ty * nx + tx].tolist())
             nonempty += len(hit)
-    assert nonempty > 0
+            listed += len(lists[ty * nx + tx])
+    assert nonempty > 0 and listed < 4 * nonempty
 
 
 # ----------------------------------------------------------------------------- adjoint vs finite differences

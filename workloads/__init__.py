@@ -58,6 +58,7 @@ class Geometry:
     center_x: float        # beam centre, pixel units
     center_y: float
     tilt: float = 0.0      # fibre axis tilted by this angle (rad) about lab y, toward +x
+    tile_w: int = 0        # pixel tile width of the GPU launches (0: 8 x 8 tiles); no effect on the pattern
 
 
 @dataclasses.dataclass
