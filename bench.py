@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--no-cyl", action="store_true", help="skip the exact cylindrical-average leg")
     ap.add_argument("--tile-w", type=int, default=0, choices=(0, 2, 4, 8, 16, 32),
                     help="pixel-tile width of the medium forward (0: chosen by the tile tuner)")
+    ap.add_argument("--no-mirror", action="store_true", help="run every tile (no left-right mirror fold)")
+    ap.add_argument("--no-unfolded", action="store_true", help="skip the unfolded reference forward")
     ap.add_argument("--batch-models", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -153,6 +155,20 @@ def forward_leg(wl, steps, warmup):
     return ms_step, prof_ms, n_evals, state
 
 
+MIRROR = {"on": True}
+
+
+def fold(wl):
+    """wl with the left-right mirror fold on when its geometry allows it (beam centre at
+    width/2, width a multiple of the tile width) and --no-mirror was not given: the per-tile
+    launches run the left tile columns and write each value to the pixel and its mirror (the
+    image is bit-identical; the evaluations counted are the ones performed)."""
+    g = wl.geom
+    if not MIRROR["on"] or not (g.center_x == 0.5 * g.width and g.width % (g.tile_w or 8) == 0):
+        return wl
+    return dataclasses.replace(wl, geom=dataclasses.replace(g, mirror=1))
+
+
 def tune_tiles(wl):
     """Tile shape of workload wl chosen by the tuner (set-up, outside every timed region)."""
     import dataclasses
@@ -182,7 +198,7 @@ def tune_tiles(wl):
 def bench_tilted(args):
     """The medium forward step with the fibre tilted 22 degrees toward the beam."""
     import workloads as W
-    wl = W.with_tilt(W.config1(), math.radians(22.0))
+    wl = fold(W.with_tilt(W.config1(), math.radians(22.0)))
     ms_step, prof_ms, n_evals, state = forward_leg(wl, max(1, min(args.steps, 3)), 1)
     return {"workload": wl.name, "culled_pairs": int(state["idx"].shape[0]), "useful_evals_per_step": int(n_evals),
             "ms_per_pattern": ms_step, "profile_kernel_ms": prof_ms, "evals_per_s": n_evals / (ms_step * 1e-3),
@@ -207,7 +223,7 @@ def bench_lineshapes(args):
     import workloads as W
     out = {}
     for name, code in (("gaussian", 1), ("hosemann", 2)):
-        wl = W.with_disorder(W.config1(), lineshape=code, B_axis=(10.0, 10.0, 10.0))
+        wl = fold(W.with_disorder(W.config1(), lineshape=code, B_axis=(10.0, 10.0, 10.0)))
         ms_step, prof_ms, n_evals, state = forward_leg(wl, max(1, min(args.steps, 3)), 1)
         ach = n_evals * SLOTS_PER_EVAL_LS[name] / (prof_ms * 1e-3)
         out[name] = {"ms_per_pattern": ms_step, "profile_kernel_ms": prof_ms, "useful_evals_per_step": int(n_evals),
@@ -268,7 +284,7 @@ def bench_cyl(args, n_sub=300):
     from paper_2608_23245_amd import atoms_to_device
     from paper_2608_23245_amd import binding as B
 
-    wl = W.config1()
+    wl = fold(W.config1())
     g = wl.geom
     arc = g.pixel / g.distance / g.wavelength
     model = B.make_model(wl)
@@ -324,12 +340,16 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    MIRROR["on"] = not args.no_mirror
     if args.tile_w:
         wl = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, tile_w=args.tile_w))
         tiles = {"tile": f"{args.tile_w}x{64 // args.tile_w}", "tuned": False}
     else:
-        wl, tiles = tune_tiles(wl)
+        wl, tiles = tune_tiles(fold(wl))
+    wl = fold(wl)
     ms_step, prof_ms, n_evals, state = forward_leg(wl, args.steps, args.warmup)
+    from paper_2608_23245_amd import binding as B
+    waves_main = B.launch_waves(B.make_model(wl).geom)
     log(f"forward: {ms_step:.1f} ms/step, profile kernel {prof_ms:.1f} ms, {n_evals:.4e} useful evaluations")
     slots = n_evals * SLOTS_PER_EVAL
     achieved = slots / (prof_ms * 1e-3) / 1e12
@@ -348,7 +368,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "n_hkl": int(state["hkl"].shape[0]), "pixels": wl.geom.width * wl.geom.height,
-                   "tile": tiles["tile"],
+                   "tile": tiles["tile"], "mirror_fold": bool(wl.geom.mirror), "waves_per_tile": waves_main,
                    "nodes": wl.quad.n_nodes ** 2, "culled_pairs": int(state["idx"].shape[0]),
                    "useful_evals_per_step": int(n_evals), "pass": "forward"},
         "ms_per_pattern": ms_step,
@@ -356,9 +376,20 @@ def main():
         "profile_kernel_evals_per_s": n_evals / (prof_ms * 1e-3),
         "tile_tuning": tiles,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(), "kernel": "k_profile<false, 0>", "sources_sha": profile_source_sha(),
+                     "traffic": measured_traffic(), "kernel": f"k_profile<false, 0, {waves_main}>", "sources_sha": profile_source_sha(),
                      "slots_per_eval": SLOTS_PER_EVAL},
     }
+    if wl.geom.mirror and not args.no_unfolded:
+        # the same forward step without the fold, for reference (with the same waves per tile,
+        # so that the two images can be compared bit for bit)
+        waves = waves_main
+        wl0 = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, mirror=0, tile_waves=waves))
+        ms0, prof0, n0, st0 = forward_leg(wl0, max(1, min(args.steps, 3)), 1)
+        assert torch.equal(st0["img"], state["img"]), "the folded image differs from the unfolded one"
+        out["unfolded"] = {"ms_per_pattern": ms0, "profile_kernel_ms": prof0, "useful_evals_per_step": int(n0),
+                           "waves_per_tile": waves,
+                           "profile_kernel_evals_per_s": n0 / (prof0 * 1e-3), "image_bit_identical": True}
+        del st0
     if not args.no_cpu:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(wl, state, args.cpu_pixels)
@@ -401,6 +432,7 @@ def bench_fwd_bwd(args):
     from paper_2608_23245_amd import binding as B
 
     gw = W.config3()
+    gw = dataclasses.replace(gw, model=fold(gw.model), target=fold(gw.target))
     eng_t = AG.PatternEngine(gw.target)
     ta = gw.target.atoms
     at_t = eng_t.atoms(*(torch.as_tensor(v) for v in (ta.x, ta.y, ta.z, ta.B, ta.occ)))
@@ -481,7 +513,7 @@ def bench_batched(args):
     from paper_2608_23245_amd.autotune import tune_batch
     from paper_2608_23245_amd.batch import GraphStep
 
-    wls = W.config4(n_models=args.batch_models)
+    wls = [fold(w) for w in W.config4(n_models=args.batch_models)]
     t0 = time.perf_counter()
     be, tile_ms = tune_batch(wls, candidates=(8, 16, 4))
     torch.cuda.synchronize()

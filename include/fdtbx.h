@@ -70,7 +70,23 @@ typedef struct fdtbx_geometry {
   double tilt;                /* fibre tilt, radians, |tilt| < pi/2 */
   int32_t tile_w;             /* pixel tile width: 2, 4, 8, 16 or 32 (0 means FDTBX_TILE); a tile
                                  is tile_w x (64 / tile_w) pixels, one 64-lane wave */
+  int32_t mirror;             /* 1: fold the left-right mirror symmetry (below); 0: every tile runs */
+  int32_t tile_waves;         /* waves per tile of fdtbx_profile and fdtbx_profile_adjoint: 1, 2 or 4
+                                 (wave w takes the chunks w, w + waves, ... of 64 pairs of the
+                                 tile's list; the forward's first wave adds the others' pixel
+                                 sums in wave order); 0: the library's choice, 4 when the
+                                 launched tiles fit in one round of one-wave workgroups (32 per
+                                 compute unit), 2 up to four rounds, else 1 */
 } fdtbx_geometry;
+/* Mirror fold.  With center_x = width / 2 exactly, pixel (i, j) and its mirror (width-1-i, j)
+ * have y of opposite sign and equal z, so their (R, Z) are bit-identical (R depends on y only
+ * through y^2, for any tilt).  With width a multiple of tile_w, the mirror of a tile is a tile
+ * with the same (R, Z) box, hence the same culling list, and the per-tile kernels compute the
+ * same value for a pixel and its mirror.  mirror = 1 (which requires both conditions) makes
+ * fdtbx_profile, fdtbx_profile_cyl and the batched forward run the left ceil(tiles_x / 2) tile
+ * columns only and write each value to the pixel and its mirror (the image is bit-identical to
+ * the unfolded one with the same waves per tile, fdtbx_launch_waves), and makes the adjoints take grad(i, j) + grad(width-1-i, j) as the
+ * weight of the computed pixel.  fdtbx_pixel_map and fdtbx_cull still produce every tile. */
 
 /* Orientational and lattice disorder (section "Angular peak shapes", tutorial
  * Table "paracrystal").  sigma_theta: Gaussian standard deviation; gamma_theta:
@@ -209,6 +225,11 @@ int fdtbx_structure_factors(const fdtbx_cell* cell, int64_t n_atoms, const float
  * tiles_y = ceil(height / (64 / tile_w)) rows; tile t covers columns (t % tiles_x) tile_w
  * onward and rows (t / tiles_x) (64 / tile_w) onward. */
 int fdtbx_tile_grid(const fdtbx_geometry* geom, int32_t* tiles_x, int32_t* tiles_y);
+
+/* Host: the waves per tile that fdtbx_profile and fdtbx_profile_adjoint use for this
+ * geometry (its tile_waves, or the library's choice for its launched tiles on the current
+ * device). */
+int fdtbx_launch_waves(const fdtbx_geometry* geom, int32_t* waves);
 
 /* Rows of FDTBX_NODE_FLOATS float32 in the node table of n_nodes per side:
  * n_nodes^2 + ceil(n_nodes/FDTBX_NODE_BLOCK)^2; 0 if n_nodes is outside 1..256. */

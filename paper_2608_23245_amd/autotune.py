@@ -65,6 +65,16 @@ def with_tile_w(model: B.Model, tile_w: int) -> B.Model:
     return m
 
 
+def shape_allowed(geom: B.Geometry) -> bool:
+    """The library accepts this tile width for this geometry (under the mirror fold the
+    width must be a multiple of it)."""
+    try:
+        B.tile_grid(geom)
+        return True
+    except B.FdtbxError:
+        return False
+
+
 class TileTuner:
     def __init__(self, candidates=CANDIDATES, reps: int = 2, margin: float = 0.02, min_tiles: int = 0):
         if DEFAULT not in candidates:
@@ -107,13 +117,15 @@ class TileTuner:
         if n_hkl == 0 or tx * ty < self.min_tiles:
             times = {}
         else:
-            times = {tw: self._time(with_tile_w(model, tw), refl, nodes, cull_rec) for tw in self.candidates}
+            times = {tw: self._time(with_tile_w(model, tw), refl, nodes, cull_rec) for tw in self.candidates
+                     if shape_allowed(with_tile_w(model, tw).geom)}
         if not times:
+            own = model.geom.tile_w or DEFAULT
             with self._lock:
-                self._cache[model_key(model, n_hkl)] = (DEFAULT, times)
-            return DEFAULT
+                self._cache[model_key(model, n_hkl)] = (own, times)
+            return own
         best = min(times, key=times.get)
-        if times[best] > (1.0 - self.margin) * times[DEFAULT]:
+        if DEFAULT in times and times[best] > (1.0 - self.margin) * times[DEFAULT]:
             best = DEFAULT
         with self._lock:
             self._cache[model_key(model, n_hkl)] = (best, times)
@@ -136,6 +148,8 @@ def tune_batch(workloads, candidates=(8, 16, 4), reps: int = 1, margin: float = 
         raise ValueError("the candidates must include the default tile width 8")
     best_tw, best_t, best_be, times = None, float("inf"), None, {}
     for tw in order:
+        if not all(shape_allowed(with_tile_w(B.make_model(w), tw).geom) for w in workloads):
+            continue
         be = BatchEngine([dataclasses.replace(w, geom=dataclasses.replace(w.geom, tile_w=tw)) for w in workloads],
                          device=device)
         be.forward()
@@ -155,4 +169,6 @@ def tune_batch(workloads, candidates=(8, 16, 4), reps: int = 1, margin: float = 
         else:
             del be
         torch.cuda.empty_cache()
+    if best_be is None:
+        raise ValueError("no candidate tile shape is allowed for every model of the batch")
     return best_be, times

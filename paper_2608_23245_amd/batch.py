@@ -76,8 +76,12 @@ class BatchEngine:
             n_rows = B.node_rows(wl.quad.n_nodes)
             node_blocks += [_pack(m, r) for r in range(0, n_rows, RB)]
             lens = (rowptr[1:] - rowptr[:-1]).cpu().numpy()
-            items += [_pack(m, t) for t in range(n_tiles)]
-            costs.append(lens)
+            # under the mirror fold only the left tile columns run (their lists serve the mirror)
+            tx_n, _ = B.tile_grid(mod.geom)
+            lcols = (tx_n + 1) // 2 if mod.geom.mirror else tx_n
+            keep = np.nonzero(np.arange(n_tiles) % tx_n < lcols)[0]
+            items += [_pack(m, int(t)) for t in keep]
+            costs.append(lens[keep])
             self.list_len.append(int(idx.shape[0]))
             hkls.append(hkl)
             pixs.append(pix.reshape(-1, 2))

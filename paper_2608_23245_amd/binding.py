@@ -41,7 +41,7 @@ class Geometry(ctypes.Structure):
     _fields_ = [("wavelength", ctypes.c_double), ("distance", ctypes.c_double), ("pixel", ctypes.c_double),
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("center_x", ctypes.c_double), ("center_y", ctypes.c_double), ("tilt", ctypes.c_double),
-                ("tile_w", ctypes.c_int32)]
+                ("tile_w", ctypes.c_int32), ("mirror", ctypes.c_int32), ("tile_waves", ctypes.c_int32)]
 
 
 class Disorder(ctypes.Structure):
@@ -88,6 +88,7 @@ _SIGS = {
                                              ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdtbx_pixel_map": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "fdtbx_tile_grid": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "fdtbx_launch_waves": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "fdtbx_cull_workspace": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64]),
     "fdtbx_cull": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
@@ -187,11 +188,19 @@ def make_model(wl) -> Model:
     g, d, q = wl.geom, wl.dis, wl.quad
     return Model(make_cell(wl.cell),
                  Geometry(g.wavelength, g.distance, g.pixel, g.width, g.height, g.center_x, g.center_y,
-                          float(getattr(g, "tilt", 0.0)), int(getattr(g, "tile_w", 0))),
+                          float(getattr(g, "tilt", 0.0)), int(getattr(g, "tile_w", 0)), int(getattr(g, "mirror", 0)),
+                          int(getattr(g, "tile_waves", 0))),
                  Disorder(d.sigma_theta, d.gamma_theta, (ctypes.c_double * 3)(*d.N_base),
                           (ctypes.c_double * 3)(*d.g), d.intensity_model, int(getattr(d, "lineshape", 0)),
                           (ctypes.c_double * 3)(*getattr(d, "B_axis", (0.0, 0.0, 0.0)))),
                  Quadrature(q.n_nodes, q.T, q.sigma_r, q.m, q.delta, q.d_min, q.d_max, q.extinction))
+
+
+def launch_waves(geom: Geometry) -> int:
+    """fdtbx_launch_waves: waves per tile of the profile and adjoint launches."""
+    w = ctypes.c_int32(0)
+    _check(lib().fdtbx_launch_waves(ctypes.byref(geom), ctypes.byref(w)))
+    return int(w.value)
 
 
 def tile_grid(geom: Geometry):

@@ -32,18 +32,36 @@
 
 namespace fdtbx {
 
-template <int LS>
-__global__ void __launch_bounds__(64) k_profile_adj(ProfParams q, const float* __restrict__ refl, const float* __restrict__ nodes,
-                                                    const double* __restrict__ pix, const double* __restrict__ tile,
-                                                    const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
-                                                    const float* __restrict__ grad_image, double* __restrict__ sums,
-                                                    const int32_t* __restrict__ order) {
-  __shared__ float4 qn[128];
-  __shared__ float2 qd[128];
-  __shared__ int bq[64];
+template <int LS, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_profile_adj(ProfParams q, const float* __restrict__ refl,
+                                                            const float* __restrict__ nodes, const double* __restrict__ pix,
+                                                            const double* __restrict__ tile,
+                                                            const int64_t* __restrict__ offsets,
+                                                            const int32_t* __restrict__ idx,
+                                                            const float* __restrict__ grad_image, double* __restrict__ sums,
+                                                            const int32_t* __restrict__ order) {
+  __shared__ float4 qn[128 * WAVES];
+  __shared__ float2 qd[128 * WAVES];
+  __shared__ int bq[64 * WAVES];
   const int t = order ? order[blockIdx.x] : tile_of_block(q, blockIdx.x);
   if (t < 0) return;
-  adjoint_tile<LS>(q, refl, nodes, pix, tile, offsets, idx, grad_image, sums, t, qn, qd, bq);
+  adjoint_tile<LS, WAVES>(q, refl, nodes, pix, tile, offsets, idx, grad_image, sums, t, qn, qd, bq);
+}
+
+template <int WAVES>
+static void launch_adj(const ProfParams& q, dim3 grid, hipStream_t s, const float* refl, const float* nodes,
+                       const double* pix, const double* tile, const int64_t* offsets, const int32_t* idx,
+                       const int32_t* order, const float* grad_image, double* sums) {
+  const dim3 block(64 * WAVES);
+  if (q.lineshape == FDTBX_LINESHAPE_GAUSSIAN)
+    hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_GAUSSIAN, WAVES>), grid, block, 0, s, q, refl, nodes, pix, tile,
+                       offsets, idx, grad_image, sums, order);
+  else if (q.lineshape == FDTBX_LINESHAPE_HOSEMANN)
+    hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_HOSEMANN, WAVES>), grid, block, 0, s, q, refl, nodes, pix, tile,
+                       offsets, idx, grad_image, sums, order);
+  else
+    hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_LAUE, WAVES>), grid, block, 0, s, q, refl, nodes, pix, tile, offsets,
+                       idx, grad_image, sums, order);
 }
 
 __global__ void k_zero_f64(double* __restrict__ v, int64_t n) {
@@ -289,13 +307,13 @@ __global__ void __launch_bounds__(64) k_b_profile_adj(const fdtbx_batch_entry* _
     double* sm = sums + 6 * e.hkl_off;
     switch (q.lineshape) {  // uniform across the wave
       case FDTBX_LINESHAPE_GAUSSIAN:
-        adjoint_tile<FDTBX_LINESHAPE_GAUSSIAN>(q, rf, nd, px, tb, rp, ix, gi, sm, t, qn, qd, bq);
+        adjoint_tile<FDTBX_LINESHAPE_GAUSSIAN, 1>(q, rf, nd, px, tb, rp, ix, gi, sm, t, qn, qd, bq);
         break;
       case FDTBX_LINESHAPE_HOSEMANN:
-        adjoint_tile<FDTBX_LINESHAPE_HOSEMANN>(q, rf, nd, px, tb, rp, ix, gi, sm, t, qn, qd, bq);
+        adjoint_tile<FDTBX_LINESHAPE_HOSEMANN, 1>(q, rf, nd, px, tb, rp, ix, gi, sm, t, qn, qd, bq);
         break;
       default:
-        adjoint_tile<FDTBX_LINESHAPE_LAUE>(q, rf, nd, px, tb, rp, ix, gi, sm, t, qn, qd, bq);
+        adjoint_tile<FDTBX_LINESHAPE_LAUE, 1>(q, rf, nd, px, tb, rp, ix, gi, sm, t, qn, qd, bq);
     }
   }
 }
@@ -490,16 +508,16 @@ extern "C" int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(6 * n_hkl, 256)), dim3(256), 0, s, sums, 6 * n_hkl);
   FDTBX_LAUNCH_CHECK("adjoint zero");
-  const dim3 grid((unsigned)(order ? order_grid(q.tiles_x, q.tiles_y) : tile_grid(q)));
-  if (q.lineshape == FDTBX_LINESHAPE_GAUSSIAN)
-    hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_GAUSSIAN>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
-                       grad_image, sums, order);
-  else if (q.lineshape == FDTBX_LINESHAPE_HOSEMANN)
-    hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_HOSEMANN>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
-                       grad_image, sums, order);
+  const dim3 grid((unsigned)(order ? order_grid(q.lcols, q.tiles_y) : tile_grid(q)));
+  int waves = 1;
+  rc = tile_waves(&model->geom, (int64_t)q.lcols * q.tiles_y, &waves);
+  if (rc) return rc;
+  if (waves == 4)
+    launch_adj<4>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, grad_image, sums);
+  else if (waves == 2)
+    launch_adj<2>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, grad_image, sums);
   else
-    hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
-                       grad_image, sums, order);
+    launch_adj<1>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, grad_image, sums);
   FDTBX_LAUNCH_CHECK("profile adjoint");
   return FDTBX_OK;
 }

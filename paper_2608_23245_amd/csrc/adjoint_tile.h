@@ -95,29 +95,40 @@ __device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* q
   }
 }
 
-// One 8x8 tile t of one model, walked by one 64-lane wave.  qn, qd: LDS queue of 128 entries;
-// bq: LDS scratch of 64 ints for the block test.
-template <int LS>
+// One tile t of one model, walked by WAVES 64-lane waves: wave w takes the chunks w,
+// w + WAVES, ... of 64 pairs of the tile's list (each pair's sums go out on their own, so the
+// waves need no combining).  qn, qd: LDS queues of 128 entries per wave; bq: LDS scratch of
+// 64 ints per wave for the block test.
+template <int LS, int WAVES = 1>
 __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* __restrict__ refl, const float* __restrict__ nodes,
                                              const double* __restrict__ pix, const double* __restrict__ tile,
                                              const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
                                              const float* __restrict__ grad_image, double* __restrict__ sums, const int t,
                                              float4* qn, float2* qd, int* bq) {
   const int lane = threadIdx.x & 63;
+  const int wv = WAVES > 1 ? (int)(threadIdx.x >> 6) : 0;
+  qn += 128 * wv;
+  qd += 128 * wv;
+  bq += 64 * wv;
   const int tx = t % q.tiles_x, ty = t / q.tiles_x;
   const int i = (tx << q.tlg) + (lane & ((1 << q.tlg) - 1));
   const int j = ty * (64 >> q.tlg) + (lane >> q.tlg);
   const bool in = i < q.W && j < q.H;
   const double R = in ? pix[2 * ((int64_t)j * q.W + i) + 0] : 1.0e30;
   const double Z = in ? pix[2 * ((int64_t)j * q.W + i) + 1] : 0.0;
-  const float gp = in ? grad_image[(int64_t)j * q.W + i] * (float)(q.delta / (R + q.delta)) : 0.0f;
+  // under the mirror fold this pixel also stands for its mirror (unless both are in this tile)
+  const float gimg = !in ? 0.0f
+                         : (q.mirror && 2 * tx + 1 != q.tiles_x)
+                               ? grad_image[(int64_t)j * q.W + i] + grad_image[(int64_t)j * q.W + (q.W - 1 - i)]
+                               : grad_image[(int64_t)j * q.W + i];
+  const float gp = gimg * (float)(q.delta / (R + q.delta));
   const TileBox box = {tile[8 * (int64_t)t + 0], tile[8 * (int64_t)t + 1], tile[8 * (int64_t)t + 2],
                        tile[8 * (int64_t)t + 3]};
   const int64_t p0 = offsets[t], p1 = offsets[t + 1];
   // a tile whose pixels all carry zero weight adds nothing
   if (__ballot(gp != 0.0f) == 0ull) return;
   // 64 pairs at a time, set up lane-parallel as in the forward tile loop
-  for (int64_t base = p0; base < p1; base += 64) {
+  for (int64_t base = p0 + 64 * wv; base < p1; base += 64 * WAVES) {
     int32_t rl = 0;
     int w01 = 0, w23 = 0;
     float lol[3] = {0.f, 0.f, 0.f}, hil[3] = {0.f, 0.f, 0.f};

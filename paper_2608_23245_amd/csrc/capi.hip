@@ -48,6 +48,11 @@ int check_geometry(const fdtbx_geometry* g) {
   const int32_t tw = g->tile_w;
   if (!(tw == 0 || tw == 2 || tw == 4 || tw == 8 || tw == 16 || tw == 32))
     return fail(FDTBX_ERR_INVALID_ARGUMENT, "tile_w must be 0, 2, 4, 8, 16 or 32");
+  if (g->mirror != 0 && g->mirror != 1) return fail(FDTBX_ERR_INVALID_ARGUMENT, "mirror must be 0 or 1");
+  if (!(g->tile_waves == 0 || g->tile_waves == 1 || g->tile_waves == 2 || g->tile_waves == 4))
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "tile_waves must be 0, 1, 2 or 4");
+  if (g->mirror && !(g->center_x == 0.5 * g->width && g->width % (tw ? tw : FDTBX_TILE) == 0))
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "mirror needs center_x = width/2 and width a multiple of tile_w");
   return FDTBX_OK;
 }
 
@@ -125,6 +130,35 @@ extern "C" const char* fdtbx_error_string(int code) {
 }
 
 extern "C" int fdtbx_last_hip_error(void) { return g_hip; }
+
+// Waves per tile of a profile launch over n_tiles tiles: the geometry's tile_waves, or the
+// library's choice.
+// The library's choice: a launch whose tiles fit in one round of one-wave workgroups (32 per
+// compute unit) ends with its longest tiles, so 4 waves share each tile; up to four rounds,
+// 2; beyond that the rounds balance themselves and one wave per tile keeps the most lanes
+// busy per workgroup.
+int fdtbx::tile_waves(const fdtbx_geometry* g, int64_t n_tiles, int* waves) {
+  if (g->tile_waves) {
+    *waves = g->tile_waves;
+    return FDTBX_OK;
+  }
+  int dev = 0, cus = 256;
+  FDTBX_HIP(hipGetDevice(&dev));
+  FDTBX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int64_t round = (int64_t)cus * 32;
+  *waves = n_tiles <= round ? 4 : n_tiles <= 4 * round ? 2 : 1;
+  return FDTBX_OK;
+}
+
+extern "C" int fdtbx_launch_waves(const fdtbx_geometry* geom, int32_t* waves) {
+  if (!geom || !waves) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  int rc = check_geometry(geom);
+  if (rc) return rc;
+  int w = 1;
+  rc = tile_waves(geom, (int64_t)lcols_of(geom) * tiles_y_of(geom), &w);
+  *waves = w;
+  return rc;
+}
 
 extern "C" int fdtbx_tile_grid(const fdtbx_geometry* geom, int32_t* tiles_x, int32_t* tiles_y) {
   if (!geom || !tiles_x || !tiles_y) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");

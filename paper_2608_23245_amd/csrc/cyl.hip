@@ -197,7 +197,9 @@ __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict
     for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
     if (lane == 0 && cnt) atomicAdd(counts, cnt);
   } else if (in) {
-    image[(int64_t)pj * q.W + pi_] = acc * (float)(dphi / (2.0 * M_PI));
+    const float v = acc * (float)(dphi / (2.0 * M_PI));
+    image[(int64_t)pj * q.W + pi_] = v;
+    if (q.mirror && 2 * tx + 1 != q.tiles_x) image[(int64_t)pj * q.W + (q.W - 1 - pi_)] = v;
   }
 }
 
@@ -224,7 +226,7 @@ extern "C" int fdtbx_profile_cyl(const fdtbx_model* model, const float* refl, co
   // a few superblocks, which the spatially grouped order would pile onto few XCDs)
   p.q.sbw = 0;
   hipStream_t s = (hipStream_t)stream;
-  const dim3 grid((unsigned)(order ? order_grid(p.q.tiles_x, p.q.tiles_y) : tile_grid(p.q)));
+  const dim3 grid((unsigned)(order ? order_grid(p.q.lcols, p.q.tiles_y) : tile_grid(p.q)));
   unsigned long long* cp = (unsigned long long*)counts;
   if (counts) {
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, cp);

@@ -13,15 +13,17 @@
 
 namespace fdtbx {
 
+// tiles_x: the launched tile columns (all, or the left half under the mirror fold); stride:
+// tile columns of the detector (tile t = ty * stride + tx).
 struct OrderParams {
-  int32_t tiles_x, tiles_y, S, sbw, sbh;
+  int32_t tiles_x, tiles_y, S, sbw, sbh, stride;
   int64_t nsb;
 };
 
 __device__ static inline int64_t tile_len(const OrderParams& p, const int64_t* offsets, int64_t sb, int i) {
   const int64_t tx = (sb % p.sbw) * p.S + i % p.S, ty = (sb / p.sbw) * p.S + i / p.S;
   if (tx >= p.tiles_x || ty >= p.tiles_y) return -1;
-  const int64_t t = ty * p.tiles_x + tx;
+  const int64_t t = ty * p.stride + tx;
   return offsets[t + 1] - offsets[t];
 }
 
@@ -73,14 +75,15 @@ __global__ void __launch_bounds__(256) k_order_fill(OrderParams p, int64_t n_blo
     const int64_t sb = sorted ? sorted[slot] : slot;
     const int i = sorted ? inner[sb * n + k % n] : (int)(k % n);
     const int64_t tx = (sb % p.sbw) * p.S + i % p.S, ty = (sb / p.sbw) * p.S + i / p.S;
-    if (tx < p.tiles_x && ty < p.tiles_y) t = (int32_t)(ty * p.tiles_x + tx);
+    if (tx < p.tiles_x && ty < p.tiles_y) t = (int32_t)(ty * p.stride + tx);
   }
   order[b] = t;
 }
 
 static void order_params(const fdtbx_geometry* g, OrderParams* p) {
-  p->tiles_x = tiles_x_of(g);
+  p->tiles_x = lcols_of(g);
   p->tiles_y = tiles_y_of(g);
+  p->stride = tiles_x_of(g);
   p->S = order_super(p->tiles_x, p->tiles_y);
   p->sbw = (int32_t)ceil_div(p->tiles_x, p->S);
   p->sbh = (int32_t)ceil_div(p->tiles_y, p->S);
@@ -93,7 +96,7 @@ using namespace fdtbx;
 
 extern "C" int64_t fdtbx_tile_order_size(const fdtbx_geometry* geom) {
   if (!geom || check_geometry(geom)) return 0;
-  return order_grid(tiles_x_of(geom), tiles_y_of(geom));
+  return order_grid(lcols_of(geom), tiles_y_of(geom));
 }
 
 extern "C" size_t fdtbx_tile_order_workspace(const fdtbx_geometry* geom) {

@@ -29,19 +29,42 @@
 
 namespace fdtbx {
 
-// COUNT: counting pass (support test only, the same for every lineshape); LS: lineshape.
-template <bool COUNT, int LS>
-__global__ void __launch_bounds__(64) k_profile(ProfParams q, const float* __restrict__ refl, const float* __restrict__ nodes,
-                                                const double* __restrict__ pix, const double* __restrict__ tile,
-                                                const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
-                                                float* __restrict__ image, unsigned long long* __restrict__ counts,
-                                                const int32_t* __restrict__ order) {
-  // queue of window nodes that can be inside the support of some pixel of the tile
-  __shared__ float4 qn[128];
-  __shared__ int bq[64];
+// COUNT: counting pass (support test only, the same for every lineshape); LS: lineshape;
+// WAVES: waves per tile (each its share of the tile's list).
+template <bool COUNT, int LS, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_profile(ProfParams q, const float* __restrict__ refl,
+                                                        const float* __restrict__ nodes, const double* __restrict__ pix,
+                                                        const double* __restrict__ tile, const int64_t* __restrict__ offsets,
+                                                        const int32_t* __restrict__ idx, float* __restrict__ image,
+                                                        unsigned long long* __restrict__ counts,
+                                                        const int32_t* __restrict__ order) {
+  // per wave, the queue of window nodes that can be inside the support of some pixel of the tile
+  __shared__ float4 qn[128 * WAVES];
+  __shared__ int bq[64 * WAVES];
+  __shared__ float xacc[WAVES > 1 ? 64 * (WAVES - 1) : 1];
   const int t = order ? order[blockIdx.x] : tile_of_block(q, blockIdx.x);
-  if (t < 0) return;
-  profile_tile<COUNT, LS>(q, refl, nodes, pix, tile, offsets, idx, image, counts, t, qn, bq);
+  if (t < 0) return;  // uniform across the workgroup
+  profile_tile<COUNT, LS, WAVES>(q, refl, nodes, pix, tile, offsets, idx, image, counts, t, qn, bq, xacc);
+}
+
+template <int WAVES>
+static void launch_profile(const ProfParams& q, dim3 grid, hipStream_t s, const float* refl, const float* nodes,
+                           const double* pix, const double* tile, const int64_t* offsets, const int32_t* idx,
+                           const int32_t* order, float* image, int64_t* counts) {
+  const dim3 block(64 * WAVES);
+  unsigned long long* const nc = nullptr;
+  if (counts)
+    hipLaunchKernelGGL((k_profile<true, FDTBX_LINESHAPE_LAUE, WAVES>), grid, block, 0, s, q, refl, nodes, pix, tile, offsets,
+                       idx, image, (unsigned long long*)counts, order);
+  else if (q.lineshape == FDTBX_LINESHAPE_GAUSSIAN)
+    hipLaunchKernelGGL((k_profile<false, FDTBX_LINESHAPE_GAUSSIAN, WAVES>), grid, block, 0, s, q, refl, nodes, pix, tile,
+                       offsets, idx, image, nc, order);
+  else if (q.lineshape == FDTBX_LINESHAPE_HOSEMANN)
+    hipLaunchKernelGGL((k_profile<false, FDTBX_LINESHAPE_HOSEMANN, WAVES>), grid, block, 0, s, q, refl, nodes, pix, tile,
+                       offsets, idx, image, nc, order);
+  else
+    hipLaunchKernelGGL((k_profile<false, FDTBX_LINESHAPE_LAUE, WAVES>), grid, block, 0, s, q, refl, nodes, pix, tile, offsets,
+                       idx, image, nc, order);
 }
 
 // Batched models, persistent: every wave takes (model, tile) items from a shared counter
@@ -72,13 +95,13 @@ __global__ void __launch_bounds__(64) k_b_profile(const fdtbx_batch_entry* __res
     float* im = image + e.pix_off;
     switch (q.lineshape) {  // uniform across the wave
       case FDTBX_LINESHAPE_GAUSSIAN:
-        profile_tile<false, FDTBX_LINESHAPE_GAUSSIAN>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
+        profile_tile<false, FDTBX_LINESHAPE_GAUSSIAN, 1>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
         break;
       case FDTBX_LINESHAPE_HOSEMANN:
-        profile_tile<false, FDTBX_LINESHAPE_HOSEMANN>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
+        profile_tile<false, FDTBX_LINESHAPE_HOSEMANN, 1>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
         break;
       default:
-        profile_tile<false, FDTBX_LINESHAPE_LAUE>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
+        profile_tile<false, FDTBX_LINESHAPE_LAUE, 1>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
     }
   }
 }
@@ -116,21 +139,16 @@ extern "C" int fdtbx_profile(const fdtbx_model* model, const float* refl, const 
   ProfParams q;
   prof_params(model, &q);
   hipStream_t s = (hipStream_t)stream;
-  const dim3 grid((unsigned)(order ? order_grid(q.tiles_x, q.tiles_y) : tile_grid(q)));
-  unsigned long long* const nc = nullptr;
-  if (counts) {
-    hipLaunchKernelGGL((k_profile<true, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets, idx,
-                       image, (unsigned long long*)counts, order);
-  } else if (q.lineshape == FDTBX_LINESHAPE_GAUSSIAN) {
-    hipLaunchKernelGGL((k_profile<false, FDTBX_LINESHAPE_GAUSSIAN>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets,
-                       idx, image, nc, order);
-  } else if (q.lineshape == FDTBX_LINESHAPE_HOSEMANN) {
-    hipLaunchKernelGGL((k_profile<false, FDTBX_LINESHAPE_HOSEMANN>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets,
-                       idx, image, nc, order);
-  } else {
-    hipLaunchKernelGGL((k_profile<false, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, q, refl, nodes, pix, tile, offsets,
-                       idx, image, nc, order);
-  }
+  const dim3 grid((unsigned)(order ? order_grid(q.lcols, q.tiles_y) : tile_grid(q)));
+  int waves = 1;
+  rc = tile_waves(&model->geom, (int64_t)q.lcols * q.tiles_y, &waves);
+  if (rc) return rc;
+  if (waves == 4)
+    launch_profile<4>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, image, counts);
+  else if (waves == 2)
+    launch_profile<2>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, image, counts);
+  else
+    launch_profile<1>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, image, counts);
   FDTBX_LAUNCH_CHECK("profile");
   return FDTBX_OK;
 }

@@ -13,6 +13,8 @@ namespace fdtbx {
 struct ProfParams {
   int32_t W, H, tiles_x, tiles_y;
   int32_t tlg;      // tiles are 2^tlg pixels wide and 64 >> tlg high
+  int32_t lcols;    // tile columns launched: tiles_x, or the left half under the mirror fold
+  int32_t mirror;   // 1: each computed pixel is also written to (W - 1 - i, j)
   int32_t lineshape;
   int32_t n;        // nodes per side
   float T, inv_h;   // grid half extent, 1/spacing
@@ -36,9 +38,10 @@ __host__ __device__ inline int32_t superblocks_per_row(int32_t tiles_x, int32_t 
   return sbw * sbh >= 8 * kXcds ? (int32_t)sbw : 0;
 }
 
-// Workgroups of a per-tile launch (the padded superblock grid, or one per tile).
+// Workgroups of a per-tile launch (the padded superblock grid of the launched columns, or one
+// per launched tile).
 __host__ __device__ inline int64_t tile_grid(const ProfParams& q) {
-  if (q.sbw == 0) return (int64_t)q.tiles_x * q.tiles_y;
+  if (q.sbw == 0) return (int64_t)q.lcols * q.tiles_y;
   const int64_t nsb = (int64_t)q.sbw * ((q.tiles_y + kSuper - 1) / kSuper);
   return (int64_t)kXcds * kSuper * kSuper * ((nsb + kXcds - 1) / kXcds);
 }
@@ -54,13 +57,13 @@ __host__ __device__ inline int64_t order_grid(int32_t tiles_x, int32_t tiles_y) 
   return (int64_t)kXcds * S * S * ((nsb + kXcds - 1) / kXcds);
 }
 
-// Tile of workgroup b, or -1 for a padding workgroup (past the detector).
+// Tile of workgroup b, or -1 for a padding workgroup (past the launched columns).
 __device__ inline int tile_of_block(const ProfParams& q, int b) {
-  if (q.sbw == 0) return b;
+  if (q.sbw == 0) return (b / q.lcols) * q.tiles_x + b % q.lcols;
   const int x = b % kXcds, k = b / kXcds;
   const int sb = (k / (kSuper * kSuper)) * kXcds + x, i = k % (kSuper * kSuper);
   const int tx = (sb % q.sbw) * kSuper + i % kSuper, ty = (sb / q.sbw) * kSuper + i / kSuper;
-  return tx < q.tiles_x && ty < q.tiles_y ? ty * q.tiles_x + tx : -1;
+  return tx < q.lcols && ty < q.tiles_y ? ty * q.tiles_x + tx : -1;
 }
 
 struct Window {
@@ -317,6 +320,8 @@ __host__ __device__ inline void prof_params(const fdtbx_model* model, ProfParams
   q->tlg = __builtin_ctz((unsigned)tw);
   q->tiles_x = (q->W + tw - 1) / tw;
   q->tiles_y = (q->H + th - 1) / th;
+  q->mirror = model->geom.mirror;
+  q->lcols = q->mirror ? (q->tiles_x + 1) / 2 : q->tiles_x;
   q->n = model->quad.n_nodes;
   q->T = (float)model->quad.T;
   q->inv_h = (float)(model->quad.n_nodes / (2.0 * model->quad.T));
@@ -326,7 +331,7 @@ __host__ __device__ inline void prof_params(const fdtbx_model* model, ProfParams
   q->tiny = 1.0e-12f;
   q->margin = 1.0e-3f;
   q->delta = model->quad.delta;
-  q->sbw = superblocks_per_row(q->tiles_x, q->tiles_y);
+  q->sbw = superblocks_per_row(q->lcols, q->tiles_y);
 }
 
 }  // namespace fdtbx

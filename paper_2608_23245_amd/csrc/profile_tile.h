@@ -83,13 +83,20 @@ __device__ __forceinline__ void walk_queue(const float4* qn, int cnt, const floa
   accr += part;
 }
 
-template <bool COUNT, int LS>
+// WAVES waves share a tile: wave w takes the chunks w, w + WAVES, ... of 64 pairs of the
+// tile's list (its own LDS queue: qn + 128 w, bq + 64 w), and wave 0 adds the others' pixel
+// sums (xacc, 64 floats per extra wave) in wave order before it writes the tile.
+template <bool COUNT, int LS, int WAVES = 1>
 __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* __restrict__ refl,
                                              const float* __restrict__ nodes, const double* __restrict__ pix,
                                              const double* __restrict__ tile, const int64_t* __restrict__ offsets,
                                              const int32_t* __restrict__ idx, float* __restrict__ image,
-                                             unsigned long long* __restrict__ counts, const int t, float4* qn, int* bq) {
+                                             unsigned long long* __restrict__ counts, const int t, float4* qn, int* bq,
+                                             float* xacc = nullptr) {
   const int lane = threadIdx.x & 63;
+  const int wv = WAVES > 1 ? (int)(threadIdx.x >> 6) : 0;
+  qn += 128 * wv;
+  bq += 64 * wv;
   const int tx = t % q.tiles_x, ty = t / q.tiles_x;
   const int i = (tx << q.tlg) + (lane & ((1 << q.tlg) - 1));
   const int j = ty * (64 >> q.tlg) + (lane >> q.tlg);
@@ -105,7 +112,7 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
   unsigned long long cnt = 0;
   // 64 pairs at a time: each lane sets up one pair (window and alpha box); the wave then
   // works through the pairs with a non-empty window, reading their set-up from that lane
-  for (int64_t base = p0; base < p1; base += 64) {
+  for (int64_t base = p0 + 64 * wv; base < p1; base += 64 * WAVES) {
     int32_t rl = 0;
     int w01 = 0, w23 = 0;
     float lol[3] = {0.f, 0.f, 0.f}, hil[3] = {0.f, 0.f, 0.f};
@@ -163,8 +170,18 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
   if (COUNT) {
     for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
     if (lane == 0 && cnt) atomicAdd(counts, cnt);
-  } else if (in) {
-    image[(int64_t)j * q.W + i] = (float)(q.delta / (R + q.delta)) * acc;
+  } else {
+    if (WAVES > 1) {
+      if (wv > 0) xacc[64 * (wv - 1) + lane] = acc;
+      __syncthreads();
+      if (wv > 0) return;
+      for (int k = 1; k < WAVES; ++k) acc += xacc[64 * (k - 1) + lane];
+    }
+    if (!in) return;
+    const float v = (float)(q.delta / (R + q.delta)) * acc;
+    image[(int64_t)j * q.W + i] = v;
+    // mirror fold: tile column tiles_x - 1 - tx holds the mirror pixels (unless it is this one)
+    if (q.mirror && 2 * tx + 1 != q.tiles_x) image[(int64_t)j * q.W + (q.W - 1 - i)] = v;
   }
 }
 

@@ -150,3 +150,36 @@ def test_tile_grid(lib):
         g.tile_w = bad
         assert lib.fdtbx_tile_grid(ctypes.byref(g), ctypes.byref(tx), ctypes.byref(ty)) == -1
         assert "tile_w" in lib.fdtbx_error_string(-1).decode()
+
+
+def test_mirror_fold_conditions(lib):
+    from paper_2608_23245_amd import binding as B
+    tx, ty = ctypes.c_int32(0), ctypes.c_int32(0)
+    ok = B.Geometry(1.0, 100.0, 0.1, 48, 23, 24.0, 11.5, 0.3, 16, 1)
+    assert lib.fdtbx_tile_grid(ctypes.byref(ok), ctypes.byref(tx), ctypes.byref(ty)) == 0
+    assert (tx.value, ty.value) == (3, 6)      # every tile column is still in the grid
+    for bad in (B.Geometry(1.0, 100.0, 0.1, 48, 23, 24.2, 11.5, 0.0, 16, 1),   # beam off the middle
+                B.Geometry(1.0, 100.0, 0.1, 40, 23, 20.0, 11.5, 0.0, 16, 1),   # width not a multiple of 16
+                B.Geometry(1.0, 100.0, 0.1, 48, 23, 24.0, 11.5, 0.0, 16, 2)):
+        assert lib.fdtbx_tile_grid(ctypes.byref(bad), ctypes.byref(tx), ctypes.byref(ty)) == -1
+        assert "mirror" in lib.fdtbx_error_string(-1).decode()
+    # the launch order covers the left 3 of the 6 tile columns of 8 pixels (3 x 3 tiles, padded
+    # to whole rounds of the 8 XCDs), against 6 x 3 without the fold
+    g = B.Geometry(1.0, 100.0, 0.1, 48, 23, 24.0, 11.5, 0.0, 8, 1)
+    lib.fdtbx_tile_order_size.restype = ctypes.c_int64
+    assert lib.fdtbx_tile_order_size(ctypes.byref(g)) == 16
+    g.mirror = 0
+    assert lib.fdtbx_tile_order_size(ctypes.byref(g)) == 24
+
+
+def test_tile_waves_values(lib):
+    from paper_2608_23245_amd import binding as B
+    tx, ty = ctypes.c_int32(0), ctypes.c_int32(0)
+    g = B.Geometry(1.0, 100.0, 0.1, 48, 23, 20.0, 11.5, 0.0, 8, 0, 0)
+    for w in (0, 1, 2, 4):
+        g.tile_waves = w
+        assert lib.fdtbx_tile_grid(ctypes.byref(g), ctypes.byref(tx), ctypes.byref(ty)) == 0
+    for w in (3, 8, -1):
+        g.tile_waves = w
+        assert lib.fdtbx_tile_grid(ctypes.byref(g), ctypes.byref(tx), ctypes.byref(ty)) == -1
+        assert "tile_waves" in lib.fdtbx_error_string(-1).decode()

@@ -1,0 +1,154 @@
+"""The left-right mirror fold (fdtbx_geometry.mirror), through the C ABI: with the beam
+centre at width/2 the folded launches give images bit-identical to the unfolded ones
+(pattern and cylindrical average, any tilt, tile shape and lineshape, an odd number of tile
+columns included), gradients equal to the unfolded ones to float32 summation order, about
+half the evaluations, and a batch of folded models equal to their unfolded single runs."""
+import dataclasses
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2608_23245_amd import Pipeline  # noqa: E402
+from paper_2608_23245_amd import autograd as AG  # noqa: E402
+from paper_2608_23245_amd import binding as B  # noqa: E402
+from paper_2608_23245_amd.batch import BatchEngine  # noqa: E402
+
+DEG = math.pi / 180
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def folded(wl, mirror=1, tw=None):
+    g = dataclasses.replace(wl.geom, mirror=mirror)
+    if tw is not None:
+        g = dataclasses.replace(g, tile_w=tw)
+    return dataclasses.replace(wl, geom=g)
+
+
+# centred beams (center_x = width / 2); widths multiples of the tile width
+CASES = {
+    "laue_voigt": (dict(seed=161, width=48, height=30, sigma_theta=3 * DEG, gamma_theta=1 * DEG,
+                        g=(0.02, 0.02, 0.0)), 8),
+    "odd_columns": (dict(seed=162, width=40, height=27, sigma_theta=2 * DEG, gamma_theta=2 * DEG), 8),
+    "tilted_16x4": (dict(seed=163, width=64, height=36, tilt=22 * DEG, sigma_theta=2 * DEG, gamma_theta=1 * DEG), 16),
+    "gaussian_4x16": (dict(seed=164, width=44, height=40, sigma_theta=3 * DEG, lineshape=1, B_axis=(4.0, 9.0, 2.5)), 4),
+    "hosemann_odd": (dict(seed=165, width=56, height=25, sigma_theta=3 * DEG, g=(0.03, 0.02, 0.01), lineshape=2), 8),
+}
+
+
+def _small(name):
+    kw, tw = CASES[name]
+    kw = dict(kw)
+    kw["center"] = (kw["width"] / 2.0, kw["height"] / 2.0 + 0.3)
+    wl = W.small(**kw)
+    return dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, tile_w=tw))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_folded_pattern_is_bit_identical(name):
+    wl = _small(name)
+    say(f"mirror fold, pattern {name} (tile width {wl.geom.tile_w})")
+    full = Pipeline(wl)
+    img_full = full.pattern()
+    fold = Pipeline(folded(wl))
+    img_fold = fold.pattern()
+    torch.cuda.synchronize()
+    assert torch.equal(img_full, img_fold)
+    a = img_full.cpu().numpy()
+    assert a.max() > 0 and np.array_equal(a, a[:, ::-1])
+    # the folded launch evaluates only the left tile columns
+    def count(p):
+        _, F2 = p.structure_factors()
+        refl, cull = B.reflection_prep(p.model, p.hkl, F2)
+        pix, tile = B.pixel_map(p.model.geom)
+        off, idx = B.cull(p.model.geom, tile, cull)
+        return B.profile(p.model, refl, B.node_table(p.model), pix, tile, off, idx, count=True,
+                         order=B.tile_order(p.model.geom, off))
+    n_full, n_fold = count(full), count(fold)
+    say(f"  evaluations {n_full} unfolded, {n_fold} folded")
+    tx, _ = B.tile_grid(fold.model.geom)
+    if tx % 2 == 0:
+        assert 2 * n_fold == n_full
+    else:
+        assert n_full / 2 < n_fold < n_full
+
+
+def test_folded_pattern_vs_oracle():
+    wl = folded(_small("tilted_16x4"))
+    pipe = Pipeline(wl)
+    img = pipe.pattern().cpu().numpy().astype(np.float64)
+    ref = O.pattern(wl, O.prepare(wl, hkl=pipe.hkl.cpu().numpy()))
+    r = float(np.linalg.norm(img - ref) / np.linalg.norm(ref))
+    big = ref > 1e-3 * ref.max()
+    px = float(np.max(np.abs(img[big] - ref[big]) / ref[big]))
+    say(f"folded vs oracle: rel-L2 {r:.2e}, per-pixel {px:.2e}")
+    assert r <= 1e-4 and px <= 1e-3
+
+
+@pytest.mark.parametrize("name", ["laue_voigt", "odd_columns"])
+def test_folded_cyl_is_bit_identical(name):
+    wl = _small(name)
+    imgs = []
+    for mirror in (0, 1):
+        w = folded(wl, mirror)
+        model = B.make_model(w)
+        hkl = O.enumerate_hkl(w.cell, w.quad.d_min, w.quad.d_max)
+        h = torch.from_numpy(np.ascontiguousarray(hkl[~O.extinct_mask(hkl, w.dis, w.quad.extinction)])).cuda()
+        refl, _ = B.reflection_prep(model, h, torch.ones(h.shape[0], dtype=torch.float32, device="cuda"))
+        cull = B.cyl_records(model, h)
+        pix, tile = B.pixel_map(model.geom)
+        off, idx = B.cull(model.geom, tile, cull)
+        imgs.append(B.profile_cyl(model, refl, B.node_table(model), pix, off, idx, 2e-3,
+                                  order=B.tile_order(model.geom, off)))
+    torch.cuda.synchronize()
+    assert imgs[0].max() > 0 and torch.equal(imgs[0], imgs[1])
+
+
+@pytest.mark.parametrize("name", ["laue_voigt", "odd_columns", "tilted_16x4"])
+def test_folded_gradients(name):
+    wl = _small(name)
+    say(f"mirror fold, gradients {name}")
+    G = np.random.default_rng(9).normal(size=(wl.geom.height, wl.geom.width))
+    res = []
+    for mirror in (0, 1):
+        eng = AG.PatternEngine(folded(wl, mirror))
+        a = wl.atoms
+        atoms = eng.atoms(*(torch.as_tensor(v) for v in (a.x, a.y, a.z, a.B, a.occ)))
+        F, F2 = B.structure_factors(eng.cell, atoms, eng.hkl)
+        eng.plan.run(eng.hkl, F2)
+        out, glob, dF2 = B.pattern_backward(eng.plan, eng.hkl, F, torch.as_tensor(G, dtype=torch.float32).cuda(), atoms)
+        res.append(({k: v.cpu().numpy().astype(np.float64) for k, v in out.items()}, glob.cpu().numpy(),
+                    dF2.cpu().numpy().astype(np.float64)))
+    (o0, g0, d0), (o1, g1, d1) = res
+    assert np.abs(d1 - d0).max() <= 1e-5 * np.abs(d0).max()
+    for k in o0:
+        assert np.abs(o1[k] - o0[k]).max() <= 1e-5 * np.abs(o0[k]).max(), k
+    assert np.all(np.abs(g1 - g0) <= 1e-5 * np.abs(g0) + 1e-9 * np.abs(g0).max())
+
+
+def test_folded_batch_matches_unfolded_single_runs():
+    wls = [folded(_small("laue_voigt")), folded(_small("odd_columns")), folded(_small("tilted_16x4")),
+           _small("gaussian_4x16")]
+    be = BatchEngine(wls)
+    be.forward()
+    torch.cuda.synchronize()
+    for m, wl in enumerate(wls):
+        ref = Pipeline(folded(wl, 0)).pattern().cpu().numpy().astype(np.float64)
+        got = be.image_of(m).cpu().numpy().astype(np.float64)
+        r = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        say(f"  model {m} (mirror {wl.geom.mirror}): rel-L2 vs unfolded single run {r:.2e}")
+        assert r <= 1e-5

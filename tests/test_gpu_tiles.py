@@ -209,3 +209,51 @@ def test_tune_batch_keeps_the_fastest_engine():
         ref = Pipeline(wl).pattern().cpu().numpy().astype(np.float64)
         got = be.image_of(m).cpu().numpy().astype(np.float64)
         assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref), m
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4])
+@pytest.mark.parametrize("name", ["ragged", "hosemann"])
+def test_tile_waves_pattern_and_counts(name, waves):
+    """Waves per tile (fdtbx_geometry.tile_waves): the same image to float32 summation order
+    and the same number of support-passing evaluations for 1, 2 and 4 waves."""
+    base = W.small(**CASES[name])
+    wl = dataclasses.replace(base, geom=dataclasses.replace(base.geom, tile_waves=waves))
+    pipe = Pipeline(wl)
+    img = pipe.pattern().cpu().numpy()
+    ref = O.pattern(wl, O.prepare(wl, hkl=pipe.hkl.cpu().numpy()))
+    check_pattern(img, ref, f"pattern {name}, {waves} waves per tile")
+    counts = []
+    for w in (1, waves):
+        m = B.make_model(dataclasses.replace(base, geom=dataclasses.replace(base.geom, tile_waves=w)))
+        _, F2 = pipe.structure_factors()
+        refl, cull = B.reflection_prep(m, pipe.hkl, F2)
+        pix, tile = B.pixel_map(m.geom)
+        off, idx = B.cull(m.geom, tile, cull)
+        counts.append(B.profile(m, refl, B.node_table(m), pix, tile, off, idx, count=True))
+    assert counts[0] == counts[1] > 0
+
+
+@pytest.mark.parametrize("waves", [1, 2, 4])
+def test_tile_waves_adjoint_vs_oracle(waves):
+    wl = W.small(127, n_atoms=30, width=23, height=18, sigma_theta=3 * DEG, gamma_theta=1 * DEG, g=(0.03, 0.02, 0.01))
+    wl = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, tile_waves=waves))
+    say(f"adjoint, {waves} waves per tile")
+    G = np.random.default_rng(10).normal(size=(wl.geom.height, wl.geom.width))
+    eng = AG.PatternEngine(wl)
+    a = wl.atoms
+    atoms = eng.atoms(*(torch.as_tensor(v) for v in (a.x, a.y, a.z, a.B, a.occ)))
+    F, F2 = B.structure_factors(eng.cell, atoms, eng.hkl)
+    eng.plan.run(eng.hkl, F2)
+    out, glob, _ = B.pattern_backward(eng.plan, eng.hkl, F, torch.as_tensor(G, dtype=torch.float32).cuda(), atoms)
+    P = O.prepare(wl, hkl=eng.hkl.cpu().numpy(), cull_extinct=False)
+    ref = O.gradients(wl, P, G)
+    for k in ("x", "y", "z", "B", "occ"):
+        got = out[k].cpu().numpy().astype(np.float64)
+        r = np.asarray(ref["atoms"][k], np.float64)
+        err = np.abs(got - r) / np.maximum(np.abs(r), 1e-3 * np.abs(r).max())
+        assert err.max() <= 1e-3, (k, err.max())
+    rg = np.array([ref["sigma_theta"], ref["gamma_theta"], *ref["N_base"], *ref["g"], *ref["B_axis"]], np.float64)
+    gg = glob.cpu().numpy()[:rg.size]
+    err = np.abs(gg - rg) / np.maximum(np.abs(rg), 1e-3 * np.abs(rg).max())
+    say(f"  globals: max rel err {err.max():.2e}")
+    assert err.max() <= 1e-3
