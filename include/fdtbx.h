@@ -71,10 +71,11 @@ typedef struct fdtbx_geometry {
   int32_t tile_w;             /* pixel tile width: 2, 4, 8, 16 or 32 (0 means FDTBX_TILE); a tile
                                  is tile_w x (64 / tile_w) pixels, one 64-lane wave */
   int32_t mirror;             /* 1: fold the left-right mirror symmetry (below); 0: every tile runs */
-  int32_t tile_waves;         /* waves per tile of fdtbx_profile and fdtbx_profile_adjoint: 1, 2 or 4
-                                 (wave w takes the chunks w, w + waves, ... of 64 pairs of the
-                                 tile's list; the forward's first wave adds the others' pixel
-                                 sums in wave order); 0: the library's choice, 4 when the
+  int32_t tile_waves;         /* waves per tile of fdtbx_profile, fdtbx_profile_adjoint and
+                                 fdtbx_profile_cyl: 1, 2 or 4 (wave w takes the chunks w, w + waves,
+                                 ... of 64 pairs of the tile's list, or for the cylindrical average
+                                 of 8 ring indices of each pair; the forward's first wave adds the
+                                 others' pixel sums in wave order); 0: the library's choice, 4 when the
                                  launched tiles fit in one round of one-wave workgroups (32 per
                                  compute unit), 2 up to four rounds, else 1 */
 } fdtbx_geometry;

@@ -48,17 +48,25 @@ __device__ __forceinline__ void walk_ring(const float4* qn, int cnt, const float
   accr += part;
 }
 
-template <bool COUNT, int LS>
-__global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict__ refl, const float* __restrict__ nodes,
-                                            const double* __restrict__ pix, const int64_t* __restrict__ offsets,
-                                            const int32_t* __restrict__ idx, float* __restrict__ image,
-                                            unsigned long long* __restrict__ counts, const int32_t* __restrict__ order) {
-  __shared__ float4 qn[128];
-  __shared__ int bq[64];
+// WAVES waves share a tile: per (tile, reflection), wave w takes the blocks w, w + WAVES, ...
+// of kJB ring indices (its own LDS queue), and wave 0 adds the others' pixel sums in wave
+// order at the end.
+template <bool COUNT, int LS, int WAVES>
+__global__ void __launch_bounds__(64 * WAVES) k_cyl(CylParams p, const float* __restrict__ refl,
+                                                    const float* __restrict__ nodes, const double* __restrict__ pix,
+                                                    const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
+                                                    float* __restrict__ image, unsigned long long* __restrict__ counts,
+                                                    const int32_t* __restrict__ order) {
+  __shared__ float4 qn_all[128 * WAVES];
+  __shared__ int bq_all[64 * WAVES];
+  __shared__ float xacc[WAVES > 1 ? 64 * (WAVES - 1) : 1];
   const ProfParams& q = p.q;
   const int lane = threadIdx.x & 63;
+  const int wv = WAVES > 1 ? (int)(threadIdx.x >> 6) : 0;
+  float4* const qn = qn_all + 128 * wv;
+  int* const bq = bq_all + 64 * wv;
   const int t = order ? order[blockIdx.x] : tile_of_block(q, blockIdx.x);
-  if (t < 0) return;
+  if (t < 0) return;  // uniform across the workgroup
   const int tx = t % q.tiles_x, ty = t / q.tiles_x;
   const int pi_ = (tx << q.tlg) + (lane & ((1 << q.tlg) - 1));
   const int pj = ty * (64 >> q.tlg) + (lane >> q.tlg);
@@ -71,6 +79,9 @@ __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict
   const double dphi = 2.0 * M_PI / (double)n;
   const int ring_lo = -(n / 2), ring_hi = n - n / 2 - 1;
   const double cd = cos(dphi), sd = sin(dphi);
+  // rotation over the blocks of the other waves
+  const double cw = WAVES > 1 ? cos((double)(kJB * (WAVES - 1)) * dphi) : 1.0;
+  const double sw = WAVES > 1 ? sin((double)(kJB * (WAVES - 1)) * dphi) : 0.0;
   const int64_t p0 = offsets[t], p1 = offsets[t + 1];
   float acc = 0.0f;
   unsigned long long cnt = 0;
@@ -126,11 +137,11 @@ __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict
     if (J0 > J1) continue;
     HoseK hk = {};
     if (LS == FDTBX_LINESHAPE_HOSEMANN && !COUNT) hose_constants(rec, hk);
-    double cj = cos((double)J0 * dphi), sj = sin((double)J0 * dphi);
+    double cj = cos((double)(J0 + kJB * wv) * dphi), sj = sin((double)(J0 + kJB * wv) * dphi);
     const float fZ = (float)(Z - ZD), fz = (float)Z;
     float accp = 0.0f;
     // kJB consecutive ring indices share one node window, queue and walk
-    for (int jb = J0; jb <= J1; jb += kJB) {
+    for (int jb = J0 + kJB * wv; jb <= J1; jb += kJB * WAVES) {
       float al[kJB][3];
       float amin[3] = {INFINITY, INFINITY, INFINITY}, amax[3] = {-INFINITY, -INFINITY, -INFINITY};
       float pmin[3] = {INFINITY, INFINITY, INFINITY}, pmax[3] = {-INFINITY, -INFINITY, -INFINITY};
@@ -155,6 +166,11 @@ __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict
         }
         const double cn = cj * cd - sj * sd;
         sj = sj * cd + cj * sd;
+        cj = cn;
+      }
+      if (WAVES > 1) {
+        const double cn = cj * cw - sj * sw;
+        sj = sj * cw + cj * sw;
         cj = cn;
       }
       float lo[3], hi[3];
@@ -196,7 +212,14 @@ __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict
   if (COUNT) {
     for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
     if (lane == 0 && cnt) atomicAdd(counts, cnt);
-  } else if (in) {
+  } else {
+    if (WAVES > 1) {
+      if (wv > 0) xacc[64 * (wv - 1) + lane] = acc;
+      __syncthreads();
+      if (wv > 0) return;
+      for (int k = 1; k < WAVES; ++k) acc += xacc[64 * (k - 1) + lane];
+    }
+    if (!in) return;
     const float v = acc * (float)(dphi / (2.0 * M_PI));
     image[(int64_t)pj * q.W + pi_] = v;
     if (q.mirror && 2 * tx + 1 != q.tiles_x) image[(int64_t)pj * q.W + (q.W - 1 - pi_)] = v;
@@ -205,6 +228,25 @@ __global__ void __launch_bounds__(64) k_cyl(CylParams p, const float* __restrict
 
 __global__ void k_zero_count(unsigned long long* c) {
   if (threadIdx.x == 0) *c = 0ull;
+}
+
+template <int WAVES>
+static void launch_cyl(const CylParams& p, dim3 grid, hipStream_t s, const float* refl, const float* nodes,
+                       const double* pix, const int64_t* offsets, const int32_t* idx, const int32_t* order, float* image,
+                       unsigned long long* counts) {
+  const dim3 block(64 * WAVES);
+  if (counts)
+    hipLaunchKernelGGL((k_cyl<true, FDTBX_LINESHAPE_LAUE, WAVES>), grid, block, 0, s, p, refl, nodes, pix, offsets, idx, image,
+                       counts, order);
+  else if (p.q.lineshape == FDTBX_LINESHAPE_GAUSSIAN)
+    hipLaunchKernelGGL((k_cyl<false, FDTBX_LINESHAPE_GAUSSIAN, WAVES>), grid, block, 0, s, p, refl, nodes, pix, offsets, idx,
+                       image, counts, order);
+  else if (p.q.lineshape == FDTBX_LINESHAPE_HOSEMANN)
+    hipLaunchKernelGGL((k_cyl<false, FDTBX_LINESHAPE_HOSEMANN, WAVES>), grid, block, 0, s, p, refl, nodes, pix, offsets, idx,
+                       image, counts, order);
+  else
+    hipLaunchKernelGGL((k_cyl<false, FDTBX_LINESHAPE_LAUE, WAVES>), grid, block, 0, s, p, refl, nodes, pix, offsets, idx, image,
+                       counts, order);
 }
 
 }  // namespace fdtbx
@@ -231,18 +273,16 @@ extern "C" int fdtbx_profile_cyl(const fdtbx_model* model, const float* refl, co
   if (counts) {
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, cp);
     FDTBX_LAUNCH_CHECK("cylindrical average counter");
-    hipLaunchKernelGGL((k_cyl<true, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, p, refl, nodes, pix, offsets, idx, image, cp,
-                       order);
-  } else if (p.q.lineshape == FDTBX_LINESHAPE_GAUSSIAN) {
-    hipLaunchKernelGGL((k_cyl<false, FDTBX_LINESHAPE_GAUSSIAN>), grid, dim3(64), 0, s, p, refl, nodes, pix, offsets, idx, image,
-                       cp, order);
-  } else if (p.q.lineshape == FDTBX_LINESHAPE_HOSEMANN) {
-    hipLaunchKernelGGL((k_cyl<false, FDTBX_LINESHAPE_HOSEMANN>), grid, dim3(64), 0, s, p, refl, nodes, pix, offsets, idx, image,
-                       cp, order);
-  } else {
-    hipLaunchKernelGGL((k_cyl<false, FDTBX_LINESHAPE_LAUE>), grid, dim3(64), 0, s, p, refl, nodes, pix, offsets, idx, image, cp,
-                       order);
   }
+  int waves = 1;
+  rc = tile_waves(&model->geom, (int64_t)p.q.lcols * p.q.tiles_y, &waves);
+  if (rc) return rc;
+  if (waves == 4)
+    launch_cyl<4>(p, grid, s, refl, nodes, pix, offsets, idx, order, image, cp);
+  else if (waves == 2)
+    launch_cyl<2>(p, grid, s, refl, nodes, pix, offsets, idx, order, image, cp);
+  else
+    launch_cyl<1>(p, grid, s, refl, nodes, pix, offsets, idx, order, image, cp);
   FDTBX_LAUNCH_CHECK("cylindrical average");
   return FDTBX_OK;
 }

@@ -101,9 +101,10 @@ def test_pattern_vs_oracle(name, tw):
     check_pattern(img, ref, f"pattern {name}, tiles {tw}x{64 // tw}")
 
 
-@pytest.mark.parametrize("tw", [4, 16])
-def test_cyl_vs_oracle(tw):
+@pytest.mark.parametrize("tw,waves", [(4, 0), (16, 0), (8, 1), (8, 2)])
+def test_cyl_vs_oracle(tw, waves):
     wl = shaped(W.small(**CASES["ragged"]), tw)
+    wl = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, tile_waves=waves))
     arc = 2e-3
     hkl = _hkl(wl)
     model = B.make_model(wl)
@@ -123,7 +124,7 @@ def test_cyl_vs_oracle(tw):
     img = B.profile_cyl(model, refl, nodes, pix, off, idx, arc, order=order).cpu().numpy()
     P = O.prepare(wl, hkl=hkl, F=F, cull_extinct=False)
     R, Z = O.pixel_rz(wl.geom)
-    check_pattern(img, O.cyl_at(P, R, Z, arc).reshape(img.shape), f"cylindrical average, tiles {tw}x{64 // tw}")
+    check_pattern(img, O.cyl_at(P, R, Z, arc).reshape(img.shape), f"cylindrical average, tiles {tw}x{64 // tw}, waves {waves}")
 
 
 @pytest.mark.parametrize("tw", [4, 32])
