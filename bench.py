@@ -169,6 +169,19 @@ def fold(wl):
     return dataclasses.replace(wl, geom=dataclasses.replace(g, mirror=1))
 
 
+def other_rates(kernel_evals_per_s, prof_ms):
+    """The profile kernel's rate against the other peaks: the transcendental unit at a quarter
+    of the lane rate (3 sines and 1 reciprocal per evaluation), FP32 FLOPs against the 157.3
+    TFLOP/s vector peak (13 FLOPs per evaluation: the FMA counts two, compare and max3 one each,
+    the transcendentals none), and HBM bandwidth from the committed counters."""
+    trans = 4 * kernel_evals_per_s
+    flops = 13 * kernel_evals_per_s
+    tr = measured_traffic()
+    return {"transcendental_lane_ops_per_s": trans, "transcendental_frac_of_quarter_rate": trans / (PEAK_SLOTS / 4),
+            "fp32_flop_per_s": flops, "fp32_flop_frac_of_157.3T": flops / 157.3e12,
+            "hbm_GBps": None if tr is None else tr / (prof_ms * 1e-3) / 1e9}
+
+
 def tune_tiles(wl):
     """Tile shape of workload wl chosen by the tuner (set-up, outside every timed region)."""
     import dataclasses
@@ -375,6 +388,7 @@ def main():
         "profile_kernel_ms": prof_ms,
         "profile_kernel_evals_per_s": n_evals / (prof_ms * 1e-3),
         "tile_tuning": tiles,
+        "rates": other_rates(n_evals / (prof_ms * 1e-3), prof_ms),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak,
                      "traffic": measured_traffic(), "kernel": f"k_profile<false, 0, {waves_main}>", "sources_sha": profile_source_sha(),
                      "slots_per_eval": SLOTS_PER_EVAL},
