@@ -7,7 +7,7 @@
 // profile kernel (one query point per pixel at each reflection's own azimuth, weighted by the
 // Lorentz factor of Eq. lorentz), every point of the ring is visited; no Lorentz factor enters.
 //
-// Mapping: one 64-lane wave per 8x8 pixel tile over the tile's list under the cylindrical
+// Mapping: one to four 64-lane waves per pixel tile (8x8 by default) over the tile's list under the cylindrical
 // culling description (fdtbx_cyl_records).  Per (tile, reflection) each lane bounds the part
 // of its ring that can reach the reflection's support (the ball of radius rho_B about D) and
 // the wave steps a shared index j over the union of those ranges, kJB indices at a time; the

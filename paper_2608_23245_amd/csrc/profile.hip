@@ -3,7 +3,8 @@
 // profile: Eq. I_shape with N -> N_eff, or its Gaussian or Hosemann (Eq. Z) form of the
 // same integral breadth), times the Lorentz factor delta/(R + delta) (Eq. lorentz).
 //
-// Mapping: one 64-lane wave per 8x8 pixel tile, one lane per pixel, pixel sums in
+// Mapping: one to four 64-lane waves per pixel tile (tile_w x 64/tile_w pixels, 8x8 by
+// default; the waves split the tile's list), one lane per pixel, pixel sums in
 // registers.  Reflections of the tile list are uniform across the wave (their
 // records come through scalar loads).  For each (tile, reflection) the wave
 // bounds the node window that the tile's query points can reach, builds the

@@ -62,8 +62,7 @@ __device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1,
   }
 }
 
-// One 8x8 tile t of one model, walked by one 64-lane wave.  qn: LDS queue of 128 entries;
-// bq: LDS scratch of 64 ints for the block test.
+// The walk of one wave's node queue (qn: 128 entries of LDS; see profile_tile below).
 // Every lane walks the first cnt queue entries; the read of entry jj + 1 is issued before
 // entry jj is evaluated (the buffer holds 128 entries, cnt <= 64, so it stays in bounds).
 // The queue is addressed from threadIdx.y (always 0: the launches are one-dimensional), which
