@@ -1,7 +1,8 @@
 """Per-model choice of the pixel-tile shape of the per-tile launches.
 
-Every per-tile kernel runs one 64-lane wave per tile of tile_w x (64 / tile_w) pixels
-(fdtbx_geometry.tile_w).  The shape changes how many (tile, reflection) pairs the culling
+Every per-tile kernel runs one to four 64-lane waves per tile of tile_w x (64 / tile_w)
+pixels (fdtbx_geometry.tile_w; the waves per tile follow tile_waves, which the tuner leaves
+as the model has it).  The shape changes how many (tile, reflection) pairs the culling
 lists hold, how large each pair's node window and alpha box are, and how many of a queued
 node's 64 lanes fall inside their supports; which shape is fastest depends on the detector
 geometry and on the size of the reflections' supports in pixels.  The image does not depend
