@@ -183,3 +183,13 @@ def test_tile_waves_values(lib):
         g.tile_waves = w
         assert lib.fdtbx_tile_grid(ctypes.byref(g), ctypes.byref(tx), ctypes.byref(ty)) == -1
         assert "tile_waves" in lib.fdtbx_error_string(-1).decode()
+
+
+def test_launch_waves_explicit(lib):
+    """An explicit tile_waves is returned as it is (no device query)."""
+    from paper_2608_23245_amd import binding as B
+    w = ctypes.c_int32(0)
+    for tw in (1, 2, 4):
+        g = B.Geometry(1.0, 100.0, 0.1, 48, 23, 24.0, 11.5, 0.0, 8, 1, tw)
+        assert lib.fdtbx_launch_waves(ctypes.byref(g), ctypes.byref(w)) == 0 and w.value == tw
+    assert lib.fdtbx_launch_waves(None, ctypes.byref(w)) == -1
