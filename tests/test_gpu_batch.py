@@ -132,8 +132,20 @@ def test_batch_set_globals_in_place():
         assert r <= 1e-5
 
 
-def test_graph_replay_matches_eager():
+def _folded_16x4(wl):
+    """The same model in 16 x 4 tiles with the mirror fold (a centred beam and a width of a
+    multiple of 16 are made up for it)."""
+    import dataclasses
+    w = -(-wl.geom.width // 16) * 16
+    g = dataclasses.replace(wl.geom, width=w, center_x=w / 2.0, tile_w=16, mirror=1)
+    return dataclasses.replace(wl, geom=g)
+
+
+@pytest.mark.parametrize("variant", ["default", "folded_16x4"])
+def test_graph_replay_matches_eager(variant):
     wls = small_batch()
+    if variant == "folded_16x4":
+        wls = [_folded_16x4(w) for w in wls]
     be = BatchEngine(wls)
     tgt_eng = BatchEngine(wls)
     glob = tgt_eng.globals()
