@@ -80,7 +80,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
-    ap.add_argument("--cpu-pixels", type=int, default=256)
+    ap.add_argument("--cpu-pixels", type=int, default=1024)
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-model leg")
     ap.add_argument("--no-tilt", action="store_true", help="skip the tilted-fibre forward leg")
