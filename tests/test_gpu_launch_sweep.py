@@ -1,0 +1,76 @@
+"""A seeded sweep of launch configurations through the C ABI: random small workloads (detector
+sizes, beam centres, cells, tilts, lineshapes, node grids) crossed with random tile shapes,
+waves per tile and, where the beam is centred, the mirror fold.  Every pattern is compared
+with the oracle at the pattern tolerances, and every folded pattern with its unfolded twin
+(same waves per tile) bit for bit."""
+import dataclasses
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import oracle as O
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_2608_23245_amd import Pipeline  # noqa: E402
+
+DEG = math.pi / 180
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def random_case(seed):
+    rng = np.random.default_rng(1000 + seed)
+    tw = int(rng.choice([2, 4, 8, 16, 32]))
+    waves = int(rng.choice([0, 1, 2, 4]))
+    fold = bool(rng.integers(0, 2))
+    width = int(rng.integers(9, 50))
+    if fold:
+        width = max(tw, (width // tw) * tw)
+    height = int(rng.integers(7, 40))
+    cx = width / 2.0 if fold else float(rng.uniform(-5.0, width + 5.0))
+    cy = float(rng.uniform(0.2, 0.8)) * height
+    ls = int(rng.integers(0, 3))
+    st, gt = [(3 * DEG, 0.0), (0.0, 2 * DEG), (2 * DEG, 1.5 * DEG)][int(rng.integers(0, 3))]
+    edges = rng.uniform(8.0, 13.0, 3)
+    angles = rng.uniform(85.0, 100.0, 3) * DEG
+    wl = W.small(seed, n_atoms=int(rng.integers(5, 30)), width=width, height=height, center=(cx, cy),
+                 cell=W.Cell(*edges, *angles), sigma_theta=st, gamma_theta=gt,
+                 g=tuple(float(v) for v in rng.uniform(0.0, 0.04, 3)), n_nodes=int(rng.integers(6, 20)),
+                 d_min=float(rng.uniform(4.0, 6.0)), tilt=float(rng.uniform(-30.0, 30.0)) * DEG, lineshape=ls)
+    geom = dataclasses.replace(wl.geom, tile_w=tw, tile_waves=waves)
+    return dataclasses.replace(wl, geom=geom), fold
+
+
+@pytest.mark.parametrize("seed", range(40))
+def test_random_launch_vs_oracle(seed):
+    wl, fold = random_case(seed)
+    g = wl.geom
+    say(f"seed {seed}: {g.width}x{g.height}, centre ({g.center_x:.1f}, {g.center_y:.1f}), tile {g.tile_w} wide, "
+        f"waves {g.tile_waves}, fold {fold}, tilt {g.tilt / DEG:.0f} deg, lineshape {wl.dis.lineshape}")
+    pipe = Pipeline(wl)
+    if pipe.n_hkl == 0:
+        pytest.skip("empty reflection list")
+    img = pipe.pattern()
+    ref = O.pattern(wl, O.prepare(wl, hkl=pipe.hkl.cpu().numpy()))
+    got = img.cpu().numpy().astype(np.float64)
+    assert ref.max() > 0
+    r = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    big = ref > 1e-3 * ref.max()
+    px = float(np.max(np.abs(got[big] - ref[big]) / ref[big]))
+    say(f"  rel-L2 {r:.2e}, per-pixel {px:.2e}")
+    assert r <= 1e-4 and px <= 1e-3
+    if fold:
+        folded = Pipeline(dataclasses.replace(wl, geom=dataclasses.replace(g, mirror=1))).pattern()
+        torch.cuda.synchronize()
+        assert torch.equal(folded, img)
