@@ -86,8 +86,10 @@ typedef struct fdtbx_geometry {
  * same value for a pixel and its mirror.  mirror = 1 (which requires both conditions) makes
  * fdtbx_profile, fdtbx_profile_cyl and the batched forward run the left ceil(tiles_x / 2) tile
  * columns only and write each value to the pixel and its mirror (the image is bit-identical to
- * the unfolded one with the same waves per tile, fdtbx_launch_waves), and makes the adjoints take grad(i, j) + grad(width-1-i, j) as the
- * weight of the computed pixel.  fdtbx_pixel_map and fdtbx_cull still produce every tile. */
+ * the unfolded one with the same waves per tile, fdtbx_launch_waves), and makes the adjoints
+ * take grad(i, j) + grad(width-1-i, j) as the weight of the computed pixel.  fdtbx_pixel_map
+ * still produces every tile; fdtbx_cull lists the launched columns only (the right columns'
+ * lists are empty). */
 
 /* Orientational and lattice disorder (section "Angular peak shapes", tutorial
  * Table "paracrystal").  sigma_theta: Gaussian standard deviation; gamma_theta:
@@ -262,7 +264,8 @@ int fdtbx_reflection_prep(const fdtbx_model* model, const int32_t* hkl, int64_t 
  *        n_tiles = tiles_x * tiles_y */
 int fdtbx_pixel_map(const fdtbx_geometry* geom, double* pix, double* tile, void* stream);
 
-/* Per-tile culling lists: reflection r is listed for tile t iff it is kept and
+/* Per-tile culling lists (under the mirror fold, of the launched tile columns only; the other
+ * columns' lists are empty): reflection r is listed for tile t iff it is kept and
  *   R_lo(r) <= R_hi(t), R_lo(t) <= R_hi(r), Z_lo(r) <= Z_hi(t), Z_lo(t) <= Z_hi(r),
  *   P2_lo(r) <= P2_hi(t), P2_lo(t) <= P2_hi(r), and (if rho1 >= 0)
  *   max_corner(n1 . p) >= -rho1 and max_corner(n2 . p) >= -rho2 over the tile box corners,

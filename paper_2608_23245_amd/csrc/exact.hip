@@ -492,8 +492,10 @@ __global__ void __launch_bounds__(256) k_b_prep(const fdtbx_batch_entry* __restr
 // candidates and writes the exact per-tile lists in ascending order.
 static constexpr int kSB = 4;
 
+// lcols: tile columns that get lists (all, or the left half under the mirror fold, whose
+// right columns keep empty lists: no launch reads them).
 struct CullParams {
-  int32_t tiles_x, tiles_y, sb_x, sb_y;
+  int32_t tiles_x, tiles_y, sb_x, sb_y, lcols;
   int64_t n_hkl, n_words;
 };
 
@@ -543,6 +545,7 @@ __global__ void __launch_bounds__(64) k_sb_mask(CullParams q, const double* __re
   for (int k = 0; k < 13; ++k) c[k] = have ? cull[FDTBX_CULL_DOUBLES * r + k] : 0.0;
   const int nsb = q.sb_x * q.sb_y;
   for (int s = 0; s < nsb; ++s) {
+    if ((s % q.sb_x) * kSB >= q.lcols) continue;  // no tile of this superblock gets a list
     double box[6];
     for (int k = 0; k < 6; ++k) box[k] = sb[8 * (int64_t)s + k];
     bool hit = have && cull_test(box, c);
@@ -563,6 +566,10 @@ __global__ void __launch_bounds__(64 * kSB * kSB) k_tile_lists(CullParams q, con
   const int tx = sx * kSB + (wv % kSB), ty = sy * kSB + (wv / kSB);
   if (tx >= q.tiles_x || ty >= q.tiles_y) return;  // whole wave leaves; no block barrier below
   const int64_t t = (int64_t)ty * q.tiles_x + tx;
+  if (tx >= q.lcols) {  // a column the mirror fold does not launch: empty list
+    if (!MODE && lane == 0) counts[t] = 0;
+    return;
+  }
   double box[6];
   for (int k = 0; k < 6; ++k) box[k] = tile[8 * t + k];
   const uint64_t* mrow = mask + (int64_t)s * q.n_words;
@@ -683,6 +690,7 @@ extern "C" int fdtbx_cyl_records(const fdtbx_model* model, const int32_t* hkl, i
 static void cull_params(const fdtbx_geometry* g, int64_t n_hkl, CullParams* q) {
   q->tiles_x = tiles_x_of(g);
   q->tiles_y = tiles_y_of(g);
+  q->lcols = lcols_of(g);
   q->sb_x = (int32_t)ceil_div(q->tiles_x, kSB);
   q->sb_y = (int32_t)ceil_div(q->tiles_y, kSB);
   q->n_hkl = n_hkl;

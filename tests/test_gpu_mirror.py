@@ -152,3 +152,27 @@ def test_folded_batch_matches_unfolded_single_runs():
         r = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         say(f"  model {m} (mirror {wl.geom.mirror}): rel-L2 vs unfolded single run {r:.2e}")
         assert r <= 1e-5
+
+
+def test_folded_culling_lists_cover_the_launched_columns():
+    """Under the fold the left tile columns get the unfolded lists and the right ones none."""
+    wl = _small("odd_columns")
+    lists = []
+    for mirror in (0, 1):
+        w = folded(wl, mirror)
+        model = B.make_model(w)
+        hkl = O.enumerate_hkl(w.cell, w.quad.d_min, w.quad.d_max)
+        h = torch.from_numpy(np.ascontiguousarray(hkl)).cuda()
+        _, cull = B.reflection_prep(model, h, torch.ones(h.shape[0], dtype=torch.float32, device="cuda"))
+        pix, tile = B.pixel_map(model.geom)
+        off, idx = B.cull(model.geom, tile, cull)
+        lists.append((off.cpu().numpy(), idx.cpu().numpy()))
+    (o0, i0), (o1, i1) = lists
+    tx, ty = B.tile_grid(B.make_model(wl).geom)
+    lcols = (tx + 1) // 2
+    for t in range(tx * ty):
+        got = i1[o1[t]:o1[t + 1]]
+        if t % tx < lcols:
+            assert np.array_equal(got, i0[o0[t]:o0[t + 1]]), t
+        else:
+            assert got.size == 0, t
