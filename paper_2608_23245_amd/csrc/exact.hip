@@ -555,11 +555,17 @@ __global__ void __launch_bounds__(64) k_sb_mask(CullParams q, const double* __re
 }
 
 // One wave per tile, kSB*kSB waves per block (one superblock).  mode 0: count; mode 1: fill.
+// The superblock's candidate mask is sparse, so each wave first compacts the set bits of
+// kWordsPer mask words into an LDS list of reflection indices (in ascending order: words in
+// order, bits in order within a word) and then tests 64 listed candidates per pass.
+static constexpr int kWordsPer = 16;
+
 template <int MODE>
 __global__ void __launch_bounds__(64 * kSB * kSB) k_tile_lists(CullParams q, const double* __restrict__ tile,
                                                                const uint64_t* __restrict__ mask,
                                                                const double* __restrict__ cull, int64_t* __restrict__ counts,
                                                                int32_t* __restrict__ idx) {
+  __shared__ int32_t cand_all[kSB * kSB][kWordsPer * 64];
   const int s = blockIdx.x;
   const int sx = s % q.sb_x, sy = s / q.sb_x;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -570,36 +576,50 @@ __global__ void __launch_bounds__(64 * kSB * kSB) k_tile_lists(CullParams q, con
     if (!MODE && lane == 0) counts[t] = 0;
     return;
   }
+  int32_t* const cand = cand_all[wv];
   double box[6];
   for (int k = 0; k < 6; ++k) box[k] = tile[8 * t + k];
   const uint64_t* mrow = mask + (int64_t)s * q.n_words;
-  int64_t pos = MODE ? counts[t] : 0;
+  int64_t opos = MODE ? counts[t] : 0;
   int64_t cnt = 0;
-  for (int64_t w0 = 0; w0 < q.n_words; w0 += 64) {
-    uint64_t myword = (w0 + lane < q.n_words) ? mrow[w0 + lane] : 0ull;
-    uint64_t nz = __ballot(myword != 0ull);
-    while (nz) {
-      int src = __builtin_ctzll(nz);
-      nz &= nz - 1;
-      uint64_t word = __shfl(myword, src, 64);
-      int64_t r = (w0 + src) * 64 + lane;
+  for (int64_t w0 = 0; w0 < q.n_words; w0 += kWordsPer) {
+    const uint64_t myword = (lane < kWordsPer && w0 + lane < q.n_words) ? mrow[w0 + lane] : 0ull;
+    const int c = __popcll(myword);
+    int pre = c;  // inclusive prefix of the set-bit counts over the word lanes
+    for (int o = 1; o < kWordsPer; o <<= 1) {
+      const int v = __shfl_up(pre, o, 64);
+      if (lane >= o) pre += v;
+    }
+    const int total = __shfl(pre, kWordsPer - 1, 64);
+    if (total == 0) continue;  // uniform
+    int pos = pre - c;
+    uint64_t m = myword;
+    while (m) {
+      cand[pos++] = (int32_t)((w0 + lane) * 64 + __builtin_ctzll(m));
+      m &= m - 1;
+    }
+    wave_sync();
+    for (int k0 = 0; k0 < total; k0 += 64) {
       bool hit = false;
-      if ((word >> lane) & 1ull) {
-        double c[13];
-        for (int k = 0; k < 13; ++k) c[k] = cull[FDTBX_CULL_DOUBLES * r + k];
-        hit = cull_test(box, c);
+      int32_t r = 0;
+      if (k0 + lane < total) {
+        r = cand[k0 + lane];
+        double cr[13];
+        for (int k = 0; k < 13; ++k) cr[k] = cull[FDTBX_CULL_DOUBLES * (int64_t)r + k];
+        hit = cull_test(box, cr);
       }
-      uint64_t hm = __ballot(hit);
+      const uint64_t hm = __ballot(hit);
       if (MODE) {
         if (hit) {
-          uint64_t below = lane ? (hm & ((~0ull) >> (64 - lane))) : 0ull;
-          idx[pos + __popcll(below)] = (int32_t)r;
+          const uint64_t below = lane ? (hm & ((~0ull) >> (64 - lane))) : 0ull;
+          idx[opos + __popcll(below)] = r;
         }
-        pos += __popcll(hm);
+        opos += __popcll(hm);
       } else {
         cnt += __popcll(hm);
       }
     }
+    wave_sync();  // the list is rewritten by the next words
   }
   if (!MODE && lane == 0) counts[t] = cnt;
 }
