@@ -84,6 +84,7 @@ def parse():
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-model leg")
     ap.add_argument("--no-tilt", action="store_true", help="skip the tilted-fibre forward leg")
+    ap.add_argument("--no-large", action="store_true", help="skip the large-workload forward leg")
     ap.add_argument("--no-lineshapes", action="store_true", help="skip the Gaussian/Hosemann lineshape legs")
     ap.add_argument("--no-splat", action="store_true", help="skip the forward-splat leg")
     ap.add_argument("--no-cyl", action="store_true", help="skip the exact cylindrical-average leg")
@@ -206,6 +207,24 @@ def tune_tiles(wl):
             "tuned": True, "tuning_s": time.perf_counter() - t0}
     log(f"tile tuner: {info['profile_ms']} -> {info['tile']}")
     return dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, tile_w=tw)), info
+
+
+def bench_large(args):
+    """The large workload's forward step (2048^2 detector, 96 x 96 nodes, about 2.9e5
+    reflections after the extinction cull), folded, 8 x 8 tiles, the library's waves per
+    tile."""
+    import workloads as W
+    from paper_2608_23245_amd import binding as B
+    wl = fold(W.config2())
+    ms_step, prof_ms, n_evals, state = forward_leg(wl, 2, 1)
+    ach = n_evals * SLOTS_PER_EVAL / (prof_ms * 1e-3)
+    out = {"workload": wl.name, "n_hkl": int(state["hkl"].shape[0]), "culled_pairs": int(state["idx"].shape[0]),
+           "useful_evals_per_step": int(n_evals), "ms_per_pattern": ms_step, "profile_kernel_ms": prof_ms,
+           "evals_per_s": n_evals / (ms_step * 1e-3), "profile_kernel_evals_per_s": n_evals / (prof_ms * 1e-3),
+           "issue_frac": ach / PEAK_SLOTS, "mirror_fold": bool(wl.geom.mirror),
+           "waves_per_tile": B.launch_waves(B.make_model(wl).geom), "pass": "forward"}
+    del state
+    return out
 
 
 def bench_tilted(args):
@@ -412,6 +431,10 @@ def main():
     if not args.no_tilt:
         log("forward, tilted fibre")
         out["tilted"] = bench_tilted(args)
+        torch.cuda.empty_cache()
+    if not args.no_large:
+        log("forward, large workload")
+        out["large"] = bench_large(args)
         torch.cuda.empty_cache()
     if not args.no_lineshapes:
         log("forward, Gaussian and Hosemann lineshapes")

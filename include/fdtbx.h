@@ -76,8 +76,8 @@ typedef struct fdtbx_geometry {
                                  ... of 64 pairs of the tile's list, or for the cylindrical average
                                  of 8 ring indices of each pair; the forward's first wave adds the
                                  others' pixel sums in wave order); 0: the library's choice, 4 when the
-                                 launched tiles fit in one round of one-wave workgroups (32 per
-                                 compute unit), 2 up to four rounds, else 1 */
+                                 launched tiles fit in eight rounds of one-wave workgroups (32 per
+                                 compute unit), else 2 */
 } fdtbx_geometry;
 /* Mirror fold.  With center_x = width / 2 exactly, pixel (i, j) and its mirror (width-1-i, j)
  * have y of opposite sign and equal z, so their (R, Z) are bit-identical (R depends on y only
@@ -285,7 +285,7 @@ int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_t n_hkl, co
  * padding.  Workgroups are dealt to the 8 XCDs round-robin; tiles are grouped into
  * superblocks of 8 x 8 tiles (single tiles when the detector has fewer than 64
  * superblocks) that run on one XCD in consecutive dispatch slots.  When the launch holds
- * fewer than 8 rounds of workgroups per slot (16 per compute unit of the current device),
+ * at most 8 rounds of workgroups per slot (16 per compute unit of the current device),
  * the superblocks run by decreasing length of their longest list and the tiles of a
  * superblock by decreasing list length (the long tiles start first); otherwise in index
  * order.  Performance only: every tile is listed once, and the images do not depend on

@@ -133,10 +133,10 @@ extern "C" int fdtbx_last_hip_error(void) { return g_hip; }
 
 // Waves per tile of a profile launch over n_tiles tiles: the geometry's tile_waves, or the
 // library's choice.
-// The library's choice: a launch whose tiles fit in one round of one-wave workgroups (32 per
-// compute unit) ends with its longest tiles, so 4 waves share each tile; up to four rounds,
-// 2; beyond that the rounds balance themselves and one wave per tile keeps the most lanes
-// busy per workgroup.
+// The library's choice: a launch of a few rounds of one-wave workgroups (32 per compute unit)
+// ends with its longest tiles, so 4 waves share each tile up to eight rounds (measured best or
+// equal from one round, the folded medium workload, to eight, the unfolded large one); beyond
+// that, 2.
 int fdtbx::tile_waves(const fdtbx_geometry* g, int64_t n_tiles, int* waves) {
   if (g->tile_waves) {
     *waves = g->tile_waves;
@@ -146,7 +146,7 @@ int fdtbx::tile_waves(const fdtbx_geometry* g, int64_t n_tiles, int* waves) {
   FDTBX_HIP(hipGetDevice(&dev));
   FDTBX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   const int64_t round = (int64_t)cus * 32;
-  *waves = n_tiles <= round ? 4 : n_tiles <= 4 * round ? 2 : 1;
+  *waves = n_tiles <= 8 * round ? 4 : 2;
   return FDTBX_OK;
 }
 

@@ -121,7 +121,7 @@ extern "C" int fdtbx_tile_order(const fdtbx_geometry* geom, const int64_t* offse
   FDTBX_HIP(hipGetDevice(&dev));
   FDTBX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
   const int64_t slots = (int64_t)cus * 16;
-  const bool work = (int64_t)p.tiles_x * p.tiles_y < 8 * slots;
+  const bool work = (int64_t)p.tiles_x * p.tiles_y <= 8 * slots;
   char* w = (char*)ws;
   int64_t* key = (int64_t*)w;
   w += align_up((size_t)p.nsb * sizeof(int64_t), 256);

@@ -261,12 +261,12 @@ def test_tile_waves_adjoint_vs_oracle(waves):
 
 
 def test_library_choice_of_waves():
-    """tile_waves = 0: 4 waves when the launched tiles fit in one round of one-wave workgroups
-    (32 per compute unit), 2 up to four rounds, else 1."""
+    """tile_waves = 0: 4 waves when the launched tiles fit in eight rounds of one-wave
+    workgroups (32 per compute unit), else 2."""
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    for width, height, mirror in [(64, 64, 0), (1024, 1024, 0), (1024, 1024, 1), (2048, 2048, 0)]:
+    for width, height, mirror in [(64, 64, 0), (1024, 1024, 0), (2048, 2048, 1), (2048, 2048, 0), (4096, 4096, 0)]:
         g = B.Geometry(1.0, 100.0, 0.1, width, height, width / 2.0, height / 2.0, 0.0, 8, mirror, 0)
         tx, ty = B.tile_grid(g)
         n = ((tx + 1) // 2 if mirror else tx) * ty
-        want = 4 if n <= 32 * cus else 2 if n <= 128 * cus else 1
+        want = 4 if n <= 8 * 32 * cus else 2
         assert B.launch_waves(g) == want, (width, mirror, n)
