@@ -73,6 +73,14 @@ def test_empty_resolution_shell():
     _zero_everything(wl)
 
 
+def test_empty_resolution_shell_folded_16x4():
+    """The same with the mirror fold and 16 x 4 tiles of 4 waves."""
+    wl = W.small(61, width=32, height=11, d_min=14.0, center=(16.0, 5.5))
+    wl = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, tile_w=16, mirror=1, tile_waves=4))
+    say("empty shell, folded")
+    _zero_everything(wl)
+
+
 def test_every_reflection_extinct():
     """Disorder so strong that the extinction cull removes every reflection of a
     high-resolution shell (2.5 to 3 A)."""
