@@ -554,74 +554,119 @@ __global__ void __launch_bounds__(64) k_sb_mask(CullParams q, const double* __re
   }
 }
 
-// One wave per tile, kSB*kSB waves per block (one superblock).  mode 0: count; mode 1: fill.
-// The superblock's candidate mask is sparse, so each wave first compacts the set bits of
-// kWordsPer mask words into an LDS list of reflection indices (in ascending order: words in
-// order, bits in order within a word) and then tests 64 listed candidates per pass.
+// One block per superblock of kSB x kSB tiles, mode 0: count; mode 1: fill.  The block's
+// waves split the superblock's candidate mask into kTB contiguous word ranges.  Each wave
+// compacts the set bits of kWordsPer words at a time into an LDS list of reflection indices
+// (ascending: words in order, bits in order within a word), reads each listed candidate's
+// record once and tests it against every tile box of the superblock.  Mode 0 stores the hits
+// of every (wave, tile) in part and, after a block barrier, each tile's total in counts; mode
+// 1 (counts holding the exclusive offsets) writes the hits of wave w for tile t at t's offset
+// plus the hits of the waves before w, so every list comes out ascending.  Tiles off the
+// detector or in a column the mirror fold does not launch get no list (NaN boxes fail every
+// test; their count is 0).
 static constexpr int kWordsPer = 16;
+static constexpr int kTB = kSB * kSB;  // tiles and waves per block
 
 template <int MODE>
-__global__ void __launch_bounds__(64 * kSB * kSB) k_tile_lists(CullParams q, const double* __restrict__ tile,
-                                                               const uint64_t* __restrict__ mask,
-                                                               const double* __restrict__ cull, int64_t* __restrict__ counts,
-                                                               int32_t* __restrict__ idx) {
-  __shared__ int32_t cand_all[kSB * kSB][kWordsPer * 64];
+__global__ void __launch_bounds__(64 * kTB) k_tile_lists(CullParams q, const double* __restrict__ tile,
+                                                         const uint64_t* __restrict__ mask, const double* __restrict__ cull,
+                                                         int64_t* __restrict__ counts, int32_t* __restrict__ part,
+                                                         int32_t* __restrict__ idx) {
+  __shared__ int32_t cand_all[kTB][kWordsPer * 64];
+  __shared__ double boxes[kTB][6];
+  __shared__ int32_t hits[kTB][kTB];  // [wave][tile]
   const int s = blockIdx.x;
   const int sx = s % q.sb_x, sy = s / q.sb_x;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int tx = sx * kSB + (wv % kSB), ty = sy * kSB + (wv / kSB);
-  if (tx >= q.tiles_x || ty >= q.tiles_y) return;  // whole wave leaves; no block barrier below
-  const int64_t t = (int64_t)ty * q.tiles_x + tx;
-  if (tx >= q.lcols) {  // a column the mirror fold does not launch: empty list
-    if (!MODE && lane == 0) counts[t] = 0;
-    return;
+  if (threadIdx.x < kTB * 6) {
+    const int u = threadIdx.x / 6, c = threadIdx.x % 6;
+    const int tx = sx * kSB + u % kSB, ty = sy * kSB + u / kSB;
+    boxes[u][c] = (tx < q.lcols && ty < q.tiles_y) ? tile[8 * ((int64_t)ty * q.tiles_x + tx) + c] : (double)NAN;
   }
-  int32_t* const cand = cand_all[wv];
-  double box[6];
-  for (int k = 0; k < 6; ++k) box[k] = tile[8 * t + k];
-  const uint64_t* mrow = mask + (int64_t)s * q.n_words;
-  int64_t opos = MODE ? counts[t] : 0;
-  int64_t cnt = 0;
-  for (int64_t w0 = 0; w0 < q.n_words; w0 += kWordsPer) {
-    const uint64_t myword = (lane < kWordsPer && w0 + lane < q.n_words) ? mrow[w0 + lane] : 0ull;
-    const int c = __popcll(myword);
-    int pre = c;  // inclusive prefix of the set-bit counts over the word lanes
-    for (int o = 1; o < kWordsPer; o <<= 1) {
-      const int v = __shfl_up(pre, o, 64);
-      if (lane >= o) pre += v;
+  __syncthreads();
+  int cnt[kTB];
+  int64_t pos[kTB];
+#pragma unroll
+  for (int u = 0; u < kTB; ++u) {
+    cnt[u] = 0;
+    pos[u] = 0;
+    if (MODE) {
+      const int tx = sx * kSB + u % kSB, ty = sy * kSB + u / kSB;
+      if (tx < q.lcols && ty < q.tiles_y) {
+        pos[u] = counts[(int64_t)ty * q.tiles_x + tx];
+        for (int w = 0; w < wv; ++w) pos[u] += part[((int64_t)s * kTB + w) * kTB + u];
+      }
     }
-    const int total = __shfl(pre, kWordsPer - 1, 64);
-    if (total == 0) continue;  // uniform
-    int pos = pre - c;
-    uint64_t m = myword;
-    while (m) {
-      cand[pos++] = (int32_t)((w0 + lane) * 64 + __builtin_ctzll(m));
-      m &= m - 1;
-    }
-    wave_sync();
-    for (int k0 = 0; k0 < total; k0 += 64) {
-      bool hit = false;
-      int32_t r = 0;
-      if (k0 + lane < total) {
-        r = cand[k0 + lane];
+  }
+  // superblocks wholly right of the launched columns have no mask row
+  if (sx * kSB < q.lcols) {
+    const int64_t per = (q.n_words + kTB - 1) / kTB;
+    const int64_t wlo = per * wv, whi = wlo + per < q.n_words ? wlo + per : q.n_words;
+    const uint64_t* mrow = mask + (int64_t)s * q.n_words;
+    int32_t* const cand = cand_all[wv];
+    for (int64_t w0 = wlo; w0 < whi; w0 += kWordsPer) {
+      const uint64_t myword = (lane < kWordsPer && w0 + lane < whi) ? mrow[w0 + lane] : 0ull;
+      const int c = __popcll(myword);
+      int pre = c;  // inclusive prefix of the set-bit counts over the word lanes
+      for (int o = 1; o < kWordsPer; o <<= 1) {
+        const int v = __shfl_up(pre, o, 64);
+        if (lane >= o) pre += v;
+      }
+      const int total = __shfl(pre, kWordsPer - 1, 64);
+      if (total == 0) continue;  // uniform
+      int at = pre - c;
+      uint64_t m = myword;
+      while (m) {
+        cand[at++] = (int32_t)((w0 + lane) * 64 + __builtin_ctzll(m));
+        m &= m - 1;
+      }
+      wave_sync();
+      for (int k0 = 0; k0 < total; k0 += 64) {
+        const bool have = k0 + lane < total;
+        int32_t r = 0;
         double cr[13];
-        for (int k = 0; k < 13; ++k) cr[k] = cull[FDTBX_CULL_DOUBLES * (int64_t)r + k];
-        hit = cull_test(box, cr);
-      }
-      const uint64_t hm = __ballot(hit);
-      if (MODE) {
-        if (hit) {
-          const uint64_t below = lane ? (hm & ((~0ull) >> (64 - lane))) : 0ull;
-          idx[opos + __popcll(below)] = r;
+        for (int k = 0; k < 13; ++k) cr[k] = 0.0;
+        if (have) {
+          r = cand[k0 + lane];
+          for (int k = 0; k < 13; ++k) cr[k] = cull[FDTBX_CULL_DOUBLES * (int64_t)r + k];
         }
-        opos += __popcll(hm);
-      } else {
-        cnt += __popcll(hm);
+#pragma unroll
+        for (int u = 0; u < kTB; ++u) {
+          const bool hit = have && cull_test(boxes[u], cr);
+          const uint64_t hm = __ballot(hit);
+          if (MODE) {
+            if (hit) {
+              const uint64_t below = lane ? (hm & ((~0ull) >> (64 - lane))) : 0ull;
+              idx[pos[u] + __popcll(below)] = r;
+            }
+            pos[u] += __popcll(hm);
+          } else {
+            cnt[u] += __popcll(hm);
+          }
+        }
+      }
+      wave_sync();  // the list is rewritten by the next words
+    }
+  }
+  if (!MODE) {
+    if (lane == 0) {
+#pragma unroll
+      for (int u = 0; u < kTB; ++u) {
+        hits[wv][u] = cnt[u];
+        part[((int64_t)s * kTB + wv) * kTB + u] = cnt[u];
       }
     }
-    wave_sync();  // the list is rewritten by the next words
+    __syncthreads();
+    if (threadIdx.x < kTB) {
+      const int u = threadIdx.x;
+      const int tx = sx * kSB + u % kSB, ty = sy * kSB + u / kSB;
+      if (tx < q.tiles_x && ty < q.tiles_y) {
+        int64_t sum = 0;
+        for (int w = 0; w < kTB; ++w) sum += hits[w][u];
+        counts[(int64_t)ty * q.tiles_x + tx] = sum;  // 0 for columns without lists
+      }
+    }
   }
-  if (!MODE && lane == 0) counts[t] = cnt;
 }
 
 }  // namespace fdtbx
@@ -726,6 +771,7 @@ extern "C" size_t fdtbx_cull_workspace(const fdtbx_geometry* geom, int64_t n_hkl
   size_t b = align_up((size_t)nsb * 8 * sizeof(double), 256);
   b += align_up((size_t)nsb * q.n_words * sizeof(uint64_t), 256);
   b += align_up(sizeof(int64_t) * 2, 256);
+  b += align_up((size_t)nsb * kTB * kTB * sizeof(int32_t), 256);
   return b;
 }
 
@@ -754,12 +800,14 @@ extern "C" int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_
   uint64_t* mask = (uint64_t*)w;
   w += align_up((size_t)nsb * q.n_words * sizeof(uint64_t), 256);
   int64_t* total = (int64_t*)w;
+  w += align_up(sizeof(int64_t) * 2, 256);
+  int32_t* part = (int32_t*)w;
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_sb_boxes, dim3((unsigned)ceil_div(nsb, 256)), dim3(256), 0, s, q, tile, sb);
   FDTBX_LAUNCH_CHECK("cull superblocks");
   hipLaunchKernelGGL(k_sb_mask, dim3((unsigned)q.n_words), dim3(64), 0, s, q, sb, cull, mask);
   FDTBX_LAUNCH_CHECK("cull masks");
-  hipLaunchKernelGGL(k_tile_lists<0>, dim3((unsigned)nsb), dim3(64 * kSB * kSB), 0, s, q, tile, mask, cull, offsets,
+  hipLaunchKernelGGL(k_tile_lists<0>, dim3((unsigned)nsb), dim3(64 * kTB), 0, s, q, tile, mask, cull, offsets, part,
                      (int32_t*)nullptr);
   FDTBX_LAUNCH_CHECK("cull count");
   hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, offsets, n_tiles, total);
@@ -771,7 +819,7 @@ extern "C" int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_
   FDTBX_HIP(hipMemcpyAsync(offsets + n_tiles, total, sizeof(int64_t), hipMemcpyDeviceToDevice, s));
   if (h_total > cap || (h_total > 0 && !idx)) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "culling pair capacity too small");
   if (h_total > 0) {
-    hipLaunchKernelGGL(k_tile_lists<1>, dim3((unsigned)nsb), dim3(64 * kSB * kSB), 0, s, q, tile, mask, cull, offsets,
+    hipLaunchKernelGGL(k_tile_lists<1>, dim3((unsigned)nsb), dim3(64 * kTB), 0, s, q, tile, mask, cull, offsets, part,
                        idx);
     FDTBX_LAUNCH_CHECK("cull fill");
   }
