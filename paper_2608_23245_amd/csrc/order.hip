@@ -27,24 +27,26 @@ __device__ static inline int64_t tile_len(const OrderParams& p, const int64_t* o
   return offsets[t + 1] - offsets[t];
 }
 
-// Per superblock: its key (longest list) and the rank order of its tiles.
-__global__ void __launch_bounds__(256) k_order_keys(OrderParams p, const int64_t* __restrict__ offsets,
-                                                    int64_t* __restrict__ key, uint8_t* __restrict__ inner) {
-  const int64_t sb = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (sb >= p.nsb) return;
+// Per superblock (one wave; lane i holds tile i of the S^2 <= 64): its key (longest list) and
+// the rank order of its tiles, each lane counting the tiles that go before its own.
+__global__ void __launch_bounds__(64) k_order_keys(OrderParams p, const int64_t* __restrict__ offsets,
+                                                   int64_t* __restrict__ key, uint8_t* __restrict__ inner) {
+  const int64_t sb = blockIdx.x;
+  const int i = threadIdx.x;
   const int n = p.S * p.S;
-  int64_t best = -1;
-  for (int i = 0; i < n; ++i) {
-    const int64_t ci = tile_len(p, offsets, sb, i);
-    best = ci > best ? ci : best;
-    int rank = 0;
-    for (int k = 0; k < n; ++k) {
-      const int64_t ck = tile_len(p, offsets, sb, k);
-      rank += (ck > ci || (ck == ci && k < i)) ? 1 : 0;
-    }
-    inner[sb * n + rank] = (uint8_t)i;
+  const int64_t ci = i < n ? tile_len(p, offsets, sb, i) : -1;
+  int rank = 0;
+  for (int k = 0; k < n; ++k) {
+    const int64_t ck = __shfl(ci, k, 64);
+    rank += (ck > ci || (ck == ci && k < i)) ? 1 : 0;
   }
-  key[sb] = best;
+  if (i < n) inner[sb * n + rank] = (uint8_t)i;
+  int64_t best = ci;
+  for (int o = 32; o >= 1; o >>= 1) {
+    const int64_t other = __shfl_xor(best, o, 64);
+    best = other > best ? other : best;
+  }
+  if (i == 0) key[sb] = best;
 }
 
 // Superblocks by decreasing key (ties in index order).
@@ -131,7 +133,7 @@ extern "C" int fdtbx_tile_order(const fdtbx_geometry* geom, const int64_t* offse
   hipStream_t s = (hipStream_t)stream;
   const unsigned nb = (unsigned)ceil_div(p.nsb, 256);
   if (work) {
-    hipLaunchKernelGGL(k_order_keys, dim3(nb), dim3(256), 0, s, p, offsets, key, inner);
+    hipLaunchKernelGGL(k_order_keys, dim3((unsigned)p.nsb), dim3(64), 0, s, p, offsets, key, inner);
     FDTBX_LAUNCH_CHECK("tile order keys");
     hipLaunchKernelGGL(k_order_rank, dim3(nb), dim3(256), 0, s, p, (const int64_t*)key, sorted);
     FDTBX_LAUNCH_CHECK("tile order ranks");
