@@ -7,6 +7,7 @@ the oracle (dropped term, wrong sign or index, transposed operand) fails at
 least one of them.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -890,3 +891,36 @@ def test_profile_points_sum_to_the_pattern():
     ref = O.pattern_at(P, R, Z, use_skip=False)
     assert ref.max() > 0
     np.testing.assert_allclose(L * vals.sum(1), ref, rtol=1e-11, atol=1e-14 * ref.max())
+
+
+def _golden(name):
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", name)
+    out = {}
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            key, value, decimals = line.split()[:3]
+            out[key] = (float(value), None if decimals == "-" else int(decimals))
+    return out
+
+
+def test_oracle_reproduces_the_numbers_the_paper_prints():
+    """The oracle's angular weights and Lorentz factor give, at the precision the paper prints
+    them, the numbers of tests/golden/paper_printed_values.txt; the synthetic detectors follow
+    Eq. SF with its 0.9 fill."""
+    g = _golden("paper_printed_values.txt")
+    s = 2.5 * DEG
+    half = lambda st, gt: optimize.brentq(lambda x: O.angular_shape(x, st, gt) - 0.5, 0.0, 20 * max(st, gt))
+    v, d = g["gaussian_fwhm_over_sigma"]
+    assert round(2 * half(s, 0.0) / s, d) == v
+    v, d = g["gaussian_over_lorentz_half_width"]
+    assert round(half(s, 0.0) / half(0.0, s), d) == v
+    delta = g["lorentz_delta"][0]
+    assert W.config1().quad.delta == delta and W.config0().quad.delta == delta
+    assert O.lorentz(0.0, delta) == 1.0
+    assert abs(O.lorentz(1e3 * delta, delta) * 1e3 - 1.0) < 2e-3      # L ~ delta / R for R >> delta
+    fill = g["detector_fill"][0]
+    for wl in W.config4(n_models=4):
+        geo = wl.geom
+        two_theta = 2 * math.asin(geo.wavelength / (2 * wl.quad.d_min))
+        want = fill * min(geo.width, geo.height) * geo.pixel / (2 * math.tan(two_theta))
+        assert abs(geo.distance - want) <= 1e-12 * want
