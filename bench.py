@@ -373,6 +373,18 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     MIRROR["on"] = not args.no_mirror
+    # the first pattern of the process (code objects loaded, first allocations), timed alone;
+    # not in the runs with a fixed tile width (the profiler runs, whose kernel averages must be
+    # those of the timed steps)
+    cold_ms = None
+    if not args.tile_w:
+        from paper_2608_23245_amd import Pipeline
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Pipeline(fold(wl)).pattern()
+        torch.cuda.synchronize()
+        cold_ms = (time.perf_counter() - t0) * 1e3
+        log(f"cold first pattern: {cold_ms:.0f} ms")
     if args.tile_w:
         wl = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, tile_w=args.tile_w))
         tiles = {"tile": f"{args.tile_w}x{64 // args.tile_w}", "tuned": False}
@@ -404,6 +416,7 @@ def main():
                    "nodes": wl.quad.n_nodes ** 2, "culled_pairs": int(state["idx"].shape[0]),
                    "useful_evals_per_step": int(n_evals), "pass": "forward"},
         "ms_per_pattern": ms_step,
+        "cold_first_pattern_ms": cold_ms,
         "profile_kernel_ms": prof_ms,
         "profile_kernel_evals_per_s": n_evals / (prof_ms * 1e-3),
         "tile_tuning": tiles,
