@@ -69,7 +69,7 @@ typedef struct fdtbx_geometry {
   double center_x, center_y;  /* beam centre in pixel units (width/2, height/2 puts it between pixels) */
   double tilt;                /* fibre tilt, radians, |tilt| < pi/2 */
   int32_t tile_w;             /* pixel tile width: 2, 4, 8, 16 or 32 (0 means FDTBX_TILE); a tile
-                                 is tile_w x (64 / tile_w) pixels, one 64-lane wave */
+                                 is tile_w x (64 / tile_w) pixels, one pixel per lane of a wave */
   int32_t mirror;             /* 1: fold the left-right mirror symmetry (below); 0: every tile runs */
   int32_t tile_waves;         /* waves per tile of fdtbx_profile, fdtbx_profile_adjoint and
                                  fdtbx_profile_cyl: 1, 2 or 4 (wave w takes the chunks w, w + waves,
@@ -77,7 +77,8 @@ typedef struct fdtbx_geometry {
                                  of 8 ring indices of each pair; the forward's first wave adds the
                                  others' pixel sums in wave order); 0: the library's choice, 4 when the
                                  launched tiles fit in eight rounds of one-wave workgroups (32 per
-                                 compute unit), else 2 */
+                                 compute unit), else 2.  The batched persistent kernels run one
+                                 wave per (model, tile) item whatever the value */
 } fdtbx_geometry;
 /* Mirror fold.  With center_x = width / 2 exactly, pixel (i, j) and its mirror (width-1-i, j)
  * have y of opposite sign and equal z, so their (R, Z) are bit-identical (R depends on y only
