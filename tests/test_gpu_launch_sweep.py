@@ -2,7 +2,8 @@
 sizes, beam centres, cells, tilts, lineshapes, node grids) crossed with random tile shapes,
 waves per tile and, where the beam is centred, the mirror fold.  Every pattern is compared
 with the oracle at the pattern tolerances, and every folded pattern with its unfolded twin
-(same waves per tile) bit for bit."""
+(same waves per tile) bit for bit; eight more cases compare the atom gradients of the
+hand-written adjoint with the oracle's."""
 import dataclasses
 import math
 import sys
@@ -74,3 +75,31 @@ def test_random_launch_vs_oracle(seed):
         folded = Pipeline(dataclasses.replace(wl, geom=dataclasses.replace(g, mirror=1))).pattern()
         torch.cuda.synchronize()
         assert torch.equal(folded, img)
+
+
+@pytest.mark.parametrize("seed", range(100, 108))
+def test_random_launch_gradients_vs_oracle(seed):
+    from paper_2608_23245_amd import autograd as AG
+    from paper_2608_23245_amd import binding as B
+    wl, fold = random_case(seed)
+    if fold:
+        wl = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, mirror=1))
+    g = wl.geom
+    say(f"gradients seed {seed}: {g.width}x{g.height}, tile {g.tile_w} wide, waves {g.tile_waves}, "
+        f"fold {fold}, lineshape {wl.dis.lineshape}")
+    eng = AG.PatternEngine(wl)
+    if eng.n_hkl == 0:
+        pytest.skip("empty reflection list")
+    G = np.random.default_rng(seed).normal(size=(g.height, g.width))
+    a = wl.atoms
+    atoms = eng.atoms(*(torch.as_tensor(v) for v in (a.x, a.y, a.z, a.B, a.occ)))
+    F, F2 = B.structure_factors(eng.cell, atoms, eng.hkl)
+    eng.plan.run(eng.hkl, F2)
+    out, glob, _ = B.pattern_backward(eng.plan, eng.hkl, F, torch.as_tensor(G, dtype=torch.float32).cuda(), atoms)
+    ref = O.gradients(wl, O.prepare(wl, hkl=eng.hkl.cpu().numpy(), cull_extinct=False), G)
+    for k in ("x", "y", "z", "B", "occ"):
+        got = out[k].cpu().numpy().astype(np.float64)
+        r = np.asarray(ref["atoms"][k], np.float64)
+        err = np.abs(got - r) / np.maximum(np.abs(r), 1e-3 * np.abs(r).max())
+        assert err.max() <= 1e-3, (k, err.max())
+    say("  atom gradients within 1e-3")
