@@ -6,6 +6,9 @@ lists), splat.hip (sample positions and their detector pixels), cyl.hip (ring
 quadrature sizes) and points.hip (the Ewald projection) are compiled without
 floating-point contraction so that their binary64 predicates are
 evaluated exactly as written.
+
+The example program examples/fdtbx_pattern.cpp, a caller of the C ABI without Python, is
+linked against the library as _lib/fdtbx_pattern (run path $ORIGIN).
 """
 from __future__ import annotations
 
@@ -18,6 +21,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT_DIR = os.path.join(HERE, "_lib")
 LIB = os.path.join(OUT_DIR, "libfdtbx.so")
+EXAMPLE = os.path.join(OUT_DIR, "fdtbx_pattern")
+INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 SOURCES = {
     "exact.hip": ["-ffp-contract=off"],
@@ -60,6 +65,13 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    tmp = EXAMPLE + ".tmp"
+    cmd = [cc, *COMMON, "-I", INCLUDE, os.path.join(HERE, "examples", "fdtbx_pattern.cpp"), "-o", tmp,
+           "-L", OUT_DIR, "-lfdtbx", "-Wl,-rpath,$ORIGIN"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, EXAMPLE)
     return LIB
 
 
