@@ -90,7 +90,8 @@ def parse():
     ap.add_argument("--no-cyl", action="store_true", help="skip the exact cylindrical-average leg")
     ap.add_argument("--tile-w", type=int, default=0, choices=(0, 2, 4, 8, 16, 32),
                     help="pixel-tile width of the medium forward (0: chosen by the tile tuner)")
-    ap.add_argument("--no-mirror", action="store_true", help="run every tile (no left-right mirror fold)")
+    ap.add_argument("--no-mirror", action="store_true", help="run every tile (no mirror fold)")
+    ap.add_argument("--no-updown", action="store_true", help="fold the left-right mirror only (not the up-down one)")
     ap.add_argument("--no-unfolded", action="store_true", help="skip the unfolded reference forward")
     ap.add_argument("--batch-models", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
@@ -156,18 +157,51 @@ def forward_leg(wl, steps, warmup):
     return ms_step, prof_ms, n_evals, state
 
 
-MIRROR = {"on": True}
+MIRROR = {"on": True, "updown": True}
 
 
 def fold(wl):
-    """wl with the left-right mirror fold on when its geometry allows it (beam centre at
-    width/2, width a multiple of the tile width) and --no-mirror was not given: the per-tile
-    launches run the left tile columns and write each value to the pixel and its mirror (the
-    image is bit-identical; the evaluations counted are the ones performed)."""
+    """wl with the mirror folds its geometry allows, unless --no-mirror was given: left-right
+    (bit 0) with the beam centre at width/2 and the width a multiple of the tile width (the
+    image is bit-identical); up-down (bit 1, unless --no-updown) with the fibre normal to the
+    beam, the beam centre at height/2 and the height a multiple of the tile height (the pattern's
+    Friedel symmetry: the mirrored rows agree with an unfolded run to float32 rounding).  The
+    per-tile launches run the left columns and top rows and write each value to its mirror
+    images; the evaluations counted are the ones performed."""
     g = wl.geom
-    if not MIRROR["on"] or not (g.center_x == 0.5 * g.width and g.width % (g.tile_w or 8) == 0):
-        return wl
-    return dataclasses.replace(wl, geom=dataclasses.replace(g, mirror=1))
+    tw = g.tile_w or 8
+    bits = 0
+    if MIRROR["on"] and g.center_x == 0.5 * g.width and g.width % tw == 0:
+        bits |= 1
+    if MIRROR["on"] and MIRROR["updown"] and g.tilt == 0.0 and g.center_y == 0.5 * g.height and g.height % (64 // tw) == 0:
+        bits |= 2
+    return dataclasses.replace(wl, geom=dataclasses.replace(g, mirror=bits))
+
+
+def fold_name(wl):
+    m = wl.geom.mirror
+    return {0: "none", 1: "left-right", 2: "up-down", 3: "left-right and up-down"}[m]
+
+
+def compare_unfolded(wl, img, img0):
+    """A folded image against the unfolded one of the same waves per tile: the pixels the folded
+    launches compute are bit-identical, the left-right mirror pixels too; the up-down mirror rows
+    agree to float32 rounding (Friedel mates summed in another order).  Asserts the first and
+    returns the relative L2 and largest per-pixel differences of the whole image."""
+    import torch
+    g = wl.geom
+    th = 64 // (g.tile_w or 8)
+    tiles_y = -(-g.height // th)
+    top = ((tiles_y + 1) // 2) * th if g.mirror & 2 else g.height
+    assert torch.equal(img[:top], img0[:top]), "the folded image's computed rows differ from the unfolded ones"
+    if g.mirror & 2:
+        low = g.height - top  # rows written from their up-down mirrors
+        assert torch.equal(img[g.height - low:], torch.flip(img[:low], [0]))
+    a, b = img.double(), img0.double()
+    big = b > 1e-3 * b.max()
+    return {"computed_rows_bit_identical": True, "image_bit_identical": bool(torch.equal(img, img0)),
+            "rel_l2": float(torch.linalg.norm(a - b) / torch.linalg.norm(b)),
+            "max_rel_pixel": float(((a - b).abs()[big] / b[big]).max())}
 
 
 def other_rates(kernel_evals_per_s, prof_ms):
@@ -221,7 +255,7 @@ def bench_large(args):
     out = {"workload": wl.name, "n_hkl": int(state["hkl"].shape[0]), "culled_pairs": int(state["idx"].shape[0]),
            "useful_evals_per_step": int(n_evals), "ms_per_pattern": ms_step, "profile_kernel_ms": prof_ms,
            "evals_per_s": n_evals / (ms_step * 1e-3), "profile_kernel_evals_per_s": n_evals / (prof_ms * 1e-3),
-           "issue_frac": ach / PEAK_SLOTS, "mirror_fold": bool(wl.geom.mirror),
+           "issue_frac": ach / PEAK_SLOTS, "mirror_fold": fold_name(wl),
            "waves_per_tile": B.launch_waves(B.make_model(wl).geom), "pass": "forward"}
     del state
     return out
@@ -373,6 +407,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     MIRROR["on"] = not args.no_mirror
+    MIRROR["updown"] = not args.no_updown
     # the first pattern of the process (code objects loaded, first allocations), timed alone;
     # not in the runs with a fixed tile width (the profiler runs, whose kernel averages must be
     # those of the timed steps)
@@ -412,7 +447,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": wl.name, "n_hkl": int(state["hkl"].shape[0]), "pixels": wl.geom.width * wl.geom.height,
-                   "tile": tiles["tile"], "mirror_fold": bool(wl.geom.mirror), "waves_per_tile": waves_main,
+                   "tile": tiles["tile"], "mirror_fold": fold_name(wl), "waves_per_tile": waves_main,
                    "nodes": wl.quad.n_nodes ** 2, "culled_pairs": int(state["idx"].shape[0]),
                    "useful_evals_per_step": int(n_evals), "pass": "forward"},
         "ms_per_pattern": ms_step,
@@ -426,15 +461,14 @@ def main():
                      "slots_per_eval": SLOTS_PER_EVAL},
     }
     if wl.geom.mirror and not args.no_unfolded:
-        # the same forward step without the fold, for reference (with the same waves per tile,
-        # so that the two images can be compared bit for bit)
+        # the same forward step without the folds, for reference (with the same waves per tile,
+        # so that the computed pixels can be compared bit for bit)
         waves = waves_main
         wl0 = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, mirror=0, tile_waves=waves))
         ms0, prof0, n0, st0 = forward_leg(wl0, max(1, min(args.steps, 3)), 1)
-        assert torch.equal(st0["img"], state["img"]), "the folded image differs from the unfolded one"
         out["unfolded"] = {"ms_per_pattern": ms0, "profile_kernel_ms": prof0, "useful_evals_per_step": int(n0),
-                           "waves_per_tile": waves,
-                           "profile_kernel_evals_per_s": n0 / (prof0 * 1e-3), "image_bit_identical": True}
+                           "waves_per_tile": waves, "profile_kernel_evals_per_s": n0 / (prof0 * 1e-3),
+                           **compare_unfolded(wl, state["img"], st0["img"])}
         del st0
     if not args.no_cpu:
         log("cpu baseline (oracle)")

@@ -70,7 +70,8 @@ typedef struct fdtbx_geometry {
   double tilt;                /* fibre tilt, radians, |tilt| < pi/2 */
   int32_t tile_w;             /* pixel tile width: 2, 4, 8, 16 or 32 (0 means FDTBX_TILE); a tile
                                  is tile_w x (64 / tile_w) pixels, one pixel per lane of a wave */
-  int32_t mirror;             /* 1: fold the left-right mirror symmetry (below); 0: every tile runs */
+  int32_t mirror;             /* bit 0: fold the left-right mirror symmetry, bit 1: the up-down
+                                 (Friedel) symmetry (below); 0: every tile runs */
   int32_t tile_waves;         /* waves per tile of fdtbx_profile, fdtbx_profile_adjoint and
                                  fdtbx_profile_cyl: 1, 2 or 4 (wave w takes the chunks w, w + waves,
                                  ... of 64 pairs of the tile's list, or for the cylindrical average
@@ -90,7 +91,23 @@ typedef struct fdtbx_geometry {
  * the unfolded one with the same waves per tile, fdtbx_launch_waves), and makes the adjoints
  * take grad(i, j) + grad(width-1-i, j) as the weight of the computed pixel.  fdtbx_pixel_map
  * still produces every tile; fdtbx_cull lists the launched columns only (the right columns'
- * lists are empty). */
+ * lists are empty).
+ *
+ * Up-down (Friedel) fold, bit 1 of mirror.  With the fibre normal to the beam (tilt 0) and
+ * center_y = height / 2 exactly, pixel (i, j) and (i, height-1-j) have z of opposite sign, so
+ * their (R, Z) are (R, Z) and (R, -Z) bit for bit.  The reflection list is closed under
+ * negation.  The mate -D of a reflection D has the same weight (|F|^2 by Friedel's law with
+ * real form factors; the disorder and damping factors are even in hkl); its ring point at
+ * (R, -Z) and its nodes are those of D at (R, Z) negated, with the same orientational weights
+ * (the tangent frame of -D spans the same plane and the node grid is symmetric); and every
+ * lineshape is even.  So the pattern obeys I(R, -Z) = I(R, Z) exactly in the model.  The per-tile
+ * kernels then run the top ceil(tiles_y / 2) tile rows only (height must be a multiple of the
+ * tile height 64 / tile_w, so tile row tiles_y-1-ty holds the mirror rows of row ty) and write
+ * each value also to (i, height-1-j); with both bits, to all four mirror images.  Unlike the
+ * left-right fold this is not bit-identical to the unfolded image: a mirrored pixel sums the
+ * mates' contributions in another order, so the two agree to float32 rounding (the top rows
+ * computed are bit-identical).  The adjoints take the sum of grad over the mirror images as
+ * the weight of the computed pixel, and fdtbx_cull lists the launched rows only. */
 
 /* Orientational and lattice disorder (section "Angular peak shapes", tutorial
  * Table "paracrystal").  sigma_theta: Gaussian standard deviation; gamma_theta:
@@ -265,8 +282,8 @@ int fdtbx_reflection_prep(const fdtbx_model* model, const int32_t* hkl, int64_t 
  *        n_tiles = tiles_x * tiles_y */
 int fdtbx_pixel_map(const fdtbx_geometry* geom, double* pix, double* tile, void* stream);
 
-/* Per-tile culling lists (under the mirror fold, of the launched tile columns only; the other
- * columns' lists are empty): reflection r is listed for tile t iff it is kept and
+/* Per-tile culling lists (under the mirror folds, of the launched tile columns and rows only;
+ * the other tiles' lists are empty): reflection r is listed for tile t iff it is kept and
  *   R_lo(r) <= R_hi(t), R_lo(t) <= R_hi(r), Z_lo(r) <= Z_hi(t), Z_lo(t) <= Z_hi(r),
  *   P2_lo(r) <= P2_hi(t), P2_lo(t) <= P2_hi(r), and (if rho1 >= 0)
  *   max_corner(n1 . p) >= -rho1 and max_corner(n2 . p) >= -rho2 over the tile box corners,

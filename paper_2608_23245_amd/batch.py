@@ -76,10 +76,13 @@ class BatchEngine:
             n_rows = B.node_rows(wl.quad.n_nodes)
             node_blocks += [_pack(m, r) for r in range(0, n_rows, RB)]
             lens = (rowptr[1:] - rowptr[:-1]).cpu().numpy()
-            # under the mirror fold only the left tile columns run (their lists serve the mirror)
-            tx_n, _ = B.tile_grid(mod.geom)
-            lcols = (tx_n + 1) // 2 if mod.geom.mirror else tx_n
-            keep = np.nonzero(np.arange(n_tiles) % tx_n < lcols)[0]
+            # under the mirror folds only the left tile columns (bit 0) and the top tile rows
+            # (bit 1) run; their values serve the mirror pixels
+            tx_n, ty_n = B.tile_grid(mod.geom)
+            lcols = (tx_n + 1) // 2 if mod.geom.mirror & 1 else tx_n
+            lrows = (ty_n + 1) // 2 if mod.geom.mirror & 2 else ty_n
+            t_all = np.arange(n_tiles)
+            keep = np.nonzero((t_all % tx_n < lcols) & (t_all // tx_n < lrows))[0]
             items += [_pack(m, int(t)) for t in keep]
             costs.append(lens[keep])
             self.list_len.append(int(idx.shape[0]))

@@ -508,9 +508,9 @@ extern "C" int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(6 * n_hkl, 256)), dim3(256), 0, s, sums, 6 * n_hkl);
   FDTBX_LAUNCH_CHECK("adjoint zero");
-  const dim3 grid((unsigned)(order ? order_grid(q.lcols, q.tiles_y) : tile_grid(q)));
+  const dim3 grid((unsigned)(order ? order_grid(q.lcols, q.lrows) : tile_grid(q)));
   int waves = 1;
-  rc = tile_waves(&model->geom, (int64_t)q.lcols * q.tiles_y, &waves);
+  rc = tile_waves(&model->geom, (int64_t)q.lcols * q.lrows, &waves);
   if (rc) return rc;
   if (waves == 4)
     launch_adj<4>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, grad_image, sums);

@@ -116,11 +116,8 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
   const bool in = i < q.W && j < q.H;
   const double R = in ? pix[2 * ((int64_t)j * q.W + i) + 0] : 1.0e30;
   const double Z = in ? pix[2 * ((int64_t)j * q.W + i) + 1] : 0.0;
-  // under the mirror fold this pixel also stands for its mirror (unless both are in this tile)
-  const float gimg = !in ? 0.0f
-                         : (q.mirror && 2 * tx + 1 != q.tiles_x)
-                               ? grad_image[(int64_t)j * q.W + i] + grad_image[(int64_t)j * q.W + (q.W - 1 - i)]
-                               : grad_image[(int64_t)j * q.W + i];
+  // under the mirror folds this pixel also stands for its mirror images
+  const float gimg = in ? folded_weight(q, grad_image, i, j, tx, ty) : 0.0f;
   const float gp = gimg * (float)(q.delta / (R + q.delta));
   const TileBox box = {tile[8 * (int64_t)t + 0], tile[8 * (int64_t)t + 1], tile[8 * (int64_t)t + 2],
                        tile[8 * (int64_t)t + 3]};

@@ -48,11 +48,15 @@ int check_geometry(const fdtbx_geometry* g) {
   const int32_t tw = g->tile_w;
   if (!(tw == 0 || tw == 2 || tw == 4 || tw == 8 || tw == 16 || tw == 32))
     return fail(FDTBX_ERR_INVALID_ARGUMENT, "tile_w must be 0, 2, 4, 8, 16 or 32");
-  if (g->mirror != 0 && g->mirror != 1) return fail(FDTBX_ERR_INVALID_ARGUMENT, "mirror must be 0 or 1");
+  if (g->mirror < 0 || g->mirror > 3) return fail(FDTBX_ERR_INVALID_ARGUMENT, "mirror must be 0, 1, 2 or 3");
   if (!(g->tile_waves == 0 || g->tile_waves == 1 || g->tile_waves == 2 || g->tile_waves == 4))
     return fail(FDTBX_ERR_INVALID_ARGUMENT, "tile_waves must be 0, 1, 2 or 4");
-  if (g->mirror && !(g->center_x == 0.5 * g->width && g->width % (tw ? tw : FDTBX_TILE) == 0))
-    return fail(FDTBX_ERR_INVALID_ARGUMENT, "mirror needs center_x = width/2 and width a multiple of tile_w");
+  const int32_t tww = tw ? tw : FDTBX_TILE;
+  if ((g->mirror & 1) && !(g->center_x == 0.5 * g->width && g->width % tww == 0))
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "the left-right fold needs center_x = width/2 and width a multiple of tile_w");
+  if ((g->mirror & 2) && !(g->center_y == 0.5 * g->height && g->tilt == 0.0 && g->height % (64 / tww) == 0))
+    return fail(FDTBX_ERR_INVALID_ARGUMENT,
+                "the up-down fold needs center_y = height/2, no fibre tilt and height a multiple of 64/tile_w");
   return FDTBX_OK;
 }
 
@@ -155,7 +159,7 @@ extern "C" int fdtbx_launch_waves(const fdtbx_geometry* geom, int32_t* waves) {
   int rc = check_geometry(geom);
   if (rc) return rc;
   int w = 1;
-  rc = tile_waves(geom, (int64_t)lcols_of(geom) * tiles_y_of(geom), &w);
+  rc = tile_waves(geom, (int64_t)lcols_of(geom) * lrows_of(geom), &w);
   *waves = w;
   return rc;
 }

@@ -220,9 +220,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_cyl(CylParams p, const float* __
       for (int k = 1; k < WAVES; ++k) acc += xacc[64 * (k - 1) + lane];
     }
     if (!in) return;
-    const float v = acc * (float)(dphi / (2.0 * M_PI));
-    image[(int64_t)pj * q.W + pi_] = v;
-    if (q.mirror && 2 * tx + 1 != q.tiles_x) image[(int64_t)pj * q.W + (q.W - 1 - pi_)] = v;
+    write_folded(q, image, pi_, pj, tx, ty, acc * (float)(dphi / (2.0 * M_PI)));
   }
 }
 
@@ -268,14 +266,14 @@ extern "C" int fdtbx_profile_cyl(const fdtbx_model* model, const float* refl, co
   // a few superblocks, which the spatially grouped order would pile onto few XCDs)
   p.q.sbw = 0;
   hipStream_t s = (hipStream_t)stream;
-  const dim3 grid((unsigned)(order ? order_grid(p.q.lcols, p.q.tiles_y) : tile_grid(p.q)));
+  const dim3 grid((unsigned)(order ? order_grid(p.q.lcols, p.q.lrows) : tile_grid(p.q)));
   unsigned long long* cp = (unsigned long long*)counts;
   if (counts) {
     hipLaunchKernelGGL(k_zero_count, dim3(1), dim3(64), 0, s, cp);
     FDTBX_LAUNCH_CHECK("cylindrical average counter");
   }
   int waves = 1;
-  rc = tile_waves(&model->geom, (int64_t)p.q.lcols * p.q.tiles_y, &waves);
+  rc = tile_waves(&model->geom, (int64_t)p.q.lcols * p.q.lrows, &waves);
   if (rc) return rc;
   if (waves == 4)
     launch_cyl<4>(p, grid, s, refl, nodes, pix, offsets, idx, order, image, cp);

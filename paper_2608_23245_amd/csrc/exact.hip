@@ -492,10 +492,10 @@ __global__ void __launch_bounds__(256) k_b_prep(const fdtbx_batch_entry* __restr
 // candidates and writes the exact per-tile lists in ascending order.
 static constexpr int kSB = 4;
 
-// lcols: tile columns that get lists (all, or the left half under the mirror fold, whose
-// right columns keep empty lists: no launch reads them).
+// lcols, lrows: tile columns and rows that get lists (all, or the left or top half under the
+// mirror folds, the other tiles keeping empty lists: no launch reads them).
 struct CullParams {
-  int32_t tiles_x, tiles_y, sb_x, sb_y, lcols;
+  int32_t tiles_x, tiles_y, sb_x, sb_y, lcols, lrows;
   int64_t n_hkl, n_words;
 };
 
@@ -545,7 +545,7 @@ __global__ void __launch_bounds__(64) k_sb_mask(CullParams q, const double* __re
   for (int k = 0; k < 13; ++k) c[k] = have ? cull[FDTBX_CULL_DOUBLES * r + k] : 0.0;
   const int nsb = q.sb_x * q.sb_y;
   for (int s = 0; s < nsb; ++s) {
-    if ((s % q.sb_x) * kSB >= q.lcols) continue;  // no tile of this superblock gets a list
+    if ((s % q.sb_x) * kSB >= q.lcols || (s / q.sb_x) * kSB >= q.lrows) continue;  // no tile of it gets a list
     double box[6];
     for (int k = 0; k < 6; ++k) box[k] = sb[8 * (int64_t)s + k];
     bool hit = have && cull_test(box, c);
@@ -563,7 +563,7 @@ __global__ void __launch_bounds__(64) k_sb_mask(CullParams q, const double* __re
 // 1 (counts holding the exclusive offsets) writes the hits of wave w for tile t at t's offset
 // plus the hits of the waves before w, so every list comes out ascending.  Tiles off the
 // detector or in a column the mirror fold does not launch get no list (NaN boxes fail every
-// test; their count is 0).
+// test; their count is 0), and so do the rows the up-down fold does not launch.
 static constexpr int kWordsPer = 16;
 static constexpr int kTB = kSB * kSB;  // tiles and waves per block
 
@@ -581,7 +581,7 @@ __global__ void __launch_bounds__(64 * kTB) k_tile_lists(CullParams q, const dou
   if (threadIdx.x < kTB * 6) {
     const int u = threadIdx.x / 6, c = threadIdx.x % 6;
     const int tx = sx * kSB + u % kSB, ty = sy * kSB + u / kSB;
-    boxes[u][c] = (tx < q.lcols && ty < q.tiles_y) ? tile[8 * ((int64_t)ty * q.tiles_x + tx) + c] : (double)NAN;
+    boxes[u][c] = (tx < q.lcols && ty < q.lrows) ? tile[8 * ((int64_t)ty * q.tiles_x + tx) + c] : (double)NAN;
   }
   __syncthreads();
   int cnt[kTB];
@@ -592,14 +592,14 @@ __global__ void __launch_bounds__(64 * kTB) k_tile_lists(CullParams q, const dou
     pos[u] = 0;
     if (MODE) {
       const int tx = sx * kSB + u % kSB, ty = sy * kSB + u / kSB;
-      if (tx < q.lcols && ty < q.tiles_y) {
+      if (tx < q.lcols && ty < q.lrows) {
         pos[u] = counts[(int64_t)ty * q.tiles_x + tx];
         for (int w = 0; w < wv; ++w) pos[u] += part[((int64_t)s * kTB + w) * kTB + u];
       }
     }
   }
-  // superblocks wholly right of the launched columns have no mask row
-  if (sx * kSB < q.lcols) {
+  // superblocks wholly right of the launched columns or below the launched rows have no mask row
+  if (sx * kSB < q.lcols && sy * kSB < q.lrows) {
     const int64_t per = (q.n_words + kTB - 1) / kTB;
     const int64_t wlo = per * wv, whi = wlo + per < q.n_words ? wlo + per : q.n_words;
     const uint64_t* mrow = mask + (int64_t)s * q.n_words;
@@ -663,7 +663,7 @@ __global__ void __launch_bounds__(64 * kTB) k_tile_lists(CullParams q, const dou
       if (tx < q.tiles_x && ty < q.tiles_y) {
         int64_t sum = 0;
         for (int w = 0; w < kTB; ++w) sum += hits[w][u];
-        counts[(int64_t)ty * q.tiles_x + tx] = sum;  // 0 for columns without lists
+        counts[(int64_t)ty * q.tiles_x + tx] = sum;  // 0 for tiles without lists
       }
     }
   }
@@ -756,6 +756,7 @@ static void cull_params(const fdtbx_geometry* g, int64_t n_hkl, CullParams* q) {
   q->tiles_x = tiles_x_of(g);
   q->tiles_y = tiles_y_of(g);
   q->lcols = lcols_of(g);
+  q->lrows = lrows_of(g);
   q->sb_x = (int32_t)ceil_div(q->tiles_x, kSB);
   q->sb_y = (int32_t)ceil_div(q->tiles_y, kSB);
   q->n_hkl = n_hkl;

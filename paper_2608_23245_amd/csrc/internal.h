@@ -34,9 +34,11 @@ inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int tile_lg(const fdtbx_geometry* g) { return __builtin_ctz((unsigned)(g->tile_w ? g->tile_w : FDTBX_TILE)); }
 inline int32_t tiles_x_of(const fdtbx_geometry* g) { return (int32_t)ceil_div(g->width, 1 << tile_lg(g)); }
 inline int32_t tiles_y_of(const fdtbx_geometry* g) { return (int32_t)ceil_div(g->height, 64 >> tile_lg(g)); }
-// Tile columns the per-tile kernels launch: all, or the left half (with the middle column)
-// under the mirror fold.
-inline int32_t lcols_of(const fdtbx_geometry* g) { return g->mirror ? (tiles_x_of(g) + 1) / 2 : tiles_x_of(g); }
+// Tile columns and rows the per-tile kernels launch: all, or the left half (with the middle
+// column) under the left-right fold (mirror bit 0), the top half (with the middle row) under
+// the up-down fold (mirror bit 1).
+inline int32_t lcols_of(const fdtbx_geometry* g) { return (g->mirror & 1) ? (tiles_x_of(g) + 1) / 2 : tiles_x_of(g); }
+inline int32_t lrows_of(const fdtbx_geometry* g) { return (g->mirror & 2) ? (tiles_y_of(g) + 1) / 2 : tiles_y_of(g); }
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // v[0..n) = x, by a kernel (hipMemsetAsync nodes do not belong in captured graphs).

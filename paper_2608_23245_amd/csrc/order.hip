@@ -13,8 +13,8 @@
 
 namespace fdtbx {
 
-// tiles_x: the launched tile columns (all, or the left half under the mirror fold); stride:
-// tile columns of the detector (tile t = ty * stride + tx).
+// tiles_x, tiles_y: the launched tile columns and rows (all, or the left or top half under the
+// mirror folds); stride: tile columns of the detector (tile t = ty * stride + tx).
 struct OrderParams {
   int32_t tiles_x, tiles_y, S, sbw, sbh, stride;
   int64_t nsb;
@@ -84,7 +84,7 @@ __global__ void __launch_bounds__(256) k_order_fill(OrderParams p, int64_t n_blo
 
 static void order_params(const fdtbx_geometry* g, OrderParams* p) {
   p->tiles_x = lcols_of(g);
-  p->tiles_y = tiles_y_of(g);
+  p->tiles_y = lrows_of(g);
   p->stride = tiles_x_of(g);
   p->S = order_super(p->tiles_x, p->tiles_y);
   p->sbw = (int32_t)ceil_div(p->tiles_x, p->S);
@@ -98,7 +98,7 @@ using namespace fdtbx;
 
 extern "C" int64_t fdtbx_tile_order_size(const fdtbx_geometry* geom) {
   if (!geom || check_geometry(geom)) return 0;
-  return order_grid(lcols_of(geom), tiles_y_of(geom));
+  return order_grid(lcols_of(geom), lrows_of(geom));
 }
 
 extern "C" size_t fdtbx_tile_order_workspace(const fdtbx_geometry* geom) {

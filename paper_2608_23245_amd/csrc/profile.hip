@@ -140,9 +140,9 @@ extern "C" int fdtbx_profile(const fdtbx_model* model, const float* refl, const 
   ProfParams q;
   prof_params(model, &q);
   hipStream_t s = (hipStream_t)stream;
-  const dim3 grid((unsigned)(order ? order_grid(q.lcols, q.tiles_y) : tile_grid(q)));
+  const dim3 grid((unsigned)(order ? order_grid(q.lcols, q.lrows) : tile_grid(q)));
   int waves = 1;
-  rc = tile_waves(&model->geom, (int64_t)q.lcols * q.tiles_y, &waves);
+  rc = tile_waves(&model->geom, (int64_t)q.lcols * q.lrows, &waves);
   if (rc) return rc;
   if (waves == 4)
     launch_profile<4>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, image, counts);

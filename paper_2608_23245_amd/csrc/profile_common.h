@@ -13,8 +13,10 @@ namespace fdtbx {
 struct ProfParams {
   int32_t W, H, tiles_x, tiles_y;
   int32_t tlg;      // tiles are 2^tlg pixels wide and 64 >> tlg high
-  int32_t lcols;    // tile columns launched: tiles_x, or the left half under the mirror fold
-  int32_t mirror;   // 1: each computed pixel is also written to (W - 1 - i, j)
+  int32_t lcols;    // tile columns launched: tiles_x, or the left half under the left-right fold
+  int32_t lrows;    // tile rows launched: tiles_y, or the top half under the up-down fold
+  int32_t mirror;   // bit 0: each computed pixel is also written to (W - 1 - i, j); bit 1: to
+                    // (i, H - 1 - j); both: also to (W - 1 - i, H - 1 - j)
   int32_t lineshape;
   int32_t n;        // nodes per side
   float T, inv_h;   // grid half extent, 1/spacing
@@ -38,11 +40,11 @@ __host__ __device__ inline int32_t superblocks_per_row(int32_t tiles_x, int32_t 
   return sbw * sbh >= 8 * kXcds ? (int32_t)sbw : 0;
 }
 
-// Workgroups of a per-tile launch (the padded superblock grid of the launched columns, or one
+// Workgroups of a per-tile launch (the padded superblock grid of the launched tiles, or one
 // per launched tile).
 __host__ __device__ inline int64_t tile_grid(const ProfParams& q) {
-  if (q.sbw == 0) return (int64_t)q.lcols * q.tiles_y;
-  const int64_t nsb = (int64_t)q.sbw * ((q.tiles_y + kSuper - 1) / kSuper);
+  if (q.sbw == 0) return (int64_t)q.lcols * q.lrows;
+  const int64_t nsb = (int64_t)q.sbw * ((q.lrows + kSuper - 1) / kSuper);
   return (int64_t)kXcds * kSuper * kSuper * ((nsb + kXcds - 1) / kXcds);
 }
 
@@ -57,13 +59,38 @@ __host__ __device__ inline int64_t order_grid(int32_t tiles_x, int32_t tiles_y) 
   return (int64_t)kXcds * S * S * ((nsb + kXcds - 1) / kXcds);
 }
 
-// Tile of workgroup b, or -1 for a padding workgroup (past the launched columns).
+// Tile of workgroup b, or -1 for a padding workgroup (past the launched columns or rows).
 __device__ inline int tile_of_block(const ProfParams& q, int b) {
   if (q.sbw == 0) return (b / q.lcols) * q.tiles_x + b % q.lcols;
   const int x = b % kXcds, k = b / kXcds;
   const int sb = (k / (kSuper * kSuper)) * kXcds + x, i = k % (kSuper * kSuper);
   const int tx = (sb % q.sbw) * kSuper + i % kSuper, ty = (sb / q.sbw) * kSuper + i / kSuper;
-  return tx < q.lcols && ty < q.tiles_y ? ty * q.tiles_x + tx : -1;
+  return tx < q.lcols && ty < q.lrows ? ty * q.tiles_x + tx : -1;
+}
+
+// Mirror folds.  Tile column tiles_x - 1 - tx holds the left-right mirror pixels of column tx
+// and tile row tiles_y - 1 - ty the up-down ones of row ty; a middle column or row (odd count)
+// is its own mirror, its pixels all computed.  write_folded stores a computed value at pixel
+// (i, j) of tile (tx, ty) and at the mirror pixels no launched tile computes; folded_weight is
+// the sum of an image-shaped weight over the same pixels (the adjoint's weight of the value).
+__device__ inline void write_folded(const ProfParams& q, float* image, int i, int j, int tx, int ty, float v) {
+  const bool mx = (q.mirror & 1) && 2 * tx + 1 != q.tiles_x;
+  const bool my = (q.mirror & 2) && 2 * ty + 1 != q.tiles_y;
+  const int64_t row = (int64_t)j * q.W, mrow = (int64_t)(q.H - 1 - j) * q.W;
+  image[row + i] = v;
+  if (mx) image[row + (q.W - 1 - i)] = v;
+  if (my) image[mrow + i] = v;
+  if (mx && my) image[mrow + (q.W - 1 - i)] = v;
+}
+__device__ inline float folded_weight(const ProfParams& q, const float* g, int i, int j, int tx, int ty) {
+  const bool mx = (q.mirror & 1) && 2 * tx + 1 != q.tiles_x;
+  const bool my = (q.mirror & 2) && 2 * ty + 1 != q.tiles_y;
+  const int64_t row = (int64_t)j * q.W, mrow = (int64_t)(q.H - 1 - j) * q.W;
+  float w = g[row + i];
+  if (mx) w += g[row + (q.W - 1 - i)];
+  if (my) w += g[mrow + i];
+  if (mx && my) w += g[mrow + (q.W - 1 - i)];
+  return w;
 }
 
 struct Window {
@@ -321,7 +348,8 @@ __host__ __device__ inline void prof_params(const fdtbx_model* model, ProfParams
   q->tiles_x = (q->W + tw - 1) / tw;
   q->tiles_y = (q->H + th - 1) / th;
   q->mirror = model->geom.mirror;
-  q->lcols = q->mirror ? (q->tiles_x + 1) / 2 : q->tiles_x;
+  q->lcols = (q->mirror & 1) ? (q->tiles_x + 1) / 2 : q->tiles_x;
+  q->lrows = (q->mirror & 2) ? (q->tiles_y + 1) / 2 : q->tiles_y;
   q->n = model->quad.n_nodes;
   q->T = (float)model->quad.T;
   q->inv_h = (float)(model->quad.n_nodes / (2.0 * model->quad.T));
@@ -331,7 +359,7 @@ __host__ __device__ inline void prof_params(const fdtbx_model* model, ProfParams
   q->tiny = 1.0e-12f;
   q->margin = 1.0e-3f;
   q->delta = model->quad.delta;
-  q->sbw = superblocks_per_row(q->lcols, q->tiles_y);
+  q->sbw = superblocks_per_row(q->lcols, q->lrows);
 }
 
 }  // namespace fdtbx

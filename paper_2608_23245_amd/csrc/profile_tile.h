@@ -177,10 +177,7 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
       for (int k = 1; k < WAVES; ++k) acc += xacc[64 * (k - 1) + lane];
     }
     if (!in) return;
-    const float v = (float)(q.delta / (R + q.delta)) * acc;
-    image[(int64_t)j * q.W + i] = v;
-    // mirror fold: tile column tiles_x - 1 - tx holds the mirror pixels (unless it is this one)
-    if (q.mirror && 2 * tx + 1 != q.tiles_x) image[(int64_t)j * q.W + (q.W - 1 - i)] = v;
+    write_folded(q, image, i, j, tx, ty, (float)(q.delta / (R + q.delta)) * acc);
   }
 }
 

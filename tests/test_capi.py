@@ -158,18 +158,34 @@ def test_mirror_fold_conditions(lib):
     ok = B.Geometry(1.0, 100.0, 0.1, 48, 23, 24.0, 11.5, 0.3, 16, 1)
     assert lib.fdtbx_tile_grid(ctypes.byref(ok), ctypes.byref(tx), ctypes.byref(ty)) == 0
     assert (tx.value, ty.value) == (3, 6)      # every tile column is still in the grid
-    for bad in (B.Geometry(1.0, 100.0, 0.1, 48, 23, 24.2, 11.5, 0.0, 16, 1),   # beam off the middle
-                B.Geometry(1.0, 100.0, 0.1, 40, 23, 20.0, 11.5, 0.0, 16, 1),   # width not a multiple of 16
-                B.Geometry(1.0, 100.0, 0.1, 48, 23, 24.0, 11.5, 0.0, 16, 2)):
-        assert lib.fdtbx_tile_grid(ctypes.byref(bad), ctypes.byref(tx), ctypes.byref(ty)) == -1
-        assert "mirror" in lib.fdtbx_error_string(-1).decode()
+    bad = {
+        "left-right fold": [B.Geometry(1.0, 100.0, 0.1, 48, 23, 24.2, 11.5, 0.0, 16, 1),   # beam off the middle
+                            B.Geometry(1.0, 100.0, 0.1, 40, 23, 20.0, 11.5, 0.0, 16, 1)],  # width not a multiple of 16
+        "up-down fold": [B.Geometry(1.0, 100.0, 0.1, 48, 23, 24.0, 11.5, 0.0, 16, 2),      # height not a multiple of 4
+                         B.Geometry(1.0, 100.0, 0.1, 48, 24, 24.0, 12.0, 0.1, 16, 2),      # tilted fibre
+                         B.Geometry(1.0, 100.0, 0.1, 48, 24, 24.0, 12.3, 0.0, 16, 3)],     # beam off the middle row
+        "mirror must be": [B.Geometry(1.0, 100.0, 0.1, 48, 24, 24.0, 12.0, 0.0, 16, m) for m in (-1, 4)],
+    }
+    for msg, geoms in bad.items():
+        for g in geoms:
+            assert lib.fdtbx_tile_grid(ctypes.byref(g), ctypes.byref(tx), ctypes.byref(ty)) == -1
+            assert msg in lib.fdtbx_error_string(-1).decode()
+    for m in (2, 3):
+        g = B.Geometry(1.0, 100.0, 0.1, 48, 24, 24.0, 12.0, 0.0, 16, m)
+        assert lib.fdtbx_tile_grid(ctypes.byref(g), ctypes.byref(tx), ctypes.byref(ty)) == 0
+        assert (tx.value, ty.value) == (3, 6)
     # the launch order covers the left 3 of the 6 tile columns of 8 pixels (3 x 3 tiles, padded
-    # to whole rounds of the 8 XCDs), against 6 x 3 without the fold
+    # to whole rounds of the 8 XCDs), against 6 x 3 without the fold; with the up-down fold too
+    # (24 rows of 8-row tiles), the top 2 of the 3 tile rows
     g = B.Geometry(1.0, 100.0, 0.1, 48, 23, 24.0, 11.5, 0.0, 8, 1)
     lib.fdtbx_tile_order_size.restype = ctypes.c_int64
     assert lib.fdtbx_tile_order_size(ctypes.byref(g)) == 16
     g.mirror = 0
     assert lib.fdtbx_tile_order_size(ctypes.byref(g)) == 24
+    g = B.Geometry(1.0, 100.0, 0.1, 48, 24, 24.0, 12.0, 0.0, 8, 3)
+    assert lib.fdtbx_tile_order_size(ctypes.byref(g)) == 8
+    g.mirror = 2
+    assert lib.fdtbx_tile_order_size(ctypes.byref(g)) == 16
 
 
 def test_tile_waves_values(lib):

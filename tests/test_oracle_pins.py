@@ -704,6 +704,25 @@ def test_pattern_symmetries_and_skip():
     assert np.all(img >= 0) and img.max() > 0
 
 
+@pytest.mark.parametrize("kw", [
+    dict(seed=2, sigma_theta=3 * DEG, gamma_theta=1 * DEG, g=(0.02, 0.01, 0.03)),
+    dict(seed=3, lineshape=2, g=(0.03, 0.02, 0.01), sigma_theta=2 * DEG),
+    dict(seed=4, lineshape=1, sigma_theta=2 * DEG, B_axis=(4.0, 9.0, 2.5), cell=W.Cell(11.0, 9.0, 13.0, 1.55, 1.68, 1.49)),
+])
+def test_friedel_up_down_symmetry_and_its_conditions(kw):
+    """The up-down fold's premise: with the fibre normal to the beam and the beam centred on the
+    rows, the pattern is symmetric under z -> -z to rounding (Friedel mates, even lineshapes,
+    point-symmetric node sets) for any lineshape, disorder and skewed cell, also with the beam off
+    the middle column; a tilted fibre or a beam off the middle row breaks it."""
+    base = dict(width=30, height=28, **kw)
+    sym = O.pattern(W.small(center=(11.3, 14.0), **base), O.prepare(W.small(center=(11.3, 14.0), **base)))
+    assert sym.max() > 0 and np.abs(sym - sym[::-1, :]).max() <= 1e-12 * sym.max()
+    for extra in (dict(center=(15.0, 14.0), tilt=10 * DEG), dict(center=(15.0, 14.3))):
+        wl = W.small(**base, **extra)
+        img = O.pattern(wl, O.prepare(wl))
+        assert np.abs(img - img[::-1, :]).max() > 1e-3 * img.max()
+
+
 def test_g_zero_reduces_to_plain_laue():
     """g -> 0: A = 1, N_eff = N_base, I_para = 1, and the pattern equals the one computed
     with the plain Laue kernel of size N_base."""
