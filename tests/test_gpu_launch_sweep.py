@@ -1,9 +1,11 @@
 """A seeded sweep of launch configurations through the C ABI: random small workloads (detector
 sizes, beam centres, cells, tilts, lineshapes, node grids) crossed with random tile shapes,
-waves per tile and, where the beam is centred, the mirror fold.  Every pattern is compared
-with the oracle at the pattern tolerances, and every folded pattern with its unfolded twin
-(same waves per tile) bit for bit; eight more cases compare the atom gradients of the
-hand-written adjoint with the oracle's."""
+waves per tile and, where the beam is centred, the mirror folds (left-right; up-down for a
+third of the cases, which are then made untilted and centred on the rows).  Every pattern is
+compared with the oracle at the pattern tolerances, and every folded pattern with its unfolded
+twin (same waves per tile): bit for bit under the left-right fold alone, the computed rows bit
+for bit and the rest to float32 rounding under the up-down one.  Eight more cases compare the
+atom gradients of the hand-written adjoint with the oracle's."""
 import dataclasses
 import math
 import sys
@@ -21,6 +23,7 @@ if not torch.cuda.is_available():
     pytest.skip("no GPU", allow_module_level=True)
 
 from paper_2608_23245_amd import Pipeline  # noqa: E402
+from paper_2608_23245_amd import binding as B  # noqa: E402
 
 DEG = math.pi / 180
 
@@ -50,7 +53,13 @@ def random_case(seed):
                  g=tuple(float(v) for v in rng.uniform(0.0, 0.04, 3)), n_nodes=int(rng.integers(6, 20)),
                  d_min=float(rng.uniform(4.0, 6.0)), tilt=float(rng.uniform(-30.0, 30.0)) * DEG, lineshape=ls)
     geom = dataclasses.replace(wl.geom, tile_w=tw, tile_waves=waves)
-    return dataclasses.replace(wl, geom=geom), fold
+    # drawn last, so that the earlier draws of every seed stay as they were
+    updown = bool(rng.integers(0, 3) == 0)
+    if updown:
+        th = 64 // tw
+        h = max(th, (height // th) * th)
+        geom = dataclasses.replace(geom, height=h, center_y=h / 2.0, tilt=0.0)
+    return dataclasses.replace(wl, geom=geom), int(fold) | (2 if updown else 0)
 
 
 @pytest.mark.parametrize("seed", range(40))
@@ -58,7 +67,7 @@ def test_random_launch_vs_oracle(seed):
     wl, fold = random_case(seed)
     g = wl.geom
     say(f"seed {seed}: {g.width}x{g.height}, centre ({g.center_x:.1f}, {g.center_y:.1f}), tile {g.tile_w} wide, "
-        f"waves {g.tile_waves}, fold {fold}, tilt {g.tilt / DEG:.0f} deg, lineshape {wl.dis.lineshape}")
+        f"waves {g.tile_waves}, mirror bits {fold}, tilt {g.tilt / DEG:.0f} deg, lineshape {wl.dis.lineshape}")
     pipe = Pipeline(wl)
     if pipe.n_hkl == 0:
         pytest.skip("empty reflection list")
@@ -72,9 +81,20 @@ def test_random_launch_vs_oracle(seed):
     say(f"  rel-L2 {r:.2e}, per-pixel {px:.2e}")
     assert r <= 1e-4 and px <= 1e-3
     if fold:
-        folded = Pipeline(dataclasses.replace(wl, geom=dataclasses.replace(g, mirror=1))).pattern()
+        # at the unfolded launch's waves per tile (the library's choice depends on the tile count)
+        fg = dataclasses.replace(g, mirror=fold, tile_waves=B.launch_waves(pipe.model.geom))
+        folded = Pipeline(dataclasses.replace(wl, geom=fg)).pattern()
         torch.cuda.synchronize()
-        assert torch.equal(folded, img)
+        if fold & 2:
+            th = 64 // g.tile_w
+            top = ((g.height // th + 1) // 2) * th
+            assert torch.equal(folded[:top], img[:top])
+            low = g.height - top
+            assert torch.equal(folded[g.height - low:], torch.flip(folded[:low], [0]))
+            a, b = folded.double().cpu().numpy(), img.double().cpu().numpy()
+            assert np.linalg.norm(a - b) <= 2e-6 * np.linalg.norm(b)
+        else:
+            assert torch.equal(folded, img)
 
 
 @pytest.mark.parametrize("seed", range(100, 108))
@@ -83,7 +103,7 @@ def test_random_launch_gradients_vs_oracle(seed):
     from paper_2608_23245_amd import binding as B
     wl, fold = random_case(seed)
     if fold:
-        wl = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, mirror=1))
+        wl = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, mirror=fold))
     g = wl.geom
     say(f"gradients seed {seed}: {g.width}x{g.height}, tile {g.tile_w} wide, waves {g.tile_waves}, "
         f"fold {fold}, lineshape {wl.dis.lineshape}")
