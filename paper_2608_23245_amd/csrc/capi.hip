@@ -139,8 +139,8 @@ extern "C" int fdtbx_last_hip_error(void) { return g_hip; }
 // library's choice.
 // The library's choice: a launch of a few rounds of one-wave workgroups (32 per compute unit)
 // ends with its longest tiles, so 4 waves share each tile up to eight rounds (measured best or
-// equal from one round, the folded medium workload, to eight, the unfolded large one); beyond
-// that, 2.
+// equal from half a round, the medium workload under both mirror folds, to eight, the unfolded
+// large one); beyond that, 2.
 int fdtbx::tile_waves(const fdtbx_geometry* g, int64_t n_tiles, int* waves) {
   if (g->tile_waves) {
     *waves = g->tile_waves;
