@@ -59,7 +59,8 @@ class Geometry:
     center_y: float
     tilt: float = 0.0      # fibre axis tilted by this angle (rad) about lab y, toward +x
     tile_w: int = 0        # pixel tile width of the GPU launches (0: 8 x 8 tiles); no effect on the pattern
-    mirror: int = 0        # 1: the GPU launches fold the left-right mirror (needs center_x = width/2)
+    mirror: int = 0        # GPU launch folds, bit 0: left-right (needs center_x = width/2); bit 1: up-down
+                           # (needs center_y = height/2 and tilt 0)
     tile_waves: int = 0    # waves per tile of the GPU profile launch (0: the library's choice)
 
 
