@@ -67,8 +67,9 @@ def with_tile_w(model: B.Model, tile_w: int) -> B.Model:
 
 
 def shape_allowed(geom: B.Geometry) -> bool:
-    """The library accepts this tile width for this geometry (under the mirror fold the
-    width must be a multiple of it)."""
+    """The library accepts this tile width for this geometry (under the left-right fold the
+    width must be a multiple of it, under the up-down fold the height a multiple of the tile
+    height 64 / tile_w)."""
     try:
         B.tile_grid(geom)
         return True
