@@ -7,9 +7,11 @@ product package.
 
 Plain, slow and written to be checked against the paper by eye: IEEE binary64
 throughout, numpy for elementwise arrays (numpy does not fuse multiply-adds),
-scipy.special.voigt_profile for the Voigt shape as the paper itself does, and
-a small C file (oracle_c.c, built with -ffp-contract=off) for the two
-per-pixel loops that are too slow in Python.
+scipy.special.voigt_profile for the Voigt shape as the paper itself does (and
+the Faddeeva function in mpmath's extended precision for its width
+derivatives), and a
+small C file (oracle_c.c, built with -ffp-contract=off) for the per-pixel
+loops that are too slow in Python.
 
 Steps, in the order of the method:
   frame             reciprocal basis            Eq. recip_basis, tutorial frame convention
@@ -30,6 +32,7 @@ import os
 import subprocess
 from dataclasses import dataclass
 
+import mpmath
 import numpy as np
 from scipy.special import voigt_profile
 
@@ -437,12 +440,54 @@ def threads() -> int:
     return int(_c().oracle_threads())
 
 
-def profile_table(P: Prepared, R, Z):
-    """Per-reflection shell-quadrature profiles I_hkl(p*) at each pixel, [n_pix][n_hkl]."""
+def set_threads(n: int) -> None:
+    """Set the OpenMP threads of the compiled oracle loops."""
+    _c().oracle_set_threads(ctypes.c_int(int(n)))
+
+
+def reachable(wl, hkl, R, Z):
+    """Ascending indices of the reflections of hkl (extinction cull already applied) whose
+    support can reach the query point of at least one pixel with ring coordinates (R, Z):
+    the complement of the exact skip of oracle_pattern, which needs no structure factors.
+    The pattern at those pixels over these reflections alone equals the pattern over all of
+    hkl bit for bit (same terms, same ascending order)."""
+    hkl = np.ascontiguousarray(hkl)
+    P = prepare(wl, hkl=hkl, F=np.zeros(hkl.shape[0], dtype=np.complex128), cull_extinct=False)
+    R = np.ascontiguousarray(np.ravel(R), dtype=np.float64)
+    Z = np.ascontiguousarray(np.ravel(Z), dtype=np.float64)
+    mask = np.zeros(hkl.shape[0], dtype=np.uint8)
+    prob, keep = _c_problem(P, True)
+    _c().oracle_reach(ctypes.byref(prob), ctypes.c_int64(R.shape[0]), ctypes.c_void_p(R.ctypes.data),
+                      ctypes.c_void_p(Z.ctypes.data), ctypes.c_void_p(mask.ctypes.data))
+    del keep
+    return np.nonzero(mask)[0]
+
+
+def pattern_sampled(wl, R, Z, hkl=None, count=False):
+    """The image at pixels with ring coordinates (R, Z) over the workload's whole reflection
+    list (extinction cull applied): the reachable reflections' structure factors from the
+    C loop, then oracle_pattern with its exact skip.  Returns (values, reflection indices
+    used, evaluations if count)."""
+    if hkl is None:
+        hkl = enumerate_hkl(wl.cell, wl.quad.d_min, wl.quad.d_max)
+        hkl = np.ascontiguousarray(hkl[~extinct_mask(hkl, wl.dis, wl.quad.extinction)])
+    sub = reachable(wl, hkl, R, Z)
+    hs = np.ascontiguousarray(hkl[sub])
+    P = prepare(wl, hkl=hs, F=structure_factors_c(hs, wl.cell, wl.atoms), cull_extinct=False)
+    res = pattern_at(P, R, Z, count=count)
+    if count:
+        return res[0], sub, res[1]
+    return res, sub
+
+
+def profile_table(P: Prepared, R, Z, use_skip=False):
+    """Per-reflection shell-quadrature profiles I_hkl(p*) at each pixel, [n_pix][n_hkl]
+    (with use_skip, 0 for the reflections the exact skip rules out, the value the profile
+    has there)."""
     R = np.ascontiguousarray(np.ravel(R), dtype=np.float64)
     Z = np.ascontiguousarray(np.ravel(Z), dtype=np.float64)
     out = np.zeros((R.shape[0], P.hkl.shape[0]))
-    prob, keep = _c_problem(P, False)
+    prob, keep = _c_problem(P, use_skip)
     _c().oracle_profile_table(ctypes.byref(prob), ctypes.c_int64(R.shape[0]), ctypes.c_void_p(R.ctypes.data),
                               ctypes.c_void_p(Z.ctypes.data), ctypes.c_void_p(out.ctypes.data))
     del keep
@@ -462,29 +507,60 @@ def pattern(wl, P: Prepared = None, use_skip=True, count=False):
 
 
 # --------------------------------------------------------------------------- adjoint
+def _voigt_width_derivs(delta, sigma, gamma, digits=50):
+    """(d g/d sigma, d g/d gamma) of the unit-peak Voigt g = Re w(z)/Re w(z0) at one angle,
+    z = (delta + i gamma)/(sigma sqrt 2), z0 = i gamma/(sigma sqrt 2), evaluated entirely in
+    mpmath with `digits` significant digits: w(z) = exp(-z^2) erfc(-i z), w'(z) = -2 z w(z) +
+    2 i/sqrt(pi), dz/dsigma = -z/sigma, dz/dgamma = i/(sigma sqrt 2), d Re w = Re(w' dz), and
+    the quotient rule.  Near the Lorentzian limit the quotient rule cancels terms of size sigma
+    to a result of size sigma^3, and w' cancels two terms of size 1 to |z|^-2; fifty digits keep
+    the result exact to double precision for sigma/gamma and |z|^-1 down to about 1e-15."""
+    with mpmath.workdps(digits):
+        s, g, d = mpmath.mpf(sigma), mpmath.mpf(gamma), mpmath.mpf(delta)
+        k = 1 / (s * mpmath.sqrt(2))
+        c = 2j / mpmath.sqrt(mpmath.pi)
+
+        def w_and_wp(z):
+            w = mpmath.exp(-z * z) * mpmath.erfc(-1j * z)
+            return w, -2 * z * w + c
+
+        z, z0 = mpmath.mpc(d * k, g * k), mpmath.mpc(0, g * k)
+        w, wp = w_and_wp(z)
+        w0, wp0 = w_and_wp(z0)
+        u, v = mpmath.re(w), mpmath.re(w0)
+        du_s, dv_s = mpmath.re(wp * (-z / s)), mpmath.re(wp0 * (-z0 / s))
+        du_g, dv_g = mpmath.re(wp * 1j * k), mpmath.re(wp0 * 1j * k)
+        return float((du_s * v - u * dv_s) / (v * v)), float((du_g * v - u * dv_g) / (v * v))
+
+
 def angular_shape_derivs(delta, sigma_theta, gamma_theta):
-    """d g/d sigma_theta and d g/d gamma_theta of the unit-peak angular weight, by
-    Richardson-extrapolated central differences of angular_shape (forward differences at a
-    width that is zero, where the Gaussian or Lorentzian branch is the boundary value)."""
+    """d g/d sigma_theta and d g/d gamma_theta of the unit-peak angular weight (section
+    "Angular peak shapes"), in closed form.
+
+    Voigt: g = Re w(z)/Re w(z0) with z = (delta + i gamma)/(sigma sqrt 2), z0 = i gamma/(sigma
+    sqrt 2) and w the Faddeeva function, whose derivative is w'(z) = -2 z w(z) + 2 i/sqrt(pi);
+    dz/dsigma = -z/sigma and dz/dgamma = i/(sigma sqrt 2), so d Re w(z) = Re(w'(z) dz), and the
+    quotient rule gives both derivatives (in extended precision, _voigt_width_derivs).
+    Gaussian (gamma = 0): dg/dsigma = g delta^2/sigma^3; dg/dgamma is the one-sided derivative
+    of the Voigt at gamma = 0+, the Voigt formula above evaluated at gamma = 0.
+    Lorentzian (sigma = 0): dg/dgamma = 2 gamma delta^2/(delta^2 + gamma^2)^2; the Voigt is a
+    smooth function of sigma^2 (the Lorentzian convolved with a Gaussian of variance sigma^2),
+    so dg/dsigma = 0 there."""
     delta = np.asarray(delta, dtype=np.float64)
-
-    def d_dwidth(which):
-        base = sigma_theta if which == 0 else gamma_theta
-        scale = max(sigma_theta, gamma_theta)
-
-        def g(v):
-            return angular_shape(delta, v, gamma_theta) if which == 0 else angular_shape(delta, sigma_theta, v)
-
-        if base > 0.0:
-            def D(h):
-                return (g(base + h) - g(base - h)) / (2.0 * h)
-            h = 1e-3 * base
-            return (4.0 * D(h / 2) - D(h)) / 3.0
-        # one-sided at zero width: second-order forward difference
-        h = 1e-6 * scale
-        return (-3.0 * g(0.0) + 4.0 * g(h) - g(2.0 * h)) / (2.0 * h)
-
-    return d_dwidth(0), d_dwidth(1)
+    s, g = float(sigma_theta), float(gamma_theta)
+    if s == 0.0 and g == 0.0:
+        raise ValueError("sigma_theta and gamma_theta are both zero")
+    if s == 0.0:
+        den = delta * delta + g * g
+        return np.zeros_like(delta), 2.0 * g * delta * delta / (den * den)
+    vals, inverse = np.unique(delta.ravel(), return_inverse=True)   # node angles repeat by symmetry
+    d = np.array([_voigt_width_derivs(x, s, g) for x in vals])
+    d_sigma = d[:, 0][inverse].reshape(delta.shape)
+    d_gamma = d[:, 1][inverse].reshape(delta.shape)
+    if g == 0.0:
+        gau = np.exp(-delta * delta / (2.0 * s * s))
+        return gau * delta * delta / (s * s * s), d_gamma
+    return d_sigma, d_gamma
 
 
 def node_weight_derivs(nodes: Nodes, sigma_r, sigma_theta, gamma_theta):
@@ -577,7 +653,9 @@ def gradients(wl, P: Prepared, G, R=None, Z=None, use_skip=True):
     for i in range(3):
         ahat = avec[i] / np.linalg.norm(avec[i])
         d_B[i] = np.sum(dW * P.W * (-0.25) * (P.D @ ahat) ** 2)
-    atom = sf_adjoint(P.hkl, wl.cell, wl.atoms, P.F, dW * P.Ip * Dw)
+    # reflections with dL/dW = 0 add nothing to the atom sums
+    nz = np.nonzero(dW)[0]
+    atom = sf_adjoint(np.ascontiguousarray(P.hkl[nz]), wl.cell, wl.atoms, P.F[nz], (dW * P.Ip * Dw)[nz])
     return {"atoms": atom, "sigma_theta": d_sigma, "gamma_theta": d_gamma, "N_base": d_Nbase, "g": d_g,
             "B_axis": d_B, "dW": dW, "sums": sums}
 

@@ -194,15 +194,35 @@ void oracle_pattern(const oracle_problem* P, int64_t n_pix, const double* R, con
   if (n_evals) *n_evals = total;
 }
 
+/* Reflections whose support can reach the query point of at least one of n_pix pixels:
+ * reach[h] = 1 unless provably_empty holds for every listed pixel.  Every other reflection
+ * adds exactly nothing to oracle_pattern at those pixels, so the pattern over the reachable
+ * reflections alone is bit-identical to the pattern over all of them. */
+void oracle_reach(const oracle_problem* P, int64_t n_pix, const double* R, const double* Z, unsigned char* reach) {
+  double theta_nodes = nodes_max_angle(P);
+#pragma omp parallel for schedule(dynamic, 256)
+  for (int64_t h = 0; h < P->n_hkl; ++h) {
+    unsigned char any = 0;
+    for (int64_t q = 0; q < n_pix && !any; ++q) {
+      double p[3];
+      query_point(P, h, R[q], Z[q], p);
+      if (!provably_empty(P, h, p, theta_nodes)) any = 1;
+    }
+    reach[h] = any;
+  }
+}
+
 /* Per-reflection profile values at each pixel, [n_pix][n_hkl] (no W, no Lorentz):
- * used by tests that check the culling lists and the per-reflection adjoint. */
+ * used by tests that check the culling lists and the per-reflection adjoint.  With use_skip,
+ * the reflections the exact skip rules out hold 0 (which profile_at would return too). */
 void oracle_profile_table(const oracle_problem* P, int64_t n_pix, const double* R, const double* Z, double* out) {
+  double theta_nodes = nodes_max_angle(P);
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t q = 0; q < n_pix; ++q) {
     for (int64_t h = 0; h < P->n_hkl; ++h) {
       double p[3];
       query_point(P, h, R[q], Z[q], p);
-      out[q * P->n_hkl + h] = profile_at(P, h, p, NULL);
+      out[q * P->n_hkl + h] = (P->use_skip && provably_empty(P, h, p, theta_nodes)) ? 0.0 : profile_at(P, h, p, NULL);
     }
   }
 }
@@ -447,6 +467,8 @@ void oracle_cyl(const oracle_problem* P, int64_t n_pix, const double* R, const d
   if (n_evals) *n_evals = total;
 }
 
-/* Threads the OpenMP loops above use. */
+/* Threads the OpenMP loops above use, and a way to set them (the CPU baseline times the
+ * oracle on one core and on all cores). */
 #include <omp.h>
 int oracle_threads(void) { return omp_get_max_threads(); }
+void oracle_set_threads(int n) { omp_set_num_threads(n); }

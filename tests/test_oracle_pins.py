@@ -338,6 +338,86 @@ def test_voigt_is_normalised_convolution():
         assert abs(O.angular_shape(x, s, gm) - conv(x) / c0) < 1e-7
 
 
+def _richardson(f, x0, h):
+    """Richardson-extrapolated central difference of f at x0 (error O(h^4))."""
+    D = lambda hh: (f(x0 + hh) - f(x0 - hh)) / (2.0 * hh)
+    return (4.0 * D(h / 2) - D(h)) / 3.0
+
+
+@pytest.mark.parametrize("sig_deg,eta", [(3.0, 1e-6), (3.0, 1e-3), (3.0, 0.5), (3.0, 1 - 1e-3), (3.0, 1 - 1e-6),
+                                         (1.0, 0.2), (8.0, 0.9)])
+def test_angular_shape_width_derivatives_match_differences(sig_deg, eta):
+    """The closed-form width derivatives (through the Faddeeva function's derivative) agree
+    with Richardson differences of the unit-peak Voigt itself (scipy's voigt_profile, a
+    different routine) at every angle of a node patch."""
+    st, gt = (1 - eta) * sig_deg * DEG, eta * sig_deg * DEG
+    x = np.linspace(0.0, 12 * sig_deg * DEG, 41)
+    ds, dg = O.angular_shape_derivs(x, st, gt)
+    # steps on the scale of the wider width (the shape varies on that scale), kept inside (0, width)
+    width = max(st, gt)
+    fs = _richardson(lambda v: O.angular_shape(x, v, gt), st, min(1e-3 * width, 0.5 * st))
+    fg = _richardson(lambda v: O.angular_shape(x, st, v), gt, min(1e-3 * width, 0.5 * gt))
+    scale = 1.0 / max(st, gt)      # derivatives of a unit-peak shape are O(1/width)
+    np.testing.assert_allclose(ds, fs, rtol=1e-7, atol=1e-9 * scale)
+    np.testing.assert_allclose(dg, fg, rtol=1e-7, atol=1e-9 * scale)
+
+
+def test_angular_shape_width_derivatives_at_the_gaussian_and_lorentzian_limits():
+    """Continuity of the derivatives across the branch points eta = 0 and eta = 1, and the
+    one-sided gamma derivative of the Gaussian written with Dawson's integral F:
+    d g/d gamma at gamma = 0+ = (2/sqrt(pi)) (2 x F(x) - 1 + exp(-x^2))/(sigma sqrt 2),
+    x = delta/(sigma sqrt 2) (from w(x) = exp(-x^2) + (2i/sqrt(pi)) F(x) on the real axis and
+    erfcx'(0) = -2/sqrt(pi))."""
+    s = 3 * DEG
+    x = np.linspace(0.0, 14 * s, 57)
+    ds0, dg0 = O.angular_shape_derivs(x, s, 0.0)
+    xx = x / (s * math.sqrt(2.0))
+    closed = (2 / math.sqrt(math.pi)) * (2 * xx * special.dawsn(xx) - 1 + np.exp(-xx * xx)) / (s * math.sqrt(2.0))
+    np.testing.assert_allclose(dg0, closed, rtol=1e-10, atol=1e-12 / s)
+    np.testing.assert_allclose(ds0, np.exp(-xx * xx) * x * x / s ** 3, rtol=1e-13, atol=0)
+    # the Voigt branch just above gamma = 0 tends to both
+    ds1, dg1 = O.angular_shape_derivs(x, s, 1e-9 * s)
+    np.testing.assert_allclose(ds1, ds0, rtol=1e-6, atol=1e-6 / s)
+    np.testing.assert_allclose(dg1, dg0, rtol=1e-6, atol=1e-6 / s)
+    # one-sided difference of the shape at gamma = 0 (second order)
+    h = 1e-6 * s
+    fd = (-3 * O.angular_shape(x, s, 0.0) + 4 * O.angular_shape(x, s, h) - O.angular_shape(x, s, 2 * h)) / (2 * h)
+    np.testing.assert_allclose(dg0, fd, rtol=1e-5, atol=1e-5 / s)
+    # sigma -> 0: the Lorentzian's gamma derivative, and a sigma derivative that vanishes like sigma
+    gm = 2 * DEG
+    x = np.linspace(0.0, 14 * gm, 57)
+    dsL, dgL = O.angular_shape_derivs(x, 0.0, gm)
+    np.testing.assert_allclose(dgL, 2 * gm * x * x / (x * x + gm * gm) ** 2, rtol=1e-14, atol=0)
+    assert np.all(dsL == 0.0)
+    for eps in (1e-4, 1e-6):
+        dsV, dgV = O.angular_shape_derivs(x, eps * gm, gm)
+        np.testing.assert_allclose(dgV, dgL, rtol=0, atol=10 * eps / gm)
+        assert np.max(np.abs(dsV)) < 10 * eps / gm
+
+
+@pytest.mark.parametrize("eta", [0.5, 1 - 1e-3, 1 - 1e-6])
+def test_voigt_sigma_derivative_follows_the_heat_equation(eta):
+    """The Voigt is a Lorentzian convolved with a Gaussian of variance sigma^2, and a Gaussian
+    kernel obeys dG/dsigma = sigma d^2G/dt^2, so dV/dsigma = sigma V''(x) and the unit-peak
+    shape has dg/dsigma = sigma (V''(x) V(0) - V(x) V''(0))/V(0)^2.  V'' by Richardson second
+    differences of scipy's voigt_profile in x: an independent route to the sigma derivative
+    that stays accurate next to the Lorentzian limit, where the derivative is of size sigma."""
+    sig = 3 * DEG
+    st, gt = (1 - eta) * sig, eta * sig
+    x = np.linspace(0.0, 10 * sig, 21)
+    V = lambda t: special.voigt_profile(t, st, gt)
+    h = 1e-2 * min(gt, max(st, 1e-3 * gt)) if eta < 1 - 1e-4 else 1e-3 * gt
+
+    def Vxx(t):
+        d2 = lambda hh: (V(t + hh) - 2 * V(t) + V(t - hh)) / (hh * hh)
+        return (4 * d2(h / 2) - d2(h)) / 3
+
+    ref = st * (Vxx(x) * V(0.0) - V(x) * Vxx(0.0)) / V(0.0) ** 2
+    ds, _ = O.angular_shape_derivs(x, st, gt)
+    big = np.abs(ref).max()
+    np.testing.assert_allclose(ds, ref, rtol=2e-5, atol=2e-5 * big)
+
+
 # ----------------------------------------------------------------------------- nodes
 def test_node_solid_angle_converges_to_gnomonic_square():
     """With g = 1 the node weights sum to the solid angle of the gnomonic square
