@@ -18,7 +18,7 @@ namespace fdtbx {
 // Hosemann: Z' (c_i (1 + A_i^2) - 2 A_i)/den_i with c_i = cos(2 pi y_i) (0 where A_i is held at 0).
 template <int LS>
 __device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, float al0, float al1, float al2, float gp,
-                                              float half_m, float tiny, const HoseK& hk, float* acc) {
+                                              float half_m, const HoseK& hk, float* acc) {
   float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
   float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
   if (mx <= half_m) {
@@ -50,9 +50,11 @@ __device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, 
       acc[4] = fmaf(t2 * (da * dc), fmaf(cb, hk.e0[1], -hk.e1[1]), acc[4]);
       acc[5] = fmaf(t2 * dab, fmaf(cc, hk.e0[2], -hk.e1[2]), acc[5]);
     } else {
-      ya = fabsf(ya) + tiny;
-      yb = fabsf(yb) + tiny;
-      yc = fabsf(yc) + tiny;
+      // no y is 0 (tag_alpha, tag_kappa); every factor below is even in its y, and |y| keeps
+      // the hardware sine and cosine on positive arguments as in the forward
+      ya = fabsf(ya);
+      yb = fabsf(yb);
+      yc = fabsf(yc);
       const float sa = __builtin_amdgcn_sinf(ya), sb = __builtin_amdgcn_sinf(yb), sc = __builtin_amdgcn_sinf(yc);
       const float ca = __builtin_amdgcn_cosf(ya), cb = __builtin_amdgcn_cosf(yb), cc = __builtin_amdgcn_cosf(yc);
       const float yab = ya * yb;
@@ -81,7 +83,7 @@ __device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, 
 // registers and the unrolled reads use instruction offsets.
 template <int LS>
 __device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* qd, int cnt, const float* al, float gp,
-                                               float half_m, float tiny, const HoseK& hk, float* acc) {
+                                               float half_m, const HoseK& hk, float* acc) {
   qn += threadIdx.y;
   qd += threadIdx.y;
   float4 nxt = qn[0];
@@ -91,7 +93,7 @@ __device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* q
     const float2 cur2 = nxt2;
     nxt = qn[jj + 1];
     nxt2 = qd[jj + 1];
-    eval_node_adj<LS>(cur, cur2, al[0], al[1], al[2], gp, half_m, tiny, hk, acc);
+    eval_node_adj<LS>(cur, cur2, al[0], al[1], al[2], gp, half_m, hk, acc);
   }
 }
 
@@ -148,6 +150,7 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         al[a] = fmaf(f.at(RS_TR + a), dR, f.at(RS_TZ + a) * dZ);
+        if (LS == FDTBX_LINESHAPE_LAUE) al[a] = tag_alpha(al[a]);
         lo[a] = lane_float(lol[a], src);
         hi[a] = lane_float(hil[a], src);
         Bv[a] = f.at(RS_B + a);
@@ -162,13 +165,13 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
         const unsigned long long b = __ballot(keep);
         if (keep) {
           const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
-          qn[pos] = e;
+          qn[pos] = LS == FDTBX_LINESHAPE_LAUE ? tag_kappa4(e) : e;
           qd[pos] = *(const float2*)(nodes + (int64_t)FDTBX_NODE_FLOATS * k + 4);
         }
         qlen += __popcll(b);
         wave_sync();
         if (qlen >= 64) {
-          walk_queue_adj<LS>(qn, qd, 64, al, gp, q.half_m, q.tiny, hk, acc);
+          walk_queue_adj<LS>(qn, qd, 64, al, gp, q.half_m, hk, acc);
           qlen -= 64;
           wave_sync();
           if (lane < qlen) {
@@ -178,7 +181,7 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
           wave_sync();
         }
       });
-      walk_queue_adj<LS>(qn, qd, qlen, al, gp, q.half_m, q.tiny, hk, acc);
+      walk_queue_adj<LS>(qn, qd, qlen, al, gp, q.half_m, hk, acc);
       wave_sync();
       bool any = false;
 #pragma unroll

@@ -34,7 +34,7 @@ constexpr int kJB = 8;
 
 // The queue walk of walk_queue, each entry evaluated at the lane's kJB ring points.
 template <bool COUNT, int LS>
-__device__ __forceinline__ void walk_ring(const float4* qn, int cnt, const float (*al)[3], float half_m, float tiny,
+__device__ __forceinline__ void walk_ring(const float4* qn, int cnt, const float (*al)[3], float half_m,
                                           const HoseK& hk, float& accr, unsigned long long& cnt_eval) {
   qn += threadIdx.y;
   float4 nxt = qn[0];
@@ -43,7 +43,7 @@ __device__ __forceinline__ void walk_ring(const float4* qn, int cnt, const float
     const float4 cur = nxt;
     nxt = qn[jj + 1];
 #pragma unroll
-    for (int u = 0; u < kJB; ++u) eval_node<COUNT, LS>(cur, al[u][0], al[u][1], al[u][2], half_m, tiny, hk, part, cnt_eval);
+    for (int u = 0; u < kJB; ++u) eval_node<COUNT, LS>(cur, al[u][0], al[u][1], al[u][2], half_m, hk, part, cnt_eval);
   }
   accr += part;
 }
@@ -158,7 +158,7 @@ __global__ void __launch_bounds__(64 * WAVES) k_cyl(CylParams p, const float* __
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
           const float v = fmaf(tr[a], fX, fmaf(ta[a], fY, tz[a] * fZ));
-          al[u][a] = act ? v : 1.0e30f;
+          al[u][a] = act ? (LS == FDTBX_LINESHAPE_LAUE ? tag_alpha(v) : v) : 1.0e30f;
           amin[a] = act ? fminf(amin[a], v) : amin[a];
           amax[a] = act ? fmaxf(amax[a], v) : amax[a];
           pmin[a] = act ? fminf(pmin[a], pv[a]) : pmin[a];
@@ -190,19 +190,19 @@ __global__ void __launch_bounds__(64 * WAVES) k_cyl(CylParams p, const float* __
           const unsigned long long bal = __ballot(keep);
           if (keep) {
             const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-            qn[pos] = e;
+            qn[pos] = LS == FDTBX_LINESHAPE_LAUE ? tag_kappa4(e) : e;
           }
           qlen += __popcll(bal);
           wave_sync();
           if (qlen >= 64) {
-            walk_ring<COUNT, LS>(qn, 64, al, q.half_m, q.tiny, hk, accr, cnt);
+            walk_ring<COUNT, LS>(qn, 64, al, q.half_m, hk, accr, cnt);
             qlen -= 64;
             wave_sync();
             if (lane < qlen) qn[lane] = qn[64 + lane];
             wave_sync();
           }
         });
-        walk_ring<COUNT, LS>(qn, qlen, al, q.half_m, q.tiny, hk, accr, cnt);
+        walk_ring<COUNT, LS>(qn, qlen, al, q.half_m, hk, accr, cnt);
         wave_sync();
         accp += accr;
       }

@@ -6,7 +6,11 @@
 //   w(z) = 2 p(Z)/(L - i z)^2 + (1/sqrt(pi))/(L - i z),   Z = (L + i z)/(L - i z),
 //   p(Z) = sum_{n=0}^{N-1} a_{n+1} Z^n,  L = sqrt(N/sqrt(2)),
 // where a_n are the Fourier coefficients of f(theta) = exp(-t^2)(L^2 + t^2),
-// t = L tan(theta/2), obtained with the trapezoid rule on 4N points.
+// t = L tan(theta/2), obtained with the trapezoid rule on 4N points.  Its derivative is
+// taken from the same rational form, with D = L - i z and dZ/dz = 2 i L/D^2:
+//   w'(z) = 4 i L p'(Z)/D^4 + 4 i p(Z)/D^3 + (i/sqrt(pi))/D^2.
+// (The identity w' = -2 z w + 2 i/sqrt(pi) cancels two terms of size 1 down to the
+// 1/z^2 of w' itself and loses about 2 log10|z| digits, a few per cent at |z| = 1e7.)
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -15,7 +19,7 @@
 
 namespace fdtbx {
 
-static constexpr int kWN = 40;  // series length (relative error ~1e-13 for Im z >= 0.1)
+static constexpr int kWN = 40;  // series length (relative error of w and w' below 1e-13 on Im z >= 0)
 
 struct cplx {
   double re, im;
@@ -39,26 +43,59 @@ __device__ static double weideman_coef(int n, double L) {
   return sum / M2;  // the theta = -pi sample has f = 0
 }
 
-__device__ static cplx faddeeva(cplx z, const double* coef, double L) {
+// w(z) and w'(z) (Im z >= 0).
+__device__ static void faddeeva(cplx z, const double* coef, double L, cplx* w, cplx* wp) {
   cplx iz = {-z.im, z.re};
-  cplx den = {L - iz.re, -iz.im};          // L - i z
+  cplx den = {L - iz.re, -iz.im};          // D = L - i z
   cplx num = {L + iz.re, iz.im};           // L + i z
   cplx Z = cdiv(num, den);
-  cplx p = {coef[kWN - 1], 0.0};
+  cplx p = {coef[kWN - 1], 0.0}, dp = {0.0, 0.0};
   for (int n = kWN - 2; n >= 0; --n) {
+    dp = cmul(dp, Z);
+    dp.re += p.re;
+    dp.im += p.im;
     p = cmul(p, Z);
     p.re += coef[n];
   }
-  cplx d2 = cmul(den, den);
-  cplx a = cdiv({2.0 * p.re, 2.0 * p.im}, d2);
-  cplx b = cdiv({1.0 / sqrt(M_PI), 0.0}, den);
-  return {a.re + b.re, a.im + b.im};
+  const double c = 1.0 / sqrt(M_PI);
+  cplx inv = cdiv({1.0, 0.0}, den);        // 1/D
+  cplx inv2 = cmul(inv, inv), inv3 = cmul(inv2, inv), inv4 = cmul(inv2, inv2);
+  cplx a = cmul({2.0 * p.re, 2.0 * p.im}, inv2);
+  *w = {a.re + c * inv.re, a.im + c * inv.im};
+  // i * (4 L p' D^-4 + 4 p D^-3 + c D^-2)
+  cplx t1 = cmul({4.0 * L * dp.re, 4.0 * L * dp.im}, inv4);
+  cplx t2 = cmul({4.0 * p.re, 4.0 * p.im}, inv3);
+  cplx sum = {t1.re + t2.re + c * inv2.re, t1.im + t2.im + c * inv2.im};
+  *wp = {-sum.im, sum.re};
 }
 
-// w'(z) = -2 z w(z) + 2 i/sqrt(pi)
-__device__ static inline cplx faddeeva_deriv(cplx z, cplx w) {
-  cplx zw = cmul(z, w);
-  return {-2.0 * zw.re, -2.0 * zw.im + 2.0 / sqrt(M_PI)};
+// E(z) = d(z w(z))/dz = w(z) + z w'(z) (Im z >= 0).  For |z| < 10 from the rational form
+// (the two terms cancel to the |z|^-2 of their size there, two digits at most); for |z| >= 10
+// from the asymptotic series of z w(z) = (i/sqrt(pi)) sum_n a_n z^-2n, a_n = (2n-1)!!/2^n:
+//   E(z) = -(i/sqrt(pi)) sum_{n>=1} 2 n a_n z^-(2n+1),
+// summed until a term falls below 1e-18 of the sum (the terms shrink by about (2n+1)/(2|z|^2)).
+__device__ static cplx faddeeva_E(cplx z, cplx w, cplx wp) {
+  const double r2 = z.re * z.re + z.im * z.im;
+  if (r2 < 100.0) {
+    const cplx zw = cmul(z, wp);
+    return {w.re + zw.re, w.im + zw.im};
+  }
+  const cplx zi = {z.re / r2, -z.im / r2};   // 1/z
+  const cplx zi2 = cmul(zi, zi);
+  cplx pw = cmul(zi2, zi);                   // z^-3
+  cplx sum = pw;                             // n = 1: 2 * 1 * a_1 = 1
+  double an = 0.5;
+  for (int n = 2; n < 60; ++n) {
+    an *= 0.5 * (2 * n - 1);
+    pw = cmul(pw, zi2);
+    const double c = 2.0 * n * an;
+    const cplx t = {c * pw.re, c * pw.im};
+    sum.re += t.re;
+    sum.im += t.im;
+    if (t.re * t.re + t.im * t.im < 1e-36 * (sum.re * sum.re + sum.im * sum.im)) break;
+  }
+  const double q = 1.0 / sqrt(M_PI);
+  return {q * sum.im, -q * sum.re};          // -(i q) sum
 }
 
 struct NodeParams {
@@ -69,6 +106,12 @@ struct NodeParams {
 // g and its derivatives with respect to sigma_theta and gamma_theta at angle D.
 // gamma = 0: Gaussian value; the gamma derivative is the one-sided derivative of the
 // Voigt at gamma = 0+.  sigma = 0: Lorentzian; its sigma derivative vanishes.
+// Voigt, with u = Re w(z), v = Re w(z0), z = (D + i gamma) k, z0 = i gamma k, k = 1/(sigma sqrt 2):
+// dz/dsigma = -z/sigma, so du/dsigma = -Re(z w'(z))/sigma = (u - Re E(z))/sigma and likewise for
+// v; the quotient rule's u v terms cancel exactly, leaving
+//   dg/dsigma = -(v Re E(z) - u Re E(z0))/(sigma v^2),
+// which keeps its accuracy near the Lorentzian limit, where the quotient rule written with
+// Re(z w') cancels two terms of size sigma to a result of size sigma^3.
 __device__ static void shape(double D, double s, double g, const double* coef, double L, double* val, double* ds,
                              double* dg) {
   if (s == 0.0) {
@@ -82,12 +125,11 @@ __device__ static void shape(double D, double s, double g, const double* coef, d
   double k = 1.0 / (s * sq2);
   cplx z = {D * k, g * k};
   cplx z0 = {0.0, g * k};
-  cplx w = faddeeva(z, coef, L), w0 = faddeeva(z0, coef, L);
-  cplx wp = faddeeva_deriv(z, w), wp0 = faddeeva_deriv(z0, w0);
-  // d z/d sigma = -z/sigma, d z/d gamma = i k
+  cplx w, w0, wp, wp0;
+  faddeeva(z, coef, L, &w, &wp);
+  faddeeva(z0, coef, L, &w0, &wp0);
+  // d z/d gamma = i k
   double u = w.re, v = w0.re;
-  double du_s = -(wp.re * z.re - wp.im * z.im) / s;
-  double dv_s = -(wp0.re * z0.re - wp0.im * z0.im) / s;
   double du_g = -wp.im * k;
   double dv_g = -wp0.im * k;
   if (g == 0.0) {
@@ -96,7 +138,8 @@ __device__ static void shape(double D, double s, double g, const double* coef, d
     *ds = *val * t * t / s;
   } else {
     *val = u / v;
-    *ds = (du_s * v - u * dv_s) / (v * v);
+    const cplx E = faddeeva_E(z, w, wp), E0 = faddeeva_E(z0, w0, wp0);
+    *ds = -(v * E.re - u * E0.re) / (s * v * v);
   }
   *dg = (du_g * v - u * dv_g) / (v * v);
 }

@@ -42,6 +42,7 @@ __global__ void __launch_bounds__(256) k_profile_points(PointParams p, const int
   for (int i = 0; i < 3; ++i) {
     const double sc = LS == FDTBX_LINESHAPE_HOSEMANN ? 1.0 : 0.5 * (double)rec[RS_N + i];
     al[i] = (float)(sc * dotv(&p.f.a[3 * i], x));
+    if (LS == FDTBX_LINESHAPE_LAUE) al[i] = tag_alpha(al[i]);
     Bv[i] = rec[RS_B + i];
     G1[i] = rec[RS_G1 + i];
     G2[i] = rec[RS_G2 + i];
@@ -64,7 +65,8 @@ __global__ void __launch_bounds__(256) k_profile_points(PointParams p, const int
       e.y = fmaf(nd.x, Bv[1], fmaf(nd.y, G1[1], nd.z * G2[1]));
       e.z = fmaf(nd.x, Bv[2], fmaf(nd.y, G1[2], nd.z * G2[2]));
       e.w = nd.w;
-      eval_node<false, LS>(e, al[0], al[1], al[2], q.half_m, q.tiny, hk, acc, cnt);
+      if (LS == FDTBX_LINESHAPE_LAUE) e = tag_kappa4(e);
+      eval_node<false, LS>(e, al[0], al[1], al[2], q.half_m, hk, acc, cnt);
     }
   }
   out[k] = rec[RS_WK] * acc;

@@ -22,7 +22,6 @@ struct ProfParams {
   float T, inv_h;   // grid half extent, 1/spacing
   float half_m;     // support half-width in y (lineshape_half)
   float cmin;       // (1 + 2T^2)^(-1/2)
-  float tiny;       // added to |y|: keeps sin(2 pi y)/y finite at y = 0, exact in float32 for |y| > 1e-5
   float margin;     // slack of the tile-level node test, in y units
   double delta;     // Lorentz regulariser
   int32_t sbw;      // superblocks per tile row in the XCD-aware tile order; 0: plain order
@@ -356,7 +355,6 @@ __host__ __device__ inline void prof_params(const fdtbx_model* model, ProfParams
   q->lineshape = model->dis.lineshape;
   q->half_m = (float)lineshape_half(model->dis.lineshape, model->quad.m);
   q->cmin = (float)(1.0 / sqrt(1.0 + 2.0 * model->quad.T * model->quad.T));
-  q->tiny = 1.0e-12f;
   q->margin = 1.0e-3f;
   q->delta = model->quad.delta;
   q->sbw = superblocks_per_row(q->lcols, q->lrows);

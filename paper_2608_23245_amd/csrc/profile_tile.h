@@ -29,14 +29,36 @@ __device__ __forceinline__ void hose_constants(const float* rec, HoseK& h) {
 // exp(-4 pi s) = exp2(kGauss s)
 constexpr float kGauss = -18.129440567308775f;
 
+// Laue lattice offsets y = alpha - kappa without a zero.  The pixel's alpha gets a last
+// mantissa bit of 1 and a magnitude clamped to [2^-18, 2^30] (tag_alpha); the node's kappa
+// gets a last mantissa bit of 0 (tag_kappa, a zero stays a zero).  Then alpha != kappa: if
+// |kappa| >= 2^-18 the two floats differ in their last bit within one binade or in their
+// binade, and if |kappa| < 2^-18 they differ in magnitude.  So y, an exactly rounded
+// difference, is not 0 and sin(2 pi y)/y needs no guard; |y| >= 2^-42 (the spacing of floats
+// just below 2^-18), so the product of three y stays a normal float.  Both tags are odd
+// functions of their argument (a Friedel mate, whose alpha and kappa are exact negatives,
+// gets exactly negated offsets), except for the sign that a zero alpha takes, which is rare.
+// They move a value by at most one unit in its last place, alpha by less than 2^-18 near
+// zero (where sin(2 pi y)/y is flat); the upper clamp turns the far-away alpha of lanes
+// outside the detector into a finite value outside every support.
+__device__ __forceinline__ float tag_alpha(float v) {
+  const float a = __builtin_amdgcn_fmed3f(fabsf(v), 0x1p-18f, 0x1p30f);
+  return copysignf(__int_as_float(__float_as_int(a) | 1), v);
+}
+__device__ __forceinline__ float tag_kappa(float v) { return __int_as_float(__float_as_int(v) & ~1); }
+__device__ __forceinline__ float4 tag_kappa4(float4 e) {
+  return make_float4(tag_kappa(e.x), tag_kappa(e.y), tag_kappa(e.z), e.w);
+}
+
 // Per-lane evaluation of one queued node: returns omega times the lineshape's profile
 // product (without its per-reflection constant) if the node is inside this pixel's support,
 // else 0 (and counts it in COUNT mode).
-//   Laue:     (prod_i sin(2 pi y_i)/y_i)^2      (y_i = N_i u_i/2)
+//   Laue:     (prod_i sin(2 pi y_i)/y_i)^2      (y_i = N_i u_i/2; al from tag_alpha and
+//                                                nd from tag_kappa, so no y_i is 0)
 //   Gaussian: exp(-4 pi sum_i y_i^2)            (y_i = N_i u_i/2)
 //   Hosemann: 1/prod_i (c0_i - c1_i cos(2 pi y_i))   (y_i = u_i)
 template <bool COUNT, int LS>
-__device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1, float al2, float half_m, float tiny,
+__device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1, float al2, float half_m,
                                           const HoseK& hk, float& accr, unsigned long long& cnt) {
   float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
   float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
@@ -52,9 +74,12 @@ __device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1,
       const float dc = fmaf(-hk.c1[2], __builtin_amdgcn_cosf(yc), hk.c0[2]);
       accr = fmaf(nd.w, __builtin_amdgcn_rcpf(da * db * dc), accr);
     } else {
-      ya = fabsf(ya) + tiny;
-      yb = fabsf(yb) + tiny;
-      yc = fabsf(yc) + tiny;
+      // |y| throughout (free input modifiers): the hardware sine of a negative argument in
+      // turns is reduced from another fraction, so sin(-y) = -sin(y) need not hold to the last
+      // bit; with |y| a reflection and its Friedel mate give bit-identical terms
+      ya = fabsf(ya);
+      yb = fabsf(yb);
+      yc = fabsf(yc);
       const float num = __builtin_amdgcn_sinf(ya) * __builtin_amdgcn_sinf(yb) * __builtin_amdgcn_sinf(yc);
       const float rr = num * __builtin_amdgcn_rcpf(ya * yb * yc);
       accr = fmaf(nd.w, rr * rr, accr);
@@ -69,7 +94,7 @@ __device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1,
 // keeps its address in a vector register; the unrolled reads then use instruction offsets
 // instead of moving a scalar loop counter into a vector register for every entry.
 template <bool COUNT, int LS>
-__device__ __forceinline__ void walk_queue(const float4* qn, int cnt, const float* al, float half_m, float tiny,
+__device__ __forceinline__ void walk_queue(const float4* qn, int cnt, const float* al, float half_m,
                                            const HoseK& hk, float& accr, unsigned long long& cnt_eval) {
   qn += threadIdx.y;
   float4 nxt = qn[0];
@@ -77,7 +102,7 @@ __device__ __forceinline__ void walk_queue(const float4* qn, int cnt, const floa
   for (int jj = 0; jj < cnt; ++jj) {
     const float4 cur = nxt;
     nxt = qn[jj + 1];
-    eval_node<COUNT, LS>(cur, al[0], al[1], al[2], half_m, tiny, hk, part, cnt_eval);
+    eval_node<COUNT, LS>(cur, al[0], al[1], al[2], half_m, hk, part, cnt_eval);
   }
   accr += part;
 }
@@ -106,7 +131,6 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
   const TileBox box = {tile[8 * (int64_t)t + 0], tile[8 * (int64_t)t + 1], tile[8 * (int64_t)t + 2],
                        tile[8 * (int64_t)t + 3]};
   const int64_t p0 = offsets[t], p1 = offsets[t + 1];
-  const float tiny = q.tiny;
   float acc = 0.0f;
   unsigned long long cnt = 0;
   // 64 pairs at a time: each lane sets up one pair (window and alpha box); the wave then
@@ -134,6 +158,7 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
         al[a] = fmaf(f.at(RS_TR + a), dR, f.at(RS_TZ + a) * dZ);
+        if (LS == FDTBX_LINESHAPE_LAUE) al[a] = tag_alpha(al[a]);
         lo[a] = lane_float(lol[a], src);
         hi[a] = lane_float(hil[a], src);
         Bv[a] = f.at(RS_B + a);
@@ -149,19 +174,19 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
         const unsigned long long b = __ballot(keep);
         if (keep) {
           const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
-          qn[pos] = e;
+          qn[pos] = LS == FDTBX_LINESHAPE_LAUE ? tag_kappa4(e) : e;
         }
         qlen += __popcll(b);
         wave_sync();
         if (qlen >= 64) {
-          walk_queue<COUNT, LS>(qn, 64, al, q.half_m, tiny, hk, accr, cnt);
+          walk_queue<COUNT, LS>(qn, 64, al, q.half_m, hk, accr, cnt);
           qlen -= 64;
           wave_sync();
           if (lane < qlen) qn[lane] = qn[64 + lane];
           wave_sync();
         }
       });
-      walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, tiny, hk, accr, cnt);
+      walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, hk, accr, cnt);
       wave_sync();
       if (!COUNT) acc = fmaf(f.at(RS_WK), accr, acc);
     }

@@ -118,6 +118,7 @@ __global__ void __launch_bounds__(64) k_splat(SplatParams p, const int32_t* __re
       al[i] = in ? (float)dotv(&p.f.a[3 * i], X) * sc[i] : 1.0e30f;
       lo[i] = wave_min(in ? al[i] : INFINITY) - q.half_m - q.margin;
       hi[i] = wave_max(in ? al[i] : -INFINITY) + q.half_m + q.margin;
+      if (LS == FDTBX_LINESHAPE_LAUE) al[i] = tag_alpha(al[i]);
     }
     const float pS = (float)dotv(S, F.S), p1 = (float)dotv(S, F.e1), p2 = (float)dotv(S, F.e2);
     const float sl = wave_min(in ? pS : INFINITY), sh = wave_max(in ? pS : -INFINITY);
@@ -132,19 +133,19 @@ __global__ void __launch_bounds__(64) k_splat(SplatParams p, const int32_t* __re
         const unsigned long long bal = __ballot(keep);
         if (keep) {
           const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
-          qn[pos] = e;
+          qn[pos] = LS == FDTBX_LINESHAPE_LAUE ? tag_kappa4(e) : e;
         }
         qlen += __popcll(bal);
         wave_sync();
         if (qlen >= 64) {
-          walk_queue<COUNT, LS>(qn, 64, al, q.half_m, q.tiny, hk, accr, cnt);
+          walk_queue<COUNT, LS>(qn, 64, al, q.half_m, hk, accr, cnt);
           qlen -= 64;
           wave_sync();
           if (lane < qlen) qn[lane] = qn[64 + lane];
           wave_sync();
         }
       });
-      walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, q.tiny, hk, accr, cnt);
+      walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, hk, accr, cnt);
       wave_sync();
     }
     if (!COUNT && in && accr != 0.0f) {
