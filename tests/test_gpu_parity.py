@@ -8,6 +8,7 @@ structure factors feed the patterns linearly through |F|^2 and are held to a
 relative L2 of 2e-5 on |F|^2.  At the full benchmark sizes the oracle computes
 sampled pixels and reflections one by one.
 """
+import dataclasses
 import math
 import sys
 
@@ -16,6 +17,7 @@ import pytest
 
 import workloads as W
 from oracle import oracle as O
+from strata import stratified_pixels
 
 pytestmark = pytest.mark.gpu
 
@@ -114,16 +116,18 @@ def _prep_inputs(wl, n_sample=None, seed=0):
     return np.ascontiguousarray(hkl)
 
 
-@pytest.mark.parametrize("cfg,n_sample", [(0, None), (1, 3000), (2, 600)])
+@pytest.mark.parametrize("cfg,n_sample", [(0, None), (1, None), (2, 20000)])
 def test_structure_factors(cfg, n_sample):
+    """All reflections of the tiny and medium workloads and a seeded 20,000 of the large one's
+    293,298 (50,000 atoms each: 1e9 atom-reflection pairs in the oracle's C loop)."""
     wl = W.config(cfg)
-    say(f"structure factors config {cfg}")
     hkl = _prep_inputs(wl, n_sample)
+    say(f"structure factors config {cfg}: {hkl.shape[0]} reflections x {wl.atoms.n} atoms")
     atoms = atoms_to_device(wl.atoms)
     F, F2 = B.structure_factors(B.make_cell(wl.cell), atoms, torch.from_numpy(hkl).cuda())
     F = F.cpu().numpy().astype(np.float64)
     F2 = F2.cpu().numpy().astype(np.float64)
-    ref = O.structure_factors(hkl, wl.cell, wl.atoms)
+    ref = O.structure_factors_c(hkl, wl.cell, wl.atoms)
     ref2 = np.abs(ref) ** 2
     r = rel_l2(F2, ref2)
     big = ref2 > 1e-3 * ref2.max()
@@ -151,11 +155,36 @@ def test_structure_factor_invariants():
     np.testing.assert_allclose(F[::-1, 0], F[:, 0], atol=2e-5 * scale)
 
 
-@pytest.mark.parametrize("case", ["g0", "l1", "v1", "wide"])
+def _voigt_case(sigma_deg, eta, n_nodes=48):
+    """A workload whose angular shape is the Voigt of width sigma and mixing eta (reading R9:
+    sigma_theta = (1 - eta) sigma, gamma_theta = eta sigma)."""
+    st, gt = W.voigt_split(sigma_deg * DEG, eta)
+    return W.small(5, sigma_theta=st, gamma_theta=gt, n_nodes=n_nodes)
+
+
+NODE_CASES = {
+    "g0": W.config0, "l1": W.config2, "v1": W.config1,
+    "wide": lambda: W.small(5, sigma_theta=0.5 * DEG, gamma_theta=6 * DEG, n_nodes=100),
+    # near the Gaussian limit: Im z = gamma/(sigma sqrt 2) ~ 7e-7 and 7e-4 (the real axis)
+    "eta1e-6": lambda: _voigt_case(3.0, 1e-6),
+    "eta1e-3": lambda: _voigt_case(3.0, 1e-3),
+    # Im z ~ 0.037 < 0.1
+    "eta0.05": lambda: _voigt_case(3.0, 0.05),
+    "eta0.5": lambda: _voigt_case(3.0, 0.5),
+    # near the Lorentzian limit: |z| up to ~1e7
+    "eta1-1e-6": lambda: _voigt_case(3.0, 1 - 1e-6),
+}
+
+
+@pytest.mark.parametrize("case", list(NODE_CASES))
 def test_node_table(case):
-    say(f"node table {case}")
-    wl = {"g0": W.config0(), "l1": W.config2(), "v1": W.config1(),
-          "wide": W.small(5, sigma_theta=0.5 * DEG, gamma_theta=6 * DEG, n_nodes=100)}[case]
+    """Node records against the oracle's node table and width derivatives (closed form
+    through the Faddeeva function), near both limits of the Voigt and in its small-Im z
+    region.  The float32 records hold each value to a few units in the last place; the
+    derivatives are compared relative to their largest magnitude."""
+    wl = NODE_CASES[case]()
+    say(f"node table {case}: sigma_theta {wl.dis.sigma_theta:.3e}, gamma_theta {wl.dis.gamma_theta:.3e}, "
+        f"Im z0 {wl.dis.gamma_theta / (math.sqrt(2) * wl.dis.sigma_theta) if wl.dis.sigma_theta else float('inf'):.2e}")
     n = wl.quad.n_nodes
     table = B.node_table(B.make_model(wl)).cpu().numpy().astype(np.float64)
     nodes = table[:n * n]
@@ -164,6 +193,12 @@ def test_node_table(case):
     np.testing.assert_allclose(nodes[:, 1], nd.c * nd.d1, rtol=2e-7, atol=1e-9)
     np.testing.assert_allclose(nodes[:, 2], nd.c * nd.d2, rtol=2e-7, atol=1e-9)
     np.testing.assert_allclose(nodes[:, 3], nd.omega, rtol=1e-6, atol=1e-7 * nd.omega.max())
+    ds, dg = O.node_weight_derivs(nd, wl.quad.sigma_r, wl.dis.sigma_theta, wl.dis.gamma_theta)
+    for col, ref, name in ((4, ds, "d omega/d sigma"), (5, dg, "d omega/d gamma")):
+        big = np.max(np.abs(ref))
+        err = float(np.max(np.abs(nodes[:, col] - ref))) / big if big > 0 else float(np.max(np.abs(nodes[:, col])))
+        say(f"  {name}: max |ref| {big:.3e}, max error / max |ref| {err:.2e}")
+        np.testing.assert_allclose(nodes[:, col], ref, rtol=1e-6, atol=1e-7 * big)
     np.testing.assert_allclose(nodes[:, 6], nd.d1, rtol=2e-7, atol=1e-9)
     np.testing.assert_allclose(nodes[:, 7], nd.d2, rtol=2e-7, atol=1e-9)
     check_block_records(table, n)
@@ -199,10 +234,18 @@ def test_reflection_records(name):
     rb = O.reflection_boxes(wl, hkl)
     assert np.array_equal(cull.cpu().numpy()[:, :13], rb)
     P = O.prepare(wl, hkl=hkl, F=np.sqrt(F2.astype(np.float64)).astype(complex), cull_extinct=False)
-    r = refl.cpu().numpy().astype(np.float64)
+    raw = refl.cpu().numpy()
+    r = raw.astype(np.float64)
     np.testing.assert_allclose(r[:, 0], P.W, rtol=2e-6)
     np.testing.assert_allclose(r[:, 1:4], P.N, rtol=2e-6)
     np.testing.assert_allclose(r[:, 4], P.r0, rtol=2e-7)
+    # the two binary64 fields behind the kernels' cancellation-free offsets R - R_D and Z - Z_D
+    # (record floats 22..23: D.e_perp, 24..25: D_z, each a little-endian float64), bit for bit:
+    # D = h a* + k b* + l c* and e_perp (reading R6) in the oracle's operation order
+    f64 = np.ascontiguousarray(raw[:, 22:26]).view(np.float64)
+    RD = (P.D[:, 0] * P.ep[:, 0] + P.D[:, 1] * P.ep[:, 1]) + P.D[:, 2] * P.ep[:, 2]
+    assert np.array_equal(f64[:, 0], RD), int(np.sum(f64[:, 0] != RD))
+    assert np.array_equal(f64[:, 1], P.D[:, 2])
 
 
 @pytest.mark.parametrize("name", list(SMALL) + ["config0", "config1_sample"])
@@ -265,38 +308,41 @@ def test_pattern_config0_full_and_counts():
     assert abs(n_gpu - n_ref) <= 1e-4 * n_ref
 
 
-def _sampled(wl, n_pix, seed):
-    """GPU image at full size, oracle at sampled pixels.  The oracle sums only the
-    reflections of the sampled pixels' tile lists (its own culling contract, pinned
-    as conservative), with structure factors from its C loop."""
+MEDIUM_STRATA = {"strong": 96, "meridian": 32, "equator": 32, "corners": 16, "uniform": 80}
+
+
+def _oracle_full(wl):
+    """The oracle's whole reflection list of wl (extinction cull applied) and its prepared
+    problem, with the structure factors of every reflection from the oracle's C loop."""
+    hkl = _prep_inputs(wl)
+    return hkl, O.prepare(wl, hkl=hkl, F=O.structure_factors_c(hkl, wl.cell, wl.atoms), cull_extinct=False)
+
+
+def _sampled(wl, counts=MEDIUM_STRATA, seed=0):
+    """GPU image at full size; the oracle at stratified pixels (tests/strata.py: picked from
+    the oracle's own weights and geometry, never from the GPU image), summed over the whole
+    reflection list with the oracle's own exact skip, independent of the culling lists."""
     pipe = Pipeline(wl)
     img = pipe.pattern().cpu().numpy()
     torch.cuda.synchronize()
-    H, Wd = img.shape
-    rng = np.random.default_rng(seed)
-    flat = img.ravel()
-    strong = np.nonzero(flat > 1e-2 * flat.max())[0]
-    pick = np.concatenate([rng.choice(strong, n_pix // 2, replace=False), rng.choice(flat.size, n_pix // 2, replace=False),
-                           [int(np.argmax(flat))]])
+    hkl, P = _oracle_full(wl)
+    assert np.array_equal(pipe.hkl.cpu().numpy(), hkl)
+    pix = stratified_pixels(wl, P, counts, seed)
+    q = np.array([p for p, _ in pix], dtype=np.int64)
     R, Z = O.pixel_rz(wl.geom)
-    hkl = pipe.hkl.cpu().numpy()
-    tx_n = (Wd + 7) // 8
-    tiles = sorted({int((p // Wd) // 8 * tx_n + (p % Wd) // 8) for p in pick})
-    lists = O.culling_lists(wl, hkl, tiles=tiles)
-    sub = np.unique(np.concatenate(lists))
-    say(f"  oracle on {len(pick)} pixels over {sub.size} of {hkl.shape[0]} reflections")
-    F = O.structure_factors_c(hkl[sub], wl.cell, wl.atoms)
-    P = O.prepare(wl, hkl=np.ascontiguousarray(hkl[sub]), F=F, cull_extinct=False)
-    vals = O.pattern_at(P, R.ravel()[pick], Z.ravel()[pick])
-    return flat[pick], vals
+    vals = O.pattern_at(P, R.ravel()[q], Z.ravel()[q])
+    names = sorted({s for _, s in pix})
+    say(f"  oracle at {q.size} pixels ({', '.join(f'{n} {sum(1 for _, s in pix if s == n)}' for n in names)}) "
+        f"over all {hkl.shape[0]} reflections")
+    return img.ravel()[q], vals
 
 
 def test_pattern_tilted_medium_sampled():
     """The medium workload with its fibre tilted by 22 degrees toward the beam (the tilt of
     the paper's A-DNA example), full size, oracle at sampled pixels."""
     wl = W.with_tilt(W.config1(), 22 * DEG)
-    say("pattern medium, fibre tilt 22 deg, 48 sampled pixels")
-    got, ref = _sampled(wl, 48, seed=11)
+    say("pattern medium, fibre tilt 22 deg, stratified pixels")
+    got, ref = _sampled(wl, seed=11)
     check_pattern(got, ref, "medium tilted sampled")
 
 
@@ -305,17 +351,21 @@ def test_pattern_lineshapes_medium_sampled(lineshape):
     """The medium workload with the Gaussian or Hosemann lineshape and axis damping
     B = (10, 10, 10) A^2 (the tutorial's values), full size, oracle at sampled pixels."""
     wl = W.with_disorder(W.config1(), lineshape=W.LINESHAPES[lineshape], B_axis=(10.0, 10.0, 10.0))
-    say(f"pattern medium, {lineshape} lineshape, damping, 48 sampled pixels")
-    got, ref = _sampled(wl, 48, seed=12)
+    say(f"pattern medium, {lineshape} lineshape, damping, stratified pixels")
+    got, ref = _sampled(wl, seed=12)
     check_pattern(got, ref, f"medium {lineshape} sampled")
 
 
-@pytest.mark.parametrize("cfg,n_pix", [(1, 48), (2, 16)])
-def test_pattern_full_size_sampled(cfg, n_pix):
-    wl = W.config(cfg)
-    say(f"pattern config {cfg}, {n_pix} sampled pixels")
-    got, ref = _sampled(wl, n_pix, seed=cfg)
-    check_pattern(got, ref, f"config{cfg} sampled")
+@pytest.mark.parametrize("tile_w,mirror", [(8, 0), (16, 3)])
+def test_pattern_medium_full_size_sampled(tile_w, mirror):
+    """The medium workload at full size, unfolded in 8x8 tiles and in the benchmark's launch
+    (16x4 tiles, both mirror folds), the oracle at 256 stratified pixels.  (The large workload
+    is compared at 1024 stratified pixels in test_gpu_fullsize.py.)"""
+    wl = W.config1()
+    wl = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, tile_w=tile_w, mirror=mirror))
+    say(f"pattern medium, {tile_w}x{64 // tile_w} tiles, mirror bits {mirror}, stratified pixels")
+    got, ref = _sampled(wl, seed=1)
+    check_pattern(got, ref, "medium sampled")
 
 
 @pytest.mark.parametrize("name", ["ragged", "tilted", "config0", "config1"])
