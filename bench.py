@@ -1,18 +1,20 @@
 """Benchmark of the fibre-diffraction profile-quadrature path on one MI355X.
 
-A step is one pass of the whole forward path over the medium workload
-(40x40x60 A cell, beta 95 deg, 5000 atoms, reflections to 2 A, 1024x1024
-detector, Voigt 3 deg eta .5, Hosemann g .03 lateral, 64x64 nodes):
-reflection enumeration, structure factors, reflection preparation, node table,
-pixel map, tile culling and the profile kernel.  Inputs are seeded and
-synthetic and resident in device memory before the timed region.
+A step is one pass of the whole forward path over the large workload (100x100x120 A
+cell, 50,000 atoms, reflections to 1.5 A: 293,298 after the extinction cull, 2048x2048
+detector, Lorentzian 2 deg, Hosemann g .05 lateral, 96x96 nodes), the largest
+configuration that one GPU holds: reflection enumeration, structure factors, reflection
+preparation, node table, pixel map, tile culling and the profile kernel.  Inputs are
+seeded and synthetic and resident in device memory before the timed region.
 
-Prints one JSON line.  value = useful profile evaluations per second of the
-whole step (evaluations = (pixel, reflection, node) triples inside the kernel
-support, counted once by a counting pass of the same kernel).  The roofline
-object refers to the profile kernel, timed with HIP events on the stream it is
-launched on; cpu_baseline is the FP64 oracle on a bounded pixel sample of the
-same workload.
+Prints one JSON line.  value = useful profile evaluations per second of the whole step
+(evaluations = (pixel, reflection, node) triples inside the kernel support, counted once
+by a counting pass of the same kernel).  The roofline object refers to the profile
+kernel, timed with HIP events on the stream it is launched on; cpu_baseline is the FP64
+oracle on a bounded pixel sample of the same workload, on all host cores and on one.
+The medium workload's forward step, the tilted fibre, the other lineshapes, the exact
+cylindrical average, the forward splat, the refinement step (forward + adjoint) and the
+batch of 256 ragged models are reported as further keys.
 """
 from __future__ import annotations
 
@@ -80,16 +82,21 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline leg")
-    ap.add_argument("--cpu-pixels", type=int, default=1024)
+    ap.add_argument("--cpu-block", type=int, default=8, help="side of the pixel block the CPU baseline times")
+    ap.add_argument("--cpu-one-core-pixels", type=int, default=8,
+                    help="pixels of the block the one-core CPU baseline times")
     ap.add_argument("--no-bwd", action="store_true", help="skip the forward+backward leg")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched 256-model leg")
     ap.add_argument("--no-tilt", action="store_true", help="skip the tilted-fibre forward leg")
-    ap.add_argument("--no-large", action="store_true", help="skip the large-workload forward leg")
+    ap.add_argument("--no-medium", action="store_true", help="skip the medium-workload forward leg")
     ap.add_argument("--no-lineshapes", action="store_true", help="skip the Gaussian/Hosemann lineshape legs")
     ap.add_argument("--no-splat", action="store_true", help="skip the forward-splat leg")
     ap.add_argument("--no-cyl", action="store_true", help="skip the exact cylindrical-average leg")
     ap.add_argument("--tile-w", type=int, default=0, choices=(0, 2, 4, 8, 16, 32),
+                    help="pixel-tile width of the large (headline) forward (0: chosen by the tile tuner)")
+    ap.add_argument("--medium-tile-w", type=int, default=0, choices=(0, 2, 4, 8, 16, 32),
                     help="pixel-tile width of the medium forward (0: chosen by the tile tuner)")
+    ap.add_argument("--only-headline", action="store_true", help="run the large forward leg alone (profiler runs)")
     ap.add_argument("--no-mirror", action="store_true", help="run every tile (no mirror fold)")
     ap.add_argument("--no-updown", action="store_true", help="fold the left-right mirror only (not the up-down one)")
     ap.add_argument("--no-unfolded", action="store_true", help="skip the unfolded reference forward")
@@ -243,20 +250,35 @@ def tune_tiles(wl):
     return dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, tile_w=tw)), info
 
 
-def bench_large(args):
-    """The large workload's forward step (2048^2 detector, 96 x 96 nodes, about 2.9e5
-    reflections after the extinction cull), folded, 8 x 8 tiles, the library's waves per
-    tile."""
+def bench_medium(args):
+    """The medium workload's forward step (40x40x60 A cell, beta 95 deg, 5000 atoms,
+    reflections to 2 A, 1024^2 detector, Voigt 3 deg eta .5, Hosemann g .03 lateral, 64x64
+    nodes), folded, in the tile shape the tuner picks (or --medium-tile-w), the library's
+    waves per tile; the same step unfolded beside it."""
     import workloads as W
     from paper_2608_23245_amd import binding as B
-    wl = fold(W.config2())
-    ms_step, prof_ms, n_evals, state = forward_leg(wl, 2, 1)
+    wl = W.config1()
+    if args.medium_tile_w:
+        wl = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, tile_w=args.medium_tile_w))
+        tiles = {"tile": f"{args.medium_tile_w}x{64 // args.medium_tile_w}", "tuned": False}
+    else:
+        wl, tiles = tune_tiles(fold(wl))
+    wl = fold(wl)
+    ms_step, prof_ms, n_evals, state = forward_leg(wl, max(1, min(args.steps, 5)), 1)
+    waves = B.launch_waves(B.make_model(wl).geom)
     ach = n_evals * SLOTS_PER_EVAL / (prof_ms * 1e-3)
     out = {"workload": wl.name, "n_hkl": int(state["hkl"].shape[0]), "culled_pairs": int(state["idx"].shape[0]),
            "useful_evals_per_step": int(n_evals), "ms_per_pattern": ms_step, "profile_kernel_ms": prof_ms,
            "evals_per_s": n_evals / (ms_step * 1e-3), "profile_kernel_evals_per_s": n_evals / (prof_ms * 1e-3),
-           "issue_frac": ach / PEAK_SLOTS, "mirror_fold": fold_name(wl),
-           "waves_per_tile": B.launch_waves(B.make_model(wl).geom), "pass": "forward"}
+           "issue_frac": ach / PEAK_SLOTS, "mirror_fold": fold_name(wl), "tile_tuning": tiles,
+           "waves_per_tile": waves, "pass": "forward"}
+    if wl.geom.mirror and not args.no_unfolded:
+        wl0 = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, mirror=0, tile_waves=waves))
+        ms0, prof0, n0, st0 = forward_leg(wl0, max(1, min(args.steps, 3)), 1)
+        out["unfolded"] = {"ms_per_pattern": ms0, "profile_kernel_ms": prof0, "useful_evals_per_step": int(n0),
+                           "waves_per_tile": waves, "profile_kernel_evals_per_s": n0 / (prof0 * 1e-3),
+                           **compare_unfolded(wl, state["img"], st0["img"])}
+        del st0
     del state
     return out
 
@@ -397,7 +419,7 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
-    wl = W.config1()
+    wl = W.config2()
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -420,6 +442,7 @@ def main():
         torch.cuda.synchronize()
         cold_ms = (time.perf_counter() - t0) * 1e3
         log(f"cold first pattern: {cold_ms:.0f} ms")
+        torch.cuda.empty_cache()
     if args.tile_w:
         wl = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, tile_w=args.tile_w))
         tiles = {"tile": f"{args.tile_w}x{64 // args.tile_w}", "tuned": False}
@@ -457,31 +480,34 @@ def main():
         "tile_tuning": tiles,
         "rates": other_rates(n_evals / (prof_ms * 1e-3), prof_ms),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(), "kernel": f"k_profile<false, 0, {waves_main}>", "sources_sha": profile_source_sha(),
-                     "slots_per_eval": SLOTS_PER_EVAL},
+                     "traffic": measured_traffic(), "kernel": f"k_profile<false, 0, {waves_main}>",
+                     "sources_sha": profile_source_sha(), "slots_per_eval": SLOTS_PER_EVAL},
     }
-    if wl.geom.mirror and not args.no_unfolded:
+    if wl.geom.mirror and not args.no_unfolded and not args.only_headline:
         # the same forward step without the folds, for reference (with the same waves per tile,
         # so that the computed pixels can be compared bit for bit)
-        waves = waves_main
-        wl0 = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, mirror=0, tile_waves=waves))
-        ms0, prof0, n0, st0 = forward_leg(wl0, max(1, min(args.steps, 3)), 1)
+        wl0 = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, mirror=0, tile_waves=waves_main))
+        ms0, prof0, n0, st0 = forward_leg(wl0, 1, 1)
         out["unfolded"] = {"ms_per_pattern": ms0, "profile_kernel_ms": prof0, "useful_evals_per_step": int(n0),
-                           "waves_per_tile": waves, "profile_kernel_evals_per_s": n0 / (prof0 * 1e-3),
+                           "waves_per_tile": waves_main, "profile_kernel_evals_per_s": n0 / (prof0 * 1e-3),
                            **compare_unfolded(wl, state["img"], st0["img"])}
         del st0
-    if not args.no_cpu:
+        torch.cuda.empty_cache()
+    if not args.no_cpu and not args.only_headline:
         log("cpu baseline (oracle)")
-        out["cpu_baseline"] = cpu_baseline(wl, state, args.cpu_pixels)
+        out["cpu_baseline"] = cpu_baseline(wl, state, args.cpu_block, args.cpu_one_core_pixels)
     del state
     torch.cuda.empty_cache()
+    if args.only_headline:
+        print(json.dumps(out), flush=True)
+        return
+    if not args.no_medium:
+        log("forward, medium workload")
+        out["medium"] = bench_medium(args)
+        torch.cuda.empty_cache()
     if not args.no_tilt:
         log("forward, tilted fibre")
         out["tilted"] = bench_tilted(args)
-        torch.cuda.empty_cache()
-    if not args.no_large:
-        log("forward, large workload")
-        out["large"] = bench_large(args)
         torch.cuda.empty_cache()
     if not args.no_lineshapes:
         log("forward, Gaussian and Hosemann lineshapes")
@@ -673,36 +699,51 @@ def bench_batched(args):
             "pass": "one HIP graph: batched forward + pixel weights + batched adjoint of all models"}
 
 
-def cpu_baseline(wl, state, n_pix):
-    """The FP64 oracle on a seeded sample of pixels of the same workload (all
-    reflections of their tiles' lists, oracle structure factors), in useful
-    evaluations per second."""
+def cpu_baseline(wl, state, block, n_one):
+    """The FP64 oracle as it stands on a bounded sample of the same workload: the block x block
+    pixels whose lower-left pixel is (width/2 + 128, height/2 + 256), over the whole reflection
+    list with the oracle's own exact skip.  The structure factors of the reflections that can
+    reach the block come first from the oracle's C loop (not timed); then oracle_pattern is
+    timed on all the host threads over the block and on one thread over its first n_one pixels.
+    The GPU image on the block is compared with the oracle's as a check of the sample."""
     import numpy as np
+    import torch
 
     from oracle import oracle as O
-    img = state["img"].cpu().numpy()
-    H, Wd = img.shape
-    rng = np.random.default_rng(12345)
-    flat = img.ravel()
-    strong = np.nonzero(flat > 1e-2 * flat.max())[0]
-    pick = np.concatenate([rng.choice(strong, n_pix // 2, replace=False), rng.choice(flat.size, n_pix - n_pix // 2,
-                                                                                      replace=False)])
-    hkl = state["hkl"].cpu().numpy()
-    tx_n = (Wd + 7) // 8
-    tiles = sorted({int((p // Wd) // 8 * tx_n + (p % Wd) // 8) for p in pick})
-    sub = np.unique(np.concatenate(O.culling_lists(wl, hkl, tiles=tiles)))
-    F = O.structure_factors_c(hkl[sub], wl.cell, wl.atoms)
-    P = O.prepare(wl, hkl=np.ascontiguousarray(hkl[sub]), F=F, cull_extinct=False)
-    R, Z = O.pixel_rz(wl.geom)
+    g = wl.geom
+    i0, j0 = g.width // 2 + 128, g.height // 2 + 256
+    q = np.array([(j0 + dj) * g.width + (i0 + di) for dj in range(block) for di in range(block)], dtype=np.int64)
+    hkl = O.enumerate_hkl(wl.cell, wl.quad.d_min, wl.quad.d_max)
+    hkl = np.ascontiguousarray(hkl[~O.extinct_mask(hkl, wl.dis, wl.quad.extinction)])
+    R, Z = O.pixel_rz(g)
+    Rq, Zq = R.ravel()[q], Z.ravel()[q]
+    del R, Z
     t0 = time.perf_counter()
-    vals, n = O.pattern_at(P, R.ravel()[pick], Z.ravel()[pick], count=True)
+    sub = O.reachable(wl, hkl, Rq, Zq)
+    hs = np.ascontiguousarray(hkl[sub])
+    P = O.prepare(wl, hkl=hs, F=O.structure_factors_c(hs, wl.cell, wl.atoms), cull_extinct=False)
+    setup_s = time.perf_counter() - t0
+    threads = O.threads()
+    t0 = time.perf_counter()
+    vals, n = O.pattern_at(P, Rq, Zq, count=True)
     dt = time.perf_counter() - t0
-    ref = vals
-    got = flat[pick].astype(np.float64)
-    rel = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    return {"value": n / dt, "unit": "evals/s", "cores": O.threads(), "kind": "oracle",
-            "sample": f"{n_pix} seeded pixels of the 1024x1024 image ({n} useful evaluations, {dt:.1f} s), "
-                      f"reflections of their tiles' lists; GPU vs oracle rel-L2 on the sample {rel:.1e}"}
+    O.set_threads(1)
+    try:
+        t0 = time.perf_counter()
+        _, n1 = O.pattern_at(P, Rq[:n_one], Zq[:n_one], count=True)
+        dt1 = time.perf_counter() - t0
+    finally:
+        O.set_threads(threads)
+    got = state["img"].reshape(-1)[torch.as_tensor(q, device="cuda")].cpu().numpy().astype(np.float64)
+    rel = float(np.linalg.norm(got - vals) / np.linalg.norm(vals))
+    log(f"cpu baseline: {n / dt:.3e} evals/s on {threads} threads, {n1 / dt1:.3e} on one")
+    return {"value": n / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{block}x{block} pixels of the {g.width}x{g.height} image from ({i0}, {j0}) ({n} useful "
+                      f"evaluations, {dt:.1f} s on {threads} threads), over all {hkl.shape[0]} reflections with the "
+                      f"oracle's exact skip ({sub.size} can reach the block; their structure factors took "
+                      f"{setup_s:.1f} s, not timed); GPU vs oracle rel-L2 on the block {rel:.1e}",
+            "one_core": {"value": n1 / dt1, "unit": "evals/s", "cores": 1,
+                         "sample": f"the first {n_one} pixels of the block ({n1} useful evaluations, {dt1:.1f} s)"}}
 
 
 if __name__ == "__main__":
