@@ -420,6 +420,36 @@ int fdtbx_profile_pattern(const fdtbx_model* model, const int32_t* hkl, int64_t 
                           float* image, int64_t pair_cap, int64_t* pairs_needed, void* ws, size_t ws_bytes,
                           void* stream);
 
+/* Device-written statistics of one fdtbx_profile_pattern_async call.  stamp[k] is the
+ * device wall clock (clock_khz ticks per millisecond) when step k began: 0 reflection
+ * preparation, 1 node table, 2 pixel map, 3 culling, 4 launch order, 5 profile, 6 counting
+ * pass (when asked for), 7 the end; a step took (stamp[k+1] - stamp[k]) / clock_khz ms
+ * (stamp[6] = stamp[7] without the counting pass). */
+#define FDTBX_STATS_STAMPS 8
+typedef struct fdtbx_stats {
+  int64_t n_hkl;          /* reflections of the call */
+  int64_t n_pairs;        /* (tile, reflection) pairs the culling lists need */
+  int64_t pair_cap;       /* the capacity the call was given */
+  int64_t useful_evals;   /* (pixel, reflection, node) triples inside the support, or -1 if not counted */
+  int32_t overflow;       /* 1 if n_pairs > pair_cap: no lists were built and the image is all zero */
+  int32_t n_stamps;       /* FDTBX_STATS_STAMPS */
+  int64_t clock_khz;      /* rate of the stamps */
+  uint64_t stamp[FDTBX_STATS_STAMPS];
+} fdtbx_stats;
+
+/* fdtbx_profile_pattern_async: fdtbx_profile_pattern without any host round trip, so that a
+ * caller can capture it in a HIP graph: the pair capacity is checked on the device (with more
+ * than pair_cap pairs the lists stay empty, the image comes out zero and stats->overflow is
+ * set; the caller reads stats after the stream and retries with stats->n_pairs), every buffer
+ * is cleared by a kernel, and nothing is copied to the host.  count_evals nonzero adds the
+ * counting pass of fdtbx_profile (a second walk) for stats->useful_evals.
+ *   stats  device fdtbx_stats [1] output (may be NULL)
+ *   ws     device workspace of fdtbx_pattern_workspace(model, n_hkl, pair_cap) bytes, laid
+ *          out as for fdtbx_profile_pattern, so fdtbx_pattern_backward can follow it. */
+int fdtbx_profile_pattern_async(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F2,
+                                float* image, int64_t pair_cap, int32_t count_evals, fdtbx_stats* stats, void* ws,
+                                size_t ws_bytes, void* stream);
+
 /* ------------------------------------------------------------------ adjoint
  * Gradients of a scalar L through the image, given G = dL/dimage (float32 [height][width],
  * device).  The parameters are the atoms (fractional x, y, z, B, occupancy) and the
@@ -436,10 +466,47 @@ int fdtbx_profile_pattern(const fdtbx_model* model, const int32_t* hkl, int64_t 
  *   sums[r][3+i] = sum G L(R) sum_k omega_k N_i (dZ_k/dN_i)/C_r   (u held fixed)
  * sums: device float64 [n_hkl][6], zeroed by the call, then accumulated with binary64 atomic
  * adds (the result depends on the order of those adds only below binary64 rounding).
- * order: as in fdtbx_profile. */
+ * order: as in fdtbx_profile.
+ * Under the up-down fold (bit 1 of geom.mirror) a computed pixel also stands for its mirror
+ * (R, -Z), whose value reflection r gives through its Friedel mate: I_r(R, -Z) = I_{-r}(R, Z).
+ * The kernel weights each pair's lane sums by G of the pixel (and its left-right mirror) into
+ * r's sums and by G of the up-down mirrors into the sums of the mate -r, entry n_hkl - 1 - r of
+ * the list (which must then be closed under negation in that order, as fdtbx_enumerate_hkl's
+ * is), so the sums, dF2 and every gradient are those of the unfolded image, per reflection. */
 int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
                           const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
                           int64_t n_hkl, const float* grad_image, double* sums, void* stream);
+
+/* Fixed-order (deterministic) accumulation of the same sums, in three calls (section
+ * "Race detection" of the method's test strategy: gradients reproducible bit for bit).
+ *
+ * fdtbx_profile_adjoint_pairs: the walk of fdtbx_profile_adjoint, but pair p of the culling
+ * lists (position p of idx) stores its twelve float32 lane-sum totals at partials[12 p]: the
+ * six of its reflection r, then the six of the mate n_hkl - 1 - r (zero without the up-down
+ * fold).  partials: device float32 [pair_cap][12], zeroed by the call (pairs that add nothing
+ * keep zeros); pair_cap >= the pair count of the lists.
+ *
+ * fdtbx_pair_transpose: the pairs of each reflection in ascending list position, by a stable
+ * radix sort of their reflection indices: refl_pairs[refl_ptr[r] .. refl_ptr[r+1]) are the
+ * positions p with idx[p] = r.  n_pairs: device int64 [1] holding the pair count (for
+ * instance offsets[n_tiles] of fdtbx_cull), or NULL when all pair_cap entries are pairs.
+ *   refl_ptr   device int64 [n_hkl + 1] output;  refl_pairs device int32 [pair_cap] output
+ *   ws         device workspace of fdtbx_pair_transpose_workspace(n_hkl, pair_cap) bytes
+ *              (0 when pair_cap >= 2^31 or n_hkl >= 2^30: FDTBX_ERR_UNSUPPORTED)
+ *
+ * fdtbx_pair_reduce: sums[r][c] = sum over r's pairs p, in that order, of partials[p][c], plus
+ * sum over the pairs p of its mate m of partials[p][6 + c], in binary64: m = mate[r] (device
+ * int64 [n_hkl], -1 for none), or, with mate NULL, n_hkl - 1 - r if updown is nonzero and none
+ * otherwise.  sums: device float64 [n_hkl][6] output.  No atomics: the same inputs give the
+ * same bits on every run and every schedule. */
+int fdtbx_profile_adjoint_pairs(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
+                                const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
+                                int64_t n_hkl, int64_t pair_cap, const float* grad_image, float* partials, void* stream);
+size_t fdtbx_pair_transpose_workspace(int64_t n_hkl, int64_t pair_cap);
+int fdtbx_pair_transpose(int64_t n_hkl, const int32_t* idx, int64_t pair_cap, const int64_t* n_pairs, int64_t* refl_ptr,
+                         int32_t* refl_pairs, void* ws, size_t ws_bytes, void* stream);
+int fdtbx_pair_reduce(int64_t n_hkl, const int64_t* refl_ptr, const int32_t* refl_pairs, const float* partials,
+                      const int64_t* mate, int32_t updown, double* sums, void* stream);
 
 /* fdtbx_adjoint_finish: chain rule per reflection in binary64 (Eqs. Ah, Neff, Ipara, axis
  * damping):
@@ -480,6 +547,20 @@ int fdtbx_pattern_backward(const fdtbx_model* model, const int32_t* hkl, int64_t
                            float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals, float* dF2, void* ws,
                            size_t ws_bytes, void* stream);
 
+/* fdtbx_pattern_backward_deterministic: fdtbx_pattern_backward with the fixed-order sums
+ * (fdtbx_profile_adjoint_pairs, fdtbx_pair_transpose, fdtbx_pair_reduce) instead of atomic
+ * adds: every output is reproducible bit for bit.  Same arguments; ws: device workspace of
+ * fdtbx_backward_deterministic_workspace(n_hkl, n_atoms, pair_cap) bytes (about 60 bytes per
+ * pair of capacity beyond fdtbx_backward_workspace; 0 for sizes the sort cannot take). */
+size_t fdtbx_backward_deterministic_workspace(int64_t n_hkl, int64_t n_atoms, int64_t pair_cap);
+int fdtbx_pattern_backward_deterministic(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F,
+                                         const float* grad_image, const void* fwd_ws, size_t fwd_ws_bytes,
+                                         int64_t pair_cap, int64_t n_atoms, const float* x, const float* y,
+                                         const float* z, const float* B, const float* occ, const int32_t* type,
+                                         const float* ff, int32_t n_types, float* d_x, float* d_y, float* d_z, float* d_B,
+                                         float* d_occ, double* d_globals, float* dF2, void* ws, size_t ws_bytes,
+                                         void* stream);
+
 /* ------------------------------------------------------------------ batched models
  * Many models of different cells, atom counts, reflection lists and detectors in one
  * launch per step.  Each model's static data (reflection list, pixel map, tile boxes,
@@ -511,15 +592,32 @@ typedef struct fdtbx_batch_entry {
   int64_t pair_off;     /* first culling-list entry; the row pointers are relative to it */
   int64_t node_off;     /* first row of this model's node table (fdtbx_node_rows(n_nodes) rows) */
   int64_t ff_off;       /* first scattering-factor row */
-  int32_t n_types, n_tiles;
+  int32_t n_types, n_tiles;  /* scattering-factor rows (1..16) and tiles of this model */
+  double setup_g[3];         /* g and N_base the culling lists were built with */
+  double setup_N_base[3];
+  int32_t stale;             /* set by fdtbx_batch_set_globals: 1 if the current globals widen a
+                                support beyond those (some g_i > setup_g[i] or some
+                                N_base_i < setup_N_base[i]), so the lists may miss pairs */
+  int32_t reserved;
 } fdtbx_batch_entry;
 
-/* Host: validate the model and fill e->model and e->frame (offsets are the caller's). */
+/* Host: validate the model and fill e->model, e->frame and e->setup_g, e->setup_N_base (from
+ * the model: the parameters its culling lists are built with); offsets are the caller's. */
 int fdtbx_batch_entry_init(const fdtbx_model* model, fdtbx_batch_entry* e);
+/* Host: check host copies of the entries before they are uploaded: n_types in 1..16, sizes
+ * and offsets non-negative.  FDTBX_ERR_INVALID_ARGUMENT names the first bad entry's field. */
+int fdtbx_batch_entries_check(const fdtbx_batch_entry* entries, int32_t n_models);
 /* sizeof(fdtbx_batch_entry), for bindings that mirror the struct. */
 size_t fdtbx_batch_entry_size(void);
 
-/* Device: entries[m].model.dis <- globals[m][0..FDTBX_N_GLOBALS-1] (order of FDTBX_N_GLOBALS). */
+/* Device: entries[m].model.dis <- globals[m][0..FDTBX_N_GLOBALS-1] (order of FDTBX_N_GLOBALS),
+ * and entries[m].stale <- whether those globals widen a lineshape support beyond the set-up
+ * values (a larger g or a smaller N_base gives a smaller N_eff, hence a wider support in u; the
+ * culling lists, built for the set-up supports, may then miss contributing pairs).  Smaller g,
+ * larger N_base and every change of sigma_theta, gamma_theta and B_axis keep the lists exact
+ * supersets.  (The reflection list keeps the set-up extinction cull: with g below its set-up
+ * value a reflection it lacks has an intensity factor below exp(-limit (g/g_setup)^2).)
+ * The caller reads the stale words back (outside any graph) before trusting the next step. */
 int fdtbx_batch_set_globals(fdtbx_batch_entry* entries, int32_t n_models, const double* globals, void* stream);
 
 /* Forward step for all models: structure factors F [sum n_hkl][2] and F2, reflection
@@ -546,6 +644,25 @@ int fdtbx_batch_backward(const fdtbx_batch_entry* entries, int32_t n_models, con
                          const float* refl, const float* nodes, const float* grad_image, double* sums, double* part,
                          float* dF2, float* d_x, float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals,
                          int64_t* counter, void* stream);
+
+/* fdtbx_batch_backward_deterministic: fdtbx_batch_backward with the fixed-order sums.
+ * The batch's culling lists are fixed at set-up, so the caller builds, once, the order of
+ * its pairs by reflection over the whole batch (global reflection index hkl_off + idx, global
+ * pair index pair_off + position; as fdtbx_pair_transpose would): refl_ptr device int64
+ * [n_hkl_total + 1], refl_pairs device int32 [n_pairs_total], and mate device int64
+ * [n_hkl_total] (the global index of each reflection's Friedel mate, hkl_off + n_hkl - 1 - r,
+ * for models with the up-down fold, else -1).  partials: device float32 [n_pairs_total][12]
+ * scratch.  sums is then written by the reduction, not accumulated.  Graph-capturable like
+ * fdtbx_batch_backward. */
+int fdtbx_batch_backward_deterministic(
+    const fdtbx_batch_entry* entries, int32_t n_models, const int64_t* refl_blocks, int64_t n_rb, const int64_t* model_rb,
+    const int64_t* atom_blocks, int64_t n_ab, const int64_t* tile_items, int64_t n_items, int64_t n_hkl_total,
+    const int32_t* hkl, const float* x, const float* y, const float* z, const float* B, const float* occ,
+    const int32_t* type, const float* ff, const double* pix, const double* tile, const int64_t* rowptr, const int32_t* idx,
+    const float* F, const float* refl, const float* nodes, const float* grad_image, int64_t n_pairs_total,
+    const int64_t* refl_ptr, const int32_t* refl_pairs, const int64_t* mate, float* partials, double* sums, double* part,
+    float* dF2, float* d_x, float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals, int64_t* counter,
+    void* stream);
 
 #ifdef __cplusplus
 }

@@ -29,8 +29,12 @@ def _pack(model: int, first: int) -> int:
     return (model << 40) | first
 
 
+class StaleListsError(RuntimeError):
+    """The globals of some model widen a lineshape support beyond its set-up culling lists."""
+
+
 class BatchEngine:
-    def __init__(self, workloads: List, device="cuda"):
+    def __init__(self, workloads: List, device="cuda", deterministic: bool = False):
         L = B.lib()
         if L.fdtbx_batch_entry_size() != ctypes.sizeof(B.BatchEntry):
             raise RuntimeError("fdtbx_batch_entry layout differs between the library and the binding")
@@ -122,6 +126,7 @@ class BatchEngine:
         self.model_rb = dev(np.asarray(model_rb, dtype=np.int64), torch.int64)
         self.atom_blocks = dev(np.asarray(atom_blocks, dtype=np.int64), torch.int64)
         self.node_blocks = dev(np.asarray(node_blocks, dtype=np.int64), torch.int64)
+        B._check(L.fdtbx_batch_entries_check(ctypes.byref(ents), n))
         raw = bytes(ctypes.string_at(ctypes.addressof(ents), ctypes.sizeof(ents)))
         self.entries = torch.frombuffer(bytearray(raw), dtype=torch.uint8).to(device)
         self._host_entries = ents
@@ -143,6 +148,22 @@ class BatchEngine:
         self.pix_off = pix_off
         self.hkl_off = [ents[m].hkl_off for m in range(n)] + [H]
         self.atom_off = [ents[m].atom_off for m in range(n)] + [off["atom"]]
+        # fixed-order adjoint sums: the batch's pairs by reflection (global indices), once
+        self.deterministic = bool(deterministic)
+        if self.deterministic:
+            keys = np.concatenate([idxs[m].cpu().numpy().astype(np.int64) + ents[m].hkl_off for m in range(n)]) \
+                if off["pair"] > 0 else np.zeros(0, dtype=np.int64)
+            perm = np.argsort(keys, kind="stable")
+            ptr = np.searchsorted(keys[perm], np.arange(H + 1), side="left")
+            mate = np.full(H, -1, dtype=np.int64)
+            for m, mod in enumerate(self.models):
+                if mod.geom.mirror & 2:
+                    h0, nh = ents[m].hkl_off, ents[m].n_hkl
+                    mate[h0:h0 + nh] = h0 + nh - 1 - np.arange(nh)
+            self.refl_ptr = dev(ptr, torch.int64)
+            self.refl_pairs = dev(perm, torch.int32) if perm.size else torch.zeros(1, dtype=torch.int32, device=device)
+            self.mate = dev(mate, torch.int64)
+            self.partials = torch.empty((max(off["pair"], 1), 12), dtype=torch.float32, device=device)
 
     # ------------------------------------------------------------------ views
     def image_of(self, m: int) -> torch.Tensor:
@@ -154,9 +175,45 @@ class BatchEngine:
         return torch.tensor(g, dtype=torch.float64, device=self.device)
 
     # ------------------------------------------------------------------ step
-    def set_globals(self, glob: torch.Tensor):
+    def set_globals(self, glob: torch.Tensor, on_stale: str = "raise"):
+        """Write every model's globals on the device.  The culling lists were built for the
+        set-up g and N_base; a larger g or a smaller N_base widens a support past them, which
+        fdtbx_batch_set_globals flags per model.  The flags are read back here (one small copy;
+        keep this call outside a captured graph), and such a move either raises
+        (on_stale="raise") or rebuilds the batch's static data for the new globals
+        (on_stale="rebuild"; the atoms keep their current device values)."""
+        if on_stale not in ("raise", "rebuild"):
+            raise ValueError("on_stale must be 'raise' or 'rebuild'")
         glob = glob.to(self.device, torch.float64).contiguous()
         B._check(B.lib().fdtbx_batch_set_globals(B._ptr(self.entries), self.n, B._ptr(glob), B._stream()))
+        stale = self.stale_models()
+        if not stale:
+            return
+        if on_stale == "raise":
+            raise StaleListsError(f"models {stale} widen a support beyond their culling lists (larger g or smaller "
+                                  "N_base than at set-up); rebuild the batch")
+        self._rebuild(glob)
+
+    def stale_models(self) -> List[int]:
+        """Models whose current globals widen a support beyond their set-up culling lists."""
+        size = ctypes.sizeof(B.BatchEntry)
+        off = B.BatchEntry.stale.offset
+        raw = self.entries.view(self.n, size)[:, off:off + 4].cpu().numpy().copy().view(np.int32).ravel()
+        return [int(m) for m in np.nonzero(raw)[0]]
+
+    def _rebuild(self, glob: torch.Tensor):
+        import dataclasses
+        g = glob.cpu().numpy()
+        wls = []
+        for m, wl in enumerate(self.workloads):
+            d = dataclasses.replace(wl.dis, sigma_theta=float(g[m, 0]), gamma_theta=float(g[m, 1]),
+                                    N_base=tuple(float(v) for v in g[m, 2:5]), g=tuple(float(v) for v in g[m, 5:8]),
+                                    B_axis=tuple(float(v) for v in g[m, 8:11]))
+            wls.append(dataclasses.replace(wl, dis=d))
+        atoms = {k: v.clone() for k, v in self.atoms.items()}
+        self.__init__(wls, device=self.device, deterministic=self.deterministic)
+        for k, v in atoms.items():
+            self.atoms[k].copy_(v)
 
     def forward(self) -> torch.Tensor:
         a = self.atoms
@@ -173,6 +230,17 @@ class BatchEngine:
         a = self.atoms
         g = self.grads
         d = [B._ptr(g[k]) if atoms else None for k in ("x", "y", "z", "B", "occ")]
+        if self.deterministic:
+            B._check(B.lib().fdtbx_batch_backward_deterministic(
+                B._ptr(self.entries), self.n, B._ptr(self.refl_blocks), int(self.refl_blocks.shape[0]),
+                B._ptr(self.model_rb), B._ptr(self.atom_blocks), int(self.atom_blocks.shape[0]), B._ptr(self.items),
+                int(self.items.shape[0]), int(self.totals["hkl"]), B._ptr(self.hkl), B._ptr(a["x"]), B._ptr(a["y"]),
+                B._ptr(a["z"]), B._ptr(a["B"]), B._ptr(a["occ"]), B._ptr(a["type"]), B._ptr(a["ff"]), B._ptr(self.pix),
+                B._ptr(self.tile), B._ptr(self.rowptr), B._ptr(self.idx), B._ptr(self.F), B._ptr(self.refl),
+                B._ptr(self.nodes), B._ptr(grad_image), int(self.totals["pair"]), B._ptr(self.refl_ptr),
+                B._ptr(self.refl_pairs), B._ptr(self.mate), B._ptr(self.partials), B._ptr(self.sums), B._ptr(self.part),
+                B._ptr(self.dF2), *d, B._ptr(self.d_globals), B._ptr(self.counter), B._stream()))
+            return g, self.d_globals
         B._check(B.lib().fdtbx_batch_backward(
             B._ptr(self.entries), self.n, B._ptr(self.refl_blocks), int(self.refl_blocks.shape[0]),
             B._ptr(self.model_rb), B._ptr(self.atom_blocks), int(self.atom_blocks.shape[0]), B._ptr(self.items),

@@ -65,8 +65,20 @@ class BatchEntry(ctypes.Structure):
                 ("n_atoms", ctypes.c_int64), ("hkl_off", ctypes.c_int64), ("n_hkl", ctypes.c_int64),
                 ("pix_off", ctypes.c_int64), ("tile_off", ctypes.c_int64), ("rowptr_off", ctypes.c_int64),
                 ("pair_off", ctypes.c_int64), ("node_off", ctypes.c_int64), ("ff_off", ctypes.c_int64),
-                ("n_types", ctypes.c_int32), ("n_tiles", ctypes.c_int32)]
+                ("n_types", ctypes.c_int32), ("n_tiles", ctypes.c_int32), ("setup_g", ctypes.c_double * 3),
+                ("setup_N_base", ctypes.c_double * 3), ("stale", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
+
+STATS_STAMPS = 8
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("n_hkl", ctypes.c_int64), ("n_pairs", ctypes.c_int64), ("pair_cap", ctypes.c_int64),
+                ("useful_evals", ctypes.c_int64), ("overflow", ctypes.c_int32), ("n_stamps", ctypes.c_int32),
+                ("clock_khz", ctypes.c_int64), ("stamp", ctypes.c_uint64 * STATS_STAMPS)]
+
+
+STATS_STEPS = ("reflection_prep", "node_table", "pixel_map", "cull", "tile_order", "profile", "count")
 
 _lib = None
 
@@ -108,6 +120,9 @@ _SIGS = {
     "fdtbx_profile_pattern": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                              ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                              ctypes.c_size_t, ctypes.c_void_p]),
+    "fdtbx_profile_pattern_async": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_void_p,
+                                                   ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "fdtbx_profile_adjoint": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                                                       ctypes.c_void_p]),
     "fdtbx_adjoint_finish_workspace": (ctypes.c_size_t, [ctypes.c_int64]),
@@ -122,8 +137,29 @@ _SIGS = {
                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int64,
                                               ctypes.c_int64] + [ctypes.c_void_p] * 7 + [ctypes.c_int32] +
                                [ctypes.c_void_p] * 8 + [ctypes.c_size_t, ctypes.c_void_p]),
+    "fdtbx_profile_adjoint_pairs": (ctypes.c_int, [ctypes.c_void_p] * 8 + [ctypes.c_int64, ctypes.c_int64,
+                                                                            ctypes.c_void_p, ctypes.c_void_p,
+                                                                            ctypes.c_void_p]),
+    "fdtbx_pair_transpose_workspace": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64]),
+    "fdtbx_pair_transpose": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                            ctypes.c_void_p]),
+    "fdtbx_pair_reduce": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+    "fdtbx_backward_deterministic_workspace": (ctypes.c_size_t, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int64]),
+    "fdtbx_pattern_backward_deterministic": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                                            ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                            ctypes.c_size_t, ctypes.c_int64, ctypes.c_int64] +
+                                             [ctypes.c_void_p] * 7 + [ctypes.c_int32] + [ctypes.c_void_p] * 8 +
+                                             [ctypes.c_size_t, ctypes.c_void_p]),
+    "fdtbx_batch_backward_deterministic": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                                          ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                                          ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                                          ctypes.c_int64] + [ctypes.c_void_p] * 16 +
+                                           [ctypes.c_int64] + [ctypes.c_void_p] * 15),
     "fdtbx_batch_entry_init": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
     "fdtbx_batch_entry_size": (ctypes.c_size_t, []),
+    "fdtbx_batch_entries_check": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32]),
     "fdtbx_batch_set_globals": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
     "fdtbx_batch_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64] +
@@ -433,6 +469,40 @@ class PatternPlan:
             return out
         raise FdtbxError(-3, "pattern workspace")
 
+    def run_async(self, hkl: torch.Tensor, F2: torch.Tensor, out: torch.Tensor, stats: torch.Tensor,
+                  count: bool = False) -> torch.Tensor:
+        """fdtbx_profile_pattern_async into out with the plan's current capacity: no host round
+        trip, so it can be captured in a graph.  stats: a device buffer of sizeof(fdtbx_stats)
+        bytes (new_stats()); read it after the stream with read_stats() and, on overflow,
+        grow(n_pairs) and run again."""
+        _check(lib().fdtbx_profile_pattern_async(ctypes.byref(self.model), _ptr(hkl), self.n_hkl, _ptr(F2), _ptr(out),
+                                                 self.pair_cap, 1 if count else 0, _ptr(stats), _ptr(self.ws),
+                                                 self.ws_bytes, _stream()))
+        return out
+
+    def grow(self, n_pairs: int):
+        """Capacity for at least n_pairs culling-list entries (reallocates the workspace)."""
+        if n_pairs > self.pair_cap:
+            self.pair_cap = int(n_pairs * 1.05) + 1024
+            self._alloc()
+
+
+def new_stats(device="cuda") -> torch.Tensor:
+    """A device buffer for one fdtbx_stats."""
+    return torch.zeros(ctypes.sizeof(Stats), dtype=torch.uint8, device=device)
+
+
+def read_stats(stats: torch.Tensor) -> dict:
+    """The fdtbx_stats in a device buffer (synchronises), with per-step milliseconds."""
+    raw = bytes(stats.cpu().numpy().tobytes())
+    st = Stats.from_buffer_copy(raw)
+    khz = max(int(st.clock_khz), 1)
+    stamps = [int(v) for v in st.stamp]
+    ms = {name: (stamps[k + 1] - stamps[k]) / khz for k, name in enumerate(STATS_STEPS)}
+    return {"n_hkl": int(st.n_hkl), "n_pairs": int(st.n_pairs), "pair_cap": int(st.pair_cap),
+            "useful_evals": int(st.useful_evals), "overflow": bool(st.overflow), "clock_khz": int(st.clock_khz),
+            "ms": ms, "total_ms": (stamps[-1] - stamps[0]) / khz}
+
 
 # ----------------------------------------------------------------------------- adjoint
 GLOBAL_NAMES = ("sigma_theta", "gamma_theta", "N_base_a", "N_base_b", "N_base_c", "g_a", "g_b", "g_c",
@@ -448,6 +518,44 @@ def profile_adjoint(model: Model, refl, nodes, pix, tile, offsets, idx, grad_ima
     sums = torch.empty((n, 6), dtype=torch.float64, device=refl.device)
     _check(lib().fdtbx_profile_adjoint(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(tile), _ptr(offsets),
                                        _ptr(idx), _ptr(order), n, _ptr(grad_image), _ptr(sums), _stream()))
+    return sums
+
+
+def profile_adjoint_pairs(model: Model, refl, nodes, pix, tile, offsets, idx, grad_image: torch.Tensor,
+                          order=None) -> torch.Tensor:
+    """fdtbx_profile_adjoint_pairs: per-pair partial sums float32 [n_pairs][12] (the pair's
+    reflection's six, then its Friedel mate's six)."""
+    n = int(refl.shape[0])
+    _dev(grad_image, torch.float32, "grad_image")
+    cap = int(idx.shape[0])
+    partials = torch.empty((max(cap, 1), 12), dtype=torch.float32, device=refl.device)
+    _check(lib().fdtbx_profile_adjoint_pairs(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(tile),
+                                             _ptr(offsets), _ptr(idx), _ptr(order), n, cap, _ptr(grad_image),
+                                             _ptr(partials), _stream()))
+    return partials[:cap]
+
+
+def pair_transpose(n_hkl: int, idx: torch.Tensor, n_pairs_dev: Optional[torch.Tensor] = None):
+    """fdtbx_pair_transpose: (refl_ptr int64 [n_hkl+1], refl_pairs int32 [len(idx)])."""
+    L = lib()
+    cap = int(idx.shape[0])
+    dev = idx.device
+    refl_ptr = torch.empty(n_hkl + 1, dtype=torch.int64, device=dev)
+    refl_pairs = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    wsb = L.fdtbx_pair_transpose_workspace(n_hkl, cap)
+    if wsb == 0:
+        raise FdtbxError(-5, "fdtbx_pair_transpose_workspace: sizes out of range")
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    _check(L.fdtbx_pair_transpose(n_hkl, _ptr(idx), cap, _ptr(n_pairs_dev), _ptr(refl_ptr), _ptr(refl_pairs), _ptr(ws),
+                                  wsb, _stream()))
+    return refl_ptr, refl_pairs[:cap]
+
+
+def pair_reduce(n_hkl: int, refl_ptr, refl_pairs, partials, mate=None, updown: bool = False) -> torch.Tensor:
+    """fdtbx_pair_reduce: per-reflection sums float64 [n_hkl][6] in a fixed order."""
+    sums = torch.empty((n_hkl, 6), dtype=torch.float64, device=refl_ptr.device)
+    _check(lib().fdtbx_pair_reduce(n_hkl, _ptr(refl_ptr), _ptr(refl_pairs), _ptr(partials), _ptr(mate),
+                                   1 if updown else 0, _ptr(sums), _stream()))
     return sums
 
 
@@ -481,14 +589,22 @@ def sf_adjoint(cell: Cell, atoms: dict, hkl, F, dF2):
     return out
 
 
-def pattern_backward(plan: "PatternPlan", hkl, F, grad_image, atoms: Optional[dict]):
-    """fdtbx_pattern_backward after plan.run(hkl, |F|^2): (atom gradients dict or None,
-    d_globals float64 [N_GLOBALS], dF2 float32 [n_hkl])."""
+def pattern_backward(plan: "PatternPlan", hkl, F, grad_image, atoms: Optional[dict], deterministic: bool = False):
+    """fdtbx_pattern_backward (or, with deterministic, fdtbx_pattern_backward_deterministic:
+    fixed-order sums, the same bits on every run) after plan.run(hkl, |F|^2): (atom gradients
+    dict or None, d_globals float64 [N_GLOBALS], dF2 float32 [n_hkl])."""
     L = lib()
     n_hkl = plan.n_hkl
     dev = hkl.device
     n_atoms = int(atoms["x"].shape[0]) if atoms is not None else 0
-    wsb = L.fdtbx_backward_workspace(n_hkl, n_atoms)
+    if deterministic:
+        wsb = L.fdtbx_backward_deterministic_workspace(n_hkl, n_atoms, plan.pair_cap)
+        if wsb == 0:
+            raise FdtbxError(-5, "fdtbx_backward_deterministic_workspace: sizes out of range")
+        entry = L.fdtbx_pattern_backward_deterministic
+    else:
+        wsb = L.fdtbx_backward_workspace(n_hkl, n_atoms)
+        entry = L.fdtbx_pattern_backward
     ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=dev)
     glob = torch.empty(N_GLOBALS, dtype=torch.float64, device=dev)
     dF2 = torch.empty(n_hkl, dtype=torch.float32, device=dev)
@@ -501,7 +617,6 @@ def pattern_backward(plan: "PatternPlan", hkl, F, grad_image, atoms: Optional[di
         a = [_ptr(atoms[k]) for k in ("x", "y", "z", "B", "occ", "type", "ff")]
         d = [_ptr(out[k]) for k in ("x", "y", "z", "B", "occ")]
         nt = int(atoms["ff"].shape[0])
-    _check(L.fdtbx_pattern_backward(ctypes.byref(plan.model), _ptr(hkl), n_hkl, _ptr(F), _ptr(grad_image), _ptr(plan.ws),
-                                    plan.ws_bytes, plan.pair_cap, n_atoms, *a, nt, *d, _ptr(glob), _ptr(dF2), _ptr(ws),
-                                    wsb, _stream()))
+    _check(entry(ctypes.byref(plan.model), _ptr(hkl), n_hkl, _ptr(F), _ptr(grad_image), _ptr(plan.ws), plan.ws_bytes,
+                 plan.pair_cap, n_atoms, *a, nt, *d, _ptr(glob), _ptr(dF2), _ptr(ws), wsb, _stream()))
     return out, glob, dF2

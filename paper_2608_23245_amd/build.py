@@ -34,6 +34,7 @@ SOURCES = {
     "cyl.hip": ["-ffp-contract=off"],
     "points.hip": ["-ffp-contract=off"],
     "order.hip": [],
+    "pairs.hip": [],
     "capi.hip": [],
 }
 

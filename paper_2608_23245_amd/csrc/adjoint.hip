@@ -38,35 +38,69 @@ __global__ void __launch_bounds__(64 * WAVES) k_profile_adj(ProfParams q, const 
                                                             const double* __restrict__ tile,
                                                             const int64_t* __restrict__ offsets,
                                                             const int32_t* __restrict__ idx,
-                                                            const float* __restrict__ grad_image, double* __restrict__ sums,
+                                                            const float* __restrict__ grad_image, int64_t n_hkl,
+                                                            double* __restrict__ sums, float* __restrict__ partials,
                                                             const int32_t* __restrict__ order) {
   __shared__ float4 qn[128 * WAVES];
   __shared__ float2 qd[128 * WAVES];
   __shared__ int bq[64 * WAVES];
   const int t = order ? order[blockIdx.x] : tile_of_block(q, blockIdx.x);
   if (t < 0) return;
-  adjoint_tile<LS, WAVES>(q, refl, nodes, pix, tile, offsets, idx, grad_image, sums, t, qn, qd, bq);
+  adjoint_tile<LS, WAVES>(q, refl, nodes, pix, tile, offsets, idx, grad_image, n_hkl, sums, partials, t, qn, qd, bq);
 }
 
 template <int WAVES>
 static void launch_adj(const ProfParams& q, dim3 grid, hipStream_t s, const float* refl, const float* nodes,
                        const double* pix, const double* tile, const int64_t* offsets, const int32_t* idx,
-                       const int32_t* order, const float* grad_image, double* sums) {
+                       const int32_t* order, const float* grad_image, int64_t n_hkl, double* sums, float* partials) {
   const dim3 block(64 * WAVES);
   if (q.lineshape == FDTBX_LINESHAPE_GAUSSIAN)
     hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_GAUSSIAN, WAVES>), grid, block, 0, s, q, refl, nodes, pix, tile,
-                       offsets, idx, grad_image, sums, order);
+                       offsets, idx, grad_image, n_hkl, sums, partials, order);
   else if (q.lineshape == FDTBX_LINESHAPE_HOSEMANN)
     hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_HOSEMANN, WAVES>), grid, block, 0, s, q, refl, nodes, pix, tile,
-                       offsets, idx, grad_image, sums, order);
+                       offsets, idx, grad_image, n_hkl, sums, partials, order);
   else
     hipLaunchKernelGGL((k_profile_adj<FDTBX_LINESHAPE_LAUE, WAVES>), grid, block, 0, s, q, refl, nodes, pix, tile, offsets,
-                       idx, grad_image, sums, order);
+                       idx, grad_image, n_hkl, sums, partials, order);
 }
 
 __global__ void k_zero_f64(double* __restrict__ v, int64_t n) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) v[k] = 0.0;
+}
+
+__global__ void k_zero_f32(float* __restrict__ v, int64_t n) {
+  int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) v[k] = 0.0f;
+}
+
+// ---------------------------------------------------------------- fixed-order reduction
+// sums[r][c] = sum over the pairs p of reflection r (refl_pairs[refl_ptr[r] .. refl_ptr[r+1]),
+// ascending culling-list position) of partials[p][c], then over the pairs of its mate m
+// (mate[r], or n - 1 - r when mate is NULL and updown is set; none otherwise) of
+// partials[p][6 + c]; binary64, one thread per reflection, a fixed order.
+__global__ void k_pair_reduce(int64_t n, const int64_t* __restrict__ refl_ptr, const int32_t* __restrict__ refl_pairs,
+                              const float* __restrict__ partials, const int64_t* __restrict__ mate, int32_t updown,
+                              double* __restrict__ sums) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t k = refl_ptr[r]; k < refl_ptr[r + 1]; ++k) {
+    const float* o = partials + 12 * (int64_t)refl_pairs[k];
+#pragma unroll
+    for (int c = 0; c < 6; ++c) v[c] += (double)o[c];
+  }
+  const int64_t m = mate ? mate[r] : (updown ? n - 1 - r : -1);
+  if (m >= 0) {
+    for (int64_t k = refl_ptr[m]; k < refl_ptr[m + 1]; ++k) {
+      const float* o = partials + 12 * (int64_t)refl_pairs[k] + 6;
+#pragma unroll
+      for (int c = 0; c < 6; ++c) v[c] += (double)o[c];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 6; ++c) sums[6 * r + c] = v[c];
 }
 
 // ---------------------------------------------------------------- chain rule per reflection
@@ -284,7 +318,8 @@ __global__ void __launch_bounds__(64) k_b_profile_adj(const fdtbx_batch_entry* _
                                                       const float* __restrict__ nodes, const double* __restrict__ pix,
                                                       const double* __restrict__ tile, const int64_t* __restrict__ rowptr,
                                                       const int32_t* __restrict__ idx, const float* __restrict__ grad_image,
-                                                      double* __restrict__ sums, unsigned long long* __restrict__ counter) {
+                                                      double* __restrict__ sums, float* __restrict__ partials,
+                                                      unsigned long long* __restrict__ counter) {
   __shared__ float4 qn[128];
   __shared__ float2 qd[128];
   __shared__ int bq[64];
@@ -305,15 +340,16 @@ __global__ void __launch_bounds__(64) k_b_profile_adj(const fdtbx_batch_entry* _
     const int32_t* ix = idx + e.pair_off;
     const float* gi = grad_image + e.pix_off;
     double* sm = sums + 6 * e.hkl_off;
+    float* pt = partials ? partials + 12 * e.pair_off : nullptr;
     switch (q.lineshape) {  // uniform across the wave
       case FDTBX_LINESHAPE_GAUSSIAN:
-        adjoint_tile<FDTBX_LINESHAPE_GAUSSIAN, 1>(q, rf, nd, px, tb, rp, ix, gi, sm, t, qn, qd, bq);
+        adjoint_tile<FDTBX_LINESHAPE_GAUSSIAN, 1>(q, rf, nd, px, tb, rp, ix, gi, e.n_hkl, sm, pt, t, qn, qd, bq);
         break;
       case FDTBX_LINESHAPE_HOSEMANN:
-        adjoint_tile<FDTBX_LINESHAPE_HOSEMANN, 1>(q, rf, nd, px, tb, rp, ix, gi, sm, t, qn, qd, bq);
+        adjoint_tile<FDTBX_LINESHAPE_HOSEMANN, 1>(q, rf, nd, px, tb, rp, ix, gi, e.n_hkl, sm, pt, t, qn, qd, bq);
         break;
       default:
-        adjoint_tile<FDTBX_LINESHAPE_LAUE, 1>(q, rf, nd, px, tb, rp, ix, gi, sm, t, qn, qd, bq);
+        adjoint_tile<FDTBX_LINESHAPE_LAUE, 1>(q, rf, nd, px, tb, rp, ix, gi, e.n_hkl, sm, pt, t, qn, qd, bq);
     }
   }
 }
@@ -375,7 +411,8 @@ __global__ void __launch_bounds__(kSAThreads) k_b_sf_adj(const fdtbx_batch_entry
   const int64_t al = (item & ((1ll << 40) - 1)) + threadIdx.x;
   const bool have = al < e.n_atoms;
   const int64_t a = e.atom_off + al;
-  const int n_types = e.n_types;
+  // kept in 1..kSAMaxTypes by fdtbx_batch_entries_check; clamped so the LDS table stays in bounds
+  const int n_types = e.n_types < 1 ? 1 : (e.n_types > kSAMaxTypes ? kSAMaxTypes : e.n_types);
   const float* ffm = ff + 9 * e.ff_off;
   const double ax = have ? x[a] : 0.0, ay = have ? y[a] : 0.0, az = have ? z[a] : 0.0;
   int ta = have ? type[a] : 0;
@@ -437,11 +474,15 @@ __global__ void k_b_set_globals(fdtbx_batch_entry* __restrict__ ent, int32_t n_m
   const double* gl = glob + kNG * (int64_t)m;
   d.sigma_theta = gl[0];
   d.gamma_theta = gl[1];
+  int32_t stale = 0;
   for (int i = 0; i < 3; ++i) {
     d.N_base[i] = gl[2 + i];
     d.g[i] = gl[5 + i];
     d.B_axis[i] = gl[8 + i];
+    // a larger g or a smaller N_base widens the support beyond the lists' (NaN counts as wider)
+    if (!(gl[5 + i] <= ent[m].setup_g[i]) || !(gl[2 + i] >= ent[m].setup_N_base[i])) stale = 1;
   }
+  ent[m].stale = stale;
 }
 
 static constexpr unsigned kPersistentBlocksAdj = 8192;
@@ -466,16 +507,27 @@ int launch_batch_backward(const fdtbx_batch_entry* ent, int32_t n_models, const 
                           const double* pix, const double* tile, const int64_t* rowptr, const int32_t* idx, const float* F,
                           const float* refl, const float* nodes, const float* grad_image, double* sums, double* part,
                           float* dF2, float* d_x, float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals,
-                          int64_t* counter, hipStream_t s) {
-  hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(6 * n_hkl_total, 256)), dim3(256), 0, s, sums, 6 * n_hkl_total);
-  FDTBX_LAUNCH_CHECK("batch adjoint zero");
+                          int64_t* counter, const PairOrder* fixed, hipStream_t s) {
+  if (fixed) {
+    hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)ceil_div(12 * fixed->n_pairs, 256)), dim3(256), 0, s, fixed->partials,
+                       12 * fixed->n_pairs);
+    FDTBX_LAUNCH_CHECK("batch adjoint partials zero");
+  } else {
+    hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(6 * n_hkl_total, 256)), dim3(256), 0, s, sums, 6 * n_hkl_total);
+    FDTBX_LAUNCH_CHECK("batch adjoint zero");
+  }
   hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, (double*)counter, (int64_t)1);
   FDTBX_LAUNCH_CHECK("batch adjoint counter");
   if (n_items > 0) {
     unsigned nb = n_items < (int64_t)kPersistentBlocksAdj ? (unsigned)n_items : kPersistentBlocksAdj;
     hipLaunchKernelGGL(k_b_profile_adj, dim3(nb), dim3(64), 0, s, ent, items, n_items, refl, nodes, pix, tile, rowptr, idx,
-                       grad_image, sums, (unsigned long long*)counter);
+                       grad_image, sums, fixed ? fixed->partials : nullptr, (unsigned long long*)counter);
     FDTBX_LAUNCH_CHECK("batch profile adjoint");
+  }
+  if (fixed && n_hkl_total > 0) {
+    hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)ceil_div(n_hkl_total, 256)), dim3(256), 0, s, n_hkl_total,
+                       fixed->refl_ptr, fixed->refl_pairs, fixed->partials, fixed->mate, 0, sums);
+    FDTBX_LAUNCH_CHECK("batch adjoint pair reduction");
   }
   if (n_rb > 0) {
     hipLaunchKernelGGL(k_b_finish, dim3((unsigned)n_rb), dim3(kFinThreads), 0, s, ent, refl_blocks, hkl, refl, sums, F, dF2,
@@ -493,6 +545,28 @@ int launch_batch_backward(const fdtbx_batch_entry* ent, int32_t n_models, const 
 }
 }  // namespace fdtbx
 
+namespace fdtbx {
+// The per-tile adjoint launch: atomic binary64 sums, or per-pair partials.
+static int launch_profile_adjoint(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
+                                  const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
+                                  int64_t n_hkl, const float* grad_image, double* sums, float* partials, hipStream_t s) {
+  ProfParams q;
+  prof_params(model, &q);
+  const dim3 grid((unsigned)(order ? order_grid(q.lcols, q.lrows) : tile_grid(q)));
+  int waves = 1;
+  const int rc = tile_waves(&model->geom, (int64_t)q.lcols * q.lrows, &waves);
+  if (rc) return rc;
+  if (waves == 4)
+    launch_adj<4>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, grad_image, n_hkl, sums, partials);
+  else if (waves == 2)
+    launch_adj<2>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, grad_image, n_hkl, sums, partials);
+  else
+    launch_adj<1>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, grad_image, n_hkl, sums, partials);
+  FDTBX_LAUNCH_CHECK("profile adjoint");
+  return FDTBX_OK;
+}
+}  // namespace fdtbx
+
 extern "C" int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
                                      const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
                                      int64_t n_hkl, const float* grad_image, double* sums, void* stream) {
@@ -503,22 +577,40 @@ extern "C" int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl
   if (n_hkl == 0) return FDTBX_OK;  // no reflections: nothing to sum
   if (!refl || !nodes || !pix || !tile || !offsets || !idx || !grad_image || !sums)
     return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
-  ProfParams q;
-  prof_params(model, &q);
   hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(6 * n_hkl, 256)), dim3(256), 0, s, sums, 6 * n_hkl);
   FDTBX_LAUNCH_CHECK("adjoint zero");
-  const dim3 grid((unsigned)(order ? order_grid(q.lcols, q.lrows) : tile_grid(q)));
-  int waves = 1;
-  rc = tile_waves(&model->geom, (int64_t)q.lcols * q.lrows, &waves);
+  return launch_profile_adjoint(model, refl, nodes, pix, tile, offsets, idx, order, n_hkl, grad_image, sums, nullptr, s);
+}
+
+extern "C" int fdtbx_profile_adjoint_pairs(const fdtbx_model* model, const float* refl, const float* nodes,
+                                           const double* pix, const double* tile, const int64_t* offsets, const int32_t* idx,
+                                           const int32_t* order, int64_t n_hkl, int64_t pair_cap, const float* grad_image,
+                                           float* partials, void* stream) {
+  if (!model) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl < 0 || pair_cap < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl and pair_cap must be non-negative");
+  int rc = check_model(model);
   if (rc) return rc;
-  if (waves == 4)
-    launch_adj<4>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, grad_image, sums);
-  else if (waves == 2)
-    launch_adj<2>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, grad_image, sums);
-  else
-    launch_adj<1>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, grad_image, sums);
-  FDTBX_LAUNCH_CHECK("profile adjoint");
+  if (pair_cap == 0) return FDTBX_OK;
+  if (!partials) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_zero_f32, dim3((unsigned)ceil_div(12 * pair_cap, 256)), dim3(256), 0, s, partials, 12 * pair_cap);
+  FDTBX_LAUNCH_CHECK("adjoint partials zero");
+  if (n_hkl == 0) return FDTBX_OK;
+  if (!refl || !nodes || !pix || !tile || !offsets || !idx || !grad_image)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  return launch_profile_adjoint(model, refl, nodes, pix, tile, offsets, idx, order, n_hkl, grad_image, nullptr, partials,
+                                s);
+}
+
+extern "C" int fdtbx_pair_reduce(int64_t n_hkl, const int64_t* refl_ptr, const int32_t* refl_pairs, const float* partials,
+                                 const int64_t* mate, int32_t updown, double* sums, void* stream) {
+  if (n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be non-negative");
+  if (n_hkl == 0) return FDTBX_OK;
+  if (!refl_ptr || !refl_pairs || !partials || !sums) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  hipLaunchKernelGGL(k_pair_reduce, dim3((unsigned)ceil_div(n_hkl, 256)), dim3(256), 0, (hipStream_t)stream, n_hkl,
+                     refl_ptr, refl_pairs, partials, mate, updown ? 1 : 0, sums);
+  FDTBX_LAUNCH_CHECK("pair reduction");
   return FDTBX_OK;
 }
 

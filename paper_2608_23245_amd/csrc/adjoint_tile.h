@@ -8,27 +8,26 @@
 namespace fdtbx {
 
 // Adjoint of eval_node for one queued node (nd = kappa, omega; dw = d omega/d sigma,
-// d omega/d gamma), weighted by gp = G L(R) of the lane's pixel.  With Z' the lineshape's
-// profile product as in eval_node:
-//   acc[0] += gp omega Z',  acc[1] += gp dw.x Z',  acc[2] += gp dw.y Z',
-//   acc[3+i] += gp omega N_i (dZ/dN_i)/C   (the profile's N-derivative at fixed u, C its
-//                                           per-reflection constant; see the header).
+// d omega/d gamma), before the lane's pixel weight (applied once per (tile, reflection) pair).
+// With Z' the lineshape's profile product as in eval_node:
+//   acc[0] += omega Z',  acc[1] += dw.x Z',  acc[2] += dw.y Z',
+//   acc[3+i] += omega N_i (dZ/dN_i)/C   (the profile's N-derivative at fixed u, C its
+//                                        per-reflection constant; see the header).
 // Laue:     S_i (4 pi cos(2 pi y_i) - S_i) prod_{j!=i} S_j^2 with S_i = sin(2 pi y_i)/y_i.
 // Gaussian: Z' (1 - 8 pi y_i^2).
 // Hosemann: Z' (c_i (1 + A_i^2) - 2 A_i)/den_i with c_i = cos(2 pi y_i) (0 where A_i is held at 0).
 template <int LS>
-__device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, float al0, float al1, float al2, float gp,
+__device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, float al0, float al1, float al2,
                                               float half_m, const HoseK& hk, float* acc) {
   float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
   float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
   if (mx <= half_m) {
     if (LS == FDTBX_LINESHAPE_GAUSSIAN) {
       const float P = __builtin_amdgcn_exp2f(kGauss * fmaf(ya, ya, fmaf(yb, yb, yc * yc)));
-      const float t = gp * P;
-      acc[0] = fmaf(nd.w, t, acc[0]);
-      acc[1] = fmaf(dw.x, t, acc[1]);
-      acc[2] = fmaf(dw.y, t, acc[2]);
-      const float t2 = nd.w * t;
+      acc[0] = fmaf(nd.w, P, acc[0]);
+      acc[1] = fmaf(dw.x, P, acc[1]);
+      acc[2] = fmaf(dw.y, P, acc[2]);
+      const float t2 = nd.w * P;
       const float m8pi = -25.132741228718345f;
       acc[3] = fmaf(t2, fmaf(m8pi, ya * ya, 1.0f), acc[3]);
       acc[4] = fmaf(t2, fmaf(m8pi, yb * yb, 1.0f), acc[4]);
@@ -40,12 +39,11 @@ __device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, 
       const float dc = fmaf(-hk.c1[2], cc, hk.c0[2]);
       const float dab = da * db;
       const float P = __builtin_amdgcn_rcpf(dab * dc);
-      const float t = gp * P;
-      acc[0] = fmaf(nd.w, t, acc[0]);
-      acc[1] = fmaf(dw.x, t, acc[1]);
-      acc[2] = fmaf(dw.y, t, acc[2]);
+      acc[0] = fmaf(nd.w, P, acc[0]);
+      acc[1] = fmaf(dw.x, P, acc[1]);
+      acc[2] = fmaf(dw.y, P, acc[2]);
       // 1/den_a = P db dc, ...
-      const float t2 = nd.w * t * P;
+      const float t2 = nd.w * P * P;
       acc[3] = fmaf(t2 * (db * dc), fmaf(ca, hk.e0[0], -hk.e1[0]), acc[3]);
       acc[4] = fmaf(t2 * (da * dc), fmaf(cb, hk.e0[1], -hk.e1[1]), acc[4]);
       acc[5] = fmaf(t2 * dab, fmaf(cc, hk.e0[2], -hk.e1[2]), acc[5]);
@@ -65,15 +63,13 @@ __device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, 
       const float Pa = Sa * Sa, Pb = Sb * Sb, Pc = Sc * Sc;
       const float Pab = Pa * Pb;
       const float P = Pab * Pc;
-      const float t = gp * P;
-      acc[0] = fmaf(nd.w, t, acc[0]);
-      acc[1] = fmaf(dw.x, t, acc[1]);
-      acc[2] = fmaf(dw.y, t, acc[2]);
+      acc[0] = fmaf(nd.w, P, acc[0]);
+      acc[1] = fmaf(dw.x, P, acc[1]);
+      acc[2] = fmaf(dw.y, P, acc[2]);
       const float four_pi = 12.566370614359172f;
-      const float t2 = gp * nd.w;
-      acc[3] = fmaf(t2, Sa * fmaf(four_pi, ca, -Sa) * (Pb * Pc), acc[3]);
-      acc[4] = fmaf(t2, Sb * fmaf(four_pi, cb, -Sb) * (Pa * Pc), acc[4]);
-      acc[5] = fmaf(t2, Sc * fmaf(four_pi, cc, -Sc) * Pab, acc[5]);
+      acc[3] = fmaf(nd.w, Sa * fmaf(four_pi, ca, -Sa) * (Pb * Pc), acc[3]);
+      acc[4] = fmaf(nd.w, Sb * fmaf(four_pi, cb, -Sb) * (Pa * Pc), acc[4]);
+      acc[5] = fmaf(nd.w, Sc * fmaf(four_pi, cc, -Sc) * Pab, acc[5]);
     }
   }
 }
@@ -82,8 +78,8 @@ __device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, 
 // The queue addresses go through threadIdx.y (always 0) so that they stay in vector
 // registers and the unrolled reads use instruction offsets.
 template <int LS>
-__device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* qd, int cnt, const float* al, float gp,
-                                               float half_m, const HoseK& hk, float* acc) {
+__device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* qd, int cnt, const float* al, float half_m,
+                                               const HoseK& hk, float* acc) {
   qn += threadIdx.y;
   qd += threadIdx.y;
   float4 nxt = qn[0];
@@ -93,7 +89,7 @@ __device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* q
     const float2 cur2 = nxt2;
     nxt = qn[jj + 1];
     nxt2 = qd[jj + 1];
-    eval_node_adj<LS>(cur, cur2, al[0], al[1], al[2], gp, half_m, hk, acc);
+    eval_node_adj<LS>(cur, cur2, al[0], al[1], al[2], half_m, hk, acc);
   }
 }
 
@@ -101,12 +97,22 @@ __device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* q
 // w + WAVES, ... of 64 pairs of the tile's list (each pair's sums go out on their own, so the
 // waves need no combining).  qn, qd: LDS queues of 128 entries per wave; bq: LDS scratch of
 // 64 ints per wave for the block test.
+//
+// Each lane holds two pixel weights: gA = L(R) (G of the pixel + G of its left-right mirror,
+// which has the same profile value from the same reflection) and gB = L(R) (G of its up-down
+// mirrors, under bit 1 of the fold), whose profile value comes from the Friedel mate -r at this
+// pixel (I_r(R, -Z) = I_{-r}(R, Z)).  Per pair the six unweighted lane sums are weighted by gA
+// into reflection r's sums and by gB into its mate's, n_hkl - 1 - r (the reflection list is
+// closed under negation in that order).  With partials == nullptr they are added into sums
+// (binary64 [n_hkl][6]) with hardware atomics; otherwise pair p of the culling lists stores its
+// twelve float32 sums (r's six, then the mate's six; zero without the up-down fold) at
+// partials[12 p], for a reduction in a fixed order (fdtbx_pair_reduce).
 template <int LS, int WAVES = 1>
 __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* __restrict__ refl, const float* __restrict__ nodes,
                                              const double* __restrict__ pix, const double* __restrict__ tile,
                                              const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
-                                             const float* __restrict__ grad_image, double* __restrict__ sums, const int t,
-                                             float4* qn, float2* qd, int* bq) {
+                                             const float* __restrict__ grad_image, int64_t n_hkl, double* __restrict__ sums,
+                                             float* __restrict__ partials, const int t, float4* qn, float2* qd, int* bq) {
   const int lane = threadIdx.x & 63;
   const int wv = WAVES > 1 ? (int)(threadIdx.x >> 6) : 0;
   qn += 128 * wv;
@@ -119,13 +125,16 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
   const double R = in ? pix[2 * ((int64_t)j * q.W + i) + 0] : 1.0e30;
   const double Z = in ? pix[2 * ((int64_t)j * q.W + i) + 1] : 0.0;
   // under the mirror folds this pixel also stands for its mirror images
-  const float gimg = in ? folded_weight(q, grad_image, i, j, tx, ty) : 0.0f;
-  const float gp = gimg * (float)(q.delta / (R + q.delta));
+  float wa = 0.0f, wb = 0.0f;
+  if (in) folded_weights(q, grad_image, i, j, tx, ty, &wa, &wb);
+  const bool mate = (q.mirror & 2) && 2 * ty + 1 != q.tiles_y;  // uniform: the tile has mirror rows
+  const float lor = (float)(q.delta / (R + q.delta));
+  const float gA = wa * lor, gB = wb * lor;
   const TileBox box = {tile[8 * (int64_t)t + 0], tile[8 * (int64_t)t + 1], tile[8 * (int64_t)t + 2],
                        tile[8 * (int64_t)t + 3]};
   const int64_t p0 = offsets[t], p1 = offsets[t + 1];
   // a tile whose pixels all carry zero weight adds nothing
-  if (__ballot(gp != 0.0f) == 0ull) return;
+  if (__ballot(gA != 0.0f || gB != 0.0f) == 0ull) return;
   // 64 pairs at a time, set up lane-parallel as in the forward tile loop
   for (int64_t base = p0 + 64 * wv; base < p1; base += 64 * WAVES) {
     int32_t rl = 0;
@@ -160,7 +169,7 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
       HoseK hk = {};
       if (LS == FDTBX_LINESHAPE_HOSEMANN) hose_constants(refl + (int64_t)FDTBX_REFL_FLOATS * r, hk);
       float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      int qlen = 0;
+      int qlen = 0, queued = 0;  // uniform
       scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int k, float4 e) {
         const unsigned long long b = __ballot(keep);
         if (keep) {
@@ -169,9 +178,10 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
           qd[pos] = *(const float2*)(nodes + (int64_t)FDTBX_NODE_FLOATS * k + 4);
         }
         qlen += __popcll(b);
+        queued += __popcll(b);
         wave_sync();
         if (qlen >= 64) {
-          walk_queue_adj<LS>(qn, qd, 64, al, gp, q.half_m, hk, acc);
+          walk_queue_adj<LS>(qn, qd, 64, al, q.half_m, hk, acc);
           qlen -= 64;
           wave_sync();
           if (lane < qlen) {
@@ -181,19 +191,44 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
           wave_sync();
         }
       });
-      walk_queue_adj<LS>(qn, qd, qlen, al, gp, q.half_m, hk, acc);
+      walk_queue_adj<LS>(qn, qd, qlen, al, q.half_m, hk, acc);
       wave_sync();
-      bool any = false;
+      if (queued == 0) continue;  // no node within reach of the tile: nothing to add
+      // the weighted lane sums are summed over the wave in binary64 (a float times a float is
+      // exact there): the pixel weights G carry both signs, and the sums cancel
+      double sA[6], sB[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      bool anyA = false, anyB = false;
 #pragma unroll
       for (int c = 0; c < 6; ++c) {
-        float v = acc[c];
-        v = wave_sum(v);
-        acc[c] = v;
-        any |= v != 0.0f;
+        sA[c] = wave_sum_f64((double)gA * (double)acc[c]);
+        anyA |= sA[c] != 0.0;
       }
-      if (lane == 0 && any) {
+      if (mate) {
 #pragma unroll
-        for (int c = 0; c < 6; ++c) unsafeAtomicAdd(&sums[6 * (int64_t)r + c], (double)acc[c]);
+        for (int c = 0; c < 6; ++c) {
+          sB[c] = wave_sum_f64((double)gB * (double)acc[c]);
+          anyB |= sB[c] != 0.0;
+        }
+      }
+      if (lane == 0 && (anyA || anyB)) {
+        if (partials) {
+          float* o = partials + 12 * (base + src);
+#pragma unroll
+          for (int c = 0; c < 6; ++c) {
+            o[c] = (float)sA[c];
+            o[6 + c] = (float)sB[c];
+          }
+        } else {
+          if (anyA) {
+#pragma unroll
+            for (int c = 0; c < 6; ++c) unsafeAtomicAdd(&sums[6 * (int64_t)r + c], sA[c]);
+          }
+          if (anyB) {
+            const int64_t rm = n_hkl - 1 - r;
+#pragma unroll
+            for (int c = 0; c < 6; ++c) unsafeAtomicAdd(&sums[6 * rm + c], sB[c]);
+          }
+        }
       }
     }
   }

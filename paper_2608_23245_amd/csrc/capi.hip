@@ -214,6 +214,82 @@ extern "C" int fdtbx_profile_pattern(const fdtbx_model* model, const int32_t* hk
   return fdtbx_profile(model, refl, nodes, pix, tile, offsets, idx, order, image, nullptr, stream);
 }
 
+namespace fdtbx {
+// The statistics' fixed fields and the first stamp.
+__global__ void k_stats_begin(fdtbx_stats* st, int64_t n_hkl, int64_t pair_cap, int64_t khz, int32_t counted) {
+  if (threadIdx.x != 0) return;
+  st->n_hkl = n_hkl;
+  st->n_pairs = 0;
+  st->pair_cap = pair_cap;
+  st->useful_evals = counted ? 0 : -1;
+  st->overflow = 0;
+  st->n_stamps = FDTBX_STATS_STAMPS;
+  st->clock_khz = khz;
+  for (int k = 0; k < FDTBX_STATS_STAMPS; ++k) st->stamp[k] = 0;
+  st->stamp[0] = wall_clock64();
+}
+
+// Stamp k: the kernels of the steps before it have finished (same stream).
+__global__ void k_stamp(fdtbx_stats* st, int k) {
+  if (threadIdx.x == 0) st->stamp[k] = wall_clock64();
+}
+}  // namespace fdtbx
+
+extern "C" int fdtbx_profile_pattern_async(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F2,
+                                           float* image, int64_t pair_cap, int32_t count_evals, fdtbx_stats* stats,
+                                           void* ws, size_t ws_bytes, void* stream) {
+  if (!model || !image || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be non-negative");
+  if (pair_cap < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "pair_cap must be non-negative");
+  int rc = check_model(model);
+  if (rc) return rc;
+  if (n_hkl > 0 && (!hkl || !F2)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  PatternLayout L = layout(model, n_hkl, pair_cap);
+  if (ws_bytes < L.total) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "pattern workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  int khz = 0;
+  if (stats) {
+    int dev = 0;
+    FDTBX_HIP(hipGetDevice(&dev));
+    FDTBX_HIP(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+    hipLaunchKernelGGL(k_stats_begin, dim3(1), dim3(64), 0, s, stats, n_hkl, pair_cap, (int64_t)khz, count_evals ? 1 : 0);
+    FDTBX_LAUNCH_CHECK("stats");
+  }
+  auto stamp = [&](int k) -> int {
+    if (!stats) return FDTBX_OK;
+    hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, s, stats, k);
+    FDTBX_LAUNCH_CHECK("stats stamp");
+    return FDTBX_OK;
+  };
+  char* w = (char*)ws;
+  float* refl = (float*)(w + L.refl);
+  double* cull = (double*)(w + L.cull);
+  float* nodes = (float*)(w + L.nodes);
+  double* pix = (double*)(w + L.pix);
+  double* tile = (double*)(w + L.tile);
+  int64_t* offsets = (int64_t*)(w + L.offsets);
+  int32_t* idx = (int32_t*)(w + L.idx);
+  int32_t* order = (int32_t*)(w + L.order);
+  rc = fdtbx_reflection_prep(model, hkl, n_hkl, F2, refl, cull, stream);
+  if (rc || (rc = stamp(1))) return rc;
+  rc = fdtbx_node_table(&model->dis, &model->quad, nodes, stream);
+  if (rc || (rc = stamp(2))) return rc;
+  rc = fdtbx_pixel_map(&model->geom, pix, tile, stream);
+  if (rc || (rc = stamp(3))) return rc;
+  rc = cull_on_device(&model->geom, tile, n_hkl, cull, offsets, idx, pair_cap, stats, w + L.cullws,
+                      fdtbx_cull_workspace(&model->geom, n_hkl), s);
+  if (rc || (rc = stamp(4))) return rc;
+  rc = fdtbx_tile_order(&model->geom, offsets, order, w + L.orderws, fdtbx_tile_order_workspace(&model->geom), stream);
+  if (rc || (rc = stamp(5))) return rc;
+  rc = fdtbx_profile(model, refl, nodes, pix, tile, offsets, idx, order, image, nullptr, stream);
+  if (rc || (rc = stamp(6))) return rc;
+  if (count_evals && stats) {
+    rc = fdtbx_profile(model, refl, nodes, pix, tile, offsets, idx, order, nullptr, &stats->useful_evals, stream);
+    if (rc) return rc;
+  }
+  return stamp(7);
+}
+
 extern "C" size_t fdtbx_backward_workspace(int64_t n_hkl, int64_t n_atoms) {
   if (n_hkl < 0) return 0;
   if (n_hkl == 0) return 256;  // nothing is used; a non-zero size keeps callers' allocations valid
@@ -277,6 +353,84 @@ extern "C" int fdtbx_pattern_backward(const fdtbx_model* model, const int32_t* h
                           d_occ, w, fdtbx_sf_adjoint_workspace(n_hkl, n_atoms), stream);
 }
 
+extern "C" size_t fdtbx_backward_deterministic_workspace(int64_t n_hkl, int64_t n_atoms, int64_t pair_cap) {
+  if (n_hkl < 0 || pair_cap < 0) return 0;
+  size_t b = fdtbx_backward_workspace(n_hkl, n_atoms);
+  if (n_hkl == 0) return b;
+  const size_t t = fdtbx_pair_transpose_workspace(n_hkl, pair_cap);
+  if (t == 0) return 0;
+  b += align_up((size_t)pair_cap * 12 * sizeof(float), 256);       // per-pair partials
+  b += align_up((size_t)(n_hkl + 1) * sizeof(int64_t), 256);      // reflection row pointers
+  b += align_up((size_t)pair_cap * sizeof(int32_t), 256);         // pairs in reflection order
+  b += align_up(t, 256);
+  return b;
+}
+
+extern "C" int fdtbx_pattern_backward_deterministic(
+    const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F, const float* grad_image,
+    const void* fwd_ws, size_t fwd_ws_bytes, int64_t pair_cap, int64_t n_atoms, const float* x, const float* y,
+    const float* z, const float* B, const float* occ, const int32_t* type, const float* ff, int32_t n_types, float* d_x,
+    float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals, float* dF2, void* ws, size_t ws_bytes,
+    void* stream) {
+  if (!model || !grad_image || !fwd_ws || !d_globals || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl < 0 || pair_cap < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "bad sizes");
+  int rc = check_model(model);
+  if (rc) return rc;
+  const bool atoms = d_x || d_y || d_z || d_B || d_occ;
+  if (n_hkl == 0)  // no reflections: every gradient is zero, as in fdtbx_pattern_backward
+    return fdtbx_pattern_backward(model, hkl, n_hkl, F, grad_image, fwd_ws, fwd_ws_bytes, pair_cap, n_atoms, x, y, z, B,
+                                  occ, type, ff, n_types, d_x, d_y, d_z, d_B, d_occ, d_globals, dF2, ws, ws_bytes, stream);
+  if (!hkl || !F) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (atoms && (n_atoms <= 0 || !x || !y || !z || !B || !occ || !type || !ff))
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "atom arrays required for atom gradients");
+  PatternLayout L = layout(model, n_hkl, pair_cap);
+  if (fwd_ws_bytes < L.total) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "forward workspace smaller than the layout for pair_cap");
+  const size_t need = fdtbx_backward_deterministic_workspace(n_hkl, atoms ? n_atoms : 0, pair_cap);
+  if (need == 0) return fail(FDTBX_ERR_UNSUPPORTED, "deterministic backward: pair_cap or n_hkl too large");
+  if (ws_bytes < need) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "backward workspace too small");
+  const char* fw = (const char*)fwd_ws;
+  const float* refl = (const float*)(fw + L.refl);
+  const float* nodes = (const float*)(fw + L.nodes);
+  const double* pix = (const double*)(fw + L.pix);
+  const double* tile = (const double*)(fw + L.tile);
+  const int64_t* offsets = (const int64_t*)(fw + L.offsets);
+  const int32_t* idx = (const int32_t*)(fw + L.idx);
+  const int32_t* order = (const int32_t*)(fw + L.order);
+  int32_t tiles_x = 0, tiles_y = 0;
+  rc = fdtbx_tile_grid(&model->geom, &tiles_x, &tiles_y);
+  if (rc) return rc;
+  const int64_t* n_pairs_dev = offsets + (int64_t)tiles_x * tiles_y;  // the total, written by fdtbx_cull
+  char* w = (char*)ws;
+  double* sums = (double*)w;
+  w += align_up((size_t)n_hkl * 6 * sizeof(double), 256);
+  void* fin = w;
+  const size_t fin_bytes = fdtbx_adjoint_finish_workspace(n_hkl);
+  w += align_up(fin_bytes, 256);
+  float* g2 = dF2 ? dF2 : (float*)w;
+  w += align_up((size_t)n_hkl * sizeof(float), 256);
+  void* sfw = w;
+  if (atoms) w += align_up(fdtbx_sf_adjoint_workspace(n_hkl, n_atoms), 256);
+  float* partials = (float*)w;
+  w += align_up((size_t)pair_cap * 12 * sizeof(float), 256);
+  int64_t* refl_ptr = (int64_t*)w;
+  w += align_up((size_t)(n_hkl + 1) * sizeof(int64_t), 256);
+  int32_t* refl_pairs = (int32_t*)w;
+  w += align_up((size_t)pair_cap * sizeof(int32_t), 256);
+  rc = fdtbx_profile_adjoint_pairs(model, refl, nodes, pix, tile, offsets, idx, order, n_hkl, pair_cap, grad_image,
+                                   partials, stream);
+  if (rc) return rc;
+  rc = fdtbx_pair_transpose(n_hkl, idx, pair_cap, n_pairs_dev, refl_ptr, refl_pairs, w,
+                            fdtbx_pair_transpose_workspace(n_hkl, pair_cap), stream);
+  if (rc) return rc;
+  rc = fdtbx_pair_reduce(n_hkl, refl_ptr, refl_pairs, partials, nullptr, (model->geom.mirror & 2) ? 1 : 0, sums, stream);
+  if (rc) return rc;
+  rc = fdtbx_adjoint_finish(model, hkl, n_hkl, refl, sums, F, g2, d_globals, fin, fin_bytes, stream);
+  if (rc) return rc;
+  if (!atoms) return FDTBX_OK;
+  return fdtbx_sf_adjoint(&model->cell, n_atoms, x, y, z, B, occ, type, ff, n_types, hkl, n_hkl, F, g2, d_x, d_y, d_z, d_B,
+                          d_occ, sfw, fdtbx_sf_adjoint_workspace(n_hkl, n_atoms), stream);
+}
+
 extern "C" int fdtbx_batch_forward(const fdtbx_batch_entry* entries, int32_t n_models, const int64_t* refl_blocks, int64_t n_rb,
                                    const int64_t* node_blocks, int64_t n_nb, const int64_t* tile_items, int64_t n_items,
                                    const int32_t* hkl, const float* x, const float* y, const float* z, const float* B,
@@ -313,7 +467,28 @@ extern "C" int fdtbx_batch_backward(const fdtbx_batch_entry* entries, int32_t n_
     return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
   return launch_batch_backward(entries, n_models, refl_blocks, n_rb, model_rb, atom_blocks, n_ab, tile_items, n_items,
                                n_hkl_total, hkl, x, y, z, B, occ, type, ff, pix, tile, rowptr, idx, F, refl, nodes, grad_image,
-                               sums, part, dF2, d_x, d_y, d_z, d_B, d_occ, d_globals, counter, (hipStream_t)stream);
+                               sums, part, dF2, d_x, d_y, d_z, d_B, d_occ, d_globals, counter, nullptr, (hipStream_t)stream);
+}
+
+extern "C" int fdtbx_batch_backward_deterministic(
+    const fdtbx_batch_entry* entries, int32_t n_models, const int64_t* refl_blocks, int64_t n_rb, const int64_t* model_rb,
+    const int64_t* atom_blocks, int64_t n_ab, const int64_t* tile_items, int64_t n_items, int64_t n_hkl_total,
+    const int32_t* hkl, const float* x, const float* y, const float* z, const float* B, const float* occ,
+    const int32_t* type, const float* ff, const double* pix, const double* tile, const int64_t* rowptr, const int32_t* idx,
+    const float* F, const float* refl, const float* nodes, const float* grad_image, int64_t n_pairs_total,
+    const int64_t* refl_ptr, const int32_t* refl_pairs, const int64_t* mate, float* partials, double* sums, double* part,
+    float* dF2, float* d_x, float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals, int64_t* counter,
+    void* stream) {
+  if (!entries || n_models <= 0 || n_rb < 0 || n_ab < 0 || n_items < 0 || n_hkl_total < 0 || n_pairs_total < 0)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "bad sizes");
+  if (!refl_blocks || !model_rb || !atom_blocks || !tile_items || !hkl || !x || !y || !z || !B || !occ || !type || !ff ||
+      !pix || !tile || !rowptr || !idx || !F || !refl || !nodes || !grad_image || !sums || !part || !dF2 || !d_globals ||
+      !counter || !refl_ptr || !mate || (n_pairs_total > 0 && (!refl_pairs || !partials)))
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  const PairOrder fixed = {partials, n_pairs_total, refl_ptr, refl_pairs, mate};
+  return launch_batch_backward(entries, n_models, refl_blocks, n_rb, model_rb, atom_blocks, n_ab, tile_items, n_items,
+                               n_hkl_total, hkl, x, y, z, B, occ, type, ff, pix, tile, rowptr, idx, F, refl, nodes, grad_image,
+                               sums, part, dF2, d_x, d_y, d_z, d_B, d_occ, d_globals, counter, &fixed, (hipStream_t)stream);
 }
 
 extern "C" size_t fdtbx_batch_entry_size(void) { return sizeof(fdtbx_batch_entry); }

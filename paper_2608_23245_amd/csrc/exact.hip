@@ -567,14 +567,18 @@ __global__ void __launch_bounds__(64) k_sb_mask(CullParams q, const double* __re
 static constexpr int kWordsPer = 16;
 static constexpr int kTB = kSB * kSB;  // tiles and waves per block
 
+// MODE 1 (fill) returns at once when *total exceeds cap: the lists do not fit (the launch
+// that culls without a host round trip leaves the decision to the device).
 template <int MODE>
 __global__ void __launch_bounds__(64 * kTB) k_tile_lists(CullParams q, const double* __restrict__ tile,
                                                          const uint64_t* __restrict__ mask, const double* __restrict__ cull,
                                                          int64_t* __restrict__ counts, int32_t* __restrict__ part,
-                                                         int32_t* __restrict__ idx) {
+                                                         int32_t* __restrict__ idx, const int64_t* __restrict__ total,
+                                                         int64_t cap) {
   __shared__ int32_t cand_all[kTB][kWordsPer * 64];
   __shared__ double boxes[kTB][6];
   __shared__ int32_t hits[kTB][kTB];  // [wave][tile]
+  if (MODE && *total > cap) return;  // uniform across the grid
   const int s = blockIdx.x;
   const int sx = s % q.sb_x, sy = s / q.sb_x;
   const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
@@ -809,7 +813,7 @@ extern "C" int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_
   hipLaunchKernelGGL(k_sb_mask, dim3((unsigned)q.n_words), dim3(64), 0, s, q, sb, cull, mask);
   FDTBX_LAUNCH_CHECK("cull masks");
   hipLaunchKernelGGL(k_tile_lists<0>, dim3((unsigned)nsb), dim3(64 * kTB), 0, s, q, tile, mask, cull, offsets, part,
-                     (int32_t*)nullptr);
+                     (int32_t*)nullptr, (const int64_t*)nullptr, (int64_t)0);
   FDTBX_LAUNCH_CHECK("cull count");
   hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, offsets, n_tiles, total);
   FDTBX_LAUNCH_CHECK("cull scan");
@@ -821,11 +825,64 @@ extern "C" int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_
   if (h_total > cap || (h_total > 0 && !idx)) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "culling pair capacity too small");
   if (h_total > 0) {
     hipLaunchKernelGGL(k_tile_lists<1>, dim3((unsigned)nsb), dim3(64 * kTB), 0, s, q, tile, mask, cull, offsets, part,
-                       idx);
+                       idx, (const int64_t*)total, cap);
     FDTBX_LAUNCH_CHECK("cull fill");
   }
   return FDTBX_OK;
 }
+
+namespace fdtbx {
+// Closes the exclusive scan of the counts: offsets[n_tiles] = total and the statistics; if the
+// lists need more than cap pairs every list is made empty (offsets all 0) and the overflow
+// flag is set, so the kernels after it read nothing.
+__global__ void k_cull_commit(int64_t* __restrict__ offsets, int64_t n_tiles, const int64_t* __restrict__ total, int64_t cap,
+                              fdtbx_stats* __restrict__ stats) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t t = *total;
+  const bool over = t > cap;
+  if (k <= n_tiles && (over || k == n_tiles)) offsets[k] = over ? 0 : t;
+  if (k == 0 && stats) {
+    stats->n_pairs = t;
+    stats->overflow = over ? 1 : 0;
+  }
+}
+
+// fdtbx_cull without a host round trip: the capacity check happens on the device.
+int cull_on_device(const fdtbx_geometry* geom, const double* tile, int64_t n_hkl, const double* cull, int64_t* offsets,
+                   int32_t* idx, int64_t cap, fdtbx_stats* stats, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (n_hkl == 0) return fill(offsets, (int64_t)tiles_x_of(geom) * tiles_y_of(geom) + 1, (int64_t)0, s);
+  if (!cull || !ws || !idx) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (ws_bytes < fdtbx_cull_workspace(geom, n_hkl)) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "cull workspace too small");
+  CullParams q;
+  cull_params(geom, n_hkl, &q);
+  const int64_t nsb = (int64_t)q.sb_x * q.sb_y;
+  const int64_t n_tiles = (int64_t)q.tiles_x * q.tiles_y;
+  char* w = (char*)ws;
+  double* sb = (double*)w;
+  w += align_up((size_t)nsb * 8 * sizeof(double), 256);
+  uint64_t* mask = (uint64_t*)w;
+  w += align_up((size_t)nsb * q.n_words * sizeof(uint64_t), 256);
+  int64_t* total = (int64_t*)w;
+  w += align_up(sizeof(int64_t) * 2, 256);
+  int32_t* part = (int32_t*)w;
+  hipLaunchKernelGGL(k_sb_boxes, dim3((unsigned)ceil_div(nsb, 256)), dim3(256), 0, s, q, tile, sb);
+  FDTBX_LAUNCH_CHECK("cull superblocks");
+  hipLaunchKernelGGL(k_sb_mask, dim3((unsigned)q.n_words), dim3(64), 0, s, q, sb, cull, mask);
+  FDTBX_LAUNCH_CHECK("cull masks");
+  hipLaunchKernelGGL(k_tile_lists<0>, dim3((unsigned)nsb), dim3(64 * kTB), 0, s, q, tile, mask, cull, offsets, part,
+                     (int32_t*)nullptr, (const int64_t*)nullptr, (int64_t)0);
+  FDTBX_LAUNCH_CHECK("cull count");
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, offsets, n_tiles, total);
+  FDTBX_LAUNCH_CHECK("cull scan");
+  hipLaunchKernelGGL(k_tile_lists<1>, dim3((unsigned)nsb), dim3(64 * kTB), 0, s, q, tile, mask, cull, offsets, part, idx,
+                     (const int64_t*)total, cap);
+  FDTBX_LAUNCH_CHECK("cull fill");
+  hipLaunchKernelGGL(k_cull_commit, dim3((unsigned)ceil_div(n_tiles + 1, 256)), dim3(256), 0, s, offsets, n_tiles,
+                     (const int64_t*)total, cap, stats);
+  FDTBX_LAUNCH_CHECK("cull commit");
+  return FDTBX_OK;
+}
+}  // namespace fdtbx
 
 extern "C" int fdtbx_batch_entry_init(const fdtbx_model* model, fdtbx_batch_entry* e) {
   if (!model || !e) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
@@ -839,6 +896,28 @@ extern "C" int fdtbx_batch_entry_init(const fdtbx_model* model, fdtbx_batch_entr
     e->frame[9 + k] = f.s[k];
   }
   e->frame[18] = f.V;
+  for (int i = 0; i < 3; ++i) {
+    e->setup_g[i] = model->dis.g[i];
+    e->setup_N_base[i] = model->dis.N_base[i];
+  }
+  e->stale = 0;
+  e->reserved = 0;
+  return FDTBX_OK;
+}
+
+extern "C" int fdtbx_batch_entries_check(const fdtbx_batch_entry* entries, int32_t n_models) {
+  if (!entries || n_models <= 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "batch entries: null pointer or no models");
+  for (int32_t m = 0; m < n_models; ++m) {
+    const fdtbx_batch_entry& e = entries[m];
+    if (e.n_types < 1 || e.n_types > 16) return fail(FDTBX_ERR_INVALID_ARGUMENT, "batch entry: n_types must be in 1..16");
+    if (e.n_tiles < 0 || e.n_atoms < 0 || e.n_hkl < 0)
+      return fail(FDTBX_ERR_INVALID_ARGUMENT, "batch entry: negative n_tiles, n_atoms or n_hkl");
+    if (e.atom_off < 0 || e.hkl_off < 0 || e.pix_off < 0 || e.tile_off < 0 || e.rowptr_off < 0 || e.pair_off < 0 ||
+        e.node_off < 0 || e.ff_off < 0)
+      return fail(FDTBX_ERR_INVALID_ARGUMENT, "batch entry: negative offset");
+    const int rc = check_model(&e.model);
+    if (rc) return rc;
+  }
   return FDTBX_OK;
 }
 

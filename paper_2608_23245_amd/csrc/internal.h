@@ -27,6 +27,10 @@ int check_cell(const fdtbx_cell* c);
 int check_geometry(const fdtbx_geometry* g);
 int check_model(const fdtbx_model* m);
 int tile_waves(const fdtbx_geometry* g, int64_t n_tiles, int* waves);
+// fdtbx_cull with the capacity check on the device (no host round trip): on overflow the
+// lists are left empty and stats->overflow is set (stats may be NULL).
+int cull_on_device(const fdtbx_geometry* geom, const double* tile, int64_t n_hkl, const double* cull, int64_t* offsets,
+                   int32_t* idx, int64_t cap, fdtbx_stats* stats, void* ws, size_t ws_bytes, hipStream_t s);
 
 inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
@@ -119,6 +123,26 @@ __device__ __forceinline__ int wave_max_i32(int v) {
 }
 __device__ __forceinline__ float wave_min(float v) { return order_float(wave_min_i32(float_order(v))); }
 __device__ __forceinline__ float wave_max(float v) { return order_float(wave_max_i32(float_order(v))); }
+// Binary64 wave sum through the same DPP steps on the two 32-bit halves.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, ROWS, 0xf, true);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, ROWS, 0xf, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+__device__ __forceinline__ double wave_sum_f64(double v) {
+  v += dpp_f64<0x111, 0xf>(v);
+  v += dpp_f64<0x112, 0xf>(v);
+  v += dpp_f64<0x114, 0xf>(v);
+  v += dpp_f64<0x118, 0xf>(v);
+  v += dpp_f64<0x142, 0xa>(v);
+  v += dpp_f64<0x143, 0xc>(v);
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(b & 0xffffffffll), 63);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 __device__ __forceinline__ float wave_sum(float v) {
   v += dpp_f32<0x111, 0xf>(v);
   v += dpp_f32<0x112, 0xf>(v);
@@ -173,6 +197,16 @@ int launch_batch_nodes(const fdtbx_batch_entry* ent, const int64_t* blocks, int6
 int launch_batch_profile(const fdtbx_batch_entry* ent, const int64_t* items, int64_t n_items, const float* refl,
                          const float* nodes, const double* pix, const double* tile, const int64_t* rowptr, const int32_t* idx,
                          float* image, int64_t* counter, hipStream_t s);
+// Fixed-order accumulation of the adjoint sums (fdtbx_pair_reduce): per-pair partials
+// float32 [n_pairs][12] and the pairs of each reflection in a fixed order.
+struct PairOrder {
+  float* partials;
+  int64_t n_pairs;
+  const int64_t* refl_ptr;    // [n_hkl + 1]
+  const int32_t* refl_pairs;  // [n_pairs]
+  const int64_t* mate;        // [n_hkl], -1 where the model has no up-down fold
+};
+
 int launch_batch_backward(const fdtbx_batch_entry* ent, int32_t n_models, const int64_t* refl_blocks, int64_t n_rb,
                           const int64_t* model_rb, const int64_t* atom_blocks, int64_t n_ab, const int64_t* items,
                           int64_t n_items, int64_t n_hkl_total, const int32_t* hkl, const float* x, const float* y,
@@ -180,7 +214,7 @@ int launch_batch_backward(const fdtbx_batch_entry* ent, int32_t n_models, const 
                           const double* pix, const double* tile, const int64_t* rowptr, const int32_t* idx, const float* F,
                           const float* refl, const float* nodes, const float* grad_image, double* sums, double* part,
                           float* dF2, float* d_x, float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals,
-                          int64_t* counter, hipStream_t s);
+                          int64_t* counter, const PairOrder* fixed, hipStream_t s);
 
 // Cell frame in the laboratory convention: rows of avec are a, b, c; rows of
 // astar are a*, b*, c*.  Binary64, operation order fixed (compiled without

@@ -70,8 +70,8 @@ __device__ inline int tile_of_block(const ProfParams& q, int b) {
 // Mirror folds.  Tile column tiles_x - 1 - tx holds the left-right mirror pixels of column tx
 // and tile row tiles_y - 1 - ty the up-down ones of row ty; a middle column or row (odd count)
 // is its own mirror, its pixels all computed.  write_folded stores a computed value at pixel
-// (i, j) of tile (tx, ty) and at the mirror pixels no launched tile computes; folded_weight is
-// the sum of an image-shaped weight over the same pixels (the adjoint's weight of the value).
+// (i, j) of tile (tx, ty) and at the mirror pixels no launched tile computes; folded_weights
+// gives the adjoint's weights of the value, an image-shaped weight summed over those pixels.
 __device__ inline void write_folded(const ProfParams& q, float* image, int i, int j, int tx, int ty, float v) {
   const bool mx = (q.mirror & 1) && 2 * tx + 1 != q.tiles_x;
   const bool my = (q.mirror & 2) && 2 * ty + 1 != q.tiles_y;
@@ -81,15 +81,23 @@ __device__ inline void write_folded(const ProfParams& q, float* image, int i, in
   if (my) image[mrow + i] = v;
   if (mx && my) image[mrow + (q.W - 1 - i)] = v;
 }
-__device__ inline float folded_weight(const ProfParams& q, const float* g, int i, int j, int tx, int ty) {
+// The adjoint's two weights of a computed pixel: *wa = g over the pixel and its left-right
+// mirror (the same reflection gives both the same value), *wb = g over its up-down mirrors
+// (whose value the Friedel mate of the reflection gives at this pixel); 0 where no such
+// mirror is folded onto the pixel.
+__device__ inline void folded_weights(const ProfParams& q, const float* g, int i, int j, int tx, int ty, float* wa,
+                                      float* wb) {
   const bool mx = (q.mirror & 1) && 2 * tx + 1 != q.tiles_x;
   const bool my = (q.mirror & 2) && 2 * ty + 1 != q.tiles_y;
   const int64_t row = (int64_t)j * q.W, mrow = (int64_t)(q.H - 1 - j) * q.W;
-  float w = g[row + i];
-  if (mx) w += g[row + (q.W - 1 - i)];
-  if (my) w += g[mrow + i];
-  if (mx && my) w += g[mrow + (q.W - 1 - i)];
-  return w;
+  float a = g[row + i], b = 0.0f;
+  if (mx) a += g[row + (q.W - 1 - i)];
+  if (my) {
+    b = g[mrow + i];
+    if (mx) b += g[mrow + (q.W - 1 - i)];
+  }
+  *wa = a;
+  *wb = b;
 }
 
 struct Window {

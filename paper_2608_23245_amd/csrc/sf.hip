@@ -119,7 +119,9 @@ __global__ void __launch_bounds__(kSFThreads) k_b_sf(const fdtbx_batch_entry* __
   const int64_t r = (item & ((1ll << 40) - 1)) + threadIdx.x;
   const bool have = r < e.n_hkl;
   const int64_t g = e.hkl_off + r;
-  const int n_types = e.n_types;
+  // fdtbx_batch_entries_check keeps n_types in 1..kMaxTypes; clamped here as well, so that the
+  // LDS table is never indexed past its end
+  const int n_types = e.n_types < 1 ? 1 : (e.n_types > kMaxTypes ? kMaxTypes : e.n_types);
   const float* ffm = ff + 9 * e.ff_off;
   double h = 0, k = 0, l = 0;
   float s2 = 0.0f;

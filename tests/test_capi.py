@@ -111,6 +111,51 @@ def test_empty_inputs_are_valid_calls(lib):
     assert lib.fdtbx_structure_factors(ctypes.byref(cell), -1, *([None] * 7), 1, None, 5, None, None, None, 0, None) == -1
 
 
+def test_batch_entries_check_and_setup_envelope(lib):
+    """fdtbx_batch_entry_init records the set-up g and N_base (the culling lists' envelope) and
+    clears the stale word; fdtbx_batch_entries_check rejects a scattering-factor row count
+    outside 1..16 (the batched kernels' LDS tables hold 16 rows) and negative offsets, on the
+    host, before any upload."""
+    import workloads as W
+    from paper_2608_23245_amd import binding as B
+    wl = W.config1()
+    m = B.make_model(wl)
+    ents = (B.BatchEntry * 2)()
+    for e in ents:
+        assert lib.fdtbx_batch_entry_init(ctypes.byref(m), ctypes.byref(e)) == 0
+        e.n_types = 4
+    assert list(ents[0].setup_g) == list(wl.dis.g) and list(ents[0].setup_N_base) == list(wl.dis.N_base)
+    assert ents[0].stale == 0
+    assert lib.fdtbx_batch_entries_check(ctypes.byref(ents), 2) == 0
+    for bad in (0, 17, -3):
+        ents[1].n_types = bad
+        assert lib.fdtbx_batch_entries_check(ctypes.byref(ents), 2) == -1, bad
+        assert "n_types" in lib.fdtbx_error_string(-1).decode()
+    ents[1].n_types = 16
+    assert lib.fdtbx_batch_entries_check(ctypes.byref(ents), 2) == 0
+    ents[1].pair_off = -1
+    assert lib.fdtbx_batch_entries_check(ctypes.byref(ents), 2) == -1
+    assert lib.fdtbx_batch_entries_check(None, 2) == -1
+
+
+def test_deterministic_adjoint_host_checks(lib):
+    """The fixed-order adjoint's entry points check their sizes on the host: the pair order
+    takes fewer than 2^31 pairs, empty inputs are valid, null outputs are refused."""
+    import workloads as W
+    from paper_2608_23245_amd import binding as B
+    m = B.make_model(W.config0())
+    assert lib.fdtbx_pair_transpose(10, ctypes.c_void_p(8), 1 << 31, None, ctypes.c_void_p(8), ctypes.c_void_p(8),
+                                    ctypes.c_void_p(8), 1 << 40, None) == -5
+    assert lib.fdtbx_pair_transpose(-1, None, 0, None, None, None, None, 0, None) == -1
+    assert lib.fdtbx_pair_transpose(0, None, 0, None, None, None, None, 0, None) == 0
+    assert lib.fdtbx_pair_reduce(0, None, None, None, None, 0, None, None) == 0
+    assert lib.fdtbx_pair_reduce(5, None, None, None, None, 0, None, None) == -1
+    assert lib.fdtbx_profile_adjoint_pairs(ctypes.byref(m), *([None] * 7), 0, 0, None, None, None) == 0
+    assert lib.fdtbx_profile_adjoint_pairs(ctypes.byref(m), *([None] * 7), 10, 100, None, None, None) == -1
+    assert lib.fdtbx_backward_deterministic_workspace(-1, 0, 10) == 0
+    assert lib.fdtbx_backward_deterministic_workspace(0, 0, 10) > 0
+
+
 def test_node_rows(lib):
     """Node table size: n^2 node records plus ceil(n/4)^2 block records; 0 outside 1..256."""
     from paper_2608_23245_amd import binding as B

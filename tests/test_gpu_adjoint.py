@@ -10,6 +10,7 @@ import sys
 import numpy as np
 import pytest
 
+import gradcheck as GC
 import refinement as RF
 import workloads as W
 from oracle import oracle as O
@@ -31,13 +32,8 @@ def say(*a):
     sys.stdout.flush()
 
 
-def check_group(name, got, ref, tol=1e-3):
-    got = np.asarray(got, dtype=np.float64)
-    ref = np.asarray(ref, dtype=np.float64)
-    floor = 1e-3 * np.abs(ref).max()
-    err = np.abs(got - ref) / np.maximum(np.abs(ref), floor)
-    say(f"  {name}: max rel err {err.max():.2e} (|ref| max {np.abs(ref).max():.3e})")
-    assert err.max() <= tol, (name, err.max())
+def check_group(name, got, ref, floor=GC.RANDOM_FLOOR):
+    GC.check(name, got, ref, floor, say=say)
 
 
 def gpu_gradients(wl, G):
@@ -153,17 +149,17 @@ def test_refinement_gradient_full_size_vs_oracle():
     assert np.linalg.norm(got_I - rf.I) <= 1e-4 * np.linalg.norm(rf.I)
     ref = O.gradients(rf.wl, rf.P, rf.G, rf.R, rf.Z)
     for k in RF.FIELDS:
-        check_group(k, ga[k], ref["atoms"][k])
+        check_group(k, ga[k], ref["atoms"][k], floor=GC.LOSS_FLOOR)
     for a, k in RF.fd_parameters(rf.wl.atoms.n):
         r = ref["atoms"][k][a]
-        floor = 1e-3 * np.abs(ref["atoms"][k]).max()
+        floor = GC.LOSS_FLOOR * np.abs(ref["atoms"][k]).max()
         assert abs(ga[k][a] - r) <= 1e-3 * max(abs(r), floor), (a, k, ga[k][a], r)
     refg = [ref["sigma_theta"], ref["gamma_theta"], *ref["N_base"], *ref["g"], *ref["B_axis"]]
     for i, n in enumerate(B.GLOBAL_NAMES):
         if n == "g_c":
             assert gg[i] == 0.0 and refg[i] == 0.0  # g_c = 0: dA/dg vanishes on both sides
             continue
-        check_group(n, [gg[i]], [refg[i]])
+        check_group(n, [gg[i]], [refg[i]], floor=GC.LOSS_FLOOR)
 
 
 def test_adjoint_identities_at_full_size():

@@ -12,6 +12,7 @@ import sys
 import numpy as np
 import pytest
 
+import gradcheck as GC
 import workloads as W
 from oracle import oracle as O
 
@@ -157,21 +158,26 @@ def test_updown_folded_gradients(name):
         eng.plan.run(eng.hkl, F2)
         out, glob, dF2 = B.pattern_backward(eng.plan, eng.hkl, F, torch.as_tensor(G, dtype=torch.float32).cuda(), atoms)
         res.append(({k: v.cpu().numpy().astype(np.float64) for k, v in out.items()},
-                    glob.cpu().numpy().astype(np.float64)))
-    (o0, g0), (o1, g1) = res
+                    glob.cpu().numpy().astype(np.float64), dF2.cpu().numpy().astype(np.float64)))
+    (o0, g0, f0), (o1, g1, f1) = res
     for k in o0:
         err = np.abs(o1[k] - o0[k]).max() / np.abs(o0[k]).max()
         say(f"  {k}: folded vs unfolded {err:.1e} of the largest")
         assert err <= 1e-4, k
+    # per reflection: the mirror rows' weight goes to the Friedel mate, so dL/d|F|^2 of every
+    # reflection (not only of each Friedel pair) is the unfolded one
+    err = np.abs(f1 - f0).max() / np.abs(f0).max()
+    pair = np.abs((f1 + f1[::-1]) - (f0 + f0[::-1])).max() / np.abs(f0).max()
+    say(f"  dF2: folded vs unfolded {err:.1e} of the largest (Friedel-pair sums {pair:.1e})")
+    assert err <= 1e-4
     # both against the oracle's gradients (relative 1e-3, floor 1e-3 of the group's largest)
     ref = O.gradients(wl, O.prepare(wl, hkl=eng.hkl.cpu().numpy(), cull_extinct=False), G)
     refg = np.asarray([ref["sigma_theta"], ref["gamma_theta"], *ref["N_base"], *ref["g"], *ref["B_axis"]], np.float64)
     groups = [(np.asarray(ref["atoms"][k], np.float64), o0[k], o1[k]) for k in ("x", "y", "z", "B", "occ")]
     for r, a0, a1 in groups + [(refg, g0, g1)]:
-        floor = 1e-3 * np.abs(r).max()
         for got in (a0, a1):
-            err = np.abs(got - r) / np.maximum(np.abs(r), floor)
-            assert err.max() <= 1e-3, err.max()
+            rel_l2, elem = GC.errors(got, r, GC.RANDOM_FLOOR)  # a random cotangent G
+            assert rel_l2 <= 1e-3 and elem <= 1e-3, (rel_l2, elem)
 
 
 def test_updown_folded_batch_matches_unfolded_single_runs():

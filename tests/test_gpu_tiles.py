@@ -11,6 +11,7 @@ import sys
 import numpy as np
 import pytest
 
+import gradcheck as GC
 import workloads as W
 from oracle import oracle as O
 
@@ -144,7 +145,7 @@ def test_adjoint_vs_oracle(tw):
     for k in ("x", "y", "z", "B", "occ"):
         got = out[k].cpu().numpy().astype(np.float64)
         r = np.asarray(ref["atoms"][k], np.float64)
-        err = np.abs(got - r) / np.maximum(np.abs(r), 1e-3 * np.abs(r).max())
+        err = np.abs(got - r) / np.maximum(np.abs(r), GC.RANDOM_FLOOR * np.abs(r).max())
         say(f"  {k}: max rel err {err.max():.2e}")
         assert err.max() <= 1e-3, (k, err.max())
 
@@ -251,11 +252,11 @@ def test_tile_waves_adjoint_vs_oracle(waves):
     for k in ("x", "y", "z", "B", "occ"):
         got = out[k].cpu().numpy().astype(np.float64)
         r = np.asarray(ref["atoms"][k], np.float64)
-        err = np.abs(got - r) / np.maximum(np.abs(r), 1e-3 * np.abs(r).max())
+        err = np.abs(got - r) / np.maximum(np.abs(r), GC.RANDOM_FLOOR * np.abs(r).max())
         assert err.max() <= 1e-3, (k, err.max())
     rg = np.array([ref["sigma_theta"], ref["gamma_theta"], *ref["N_base"], *ref["g"], *ref["B_axis"]], np.float64)
     gg = glob.cpu().numpy()[:rg.size]
-    err = np.abs(gg - rg) / np.maximum(np.abs(rg), 1e-3 * np.abs(rg).max())
+    err = np.abs(gg - rg) / np.maximum(np.abs(rg), GC.RANDOM_FLOOR * np.abs(rg).max())
     say(f"  globals: max rel err {err.max():.2e}")
     assert err.max() <= 1e-3
 
