@@ -59,11 +59,11 @@ def profile_source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the profile kernel from the committed counter summary,
-    or None when the kernel source has changed since the counters were taken."""
+def measured_traffic(workload="large"):
+    """HBM bytes per launch of the profile kernel on a workload from the committed counter
+    summary, or None when the kernel source has changed since the counters were taken."""
     import re
-    summ = os.path.join(ROOT, "profiles", "k_profile_medium_traffic.md")
+    summ = os.path.join(ROOT, "profiles", f"k_profile_{workload}_traffic.md")
     try:
         text = open(summ).read()
         sha = profile_source_sha()
