@@ -561,6 +561,26 @@ int fdtbx_pattern_backward_deterministic(const fdtbx_model* model, const int32_t
                                          float* d_occ, double* d_globals, float* dF2, void* ws, size_t ws_bytes,
                                          void* stream);
 
+/* fdtbx_pattern_backward_noalloc: fdtbx_pattern_backward for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The same arguments without ws and ws_bytes: the workspace is a device array of
+ * FDTBX_NOALLOC_SCRATCH_BYTES inside the library, one per device, held until the process
+ * ends.  The call itself allocates nothing; the caller still passes the inputs, the forward
+ * workspace and the outputs.  When fdtbx_backward_workspace(n_hkl, n_atoms) (n_atoms 0 when
+ * the five atom outputs are NULL) exceeds the array it returns FDTBX_ERR_BUFFER_TOO_SMALL
+ * before any launch (64 MiB covers the medium workload with its 5000 atoms, or about 1.3e6
+ * reflections without atom gradients).  Every call on a device shares that device's array:
+ * calls that overlap on one device (two streams, two threads) race and give wrong results;
+ * calls in one stream's order are safe.  The array keeps the last call's contents, which no
+ * later call reads before writing. */
+#define FDTBX_NOALLOC_SCRATCH_BYTES (64u << 20)
+int fdtbx_pattern_backward_noalloc(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F,
+                                   const float* grad_image, const void* fwd_ws, size_t fwd_ws_bytes, int64_t pair_cap,
+                                   int64_t n_atoms, const float* x, const float* y, const float* z, const float* B,
+                                   const float* occ, const int32_t* type, const float* ff, int32_t n_types, float* d_x,
+                                   float* d_y, float* d_z, float* d_B, float* d_occ, double* d_globals, float* dF2,
+                                   void* stream);
+
 /* ------------------------------------------------------------------ batched models
  * Many models of different cells, atom counts, reflection lists and detectors in one
  * launch per step.  Each model's static data (reflection list, pixel map, tile boxes,

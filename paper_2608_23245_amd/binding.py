@@ -152,6 +152,10 @@ _SIGS = {
                                                             ctypes.c_size_t, ctypes.c_int64, ctypes.c_int64] +
                                              [ctypes.c_void_p] * 7 + [ctypes.c_int32] + [ctypes.c_void_p] * 8 +
                                              [ctypes.c_size_t, ctypes.c_void_p]),
+    "fdtbx_pattern_backward_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                                       ctypes.c_size_t, ctypes.c_int64, ctypes.c_int64] +
+                                       [ctypes.c_void_p] * 7 + [ctypes.c_int32] + [ctypes.c_void_p] * 8),
     "fdtbx_batch_backward_deterministic": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                                           ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                                           ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
@@ -508,6 +512,7 @@ def read_stats(stats: torch.Tensor) -> dict:
 GLOBAL_NAMES = ("sigma_theta", "gamma_theta", "N_base_a", "N_base_b", "N_base_c", "g_a", "g_b", "g_c",
                 "B_a", "B_b", "B_c")
 N_GLOBALS = len(GLOBAL_NAMES)
+NOALLOC_SCRATCH_BYTES = 64 << 20  # FDTBX_NOALLOC_SCRATCH_BYTES of include/fdtbx.h
 LINESHAPES = {"laue": 0, "gaussian": 1, "hosemann": 2}
 
 
@@ -589,6 +594,33 @@ def sf_adjoint(cell: Cell, atoms: dict, hkl, F, dF2):
     return out
 
 
+def _backward_outputs(n_hkl, atoms, dev):
+    glob = torch.empty(N_GLOBALS, dtype=torch.float64, device=dev)
+    dF2 = torch.empty(n_hkl, dtype=torch.float32, device=dev)
+    out, a, d, nt = None, [None] * 7, [None] * 5, 1
+    if atoms is not None:
+        n_atoms = int(atoms["x"].shape[0])
+        out = {k: torch.empty(n_atoms, dtype=torch.float32, device=dev) for k in ("x", "y", "z", "B", "occ")}
+        a = [_ptr(atoms[k]) for k in ("x", "y", "z", "B", "occ", "type", "ff")]
+        d = [_ptr(out[k]) for k in ("x", "y", "z", "B", "occ")]
+        nt = int(atoms["ff"].shape[0])
+    return out, glob, dF2, a, d, nt
+
+
+def pattern_backward_noalloc(plan: "PatternPlan", hkl, F, grad_image, atoms: Optional[dict]):
+    """fdtbx_pattern_backward_noalloc: fdtbx_pattern_backward with the library's own device
+    scratch array as its workspace (the call allocates nothing; the output tensors here are
+    the caller's).  Raises FdtbxError when the problem's workspace exceeds
+    NOALLOC_SCRATCH_BYTES."""
+    L = lib()
+    n_atoms = int(atoms["x"].shape[0]) if atoms is not None else 0
+    out, glob, dF2, a, d, nt = _backward_outputs(plan.n_hkl, atoms, hkl.device)
+    _check(L.fdtbx_pattern_backward_noalloc(ctypes.byref(plan.model), _ptr(hkl), plan.n_hkl, _ptr(F), _ptr(grad_image),
+                                            _ptr(plan.ws), plan.ws_bytes, plan.pair_cap, n_atoms, *a, nt, *d, _ptr(glob),
+                                            _ptr(dF2), _stream()))
+    return out, glob, dF2
+
+
 def pattern_backward(plan: "PatternPlan", hkl, F, grad_image, atoms: Optional[dict], deterministic: bool = False):
     """fdtbx_pattern_backward (or, with deterministic, fdtbx_pattern_backward_deterministic:
     fixed-order sums, the same bits on every run) after plan.run(hkl, |F|^2): (atom gradients
@@ -606,17 +638,7 @@ def pattern_backward(plan: "PatternPlan", hkl, F, grad_image, atoms: Optional[di
         wsb = L.fdtbx_backward_workspace(n_hkl, n_atoms)
         entry = L.fdtbx_pattern_backward
     ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=dev)
-    glob = torch.empty(N_GLOBALS, dtype=torch.float64, device=dev)
-    dF2 = torch.empty(n_hkl, dtype=torch.float32, device=dev)
-    out = None
-    a = [None] * 7
-    d = [None] * 5
-    nt = 1
-    if atoms is not None:
-        out = {k: torch.empty(n_atoms, dtype=torch.float32, device=dev) for k in ("x", "y", "z", "B", "occ")}
-        a = [_ptr(atoms[k]) for k in ("x", "y", "z", "B", "occ", "type", "ff")]
-        d = [_ptr(out[k]) for k in ("x", "y", "z", "B", "occ")]
-        nt = int(atoms["ff"].shape[0])
+    out, glob, dF2, a, d, nt = _backward_outputs(n_hkl, atoms, dev)
     _check(entry(ctypes.byref(plan.model), _ptr(hkl), n_hkl, _ptr(F), _ptr(grad_image), _ptr(plan.ws), plan.ws_bytes,
                  plan.pair_cap, n_atoms, *a, nt, *d, _ptr(glob), _ptr(dF2), _ptr(ws), wsb, _stream()))
     return out, glob, dF2

@@ -4,6 +4,8 @@
 
 #include <math.h>
 
+#include <mutex>
+
 #include "internal.h"
 
 namespace fdtbx {
@@ -429,6 +431,61 @@ extern "C" int fdtbx_pattern_backward_deterministic(
   if (!atoms) return FDTBX_OK;
   return fdtbx_sf_adjoint(&model->cell, n_atoms, x, y, z, B, occ, type, ff, n_types, hkl, n_hkl, F, g2, d_x, d_y, d_z, d_B,
                           d_occ, sfw, fdtbx_sf_adjoint_workspace(n_hkl, n_atoms), stream);
+}
+
+// ------------------------------------------------------------------ backward without allocation
+// The workspace of fdtbx_pattern_backward_noalloc: a file-scope device array, one copy per
+// device, held until the process ends.  In host code the name `scratch` is a host-side stand-in,
+// not a device address: host code uses only the address hipGetSymbolAddress gives for the
+// current device.
+static __device__ __align__(256) unsigned char scratch[FDTBX_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kScratchDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch[kScratchDevices];  // device address of `scratch`, per device, once looked up
+}  // namespace
+
+// The current device's copy of the scratch array, looked up on the first call on that device.
+static int scratch_on_current_device(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kScratchDevices) return fail(FDTBX_ERR_UNSUPPORTED, "no-alloc scratch: device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(FDTBX_ERR_HIP, "hipGetSymbolAddress(scratch) gave no address");
+    g_scratch[dev] = p;
+  }
+  *out = g_scratch[dev];
+  return FDTBX_OK;
+}
+
+extern "C" int fdtbx_pattern_backward_noalloc(const fdtbx_model* model, const int32_t* hkl, int64_t n_hkl, const float* F,
+                                              const float* grad_image, const void* fwd_ws, size_t fwd_ws_bytes,
+                                              int64_t pair_cap, int64_t n_atoms, const float* x, const float* y,
+                                              const float* z, const float* B, const float* occ, const int32_t* type,
+                                              const float* ff, int32_t n_types, float* d_x, float* d_y, float* d_z,
+                                              float* d_B, float* d_occ, double* d_globals, float* dF2, void* stream) {
+  if (n_hkl < 0 || pair_cap < 0 || n_atoms < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "bad sizes");
+  const bool atoms = d_x || d_y || d_z || d_B || d_occ;
+  const size_t need = fdtbx_backward_workspace(n_hkl, atoms ? n_atoms : 0);
+  if (need > (size_t)FDTBX_NOALLOC_SCRATCH_BYTES)
+    return fail(FDTBX_ERR_BUFFER_TOO_SMALL,
+                "fdtbx_pattern_backward_noalloc: the backward workspace for n_hkl and n_atoms exceeds the "
+                "library's scratch array (FDTBX_NOALLOC_SCRATCH_BYTES); use fdtbx_pattern_backward");
+  void* ws = nullptr;
+  const int rc = scratch_on_current_device(&ws);
+  if (rc) return rc;
+  // the same steps as fdtbx_pattern_backward; every kernel there writes its workspace before
+  // reading it (the per-reflection sums are cleared by a kernel), so what an earlier call
+  // left in the array does not matter
+  return fdtbx_pattern_backward(model, hkl, n_hkl, F, grad_image, fwd_ws, fwd_ws_bytes, pair_cap, n_atoms, x, y, z, B, occ,
+                                type, ff, n_types, d_x, d_y, d_z, d_B, d_occ, d_globals, dF2, ws,
+                                (size_t)FDTBX_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 extern "C" int fdtbx_batch_forward(const fdtbx_batch_entry* entries, int32_t n_models, const int64_t* refl_blocks, int64_t n_rb,

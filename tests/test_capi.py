@@ -156,6 +156,30 @@ def test_deterministic_adjoint_host_checks(lib):
     assert lib.fdtbx_backward_deterministic_workspace(0, 0, 10) > 0
 
 
+def test_noalloc_backward_host_checks(lib):
+    """fdtbx_pattern_backward_noalloc refuses, on the host and before any HIP call, a problem
+    whose backward workspace exceeds the library's scratch array, and negative sizes; the
+    header's array size is the binding's."""
+    from paper_2608_23245_amd import binding as B
+    src = open(HEADER).read()
+    m = re.search(r"#define FDTBX_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == B.NOALLOC_SCRATCH_BYTES
+    n_big = 2_000_000
+    assert lib.fdtbx_backward_workspace(n_big, 0) > B.NOALLOC_SCRATCH_BYTES
+    assert lib.fdtbx_backward_workspace(1_000_000, 0) <= B.NOALLOC_SCRATCH_BYTES
+    args = [None, None, n_big, None, None, None, 0, 0, 0] + [None] * 7 + [1] + [None] * 8
+    assert lib.fdtbx_pattern_backward_noalloc(*args) == -3
+    assert b"scratch" in lib.fdtbx_error_string(-3)
+    with_atoms = list(args)
+    with_atoms[2], with_atoms[8], with_atoms[17] = 200_000, 20_000, ctypes.c_void_p(8)  # d_x given: atoms count
+    assert lib.fdtbx_backward_workspace(200_000, 0) <= B.NOALLOC_SCRATCH_BYTES
+    assert lib.fdtbx_backward_workspace(200_000, 20_000) > B.NOALLOC_SCRATCH_BYTES
+    assert lib.fdtbx_pattern_backward_noalloc(*with_atoms) == -3
+    neg = list(args)
+    neg[2] = -1
+    assert lib.fdtbx_pattern_backward_noalloc(*neg) == -1
+
+
 def test_node_rows(lib):
     """Node table size: n^2 node records plus ceil(n/4)^2 block records; 0 outside 1..256."""
     from paper_2608_23245_amd import binding as B
