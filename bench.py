@@ -100,6 +100,10 @@ def parse():
     ap.add_argument("--no-mirror", action="store_true", help="run every tile (no mirror fold)")
     ap.add_argument("--no-updown", action="store_true", help="fold the left-right mirror only (not the up-down one)")
     ap.add_argument("--no-unfolded", action="store_true", help="skip the unfolded reference forward")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="run the batched forward alone, at --batch-tile-w, --steps times (profiler runs)")
+    ap.add_argument("--batch-tile-w", type=int, default=16, choices=(4, 8, 16),
+                    help="tile width of every model of the batch with --only-batch")
     ap.add_argument("--batch-models", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -137,7 +141,7 @@ def forward_leg(wl, steps, warmup):
         order = B.tile_order(model.geom, off)
         if timed_events is not None:
             timed_events[0].record(stream)
-        img = B.profile(model, refl, nodes, pix, tile, off, idx, order=order)
+        img = B.profile_balanced(model, refl, nodes, pix, tile, off, idx, order=order)
         if timed_events is not None:
             timed_events[1].record(stream)
         state.update(hkl=hkl, refl=refl, nodes=nodes, pix=pix, tile=tile, off=off, idx=idx, order=order, img=img)
@@ -273,7 +277,9 @@ def bench_medium(args):
            "issue_frac": ach / PEAK_SLOTS, "mirror_fold": fold_name(wl), "tile_tuning": tiles,
            "waves_per_tile": waves, "pass": "forward"}
     if wl.geom.mirror and not args.no_unfolded:
-        wl0 = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, mirror=0, tile_waves=waves))
+        # the folded launch's pairs per work unit, so that the computed rows can be compared bit for bit
+        u = B.unit_pairs(int(state["idx"].shape[0]))
+        wl0 = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, mirror=0, tile_waves=waves, unit_pairs=u))
         ms0, prof0, n0, st0 = forward_leg(wl0, max(1, min(args.steps, 3)), 1)
         out["unfolded"] = {"ms_per_pattern": ms0, "profile_kernel_ms": prof0, "useful_evals_per_step": int(n0),
                            "waves_per_tile": waves, "profile_kernel_evals_per_s": n0 / (prof0 * 1e-3),
@@ -419,6 +425,9 @@ def main():
     import workloads as W
 
     torch.cuda.set_device(0)
+    if args.only_batch:
+        print(json.dumps({"batched_forward": bench_batched_forward(args)}), flush=True)
+        return
     wl = W.config2()
     if args.copy_calibration > 0:
         n = args.copy_calibration * (1 << 20) // 4
@@ -480,13 +489,14 @@ def main():
         "tile_tuning": tiles,
         "rates": other_rates(n_evals / (prof_ms * 1e-3), prof_ms),
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tslot/s", "frac": achieved / peak,
-                     "traffic": measured_traffic(), "kernel": f"k_profile<false, 0, {waves_main}>",
+                     "traffic": measured_traffic(), "kernel": "k_profile_units<0>",
                      "sources_sha": profile_source_sha(), "slots_per_eval": SLOTS_PER_EVAL},
     }
     if wl.geom.mirror and not args.no_unfolded and not args.only_headline:
-        # the same forward step without the folds, for reference (with the same waves per tile,
-        # so that the computed pixels can be compared bit for bit)
-        wl0 = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, mirror=0, tile_waves=waves_main))
+        # the same forward step without the folds, for reference (with the folded launch's pairs
+        # per work unit, so that the computed pixels can be compared bit for bit)
+        u = B.unit_pairs(int(state["idx"].shape[0]))
+        wl0 = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, mirror=0, tile_waves=waves_main, unit_pairs=u))
         ms0, prof0, n0, st0 = forward_leg(wl0, 1, 1)
         out["unfolded"] = {"ms_per_pattern": ms0, "profile_kernel_ms": prof0, "useful_evals_per_step": int(n0),
                            "waves_per_tile": waves_main, "profile_kernel_evals_per_s": n0 / (prof0 * 1e-3),
@@ -608,6 +618,35 @@ def bench_fwd_bwd(args):
             "slots": {"achieved": achieved, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
                       "frac": achieved / (PEAK_SLOTS / 1e12), "slots_per_eval": ADJ_SLOTS_PER_EVAL},
             "steps": args.steps, "pass": "forward + adjoint (atoms xyz/B/occ, sigma, gamma, N_base, g)"}
+
+
+def bench_batched_forward(args):
+    """The batched forward alone, every model in tile width --batch-tile-w (folded where its
+    geometry allows): one warm-up forward, then --steps forwards timed with HIP events."""
+    import torch
+
+    import workloads as W
+    from paper_2608_23245_amd.batch import BatchEngine
+
+    tw = args.batch_tile_w
+    wls = [fold(dataclasses.replace(w, geom=dataclasses.replace(w.geom, tile_w=tw)))
+           for w in W.config4(n_models=args.batch_models)]
+    t0 = time.perf_counter()
+    be = BatchEngine(wls, "cuda")
+    be.forward()
+    torch.cuda.synchronize()
+    log(f"batched forward: set-up and warm-up {time.perf_counter() - t0:.1f} s, {be.totals['pair']} pairs")
+    ms = []
+    for _ in range(args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        be.forward()
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    log(f"batched forward: {', '.join(f'{m:.1f}' for m in ms)} ms")
+    return {"n_models": len(wls), "tile": f"{tw}x{64 // tw}", "culled_pairs": int(be.totals["pair"]),
+            "forward_ms": ms}
 
 
 def bench_batched(args):

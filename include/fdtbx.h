@@ -80,6 +80,11 @@ typedef struct fdtbx_geometry {
                                  launched tiles fit in eight rounds of one-wave workgroups (32 per
                                  compute unit), else 2.  The batched persistent kernels run one
                                  wave per (model, tile) item whatever the value */
+  int32_t unit_pairs;         /* pairs per work unit of fdtbx_profile_balanced (and so of
+                                 fdtbx_profile_pattern): 0 is the library's choice from the pair
+                                 count (fdtbx_unit_pairs); the image depends on it in the last bits
+                                 (the grouping of the sums), so two launches that must agree bit for
+                                 bit (a folded and an unfolded one) fix it to the same value */
 } fdtbx_geometry;
 /* Mirror fold.  With center_x = width / 2 exactly, pixel (i, j) and its mirror (width-1-i, j)
  * have y of opposite sign and equal z, so their (R, Z) are bit-identical (R depends on y only
@@ -331,6 +336,29 @@ int fdtbx_profile(const fdtbx_model* model, const float* refl, const float* node
                   const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order, float* image,
                   int64_t* counts, void* stream);
 
+/* fdtbx_profile_balanced: the image of fdtbx_profile (the same sum, Eqs. direct_sum and
+ * lorentz) from a launch balanced over the compute units.  The launched tiles' lists are cut
+ * into work units of geom.unit_pairs pairs (0: fdtbx_unit_pairs(n_pairs), read on the device
+ * from offsets[n_tiles]); persistent waves take the units from eight queues, one per XCD
+ * (slot b of the launch order feeds queue b % 8, in slot order), each unit writes its 64 pixel
+ * sums to a slot of its own, and a second kernel adds each tile's units in unit order.  So no
+ * long list runs as one workgroup at the end of the launch, and the image is the same on every
+ * run; it equals fdtbx_profile's to float32 rounding (the sums are grouped by unit).
+ *   order     as for fdtbx_profile (or NULL)
+ *   pair_cap  capacity of idx: offsets[n_tiles] must not exceed it (units beyond the
+ *             workspace's capacity, which only a larger total would need, are not run)
+ *   ws        device workspace of fdtbx_profile_balanced_workspace(model, pair_cap) bytes:
+ *             about 260 bytes per unit, for min(2^19, ceil(pair_cap / 32)) units plus one per
+ *             tile when unit_pairs is 0 (at most 136 MB besides the tiles), ceil(pair_cap /
+ *             unit_pairs) plus one per tile otherwise
+ * fdtbx_unit_pairs(n): the library's pairs per unit for n culled pairs, max(32,
+ * ceil(n / 2^19)) (0 for n < 0). */
+int64_t fdtbx_unit_pairs(int64_t n_pairs);
+size_t fdtbx_profile_balanced_workspace(const fdtbx_model* model, int64_t pair_cap);
+int fdtbx_profile_balanced(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
+                           const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
+                           int64_t pair_cap, float* image, void* ws, size_t ws_bytes, void* stream);
+
 /* Deterministic forward splat (the paper's projection path, sampled on a fixed grid
  * instead of at random; sections "Numerical evaluation: per-reflection shell quadrature",
  * "Lorentz correction on a sampled reciprocal lattice", "Analytical Solution of the Ewald
@@ -409,9 +437,9 @@ int fdtbx_profile_points(const fdtbx_model* model, const int32_t* hkl, const flo
 int fdtbx_ewald_project(const fdtbx_geometry* geom, const double* S, int64_t n, double* out, void* stream);
 
 /* ------------------------------------------------------------------ one-call pattern
- * fdtbx_profile_pattern runs reflection_prep, node_table, pixel_map, cull and
- * profile into a caller workspace laid out by fdtbx_pattern_workspace(model,
- * n_hkl, pair_cap).  Synchronises once (pair count).  If the culling lists need
+ * fdtbx_profile_pattern runs reflection_prep, node_table, pixel_map, cull, tile_order
+ * and the balanced profile launch (fdtbx_profile_balanced) into a caller workspace laid
+ * out by fdtbx_pattern_workspace(model, n_hkl, pair_cap).  Synchronises once (pair count).  If the culling lists need
  * more than pair_cap entries it returns FDTBX_ERR_BUFFER_TOO_SMALL and writes
  * the required count to *pairs_needed (host, may be NULL); on success
  * *pairs_needed receives the pair count. */

@@ -96,12 +96,12 @@ class TileTuner:
         order = B.tile_order(model.geom, off)
         if idx.numel() == 0:
             idx = torch.zeros(1, dtype=torch.int32, device=refl.device)
-        B.profile(model, refl, nodes, pix, tile, off, idx, order=order)  # warm-up
+        B.profile_balanced(model, refl, nodes, pix, tile, off, idx, order=order)  # warm-up
         best = float("inf")
         for _ in range(self.reps):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            B.profile(model, refl, nodes, pix, tile, off, idx, order=order)
+            B.profile_balanced(model, refl, nodes, pix, tile, off, idx, order=order)
             e1.record()
             torch.cuda.synchronize()
             best = min(best, e0.elapsed_time(e1))

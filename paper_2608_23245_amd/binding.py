@@ -41,7 +41,8 @@ class Geometry(ctypes.Structure):
     _fields_ = [("wavelength", ctypes.c_double), ("distance", ctypes.c_double), ("pixel", ctypes.c_double),
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("center_x", ctypes.c_double), ("center_y", ctypes.c_double), ("tilt", ctypes.c_double),
-                ("tile_w", ctypes.c_int32), ("mirror", ctypes.c_int32), ("tile_waves", ctypes.c_int32)]
+                ("tile_w", ctypes.c_int32), ("mirror", ctypes.c_int32), ("tile_waves", ctypes.c_int32),
+                ("unit_pairs", ctypes.c_int32)]
 
 
 class Disorder(ctypes.Structure):
@@ -152,6 +153,10 @@ _SIGS = {
                                                             ctypes.c_size_t, ctypes.c_int64, ctypes.c_int64] +
                                              [ctypes.c_void_p] * 7 + [ctypes.c_int32] + [ctypes.c_void_p] * 8 +
                                              [ctypes.c_size_t, ctypes.c_void_p]),
+    "fdtbx_unit_pairs": (ctypes.c_int64, [ctypes.c_int64]),
+    "fdtbx_profile_balanced_workspace": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64]),
+    "fdtbx_profile_balanced": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 7 +
+                               [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "fdtbx_pattern_backward_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                        ctypes.c_size_t, ctypes.c_int64, ctypes.c_int64] +
@@ -229,7 +234,7 @@ def make_model(wl) -> Model:
     return Model(make_cell(wl.cell),
                  Geometry(g.wavelength, g.distance, g.pixel, g.width, g.height, g.center_x, g.center_y,
                           float(getattr(g, "tilt", 0.0)), int(getattr(g, "tile_w", 0)), int(getattr(g, "mirror", 0)),
-                          int(getattr(g, "tile_waves", 0))),
+                          int(getattr(g, "tile_waves", 0)), int(getattr(g, "unit_pairs", 0))),
                  Disorder(d.sigma_theta, d.gamma_theta, (ctypes.c_double * 3)(*d.N_base),
                           (ctypes.c_double * 3)(*d.g), d.intensity_model, int(getattr(d, "lineshape", 0)),
                           (ctypes.c_double * 3)(*getattr(d, "B_axis", (0.0, 0.0, 0.0)))),
@@ -378,6 +383,30 @@ def profile(model: Model, refl, nodes, pix, tile, offsets, idx, count=False, ord
     img = torch.empty((g.height, g.width), dtype=torch.float32, device="cuda")
     _check(lib().fdtbx_profile(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(tile), _ptr(offsets),
                                _ptr(idx), _ptr(order), _ptr(img), None, _stream()))
+    return img
+
+
+def unit_pairs(n_pairs: int) -> int:
+    """fdtbx_unit_pairs: the library's pairs per work unit of the balanced launch."""
+    return int(lib().fdtbx_unit_pairs(int(n_pairs)))
+
+
+def profile_balanced(model: Model, refl, nodes, pix, tile, offsets, idx, order=None, pair_cap=None):
+    """fdtbx_profile_balanced: the image [H][W] float32 from the launch balanced over the
+    compute units (model.geom.unit_pairs pairs per work unit, 0: the library's choice).
+    pair_cap: capacity of idx (default: its length)."""
+    g = model.geom
+    cap = int(idx.shape[0]) if pair_cap is None else int(pair_cap)
+    if idx.numel() == 0:  # empty lists: any valid pointer
+        idx = torch.zeros(1, dtype=torch.int32, device="cuda")
+    wsb = lib().fdtbx_profile_balanced_workspace(ctypes.byref(model), cap)
+    if wsb == 0:
+        raise FdtbxError(-1, "fdtbx_profile_balanced_workspace: invalid model or capacity")
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    img = torch.empty((g.height, g.width), dtype=torch.float32, device="cuda")
+    _check(lib().fdtbx_profile_balanced(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(tile),
+                                        _ptr(offsets), _ptr(idx), _ptr(order), cap, _ptr(img), _ptr(ws), wsb,
+                                        _stream()))
     return img
 
 

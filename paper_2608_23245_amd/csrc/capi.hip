@@ -114,8 +114,10 @@ static PatternLayout layout(const fdtbx_model* m, int64_t n_hkl, int64_t pair_ca
   o += align_up((size_t)tiles * 8 * sizeof(double), 256);
   L.offsets = o;
   o += align_up((size_t)(tiles + 1) * sizeof(int64_t), 256);
+  // the culling workspace, and after the culling the balanced launch's unit tables and sums
   L.cullws = o;
-  o += align_up(fdtbx_cull_workspace(&m->geom, n_hkl), 256);
+  const size_t cw = fdtbx_cull_workspace(&m->geom, n_hkl), bw = balanced_workspace(m, pair_cap);
+  o += align_up(cw > bw ? cw : bw, 256);
   L.order = o;
   o += align_up((size_t)fdtbx_tile_order_size(&m->geom) * sizeof(int32_t), 256);
   L.orderws = o;
@@ -213,7 +215,8 @@ extern "C" int fdtbx_profile_pattern(const fdtbx_model* model, const int32_t* hk
   if (rc) return rc;
   rc = fdtbx_tile_order(&model->geom, offsets, order, w + L.orderws, fdtbx_tile_order_workspace(&model->geom), stream);
   if (rc) return rc;
-  return fdtbx_profile(model, refl, nodes, pix, tile, offsets, idx, order, image, nullptr, stream);
+  return launch_balanced(model, refl, nodes, pix, tile, offsets, idx, order, pair_cap, image, w + L.cullws,
+                         balanced_workspace(model, pair_cap), (hipStream_t)stream);
 }
 
 namespace fdtbx {
@@ -283,7 +286,8 @@ extern "C" int fdtbx_profile_pattern_async(const fdtbx_model* model, const int32
   if (rc || (rc = stamp(4))) return rc;
   rc = fdtbx_tile_order(&model->geom, offsets, order, w + L.orderws, fdtbx_tile_order_workspace(&model->geom), stream);
   if (rc || (rc = stamp(5))) return rc;
-  rc = fdtbx_profile(model, refl, nodes, pix, tile, offsets, idx, order, image, nullptr, stream);
+  rc = launch_balanced(model, refl, nodes, pix, tile, offsets, idx, order, pair_cap, image, w + L.cullws,
+                       balanced_workspace(model, pair_cap), s);
   if (rc || (rc = stamp(6))) return rc;
   if (count_evals && stats) {
     rc = fdtbx_profile(model, refl, nodes, pix, tile, offsets, idx, order, nullptr, &stats->useful_evals, stream);

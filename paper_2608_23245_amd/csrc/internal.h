@@ -187,6 +187,17 @@ __host__ __device__ inline double lineshape_half(int32_t lineshape, int32_t m) {
   return lineshape == FDTBX_LINESHAPE_HOSEMANN ? 0.5 : 0.5 * (double)m;
 }
 
+// Exclusive scan of n values in place with one block of 1024 threads; writes the grand total
+// to *total (exact.hip).
+__global__ void k_scan_inplace(int64_t* v, int64_t n, int64_t* total);
+
+// Balanced forward launch (profile.hip): workspace bytes for pair_cap culled pairs, and the
+// launch (see fdtbx_profile_balanced).
+size_t balanced_workspace(const fdtbx_model* model, int64_t pair_cap);
+int launch_balanced(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
+                    const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
+                    int64_t pair_cap, float* image, void* ws, size_t ws_bytes, hipStream_t s);
+
 // Batched launchers (one per translation unit that owns the kernels).
 int launch_batch_sf(const fdtbx_batch_entry* ent, const int64_t* blocks, int64_t n_rb, const float* x, const float* y,
                     const float* z, const float* B, const float* occ, const int32_t* type, const float* ff, const int32_t* hkl,

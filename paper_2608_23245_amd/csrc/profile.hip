@@ -107,6 +107,115 @@ __global__ void __launch_bounds__(64) k_b_profile(const fdtbx_batch_entry* __res
   }
 }
 
+// ---------------------------------------------------------------- balanced launch
+// The per-tile launch ends with a tail: a tile with a long list runs as one workgroup while
+// the compute units around it have drained.  The balanced launch cuts every launched tile's
+// list into units of at most U pairs, which persistent waves take from eight queues, one per
+// XCD: slot b of the per-tile launch order (the tile order of fdtbx_tile_order, whose slot b
+// runs on XCD b % 8) puts its tile's units in queue b % 8, in slot order (heavy tiles first
+// under the work order), so the units of neighbouring tiles still share an XCD's L2.  A wave
+// whose queue is empty takes units from the next queues.  Each unit writes its 64 pixel sums
+// to its own slot of the partial sums, and a second kernel adds a tile's units in unit order:
+// the image does not depend on which wave ran which unit.
+//
+// Queue-major position of slot b: (b % 8) nj + b / 8, nj = ceil(n_slots / 8).  qscan holds the
+// units per position, then (after k_scan_inplace) the first unit of each position; queue x
+// spans the units qscan[x nj] .. qscan[(x + 1) nj] (the total for the last queue).
+struct UnitTable {
+  const int32_t* order;  // tile of each slot, or null: the plain per-tile grid (tile_of_block)
+  int64_t n_slots, nj;
+  int64_t max_units;     // capacity of unit_slot and of the partial sums
+  int64_t fixed_U;       // pairs per unit, or 0: chosen from the pair count (default_unit_pairs)
+  int64_t* qscan;        // [8 nj]
+  int64_t* meta;         // [0]: total units, [1]: pairs per unit
+  int32_t* ctr;          // [8] queue counters
+  int32_t* unit_slot;    // [max_units] slot of each unit
+};
+
+__host__ __device__ inline int64_t queue_pos(int64_t b, int64_t nj) { return (b % kXcds) * nj + b / kXcds; }
+
+__device__ inline int slot_tile(const ProfParams& q, const UnitTable& T, int64_t b) {
+  if (b >= T.n_slots) return -1;
+  return T.order ? T.order[b] : tile_of_block(q, (int)b);
+}
+
+// Units per position (and the pairs per unit, from the pair count, by the first thread).
+__global__ void __launch_bounds__(256) k_unit_count(ProfParams q, UnitTable T, const int64_t* __restrict__ offsets,
+                                                    int64_t n_tiles) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t U = T.fixed_U > 0 ? T.fixed_U : default_unit_pairs(offsets[n_tiles]);
+  if (p == 0) T.meta[1] = U;
+  if (p < kXcds) T.ctr[p] = 0;
+  if (p >= kXcds * T.nj) return;
+  const int64_t b = (p % T.nj) * kXcds + p / T.nj;
+  const int t = slot_tile(q, T, b);
+  T.qscan[p] = t >= 0 ? ceil_div_dev(offsets[t + 1] - offsets[t], U) : 0;
+}
+
+// unit_slot over each slot's units (within the capacity).
+__global__ void __launch_bounds__(256) k_unit_fill(ProfParams q, UnitTable T, const int64_t* __restrict__ offsets) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= kXcds * T.nj) return;
+  const int64_t b = (p % T.nj) * kXcds + p / T.nj;
+  const int t = slot_tile(q, T, b);
+  if (t < 0) return;
+  const int64_t U = T.meta[1];
+  const int64_t n = ceil_div_dev(offsets[t + 1] - offsets[t], U), s = T.qscan[p];
+  for (int64_t k = 0; k < n && s + k < T.max_units; ++k) T.unit_slot[s + k] = (int32_t)b;
+}
+
+// Persistent: every wave takes units from its XCD's queue, then from the following queues,
+// until all are empty (the exit every wave reaches: each queue's counter only grows).
+template <int LS>
+__global__ void __launch_bounds__(256) k_profile_units(ProfParams q, const float* __restrict__ refl,
+                                                       const float* __restrict__ nodes, const double* __restrict__ pix,
+                                                       const double* __restrict__ tile, const int64_t* __restrict__ offsets,
+                                                       const int32_t* __restrict__ idx, UnitTable T,
+                                                       float* __restrict__ partials) {
+  __shared__ float4 qn[128 * 4];
+  __shared__ int bq[64 * 4];
+  const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int64_t total = min(T.meta[0], T.max_units), U = T.meta[1];
+  const int home = (int)(blockIdx.x % kXcds);
+  for (int k = 0; k < kXcds; ++k) {
+    const int x = (home + k) % kXcds;
+    const int64_t qb = T.qscan[x * T.nj];
+    const int64_t qe = min(x + 1 < kXcds ? T.qscan[(x + 1) * T.nj] : T.meta[0], total);
+    for (;;) {
+      int got = 0;
+      if (lane == 0) got = atomicAdd(&T.ctr[x], 1);
+      const int64_t u = qb + (int64_t)__builtin_amdgcn_readfirstlane(got);
+      if (u >= qe) break;  // uniform
+      const int64_t b = T.unit_slot[u];
+      const int t = slot_tile(q, T, b);
+      const int64_t p0 = offsets[t] + (u - T.qscan[queue_pos(b, T.nj)]) * U;
+      const int64_t p1 = min(offsets[t + 1], p0 + U);
+      const TilePixel px = tile_pixel(q, pix, tile, t, lane);
+      unsigned long long cnt = 0;
+      partials[u * 64 + lane] = pairs_sum<false, LS>(q, refl, nodes, idx, px.box, px.R, px.Z, p0, p1, 64,
+                                                     qn + 128 * wv, bq + 64 * wv, cnt);
+    }
+  }
+}
+
+// Per launched tile: its units' pixel sums added in unit order, times the Lorentz factor,
+// written with the mirror folds.
+__global__ void __launch_bounds__(64) k_unit_reduce(ProfParams q, UnitTable T, const double* __restrict__ pix,
+                                                    const double* __restrict__ tile, const int64_t* __restrict__ offsets,
+                                                    const float* __restrict__ partials, float* __restrict__ image) {
+  const int64_t b = blockIdx.x;
+  const int t = slot_tile(q, T, b);
+  if (t < 0) return;  // uniform
+  const int lane = (int)threadIdx.x;
+  const TilePixel px = tile_pixel(q, pix, tile, t, lane);
+  const int64_t U = T.meta[1];
+  const int64_t n = ceil_div_dev(offsets[t + 1] - offsets[t], U), s = T.qscan[queue_pos(b, T.nj)];
+  float acc = 0.0f;
+  for (int64_t k = 0; k < n && s + k < T.max_units; ++k) acc += partials[(s + k) * 64 + lane];
+  if (!px.in) return;
+  write_folded(q, image, px.i, px.j, px.tx, px.ty, (float)(q.delta / (px.R + q.delta)) * acc);
+}
+
 __global__ void k_zero_u64(unsigned long long* v, int n) {
   if ((int)threadIdx.x < n) v[threadIdx.x] = 0ull;
 }
@@ -123,6 +232,103 @@ int launch_batch_profile(const fdtbx_batch_entry* ent, const int64_t* items, int
   hipLaunchKernelGGL(k_b_profile, dim3(nb), dim3(64), 0, s, ent, items, n_items, refl, nodes, pix, tile, rowptr, idx, image,
                      (unsigned long long*)counter);
   FDTBX_LAUNCH_CHECK("batch profile");
+  return FDTBX_OK;
+}
+
+// Workspace of the balanced launch: the unit tables and the partial sums.
+struct UnitLayout {
+  int64_t n_slots, nj, max_units;
+  size_t qscan, meta, ctr, unit_slot, partials, total;
+};
+
+static UnitLayout unit_layout(const ProfParams& q, bool has_order, int64_t pair_cap, int64_t fixed_U) {
+  UnitLayout L;
+  L.n_slots = has_order ? order_grid(q.lcols, q.lrows) : tile_grid(q);
+  L.nj = ceil_div(L.n_slots, kXcds);
+  // sum over tiles of ceil(len / U) <= pair_cap / U + n_slots, and U >= 32 with U >= n_pairs / 2^19
+  // when it is the library's choice
+  const int64_t by_cap = ceil_div(pair_cap, fixed_U > 0 ? fixed_U : 32);
+  L.max_units = (fixed_U > 0 ? by_cap : (by_cap < kUnitTarget ? by_cap : kUnitTarget)) + L.n_slots;
+  size_t o = 0;
+  L.qscan = o;
+  o += align_up((size_t)(kXcds * L.nj) * sizeof(int64_t), 256);
+  L.meta = o;
+  o += 256;
+  L.ctr = o;
+  o += 256;
+  L.unit_slot = o;
+  o += align_up((size_t)L.max_units * sizeof(int32_t), 256);
+  L.partials = o;
+  o += align_up((size_t)L.max_units * 64 * sizeof(float), 256);
+  L.total = o;
+  return L;
+}
+
+// The persistent grid: as many 4-wave workgroups as the compute units hold at once.
+template <int LS>
+static int launch_units(const ProfParams& q, const float* refl, const float* nodes, const double* pix,
+                        const double* tile, const int64_t* offsets, const int32_t* idx, const UnitTable& T,
+                        float* partials, hipStream_t s) {
+  int dev = 0, cus = 0, per_cu = 0;
+  FDTBX_HIP(hipGetDevice(&dev));
+  FDTBX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  FDTBX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_profile_units<LS>),
+                                                         256, 0));
+  const unsigned n_wg = (unsigned)(cus > 0 ? cus : 1) * (unsigned)(per_cu > 0 ? per_cu : 1);
+  hipLaunchKernelGGL(k_profile_units<LS>, dim3(n_wg), dim3(256), 0, s, q, refl, nodes, pix, tile, offsets, idx, T,
+                     partials);
+  FDTBX_LAUNCH_CHECK("balanced profile");
+  return FDTBX_OK;
+}
+
+size_t balanced_workspace(const fdtbx_model* model, int64_t pair_cap) {
+  ProfParams q;
+  prof_params(model, &q);
+  const int64_t U = model->geom.unit_pairs;
+  const UnitLayout a = unit_layout(q, true, pair_cap, U), b = unit_layout(q, false, pair_cap, U);
+  return a.total > b.total ? a.total : b.total;
+}
+
+int launch_balanced(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
+                    const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
+                    int64_t pair_cap, float* image, void* ws, size_t ws_bytes, hipStream_t s) {
+  ProfParams q;
+  prof_params(model, &q);
+  const UnitLayout L = unit_layout(q, order != nullptr, pair_cap, model->geom.unit_pairs);
+  if (ws_bytes < L.total) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "balanced profile workspace too small");
+  if (L.max_units >= (int64_t{1} << 31) || L.n_slots >= (int64_t{1} << 31))
+    return fail(FDTBX_ERR_UNSUPPORTED, "balanced profile: too many units or tiles");
+  char* w = (char*)ws;
+  UnitTable T;
+  T.order = order;
+  T.n_slots = L.n_slots;
+  T.nj = L.nj;
+  T.max_units = L.max_units;
+  T.fixed_U = model->geom.unit_pairs;
+  T.qscan = (int64_t*)(w + L.qscan);
+  T.meta = (int64_t*)(w + L.meta);
+  T.ctr = (int32_t*)(w + L.ctr);
+  T.unit_slot = (int32_t*)(w + L.unit_slot);
+  float* partials = (float*)(w + L.partials);
+  const int64_t n_tiles = (int64_t)q.tiles_x * q.tiles_y;
+  const unsigned gp = (unsigned)ceil_div(kXcds * L.nj, 256);
+  hipLaunchKernelGGL(k_unit_count, dim3(gp), dim3(256), 0, s, q, T, offsets, n_tiles);
+  FDTBX_LAUNCH_CHECK("balanced profile: unit count");
+  hipLaunchKernelGGL(k_scan_inplace, dim3(1), dim3(1024), 0, s, T.qscan, kXcds * L.nj, T.meta);
+  FDTBX_LAUNCH_CHECK("balanced profile: unit scan");
+  hipLaunchKernelGGL(k_unit_fill, dim3(gp), dim3(256), 0, s, q, T, offsets);
+  FDTBX_LAUNCH_CHECK("balanced profile: unit fill");
+  int rc;
+  if (q.lineshape == FDTBX_LINESHAPE_GAUSSIAN)
+    rc = launch_units<FDTBX_LINESHAPE_GAUSSIAN>(q, refl, nodes, pix, tile, offsets, idx, T, partials, s);
+  else if (q.lineshape == FDTBX_LINESHAPE_HOSEMANN)
+    rc = launch_units<FDTBX_LINESHAPE_HOSEMANN>(q, refl, nodes, pix, tile, offsets, idx, T, partials, s);
+  else
+    rc = launch_units<FDTBX_LINESHAPE_LAUE>(q, refl, nodes, pix, tile, offsets, idx, T, partials, s);
+  if (rc) return rc;
+  hipLaunchKernelGGL(k_unit_reduce, dim3((unsigned)L.n_slots), dim3(64), 0, s, q, T, pix, tile, offsets,
+                     (const float*)partials, image);
+  FDTBX_LAUNCH_CHECK("balanced profile: reduce");
   return FDTBX_OK;
 }
 
@@ -152,4 +358,26 @@ extern "C" int fdtbx_profile(const fdtbx_model* model, const float* refl, const 
     launch_profile<1>(q, grid, s, refl, nodes, pix, tile, offsets, idx, order, image, counts);
   FDTBX_LAUNCH_CHECK("profile");
   return FDTBX_OK;
+}
+
+extern "C" int64_t fdtbx_unit_pairs(int64_t n_pairs) { return n_pairs < 0 ? 0 : default_unit_pairs(n_pairs); }
+
+extern "C" size_t fdtbx_profile_balanced_workspace(const fdtbx_model* model, int64_t pair_cap) {
+  if (!model || pair_cap < 0 || check_model(model)) return 0;
+  if (model->geom.unit_pairs < 0) return 0;
+  return balanced_workspace(model, pair_cap);
+}
+
+extern "C" int fdtbx_profile_balanced(const fdtbx_model* model, const float* refl, const float* nodes,
+                                      const double* pix, const double* tile, const int64_t* offsets,
+                                      const int32_t* idx, const int32_t* order, int64_t pair_cap, float* image,
+                                      void* ws, size_t ws_bytes, void* stream) {
+  if (!model || !refl || !nodes || !pix || !tile || !offsets || !idx || !image || !ws)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (pair_cap < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "pair_cap must be non-negative");
+  int rc = check_model(model);
+  if (rc) return rc;
+  if (model->geom.unit_pairs < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "unit_pairs must be non-negative");
+  return launch_balanced(model, refl, nodes, pix, tile, offsets, idx, order, pair_cap, image, ws, ws_bytes,
+                         (hipStream_t)stream);
 }

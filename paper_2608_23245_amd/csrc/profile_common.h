@@ -67,6 +67,18 @@ __device__ inline int tile_of_block(const ProfParams& q, int b) {
   return tx < q.lcols && ty < q.lrows ? ty * q.tiles_x + tx : -1;
 }
 
+__host__ __device__ inline int64_t ceil_div_dev(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Pairs per work unit of the balanced launch (fdtbx_profile_balanced) for a launch of n_pairs
+// culled pairs: at most 2^19 units in all besides one partial unit per tile (64 per wave of
+// 256 compute units with 32 waves each), at least 32 pairs.  A function of the pair count
+// alone, so that the image does not depend on the device.
+constexpr int64_t kUnitTarget = int64_t{1} << 19;
+__host__ __device__ inline int64_t default_unit_pairs(int64_t n_pairs) {
+  const int64_t U = (n_pairs + kUnitTarget - 1) / kUnitTarget;
+  return U < 32 ? 32 : U;
+}
+
 // Mirror folds.  Tile column tiles_x - 1 - tx holds the left-right mirror pixels of column tx
 // and tile row tiles_y - 1 - ty the up-down ones of row ty; a middle column or row (odd count)
 // is its own mirror, its pixels all computed.  write_folded stores a computed value at pixel

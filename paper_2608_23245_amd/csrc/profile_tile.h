@@ -107,35 +107,19 @@ __device__ __forceinline__ void walk_queue(const float4* qn, int cnt, const floa
   accr += part;
 }
 
-// WAVES waves share a tile: wave w takes the chunks w, w + WAVES, ... of 64 pairs of the
-// tile's list (its own LDS queue: qn + 128 w, bq + 64 w), and wave 0 adds the others' pixel
-// sums (xacc, 64 floats per extra wave) in wave order before it writes the tile.
-template <bool COUNT, int LS, int WAVES = 1>
-__device__ __forceinline__ void profile_tile(const ProfParams& q, const float* __restrict__ refl,
-                                             const float* __restrict__ nodes, const double* __restrict__ pix,
-                                             const double* __restrict__ tile, const int64_t* __restrict__ offsets,
-                                             const int32_t* __restrict__ idx, float* __restrict__ image,
-                                             unsigned long long* __restrict__ counts, const int t, float4* qn, int* bq,
-                                             float* xacc = nullptr) {
+// A lane's pixel sum over pairs of one tile's list: the chunks of 64 pairs that start at
+// from, from + step, from + 2 step, ... below p1 (each lane sets up one pair of a chunk: its
+// node window and alpha box; the wave then works through the pairs with a non-empty window,
+// reading their set-up from that lane).  R, Z: the lane's pixel; box: the tile's (R, Z) box.
+// qn, bq: this wave's LDS queue (128 float4) and scratch (64 ints).
+template <bool COUNT, int LS>
+__device__ __forceinline__ float pairs_sum(const ProfParams& q, const float* __restrict__ refl,
+                                           const float* __restrict__ nodes, const int32_t* __restrict__ idx,
+                                           const TileBox& box, double R, double Z, int64_t from, int64_t p1,
+                                           int64_t step, float4* qn, int* bq, unsigned long long& cnt) {
   const int lane = threadIdx.x & 63;
-  const int wv = WAVES > 1 ? (int)(threadIdx.x >> 6) : 0;
-  qn += 128 * wv;
-  bq += 64 * wv;
-  const int tx = t % q.tiles_x, ty = t / q.tiles_x;
-  const int i = (tx << q.tlg) + (lane & ((1 << q.tlg) - 1));
-  const int j = ty * (64 >> q.tlg) + (lane >> q.tlg);
-  const bool in = i < q.W && j < q.H;
-  // lanes outside the detector sit far from every reflection: all supports fail
-  const double R = in ? pix[2 * ((int64_t)j * q.W + i) + 0] : 1.0e30;
-  const double Z = in ? pix[2 * ((int64_t)j * q.W + i) + 1] : 0.0;
-  const TileBox box = {tile[8 * (int64_t)t + 0], tile[8 * (int64_t)t + 1], tile[8 * (int64_t)t + 2],
-                       tile[8 * (int64_t)t + 3]};
-  const int64_t p0 = offsets[t], p1 = offsets[t + 1];
   float acc = 0.0f;
-  unsigned long long cnt = 0;
-  // 64 pairs at a time: each lane sets up one pair (window and alpha box); the wave then
-  // works through the pairs with a non-empty window, reading their set-up from that lane
-  for (int64_t base = p0 + 64 * wv; base < p1; base += 64 * WAVES) {
+  for (int64_t base = from; base < p1; base += step) {
     int32_t rl = 0;
     int w01 = 0, w23 = 0;
     float lol[3] = {0.f, 0.f, 0.f}, hil[3] = {0.f, 0.f, 0.f};
@@ -191,6 +175,51 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
       if (!COUNT) acc = fmaf(f.at(RS_WK), accr, acc);
     }
   }
+  return acc;
+}
+
+// The pixel of lane `lane` in tile t: its column i, row j, whether it lies on the detector,
+// and its ring coordinates (lanes outside the detector sit far from every reflection, so all
+// supports fail); and the tile's (R, Z) box.
+struct TilePixel {
+  int tx, ty, i, j;
+  bool in;
+  double R, Z;
+  TileBox box;
+};
+
+__device__ __forceinline__ TilePixel tile_pixel(const ProfParams& q, const double* __restrict__ pix,
+                                                const double* __restrict__ tile, int t, int lane) {
+  TilePixel p;
+  p.tx = t % q.tiles_x;
+  p.ty = t / q.tiles_x;
+  p.i = (p.tx << q.tlg) + (lane & ((1 << q.tlg) - 1));
+  p.j = p.ty * (64 >> q.tlg) + (lane >> q.tlg);
+  p.in = p.i < q.W && p.j < q.H;
+  p.R = p.in ? pix[2 * ((int64_t)p.j * q.W + p.i) + 0] : 1.0e30;
+  p.Z = p.in ? pix[2 * ((int64_t)p.j * q.W + p.i) + 1] : 0.0;
+  p.box = {tile[8 * (int64_t)t + 0], tile[8 * (int64_t)t + 1], tile[8 * (int64_t)t + 2], tile[8 * (int64_t)t + 3]};
+  return p;
+}
+
+// WAVES waves share a tile: wave w takes the chunks w, w + WAVES, ... of 64 pairs of the
+// tile's list (its own LDS queue: qn + 128 w, bq + 64 w), and wave 0 adds the others' pixel
+// sums (xacc, 64 floats per extra wave) in wave order before it writes the tile.
+template <bool COUNT, int LS, int WAVES = 1>
+__device__ __forceinline__ void profile_tile(const ProfParams& q, const float* __restrict__ refl,
+                                             const float* __restrict__ nodes, const double* __restrict__ pix,
+                                             const double* __restrict__ tile, const int64_t* __restrict__ offsets,
+                                             const int32_t* __restrict__ idx, float* __restrict__ image,
+                                             unsigned long long* __restrict__ counts, const int t, float4* qn, int* bq,
+                                             float* xacc = nullptr) {
+  const int lane = threadIdx.x & 63;
+  const int wv = WAVES > 1 ? (int)(threadIdx.x >> 6) : 0;
+  qn += 128 * wv;
+  bq += 64 * wv;
+  const TilePixel px = tile_pixel(q, pix, tile, t, lane);
+  unsigned long long cnt = 0;
+  float acc = pairs_sum<COUNT, LS>(q, refl, nodes, idx, px.box, px.R, px.Z, offsets[t] + 64 * wv, offsets[t + 1],
+                                   64 * WAVES, qn, bq, cnt);
   if (COUNT) {
     for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
     if (lane == 0 && cnt) atomicAdd(counts, cnt);
@@ -201,8 +230,8 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
       if (wv > 0) return;
       for (int k = 1; k < WAVES; ++k) acc += xacc[64 * (k - 1) + lane];
     }
-    if (!in) return;
-    write_folded(q, image, i, j, tx, ty, (float)(q.delta / (R + q.delta)) * acc);
+    if (!px.in) return;
+    write_folded(q, image, px.i, px.j, px.tx, px.ty, (float)(q.delta / (px.R + q.delta)) * acc);
   }
 }
 

@@ -62,6 +62,7 @@ class Geometry:
     mirror: int = 0        # GPU launch folds, bit 0: left-right (needs center_x = width/2); bit 1: up-down
                            # (needs center_y = height/2 and tilt 0)
     tile_waves: int = 0    # waves per tile of the GPU profile launch (0: the library's choice)
+    unit_pairs: int = 0    # pairs per work unit of the balanced GPU launch (0: the library's choice)
 
 
 @dataclasses.dataclass
