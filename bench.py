@@ -600,12 +600,14 @@ def bench_fwd_bwd(args):
     off, idx = B.cull(model.geom, tile, cull)
     order = B.tile_order(model.geom, off)
     G = res["G"]
-    B.profile_adjoint(model, refl, nodes, pix, tile, off, idx, G, order=order)
+    bws = B.balanced_workspace(model, int(idx.shape[0]))
+    B.profile_balanced(model, refl, nodes, pix, tile, off, idx, order=order, ws=bws)  # the work units
+    B.profile_adjoint_balanced(model, refl, nodes, pix, tile, off, idx, G, bws, order=order)
     torch.cuda.synchronize()
     aev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(2)]
     for e0, e1 in aev:
         e0.record(stream)
-        B.profile_adjoint(model, refl, nodes, pix, tile, off, idx, G, order=order)
+        B.profile_adjoint_balanced(model, refl, nodes, pix, tile, off, idx, G, bws, order=order)
         e1.record(stream)
     torch.cuda.synchronize()
     adj_ms = float(np.mean([a.elapsed_time(b) for a, b in aev]))
@@ -614,7 +616,7 @@ def bench_fwd_bwd(args):
     return {"workload": "refinement: medium model vs perturbed target (xyz N(0,0.1 A), B x1.2, sigma 3.5 deg, g .035), "
                         "loss sum w (I - T)^2, w = 1/(T + 1e-3 max T)",
             "ms_per_step": ms, "backward_ms": bwd_ms, "forward_ms": ms - bwd_ms, "loss": loss,
-            "profile_adjoint_ms": adj_ms, "useful_evals": int(n_evals), "kernel": "k_profile_adj<0>",
+            "profile_adjoint_ms": adj_ms, "useful_evals": int(n_evals), "kernel": "k_profile_adj_units<0>",
             "slots": {"achieved": achieved, "peak": PEAK_SLOTS / 1e12, "unit": "Tslot/s",
                       "frac": achieved / (PEAK_SLOTS / 1e12), "slots_per_eval": ADJ_SLOTS_PER_EVAL},
             "steps": args.steps, "pass": "forward + adjoint (atoms xyz/B/occ, sigma, gamma, N_base, g)"}

@@ -505,6 +505,18 @@ int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl, const flo
                           const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
                           int64_t n_hkl, const float* grad_image, double* sums, void* stream);
 
+/* fdtbx_profile_adjoint_balanced: fdtbx_profile_adjoint over the work units of a
+ * fdtbx_profile_balanced call (persistent waves taking the units from the eight XCD queues, so
+ * no long list runs as one workgroup at the end).  bal_ws, bal_ws_bytes: the workspace of that
+ * call, with the same model (unit_pairs included), lists, order and pair_cap, and no other
+ * balanced launch on it since; its unit tables are read and its queue counters reused.  The
+ * sums come out as fdtbx_profile_adjoint's (binary64 atomic adds, so their order and last bits
+ * vary from run to run). */
+int fdtbx_profile_adjoint_balanced(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
+                                   const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
+                                   int64_t pair_cap, int64_t n_hkl, const float* grad_image, double* sums, void* bal_ws,
+                                   size_t bal_ws_bytes, void* stream);
+
 /* Fixed-order (deterministic) accumulation of the same sums, in three calls (section
  * "Race detection" of the method's test strategy: gradients reproducible bit for bit).
  *

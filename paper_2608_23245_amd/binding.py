@@ -157,6 +157,9 @@ _SIGS = {
     "fdtbx_profile_balanced_workspace": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64]),
     "fdtbx_profile_balanced": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 7 +
                                [ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
+    "fdtbx_profile_adjoint_balanced": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 7 +
+                                       [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "fdtbx_pattern_backward_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
                                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                                        ctypes.c_size_t, ctypes.c_int64, ctypes.c_int64] +
@@ -391,10 +394,12 @@ def unit_pairs(n_pairs: int) -> int:
     return int(lib().fdtbx_unit_pairs(int(n_pairs)))
 
 
-def profile_balanced(model: Model, refl, nodes, pix, tile, offsets, idx, order=None, pair_cap=None):
+def profile_balanced(model: Model, refl, nodes, pix, tile, offsets, idx, order=None, pair_cap=None, ws=None):
     """fdtbx_profile_balanced: the image [H][W] float32 from the launch balanced over the
     compute units (model.geom.unit_pairs pairs per work unit, 0: the library's choice).
-    pair_cap: capacity of idx (default: its length)."""
+    pair_cap: capacity of idx (default: its length).  ws: a uint8 device tensor of at least
+    fdtbx_profile_balanced_workspace bytes to use (and keep the unit tables in, for
+    profile_adjoint_balanced), or None."""
     g = model.geom
     cap = int(idx.shape[0]) if pair_cap is None else int(pair_cap)
     if idx.numel() == 0:  # empty lists: any valid pointer
@@ -402,12 +407,37 @@ def profile_balanced(model: Model, refl, nodes, pix, tile, offsets, idx, order=N
     wsb = lib().fdtbx_profile_balanced_workspace(ctypes.byref(model), cap)
     if wsb == 0:
         raise FdtbxError(-1, "fdtbx_profile_balanced_workspace: invalid model or capacity")
-    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    if ws is None:
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     img = torch.empty((g.height, g.width), dtype=torch.float32, device="cuda")
     _check(lib().fdtbx_profile_balanced(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(tile),
-                                        _ptr(offsets), _ptr(idx), _ptr(order), cap, _ptr(img), _ptr(ws), wsb,
-                                        _stream()))
+                                        _ptr(offsets), _ptr(idx), _ptr(order), cap, _ptr(img), _ptr(ws),
+                                        int(ws.numel()), _stream()))
     return img
+
+
+def balanced_workspace(model: Model, pair_cap: int) -> torch.Tensor:
+    """A device workspace for profile_balanced and profile_adjoint_balanced."""
+    wsb = lib().fdtbx_profile_balanced_workspace(ctypes.byref(model), int(pair_cap))
+    if wsb == 0:
+        raise FdtbxError(-1, "fdtbx_profile_balanced_workspace: invalid model or capacity")
+    return torch.empty(wsb, dtype=torch.uint8, device="cuda")
+
+
+def profile_adjoint_balanced(model: Model, refl, nodes, pix, tile, offsets, idx, grad_image: torch.Tensor, ws,
+                             order=None, pair_cap=None) -> torch.Tensor:
+    """fdtbx_profile_adjoint_balanced: per-reflection sums float64 [n_hkl][6] over the work
+    units of the profile_balanced call that used ws (same model, lists, order and pair_cap)."""
+    n = int(refl.shape[0])
+    _dev(grad_image, torch.float32, "grad_image")
+    cap = int(idx.shape[0]) if pair_cap is None else int(pair_cap)
+    if idx.numel() == 0:
+        idx = torch.zeros(1, dtype=torch.int32, device="cuda")
+    sums = torch.empty((n, 6), dtype=torch.float64, device=refl.device)
+    _check(lib().fdtbx_profile_adjoint_balanced(ctypes.byref(model), _ptr(refl), _ptr(nodes), _ptr(pix), _ptr(tile),
+                                                _ptr(offsets), _ptr(idx), _ptr(order), cap, n, _ptr(grad_image),
+                                                _ptr(sums), _ptr(ws), int(ws.numel()), _stream()))
+    return sums
 
 
 def cyl_records(model: Model, hkl) -> torch.Tensor:

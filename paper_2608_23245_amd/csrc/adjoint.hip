@@ -65,6 +65,88 @@ static void launch_adj(const ProfParams& q, dim3 grid, hipStream_t s, const floa
                        idx, grad_image, n_hkl, sums, partials, order);
 }
 
+// Balanced adjoint: persistent waves over the work units of a balanced forward launch of the
+// same lists (its unit tables, read only), with queue counters of their own.  A unit's pairs
+// send their sums out on their own, as in the per-tile launch, so units need no combining.
+template <int LS>
+__global__ void __launch_bounds__(256) k_profile_adj_units(ProfParams q, const float* __restrict__ refl,
+                                                           const float* __restrict__ nodes,
+                                                           const double* __restrict__ pix,
+                                                           const double* __restrict__ tile,
+                                                           const int64_t* __restrict__ offsets,
+                                                           const int32_t* __restrict__ idx,
+                                                           const float* __restrict__ grad_image, int64_t n_hkl,
+                                                           double* __restrict__ sums, float* __restrict__ partials,
+                                                           UnitTable T) {
+  __shared__ float4 qn[128 * 4];
+  __shared__ float2 qd[128 * 4];
+  __shared__ int bq[64 * 4];
+  const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
+  const int64_t U = T.meta[1];
+  const int64_t total = U > 0 ? min(T.meta[0], T.max_units) : 0;
+  const int home = (int)(blockIdx.x % kXcds);
+  for (int k = 0; k < kXcds; ++k) {
+    const int x = (home + k) % kXcds;
+    int64_t qb, qe;
+    queue_span(T, x, total, &qb, &qe);
+    for (;;) {
+      int got = 0;
+      if (lane == 0) got = atomicAdd(&T.ctr[x], 1);
+      const int64_t u = qb + (int64_t)__builtin_amdgcn_readfirstlane(got);
+      if (u >= qe) break;  // uniform
+      int64_t p0, p1;
+      const int t = unit_range(q, T, offsets, u, U, &p0, &p1);
+      if (t < 0) continue;
+      adjoint_range<LS>(q, refl, nodes, pix, tile, idx, grad_image, n_hkl, sums, partials, t, p0, p1, 64,
+                        qn + 128 * wv, qd + 128 * wv, bq + 64 * wv);
+    }
+  }
+}
+
+__global__ void k_zero_i32(int32_t* __restrict__ v, int n) {
+  if ((int)threadIdx.x < n) v[threadIdx.x] = 0;
+}
+
+template <int LS>
+static int launch_adj_units(const ProfParams& q, const float* refl, const float* nodes, const double* pix,
+                            const double* tile, const int64_t* offsets, const int32_t* idx, const float* grad_image,
+                            int64_t n_hkl, double* sums, float* partials, const UnitTable& T, hipStream_t s) {
+  int dev = 0, cus = 0, per_cu = 0;
+  FDTBX_HIP(hipGetDevice(&dev));
+  FDTBX_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  FDTBX_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_profile_adj_units<LS>),
+                                                         256, 0));
+  const unsigned n_wg = (unsigned)(cus > 0 ? cus : 1) * (unsigned)(per_cu > 0 ? per_cu : 1);
+  hipLaunchKernelGGL(k_profile_adj_units<LS>, dim3(n_wg), dim3(256), 0, s, q, refl, nodes, pix, tile, offsets, idx,
+                     grad_image, n_hkl, sums, partials, T);
+  FDTBX_LAUNCH_CHECK("balanced profile adjoint");
+  return FDTBX_OK;
+}
+
+// The balanced adjoint over the units that the balanced forward launch with the same model,
+// lists, order and pair_cap left in units_ws; ctr: 8 int32 of device memory for its queues.
+// The sums (or partials) must be cleared by the caller.
+int launch_adjoint_units(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
+                         const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
+                         int64_t pair_cap, const void* units_ws, int32_t* ctr, int64_t n_hkl, const float* grad_image,
+                         double* sums, float* partials, hipStream_t s) {
+  ProfParams q;
+  prof_params(model, &q);
+  const UnitLayout L = unit_layout(q, order != nullptr, pair_cap, model->geom.unit_pairs);
+  UnitTable T = unit_view(L, order, model->geom.unit_pairs, const_cast<void*>(units_ws));
+  T.ctr = ctr;
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(64), 0, s, ctr, kXcds);
+  FDTBX_LAUNCH_CHECK("balanced adjoint counters");
+  if (q.lineshape == FDTBX_LINESHAPE_GAUSSIAN)
+    return launch_adj_units<FDTBX_LINESHAPE_GAUSSIAN>(q, refl, nodes, pix, tile, offsets, idx, grad_image, n_hkl, sums,
+                                                      partials, T, s);
+  if (q.lineshape == FDTBX_LINESHAPE_HOSEMANN)
+    return launch_adj_units<FDTBX_LINESHAPE_HOSEMANN>(q, refl, nodes, pix, tile, offsets, idx, grad_image, n_hkl, sums,
+                                                      partials, T, s);
+  return launch_adj_units<FDTBX_LINESHAPE_LAUE>(q, refl, nodes, pix, tile, offsets, idx, grad_image, n_hkl, sums,
+                                                partials, T, s);
+}
+
 __global__ void k_zero_f64(double* __restrict__ v, int64_t n) {
   int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (k < n) v[k] = 0.0;
@@ -581,6 +663,31 @@ extern "C" int fdtbx_profile_adjoint(const fdtbx_model* model, const float* refl
   hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(6 * n_hkl, 256)), dim3(256), 0, s, sums, 6 * n_hkl);
   FDTBX_LAUNCH_CHECK("adjoint zero");
   return launch_profile_adjoint(model, refl, nodes, pix, tile, offsets, idx, order, n_hkl, grad_image, sums, nullptr, s);
+}
+
+extern "C" int fdtbx_profile_adjoint_balanced(const fdtbx_model* model, const float* refl, const float* nodes,
+                                              const double* pix, const double* tile, const int64_t* offsets,
+                                              const int32_t* idx, const int32_t* order, int64_t pair_cap, int64_t n_hkl,
+                                              const float* grad_image, double* sums, void* bal_ws, size_t bal_ws_bytes,
+                                              void* stream) {
+  if (!model) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl < 0 || pair_cap < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl and pair_cap must be non-negative");
+  int rc = check_model(model);
+  if (rc) return rc;
+  if (model->geom.unit_pairs < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "unit_pairs must be non-negative");
+  if (n_hkl == 0) return FDTBX_OK;  // no reflections: nothing to sum
+  if (!refl || !nodes || !pix || !tile || !offsets || !idx || !grad_image || !sums || !bal_ws)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  ProfParams q;
+  prof_params(model, &q);
+  const UnitLayout L = unit_layout(q, order != nullptr, pair_cap, model->geom.unit_pairs);
+  if (bal_ws_bytes < L.total) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "balanced workspace too small");
+  hipStream_t s = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_zero_f64, dim3((unsigned)ceil_div(6 * n_hkl, 256)), dim3(256), 0, s, sums, 6 * n_hkl);
+  FDTBX_LAUNCH_CHECK("adjoint zero");
+  // the forward launch is done with its queue counters: the adjoint takes them over
+  return launch_adjoint_units(model, refl, nodes, pix, tile, offsets, idx, order, pair_cap, bal_ws,
+                              (int32_t*)((char*)bal_ws + L.ctr), n_hkl, grad_image, sums, nullptr, s);
 }
 
 extern "C" int fdtbx_profile_adjoint_pairs(const fdtbx_model* model, const float* refl, const float* nodes,

@@ -107,17 +107,18 @@ __device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* q
 // (binary64 [n_hkl][6]) with hardware atomics; otherwise pair p of the culling lists stores its
 // twelve float32 sums (r's six, then the mate's six; zero without the up-down fold) at
 // partials[12 p], for a reduction in a fixed order (fdtbx_pair_reduce).
-template <int LS, int WAVES = 1>
-__device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* __restrict__ refl, const float* __restrict__ nodes,
-                                             const double* __restrict__ pix, const double* __restrict__ tile,
-                                             const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
-                                             const float* __restrict__ grad_image, int64_t n_hkl, double* __restrict__ sums,
-                                             float* __restrict__ partials, const int t, float4* qn, float2* qd, int* bq) {
+//
+// adjoint_range walks the chunks of 64 pairs of tile t's list that start at from, from + step,
+// ... below p1, with this wave's queues qn, qd, bq; adjoint_tile gives each of its WAVES waves
+// its share of the list, and the balanced launch gives a wave one unit of the list at a time.
+template <int LS>
+__device__ __forceinline__ void adjoint_range(const ProfParams& q, const float* __restrict__ refl,
+                                              const float* __restrict__ nodes, const double* __restrict__ pix,
+                                              const double* __restrict__ tile, const int32_t* __restrict__ idx,
+                                              const float* __restrict__ grad_image, int64_t n_hkl,
+                                              double* __restrict__ sums, float* __restrict__ partials, const int t,
+                                              int64_t from, int64_t p1, int64_t step, float4* qn, float2* qd, int* bq) {
   const int lane = threadIdx.x & 63;
-  const int wv = WAVES > 1 ? (int)(threadIdx.x >> 6) : 0;
-  qn += 128 * wv;
-  qd += 128 * wv;
-  bq += 64 * wv;
   const int tx = t % q.tiles_x, ty = t / q.tiles_x;
   const int i = (tx << q.tlg) + (lane & ((1 << q.tlg) - 1));
   const int j = ty * (64 >> q.tlg) + (lane >> q.tlg);
@@ -132,11 +133,10 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
   const float gA = wa * lor, gB = wb * lor;
   const TileBox box = {tile[8 * (int64_t)t + 0], tile[8 * (int64_t)t + 1], tile[8 * (int64_t)t + 2],
                        tile[8 * (int64_t)t + 3]};
-  const int64_t p0 = offsets[t], p1 = offsets[t + 1];
   // a tile whose pixels all carry zero weight adds nothing
   if (__ballot(gA != 0.0f || gB != 0.0f) == 0ull) return;
   // 64 pairs at a time, set up lane-parallel as in the forward tile loop
-  for (int64_t base = p0 + 64 * wv; base < p1; base += 64 * WAVES) {
+  for (int64_t base = from; base < p1; base += step) {
     int32_t rl = 0;
     int w01 = 0, w23 = 0;
     float lol[3] = {0.f, 0.f, 0.f}, hil[3] = {0.f, 0.f, 0.f};
@@ -232,6 +232,17 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
       }
     }
   }
+}
+
+template <int LS, int WAVES = 1>
+__device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* __restrict__ refl, const float* __restrict__ nodes,
+                                             const double* __restrict__ pix, const double* __restrict__ tile,
+                                             const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
+                                             const float* __restrict__ grad_image, int64_t n_hkl, double* __restrict__ sums,
+                                             float* __restrict__ partials, const int t, float4* qn, float2* qd, int* bq) {
+  const int wv = WAVES > 1 ? (int)(threadIdx.x >> 6) : 0;
+  adjoint_range<LS>(q, refl, nodes, pix, tile, idx, grad_image, n_hkl, sums, partials, t, offsets[t] + 64 * wv,
+                    offsets[t + 1], 64 * WAVES, qn + 128 * wv, qd + 128 * wv, bq + 64 * wv);
 }
 
 }  // namespace fdtbx

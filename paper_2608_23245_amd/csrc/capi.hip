@@ -302,6 +302,7 @@ extern "C" size_t fdtbx_backward_workspace(int64_t n_hkl, int64_t n_atoms) {
   size_t b = align_up((size_t)n_hkl * 6 * sizeof(double), 256);
   b += align_up(fdtbx_adjoint_finish_workspace(n_hkl), 256);
   b += align_up((size_t)n_hkl * sizeof(float), 256);
+  b += 256;  // queue counters of the balanced adjoint launch
   if (n_atoms > 0) b += align_up(fdtbx_sf_adjoint_workspace(n_hkl, n_atoms), 256);
   return b;
 }
@@ -350,7 +351,14 @@ extern "C" int fdtbx_pattern_backward(const fdtbx_model* model, const int32_t* h
   w += align_up(fin_bytes, 256);
   float* g2 = dF2 ? dF2 : (float*)w;
   w += align_up((size_t)n_hkl * sizeof(float), 256);
-  rc = fdtbx_profile_adjoint(model, refl, nodes, pix, tile, offsets, idx, order, n_hkl, grad_image, sums, stream);
+  int32_t* ctr = (int32_t*)w;
+  w += 256;
+  hipStream_t s = (hipStream_t)stream;
+  rc = fill(sums, 6 * n_hkl, 0.0, s);
+  if (rc) return rc;
+  // the work units of the balanced forward launch, still in the forward workspace
+  rc = launch_adjoint_units(model, refl, nodes, pix, tile, offsets, idx, order, pair_cap, fw + L.cullws, ctr, n_hkl,
+                            grad_image, sums, nullptr, s);
   if (rc) return rc;
   rc = fdtbx_adjoint_finish(model, hkl, n_hkl, refl, sums, F, g2, d_globals, fin, fin_bytes, stream);
   if (rc) return rc;
@@ -414,6 +422,8 @@ extern "C" int fdtbx_pattern_backward_deterministic(
   w += align_up(fin_bytes, 256);
   float* g2 = dF2 ? dF2 : (float*)w;
   w += align_up((size_t)n_hkl * sizeof(float), 256);
+  int32_t* ctr = (int32_t*)w;
+  w += 256;
   void* sfw = w;
   if (atoms) w += align_up(fdtbx_sf_adjoint_workspace(n_hkl, n_atoms), 256);
   float* partials = (float*)w;
@@ -422,8 +432,12 @@ extern "C" int fdtbx_pattern_backward_deterministic(
   w += align_up((size_t)(n_hkl + 1) * sizeof(int64_t), 256);
   int32_t* refl_pairs = (int32_t*)w;
   w += align_up((size_t)pair_cap * sizeof(int32_t), 256);
-  rc = fdtbx_profile_adjoint_pairs(model, refl, nodes, pix, tile, offsets, idx, order, n_hkl, pair_cap, grad_image,
-                                   partials, stream);
+  hipStream_t s = (hipStream_t)stream;
+  rc = fill(partials, 12 * pair_cap, 0.0f, s);
+  if (rc) return rc;
+  // the work units of the balanced forward launch, still in the forward workspace
+  rc = launch_adjoint_units(model, refl, nodes, pix, tile, offsets, idx, order, pair_cap, fw + L.cullws, ctr, n_hkl,
+                            grad_image, nullptr, partials, s);
   if (rc) return rc;
   rc = fdtbx_pair_transpose(n_hkl, idx, pair_cap, n_pairs_dev, refl_ptr, refl_pairs, w,
                             fdtbx_pair_transpose_workspace(n_hkl, pair_cap), stream);

@@ -198,6 +198,13 @@ int launch_balanced(const fdtbx_model* model, const float* refl, const float* no
                     const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
                     int64_t pair_cap, float* image, void* ws, size_t ws_bytes, hipStream_t s);
 
+// Balanced adjoint (adjoint.hip) over the unit tables a balanced forward launch left in
+// units_ws; ctr: 8 int32 of device scratch; sums or partials cleared by the caller.
+int launch_adjoint_units(const fdtbx_model* model, const float* refl, const float* nodes, const double* pix,
+                         const double* tile, const int64_t* offsets, const int32_t* idx, const int32_t* order,
+                         int64_t pair_cap, const void* units_ws, int32_t* ctr, int64_t n_hkl, const float* grad_image,
+                         double* sums, float* partials, hipStream_t s);
+
 // Batched launchers (one per translation unit that owns the kernels).
 int launch_batch_sf(const fdtbx_batch_entry* ent, const int64_t* blocks, int64_t n_rb, const float* x, const float* y,
                     const float* z, const float* B, const float* occ, const int32_t* type, const float* ff, const int32_t* hkl,

@@ -118,27 +118,6 @@ __global__ void __launch_bounds__(64) k_b_profile(const fdtbx_batch_entry* __res
 // to its own slot of the partial sums, and a second kernel adds a tile's units in unit order:
 // the image does not depend on which wave ran which unit.
 //
-// Queue-major position of slot b: (b % 8) nj + b / 8, nj = ceil(n_slots / 8).  qscan holds the
-// units per position, then (after k_scan_inplace) the first unit of each position; queue x
-// spans the units qscan[x nj] .. qscan[(x + 1) nj] (the total for the last queue).
-struct UnitTable {
-  const int32_t* order;  // tile of each slot, or null: the plain per-tile grid (tile_of_block)
-  int64_t n_slots, nj;
-  int64_t max_units;     // capacity of unit_slot and of the partial sums
-  int64_t fixed_U;       // pairs per unit, or 0: chosen from the pair count (default_unit_pairs)
-  int64_t* qscan;        // [8 nj]
-  int64_t* meta;         // [0]: total units, [1]: pairs per unit
-  int32_t* ctr;          // [8] queue counters
-  int32_t* unit_slot;    // [max_units] slot of each unit
-};
-
-__host__ __device__ inline int64_t queue_pos(int64_t b, int64_t nj) { return (b % kXcds) * nj + b / kXcds; }
-
-__device__ inline int slot_tile(const ProfParams& q, const UnitTable& T, int64_t b) {
-  if (b >= T.n_slots) return -1;
-  return T.order ? T.order[b] : tile_of_block(q, (int)b);
-}
-
 // Units per position (and the pairs per unit, from the pair count, by the first thread).
 __global__ void __launch_bounds__(256) k_unit_count(ProfParams q, UnitTable T, const int64_t* __restrict__ offsets,
                                                     int64_t n_tiles) {
@@ -175,21 +154,21 @@ __global__ void __launch_bounds__(256) k_profile_units(ProfParams q, const float
   __shared__ float4 qn[128 * 4];
   __shared__ int bq[64 * 4];
   const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
-  const int64_t total = min(T.meta[0], T.max_units), U = T.meta[1];
+  const int64_t U = T.meta[1];
+  const int64_t total = U > 0 ? min(T.meta[0], T.max_units) : 0;
   const int home = (int)(blockIdx.x % kXcds);
   for (int k = 0; k < kXcds; ++k) {
     const int x = (home + k) % kXcds;
-    const int64_t qb = T.qscan[x * T.nj];
-    const int64_t qe = min(x + 1 < kXcds ? T.qscan[(x + 1) * T.nj] : T.meta[0], total);
+    int64_t qb, qe;
+    queue_span(T, x, total, &qb, &qe);
     for (;;) {
       int got = 0;
       if (lane == 0) got = atomicAdd(&T.ctr[x], 1);
       const int64_t u = qb + (int64_t)__builtin_amdgcn_readfirstlane(got);
       if (u >= qe) break;  // uniform
-      const int64_t b = T.unit_slot[u];
-      const int t = slot_tile(q, T, b);
-      const int64_t p0 = offsets[t] + (u - T.qscan[queue_pos(b, T.nj)]) * U;
-      const int64_t p1 = min(offsets[t + 1], p0 + U);
+      int64_t p0, p1;
+      const int t = unit_range(q, T, offsets, u, U, &p0, &p1);
+      if (t < 0) continue;
       const TilePixel px = tile_pixel(q, pix, tile, t, lane);
       unsigned long long cnt = 0;
       partials[u * 64 + lane] = pairs_sum<false, LS>(q, refl, nodes, idx, px.box, px.R, px.Z, p0, p1, 64,
@@ -209,9 +188,10 @@ __global__ void __launch_bounds__(64) k_unit_reduce(ProfParams q, UnitTable T, c
   const int lane = (int)threadIdx.x;
   const TilePixel px = tile_pixel(q, pix, tile, t, lane);
   const int64_t U = T.meta[1];
-  const int64_t n = ceil_div_dev(offsets[t + 1] - offsets[t], U), s = T.qscan[queue_pos(b, T.nj)];
+  const int64_t n = U > 0 ? ceil_div_dev(offsets[t + 1] - offsets[t], U) : 0, s = T.qscan[queue_pos(b, T.nj)];
   float acc = 0.0f;
-  for (int64_t k = 0; k < n && s + k < T.max_units; ++k) acc += partials[(s + k) * 64 + lane];
+  for (int64_t k = 0; k < n && s + k < T.max_units; ++k)
+    if (s + k >= 0) acc += partials[(s + k) * 64 + lane];
   if (!px.in) return;
   write_folded(q, image, px.i, px.j, px.tx, px.ty, (float)(q.delta / (px.R + q.delta)) * acc);
 }
@@ -233,35 +213,6 @@ int launch_batch_profile(const fdtbx_batch_entry* ent, const int64_t* items, int
                      (unsigned long long*)counter);
   FDTBX_LAUNCH_CHECK("batch profile");
   return FDTBX_OK;
-}
-
-// Workspace of the balanced launch: the unit tables and the partial sums.
-struct UnitLayout {
-  int64_t n_slots, nj, max_units;
-  size_t qscan, meta, ctr, unit_slot, partials, total;
-};
-
-static UnitLayout unit_layout(const ProfParams& q, bool has_order, int64_t pair_cap, int64_t fixed_U) {
-  UnitLayout L;
-  L.n_slots = has_order ? order_grid(q.lcols, q.lrows) : tile_grid(q);
-  L.nj = ceil_div(L.n_slots, kXcds);
-  // sum over tiles of ceil(len / U) <= pair_cap / U + n_slots, and U >= 32 with U >= n_pairs / 2^19
-  // when it is the library's choice
-  const int64_t by_cap = ceil_div(pair_cap, fixed_U > 0 ? fixed_U : 32);
-  L.max_units = (fixed_U > 0 ? by_cap : (by_cap < kUnitTarget ? by_cap : kUnitTarget)) + L.n_slots;
-  size_t o = 0;
-  L.qscan = o;
-  o += align_up((size_t)(kXcds * L.nj) * sizeof(int64_t), 256);
-  L.meta = o;
-  o += 256;
-  L.ctr = o;
-  o += 256;
-  L.unit_slot = o;
-  o += align_up((size_t)L.max_units * sizeof(int32_t), 256);
-  L.partials = o;
-  o += align_up((size_t)L.max_units * 64 * sizeof(float), 256);
-  L.total = o;
-  return L;
 }
 
 // The persistent grid: as many 4-wave workgroups as the compute units hold at once.
@@ -298,18 +249,8 @@ int launch_balanced(const fdtbx_model* model, const float* refl, const float* no
   if (ws_bytes < L.total) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "balanced profile workspace too small");
   if (L.max_units >= (int64_t{1} << 31) || L.n_slots >= (int64_t{1} << 31))
     return fail(FDTBX_ERR_UNSUPPORTED, "balanced profile: too many units or tiles");
-  char* w = (char*)ws;
-  UnitTable T;
-  T.order = order;
-  T.n_slots = L.n_slots;
-  T.nj = L.nj;
-  T.max_units = L.max_units;
-  T.fixed_U = model->geom.unit_pairs;
-  T.qscan = (int64_t*)(w + L.qscan);
-  T.meta = (int64_t*)(w + L.meta);
-  T.ctr = (int32_t*)(w + L.ctr);
-  T.unit_slot = (int32_t*)(w + L.unit_slot);
-  float* partials = (float*)(w + L.partials);
+  const UnitTable T = unit_view(L, order, model->geom.unit_pairs, ws);
+  float* partials = (float*)((char*)ws + L.partials);
   const int64_t n_tiles = (int64_t)q.tiles_x * q.tiles_y;
   const unsigned gp = (unsigned)ceil_div(kXcds * L.nj, 256);
   hipLaunchKernelGGL(k_unit_count, dim3(gp), dim3(256), 0, s, q, T, offsets, n_tiles);

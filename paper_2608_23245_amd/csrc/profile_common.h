@@ -359,6 +359,103 @@ __device__ __forceinline__ void scan_window(const ProfParams& q, const float* __
   }
 }
 
+// ---------------------------------------------------------------- work units of the balanced launches
+// The launched tiles' lists cut into units of at most U pairs (see fdtbx_profile_balanced).
+// Queue-major position of slot b: (b % 8) nj + b / 8, nj = ceil(n_slots / 8).  qscan holds the
+// units per position, then (after k_scan_inplace) the first unit of each position; queue x
+// spans the units qscan[x nj] .. qscan[(x + 1) nj] (the total for the last queue).
+struct UnitTable {
+  const int32_t* order;  // tile of each slot, or null: the plain per-tile grid (tile_of_block)
+  int64_t n_slots, nj;
+  int64_t max_units;     // capacity of unit_slot and of the partial sums
+  int64_t fixed_U;       // pairs per unit, or 0: chosen from the pair count (default_unit_pairs)
+  int64_t* qscan;        // [8 nj]
+  int64_t* meta;         // [0]: total units, [1]: pairs per unit
+  int32_t* ctr;          // [8] queue counters
+  int32_t* unit_slot;    // [max_units] slot of each unit
+};
+
+__host__ __device__ inline int64_t queue_pos(int64_t b, int64_t nj) { return (b % kXcds) * nj + b / kXcds; }
+
+__device__ inline int slot_tile(const ProfParams& q, const UnitTable& T, int64_t b) {
+  if (b >= T.n_slots) return -1;
+  return T.order ? T.order[b] : tile_of_block(q, (int)b);
+}
+
+// Workspace of the balanced launch: the unit tables and the partial sums.
+struct UnitLayout {
+  int64_t n_slots, nj, max_units;
+  size_t qscan, meta, ctr, unit_slot, partials, total;
+};
+
+inline UnitLayout unit_layout(const ProfParams& q, bool has_order, int64_t pair_cap, int64_t fixed_U) {
+  UnitLayout L;
+  L.n_slots = has_order ? order_grid(q.lcols, q.lrows) : tile_grid(q);
+  L.nj = ceil_div(L.n_slots, kXcds);
+  // sum over tiles of ceil(len / U) <= pair_cap / U + n_slots, and U >= 32 with U >= n_pairs / 2^19
+  // when it is the library's choice
+  const int64_t by_cap = ceil_div(pair_cap, fixed_U > 0 ? fixed_U : 32);
+  L.max_units = (fixed_U > 0 ? by_cap : (by_cap < kUnitTarget ? by_cap : kUnitTarget)) + L.n_slots;
+  size_t o = 0;
+  L.qscan = o;
+  o += align_up((size_t)(kXcds * L.nj) * sizeof(int64_t), 256);
+  L.meta = o;
+  o += 256;
+  L.ctr = o;
+  o += 256;
+  L.unit_slot = o;
+  o += align_up((size_t)L.max_units * sizeof(int32_t), 256);
+  L.partials = o;
+  o += align_up((size_t)L.max_units * 64 * sizeof(float), 256);
+  L.total = o;
+  return L;
+}
+
+
+// Unit u's tile and pair range [*p0, *p1), or -1 when the tables do not describe such a unit
+// (only tables that a launch over other lists left behind would fail these checks; they keep
+// every read in bounds).
+__device__ inline int unit_range(const ProfParams& q, const UnitTable& T, const int64_t* __restrict__ offsets,
+                                 int64_t u, int64_t U, int64_t* p0, int64_t* p1) {
+  const int64_t b = T.unit_slot[u];
+  if (b < 0 || b >= T.n_slots) return -1;
+  const int t = slot_tile(q, T, b);
+  if (t < 0) return -1;
+  const int64_t k = u - T.qscan[queue_pos(b, T.nj)];
+  const int64_t a = offsets[t] + k * U, e = offsets[t + 1];
+  if (k < 0 || a >= e) return -1;
+  *p0 = a;
+  *p1 = a + U < e ? a + U : e;
+  return t;
+}
+
+// Queue x's units [*qb, *qe), clamped to the first `total` units.
+__device__ inline void queue_span(const UnitTable& T, int x, int64_t total, int64_t* qb, int64_t* qe) {
+  int64_t b = T.qscan[x * T.nj];
+  int64_t e = x + 1 < kXcds ? T.qscan[(x + 1) * T.nj] : T.meta[0];
+  b = b < 0 ? 0 : (b > total ? total : b);
+  e = e < b ? b : (e > total ? total : e);
+  *qb = b;
+  *qe = e;
+}
+
+// The unit tables inside a workspace laid out by unit_layout (order and the fixed pairs per
+// unit as for the launch that built them).
+inline UnitTable unit_view(const UnitLayout& L, const int32_t* order, int64_t fixed_U, void* ws) {
+  char* w = (char*)ws;
+  UnitTable T;
+  T.order = order;
+  T.n_slots = L.n_slots;
+  T.nj = L.nj;
+  T.max_units = L.max_units;
+  T.fixed_U = fixed_U;
+  T.qscan = (int64_t*)(w + L.qscan);
+  T.meta = (int64_t*)(w + L.meta);
+  T.ctr = (int32_t*)(w + L.ctr);
+  T.unit_slot = (int32_t*)(w + L.unit_slot);
+  return T;
+}
+
 __host__ __device__ inline void prof_params(const fdtbx_model* model, ProfParams* q) {
   q->W = model->geom.width;
   q->H = model->geom.height;

@@ -174,3 +174,28 @@ def test_balanced_host_checks():
     torch.cuda.synchronize()
     assert torch.all(img == 7.0)  # nothing was launched
     assert B.unit_pairs(0) == 32 and B.unit_pairs(-1) == 0 and B.unit_pairs((1 << 19) * 100 + 1) == 101
+
+
+@pytest.mark.parametrize("name,mirror", [("skew_voigt", 0), ("hosemann", 0), ("medium_crop", 3)])
+def test_balanced_adjoint_matches_per_tile(name, mirror):
+    """fdtbx_profile_adjoint_balanced over the units of a balanced forward: every pair's sums
+    are computed as in the per-tile adjoint, so the per-reflection binary64 sums agree to the
+    rounding of their (atomic) addition order."""
+    wl = medium_crop(mirror=mirror) if name == "medium_crop" else W.small(**CASES[name])
+    model, hkl, F2, refl, nodes, pix, tile, off, idx, order = inputs(wl)
+    G = torch.as_tensor(np.random.default_rng(9).normal(size=(wl.geom.height, wl.geom.width)),
+                        dtype=torch.float32).cuda().contiguous()
+    say(f"balanced adjoint, {name}: {idx.numel()} pairs")
+    ref = B.profile_adjoint(model, refl, nodes, pix, tile, off, idx, G, order=order)
+    for u in (0, 7):
+        m = B.make_model(with_geom(wl, unit_pairs=u))
+        ws = B.balanced_workspace(m, int(idx.numel()))
+        B.profile_balanced(m, refl, nodes, pix, tile, off, idx, order=order, ws=ws)
+        got = B.profile_adjoint_balanced(m, refl, nodes, pix, tile, off, idx, G, ws, order=order)
+        torch.cuda.synchronize()
+        r, g = ref.cpu().numpy(), got.cpu().numpy()
+        scale = np.abs(r).max(axis=0)
+        assert np.all(scale > 0)
+        err = float(np.max(np.abs(g - r) / scale))
+        say(f"  {u or 'default'} pairs per unit: max difference {err:.1e} of each sum's largest")
+        assert err <= 1e-10, (u, err)
