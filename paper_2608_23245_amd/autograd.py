@@ -40,6 +40,8 @@ class PatternEngine:
         self.type = torch.as_tensor(wl.atoms.type, dtype=torch.int32).contiguous().to(device)
         self.ff = torch.as_tensor(wl.atoms.ff, dtype=torch.float32).contiguous().to(device)
         self.plan = B.PatternPlan(self.model, self.n_hkl)
+        # forward passes run on this engine; a backward needs the workspace of its own forward
+        self.generation = 0
 
     def set_globals(self, g):
         d = self.model.dis
@@ -65,6 +67,8 @@ class PatternFunction(torch.autograd.Function):
         atoms = engine.atoms(x, y, z, Bf, occ)
         F, F2 = B.structure_factors(engine.cell, atoms, engine.hkl)
         img = engine.plan.run(engine.hkl, F2)
+        engine.generation += 1
+        ctx.generation = engine.generation
         ctx.engine = engine
         ctx.atoms = atoms
         ctx.F = F
@@ -75,6 +79,12 @@ class PatternFunction(torch.autograd.Function):
     @staticmethod
     def backward(ctx, grad):
         engine = ctx.engine
+        if engine.generation != ctx.generation:
+            # the engine's workspace (records, node table, culling lists) and its model's globals
+            # now belong to a later forward: this graph's gradients cannot be formed from them
+            raise RuntimeError("PatternFunction.backward: the engine ran another forward pass after this one; "
+                               "call backward before the next forward on the same PatternEngine, or use one "
+                               "engine per pattern")
         grad = grad.detach().to(torch.float32).contiguous()
         need_atoms = any(ctx.needs_input_grad[:5])
         out, glob, _ = B.pattern_backward(engine.plan, engine.hkl, ctx.F, grad, ctx.atoms if need_atoms else None)

@@ -226,3 +226,19 @@ def test_autograd_module_chain_rule():
     check_group("size", model.size.grad.numpy(), ref["N_base"] / edges)
     check_group("g_ab", model.g.grad.numpy()[:2], ref["g"][:2])
     check_group("B_axis", model.B_axis.grad.numpy(), ref["B_axis"])
+
+
+def test_autograd_refuses_a_backward_after_a_later_forward():
+    """Two forwards on one engine: the first graph's backward would read the second forward's
+    workspace and globals, so it raises; the second graph's backward runs."""
+    wl = W.small(47, n_atoms=12, width=14, height=12, sigma_theta=2 * DEG)
+    say("autograd: backward after a later forward")
+    model = AG.FibreModel(wl)
+    first = model().sum()
+    with torch.no_grad():
+        model.sigma.mul_(1.05)
+    second = model().sum()
+    with pytest.raises(RuntimeError, match="another forward"):
+        first.backward()
+    second.backward()
+    assert model.sigma.grad is not None and torch.isfinite(model.sigma.grad).all()
