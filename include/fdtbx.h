@@ -85,6 +85,12 @@ typedef struct fdtbx_geometry {
                                  count (fdtbx_unit_pairs); the image depends on it in the last bits
                                  (the grouping of the sums), so two launches that must agree bit for
                                  bit (a folded and an unfolded one) fix it to the same value */
+  double det_tilt;            /* detector tilt, radians, |det_tilt| < pi/2: the detector plane
+                                 turned about its horizontal axis (through the beam centre) so that
+                                 its top leans toward the sample for det_tilt > 0; pixel (y, z) then
+                                 sits at X = (distance - z sin det_tilt, y, z cos det_tilt), which
+                                 must lie in front of the sample (X_x > 0) for every row; 0 is a
+                                 detector normal to the beam */
 } fdtbx_geometry;
 /* Mirror fold.  With center_x = width / 2 exactly, pixel (i, j) and its mirror (width-1-i, j)
  * have y of opposite sign and equal z, so their (R, Z) are bit-identical (R depends on y only

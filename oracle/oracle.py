@@ -315,18 +315,14 @@ def node_table(n, T, sigma_r, sigma_theta, gamma_theta):
 
 
 # --------------------------------------------------------------------------- O8
-def pixel_rz(geom):
-    """Ring coordinates (R, Z) of every pixel centre, arrays [H][W].
-    Pixel (i, j) (column, row; row 0 at the bottom) sits at y = (i + 1/2 - c_x) p,
-    z = (j + 1/2 - c_y) p on a detector normal to the beam at distance SF.  Its
-    outgoing direction X/|X|, X = (SF, y, z), gives the scattering vector
-    S = (X/|X| - x)/lambda, which lies on the Ewald sphere (Eq. laue); written
-    without cancellation as S = (-(y^2 + z^2)/(r (r + SF)), y/r, z/r)/lambda.
-    (R, Z) are the cylindrical coordinates of S about the fibre axis n (Eq.
-    cyl-average's coordinates): Z = S.n, R = |S - Z n|.  The fibre axis is z tilted
-    by geom.tilt about the lab y axis (the detector horizontal), n = (sin t, 0, cos t);
-    with m = (cos t, 0, -sin t), R = sqrt((S.m)^2 + S_y^2).  At tilt 0 this is
-    R = sqrt(S_x^2 + S_y^2), Z = S_z."""
+def pixel_S(geom):
+    """Scattering vectors (S_x, S_y, S_z), arrays [H][W], of every pixel centre (lab frame).
+    Pixel (i, j) (column, row; row 0 at the bottom) has detector coordinates
+    y = (i + 1/2 - c_x) p, z = (j + 1/2 - c_y) p.  The detector is normal to the beam at
+    distance SF, or turned by geom.det_tilt = d about its horizontal axis through the beam
+    centre, its top toward the sample: the pixel then sits at X = (SF - z sin d, y, z cos d).
+    Its outgoing direction X/|X| gives S = (X/|X| - x)/lambda, on the Ewald sphere (Eq. laue),
+    written without cancellation as S = (-(X_y^2 + X_z^2)/(r (r + X_x)), X_y/r, X_z/r)/lambda."""
     W, H = geom.width, geom.height
     i = np.arange(W, dtype=np.float64)
     j = np.arange(H, dtype=np.float64)
@@ -334,11 +330,27 @@ def pixel_rz(geom):
     z = ((j + 0.5) - geom.center_y) * geom.pixel
     y, z = np.meshgrid(y, z)          # [H][W]
     SF = geom.distance
-    r = np.sqrt((SF * SF + y * y) + z * z)
+    dt = float(getattr(geom, "det_tilt", 0.0))
+    sd, cd = math.sin(dt), math.cos(dt)
+    Xx = SF - z * sd
+    Xz = z * cd
+    r = np.sqrt((Xx * Xx + y * y) + Xz * Xz)
     lam = geom.wavelength
-    Sx = -(y * y + z * z) / ((r * (r + SF)) * lam)
+    Sx = -(y * y + Xz * Xz) / ((r * (r + Xx)) * lam)
     Sy = y / (r * lam)
-    Sz = z / (r * lam)
+    Sz = Xz / (r * lam)
+    return Sx, Sy, Sz
+
+
+def pixel_rz(geom):
+    """Ring coordinates (R, Z) of every pixel centre, arrays [H][W], from the pixels'
+    scattering vectors S (pixel_S: a detector normal to the beam at distance SF, or tilted).
+    (R, Z) are the cylindrical coordinates of S about the fibre axis n (Eq.
+    cyl-average's coordinates): Z = S.n, R = |S - Z n|.  The fibre axis is z tilted
+    by geom.tilt about the lab y axis (the detector horizontal), n = (sin t, 0, cos t);
+    with m = (cos t, 0, -sin t), R = sqrt((S.m)^2 + S_y^2).  At tilt 0 this is
+    R = sqrt(S_x^2 + S_y^2), Z = S_z."""
+    Sx, Sy, Sz = pixel_S(geom)
     tilt = float(getattr(geom, "tilt", 0.0))
     st, ct = math.sin(tilt), math.cos(tilt)
     Z = Sx * st + Sz * ct
@@ -664,6 +676,7 @@ def gradients(wl, P: Prepared, G, R=None, Z=None, use_skip=True):
 class _SplatParams(ctypes.Structure):
     _fields_ = [("lambda_", ctypes.c_double), ("SF", ctypes.c_double), ("pixel", ctypes.c_double),
                 ("cx", ctypes.c_double), ("cy", ctypes.c_double), ("st", ctypes.c_double), ("ct", ctypes.c_double),
+                ("sd", ctypes.c_double), ("cd", ctypes.c_double),
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32), ("n_r", ctypes.c_int32), ("n_s", ctypes.c_int32),
                 ("dr", ctypes.c_void_p), ("Ts", ctypes.c_void_p)]
 
@@ -694,8 +707,9 @@ def splat(wl, P: Prepared, n_r, n_s, count=False):
     dr = np.ascontiguousarray(dr)
     Ts = np.ascontiguousarray(Ts)
     tilt = float(getattr(g, "tilt", 0.0))
+    dt = float(getattr(g, "det_tilt", 0.0))
     sp = _SplatParams(g.wavelength, g.distance, g.pixel, g.center_x, g.center_y, math.sin(tilt), math.cos(tilt),
-                      g.width, g.height, int(n_r), int(n_s), dr.ctypes.data, Ts.ctypes.data)
+                      math.sin(dt), math.cos(dt), g.width, g.height, int(n_r), int(n_s), dr.ctypes.data, Ts.ctypes.data)
     img = np.zeros(g.width * g.height)
     n_ev = ctypes.c_int64(0)
     prob, keep = _c_problem(P, False)
@@ -710,7 +724,10 @@ def splat_project(S, geom):
     pixel's lower edge) of the two diffraction-condition rotations of fibre-frame points S,
     by the algebraic form used by the splat (see oracle_splat); both coordinates NaN where
     no rotation satisfies the condition (Eq. valid) or the diffracted ray runs away from the
-    detector (k_x <= 0, which oracle_splat skips as well)."""
+    detector plane (D = k_x cos d + k_z sin d <= 0 with d the detector tilt, which
+    oracle_splat skips as well).  The outgoing ray t k_out meets the plane (normal
+    (cos d, 0, sin d) through (SF, 0, 0)) at detector coordinates y = SF k_y cos d / D,
+    z = SF k_z / D."""
     S = np.atleast_2d(np.asarray(S, dtype=np.float64))
     tilt = float(getattr(geom, "tilt", 0.0))
     st, ct = math.sin(tilt), math.cos(tilt)
@@ -721,11 +738,15 @@ def splat_project(S, geom):
     with np.errstate(invalid="ignore"):
         sy = np.where(sy2 >= 0.0, np.sqrt(sy2), np.nan)
     kx = 1.0 / geom.wavelength + sx
-    bad = ~(sy2 >= 0.0) | ~(kx > 0.0)
+    # the detector plane, normal (cos d, 0, sin d) through (SF, 0, 0), met by t k_out
+    dt = float(getattr(geom, "det_tilt", 0.0))
+    sd, cd = math.sin(dt), math.cos(dt)
+    D = kx * cd + sz * sd
+    bad = ~(sy2 >= 0.0) | ~(D > 0.0)
     out = []
     for sgn in (1.0, -1.0):
-        y = geom.distance * (sgn * sy) / kx
-        z = geom.distance * sz / kx
+        y = geom.distance * (sgn * sy) * cd / D
+        z = geom.distance * sz / D
         o = np.stack([y / geom.pixel + geom.center_x, z / geom.pixel + geom.center_y], axis=1)
         o[bad] = np.nan
         out.append(o)
@@ -962,14 +983,26 @@ def ewald_project(S, geom, beam=np.array([1.0, 0.0, 0.0]), fibre=np.array([0.0, 
     """Detector positions (column i, row j, fractional pixel units, pixel centres at
     integers) of the two diffraction-condition rotations of each S: k_out = k_in + S_phi
     (section "Analytical Solution of the Ewald Diffraction Condition") intersected with
-    the detector plane x = SF.  NaN where no rotation reaches the sphere."""
+    the detector plane.  The plane passes through the beam centre P0 = (SF, 0, 0) with
+    horizontal axis u = y and vertical axis v = (-sin d, 0, cos d), d = geom.det_tilt (its
+    top leans toward the sample for d > 0; v = z for a detector normal to the beam), so its
+    normal is u x v = (cos d, 0, sin d): the ray t k_out meets it at t = (P0.n)/(k_out.n),
+    and the point X has detector coordinates X.u and (X - P0).v.  NaN where no rotation
+    reaches the sphere."""
     S = np.atleast_2d(np.asarray(S, dtype=np.float64))
+    d = float(getattr(geom, "det_tilt", 0.0))
+    P0 = np.array([geom.distance, 0.0, 0.0])
+    u = np.array([0.0, 1.0, 0.0])
+    v = np.array([-math.sin(d), 0.0, math.cos(d)])
+    nrm = np.cross(u, v)
     out = []
     for phi in ewald_angles(S, geom.wavelength, beam, fibre):
         Sphi = rodrigues(S, phi, fibre)
         kout = beam / geom.wavelength + Sphi
-        y = geom.distance * kout[:, 1] / kout[:, 0]
-        z = geom.distance * kout[:, 2] / kout[:, 0]
+        t = (P0 @ nrm) / (kout @ nrm)
+        X = t[:, None] * kout
+        y = X @ u
+        z = (X - P0) @ v
         out.append(np.stack([y / geom.pixel + geom.center_x - 0.5, z / geom.pixel + geom.center_y - 0.5], axis=1))
     return out[0], out[1]
 

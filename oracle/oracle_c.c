@@ -358,6 +358,7 @@ void oracle_structure_factors(int64_t n_hkl, const int32_t* hkl, const double* s
  * (floor(y/p + c_x), floor(z/p + c_y)).  Binary64, no fused multiply-add. */
 typedef struct {
   double lambda, SF, pixel, cx, cy, st, ct;
+  double sd, cd; /* sine and cosine of the detector tilt */
   int32_t width, height;
   int32_t n_r, n_s;
   const double* dr;   /* [n_hkl] radial half-extent */
@@ -377,10 +378,12 @@ static void splat_pixels(const oracle_splat_params* sp, const double* S, int64_t
   if (!(sy2 >= 0.0)) return;
   double sy = sqrt(sy2);
   double kx = 1.0 / sp->lambda + sx;
-  if (!(kx > 0.0)) return;
+  /* the detector plane, normal (cos d, 0, sin d) through (SF, 0, 0), met by t k_out */
+  double D = kx * sp->cd + sz * sp->sd;
+  if (!(D > 0.0)) return;
   for (int b = 0; b < 2; ++b) {
     double ky = b == 0 ? sy : -sy;
-    double y = sp->SF * ky / kx, z = sp->SF * sz / kx;
+    double y = sp->SF * ky * sp->cd / D, z = sp->SF * sz / D;
     double fi = floor(y / sp->pixel + sp->cx), fj = floor(z / sp->pixel + sp->cy);
     if (fi >= 0.0 && fi < (double)sp->width && fj >= 0.0 && fj < (double)sp->height)
       out[b] = (int64_t)fj * sp->width + (int64_t)fi;

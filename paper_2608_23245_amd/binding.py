@@ -42,7 +42,7 @@ class Geometry(ctypes.Structure):
                 ("width", ctypes.c_int32), ("height", ctypes.c_int32),
                 ("center_x", ctypes.c_double), ("center_y", ctypes.c_double), ("tilt", ctypes.c_double),
                 ("tile_w", ctypes.c_int32), ("mirror", ctypes.c_int32), ("tile_waves", ctypes.c_int32),
-                ("unit_pairs", ctypes.c_int32)]
+                ("unit_pairs", ctypes.c_int32), ("det_tilt", ctypes.c_double)]
 
 
 class Disorder(ctypes.Structure):
@@ -237,7 +237,8 @@ def make_model(wl) -> Model:
     return Model(make_cell(wl.cell),
                  Geometry(g.wavelength, g.distance, g.pixel, g.width, g.height, g.center_x, g.center_y,
                           float(getattr(g, "tilt", 0.0)), int(getattr(g, "tile_w", 0)), int(getattr(g, "mirror", 0)),
-                          int(getattr(g, "tile_waves", 0)), int(getattr(g, "unit_pairs", 0))),
+                          int(getattr(g, "tile_waves", 0)), int(getattr(g, "unit_pairs", 0)),
+                          float(getattr(g, "det_tilt", 0.0))),
                  Disorder(d.sigma_theta, d.gamma_theta, (ctypes.c_double * 3)(*d.N_base),
                           (ctypes.c_double * 3)(*d.g), d.intensity_model, int(getattr(d, "lineshape", 0)),
                           (ctypes.c_double * 3)(*getattr(d, "B_axis", (0.0, 0.0, 0.0)))),

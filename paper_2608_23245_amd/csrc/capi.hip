@@ -47,6 +47,14 @@ int check_geometry(const fdtbx_geometry* g) {
     return fail(FDTBX_ERR_INVALID_ARGUMENT, "detector size must be in 1..65536 pixels");
   if (!isfinite(g->center_x) || !isfinite(g->center_y)) return fail(FDTBX_ERR_INVALID_ARGUMENT, "beam centre not finite");
   if (!(fabs(g->tilt) < 0.5 * M_PI)) return fail(FDTBX_ERR_GEOMETRY, "fibre tilt must be finite with |tilt| < pi/2");
+  if (!(fabs(g->det_tilt) < 0.5 * M_PI))
+    return fail(FDTBX_ERR_GEOMETRY, "detector tilt must be finite with |det_tilt| < pi/2");
+  if (g->det_tilt != 0.0) {  // the outermost rows must face the sample
+    const double sd = sin(g->det_tilt);
+    const double z0 = (0.5 - g->center_y) * g->pixel, z1 = (((double)g->height - 0.5) - g->center_y) * g->pixel;
+    if (!(g->distance - z0 * sd > 0.0) || !(g->distance - z1 * sd > 0.0))
+      return fail(FDTBX_ERR_GEOMETRY, "detector tilt puts pixel rows behind the sample");
+  }
   const int32_t tw = g->tile_w;
   if (!(tw == 0 || tw == 2 || tw == 4 || tw == 8 || tw == 16 || tw == 32))
     return fail(FDTBX_ERR_INVALID_ARGUMENT, "tile_w must be 0, 2, 4, 8, 16 or 32");
@@ -56,9 +64,10 @@ int check_geometry(const fdtbx_geometry* g) {
   const int32_t tww = tw ? tw : FDTBX_TILE;
   if ((g->mirror & 1) && !(g->center_x == 0.5 * g->width && g->width % tww == 0))
     return fail(FDTBX_ERR_INVALID_ARGUMENT, "the left-right fold needs center_x = width/2 and width a multiple of tile_w");
-  if ((g->mirror & 2) && !(g->center_y == 0.5 * g->height && g->tilt == 0.0 && g->height % (64 / tww) == 0))
+  if ((g->mirror & 2) &&
+      !(g->center_y == 0.5 * g->height && g->tilt == 0.0 && g->det_tilt == 0.0 && g->height % (64 / tww) == 0))
     return fail(FDTBX_ERR_INVALID_ARGUMENT,
-                "the up-down fold needs center_y = height/2, no fibre tilt and height a multiple of 64/tile_w");
+                "the up-down fold needs center_y = height/2, no fibre or detector tilt and height a multiple of 64/tile_w");
   return FDTBX_OK;
 }
 

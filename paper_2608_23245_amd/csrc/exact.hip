@@ -195,6 +195,7 @@ namespace fdtbx {
 struct PixParams {
   double lam, SF, p, cx, cy;
   double st, ct;  // sine and cosine of the fibre tilt
+  double sd, cd;  // sine and cosine of the detector tilt
   int32_t W, H, tiles_x, tiles_y, tlg;
 };
 
@@ -205,10 +206,12 @@ struct PixParams {
 __device__ static inline void pixel_ewald(const PixParams& q, int i, int j, double* R, double* Z) {
   double y = (((double)i + 0.5) - q.cx) * q.p;
   double z = (((double)j + 0.5) - q.cy) * q.p;
-  double r = sqrt((q.SF * q.SF + y * y) + z * z);
-  double Sx = -(y * y + z * z) / ((r * (r + q.SF)) * q.lam);
+  // the pixel's position X = (SF - z sin d, y, z cos d) on the (tilted) detector
+  double Xx = q.SF - z * q.sd, Xz = z * q.cd;
+  double r = sqrt((Xx * Xx + y * y) + Xz * Xz);
+  double Sx = -(y * y + Xz * Xz) / ((r * (r + Xx)) * q.lam);
   double Sy = y / (r * q.lam);
-  double Sz = z / (r * q.lam);
+  double Sz = Xz / (r * q.lam);
   double Sm = Sx * q.ct - Sz * q.st;
   *R = sqrt(Sm * Sm + Sy * Sy);
   *Z = Sx * q.st + Sz * q.ct;
@@ -685,6 +688,8 @@ static void pix_params(const fdtbx_geometry* g, PixParams* q) {
   q->cy = g->center_y;
   q->st = sin(g->tilt);
   q->ct = cos(g->tilt);
+  q->sd = sin(g->det_tilt);
+  q->cd = cos(g->det_tilt);
   q->W = g->width;
   q->H = g->height;
   q->tiles_x = tiles_x_of(g);

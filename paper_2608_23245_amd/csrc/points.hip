@@ -74,15 +74,17 @@ __global__ void __launch_bounds__(256) k_profile_points(PointParams p, const int
 
 struct EwaldParams {
   double lam, SF, pixel, cx, cy, st, ct;
+  double sd, cd;  // sine and cosine of the detector tilt
 };
 
 // Both diffraction-condition positions of fibre-frame point S on the detector, as
 // fractional pixel coordinates (column, row; pixel (i, j) spans [i, i + 1) x [j, j + 1)):
 // the rotated S has S_x = -lambda |S|^2/2 (on the Ewald sphere), S.n = Z_S (n the tilted
 // fibre axis) and S_y = +-sqrt(|S|^2 - S_x^2 - S_z^2); k_out = x/lambda + S meets the
-// detector plane at y = SF k_y/k_x, z = SF k_z/k_x.  The first pair is the +S_y rotation.
-// NaN where no rotation satisfies the condition (Eq. valid) or k_out misses the detector
-// half-space (k_x <= 0).
+// detector plane at y = SF k_y cos d/D, z = SF k_z/D with D = k_x cos d + k_z sin d (d the
+// detector tilt; y = SF k_y/k_x, z = SF k_z/k_x for a detector normal to the beam).  The
+// first pair is the +S_y rotation.  NaN where no rotation satisfies the condition (Eq. valid)
+// or k_out runs away from the detector plane (D <= 0).
 __global__ void __launch_bounds__(256) k_ewald_project(EwaldParams p, const double* __restrict__ S, int64_t n,
                                                        double* __restrict__ out) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -94,14 +96,15 @@ __global__ void __launch_bounds__(256) k_ewald_project(EwaldParams p, const doub
   const double sz = (s2 - sx * p.st) / p.ct;
   const double sy2 = (q - sx * sx) - sz * sz;
   const double kx = 1.0 / p.lam + sx;
-  if (!(sy2 >= 0.0) || !(kx > 0.0)) {
+  const double D = kx * p.cd + sz * p.sd;
+  if (!(sy2 >= 0.0) || !(D > 0.0)) {
     o[0] = o[1] = o[2] = o[3] = __longlong_as_double(0x7ff8000000000000ll);
     return;
   }
   const double sy = sqrt(sy2);
   for (int b = 0; b < 2; ++b) {
     const double ky = b == 0 ? sy : -sy;
-    const double y = p.SF * ky / kx, z = p.SF * sz / kx;
+    const double y = p.SF * ky * p.cd / D, z = p.SF * sz / D;
     o[2 * b + 0] = y / p.pixel + p.cx;
     o[2 * b + 1] = z / p.pixel + p.cy;
   }
@@ -152,6 +155,8 @@ extern "C" int fdtbx_ewald_project(const fdtbx_geometry* geom, const double* S, 
   p.cy = geom->center_y;
   p.st = sin(geom->tilt);
   p.ct = cos(geom->tilt);
+  p.sd = sin(geom->det_tilt);
+  p.cd = cos(geom->det_tilt);
   hipLaunchKernelGGL(k_ewald_project, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, (hipStream_t)stream, p, S, n, out);
   FDTBX_LAUNCH_CHECK("ewald projection");
   return FDTBX_OK;

@@ -14,7 +14,8 @@
 // condition (Eqs. harmonic, solutions).  Those are written algebraically: with n the
 // (tilted) fibre axis and k_in = x/lambda, the rotated S has S_x = -lambda |S|^2/2,
 // S.n = Z_S, S_y = +-sqrt(|S|^2 - S_x^2 - S_z^2); k_out = k_in + S meets the detector at
-// y = SF k_y/k_x, z = SF k_z/k_x.
+// y = SF k_y/k_x, z = SF k_z/k_x (a detector tilted by d: y = SF k_y cos d/D, z = SF k_z/D with
+// D = k_x cos d + k_z sin d).
 //
 // Mapping: one 64-lane wave per (reflection, radial sample) walks the n_s x n_s tangent
 // samples in 8x8 patches, one sample per lane.  Per patch the wave bounds the node window
@@ -39,6 +40,7 @@ struct SplatParams {
   Frame f;
   double Nb[3], g[3], m, T;
   double lam, SF, pixel, cx, cy, st, ct, delta;
+  double sd, cd;  // sine and cosine of the detector tilt
   int32_t W, H, n_r, n_s, tiles_s, lineshape;
 };
 
@@ -52,10 +54,13 @@ __device__ static inline void splat_pixels(const SplatParams& p, const double* S
   if (!(sy2 >= 0.0)) return;
   const double sy = sqrt(sy2);
   const double kx = 1.0 / p.lam + sx;
-  if (!(kx > 0.0)) return;
+  // k_out meets the detector plane (normal (cos d, 0, sin d) through (SF, 0, 0)) where
+  // t k_out . n = SF cos d; its detector coordinates are y = SF k_y cos d / D, z = SF k_z / D
+  const double D = kx * p.cd + sz * p.sd;
+  if (!(D > 0.0)) return;
   for (int b = 0; b < 2; ++b) {
     const double ky = b == 0 ? sy : -sy;
-    const double y = p.SF * ky / kx, z = p.SF * sz / kx;
+    const double y = p.SF * ky * p.cd / D, z = p.SF * sz / D;
     const double fi = floor(y / p.pixel + p.cx), fj = floor(z / p.pixel + p.cy);
     if (fi >= 0.0 && fi < (double)p.W && fj >= 0.0 && fj < (double)p.H) out[b] = (int64_t)fj * p.W + (int64_t)fi;
   }
@@ -200,6 +205,8 @@ extern "C" int fdtbx_splat(const fdtbx_model* model, const int32_t* hkl, int64_t
   p.cy = model->geom.center_y;
   p.st = sin(model->geom.tilt);
   p.ct = cos(model->geom.tilt);
+  p.sd = sin(model->geom.det_tilt);
+  p.cd = cos(model->geom.det_tilt);
   p.delta = model->quad.delta;
   p.W = model->geom.width;
   p.H = model->geom.height;

@@ -232,7 +232,8 @@ def test_mirror_fold_conditions(lib):
                             B.Geometry(1.0, 100.0, 0.1, 40, 23, 20.0, 11.5, 0.0, 16, 1)],  # width not a multiple of 16
         "up-down fold": [B.Geometry(1.0, 100.0, 0.1, 48, 23, 24.0, 11.5, 0.0, 16, 2),      # height not a multiple of 4
                          B.Geometry(1.0, 100.0, 0.1, 48, 24, 24.0, 12.0, 0.1, 16, 2),      # tilted fibre
-                         B.Geometry(1.0, 100.0, 0.1, 48, 24, 24.0, 12.3, 0.0, 16, 3)],     # beam off the middle row
+                         B.Geometry(1.0, 100.0, 0.1, 48, 24, 24.0, 12.3, 0.0, 16, 3),      # beam off the middle row
+                         B.Geometry(1.0, 100.0, 0.1, 48, 24, 24.0, 12.0, 0.0, 16, 2, 0, 0, 0.2)],  # tilted detector
         "mirror must be": [B.Geometry(1.0, 100.0, 0.1, 48, 24, 24.0, 12.0, 0.0, 16, m) for m in (-1, 4)],
     }
     for msg, geoms in bad.items():
@@ -278,3 +279,19 @@ def test_launch_waves_explicit(lib):
         g = B.Geometry(1.0, 100.0, 0.1, 48, 23, 24.0, 11.5, 0.0, 8, 1, tw)
         assert lib.fdtbx_launch_waves(ctypes.byref(g), ctypes.byref(w)) == 0 and w.value == tw
     assert lib.fdtbx_launch_waves(None, ctypes.byref(w)) == -1
+
+
+def test_detector_tilt_checks(lib):
+    """The detector tilt: |det_tilt| < pi/2, and every pixel row in front of the sample."""
+    from paper_2608_23245_amd import binding as B
+    tx, ty = ctypes.c_int32(0), ctypes.c_int32(0)
+    ok = B.Geometry(1.0, 100.0, 0.1, 48, 24, 24.0, 12.0, 0.0, 16, 1, 0, 0, 0.4)
+    assert lib.fdtbx_tile_grid(ctypes.byref(ok), ctypes.byref(tx), ctypes.byref(ty)) == 0   # left-right fold kept
+    for d in (math.pi / 2, -2.0, float("nan")):
+        g = B.Geometry(1.0, 100.0, 0.1, 48, 24, 24.0, 12.0, 0.0, 16, 0, 0, 0, d)
+        assert lib.fdtbx_tile_grid(ctypes.byref(g), ctypes.byref(tx), ctypes.byref(ty)) == -2
+        assert "detector tilt" in lib.fdtbx_error_string(-2).decode()
+    # a row 1000 pixels (100 mm) above the beam on a detector leaning 1.2 rad toward the sample
+    behind = B.Geometry(1.0, 100.0, 0.1, 48, 2200, 24.0, 100.0, 0.0, 16, 0, 0, 0, 1.2)
+    assert lib.fdtbx_tile_grid(ctypes.byref(behind), ctypes.byref(tx), ctypes.byref(ty)) == -2
+    assert "behind the sample" in lib.fdtbx_error_string(-2).decode()

@@ -68,6 +68,10 @@ SMALL = {
     "hosemann_small_n": dict(seed=31, width=18, height=18, sigma_theta=2 * DEG, gamma_theta=2 * DEG,
                              g=(0.1, 0.02, 0.0), lineshape=2, size_A=(12.0, 60.0, 50.0), B_axis=(2.0, 2.0, 8.0)),
     "no_intensity_model": dict(seed=32, width=20, height=17, g=(0.04, 0.04, 0.0), intensity_model=0),
+    "detector_tilted": dict(seed=33, width=24, height=22, center=(11.6, 10.3), det_tilt=25 * DEG, sigma_theta=2 * DEG,
+                            gamma_theta=1 * DEG),
+    "detector_and_fibre_tilted": dict(seed=34, width=20, height=26, det_tilt=-20 * DEG, tilt=15 * DEG,
+                                      g=(0.02, 0.02, 0.0)),
 }
 
 

@@ -75,10 +75,11 @@ def test_profile_points_vs_oracle(name):
     assert np.all(np.abs(got[~big]) <= 2e-3 * ref.max())
 
 
-@pytest.mark.parametrize("tilt", [0.0, 22 * DEG, -35 * DEG])
-def test_ewald_project_vs_oracle(tilt):
-    wl = W.small(95, width=64, height=48, tilt=tilt, center=(30.3, 21.7))
-    say(f"ewald projection, tilt {math.degrees(tilt):.0f} deg")
+@pytest.mark.parametrize("tilt,det_tilt", [(0.0, 0.0), (22 * DEG, 0.0), (-35 * DEG, 0.0), (0.0, 25 * DEG),
+                                           (22 * DEG, -30 * DEG)])
+def test_ewald_project_vs_oracle(tilt, det_tilt):
+    wl = W.small(95, width=64, height=48, tilt=tilt, center=(30.3, 21.7), det_tilt=det_tilt)
+    say(f"ewald projection, fibre tilt {math.degrees(tilt):.0f} deg, detector tilt {math.degrees(det_tilt):.0f} deg")
     rng = np.random.default_rng(7)
     S = rng.uniform(-0.9, 0.9, (20000, 3))
     S[:5] = 0.0

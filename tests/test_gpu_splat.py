@@ -56,6 +56,8 @@ CASES = {
     "hosemann_lineshape": (dict(seed=73, width=30, height=34, sigma_theta=2 * DEG, gamma_theta=0.5 * DEG, lineshape=2,
                                 g=(0.03, 0.02, 0.01)), 3, 20),
     "ragged_samples": (dict(seed=74, width=25, height=27, sigma_theta=4 * DEG, n_nodes=10), 5, 13),
+    "detector_tilted": (dict(seed=75, width=34, height=30, sigma_theta=2 * DEG, gamma_theta=1 * DEG, tilt=10 * DEG,
+                             det_tilt=25 * DEG, center=(16.2, 13.9)), 4, 20),
 }
 
 

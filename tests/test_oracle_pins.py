@@ -6,6 +6,7 @@ approximation, or an independent numerical integration.  A plausible slip in
 the oracle (dropped term, wrong sign or index, transposed operand) fails at
 least one of them.
 """
+import dataclasses
 import math
 import os
 
@@ -475,14 +476,17 @@ def test_pixel_points_lie_on_ewald_sphere_and_round_trip():
     np.testing.assert_allclose(S[..., 2], Z, rtol=1e-12, atol=1e-15)
 
 
-@pytest.mark.parametrize("tilt_deg", [22.0, -35.0, 60.0])
-def test_tilted_fibre_round_trip(tilt_deg):
+@pytest.mark.parametrize("tilt_deg,det_deg", [(22.0, 0.0), (-35.0, 0.0), (60.0, 0.0), (0.0, 25.0), (22.0, -18.0)])
+def test_tilted_fibre_round_trip(tilt_deg, det_deg):
     """Fibre tilted toward the beam (k_in . n != 0, so the D term of Eq. harmonic is
-    nonzero): every point of the ring of a pixel's (R, Z) about the tilted axis, rotated
-    into the diffraction condition by Eqs. harmonic/solutions and projected onto the
-    detector, lands on the pixel or on its mirror (lab y -> -y)."""
+    nonzero), detector normal to the beam or turned about its horizontal axis: every point
+    of the ring of a pixel's (R, Z) about the tilted axis, rotated into the diffraction
+    condition by Eqs. harmonic/solutions and intersected with the detector plane (a ray and
+    plane intersection in vector form), lands on the pixel or on its mirror (lab y -> -y).
+    The pixel's (R, Z) come from its position X = (SF - z sin d, y, z cos d)."""
     t = tilt_deg * DEG
     wl = W.small(4, width=29, height=23, center=(12.3, 8.6), tilt=t)
+    wl = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, det_tilt=det_deg * DEG))
     n = np.array([math.sin(t), 0.0, math.cos(t)])
     m = np.array([math.cos(t), 0.0, -math.sin(t)])
     y = np.array([0.0, 1.0, 0.0])
@@ -497,6 +501,8 @@ def test_tilted_fibre_round_trip(tilt_deg):
         got = sorted([tuple(np.round(h, 9)) for h in hits])
         want = sorted([tuple(np.round(v, 9)) for v in {(i, j), (mirror_i, j)}])
         np.testing.assert_allclose(got, want, atol=1e-7)
+    if det_deg != 0.0 or tilt_deg == 0.0:
+        return
     # tilt 0 leaves the map unchanged; a tilt mixes S_x into Z, so Z is no longer odd in z
     R0, Z0 = O.pixel_rz(W.small(4, width=29, height=23, center=(12.3, 8.6)).geom)
     assert not np.allclose(Z, Z0)
@@ -509,13 +515,15 @@ def test_tilted_fibre_round_trip(tilt_deg):
     assert np.abs(img - img[::-1, :]).max() > 1e-3 * img.max()
 
 
-@pytest.mark.parametrize("tilt_deg", [0.0, 22.0, -35.0])
-def test_splat_projection_matches_ewald_solution(tilt_deg):
+@pytest.mark.parametrize("tilt_deg,det_deg", [(0.0, 0.0), (22.0, 0.0), (-35.0, 0.0), (0.0, 30.0), (-35.0, -20.0)])
+def test_splat_projection_matches_ewald_solution(tilt_deg, det_deg):
     """The forward splat's algebraic projection (S_x = -lambda |S|^2/2, S.n = Z_S, S_y from
-    |S|) lands where Eqs. harmonic/solutions (rotation about the tilted fibre axis, then
-    k_out = k_in + S_phi onto the detector) put the point, for both rotations."""
+    |S|, then y = SF k_y cos d / D, z = SF k_z / D) lands where Eqs. harmonic/solutions
+    (rotation about the tilted fibre axis, then k_out = k_in + S_phi intersected with the
+    detector plane) put the point, for both rotations and detector tilts d."""
     t = tilt_deg * DEG
     wl = W.small(4, width=60, height=50, center=(31.3, 22.6), tilt=t)
+    wl = dataclasses.replace(wl, geom=dataclasses.replace(wl.geom, det_tilt=det_deg * DEG))
     n = np.array([math.sin(t), 0.0, math.cos(t)])
     m = np.array([math.cos(t), 0.0, -math.sin(t)])
     R, Z = O.pixel_rz(wl.geom)
@@ -1023,3 +1031,43 @@ def test_oracle_reproduces_the_numbers_the_paper_prints():
         two_theta = 2 * math.asin(geo.wavelength / (2 * wl.quad.d_min))
         want = fill * min(geo.width, geo.height) * geo.pixel / (2 * math.tan(two_theta))
         assert abs(geo.distance - want) <= 1e-12 * want
+
+
+@pytest.mark.parametrize("det_deg", [20.0, -30.0])
+def test_detector_tilt_geometry(det_deg):
+    """A detector turned by d about its horizontal axis (top toward the sample for d > 0):
+    the pixel at detector coordinates (y, z) sits at X = (SF - z sin d, y, z cos d), so its
+    scattering angle obeys tan(2 theta) = sqrt(y^2 + (z cos d)^2) / (SF - z sin d) and
+    |S| = 2 sin(theta) / lambda, with S along X/|X| - x.  The beam-centre row keeps its
+    angles; for d > 0 the rows above the beam move toward the sample (larger angles) and the
+    rows below away from it."""
+    d = det_deg * DEG
+    base = W.small(4, width=31, height=27, center=(15.5, 13.5), distance=60.0, pixel=0.8)
+    g = dataclasses.replace(base.geom, det_tilt=d)
+    Sx, Sy, Sz = O.pixel_S(g)
+    i = np.arange(g.width, dtype=np.float64)
+    j = np.arange(g.height, dtype=np.float64)
+    y, z = np.meshgrid(((i + 0.5) - g.center_x) * g.pixel, ((j + 0.5) - g.center_y) * g.pixel)
+    two_theta = np.arctan2(np.sqrt(y ** 2 + (z * math.cos(d)) ** 2), g.distance - z * math.sin(d))
+    lam = g.wavelength
+    np.testing.assert_allclose(np.sqrt(Sx ** 2 + Sy ** 2 + Sz ** 2), 2.0 * np.sin(0.5 * two_theta) / lam, rtol=1e-12,
+                               atol=1e-15)
+    # direction: S along the unit ray minus the beam, the ray built as a vector sum: the beam
+    # centre P0 = SF x plus y along u = y and z along v = x sin(-d) + z cos(d), the vertical
+    # axis turned about u by d toward the sample
+    u = np.array([0.0, 1.0, 0.0])
+    v = math.cos(d) * np.array([0.0, 0.0, 1.0]) - math.sin(d) * np.array([1.0, 0.0, 0.0])
+    X = g.distance * np.array([1.0, 0.0, 0.0]) + y[..., None] * u + z[..., None] * v
+    dirn = X / np.linalg.norm(X, axis=-1, keepdims=True) - np.array([1.0, 0.0, 0.0])
+    np.testing.assert_allclose(np.stack([Sx, Sy, Sz], -1) * lam, dirn, rtol=0, atol=1e-14)
+    # law of cosines: |X|^2 = SF^2 + y^2 + z^2 - 2 SF z sin d (the angle at P0 between the
+    # detector's vertical axis and the way back to the sample is 90 deg - d)
+    np.testing.assert_allclose(np.sum(X ** 2, -1), g.distance ** 2 + y ** 2 + z ** 2 - 2 * g.distance * z * math.sin(d),
+                               rtol=1e-13)
+    # the row through the beam centre keeps its angles; the up-down fold needs the symmetry
+    # z -> -z, which a detector tilt breaks
+    S0 = np.stack(O.pixel_S(base.geom), -1)
+    mid = np.abs(z[:, 0]) < 1e-12
+    assert mid.sum() == 0 or np.array_equal(np.stack([Sx, Sy, Sz], -1)[mid], S0[mid])
+    S1 = np.sqrt(Sx ** 2 + Sy ** 2 + Sz ** 2)
+    assert not np.allclose(S1, S1[::-1, :])

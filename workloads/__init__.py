@@ -63,6 +63,8 @@ class Geometry:
                            # (needs center_y = height/2 and tilt 0)
     tile_waves: int = 0    # waves per tile of the GPU profile launch (0: the library's choice)
     unit_pairs: int = 0    # pairs per work unit of the balanced GPU launch (0: the library's choice)
+    det_tilt: float = 0.0  # detector plane turned by this angle (rad) about its horizontal axis, its
+                           # top toward the sample (0: normal to the beam)
 
 
 @dataclasses.dataclass
@@ -265,7 +267,7 @@ def small(seed: int, n_atoms: int = 24, width: int = 24, height: int = 20,
           g=(0.0, 0.0, 0.0), n_nodes: int = 12, d_min: float = 5.0,
           size_A=(60.0, 60.0, 80.0), distance: float = 60.0, pixel: float = 0.8,
           center=None, tilt: float = 0.0, lineshape: int = 0, B_axis=(0.0, 0.0, 0.0),
-          intensity_model: int = 1) -> Workload:
+          intensity_model: int = 1, det_tilt: float = 0.0) -> Workload:
     """Tiny seeded workload for oracle pins and parity edge cases (ragged detector
     sizes, off-centre beams, skewed cells)."""
     rng = np.random.default_rng(seed)
@@ -277,7 +279,8 @@ def small(seed: int, n_atoms: int = 24, width: int = 24, height: int = 20,
     N = (size_A[0] / cell.a, size_A[1] / cell.b, size_A[2] / cell.c)
     return Workload(
         f"small seed {seed}", cell,
-        Geometry(1.0, distance, pixel, width, height, float(center[0]), float(center[1]), float(tilt)),
+        Geometry(1.0, distance, pixel, width, height, float(center[0]), float(center[1]), float(tilt),
+                 det_tilt=float(det_tilt)),
         Disorder(sigma_theta, gamma_theta, N, tuple(g), intensity_model, lineshape, tuple(B_axis)),
         Quadrature(n_nodes, extent_T(sigma_theta, gamma_theta), d_min=d_min), atoms)
 
