@@ -425,13 +425,13 @@ __global__ void __launch_bounds__(64) k_b_profile_adj(const fdtbx_batch_entry* _
     float* pt = partials ? partials + 12 * e.pair_off : nullptr;
     switch (q.lineshape) {  // uniform across the wave
       case FDTBX_LINESHAPE_GAUSSIAN:
-        adjoint_tile<FDTBX_LINESHAPE_GAUSSIAN, 1>(q, rf, nd, px, tb, rp, ix, gi, e.n_hkl, sm, pt, t, qn, qd, bq);
+        adjoint_tile<FDTBX_LINESHAPE_GAUSSIAN, 1, true>(q, rf, nd, px, tb, rp, ix, gi, e.n_hkl, sm, pt, t, qn, qd, bq);
         break;
       case FDTBX_LINESHAPE_HOSEMANN:
-        adjoint_tile<FDTBX_LINESHAPE_HOSEMANN, 1>(q, rf, nd, px, tb, rp, ix, gi, e.n_hkl, sm, pt, t, qn, qd, bq);
+        adjoint_tile<FDTBX_LINESHAPE_HOSEMANN, 1, true>(q, rf, nd, px, tb, rp, ix, gi, e.n_hkl, sm, pt, t, qn, qd, bq);
         break;
       default:
-        adjoint_tile<FDTBX_LINESHAPE_LAUE, 1>(q, rf, nd, px, tb, rp, ix, gi, e.n_hkl, sm, pt, t, qn, qd, bq);
+        adjoint_tile<FDTBX_LINESHAPE_LAUE, 1, true>(q, rf, nd, px, tb, rp, ix, gi, e.n_hkl, sm, pt, t, qn, qd, bq);
     }
   }
 }

@@ -111,7 +111,7 @@ __device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* q
 // adjoint_range walks the chunks of 64 pairs of tile t's list that start at from, from + step,
 // ... below p1, with this wave's queues qn, qd, bq; adjoint_tile gives each of its WAVES waves
 // its share of the list, and the balanced launch gives a wave one unit of the list at a time.
-template <int LS>
+template <int LS, bool PRE = false>
 __device__ __forceinline__ void adjoint_range(const ProfParams& q, const float* __restrict__ refl,
                                               const float* __restrict__ nodes, const double* __restrict__ pix,
                                               const double* __restrict__ tile, const int32_t* __restrict__ idx,
@@ -143,7 +143,7 @@ __device__ __forceinline__ void adjoint_range(const ProfParams& q, const float* 
     bool ok = false;
     if (base + lane < p1) {
       rl = idx[base + lane];
-      ok = pair_setup(q, refl + (int64_t)FDTBX_REFL_FLOATS * rl, box, &w01, &w23, lol, hil);
+      ok = pair_setup<PRE>(q, refl + (int64_t)FDTBX_REFL_FLOATS * rl, nodes, box, &w01, &w23, lol, hil);
     }
     unsigned long long todo = __ballot(ok);
     while (todo) {
@@ -234,14 +234,14 @@ __device__ __forceinline__ void adjoint_range(const ProfParams& q, const float* 
   }
 }
 
-template <int LS, int WAVES = 1>
+template <int LS, int WAVES = 1, bool PRE = false>
 __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* __restrict__ refl, const float* __restrict__ nodes,
                                              const double* __restrict__ pix, const double* __restrict__ tile,
                                              const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
                                              const float* __restrict__ grad_image, int64_t n_hkl, double* __restrict__ sums,
                                              float* __restrict__ partials, const int t, float4* qn, float2* qd, int* bq) {
   const int wv = WAVES > 1 ? (int)(threadIdx.x >> 6) : 0;
-  adjoint_range<LS>(q, refl, nodes, pix, tile, idx, grad_image, n_hkl, sums, partials, t, offsets[t] + 64 * wv,
+  adjoint_range<LS, PRE>(q, refl, nodes, pix, tile, idx, grad_image, n_hkl, sums, partials, t, offsets[t] + 64 * wv,
                     offsets[t + 1], 64 * WAVES, qn + 128 * wv, qd + 128 * wv, bq + 64 * wv);
 }
 

@@ -96,13 +96,13 @@ __global__ void __launch_bounds__(64) k_b_profile(const fdtbx_batch_entry* __res
     float* im = image + e.pix_off;
     switch (q.lineshape) {  // uniform across the wave
       case FDTBX_LINESHAPE_GAUSSIAN:
-        profile_tile<false, FDTBX_LINESHAPE_GAUSSIAN, 1>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
+        profile_tile<false, FDTBX_LINESHAPE_GAUSSIAN, 1, true>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
         break;
       case FDTBX_LINESHAPE_HOSEMANN:
-        profile_tile<false, FDTBX_LINESHAPE_HOSEMANN, 1>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
+        profile_tile<false, FDTBX_LINESHAPE_HOSEMANN, 1, true>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
         break;
       default:
-        profile_tile<false, FDTBX_LINESHAPE_LAUE, 1>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
+        profile_tile<false, FDTBX_LINESHAPE_LAUE, 1, true>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
     }
   }
 }

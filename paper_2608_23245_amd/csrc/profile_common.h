@@ -187,13 +187,25 @@ __device__ static inline bool node_window_ranges(const ProfParams& q, float r0, 
 // tile's (R, Z) box have p.v = R (e_perp.v) + Z v_z, extreme at the box corners), and the
 // tile's alpha box, the ranges of
 // alpha_i over the tile's (R, Z) box (linear in R, Z: extremes at the corners) widened by the
-// support half-width and the margin.  Returns false if the window is empty.
+// support half-width and the margin.  With PRE, a window of at most kPreBlocks node blocks is then
+// narrowed to the blocks that can hold a queued node: each block record bounds the offsets
+// kappa of its nodes (the block test of scan_window), and every node whose kappa lies in the
+// alpha box lies in a passing block, so the nodes the scan queues are the same, in the same
+// relative order, and a pair whose blocks all fail has none.  Returns false if the window is
+// empty.
 struct TileBox {
   double Rlo, Rhi, Zlo, Zhi;
 };
 
-__device__ static inline bool pair_setup(const ProfParams& q, const float* __restrict__ rec, const TileBox& b, int* w01,
-                                         int* w23, float* lo, float* hi) {
+constexpr int kPreBlocks = 16;
+
+// PRE: narrow the window by its node blocks (the batched launches, whose pairs carry few
+// evaluations and often queue none: there it saves a tenth of the time; the single-model
+// launches keep their registers for the walk).
+template <bool PRE>
+__device__ static inline bool pair_setup(const ProfParams& q, const float* __restrict__ rec,
+                                         const float* __restrict__ nodes, const TileBox& b, int* w01, int* w23,
+                                         float* lo, float* hi) {
   const float4 x0 = *(const float4*)(rec + 4);
   const float4 x3 = *(const float4*)(rec + 12);
   const float4 x4 = *(const float4*)(rec + 16);
@@ -224,6 +236,41 @@ __device__ static inline bool pair_setup(const ProfParams& q, const float* __res
   range(x7.z, x7.w, &l2, &h2);
   Window w;
   if (!node_window_ranges(q, x0.x, sl, sh, l1, h1, l2, h2, x8.x, x8.y, x8.z, &w)) return false;
+  constexpr int NB = FDTBX_NODE_BLOCK;
+  const int b1lo = w.i1lo / NB, b1hi = w.i1hi / NB, b2lo = w.i2lo / NB, b2hi = w.i2hi / NB;
+  if (PRE && (b1hi - b1lo + 1) * (b2hi - b2lo + 1) <= kPreBlocks) {
+    const float4 x1 = *(const float4*)(rec + 8);
+    const float Bv[3] = {x0.z, x0.w, x1.x}, G1[3] = {x1.y, x1.z, x1.w}, G2[3] = {x3.x, x3.y, x3.z};
+    float sl3[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) sl3[a] = 4.0e-6f * (fabsf(Bv[a]) + fabsf(G1[a]) + fabsf(G2[a]));
+    const float* blocks = nodes + (int64_t)FDTBX_NODE_FLOATS * q.n * q.n;
+    const int nbs = (q.n + NB - 1) / NB;
+    int k1lo = b1hi + 1, k1hi = b1lo - 1, k2lo = b2hi + 1, k2hi = b2lo - 1;
+    for (int b2i = b2lo; b2i <= b2hi; ++b2i)
+      for (int b1i = b1lo; b1i <= b1hi; ++b1i) {
+        const float* br = blocks + (int64_t)FDTBX_NODE_FLOATS * (b2i * nbs + b1i);
+        const float4 cm = *(const float4*)br, rr = *(const float4*)(br + 4);
+        bool keep = true;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+          const float ec = fmaf(cm.x, Bv[a], fmaf(cm.y, G1[a], cm.z * G2[a]));
+          const float er = fmaf(sl3[a], cm.w, fmaf(rr.x, fabsf(Bv[a]), fmaf(rr.y, fabsf(G1[a]), rr.z * fabsf(G2[a]))));
+          keep = keep && ec - er <= hi[a] && ec + er >= lo[a];
+        }
+        if (keep) {
+          k1lo = min(k1lo, b1i);
+          k1hi = max(k1hi, b1i);
+          k2lo = min(k2lo, b2i);
+          k2hi = max(k2hi, b2i);
+        }
+      }
+    if (k1hi < k1lo) return false;  // no block can hold a queued node
+    w.i1lo = max(w.i1lo, k1lo * NB);
+    w.i1hi = min(w.i1hi, k1hi * NB + NB - 1);
+    w.i2lo = max(w.i2lo, k2lo * NB);
+    w.i2hi = min(w.i2hi, k2hi * NB + NB - 1);
+  }
   *w01 = w.i1lo | (w.i1hi << 16);
   *w23 = w.i2lo | (w.i2hi << 16);
   return true;

@@ -112,7 +112,7 @@ __device__ __forceinline__ void walk_queue(const float4* qn, int cnt, const floa
 // node window and alpha box; the wave then works through the pairs with a non-empty window,
 // reading their set-up from that lane).  R, Z: the lane's pixel; box: the tile's (R, Z) box.
 // qn, bq: this wave's LDS queue (128 float4) and scratch (64 ints).
-template <bool COUNT, int LS>
+template <bool COUNT, int LS, bool PRE = false>
 __device__ __forceinline__ float pairs_sum(const ProfParams& q, const float* __restrict__ refl,
                                            const float* __restrict__ nodes, const int32_t* __restrict__ idx,
                                            const TileBox& box, double R, double Z, int64_t from, int64_t p1,
@@ -126,7 +126,7 @@ __device__ __forceinline__ float pairs_sum(const ProfParams& q, const float* __r
     bool ok = false;
     if (base + lane < p1) {
       rl = idx[base + lane];
-      ok = pair_setup(q, refl + (int64_t)FDTBX_REFL_FLOATS * rl, box, &w01, &w23, lol, hil);
+      ok = pair_setup<PRE>(q, refl + (int64_t)FDTBX_REFL_FLOATS * rl, nodes, box, &w01, &w23, lol, hil);
     }
     unsigned long long todo = __ballot(ok);
     while (todo) {
@@ -205,7 +205,7 @@ __device__ __forceinline__ TilePixel tile_pixel(const ProfParams& q, const doubl
 // WAVES waves share a tile: wave w takes the chunks w, w + WAVES, ... of 64 pairs of the
 // tile's list (its own LDS queue: qn + 128 w, bq + 64 w), and wave 0 adds the others' pixel
 // sums (xacc, 64 floats per extra wave) in wave order before it writes the tile.
-template <bool COUNT, int LS, int WAVES = 1>
+template <bool COUNT, int LS, int WAVES = 1, bool PRE = false>
 __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* __restrict__ refl,
                                              const float* __restrict__ nodes, const double* __restrict__ pix,
                                              const double* __restrict__ tile, const int64_t* __restrict__ offsets,
@@ -218,7 +218,7 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
   bq += 64 * wv;
   const TilePixel px = tile_pixel(q, pix, tile, t, lane);
   unsigned long long cnt = 0;
-  float acc = pairs_sum<COUNT, LS>(q, refl, nodes, idx, px.box, px.R, px.Z, offsets[t] + 64 * wv, offsets[t + 1],
+  float acc = pairs_sum<COUNT, LS, PRE>(q, refl, nodes, idx, px.box, px.R, px.Z, offsets[t] + 64 * wv, offsets[t + 1],
                                    64 * WAVES, qn, bq, cnt);
   if (COUNT) {
     for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
