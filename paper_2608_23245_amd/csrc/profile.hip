@@ -33,14 +33,15 @@ namespace fdtbx {
 // COUNT: counting pass (support test only, the same for every lineshape); LS: lineshape;
 // WAVES: waves per tile (each its share of the tile's list).
 template <bool COUNT, int LS, int WAVES>
-__global__ void __launch_bounds__(64 * WAVES) k_profile(ProfParams q, const float* __restrict__ refl,
+__global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu(7))) k_profile(ProfParams q, const float* __restrict__ refl,
                                                         const float* __restrict__ nodes, const double* __restrict__ pix,
                                                         const double* __restrict__ tile, const int64_t* __restrict__ offsets,
                                                         const int32_t* __restrict__ idx, float* __restrict__ image,
                                                         unsigned long long* __restrict__ counts,
                                                         const int32_t* __restrict__ order) {
-  // per wave, the queue of window nodes that can be inside the support of some pixel of the tile
-  __shared__ float4 qn[128 * WAVES];
+  // per wave, the queues of window nodes that can be inside the support of some pixel of the
+  // tile (candidates, then those inside the support of every pixel)
+  __shared__ float4 qn[256 * WAVES];
   __shared__ int bq[64 * WAVES];
   __shared__ float xacc[WAVES > 1 ? 64 * (WAVES - 1) : 1];
   const int t = order ? order[blockIdx.x] : tile_of_block(q, blockIdx.x);
@@ -96,13 +97,13 @@ __global__ void __launch_bounds__(64) k_b_profile(const fdtbx_batch_entry* __res
     float* im = image + e.pix_off;
     switch (q.lineshape) {  // uniform across the wave
       case FDTBX_LINESHAPE_GAUSSIAN:
-        profile_tile<false, FDTBX_LINESHAPE_GAUSSIAN, 1, true>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
+        profile_tile<false, FDTBX_LINESHAPE_GAUSSIAN, 1, true, false>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
         break;
       case FDTBX_LINESHAPE_HOSEMANN:
-        profile_tile<false, FDTBX_LINESHAPE_HOSEMANN, 1, true>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
+        profile_tile<false, FDTBX_LINESHAPE_HOSEMANN, 1, true, false>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
         break;
       default:
-        profile_tile<false, FDTBX_LINESHAPE_LAUE, 1, true>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
+        profile_tile<false, FDTBX_LINESHAPE_LAUE, 1, true, false>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
     }
   }
 }
@@ -146,12 +147,12 @@ __global__ void __launch_bounds__(256) k_unit_fill(ProfParams q, UnitTable T, co
 // Persistent: every wave takes units from its XCD's queue, then from the following queues,
 // until all are empty (the exit every wave reaches: each queue's counter only grows).
 template <int LS>
-__global__ void __launch_bounds__(256) k_profile_units(ProfParams q, const float* __restrict__ refl,
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k_profile_units(ProfParams q, const float* __restrict__ refl,
                                                        const float* __restrict__ nodes, const double* __restrict__ pix,
                                                        const double* __restrict__ tile, const int64_t* __restrict__ offsets,
                                                        const int32_t* __restrict__ idx, UnitTable T,
                                                        float* __restrict__ partials) {
-  __shared__ float4 qn[128 * 4];
+  __shared__ float4 qn[256 * 4];
   __shared__ int bq[64 * 4];
   const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int64_t U = T.meta[1];
@@ -172,7 +173,7 @@ __global__ void __launch_bounds__(256) k_profile_units(ProfParams q, const float
       const TilePixel px = tile_pixel(q, pix, tile, t, lane);
       unsigned long long cnt = 0;
       partials[u * 64 + lane] = pairs_sum<false, LS>(q, refl, nodes, idx, px.box, px.R, px.Z, p0, p1, 64,
-                                                     qn + 128 * wv, bq + 64 * wv, cnt);
+                                                     qn + 256 * wv, bq + 64 * wv, cnt);
     }
   }
 }

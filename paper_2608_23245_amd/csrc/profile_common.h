@@ -191,8 +191,14 @@ __device__ static inline bool node_window_ranges(const ProfParams& q, float r0, 
 // narrowed to the blocks that can hold a queued node: each block record bounds the offsets
 // kappa of its nodes (the block test of scan_window), and every node whose kappa lies in the
 // alpha box lies in a passing block, so the nodes the scan queues are the same, in the same
-// relative order, and a pair whose blocks all fail has none.  Returns false if the window is
-// empty.
+// relative order, and a pair whose blocks all fail has none.  With fl, fh (the forward's
+// split walk), also the full box of the pair: the offsets kappa that lie inside the support
+// of every pixel of the tile, [max alpha - half_m + m, min alpha + half_m - m] per axis.  Its
+// margin m = margin + 2^-19 sum_v max |coef_v d_v| exceeds the float32 rounding of alpha at
+// any pixel of the box (a few units in the last place of the two products, whose magnitudes
+// the sum bounds), of the tags (at most 2^-18) and of y = alpha - kappa (a unit in the last
+// place of half_m), so a node in the full box passes the support test at every pixel of the
+// detector that the tile holds.  Returns false if the window is empty.
 struct TileBox {
   double Rlo, Rhi, Zlo, Zhi;
 };
@@ -205,7 +211,7 @@ constexpr int kPreBlocks = 16;
 template <bool PRE>
 __device__ static inline bool pair_setup(const ProfParams& q, const float* __restrict__ rec,
                                          const float* __restrict__ nodes, const TileBox& b, int* w01, int* w23,
-                                         float* lo, float* hi) {
+                                         float* lo, float* hi, float* fl = nullptr, float* fh = nullptr) {
   const float4 x0 = *(const float4*)(rec + 4);
   const float4 x3 = *(const float4*)(rec + 12);
   const float4 x4 = *(const float4*)(rec + 16);
@@ -221,8 +227,15 @@ __device__ static inline bool pair_setup(const ProfParams& q, const float* __res
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const float r1 = tr[a] * dRl, r2 = tr[a] * dRh, z1 = tz[a] * dZl, z2 = tz[a] * dZh;
-    lo[a] = fminf(r1, r2) + fminf(z1, z2) - q.half_m - q.margin;
-    hi[a] = fmaxf(r1, r2) + fmaxf(z1, z2) + q.half_m + q.margin;
+    const float amin = fminf(r1, r2) + fminf(z1, z2), amax = fmaxf(r1, r2) + fmaxf(z1, z2);
+    lo[a] = amin - q.half_m - q.margin;
+    hi[a] = amax + q.half_m + q.margin;
+    if (fl) {
+      const float mag = fmaxf(fabsf(r1), fabsf(r2)) + fmaxf(fabsf(z1), fabsf(z2));
+      const float m = fmaf(mag, 0x1p-19f, q.margin);
+      fl[a] = amax - q.half_m + m;
+      fh[a] = amin + q.half_m - m;
+    }
   }
   const float Rlo = (float)b.Rlo, Rhi = (float)b.Rhi, Zlo = (float)b.Zlo, Zhi = (float)b.Zhi;
   auto range = [&](float cR, float cZ, float* l, float* h) {

@@ -52,17 +52,17 @@ __device__ __forceinline__ float4 tag_kappa4(float4 e) {
 
 // Per-lane evaluation of one queued node: returns omega times the lineshape's profile
 // product (without its per-reflection constant) if the node is inside this pixel's support,
-// else 0 (and counts it in COUNT mode).
+// else 0 (and counts it in COUNT mode).  TEST = false: the node lies in the pair's full box
+// (inside the support of every pixel of the tile), so the support test is left out.
 //   Laue:     (prod_i sin(2 pi y_i)/y_i)^2      (y_i = N_i u_i/2; al from tag_alpha and
 //                                                nd from tag_kappa, so no y_i is 0)
 //   Gaussian: exp(-4 pi sum_i y_i^2)            (y_i = N_i u_i/2)
 //   Hosemann: 1/prod_i (c0_i - c1_i cos(2 pi y_i))   (y_i = u_i)
-template <bool COUNT, int LS>
+template <bool COUNT, int LS, bool TEST = true>
 __device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1, float al2, float half_m,
                                           const HoseK& hk, float& accr, unsigned long long& cnt) {
   float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
-  float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
-  if (mx <= half_m) {
+  if (!TEST || fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc)) <= half_m) {
     if (COUNT) {
       ++cnt;
     } else if (LS == FDTBX_LINESHAPE_GAUSSIAN) {
@@ -87,13 +87,13 @@ __device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1,
   }
 }
 
-// The walk of one wave's node queue (qn: 128 entries of LDS; see profile_tile below).
+// The walk of one wave's node queue (128 entries of LDS; see pairs_sum below).
 // Every lane walks the first cnt queue entries; the read of entry jj + 1 is issued before
 // entry jj is evaluated (the buffer holds 128 entries, cnt <= 64, so it stays in bounds).
 // The queue is addressed from threadIdx.y (always 0: the launches are one-dimensional), which
 // keeps its address in a vector register; the unrolled reads then use instruction offsets
 // instead of moving a scalar loop counter into a vector register for every entry.
-template <bool COUNT, int LS>
+template <bool COUNT, int LS, bool TEST = true>
 __device__ __forceinline__ void walk_queue(const float4* qn, int cnt, const float* al, float half_m,
                                            const HoseK& hk, float& accr, unsigned long long& cnt_eval) {
   qn += threadIdx.y;
@@ -102,31 +102,66 @@ __device__ __forceinline__ void walk_queue(const float4* qn, int cnt, const floa
   for (int jj = 0; jj < cnt; ++jj) {
     const float4 cur = nxt;
     nxt = qn[jj + 1];
-    eval_node<COUNT, LS>(cur, al[0], al[1], al[2], half_m, hk, part, cnt_eval);
+    eval_node<COUNT, LS, TEST>(cur, al[0], al[1], al[2], half_m, hk, part, cnt_eval);
+    // without the support test the unrolled entries form one block, which the scheduler would
+    // interleave at the cost of registers (and occupancy); keep each entry's arithmetic together
+    if (!TEST) __builtin_amdgcn_sched_barrier(0);
   }
   accr += part;
+}
+
+// Appends the lanes' candidates (keep) to a queue of len entries at qn (len is uniform).
+template <int LS>
+__device__ __forceinline__ void queue_append(float4* qn, int& len, bool keep, float4 e) {
+  const unsigned long long b = __ballot(keep);
+  if (keep) {
+    const int pos = len + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
+    qn[pos] = LS == FDTBX_LINESHAPE_LAUE ? tag_kappa4(e) : e;
+  }
+  len += __popcll(b);
+}
+
+// Walks the first 64 entries of a queue by all lanes once it holds that many (the rest move
+// to the front).
+template <bool COUNT, int LS, bool TEST>
+__device__ __forceinline__ void queue_flush(float4* qn, int& len, const float* al, float half_m, const HoseK& hk,
+                                            float& accr, unsigned long long& cnt) {
+  if (len >= 64) {
+    const int lane = threadIdx.x & 63;
+    walk_queue<COUNT, LS, TEST>(qn, 64, al, half_m, hk, accr, cnt);
+    len -= 64;
+    wave_sync();
+    if (lane < len) qn[lane] = qn[64 + lane];
+    wave_sync();
+  }
 }
 
 // A lane's pixel sum over pairs of one tile's list: the chunks of 64 pairs that start at
 // from, from + step, from + 2 step, ... below p1 (each lane sets up one pair of a chunk: its
 // node window and alpha box; the wave then works through the pairs with a non-empty window,
 // reading their set-up from that lane).  R, Z: the lane's pixel; box: the tile's (R, Z) box.
-// qn, bq: this wave's LDS queue (128 float4) and scratch (64 ints).
-template <bool COUNT, int LS, bool PRE = false>
+// qn, bq: this wave's LDS queues (256 float4) and scratch (64 ints).  The pair's candidate
+// nodes go to the queue at qn; with SPLIT, those in the pair's full box (inside the support
+// of every pixel of the tile) go to a second queue at qn + 128 instead, whose walk leaves out
+// the support test.  Each queue is walked 64 entries at a time as it fills, and both at the
+// end of the pair, the full queue first; the pixel sum adds each walk's block sum in that order.
+template <bool COUNT, int LS, bool PRE = false, bool SPLIT = !COUNT>
 __device__ __forceinline__ float pairs_sum(const ProfParams& q, const float* __restrict__ refl,
                                            const float* __restrict__ nodes, const int32_t* __restrict__ idx,
                                            const TileBox& box, double R, double Z, int64_t from, int64_t p1,
                                            int64_t step, float4* qn, int* bq, unsigned long long& cnt) {
+  static_assert(!(SPLIT && COUNT), "the counting pass tests every node");
   const int lane = threadIdx.x & 63;
   float acc = 0.0f;
   for (int64_t base = from; base < p1; base += step) {
     int32_t rl = 0;
     int w01 = 0, w23 = 0;
-    float lol[3] = {0.f, 0.f, 0.f}, hil[3] = {0.f, 0.f, 0.f};
+    float lol[3] = {0.f, 0.f, 0.f}, hil[3] = {0.f, 0.f, 0.f}, fll[3] = {0.f, 0.f, 0.f}, fhl[3] = {0.f, 0.f, 0.f};
     bool ok = false;
     if (base + lane < p1) {
       rl = idx[base + lane];
-      ok = pair_setup<PRE>(q, refl + (int64_t)FDTBX_REFL_FLOATS * rl, nodes, box, &w01, &w23, lol, hil);
+      ok = pair_setup<PRE>(q, refl + (int64_t)FDTBX_REFL_FLOATS * rl, nodes, box, &w01, &w23, lol, hil,
+                           SPLIT ? fll : nullptr, SPLIT ? fhl : nullptr);
     }
     unsigned long long todo = __ballot(ok);
     while (todo) {
@@ -135,7 +170,7 @@ __device__ __forceinline__ float pairs_sum(const ProfParams& q, const float* __r
       const int32_t r = lane_int(rl, src);
       const int a01 = lane_int(w01, src), a23 = lane_int(w23, src);
       const Window w = {a01 & 0xffff, a01 >> 16, a23 & 0xffff, a23 >> 16};
-      float al[3], lo[3], hi[3], Bv[3], G1[3], G2[3];
+      float al[3], lo[3], hi[3], fl[3], fh[3], Bv[3], G1[3], G2[3];
       PairRec f;
       load_pair(refl + (int64_t)FDTBX_REFL_FLOATS * r, f);
       const float dR = (float)(R - f.at_f64(RS_RD)), dZ = (float)(Z - f.at_f64(RS_ZD));
@@ -145,6 +180,8 @@ __device__ __forceinline__ float pairs_sum(const ProfParams& q, const float* __r
         if (LS == FDTBX_LINESHAPE_LAUE) al[a] = tag_alpha(al[a]);
         lo[a] = lane_float(lol[a], src);
         hi[a] = lane_float(hil[a], src);
+        fl[a] = SPLIT ? lane_float(fll[a], src) : 0.0f;
+        fh[a] = SPLIT ? lane_float(fhl[a], src) : 0.0f;
         Bv[a] = f.at(RS_B + a);
         G1[a] = f.at(RS_G1 + a);
         G2[a] = f.at(RS_G2 + a);
@@ -152,24 +189,23 @@ __device__ __forceinline__ float pairs_sum(const ProfParams& q, const float* __r
       HoseK hk = {};
       if (LS == FDTBX_LINESHAPE_HOSEMANN && !COUNT) hose_constants(refl + (int64_t)FDTBX_REFL_FLOATS * r, hk);
       float accr = 0.0f;
-      int qlen = 0;  // uniform
-      // candidates go to the LDS queue; every 64 queued nodes are walked by all lanes
+      int qlen = 0, flen = 0;  // uniform
+      // candidates go to the LDS queues; every 64 queued nodes are walked by all lanes
       scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int, float4 e) {
-        const unsigned long long b = __ballot(keep);
-        if (keep) {
-          const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
-          qn[pos] = LS == FDTBX_LINESHAPE_LAUE ? tag_kappa4(e) : e;
-        }
-        qlen += __popcll(b);
-        wave_sync();
-        if (qlen >= 64) {
-          walk_queue<COUNT, LS>(qn, 64, al, q.half_m, hk, accr, cnt);
-          qlen -= 64;
+        if (SPLIT) {
+          const bool full = keep && e.x >= fl[0] && e.x <= fh[0] && e.y >= fl[1] && e.y <= fh[1] && e.z >= fl[2] &&
+                            e.z <= fh[2];
+          queue_append<LS>(qn + 128, flen, full, e);
+          queue_append<LS>(qn, qlen, keep && !full, e);
           wave_sync();
-          if (lane < qlen) qn[lane] = qn[64 + lane];
+          queue_flush<COUNT, LS, false>(qn + 128, flen, al, q.half_m, hk, accr, cnt);
+        } else {
+          queue_append<LS>(qn, qlen, keep, e);
           wave_sync();
         }
+        queue_flush<COUNT, LS, true>(qn, qlen, al, q.half_m, hk, accr, cnt);
       });
+      if (SPLIT) walk_queue<COUNT, LS, false>(qn + 128, flen, al, q.half_m, hk, accr, cnt);
       walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, hk, accr, cnt);
       wave_sync();
       if (!COUNT) acc = fmaf(f.at(RS_WK), accr, acc);
@@ -203,9 +239,10 @@ __device__ __forceinline__ TilePixel tile_pixel(const ProfParams& q, const doubl
 }
 
 // WAVES waves share a tile: wave w takes the chunks w, w + WAVES, ... of 64 pairs of the
-// tile's list (its own LDS queue: qn + 128 w, bq + 64 w), and wave 0 adds the others' pixel
-// sums (xacc, 64 floats per extra wave) in wave order before it writes the tile.
-template <bool COUNT, int LS, int WAVES = 1, bool PRE = false>
+// tile's list (its own LDS queues: qn + 256 w, bq + 64 w; 128 float4 per wave suffice
+// without SPLIT), and wave 0 adds the others' pixel sums (xacc, 64 floats per extra wave) in
+// wave order before it writes the tile.
+template <bool COUNT, int LS, int WAVES = 1, bool PRE = false, bool SPLIT = !COUNT>
 __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* __restrict__ refl,
                                              const float* __restrict__ nodes, const double* __restrict__ pix,
                                              const double* __restrict__ tile, const int64_t* __restrict__ offsets,
@@ -214,12 +251,12 @@ __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* _
                                              float* xacc = nullptr) {
   const int lane = threadIdx.x & 63;
   const int wv = WAVES > 1 ? (int)(threadIdx.x >> 6) : 0;
-  qn += 128 * wv;
+  qn += 256 * wv;
   bq += 64 * wv;
   const TilePixel px = tile_pixel(q, pix, tile, t, lane);
   unsigned long long cnt = 0;
-  float acc = pairs_sum<COUNT, LS, PRE>(q, refl, nodes, idx, px.box, px.R, px.Z, offsets[t] + 64 * wv, offsets[t + 1],
-                                   64 * WAVES, qn, bq, cnt);
+  float acc = pairs_sum<COUNT, LS, PRE, SPLIT>(q, refl, nodes, idx, px.box, px.R, px.Z, offsets[t] + 64 * wv,
+                                              offsets[t + 1], 64 * WAVES, qn, bq, cnt);
   if (COUNT) {
     for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
     if (lane == 0 && cnt) atomicAdd(counts, cnt);
