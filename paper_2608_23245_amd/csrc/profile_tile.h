@@ -140,11 +140,12 @@ __device__ __forceinline__ void queue_flush(float4* qn, int& len, const float* a
 // from, from + step, from + 2 step, ... below p1 (each lane sets up one pair of a chunk: its
 // node window and alpha box; the wave then works through the pairs with a non-empty window,
 // reading their set-up from that lane).  R, Z: the lane's pixel; box: the tile's (R, Z) box.
-// qn, bq: this wave's LDS queues (256 float4) and scratch (64 ints).  The pair's candidate
-// nodes go to the queue at qn; with SPLIT, those in the pair's full box (inside the support
-// of every pixel of the tile) go to a second queue at qn + 128 instead, whose walk leaves out
-// the support test.  Each queue is walked 64 entries at a time as it fills, and both at the
-// end of the pair, the full queue first; the pixel sum adds each walk's block sum in that order.
+// qn, bq: this wave's LDS queues (256 float4; 128 without SPLIT) and scratch (64 ints).  The
+// pair's candidate nodes go to the queue at qn; with SPLIT, those in the pair's full box
+// (inside the support of every pixel of the tile) go to a second queue at qn + 128 instead,
+// whose walk leaves out the support test.  Each queue is walked 64 entries at a time as it
+// fills, and both at the end of the pair, the full queue first; the pixel sum adds each walk's
+// block sum in that order.
 template <bool COUNT, int LS, bool PRE = false, bool SPLIT = !COUNT>
 __device__ __forceinline__ float pairs_sum(const ProfParams& q, const float* __restrict__ refl,
                                            const float* __restrict__ nodes, const int32_t* __restrict__ idx,
