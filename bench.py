@@ -104,6 +104,8 @@ def parse():
                     help="run the batched forward alone, at --batch-tile-w, --steps times (profiler runs)")
     ap.add_argument("--batch-tile-w", type=int, default=16, choices=(4, 8, 16),
                     help="tile width of every model of the batch with --only-batch")
+    ap.add_argument("--batch-per-tile", action="store_true",
+                    help="with --only-batch, walk the per-tile culling lists instead of the stacked tiles")
     ap.add_argument("--batch-models", type=int, default=256)
     ap.add_argument("--batch-steps", type=int, default=2)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
@@ -634,7 +636,7 @@ def bench_batched_forward(args):
     wls = [fold(dataclasses.replace(w, geom=dataclasses.replace(w.geom, tile_w=tw)))
            for w in W.config4(n_models=args.batch_models)]
     t0 = time.perf_counter()
-    be = BatchEngine(wls, "cuda")
+    be = BatchEngine(wls, "cuda", stacked=not args.batch_per_tile)
     be.forward()
     torch.cuda.synchronize()
     log(f"batched forward: set-up and warm-up {time.perf_counter() - t0:.1f} s, {be.totals['pair']} pairs")
@@ -648,7 +650,7 @@ def bench_batched_forward(args):
         ms.append(e0.elapsed_time(e1))
     log(f"batched forward: {', '.join(f'{m:.1f}' for m in ms)} ms")
     return {"n_models": len(wls), "tile": f"{tw}x{64 // tw}", "culled_pairs": int(be.totals["pair"]),
-            "forward_ms": ms}
+            "stacked_pairs": int(be.totals.get("stacked_pair", 0)) if be.stacked else None, "forward_ms": ms}
 
 
 def bench_batched(args):

@@ -309,6 +309,26 @@ size_t fdtbx_cull_workspace(const fdtbx_geometry* geom, int64_t n_hkl);
 int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_t n_hkl, const double* cull, int64_t* offsets,
                int32_t* idx, int64_t cap, int64_t* n_pairs, void* ws, size_t ws_bytes, void* stream);
 
+/* Stacked tiles (the batched forward, fdtbx_batch_profile_stacked): the launched tile rows
+ * taken two at a time, rows 2 sy and 2 sy + 1 forming stacked row sy (a single row last when
+ * the launched rows are odd in number), so that one wave walks two tiles with one list.  The
+ * grid of stacked tiles is tiles_x wide (fdtbx_tile_grid) and fdtbx_stacked_rows(geom) =
+ * ceil(launched rows / 2) high, stacked tile s = sy tiles_x + sx.  Its box is the union of its
+ * tiles' boxes, and its list is the culling list of fdtbx_cull for that box (the same
+ * predicate), which contains the lists of both its tiles.
+ *   fdtbx_stacked_rows   number of stacked rows (0 for an invalid geometry)
+ *   fdtbx_stacked_boxes  stile device float64 [tiles_x * stacked rows][8] output, from the
+ *                        tile boxes of fdtbx_pixel_map
+ *   fdtbx_stacked_cull   as fdtbx_cull over the stacked grid (launched stacked columns only;
+ *                        offsets [tiles_x * stacked rows + 1]), with the workspace of
+ *                        fdtbx_stacked_cull_workspace; synchronises `stream` once */
+int32_t fdtbx_stacked_rows(const fdtbx_geometry* geom);
+int fdtbx_stacked_boxes(const fdtbx_geometry* geom, const double* tile, double* stile, void* stream);
+size_t fdtbx_stacked_cull_workspace(const fdtbx_geometry* geom, int64_t n_hkl);
+int fdtbx_stacked_cull(const fdtbx_geometry* geom, const double* stile, int64_t n_hkl, const double* cull,
+                       int64_t* offsets, int32_t* idx, int64_t cap, int64_t* n_pairs, void* ws, size_t ws_bytes,
+                       void* stream);
+
 /* Launch order of the per-tile kernels (fdtbx_profile, fdtbx_profile_adjoint,
  * fdtbx_profile_cyl) for a set of culling lists: the tile each workgroup processes, -1 for
  * padding.  Workgroups are dealt to the 8 XCDs round-robin; tiles are grouped into
@@ -695,6 +715,25 @@ int fdtbx_batch_forward(const fdtbx_batch_entry* entries, int32_t n_models, cons
                         const float* occ, const int32_t* type, const float* ff, const double* pix, const double* tile,
                         const int64_t* rowptr, const int32_t* idx, float* F, float* F2, float* refl, float* nodes,
                         float* image, int64_t* counter, void* stream);
+
+/* The profile stage of fdtbx_batch_forward on stacked tiles (Eq. direct_sum at every pixel,
+ * as fdtbx_batch_forward computes it): call fdtbx_batch_forward with n_items = 0 first (its
+ * structure factors, records and node tables; no image), then this.  Each wave takes a
+ * (model, stacked tile) item, packed (model << 40) | s, and walks the stacked tile's list once
+ * for the pixels of both its tiles, so that the per-pair set-up and window scan are shared by
+ * two tiles; every launched pixel of each item's tiles is written (with the mirror folds), so
+ * the items must cover every launched stacked tile of every model.
+ *   stack_off  device int64 [n_models][3]: the model's first stacked box in stile, first row
+ *              pointer in srowptr and first list entry in sidx (row pointers relative to it)
+ *   stile, srowptr, sidx  fdtbx_stacked_boxes and fdtbx_stacked_cull of each model, concatenated
+ *   refl, nodes  as written by fdtbx_batch_forward; pix, tile as given to it
+ *   counter    device int64 [2] scratch (the work queue)
+ * The sums run in another grouping than the per-tile launch's, so the images agree with it to
+ * float32 rounding.  Does not allocate, copy to the host or synchronise. */
+int fdtbx_batch_profile_stacked(const fdtbx_batch_entry* entries, int32_t n_models, const int64_t* stack_off,
+                                const int64_t* stack_items, int64_t n_items, const float* refl, const float* nodes,
+                                const double* pix, const double* tile, const double* stile, const int64_t* srowptr,
+                                const int32_t* sidx, float* image, int64_t* counter, void* stream);
 
 /* Backward step for all models, after fdtbx_batch_forward with the same inputs:
  * grad_image (float32, laid out as the images) -> atom gradients (float32 [sum n_atoms]

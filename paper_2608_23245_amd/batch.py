@@ -11,6 +11,9 @@ the host and never synchronises, so it can be captured in a HIP graph
 
 Each model's tiles run in its own shape (its geometry's tile_w); ``autotune.tune_batch``
 picks the shape of a whole batch by timing the batched forward in each candidate shape.
+The forward walks stacked tiles (two launched tile rows per wave, one culling list for
+both, fdtbx_batch_profile_stacked) unless the engine is built with stacked=False; the
+backward walks the single tiles.
 """
 from __future__ import annotations
 
@@ -34,7 +37,7 @@ class StaleListsError(RuntimeError):
 
 
 class BatchEngine:
-    def __init__(self, workloads: List, device="cuda", deterministic: bool = False):
+    def __init__(self, workloads: List, device="cuda", deterministic: bool = False, stacked: bool = True):
         L = B.lib()
         if L.fdtbx_batch_entry_size() != ctypes.sizeof(B.BatchEntry):
             raise RuntimeError("fdtbx_batch_entry layout differs between the library and the binding")
@@ -48,6 +51,11 @@ class BatchEngine:
         self.shapes = []
         off = dict(atom=0, hkl=0, pix=0, tile=0, rowptr=0, pair=0, node=0, ff=0)
         refl_blocks, model_rb, atom_blocks, node_blocks, items, costs = [], [], [], [], [], []
+        # the forward's stacked tiles (fdtbx_batch_profile_stacked): two launched tile rows per
+        # wave, one culling list for both (the backward keeps the per-tile lists)
+        self.stacked = bool(stacked)
+        sboxes, srowptrs, sidxs, s_items, s_costs, stack_off = [], [], [], [], [], []
+        soff = dict(box=0, rowptr=0, pair=0)
         self.list_len = []
         self.tile_w = []
         for m, (wl, mod) in enumerate(zip(workloads, self.models)):
@@ -89,6 +97,21 @@ class BatchEngine:
             keep = np.nonzero((t_all % tx_n < lcols) & (t_all // tx_n < lrows))[0]
             items += [_pack(m, int(t)) for t in keep]
             costs.append(lens[keep])
+            if self.stacked:
+                sbox, srowptr, sidx = B.stacked_cull(mod.geom, tile, cull)
+                n_st = int(sbox.shape[0])
+                slens = (srowptr[1:] - srowptr[:-1]).cpu().numpy()
+                s_all = np.arange(n_st)
+                skeep = np.nonzero(s_all % tx_n < lcols)[0]  # every stacked row holds launched rows
+                s_items += [_pack(m, int(t)) for t in skeep]
+                s_costs.append(slens[skeep])
+                stack_off += [soff["box"], soff["rowptr"], soff["pair"]]
+                sboxes.append(sbox)
+                srowptrs.append(srowptr)
+                sidxs.append(sidx)
+                soff["box"] += n_st
+                soff["rowptr"] += n_st + 1
+                soff["pair"] += int(sidx.shape[0])
             self.list_len.append(int(idx.shape[0]))
             hkls.append(hkl)
             pixs.append(pix.reshape(-1, 2))
@@ -122,6 +145,15 @@ class BatchEngine:
         cost = np.concatenate(costs)
         order = np.argsort(-cost, kind="stable")
         self.items = dev(np.asarray(items, dtype=np.int64)[order], torch.int64)
+        if self.stacked:
+            s_order = np.argsort(-np.concatenate(s_costs), kind="stable")
+            self.stack_items = dev(np.asarray(s_items, dtype=np.int64)[s_order], torch.int64)
+            self.stack_off = dev(np.asarray(stack_off, dtype=np.int64), torch.int64)
+            self.stile = torch.cat(sboxes).contiguous()
+            self.srowptr = torch.cat(srowptrs).contiguous()
+            self.sidx = torch.cat(sidxs).contiguous() if soff["pair"] > 0 else \
+                torch.zeros(1, dtype=torch.int32, device=device)
+            self.totals["stacked_pair"] = soff["pair"]
         self.refl_blocks = dev(np.asarray(refl_blocks, dtype=np.int64), torch.int64)
         self.model_rb = dev(np.asarray(model_rb, dtype=np.int64), torch.int64)
         self.atom_blocks = dev(np.asarray(atom_blocks, dtype=np.int64), torch.int64)
@@ -217,13 +249,20 @@ class BatchEngine:
 
     def forward(self) -> torch.Tensor:
         a = self.atoms
+        n_items = 0 if self.stacked else int(self.items.shape[0])
         B._check(B.lib().fdtbx_batch_forward(
             B._ptr(self.entries), self.n, B._ptr(self.refl_blocks), int(self.refl_blocks.shape[0]),
-            B._ptr(self.node_blocks), int(self.node_blocks.shape[0]), B._ptr(self.items), int(self.items.shape[0]),
+            B._ptr(self.node_blocks), int(self.node_blocks.shape[0]), B._ptr(self.items), n_items,
             B._ptr(self.hkl), B._ptr(a["x"]), B._ptr(a["y"]), B._ptr(a["z"]), B._ptr(a["B"]), B._ptr(a["occ"]),
             B._ptr(a["type"]), B._ptr(a["ff"]), B._ptr(self.pix), B._ptr(self.tile), B._ptr(self.rowptr),
             B._ptr(self.idx), B._ptr(self.F), B._ptr(self.F2), B._ptr(self.refl), B._ptr(self.nodes),
             B._ptr(self.image), B._ptr(self.counter), B._stream()))
+        if self.stacked:
+            B._check(B.lib().fdtbx_batch_profile_stacked(
+                B._ptr(self.entries), self.n, B._ptr(self.stack_off), B._ptr(self.stack_items),
+                int(self.stack_items.shape[0]), B._ptr(self.refl), B._ptr(self.nodes), B._ptr(self.pix),
+                B._ptr(self.tile), B._ptr(self.stile), B._ptr(self.srowptr), B._ptr(self.sidx), B._ptr(self.image),
+                B._ptr(self.counter), B._stream()))
         return self.image
 
     def backward(self, grad_image: torch.Tensor, atoms: bool = True):

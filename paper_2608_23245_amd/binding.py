@@ -106,6 +106,12 @@ _SIGS = {
     "fdtbx_cull": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p,
                                   ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
                                   ctypes.c_void_p]),
+    "fdtbx_stacked_rows": (ctypes.c_int32, [ctypes.c_void_p]),
+    "fdtbx_stacked_boxes": (ctypes.c_int, [ctypes.c_void_p] * 4),
+    "fdtbx_stacked_cull_workspace": (ctypes.c_size_t, [ctypes.c_void_p, ctypes.c_int64]),
+    "fdtbx_stacked_cull": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]),
     "fdtbx_profile": (ctypes.c_int, [ctypes.c_void_p] + [ctypes.c_void_p] * 10),
     "fdtbx_tile_order_size": (ctypes.c_int64, [ctypes.c_void_p]),
     "fdtbx_tile_order_workspace": (ctypes.c_size_t, [ctypes.c_void_p]),
@@ -176,6 +182,8 @@ _SIGS = {
     "fdtbx_batch_forward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64] +
                             [ctypes.c_void_p] * 18 + [ctypes.c_void_p]),
+    "fdtbx_batch_profile_stacked": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.c_int64] + [ctypes.c_void_p] * 10),
     "fdtbx_batch_backward": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
                                             ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                             ctypes.c_int64, ctypes.c_int64] + [ctypes.c_void_p] * 26 + [ctypes.c_void_p]),
@@ -358,6 +366,36 @@ def cull(geom: Geometry, tile: torch.Tensor, cull_rec: torch.Tensor, cap: Option
             continue
         _check(rc)
         return offsets, idx[: int(n_pairs.value)]
+    raise FdtbxError(-3, "culling capacity")
+
+
+def stacked_cull(geom: Geometry, tile: torch.Tensor, cull_rec: torch.Tensor, cap: Optional[int] = None):
+    """fdtbx_stacked_boxes and fdtbx_stacked_cull; returns (boxes float64 [n_stacked][8], offsets
+    int64 [n_stacked + 1], idx int32 [n_pairs]) of the stacked tiles (pairs of launched tile rows)."""
+    L = lib()
+    n_rows = int(L.fdtbx_stacked_rows(ctypes.byref(geom)))
+    if n_rows <= 0:
+        raise FdtbxError(-1, "fdtbx_stacked_rows rejected the geometry")
+    tx, _ = tile_grid(geom)
+    n = tx * n_rows
+    _dev(tile, torch.float64, "tile")
+    boxes = torch.empty((n, 8), dtype=torch.float64, device=tile.device)
+    _check(L.fdtbx_stacked_boxes(ctypes.byref(geom), _ptr(tile), _ptr(boxes), _stream()))
+    n_hkl = int(cull_rec.shape[0])
+    offsets = torch.empty(n + 1, dtype=torch.int64, device=tile.device)
+    wsb = L.fdtbx_stacked_cull_workspace(ctypes.byref(geom), n_hkl)
+    ws = torch.empty(max(wsb, 8), dtype=torch.uint8, device=tile.device)
+    cap = 1 << 20 if cap is None else cap
+    for _ in range(2):
+        idx = torch.empty(max(cap, 1), dtype=torch.int32, device=tile.device)
+        n_pairs = ctypes.c_int64(0)
+        rc = L.fdtbx_stacked_cull(ctypes.byref(geom), _ptr(boxes), n_hkl, _ptr(cull_rec), _ptr(offsets), _ptr(idx),
+                                  cap, ctypes.byref(n_pairs), _ptr(ws), wsb, _stream())
+        if rc == -3 and n_pairs.value > cap:
+            cap = int(n_pairs.value)
+            continue
+        _check(rc)
+        return boxes, offsets, idx[: int(n_pairs.value)]
     raise FdtbxError(-3, "culling capacity")
 
 

@@ -535,6 +535,18 @@ extern "C" int fdtbx_batch_forward(const fdtbx_batch_entry* entries, int32_t n_m
   return launch_batch_profile(entries, tile_items, n_items, refl, nodes, pix, tile, rowptr, idx, image, counter, s);
 }
 
+extern "C" int fdtbx_batch_profile_stacked(const fdtbx_batch_entry* entries, int32_t n_models, const int64_t* stack_off,
+                                           const int64_t* stack_items, int64_t n_items, const float* refl,
+                                           const float* nodes, const double* pix, const double* tile,
+                                           const double* stile, const int64_t* srowptr, const int32_t* sidx,
+                                           float* image, int64_t* counter, void* stream) {
+  if (!entries || n_models <= 0 || n_items < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "bad sizes");
+  if (!stack_off || !stack_items || !refl || !nodes || !pix || !tile || !stile || !srowptr || !sidx || !image || !counter)
+    return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  return launch_batch_profile_stacked(entries, stack_off, stack_items, n_items, refl, nodes, pix, tile, stile, srowptr,
+                                      sidx, image, counter, (hipStream_t)stream);
+}
+
 extern "C" int fdtbx_batch_backward(const fdtbx_batch_entry* entries, int32_t n_models, const int64_t* refl_blocks, int64_t n_rb,
                                     const int64_t* model_rb, const int64_t* atom_blocks, int64_t n_ab, const int64_t* tile_items,
                                     int64_t n_items, int64_t n_hkl_total, const int32_t* hkl, const float* x, const float* y,

@@ -773,10 +773,7 @@ static void cull_params(const fdtbx_geometry* g, int64_t n_hkl, CullParams* q) {
 }
 
 // Workspace: superblock boxes | masks | tile counts scratch.
-extern "C" size_t fdtbx_cull_workspace(const fdtbx_geometry* geom, int64_t n_hkl) {
-  if (!geom || check_geometry(geom) || n_hkl <= 0) return 0;
-  CullParams q;
-  cull_params(geom, n_hkl, &q);
+static size_t cull_workspace_of(const CullParams& q) {
   int64_t nsb = (int64_t)q.sb_x * q.sb_y;
   size_t b = align_up((size_t)nsb * 8 * sizeof(double), 256);
   b += align_up((size_t)nsb * q.n_words * sizeof(uint64_t), 256);
@@ -785,23 +782,18 @@ extern "C" size_t fdtbx_cull_workspace(const fdtbx_geometry* geom, int64_t n_hkl
   return b;
 }
 
-extern "C" int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_t n_hkl, const double* cull,
-                          int64_t* offsets, int32_t* idx, int64_t cap, int64_t* n_pairs, void* ws, size_t ws_bytes,
-                          void* stream) {
-  if (!geom || !tile || !offsets || !n_pairs) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
-  if (n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be non-negative");
-  if (n_hkl > (int64_t)INT32_MAX) return fail(FDTBX_ERR_UNSUPPORTED, "more than 2^31 reflections");
-  int rc = check_geometry(geom);
-  if (rc) return rc;
-  if (n_hkl == 0) {  // every list empty
-    *n_pairs = 0;
-    return fill(offsets, (int64_t)tiles_x_of(geom) * tiles_y_of(geom) + 1, (int64_t)0,
-                (hipStream_t)stream);
-  }
-  if (!cull || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
-  if (ws_bytes < fdtbx_cull_workspace(geom, n_hkl)) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "cull workspace too small");
+extern "C" size_t fdtbx_cull_workspace(const fdtbx_geometry* geom, int64_t n_hkl) {
+  if (!geom || check_geometry(geom) || n_hkl <= 0) return 0;
   CullParams q;
   cull_params(geom, n_hkl, &q);
+  return cull_workspace_of(q);
+}
+
+// The lists of the tile grid q (boxes in tile, row-major), as fdtbx_cull describes them.
+static int cull_lists(const CullParams& q, const double* tile, const double* cull, int64_t* offsets, int32_t* idx,
+                      int64_t cap, int64_t* n_pairs, void* ws, size_t ws_bytes, hipStream_t s) {
+  if (!cull || !ws) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (ws_bytes < cull_workspace_of(q)) return fail(FDTBX_ERR_BUFFER_TOO_SMALL, "cull workspace too small");
   int64_t nsb = (int64_t)q.sb_x * q.sb_y;
   int64_t n_tiles = (int64_t)q.tiles_x * q.tiles_y;
   char* w = (char*)ws;
@@ -812,7 +804,6 @@ extern "C" int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_
   int64_t* total = (int64_t*)w;
   w += align_up(sizeof(int64_t) * 2, 256);
   int32_t* part = (int32_t*)w;
-  hipStream_t s = (hipStream_t)stream;
   hipLaunchKernelGGL(k_sb_boxes, dim3((unsigned)ceil_div(nsb, 256)), dim3(256), 0, s, q, tile, sb);
   FDTBX_LAUNCH_CHECK("cull superblocks");
   hipLaunchKernelGGL(k_sb_mask, dim3((unsigned)q.n_words), dim3(64), 0, s, q, sb, cull, mask);
@@ -834,6 +825,101 @@ extern "C" int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_
     FDTBX_LAUNCH_CHECK("cull fill");
   }
   return FDTBX_OK;
+}
+
+extern "C" int fdtbx_cull(const fdtbx_geometry* geom, const double* tile, int64_t n_hkl, const double* cull,
+                          int64_t* offsets, int32_t* idx, int64_t cap, int64_t* n_pairs, void* ws, size_t ws_bytes,
+                          void* stream) {
+  if (!geom || !tile || !offsets || !n_pairs) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be non-negative");
+  if (n_hkl > (int64_t)INT32_MAX) return fail(FDTBX_ERR_UNSUPPORTED, "more than 2^31 reflections");
+  int rc = check_geometry(geom);
+  if (rc) return rc;
+  if (n_hkl == 0) {  // every list empty
+    *n_pairs = 0;
+    return fill(offsets, (int64_t)tiles_x_of(geom) * tiles_y_of(geom) + 1, (int64_t)0,
+                (hipStream_t)stream);
+  }
+  CullParams q;
+  cull_params(geom, n_hkl, &q);
+  return cull_lists(q, tile, cull, offsets, idx, cap, n_pairs, ws, ws_bytes, (hipStream_t)stream);
+}
+
+// ---------------------------------------------------------------- stacked tiles
+// Pairs of launched tile rows (2 sy, 2 sy + 1) form the rows sy of a grid of stacked tiles,
+// tiles_x wide and ceil(lrows / 2) high (the last one a single row when lrows is odd); a
+// stacked tile's box is the union of its tiles' boxes, and its list comes from the same test.
+static int32_t stacked_rows_of(const fdtbx_geometry* g) { return (int32_t)ceil_div(lrows_of(g), 2); }
+
+static void stacked_params(const fdtbx_geometry* g, int64_t n_hkl, CullParams* q) {
+  q->tiles_x = tiles_x_of(g);
+  q->tiles_y = stacked_rows_of(g);
+  q->lcols = lcols_of(g);
+  q->lrows = q->tiles_y;
+  q->sb_x = (int32_t)ceil_div(q->tiles_x, kSB);
+  q->sb_y = (int32_t)ceil_div(q->tiles_y, kSB);
+  q->n_hkl = n_hkl;
+  q->n_words = ceil_div(n_hkl, 64);
+}
+
+namespace fdtbx {
+__global__ void k_stack_boxes(int32_t tiles_x, int32_t lrows, int32_t n_srows, const double* __restrict__ tile,
+                              double* __restrict__ stile) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= (int64_t)tiles_x * n_srows) return;
+  const int64_t sx = s % tiles_x, sy = s / tiles_x;
+  const int64_t r0 = 2 * sy, r1 = 2 * sy + 1 < lrows ? 2 * sy + 1 : 2 * sy;
+  const double* a = tile + 8 * (r0 * tiles_x + sx);
+  const double* b = tile + 8 * (r1 * tiles_x + sx);
+  double* o = stile + 8 * s;
+  for (int c = 0; c < 6; c += 2) {
+    o[c] = fmin(a[c], b[c]);
+    o[c + 1] = fmax(a[c + 1], b[c + 1]);
+  }
+  o[6] = 0.0;
+  o[7] = 0.0;
+}
+}  // namespace fdtbx
+
+extern "C" int32_t fdtbx_stacked_rows(const fdtbx_geometry* geom) {
+  if (!geom || check_geometry(geom)) return 0;
+  return stacked_rows_of(geom);
+}
+
+extern "C" int fdtbx_stacked_boxes(const fdtbx_geometry* geom, const double* tile, double* stile, void* stream) {
+  if (!geom || !tile || !stile) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  int rc = check_geometry(geom);
+  if (rc) return rc;
+  const int32_t tx = tiles_x_of(geom), ns = stacked_rows_of(geom);
+  const int64_t n = (int64_t)tx * ns;
+  hipLaunchKernelGGL(k_stack_boxes, dim3((unsigned)ceil_div(n, 256)), dim3(256), 0, (hipStream_t)stream, tx,
+                     lrows_of(geom), ns, tile, stile);
+  FDTBX_LAUNCH_CHECK("stacked tile boxes");
+  return FDTBX_OK;
+}
+
+extern "C" size_t fdtbx_stacked_cull_workspace(const fdtbx_geometry* geom, int64_t n_hkl) {
+  if (!geom || check_geometry(geom) || n_hkl <= 0) return 0;
+  CullParams q;
+  stacked_params(geom, n_hkl, &q);
+  return cull_workspace_of(q);
+}
+
+extern "C" int fdtbx_stacked_cull(const fdtbx_geometry* geom, const double* stile, int64_t n_hkl, const double* cull,
+                                  int64_t* offsets, int32_t* idx, int64_t cap, int64_t* n_pairs, void* ws,
+                                  size_t ws_bytes, void* stream) {
+  if (!geom || !stile || !offsets || !n_pairs) return fail(FDTBX_ERR_INVALID_ARGUMENT, "null pointer");
+  if (n_hkl < 0) return fail(FDTBX_ERR_INVALID_ARGUMENT, "n_hkl must be non-negative");
+  if (n_hkl > (int64_t)INT32_MAX) return fail(FDTBX_ERR_UNSUPPORTED, "more than 2^31 reflections");
+  int rc = check_geometry(geom);
+  if (rc) return rc;
+  CullParams q;
+  stacked_params(geom, n_hkl, &q);
+  if (n_hkl == 0) {
+    *n_pairs = 0;
+    return fill(offsets, (int64_t)q.tiles_x * q.tiles_y + 1, (int64_t)0, (hipStream_t)stream);
+  }
+  return cull_lists(q, stile, cull, offsets, idx, cap, n_pairs, ws, ws_bytes, (hipStream_t)stream);
 }
 
 namespace fdtbx {

@@ -215,6 +215,10 @@ int launch_batch_nodes(const fdtbx_batch_entry* ent, const int64_t* blocks, int6
 int launch_batch_profile(const fdtbx_batch_entry* ent, const int64_t* items, int64_t n_items, const float* refl,
                          const float* nodes, const double* pix, const double* tile, const int64_t* rowptr, const int32_t* idx,
                          float* image, int64_t* counter, hipStream_t s);
+int launch_batch_profile_stacked(const fdtbx_batch_entry* ent, const int64_t* soff, const int64_t* items,
+                                 int64_t n_items, const float* refl, const float* nodes, const double* pix,
+                                 const double* tile, const double* stile, const int64_t* srowptr, const int32_t* sidx,
+                                 float* image, int64_t* counter, hipStream_t s);
 // Fixed-order accumulation of the adjoint sums (fdtbx_pair_reduce): per-pair partials
 // float32 [n_pairs][12] and the pairs of each reflection in a fixed order.
 struct PairOrder {

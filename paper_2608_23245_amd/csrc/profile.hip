@@ -216,6 +216,87 @@ int launch_batch_profile(const fdtbx_batch_entry* ent, const int64_t* items, int
   return FDTBX_OK;
 }
 
+// Batched models on stacked tiles: every wave takes (model, stacked tile) items as k_b_profile
+// takes tiles.  Stacked tile s = sy tiles_x + sx holds tile rows 2 sy and 2 sy + 1 (the second
+// when it is launched) of tile column sx; its box, row pointers and list start at the model's
+// offsets in soff ([m][3]: first box, first row pointer, first list entry; the row pointers are
+// relative to the model's first list entry).
+__global__ void __launch_bounds__(64) k_b_profile_stacked(const fdtbx_batch_entry* __restrict__ ent,
+                                                          const int64_t* __restrict__ soff,
+                                                          const int64_t* __restrict__ items, int64_t n_items,
+                                                          const float* __restrict__ refl,
+                                                          const float* __restrict__ nodes,
+                                                          const double* __restrict__ pix,
+                                                          const double* __restrict__ tile,
+                                                          const double* __restrict__ stile,
+                                                          const int64_t* __restrict__ srowptr,
+                                                          const int32_t* __restrict__ sidx, float* __restrict__ image,
+                                                          unsigned long long* __restrict__ counter) {
+  __shared__ float4 qn[128];
+  __shared__ int bq[64];
+  const int lane = threadIdx.x & 63;
+  for (;;) {
+    const int64_t it = next_item(counter);
+    if (it >= n_items) break;
+    const int64_t packed = items[it];
+    const int m = (int)(packed >> 40);
+    const int st = (int)(packed & ((1ll << 40) - 1));
+    const fdtbx_batch_entry& e = ent[m];
+    ProfParams q;
+    prof_params(&e.model, &q);
+    const double* px = pix + 2 * e.pix_off;
+    const double* tb = tile + 8 * e.tile_off;
+    const double* sbox = stile + 8 * (soff[3 * m] + st);
+    const int64_t* rp = srowptr + soff[3 * m + 1];
+    const int32_t* ix = sidx + soff[3 * m + 2];
+    float* im = image + e.pix_off;
+    const int sx = st % q.tiles_x, sy = st / q.tiles_x;
+    const int ta = 2 * sy * q.tiles_x + sx;
+    const bool two = 2 * sy + 1 < q.lrows;  // uniform
+    const TilePixel pa = tile_pixel(q, px, tb, ta, lane);
+    TilePixel pb = tile_pixel(q, px, tb, two ? ta + q.tiles_x : ta, lane);
+    if (!two) {
+      pb.in = false;
+      pb.R = 1.0e30;
+      pb.Z = 0.0;
+    }
+    const TileBox box = {sbox[0], sbox[1], sbox[2], sbox[3]};
+    const float* rf = refl + (int64_t)FDTBX_REFL_FLOATS * e.hkl_off;
+    const float* nd = nodes + (int64_t)FDTBX_NODE_FLOATS * e.node_off;
+    const int64_t p0 = rp[st], p1 = rp[st + 1];
+    float sa = 0.0f, sb = 0.0f;
+    switch (q.lineshape) {  // uniform across the wave
+      case FDTBX_LINESHAPE_GAUSSIAN:
+        pairs_sum_stacked<FDTBX_LINESHAPE_GAUSSIAN>(q, rf, nd, ix, box, pa.R, pa.Z, pb.R, pb.Z, p0, p1, qn, bq, &sa,
+                                                    &sb);
+        break;
+      case FDTBX_LINESHAPE_HOSEMANN:
+        pairs_sum_stacked<FDTBX_LINESHAPE_HOSEMANN>(q, rf, nd, ix, box, pa.R, pa.Z, pb.R, pb.Z, p0, p1, qn, bq, &sa,
+                                                    &sb);
+        break;
+      default:
+        pairs_sum_stacked<FDTBX_LINESHAPE_LAUE>(q, rf, nd, ix, box, pa.R, pa.Z, pb.R, pb.Z, p0, p1, qn, bq, &sa,
+                                                &sb);
+    }
+    if (pa.in) write_folded(q, im, pa.i, pa.j, pa.tx, pa.ty, (float)(q.delta / (pa.R + q.delta)) * sa);
+    if (pb.in) write_folded(q, im, pb.i, pb.j, pb.tx, pb.ty, (float)(q.delta / (pb.R + q.delta)) * sb);
+  }
+}
+
+int launch_batch_profile_stacked(const fdtbx_batch_entry* ent, const int64_t* soff, const int64_t* items,
+                                 int64_t n_items, const float* refl, const float* nodes, const double* pix,
+                                 const double* tile, const double* stile, const int64_t* srowptr, const int32_t* sidx,
+                                 float* image, int64_t* counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, (unsigned long long*)counter, 1);
+  FDTBX_LAUNCH_CHECK("stacked batch profile counter");
+  if (n_items <= 0) return FDTBX_OK;
+  unsigned nb = n_items < (int64_t)kPersistentBlocks ? (unsigned)n_items : kPersistentBlocks;
+  hipLaunchKernelGGL(k_b_profile_stacked, dim3(nb), dim3(64), 0, s, ent, soff, items, n_items, refl, nodes, pix, tile,
+                     stile, srowptr, sidx, image, (unsigned long long*)counter);
+  FDTBX_LAUNCH_CHECK("stacked batch profile");
+  return FDTBX_OK;
+}
+
 // The persistent grid: as many 4-wave workgroups as the compute units hold at once.
 template <int LS>
 static int launch_units(const ProfParams& q, const float* refl, const float* nodes, const double* pix,

@@ -215,6 +215,100 @@ __device__ __forceinline__ float pairs_sum(const ProfParams& q, const float* __r
   return acc;
 }
 
+// The walk of walk_queue for a lane holding two pixels (al, bl: their tagged alpha): each
+// entry is tested and evaluated for both, with a block sum each.
+template <int LS>
+__device__ __forceinline__ void walk_queue2(const float4* qn, int cnt, const float* al, const float* bl,
+                                            float half_m, const HoseK& hk, float& acca, float& accb) {
+  qn += threadIdx.y;
+  float4 nxt = qn[0];
+  float pa = 0.0f, pb = 0.0f;
+  unsigned long long none = 0;
+  for (int jj = 0; jj < cnt; ++jj) {
+    const float4 cur = nxt;
+    nxt = qn[jj + 1];
+    eval_node<false, LS>(cur, al[0], al[1], al[2], half_m, hk, pa, none);
+    eval_node<false, LS>(cur, bl[0], bl[1], bl[2], half_m, hk, pb, none);
+  }
+  acca += pa;
+  accb += pb;
+}
+
+// pairs_sum for a stacked tile: two vertically adjacent tiles walked by one wave, lane l
+// holding pixel l of the upper tile (RA, ZA) and of the lower one (RB, ZB; far from every
+// reflection when the stacked tile has one row of tiles).  The pairs are those of the stacked
+// tile's list, set up against its box (the union of the two tiles' boxes) with the block
+// narrowing of the batched launches; one queue serves both pixels, so each pair's set-up,
+// window scan and queue reads are shared by the two tiles.  *sa, *sb: the two pixel sums.
+template <int LS>
+__device__ __forceinline__ void pairs_sum_stacked(const ProfParams& q, const float* __restrict__ refl,
+                                                  const float* __restrict__ nodes, const int32_t* __restrict__ idx,
+                                                  const TileBox& box, double RA, double ZA, double RB, double ZB,
+                                                  int64_t from, int64_t p1, float4* qn, int* bq, float* sa,
+                                                  float* sb) {
+  const int lane = threadIdx.x & 63;
+  float acca = 0.0f, accb = 0.0f;
+  for (int64_t base = from; base < p1; base += 64) {
+    int32_t rl = 0;
+    int w01 = 0, w23 = 0;
+    float lol[3] = {0.f, 0.f, 0.f}, hil[3] = {0.f, 0.f, 0.f};
+    bool ok = false;
+    if (base + lane < p1) {
+      rl = idx[base + lane];
+      ok = pair_setup<true>(q, refl + (int64_t)FDTBX_REFL_FLOATS * rl, nodes, box, &w01, &w23, lol, hil);
+    }
+    unsigned long long todo = __ballot(ok);
+    while (todo) {
+      const int src = (int)__builtin_ctzll(todo);
+      todo &= todo - 1;
+      const int32_t r = lane_int(rl, src);
+      const int a01 = lane_int(w01, src), a23 = lane_int(w23, src);
+      const Window w = {a01 & 0xffff, a01 >> 16, a23 & 0xffff, a23 >> 16};
+      float al[3], bl[3], lo[3], hi[3], Bv[3], G1[3], G2[3];
+      PairRec f;
+      load_pair(refl + (int64_t)FDTBX_REFL_FLOATS * r, f);
+      const double RD = f.at_f64(RS_RD), ZD = f.at_f64(RS_ZD);
+      const float dRa = (float)(RA - RD), dZa = (float)(ZA - ZD);
+      const float dRb = (float)(RB - RD), dZb = (float)(ZB - ZD);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        al[a] = fmaf(f.at(RS_TR + a), dRa, f.at(RS_TZ + a) * dZa);
+        bl[a] = fmaf(f.at(RS_TR + a), dRb, f.at(RS_TZ + a) * dZb);
+        if (LS == FDTBX_LINESHAPE_LAUE) {
+          al[a] = tag_alpha(al[a]);
+          bl[a] = tag_alpha(bl[a]);
+        }
+        lo[a] = lane_float(lol[a], src);
+        hi[a] = lane_float(hil[a], src);
+        Bv[a] = f.at(RS_B + a);
+        G1[a] = f.at(RS_G1 + a);
+        G2[a] = f.at(RS_G2 + a);
+      }
+      HoseK hk = {};
+      if (LS == FDTBX_LINESHAPE_HOSEMANN) hose_constants(refl + (int64_t)FDTBX_REFL_FLOATS * r, hk);
+      float ra = 0.0f, rb = 0.0f;
+      int qlen = 0;  // uniform
+      scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int, float4 e) {
+        queue_append<LS>(qn, qlen, keep, e);
+        wave_sync();
+        if (qlen >= 64) {
+          walk_queue2<LS>(qn, 64, al, bl, q.half_m, hk, ra, rb);
+          qlen -= 64;
+          wave_sync();
+          if (lane < qlen) qn[lane] = qn[64 + lane];
+          wave_sync();
+        }
+      });
+      walk_queue2<LS>(qn, qlen, al, bl, q.half_m, hk, ra, rb);
+      wave_sync();
+      acca = fmaf(f.at(RS_WK), ra, acca);
+      accb = fmaf(f.at(RS_WK), rb, accb);
+    }
+  }
+  *sa = acca;
+  *sb = accb;
+}
+
 // The pixel of lane `lane` in tile t: its column i, row j, whether it lies on the detector,
 // and its ring coordinates (lanes outside the detector sit far from every reflection, so all
 // supports fail); and the tile's (R, Z) box.
