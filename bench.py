@@ -102,7 +102,7 @@ def parse():
     ap.add_argument("--no-unfolded", action="store_true", help="skip the unfolded reference forward")
     ap.add_argument("--only-batch", action="store_true",
                     help="run the batched forward alone, at --batch-tile-w, --steps times (profiler runs)")
-    ap.add_argument("--batch-tile-w", type=int, default=16, choices=(4, 8, 16),
+    ap.add_argument("--batch-tile-w", type=int, default=16, choices=(4, 8, 16, 32),
                     help="tile width of every model of the batch with --only-batch")
     ap.add_argument("--batch-per-tile", action="store_true",
                     help="with --only-batch, walk the per-tile culling lists instead of the stacked tiles")
