@@ -243,7 +243,7 @@ class BatchEngine:
                                     B_axis=tuple(float(v) for v in g[m, 8:11]))
             wls.append(dataclasses.replace(wl, dis=d))
         atoms = {k: v.clone() for k, v in self.atoms.items()}
-        self.__init__(wls, device=self.device, deterministic=self.deterministic)
+        self.__init__(wls, device=self.device, deterministic=self.deterministic, stacked=self.stacked)
         for k, v in atoms.items():
             self.atoms[k].copy_(v)
 
