@@ -3,7 +3,8 @@ fdtbx_batch_profile_stacked): the stacked boxes are the unions of their two tile
 launched stacked list contains the lists of both its tiles (ascending, the other lists empty),
 and a batch walked on stacked tiles gives the images of the per-tile walk to float32 rounding,
 with and without the mirror folds, for odd and even numbers of launched tile rows, one tile
-row, every lineshape and tile shapes from 4x16 to 32x2."""
+row, every lineshape and tile shapes from 4x16 to 32x2; and a batch of sixteen random small
+models of the launch sweep against the per-tile walk and the oracle."""
 import ctypes
 import dataclasses
 import math
@@ -157,3 +158,32 @@ def test_stacked_host_checks():
     one = torch.zeros(1, dtype=torch.int64, device="cuda")
     assert L.fdtbx_batch_profile_stacked(None, 1, B._ptr(one), B._ptr(one), 1, *([B._ptr(one)] * 9),
                                          B._stream()) == -1
+
+
+def test_stacked_random_batch_vs_oracle():
+    """Sixteen seeded random small models of the launch sweep (detector sizes, beam centres,
+    cells, fibre tilts, lineshapes, tile shapes from 2x32 to 32x2, the mirror folds where the
+    beam is centred) in one batch: stacked against per-tile walk, and each image against the
+    oracle at the pattern tolerances."""
+    from oracle import oracle as O
+    from test_gpu_launch_sweep import random_case
+    wls = []
+    for seed in range(16):
+        wl, fold = random_case(seed)
+        wl = geom(wl, mirror=fold)
+        m = B.make_model(wl)
+        ext = (wl.dis.g[0], wl.dis.g[1], wl.dis.g[2], wl.quad.extinction) if wl.quad.extinction > 0 else None
+        if B.enumerate_hkl(m.cell, wl.quad.d_min, wl.quad.d_max, extinction=ext).shape[0] > 0:
+            wls.append(wl)
+    say(f"random batch: {len(wls)} models, tile widths {[w.geom.tile_w for w in wls]}, "
+        f"mirror bits {[w.geom.mirror for w in wls]}")
+    a = compare(wls, "random")
+    for m, wl in enumerate(wls):
+        hkl = a.hkl[a.hkl_off[m]:a.hkl_off[m + 1]].cpu().numpy()
+        ref = O.pattern(wl, O.prepare(wl, hkl=hkl))
+        got = a.image_of(m).cpu().numpy().astype(np.float64)
+        r = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        big = ref > 1e-3 * ref.max()
+        px = float(np.max(np.abs(got[big] - ref[big]) / ref[big]))
+        say(f"  model {m}: rel-L2 {r:.2e}, per-pixel {px:.2e} against the oracle")
+        assert r <= 1e-4 and px <= 1e-3, (m, r, px)
