@@ -247,7 +247,7 @@ int fdtbx_structure_factors(const fdtbx_cell* cell, int64_t n_atoms, const float
  *   [7]    0
  * The profile kernels test blocks before nodes; the records are derived data, not part
  * of the quadrature. */
-#define FDTBX_REFL_FLOATS 48
+#define FDTBX_REFL_FLOATS 64 /* 256 bytes: a per-pair cache line, then the rest */
 #define FDTBX_CULL_DOUBLES 16
 #define FDTBX_NODE_FLOATS 8
 #define FDTBX_NODE_BLOCK 4

@@ -17,7 +17,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_lib", "libfdtbx.so")
 
-REFL_FLOATS = 48
+REFL_FLOATS = 64
 CULL_DOUBLES = 16
 NODE_FLOATS = 8
 NODE_BLOCK = 4

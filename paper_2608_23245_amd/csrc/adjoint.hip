@@ -44,9 +44,11 @@ __global__ void __launch_bounds__(64 * WAVES) k_profile_adj(ProfParams q, const 
   __shared__ float4 qn[128 * WAVES];
   __shared__ float2 qd[128 * WAVES];
   __shared__ int bq[64 * WAVES];
+  __shared__ int qk[LS == FDTBX_LINESHAPE_HOSEMANN ? 128 * WAVES : 1];  // node indices (support edge)
   const int t = order ? order[blockIdx.x] : tile_of_block(q, blockIdx.x);
   if (t < 0) return;
-  adjoint_tile<LS, WAVES>(q, refl, nodes, pix, tile, offsets, idx, grad_image, n_hkl, sums, partials, t, qn, qd, bq);
+  adjoint_tile<LS, WAVES>(q, refl, nodes, pix, tile, offsets, idx, grad_image, n_hkl, sums, partials, t, qn, qd, bq,
+                          LS == FDTBX_LINESHAPE_HOSEMANN ? qk : nullptr);
 }
 
 template <int WAVES>
@@ -81,6 +83,7 @@ __global__ void __launch_bounds__(256) k_profile_adj_units(ProfParams q, const f
   __shared__ float4 qn[128 * 4];
   __shared__ float2 qd[128 * 4];
   __shared__ int bq[64 * 4];
+  __shared__ int qk[LS == FDTBX_LINESHAPE_HOSEMANN ? 128 * 4 : 1];  // node indices (support edge)
   const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int64_t U = T.meta[1];
   const int64_t total = U > 0 ? min(T.meta[0], T.max_units) : 0;
@@ -98,7 +101,8 @@ __global__ void __launch_bounds__(256) k_profile_adj_units(ProfParams q, const f
       const int t = unit_range(q, T, offsets, u, U, &p0, &p1);
       if (t < 0) continue;
       adjoint_range<LS>(q, refl, nodes, pix, tile, idx, grad_image, n_hkl, sums, partials, t, p0, p1, 64,
-                        qn + 128 * wv, qd + 128 * wv, bq + 64 * wv);
+                        qn + 128 * wv, qd + 128 * wv, bq + 64 * wv,
+                        LS == FDTBX_LINESHAPE_HOSEMANN ? qk + 128 * wv : nullptr);
     }
   }
 }
@@ -395,7 +399,7 @@ static void recip_basis(const fdtbx_cell* cell, double* as) {
 }
 
 // ---------------------------------------------------------------- batched models
-__global__ void __launch_bounds__(64) k_b_profile_adj(const fdtbx_batch_entry* __restrict__ ent, const int64_t* __restrict__ items,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) k_b_profile_adj(const fdtbx_batch_entry* __restrict__ ent, const int64_t* __restrict__ items,
                                                       int64_t n_items, const float* __restrict__ refl,
                                                       const float* __restrict__ nodes, const double* __restrict__ pix,
                                                       const double* __restrict__ tile, const int64_t* __restrict__ rowptr,
@@ -405,6 +409,7 @@ __global__ void __launch_bounds__(64) k_b_profile_adj(const fdtbx_batch_entry* _
   __shared__ float4 qn[128];
   __shared__ float2 qd[128];
   __shared__ int bq[64];
+  __shared__ int qk[128];  // node indices of the queue (the Hosemann support edge)
   for (;;) {
     const int64_t it = next_item(counter);
     if (it >= n_items) break;
@@ -428,7 +433,8 @@ __global__ void __launch_bounds__(64) k_b_profile_adj(const fdtbx_batch_entry* _
         adjoint_tile<FDTBX_LINESHAPE_GAUSSIAN, 1, true>(q, rf, nd, px, tb, rp, ix, gi, e.n_hkl, sm, pt, t, qn, qd, bq);
         break;
       case FDTBX_LINESHAPE_HOSEMANN:
-        adjoint_tile<FDTBX_LINESHAPE_HOSEMANN, 1, true>(q, rf, nd, px, tb, rp, ix, gi, e.n_hkl, sm, pt, t, qn, qd, bq);
+        adjoint_tile<FDTBX_LINESHAPE_HOSEMANN, 1, true>(q, rf, nd, px, tb, rp, ix, gi, e.n_hkl, sm, pt, t, qn, qd, bq,
+                                                        qk);
         break;
       default:
         adjoint_tile<FDTBX_LINESHAPE_LAUE, 1, true>(q, rf, nd, px, tb, rp, ix, gi, e.n_hkl, sm, pt, t, qn, qd, bq);

@@ -16,12 +16,14 @@ namespace fdtbx {
 // Laue:     S_i (4 pi cos(2 pi y_i) - S_i) prod_{j!=i} S_j^2 with S_i = sin(2 pi y_i)/y_i.
 // Gaussian: Z' (1 - 8 pi y_i^2).
 // Hosemann: Z' (c_i (1 + A_i^2) - 2 A_i)/den_i with c_i = cos(2 pi y_i) (0 where A_i is held at 0).
+// adj_term adds the node's terms at offsets (ya, yb, yc); eval_node_adj tests the support
+// first.  For the Hosemann lineshape with um, nodes in the edge band (lo, hi) are left out and
+// bit jj of *um is set where some lane met one, for the second pass of walk_queue_adj (the two
+// passes of the forward walk).
 template <int LS>
-__device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, float al0, float al1, float al2,
-                                              float half_m, const HoseK& hk, float* acc) {
-  float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
-  float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
-  if (mx <= half_m) {
+__device__ __forceinline__ void adj_term(float ya, float yb, float yc, const float4 nd, const float2 dw,
+                                         const HoseK& hk, float* acc) {
+  {
     if (LS == FDTBX_LINESHAPE_GAUSSIAN) {
       const float P = __builtin_amdgcn_exp2f(kGauss * fmaf(ya, ya, fmaf(yb, yb, yc * yc)));
       acc[0] = fmaf(nd.w, P, acc[0]);
@@ -74,29 +76,61 @@ __device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, 
   }
 }
 
+template <int LS>
+__device__ __forceinline__ void eval_node_adj(const float4 nd, const float2 dw, float al0, float al1, float al2,
+                                              float half_m, const HoseK& hk, float* acc, float lo = 0.0f,
+                                              float hi = 0.0f, int jj = 0, unsigned long long* um = nullptr) {
+  const float ya = al0 - nd.x, yb = al1 - nd.y, yc = al2 - nd.z;
+  const float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
+  bool in = mx <= half_m;
+  if (LS == FDTBX_LINESHAPE_HOSEMANN && um) {
+    in = mx <= lo;
+    const unsigned long long band = __builtin_amdgcn_ballot_w64(mx < hi) & ~__builtin_amdgcn_ballot_w64(in);
+    *um = band ? *um | (1ull << jj) : *um;
+  }
+  if (in) adj_term<LS>(ya, yb, yc, nd, dw, hk, acc);
+}
+
 // Every lane walks the first cnt queue entries, reading entry jj + 1 before evaluating jj.
 // The queue addresses go through threadIdx.y (always 0) so that they stay in vector
 // registers and the unrolled reads use instruction offsets.
 template <int LS>
 __device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* qd, int cnt, const float* al, float half_m,
-                                               const HoseK& hk, float* acc) {
+                                               const HoseK& hk, float* acc, const ProfParams* qe = nullptr,
+                                               const EdgeCtx* ec = nullptr, double R = 0.0, double Z = 0.0) {
+  constexpr bool EDGE = LS == FDTBX_LINESHAPE_HOSEMANN;
+  const float4* const q0 = qn;
+  const float2* const d0 = qd;
   qn += threadIdx.y;
   qd += threadIdx.y;
   float4 nxt = qn[0];
   float2 nxt2 = qd[0];
+  unsigned long long um = 0;
+  const float lo = EDGE && ec ? ec->lo : 0.0f, hi = EDGE && ec ? ec->hi : 0.0f;
   for (int jj = 0; jj < cnt; ++jj) {
     const float4 cur = nxt;
     const float2 cur2 = nxt2;
     nxt = qn[jj + 1];
     nxt2 = qd[jj + 1];
-    eval_node_adj<LS>(cur, cur2, al[0], al[1], al[2], half_m, hk, acc);
+    eval_node_adj<LS>(cur, cur2, al[0], al[1], al[2], half_m, hk, acc, lo, hi, jj, EDGE && ec ? &um : nullptr);
+  }
+  // the second pass: the band's nodes that are inside in binary64 (hose_edge_pass)
+  while (EDGE && ec && um) {  // uniform
+    const int jj = (int)__builtin_ctzll(um);
+    um &= um - 1;
+    const float4 nd = q0[jj];
+    const float ya = al[0] - nd.x, yb = al[1] - nd.y, yc = al[2] - nd.z;
+    const float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
+    if (hose_band(mx, lo, hi) && hose_inside64(*qe, ec->rec, R, Z, ec->qk[jj]))
+      adj_term<LS>(ya, yb, yc, nd, d0[jj], hk, acc);
   }
 }
 
 // One tile t of one model, walked by WAVES 64-lane waves: wave w takes the chunks w,
 // w + WAVES, ... of 64 pairs of the tile's list (each pair's sums go out on their own, so the
 // waves need no combining).  qn, qd: LDS queues of 128 entries per wave; bq: LDS scratch of
-// 64 ints per wave for the block test.
+// 64 ints per wave for the block test; qk (the Hosemann lineshape): the queue's node indices,
+// 128 per wave, for the binary64 support-edge decisions.
 //
 // Each lane holds two pixel weights: gA = L(R) (G of the pixel + G of its left-right mirror,
 // which has the same profile value from the same reflection) and gB = L(R) (G of its up-down
@@ -117,8 +151,10 @@ __device__ __forceinline__ void adjoint_range(const ProfParams& q, const float* 
                                               const double* __restrict__ tile, const int32_t* __restrict__ idx,
                                               const float* __restrict__ grad_image, int64_t n_hkl,
                                               double* __restrict__ sums, float* __restrict__ partials, const int t,
-                                              int64_t from, int64_t p1, int64_t step, float4* qn, float2* qd, int* bq) {
+                                              int64_t from, int64_t p1, int64_t step, float4* qn, float2* qd, int* bq,
+                                              int* qk = nullptr) {
   const int lane = threadIdx.x & 63;
+  constexpr bool EDGE = LS == FDTBX_LINESHAPE_HOSEMANN;
   const int tx = t % q.tiles_x, ty = t / q.tiles_x;
   const int i = (tx << q.tlg) + (lane & ((1 << q.tlg) - 1));
   const int j = ty * (64 >> q.tlg) + (lane >> q.tlg);
@@ -168,6 +204,9 @@ __device__ __forceinline__ void adjoint_range(const ProfParams& q, const float* 
       }
       HoseK hk = {};
       if (LS == FDTBX_LINESHAPE_HOSEMANN) hose_constants(refl + (int64_t)FDTBX_REFL_FLOATS * r, hk);
+      EdgeCtx ec = {};
+      if (EDGE) ec = edge_ctx(refl + (int64_t)FDTBX_REFL_FLOATS * r, box, qk);
+      const EdgeCtx* ecp = EDGE ? &ec : nullptr;
       float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       int qlen = 0, queued = 0;  // uniform
       scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int k, float4 e) {
@@ -176,22 +215,24 @@ __device__ __forceinline__ void adjoint_range(const ProfParams& q, const float* 
           const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
           qn[pos] = LS == FDTBX_LINESHAPE_LAUE ? tag_kappa4(e) : e;
           qd[pos] = *(const float2*)(nodes + (int64_t)FDTBX_NODE_FLOATS * k + 4);
+          if (EDGE) qk[pos] = k;
         }
         qlen += __popcll(b);
         queued += __popcll(b);
         wave_sync();
         if (qlen >= 64) {
-          walk_queue_adj<LS>(qn, qd, 64, al, q.half_m, hk, acc);
+          walk_queue_adj<LS>(qn, qd, 64, al, q.half_m, hk, acc, &q, ecp, R, Z);
           qlen -= 64;
           wave_sync();
           if (lane < qlen) {
             qn[lane] = qn[64 + lane];
             qd[lane] = qd[64 + lane];
+            if (EDGE) qk[lane] = qk[64 + lane];
           }
           wave_sync();
         }
       });
-      walk_queue_adj<LS>(qn, qd, qlen, al, q.half_m, hk, acc);
+      walk_queue_adj<LS>(qn, qd, qlen, al, q.half_m, hk, acc, &q, ecp, R, Z);
       wave_sync();
       if (queued == 0) continue;  // no node within reach of the tile: nothing to add
       // the weighted lane sums are summed over the wave in binary64 (a float times a float is
@@ -239,10 +280,12 @@ __device__ __forceinline__ void adjoint_tile(const ProfParams& q, const float* _
                                              const double* __restrict__ pix, const double* __restrict__ tile,
                                              const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
                                              const float* __restrict__ grad_image, int64_t n_hkl, double* __restrict__ sums,
-                                             float* __restrict__ partials, const int t, float4* qn, float2* qd, int* bq) {
+                                             float* __restrict__ partials, const int t, float4* qn, float2* qd, int* bq,
+                                             int* qk = nullptr) {
   const int wv = WAVES > 1 ? (int)(threadIdx.x >> 6) : 0;
   adjoint_range<LS, PRE>(q, refl, nodes, pix, tile, idx, grad_image, n_hkl, sums, partials, t, offsets[t] + 64 * wv,
-                    offsets[t + 1], 64 * WAVES, qn + 128 * wv, qd + 128 * wv, bq + 64 * wv);
+                    offsets[t + 1], 64 * WAVES, qn + 128 * wv, qd + 128 * wv, bq + 64 * wv,
+                    qk ? qk + 128 * wv : nullptr);
 }
 
 }  // namespace fdtbx

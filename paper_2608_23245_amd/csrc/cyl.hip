@@ -92,7 +92,8 @@ __global__ void __launch_bounds__(64 * WAVES) k_cyl(CylParams p, const float* __
     const float* rec = refl + (int64_t)FDTBX_REFL_FLOATS * r;
     PairRec f;
     load_pair(rec, f);
-    const float4 x1 = *(const float4*)(rec + 36);
+    static_assert(RS_AZ == 31 && RS_TA == 34, "the load below reads slots 32..35 as e_az.e1, e_az.e2, TA_0, TA_1");
+    const float4 x1 = *(const float4*)(rec + 32);
     const float az[3] = {f.at(RS_AZ), x1.x, x1.y};
     const float ta[3] = {x1.z, x1.w, rec[RS_TA + 2]};
     const double RD = f.at_f64(RS_RD), ZD = f.at_f64(RS_ZD);

@@ -153,31 +153,38 @@ __device__ __forceinline__ float wave_sum(float v) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
-// Reflection record slots (float32, FDTBX_REFL_FLOATS per reflection).
+// Reflection record slots (float32, FDTBX_REFL_FLOATS = 64 per reflection: 256 bytes, two
+// 128-byte cache lines).  Slots 0..31 are everything a (tile, reflection) pair of the profile
+// walks reads (one aligned line, loaded whole); the second line holds what only the set-up, the
+// gradient, the Hosemann lineshape and the other launches read.
 enum ReflSlot {
-  RS_W = 0,        // |F|^2 I_para
-  RS_N = 1,        // N_eff a, b, c (1..3)
-  RS_R0 = 4,       // |D|
-  RS_WK = 5,       // W r0^2 N_a N_b N_c / (2 pi)^6: weight of the per-reflection node sum
-  RS_B = 6,        // N_i r0 (a_i.S)/2       (6..8)
-  RS_G1 = 9,       // N_i r0 (a_i.e1)/2      (9..11)
-  RS_G2 = 12,      // N_i r0 (a_i.e2)/2      (12..14)
-  RS_TR = 15,      // N_i (a_i.e_perp)/2     (15..17)
-  RS_TZ = 18,      // N_i a_i,z / 2          (18..20)
-  RS_IP = 21,      // I_para
-  RS_RD = 22,      // D.e_perp as float64 bits (22..23)
-  RS_ZD = 24,      // D_z as float64 bits      (24..25)
-  RS_CS = 26,      // (e_perp.S, S_z)
-  RS_C1 = 28,      // (e_perp.e1, e1_z)
-  RS_C2 = 30,      // (e_perp.e2, e2_z)
-  RS_RHO = 32,     // support extent along S, e1, e2: sum_i (m/N_i)|a*_i.v|  (32..34)
-  RS_AZ = 35,      // e_az.S, e_az.e1, e_az.e2 with e_az = z x e_perp (35..37)
-  RS_TA = 38,      // scale_i (a_i.e_az), the lattice offset along the ring direction (38..40)
-  RS_F2 = 41,      // |F|^2
-  RS_K = 42,       // r0^2 C with C the lineshape's constant (Laue prod N/(2 pi)^6, Gaussian
+  RS_HOT = 0,      // start of the per-pair line (slots 0..31)
+  RS_R0 = 0,       // |D|
+  RS_WK = 1,       // W r0^2 C: weight of the per-reflection node sum (RS_K below)
+  RS_B = 2,        // scale_i r0 (a_i.S)      (2..4)
+  RS_G1 = 5,       // scale_i r0 (a_i.e1)     (5..7)
+  RS_G2 = 8,       // scale_i r0 (a_i.e2)     (8..10)
+  RS_TR = 11,      // scale_i (a_i.e_perp)    (11..13)
+  RS_TZ = 14,      // scale_i a_i,z           (14..16)
+  RS_IP = 17,      // I_para
+  RS_RD = 18,      // D.e_perp as float64 bits (18..19)
+  RS_ZD = 20,      // D_z as float64 bits      (20..21)
+  RS_CS = 22,      // (e_perp.S, S_z)
+  RS_C1 = 24,      // (e_perp.e1, e1_z)
+  RS_C2 = 26,      // (e_perp.e2, e2_z)
+  RS_RHO = 28,     // support extent along S, e1, e2: sum_i w_i |a*_i.v|  (28..30)
+  RS_AZ = 31,      // e_az.S, e_az.e1, e_az.e2 with e_az = z x e_perp (31..33)
+  RS_TA = 34,      // scale_i (a_i.e_az), the lattice offset along the ring direction (34..36)
+  RS_F2 = 37,      // |F|^2
+  RS_K = 38,       // r0^2 C with C the lineshape's constant (Laue prod N/(2 pi)^6, Gaussian
                    // prod N, Hosemann prod (1 - A'^2)), so that RS_WK = W * RS_K
-  RS_AH = 44,      // Hosemann lineshape: A'_i = max(0, (N_i - 1)/(N_i + 1)) (44..46)
-};
+  RS_AH = 40,      // Hosemann lineshape: A'_i = max(0, (N_i - 1)/(N_i + 1)) (40..42)
+  RS_W = 44,       // |F|^2 I_para
+  RS_N = 45,       // N_eff a, b, c (45..47)
+  RS_LO = 48,      // float32 residuals x - (float)x of the binary64 values x of B, G1, G2, TR, TZ
+                   // (48..62, that order): hi + lo holds x to 2^-48 relative, for the Hosemann
+                   // walk's support-edge decisions
+};  // slots 39, 43 and 63 are 0
 
 // Per-axis scale of the lattice offsets y_i in the record (y_i = scale_i a_i.(p - s)) and
 // the support half-width in y: N_i/2 and m/2 for the Laue and Gaussian lineshapes (the

@@ -44,9 +44,11 @@ __global__ void __launch_bounds__(64 * WAVES) __attribute__((amdgpu_waves_per_eu
   __shared__ float4 qn[256 * WAVES];
   __shared__ int bq[64 * WAVES];
   __shared__ float xacc[WAVES > 1 ? 64 * (WAVES - 1) : 1];
+  __shared__ int qk[LS == FDTBX_LINESHAPE_HOSEMANN ? 128 * WAVES : 1];  // node indices (support edge)
   const int t = order ? order[blockIdx.x] : tile_of_block(q, blockIdx.x);
   if (t < 0) return;  // uniform across the workgroup
-  profile_tile<COUNT, LS, WAVES>(q, refl, nodes, pix, tile, offsets, idx, image, counts, t, qn, bq, xacc);
+  profile_tile<COUNT, LS, WAVES>(q, refl, nodes, pix, tile, offsets, idx, image, counts, t, qn, bq, xacc,
+                                 LS == FDTBX_LINESHAPE_HOSEMANN ? qk : nullptr);
 }
 
 template <int WAVES>
@@ -71,7 +73,7 @@ static void launch_profile(const ProfParams& q, dim3 grid, hipStream_t s, const 
 
 // Batched models, persistent: every wave takes (model, tile) items from a shared counter
 // until the list is exhausted (the exit every wave reaches).
-__global__ void __launch_bounds__(64) k_b_profile(const fdtbx_batch_entry* __restrict__ ent, const int64_t* __restrict__ items,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(6))) k_b_profile(const fdtbx_batch_entry* __restrict__ ent, const int64_t* __restrict__ items,
                                                   int64_t n_items, const float* __restrict__ refl,
                                                   const float* __restrict__ nodes, const double* __restrict__ pix,
                                                   const double* __restrict__ tile, const int64_t* __restrict__ rowptr,
@@ -79,6 +81,7 @@ __global__ void __launch_bounds__(64) k_b_profile(const fdtbx_batch_entry* __res
                                                   unsigned long long* __restrict__ counter) {
   __shared__ float4 qn[128];
   __shared__ int bq[64];
+  __shared__ int qk[128];  // node indices of the queue (the Hosemann support edge)
   for (;;) {
     const int64_t it = next_item(counter);
     if (it >= n_items) break;
@@ -100,7 +103,8 @@ __global__ void __launch_bounds__(64) k_b_profile(const fdtbx_batch_entry* __res
         profile_tile<false, FDTBX_LINESHAPE_GAUSSIAN, 1, true, false>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
         break;
       case FDTBX_LINESHAPE_HOSEMANN:
-        profile_tile<false, FDTBX_LINESHAPE_HOSEMANN, 1, true, false>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
+        profile_tile<false, FDTBX_LINESHAPE_HOSEMANN, 1, true, false>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq,
+                                                                      nullptr, qk);
         break;
       default:
         profile_tile<false, FDTBX_LINESHAPE_LAUE, 1, true, false>(q, rf, nd, px, tb, rp, ix, im, nullptr, t, qn, bq);
@@ -154,6 +158,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
                                                        float* __restrict__ partials) {
   __shared__ float4 qn[256 * 4];
   __shared__ int bq[64 * 4];
+  __shared__ int qk[LS == FDTBX_LINESHAPE_HOSEMANN ? 128 * 4 : 1];  // node indices (support edge)
   const int wv = (int)(threadIdx.x >> 6), lane = (int)(threadIdx.x & 63);
   const int64_t U = T.meta[1];
   const int64_t total = U > 0 ? min(T.meta[0], T.max_units) : 0;
@@ -173,7 +178,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) k
       const TilePixel px = tile_pixel(q, pix, tile, t, lane);
       unsigned long long cnt = 0;
       partials[u * 64 + lane] = pairs_sum<false, LS>(q, refl, nodes, idx, px.box, px.R, px.Z, p0, p1, 64,
-                                                     qn + 256 * wv, bq + 64 * wv, cnt);
+                                                     qn + 256 * wv, bq + 64 * wv, cnt,
+                                                     LS == FDTBX_LINESHAPE_HOSEMANN ? qk + 128 * wv : nullptr);
     }
   }
 }
@@ -221,7 +227,7 @@ int launch_batch_profile(const fdtbx_batch_entry* ent, const int64_t* items, int
 // when it is launched) of tile column sx; its box, row pointers and list start at the model's
 // offsets in soff ([m][3]: first box, first row pointer, first list entry; the row pointers are
 // relative to the model's first list entry).
-__global__ void __launch_bounds__(64) k_b_profile_stacked(const fdtbx_batch_entry* __restrict__ ent,
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(5))) k_b_profile_stacked(const fdtbx_batch_entry* __restrict__ ent,
                                                           const int64_t* __restrict__ soff,
                                                           const int64_t* __restrict__ items, int64_t n_items,
                                                           const float* __restrict__ refl,
@@ -234,6 +240,7 @@ __global__ void __launch_bounds__(64) k_b_profile_stacked(const fdtbx_batch_entr
                                                           unsigned long long* __restrict__ counter) {
   __shared__ float4 qn[128];
   __shared__ int bq[64];
+  __shared__ int qk[128];  // node indices of the queue (the Hosemann support edge)
   const int lane = threadIdx.x & 63;
   for (;;) {
     const int64_t it = next_item(counter);
@@ -272,7 +279,7 @@ __global__ void __launch_bounds__(64) k_b_profile_stacked(const fdtbx_batch_entr
         break;
       case FDTBX_LINESHAPE_HOSEMANN:
         pairs_sum_stacked<FDTBX_LINESHAPE_HOSEMANN>(q, rf, nd, ix, box, pa.R, pa.Z, pb.R, pb.Z, p0, p1, qn, bq, &sa,
-                                                    &sb);
+                                                    &sb, qk);
         break;
       default:
         pairs_sum_stacked<FDTBX_LINESHAPE_LAUE>(q, rf, nd, ix, box, pa.R, pa.Z, pb.R, pb.Z, p0, p1, qn, bq, &sa,

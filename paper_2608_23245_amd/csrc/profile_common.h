@@ -25,6 +25,7 @@ struct ProfParams {
   float margin;     // slack of the tile-level node test, in y units
   double delta;     // Lorentz regulariser
   int32_t sbw;      // superblocks per tile row in the XCD-aware tile order; 0: plain order
+  double T64, h64;  // grid half extent and spacing in binary64 (the Hosemann walk's edge decisions)
 };
 
 // Tile order of the per-tile launches.  Workgroups are dealt to the 8 XCDs in round-robin
@@ -116,18 +117,19 @@ struct Window {
   int i1lo, i1hi, i2lo, i2hi;
 };
 
-// Record slots 4..35 of one reflection (everything a (tile, reflection) pair reads), loaded
-// with one batch of 16-byte loads so that a pair waits for memory once.
+// The per-pair line of one reflection's record (slots RS_HOT..RS_HOT + 31, everything a
+// (tile, reflection) pair reads), loaded with one batch of 16-byte loads so that a pair waits
+// for memory once.
 struct PairRec {
   float v[32];
-  __device__ float at(int slot) const { return v[slot - 4]; }
+  __device__ float at(int slot) const { return v[slot - RS_HOT]; }
   __device__ double at_f64(int slot) const {
-    return __hiloint2double(__float_as_int(v[slot - 3]), __float_as_int(v[slot - 4]));
+    return __hiloint2double(__float_as_int(v[slot - RS_HOT + 1]), __float_as_int(v[slot - RS_HOT]));
   }
 };
 
 __device__ __forceinline__ void load_pair(const float* __restrict__ rec, PairRec& f) {
-  const float4* r4 = (const float4*)(rec + 4);
+  const float4* r4 = (const float4*)(rec + RS_HOT);
 #pragma unroll
   for (int k = 0; k < 8; ++k) {
     const float4 x = r4[k];
@@ -212,13 +214,18 @@ template <bool PRE>
 __device__ static inline bool pair_setup(const ProfParams& q, const float* __restrict__ rec,
                                          const float* __restrict__ nodes, const TileBox& b, int* w01, int* w23,
                                          float* lo, float* hi, float* fl = nullptr, float* fh = nullptr) {
-  const float4 x0 = *(const float4*)(rec + 4);
-  const float4 x3 = *(const float4*)(rec + 12);
-  const float4 x4 = *(const float4*)(rec + 16);
-  const float4 x5 = *(const float4*)(rec + 20);
-  const float4 x6 = *(const float4*)(rec + 24);
-  const float4 x7 = *(const float4*)(rec + 28);
-  const float4 x8 = *(const float4*)(rec + 32);
+  // xj: slots RS_HOT + 4j .. + 4j + 3 of the per-pair line
+  const float4 x0 = *(const float4*)(rec + RS_HOT);
+  const float4 x3 = *(const float4*)(rec + RS_HOT + 8);
+  const float4 x4 = *(const float4*)(rec + RS_HOT + 12);
+  const float4 x5 = *(const float4*)(rec + RS_HOT + 16);
+  const float4 x6 = *(const float4*)(rec + RS_HOT + 20);
+  const float4 x7 = *(const float4*)(rec + RS_HOT + 24);
+  const float4 x8 = *(const float4*)(rec + RS_HOT + 28);
+  static_assert(RS_R0 == RS_HOT && RS_B == RS_HOT + 2 && RS_G1 == RS_HOT + 5 && RS_G2 == RS_HOT + 8 &&
+                    RS_TR == RS_HOT + 11 && RS_TZ == RS_HOT + 14 && RS_RD == RS_HOT + 18 && RS_ZD == RS_HOT + 20 &&
+                    RS_CS == RS_HOT + 22 && RS_C1 == RS_HOT + 24 && RS_C2 == RS_HOT + 26 && RS_RHO == RS_HOT + 28,
+                "the loads below read the record by these positions");
   const float tr[3] = {x3.w, x4.x, x4.y}, tz[3] = {x4.z, x4.w, x5.x};
   const double RD = __hiloint2double(__float_as_int(x5.w), __float_as_int(x5.z));
   const double ZD = __hiloint2double(__float_as_int(x6.y), __float_as_int(x6.x));
@@ -252,7 +259,7 @@ __device__ static inline bool pair_setup(const ProfParams& q, const float* __res
   constexpr int NB = FDTBX_NODE_BLOCK;
   const int b1lo = w.i1lo / NB, b1hi = w.i1hi / NB, b2lo = w.i2lo / NB, b2hi = w.i2hi / NB;
   if (PRE && (b1hi - b1lo + 1) * (b2hi - b2lo + 1) <= kPreBlocks) {
-    const float4 x1 = *(const float4*)(rec + 8);
+    const float4 x1 = *(const float4*)(rec + RS_HOT + 4);
     const float Bv[3] = {x0.z, x0.w, x1.x}, G1[3] = {x1.y, x1.z, x1.w}, G2[3] = {x3.x, x3.y, x3.z};
     float sl3[3];
 #pragma unroll
@@ -535,6 +542,8 @@ __host__ __device__ inline void prof_params(const fdtbx_model* model, ProfParams
   q->margin = 1.0e-3f;
   q->delta = model->quad.delta;
   q->sbw = superblocks_per_row(q->lcols, q->lrows);
+  q->T64 = model->quad.T;
+  q->h64 = 2.0 * model->quad.T / model->quad.n_nodes;
 }
 
 }  // namespace fdtbx

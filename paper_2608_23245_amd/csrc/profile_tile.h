@@ -87,36 +87,155 @@ __device__ __forceinline__ void eval_node(const float4 nd, float al0, float al1,
   }
 }
 
+// The Hosemann support edge.  The Hosemann factor does not vanish at |y| = 1/2, the edge of
+// its one-period support, so where float32 and binary64 disagree on the side of the edge a node
+// lies on, the pixel gains or loses that node's whole term.  A node whose float32 max_i |y_i| lies
+// within the pair's edge band of the edge is decided again in binary64: the record's
+// coefficients as hi + lo (float32 slot and residual, RS_LO: 2^-48 relative), the node's
+// offsets recomputed from its index as the node table defines them, and the lane's binary64
+// R - R_D, Z - Z_D.  The band bounds the float32 error of
+// y_i = T_R,i dR + T_Z,i dZ - (B_i (c - 1) + G1_i c d1 + G2_i c d2), |c - 1| and |c d| <= 1,
+// formed from float32 values with about six roundings, each within 2^-24 of
+// mag_i = |T_R,i| max|dR| + |T_Z,i| max|dZ| + |B_i| + |G1_i| + |G2_i| (max over the tile's box):
+// the band is 2^-20 max_i mag_i (16 such roundings), and never below 1e-6.  A node with
+// mx = max_i |y_i| <= lo = 1/2 - band (in float32) is inside; one with lo < mx < hi = 1/2 + band
+// is decided in binary64; the others are outside.  The context is uniform across the wave; the
+// terms stay float32.
+struct EdgeCtx {
+  const float* rec;  // the pair's reflection record
+  float lo, hi;      // the edge band's bounds on mx
+  const int* qk;     // node index of each entry of the queue being walked
+};
+
+__device__ __forceinline__ EdgeCtx edge_ctx(const float* __restrict__ rec, const TileBox& box, const int* qk) {
+  EdgeCtx ec;
+  ec.rec = rec;
+  const double RD = *(const double*)(rec + RS_RD), ZD = *(const double*)(rec + RS_ZD);
+  const float mR = (float)fmax(fabs(box.Rlo - RD), fabs(box.Rhi - RD));
+  const float mZ = (float)fmax(fabs(box.Zlo - ZD), fabs(box.Zhi - ZD));
+  float mag = 0.0f;
+  for (int a = 0; a < 3; ++a)
+    mag = fmaxf(mag, fabsf(rec[RS_TR + a]) * mR + fabsf(rec[RS_TZ + a]) * mZ + fabsf(rec[RS_B + a]) +
+                         fabsf(rec[RS_G1 + a]) + fabsf(rec[RS_G2 + a]));
+  const float band = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(fmaxf(1.0e-6f, mag * 0x1p-20f))));
+  ec.lo = 0.5f - band;
+  ec.hi = 0.5f + band;
+  ec.qk = qk;
+  return ec;
+}
+
+// Whether node k is inside the support (every |u_i| <= half_m) in binary64 at the pixel (R, Z).
+// The node's offsets are formed as the node table defines them, with c = 1/sqrt(1 + rho^2)
+// from the binary64 reciprocal square root (within a few units in the last place) and c - 1
+// formed directly: its absolute error, about 1e-16, is all that enters u.
+__device__ __forceinline__ bool hose_inside64(const ProfParams& q, const float* rec, double R, double Z, int k) {
+  // coefficient c of axis a (c = 0..4: B, G1, G2, TR, TZ) as hi + lo
+  auto x64 = [&](int ca) { return (double)rec[RS_B + ca] + (double)rec[RS_LO + ca]; };
+  const double dR = R - *(const double*)(rec + RS_RD), dZ = Z - *(const double*)(rec + RS_ZD);
+  int i1, i2;
+  window_node(k, q.n, __builtin_amdgcn_rcpf((float)q.n), &i1, &i2);
+  const double d1 = -q.T64 + ((double)i1 + 0.5) * q.h64, d2 = -q.T64 + ((double)i2 + 0.5) * q.h64;
+  const double c = rsqrt(fma(d1, d1, fma(d2, d2, 1.0)));
+  const double cm1 = c - 1.0, cd1 = c * d1, cd2 = c * d2;
+  bool in = true;
+#pragma unroll 1
+  for (int a = 0; a < 3; ++a) {
+    const double kap = fma(x64(a), cm1, fma(x64(3 + a), cd1, x64(6 + a) * cd2));
+    const double al = fma(x64(9 + a), dR, x64(12 + a) * dZ);
+    in = in && fabs(al - kap) <= (double)q.half_m;
+  }
+  return in;
+}
+
+// The Hosemann profile product at offsets (ya, yb, yc), before the node weight, as eval_node
+// forms it.
+__device__ __forceinline__ float hose_prod(float ya, float yb, float yc, const HoseK& hk) {
+  const float da = fmaf(-hk.c1[0], __builtin_amdgcn_cosf(ya), hk.c0[0]);
+  const float db = fmaf(-hk.c1[1], __builtin_amdgcn_cosf(yb), hk.c0[1]);
+  const float dc = fmaf(-hk.c1[2], __builtin_amdgcn_cosf(yc), hk.c0[2]);
+  return __builtin_amdgcn_rcpf(da * db * dc);
+}
+
+// The Hosemann walks in two passes.  The walk proper (eval_node_hose_main, queue entry jj) adds
+// the nodes with mx <= lo and leaves out those in the band, setting bit jj of the wave's mask
+// um where some lane met one; a second pass over the entries of um (hose_edge_pass) adds those
+// whose binary64 decision is inside.  The double-precision work stays out of the walk's loop.
+__device__ __forceinline__ bool hose_band(float mx, float lo, float hi) { return !(mx <= lo) && mx < hi; }
+
+__device__ __forceinline__ void eval_node_hose_main(const float4 nd, const float* al, float lo, float hi,
+                                                    const HoseK& hk, float& accr, int jj, unsigned long long& um) {
+  const float ya = al[0] - nd.x, yb = al[1] - nd.y, yc = al[2] - nd.z;
+  const float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
+  const bool sure = mx <= lo;
+  // the band's lanes as (mx < hi) and not sure: two compares, the rest scalar
+  const unsigned long long band = __builtin_amdgcn_ballot_w64(mx < hi) & ~__builtin_amdgcn_ballot_w64(sure);
+  um = band ? um | (1ull << jj) : um;
+  if (sure) accr = fmaf(nd.w, hose_prod(ya, yb, yc, hk), accr);
+}
+
+// The second pass: the entries um of the queue qn (node indices ec.qk) at the pixel (R, Z)
+// with offsets al; adds the terms of the band's nodes that are inside in binary64.
+__device__ __forceinline__ void hose_edge_pass(const ProfParams& q, const float4* qn, unsigned long long um,
+                                               const float* al, const HoseK& hk, const EdgeCtx& ec, double R,
+                                               double Z, float& accr) {
+  float part = 0.0f;
+  while (um) {  // uniform
+    const int jj = (int)__builtin_ctzll(um);
+    um &= um - 1;
+    const float4 nd = qn[jj];
+    const float ya = al[0] - nd.x, yb = al[1] - nd.y, yc = al[2] - nd.z;
+    const float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
+    if (hose_band(mx, ec.lo, ec.hi) && hose_inside64(q, ec.rec, R, Z, ec.qk[jj]))
+      part = fmaf(nd.w, hose_prod(ya, yb, yc, hk), part);
+  }
+  accr += part;
+}
+
 // The walk of one wave's node queue (128 entries of LDS; see pairs_sum below).
 // Every lane walks the first cnt queue entries; the read of entry jj + 1 is issued before
 // entry jj is evaluated (the buffer holds 128 entries, cnt <= 64, so it stays in bounds).
 // The queue is addressed from threadIdx.y (always 0: the launches are one-dimensional), which
 // keeps its address in a vector register; the unrolled reads then use instruction offsets
 // instead of moving a scalar loop counter into a vector register for every entry.
+// With an edge context (the Hosemann lineshape's tested walks) the support edge is decided in
+// the two passes above for the pixel (R, Z); ec->qk is then the queue's node indices.
 template <bool COUNT, int LS, bool TEST = true>
 __device__ __forceinline__ void walk_queue(const float4* qn, int cnt, const float* al, float half_m,
-                                           const HoseK& hk, float& accr, unsigned long long& cnt_eval) {
+                                           const HoseK& hk, float& accr, unsigned long long& cnt_eval,
+                                           const ProfParams* qe = nullptr, const EdgeCtx* ec = nullptr,
+                                           double R = 0.0, double Z = 0.0) {
+  constexpr bool EDGE = LS == FDTBX_LINESHAPE_HOSEMANN && TEST && !COUNT;
+  const float4* const q0 = qn;
   qn += threadIdx.y;
   float4 nxt = qn[0];
   float part = 0.0f;  // a block sum of at most 64 terms, added once: keeps long sums accurate
+  unsigned long long um = 0;
+  const float lo = EDGE && ec ? ec->lo : 0.0f, hi = EDGE && ec ? ec->hi : 0.0f;
   for (int jj = 0; jj < cnt; ++jj) {
     const float4 cur = nxt;
     nxt = qn[jj + 1];
-    eval_node<COUNT, LS, TEST>(cur, al[0], al[1], al[2], half_m, hk, part, cnt_eval);
+    if (EDGE && ec)
+      eval_node_hose_main(cur, al, lo, hi, hk, part, jj, um);
+    else
+      eval_node<COUNT, LS, TEST>(cur, al[0], al[1], al[2], half_m, hk, part, cnt_eval);
     // without the support test the unrolled entries form one block, which the scheduler would
     // interleave at the cost of registers (and occupancy); keep each entry's arithmetic together
     if (!TEST) __builtin_amdgcn_sched_barrier(0);
   }
   accr += part;
+  if (EDGE && ec && um) hose_edge_pass(*qe, q0, um, al, hk, *ec, R, Z, accr);
 }
 
 // Appends the lanes' candidates (keep) to a queue of len entries at qn (len is uniform).
+// With qk, node index k goes to the same position of qk.
 template <int LS>
-__device__ __forceinline__ void queue_append(float4* qn, int& len, bool keep, float4 e) {
+__device__ __forceinline__ void queue_append(float4* qn, int& len, bool keep, float4 e, int* qk = nullptr,
+                                             int k = 0) {
   const unsigned long long b = __ballot(keep);
   if (keep) {
     const int pos = len + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(b >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)b, 0u));
     qn[pos] = LS == FDTBX_LINESHAPE_LAUE ? tag_kappa4(e) : e;
+    if (qk) qk[pos] = k;
   }
   len += __popcll(b);
 }
@@ -125,13 +244,18 @@ __device__ __forceinline__ void queue_append(float4* qn, int& len, bool keep, fl
 // to the front).
 template <bool COUNT, int LS, bool TEST>
 __device__ __forceinline__ void queue_flush(float4* qn, int& len, const float* al, float half_m, const HoseK& hk,
-                                            float& accr, unsigned long long& cnt) {
+                                            float& accr, unsigned long long& cnt, const ProfParams* qe = nullptr,
+                                            const EdgeCtx* ec = nullptr, int* qk = nullptr, double R = 0.0,
+                                            double Z = 0.0) {
   if (len >= 64) {
     const int lane = threadIdx.x & 63;
-    walk_queue<COUNT, LS, TEST>(qn, 64, al, half_m, hk, accr, cnt);
+    walk_queue<COUNT, LS, TEST>(qn, 64, al, half_m, hk, accr, cnt, qe, ec, R, Z);
     len -= 64;
     wave_sync();
-    if (lane < len) qn[lane] = qn[64 + lane];
+    if (lane < len) {
+      qn[lane] = qn[64 + lane];
+      if (qk) qk[lane] = qk[64 + lane];
+    }
     wave_sync();
   }
 }
@@ -150,8 +274,10 @@ template <bool COUNT, int LS, bool PRE = false, bool SPLIT = !COUNT>
 __device__ __forceinline__ float pairs_sum(const ProfParams& q, const float* __restrict__ refl,
                                            const float* __restrict__ nodes, const int32_t* __restrict__ idx,
                                            const TileBox& box, double R, double Z, int64_t from, int64_t p1,
-                                           int64_t step, float4* qn, int* bq, unsigned long long& cnt) {
+                                           int64_t step, float4* qn, int* bq, unsigned long long& cnt,
+                                           int* qk = nullptr) {
   static_assert(!(SPLIT && COUNT), "the counting pass tests every node");
+  constexpr bool EDGE = LS == FDTBX_LINESHAPE_HOSEMANN && !COUNT;
   const int lane = threadIdx.x & 63;
   float acc = 0.0f;
   for (int64_t base = from; base < p1; base += step) {
@@ -189,25 +315,31 @@ __device__ __forceinline__ float pairs_sum(const ProfParams& q, const float* __r
       }
       HoseK hk = {};
       if (LS == FDTBX_LINESHAPE_HOSEMANN && !COUNT) hose_constants(refl + (int64_t)FDTBX_REFL_FLOATS * r, hk);
+      // the Hosemann support edge is decided in binary64 (hose_edge_pass): the tested queue
+      // then carries its node indices in qk
+      EdgeCtx ec = {};
+      if (EDGE) ec = edge_ctx(refl + (int64_t)FDTBX_REFL_FLOATS * r, box, qk);
+      const EdgeCtx* ecp = EDGE ? &ec : nullptr;
+      int* qkp = EDGE ? qk : nullptr;
       float accr = 0.0f;
       int qlen = 0, flen = 0;  // uniform
       // candidates go to the LDS queues; every 64 queued nodes are walked by all lanes
-      scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int, float4 e) {
+      scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int k, float4 e) {
         if (SPLIT) {
           const bool full = keep && e.x >= fl[0] && e.x <= fh[0] && e.y >= fl[1] && e.y <= fh[1] && e.z >= fl[2] &&
                             e.z <= fh[2];
           queue_append<LS>(qn + 128, flen, full, e);
-          queue_append<LS>(qn, qlen, keep && !full, e);
+          queue_append<LS>(qn, qlen, keep && !full, e, qkp, k);
           wave_sync();
           queue_flush<COUNT, LS, false>(qn + 128, flen, al, q.half_m, hk, accr, cnt);
         } else {
-          queue_append<LS>(qn, qlen, keep, e);
+          queue_append<LS>(qn, qlen, keep, e, qkp, k);
           wave_sync();
         }
-        queue_flush<COUNT, LS, true>(qn, qlen, al, q.half_m, hk, accr, cnt);
+        queue_flush<COUNT, LS, true>(qn, qlen, al, q.half_m, hk, accr, cnt, &q, ecp, qkp, R, Z);
       });
       if (SPLIT) walk_queue<COUNT, LS, false>(qn + 128, flen, al, q.half_m, hk, accr, cnt);
-      walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, hk, accr, cnt);
+      walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, hk, accr, cnt, &q, ecp, R, Z);
       wave_sync();
       if (!COUNT) acc = fmaf(f.at(RS_WK), accr, acc);
     }
@@ -217,21 +349,33 @@ __device__ __forceinline__ float pairs_sum(const ProfParams& q, const float* __r
 
 // The walk of walk_queue for a lane holding two pixels (al, bl: their tagged alpha): each
 // entry is tested and evaluated for both, with a block sum each.
+// For the Hosemann lineshape the support edge is decided in the two passes of walk_queue (ec,
+// the pair's edge context, and the pixels (RA, ZA) and (RB, ZB)).
 template <int LS>
-__device__ __forceinline__ void walk_queue2(const float4* qn, int cnt, const float* al, const float* bl,
-                                            float half_m, const HoseK& hk, float& acca, float& accb) {
+__device__ __forceinline__ void walk_queue2(const ProfParams& q, const float4* qn, int cnt, const float* al,
+                                            const float* bl, const HoseK& hk, const EdgeCtx& ec, double RA,
+                                            double ZA, double RB, double ZB, float& acca, float& accb) {
+  constexpr bool EDGE = LS == FDTBX_LINESHAPE_HOSEMANN;
+  const float4* const q0 = qn;
   qn += threadIdx.y;
   float4 nxt = qn[0];
   float pa = 0.0f, pb = 0.0f;
-  unsigned long long none = 0;
+  unsigned long long none = 0, ua = 0, ub = 0;  // ua, ub: the edge masks of the two pixels
   for (int jj = 0; jj < cnt; ++jj) {
     const float4 cur = nxt;
     nxt = qn[jj + 1];
-    eval_node<false, LS>(cur, al[0], al[1], al[2], half_m, hk, pa, none);
-    eval_node<false, LS>(cur, bl[0], bl[1], bl[2], half_m, hk, pb, none);
+    if (EDGE) {
+      eval_node_hose_main(cur, al, ec.lo, ec.hi, hk, pa, jj, ua);
+      eval_node_hose_main(cur, bl, ec.lo, ec.hi, hk, pb, jj, ub);
+    } else {
+      eval_node<false, LS>(cur, al[0], al[1], al[2], q.half_m, hk, pa, none);
+      eval_node<false, LS>(cur, bl[0], bl[1], bl[2], q.half_m, hk, pb, none);
+    }
   }
   acca += pa;
   accb += pb;
+  if (EDGE && ua) hose_edge_pass(q, q0, ua, al, hk, ec, RA, ZA, acca);
+  if (EDGE && ub) hose_edge_pass(q, q0, ub, bl, hk, ec, RB, ZB, accb);
 }
 
 // pairs_sum for a stacked tile: two vertically adjacent tiles walked by one wave, lane l
@@ -245,8 +389,9 @@ __device__ __forceinline__ void pairs_sum_stacked(const ProfParams& q, const flo
                                                   const float* __restrict__ nodes, const int32_t* __restrict__ idx,
                                                   const TileBox& box, double RA, double ZA, double RB, double ZB,
                                                   int64_t from, int64_t p1, float4* qn, int* bq, float* sa,
-                                                  float* sb) {
+                                                  float* sb, int* qk = nullptr) {
   const int lane = threadIdx.x & 63;
+  constexpr bool EDGE = LS == FDTBX_LINESHAPE_HOSEMANN;
   float acca = 0.0f, accb = 0.0f;
   for (int64_t base = from; base < p1; base += 64) {
     int32_t rl = 0;
@@ -286,20 +431,26 @@ __device__ __forceinline__ void pairs_sum_stacked(const ProfParams& q, const flo
       }
       HoseK hk = {};
       if (LS == FDTBX_LINESHAPE_HOSEMANN) hose_constants(refl + (int64_t)FDTBX_REFL_FLOATS * r, hk);
+      EdgeCtx ec = {};
+      if (EDGE) ec = edge_ctx(refl + (int64_t)FDTBX_REFL_FLOATS * r, box, qk);
+      int* qkp = EDGE ? qk : nullptr;
       float ra = 0.0f, rb = 0.0f;
       int qlen = 0;  // uniform
-      scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int, float4 e) {
-        queue_append<LS>(qn, qlen, keep, e);
+      scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int k, float4 e) {
+        queue_append<LS>(qn, qlen, keep, e, qkp, k);
         wave_sync();
         if (qlen >= 64) {
-          walk_queue2<LS>(qn, 64, al, bl, q.half_m, hk, ra, rb);
+          walk_queue2<LS>(q, qn, 64, al, bl, hk, ec, RA, ZA, RB, ZB, ra, rb);
           qlen -= 64;
           wave_sync();
-          if (lane < qlen) qn[lane] = qn[64 + lane];
+          if (lane < qlen) {
+            qn[lane] = qn[64 + lane];
+            if (EDGE) qk[lane] = qk[64 + lane];
+          }
           wave_sync();
         }
       });
-      walk_queue2<LS>(qn, qlen, al, bl, q.half_m, hk, ra, rb);
+      walk_queue2<LS>(q, qn, qlen, al, bl, hk, ec, RA, ZA, RB, ZB, ra, rb);
       wave_sync();
       acca = fmaf(f.at(RS_WK), ra, acca);
       accb = fmaf(f.at(RS_WK), rb, accb);
@@ -335,23 +486,25 @@ __device__ __forceinline__ TilePixel tile_pixel(const ProfParams& q, const doubl
 
 // WAVES waves share a tile: wave w takes the chunks w, w + WAVES, ... of 64 pairs of the
 // tile's list (its own LDS queues: qn + 256 w, bq + 64 w; 128 float4 per wave suffice
-// without SPLIT), and wave 0 adds the others' pixel sums (xacc, 64 floats per extra wave) in
-// wave order before it writes the tile.
+// without SPLIT; for the Hosemann lineshape also qk + 128 w, the node indices of the tested
+// queue), and wave 0 adds the others' pixel sums (xacc, 64 floats per extra wave) in wave
+// order before it writes the tile.
 template <bool COUNT, int LS, int WAVES = 1, bool PRE = false, bool SPLIT = !COUNT>
 __device__ __forceinline__ void profile_tile(const ProfParams& q, const float* __restrict__ refl,
                                              const float* __restrict__ nodes, const double* __restrict__ pix,
                                              const double* __restrict__ tile, const int64_t* __restrict__ offsets,
                                              const int32_t* __restrict__ idx, float* __restrict__ image,
                                              unsigned long long* __restrict__ counts, const int t, float4* qn, int* bq,
-                                             float* xacc = nullptr) {
+                                             float* xacc = nullptr, int* qk = nullptr) {
   const int lane = threadIdx.x & 63;
   const int wv = WAVES > 1 ? (int)(threadIdx.x >> 6) : 0;
   qn += 256 * wv;
   bq += 64 * wv;
+  if (qk) qk += 128 * wv;
   const TilePixel px = tile_pixel(q, pix, tile, t, lane);
   unsigned long long cnt = 0;
   float acc = pairs_sum<COUNT, LS, PRE, SPLIT>(q, refl, nodes, idx, px.box, px.R, px.Z, offsets[t] + 64 * wv,
-                                              offsets[t + 1], 64 * WAVES, qn, bq, cnt);
+                                              offsets[t + 1], 64 * WAVES, qn, bq, cnt, qk);
   if (COUNT) {
     for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
     if (lane == 0 && cnt) atomicAdd(counts, cnt);

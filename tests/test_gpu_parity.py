@@ -239,17 +239,51 @@ def test_reflection_records(name):
     assert np.array_equal(cull.cpu().numpy()[:, :13], rb)
     P = O.prepare(wl, hkl=hkl, F=np.sqrt(F2.astype(np.float64)).astype(complex), cull_extinct=False)
     raw = refl.cpu().numpy()
-    r = raw[:, :22].astype(np.float64)  # the float32 fields (22.. hold binary64 pairs)
-    np.testing.assert_allclose(r[:, 0], P.W, rtol=2e-6)
-    np.testing.assert_allclose(r[:, 1:4], P.N, rtol=2e-6)
-    np.testing.assert_allclose(r[:, 4], P.r0, rtol=2e-7)
+    assert raw.shape[1] == 64
+    np.testing.assert_allclose(raw[:, 44].astype(np.float64), P.W, rtol=2e-6)
+    np.testing.assert_allclose(raw[:, 45:48].astype(np.float64), P.N, rtol=2e-6)
+    np.testing.assert_allclose(raw[:, 0].astype(np.float64), P.r0, rtol=2e-7)
+    assert np.all(raw[:, [39, 43, 63]] == 0.0)
     # the two binary64 fields behind the kernels' cancellation-free offsets R - R_D and Z - Z_D
-    # (record floats 22..23: D.e_perp, 24..25: D_z, each a little-endian float64), bit for bit:
+    # (record floats 18..19: D.e_perp, 20..21: D_z, each a little-endian float64), bit for bit:
     # D = h a* + k b* + l c* and e_perp (reading R6) in the oracle's operation order
-    f64 = np.ascontiguousarray(raw[:, 22:26]).view(np.float64)
+    f64 = np.ascontiguousarray(raw[:, 18:22]).view(np.float64)
     RD = (P.D[:, 0] * P.ep[:, 0] + P.D[:, 1] * P.ep[:, 1]) + P.D[:, 2] * P.ep[:, 2]
     assert np.array_equal(f64[:, 0], RD), int(np.sum(f64[:, 0] != RD))
     assert np.array_equal(f64[:, 1], P.D[:, 2])
+    check_offset_coefficients(raw, P, wl.dis.lineshape)
+
+
+def check_offset_coefficients(raw, P, lineshape):
+    """The float32 residuals (record floats 48..62) of the offset coefficients B, G1, G2, T_R,
+    T_Z (floats 2..16): each is within half a float32 unit of its coefficient's last place (a
+    residual, not a second copy), float 63 is 0, and for the Hosemann lineshape (offsets
+    y_i = u_i = a_i.(p - s)) hi + lo is the oracle's r0 a_i.S, r0 a_i.e1, r0 a_i.e2, a_i.e_perp
+    and a_i,z to 2^-47 relative."""
+    hi = raw[:, 2:17].astype(np.float64)
+    lo = raw[:, 48:63].astype(np.float64)
+    assert np.all(np.abs(lo) <= 0.5 * np.spacing(np.abs(raw[:, 2:17])).astype(np.float64))
+    assert np.all(raw[:, 63] == 0.0)
+    if lineshape != 2:
+        return
+    a = P.avec
+    want = np.concatenate([P.r0[:, None] * (P.S @ a.T), P.r0[:, None] * (P.e1 @ a.T), P.r0[:, None] * (P.e2 @ a.T),
+                           P.ep @ a.T, np.broadcast_to(a[:, 2], (P.r0.shape[0], 3))], axis=1)
+    scale = np.abs(want).max(axis=1, keepdims=True)
+    err = np.abs(hi + lo - want)
+    assert np.all(err <= 2.0 ** -47 * scale), float((err / scale).max())
+    # the float32 slot alone is off by up to 2^-25 relative: the residual carries the rest
+    assert float((np.abs(hi - want) / scale).max()) > 2.0 ** -40
+
+
+def test_reflection_records_hosemann():
+    wl = W.with_disorder(W.config0(), lineshape=2)
+    say("reflection records, config 0 with the Hosemann lineshape: the offset coefficients' residuals")
+    hkl = O.enumerate_hkl(wl.cell, wl.quad.d_min, wl.quad.d_max)
+    F2 = np.linspace(1.0, 2.0, hkl.shape[0]).astype(np.float32)
+    refl, _ = B.reflection_prep(B.make_model(wl), torch.from_numpy(hkl).cuda(), torch.from_numpy(F2).cuda())
+    P = O.prepare(wl, hkl=hkl, F=np.sqrt(F2.astype(np.float64)).astype(complex), cull_extinct=False)
+    check_offset_coefficients(refl.cpu().numpy(), P, 2)
 
 
 @pytest.mark.parametrize("name", list(SMALL) + ["config0", "config1_sample"])
