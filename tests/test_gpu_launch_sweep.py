@@ -63,7 +63,8 @@ def random_case(seed):
     return dataclasses.replace(wl, geom=geom), int(fold) | (2 if updown else 0)
 
 
-@pytest.mark.parametrize("seed", range(40))
+# seed 7660: an 8x8 detector that none of the 18 reflections reaches (the oracle's image is 0)
+@pytest.mark.parametrize("seed", list(range(40)) + [7660])
 def test_random_launch_vs_oracle(seed):
     wl, fold = random_case(seed)
     g = wl.geom
@@ -75,12 +76,15 @@ def test_random_launch_vs_oracle(seed):
     img = pipe.pattern()
     ref = O.pattern(wl, O.prepare(wl, hkl=pipe.hkl.cpu().numpy()))
     got = img.cpu().numpy().astype(np.float64)
-    assert ref.max() > 0
-    r = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    big = ref > 1e-3 * ref.max()
-    px = float(np.max(np.abs(got[big] - ref[big]) / ref[big]))
-    say(f"  rel-L2 {r:.2e}, per-pixel {px:.2e}")
-    assert r <= 1e-4 and px <= 1e-3
+    if ref.max() == 0.0:
+        say("  no reflection reaches the detector: the image must be 0")
+        assert np.all(got == 0.0)
+    else:
+        r = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        big = ref > 1e-3 * ref.max()
+        px = float(np.max(np.abs(got[big] - ref[big]) / ref[big]))
+        say(f"  rel-L2 {r:.2e}, per-pixel {px:.2e}")
+        assert r <= 1e-4 and px <= 1e-3
     if fold:
         # at the unfolded launch's waves per tile (the library's choice depends on the tile count)
         fg = dataclasses.replace(g, mirror=fold, tile_waves=B.launch_waves(pipe.model.geom))
