@@ -121,7 +121,7 @@ __device__ __forceinline__ void walk_queue_adj(const float4* qn, const float2* q
     const float4 nd = q0[jj];
     const float ya = al[0] - nd.x, yb = al[1] - nd.y, yc = al[2] - nd.z;
     const float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
-    if (hose_band(mx, lo, hi) && hose_inside64(*qe, ec->rec, R, Z, ec->qk[jj]))
+    if (hose_band(mx, lo, hi) && hose_inside64_px(*qe, ec->rec, ec->qk[jj], R, Z))
       adj_term<LS>(ya, yb, yc, nd, d0[jj], hk, acc);
   }
 }

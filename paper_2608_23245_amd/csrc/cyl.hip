@@ -48,6 +48,55 @@ __device__ __forceinline__ void walk_ring(const float4* qn, int cnt, const float
   accr += part;
 }
 
+// walk_ring for the Hosemann lineshape with its support edge decided in binary64, in the two
+// passes of the pattern walks (profile_tile.h): the walk adds the (node, ring point) terms with
+// max|y_i| <= lo and marks the queue entries where some lane's ring point falls in the band
+// (lo, hi); the second pass decides those in binary64 at ring point jb + u of the lane's ring
+// (angle (jb + u) dphi from the reflection's azimuth), node index qk[jj].
+__device__ __forceinline__ void walk_ring_edge(const ProfParams& q, const float4* qn, const int* qk, int cnt,
+                                               const float (*al)[3], float lo, float hi, const HoseK& hk,
+                                               const float* rec, double R, double Z, int jb, double dphi,
+                                               float& accr) {
+  const float4* const q0 = qn;
+  qn += threadIdx.y;
+  float4 nxt = qn[0];
+  float part = 0.0f;
+  unsigned long long um = 0;
+  for (int jj = 0; jj < cnt; ++jj) {
+    const float4 cur = nxt;
+    nxt = qn[jj + 1];
+    unsigned long long band = 0;
+#pragma unroll
+    for (int u = 0; u < kJB; ++u) {
+      const float ya = al[u][0] - cur.x, yb = al[u][1] - cur.y, yc = al[u][2] - cur.z;
+      const float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
+      const bool sure = mx <= lo;
+      band |= __builtin_amdgcn_ballot_w64(mx < hi) & ~__builtin_amdgcn_ballot_w64(sure);
+      if (sure) part = fmaf(cur.w, hose_prod(ya, yb, yc, hk), part);
+    }
+    um = band ? um | (1ull << jj) : um;
+  }
+  accr += part;
+  float fix = 0.0f;
+  const double RD = *(const double*)(rec + RS_RD), dZ = Z - *(const double*)(rec + RS_ZD);
+  while (um) {  // uniform
+    const int jj = (int)__builtin_ctzll(um);
+    um &= um - 1;
+    const float4 nd = q0[jj];
+    const int k = qk[jj];
+#pragma unroll 1
+    for (int u = 0; u < kJB; ++u) {
+      const float ya = al[u][0] - nd.x, yb = al[u][1] - nd.y, yc = al[u][2] - nd.z;
+      const float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
+      if (hose_band(mx, lo, hi)) {
+        const double ph = (double)(jb + u) * dphi;
+        if (hose_inside64(q, rec, k, R * cos(ph) - RD, R * sin(ph), dZ)) fix = fmaf(nd.w, hose_prod(ya, yb, yc, hk), fix);
+      }
+    }
+  }
+  accr += fix;
+}
+
 // WAVES waves share a tile: per (tile, reflection), wave w takes the blocks w, w + WAVES, ...
 // of kJB ring indices (its own LDS queue), and wave 0 adds the others' pixel sums in wave
 // order at the end.
@@ -57,14 +106,19 @@ __global__ void __launch_bounds__(64 * WAVES) k_cyl(CylParams p, const float* __
                                                     const int64_t* __restrict__ offsets, const int32_t* __restrict__ idx,
                                                     float* __restrict__ image, unsigned long long* __restrict__ counts,
                                                     const int32_t* __restrict__ order) {
+  // the Hosemann support edge is decided in binary64 (walk_ring_edge): the queue then carries
+  // its node indices in qk
+  constexpr bool EDGE = LS == FDTBX_LINESHAPE_HOSEMANN && !COUNT;
   __shared__ float4 qn_all[128 * WAVES];
   __shared__ int bq_all[64 * WAVES];
   __shared__ float xacc[WAVES > 1 ? 64 * (WAVES - 1) : 1];
+  __shared__ int qk_all[EDGE ? 128 * WAVES : 1];
   const ProfParams& q = p.q;
   const int lane = threadIdx.x & 63;
   const int wv = WAVES > 1 ? (int)(threadIdx.x >> 6) : 0;
   float4* const qn = qn_all + 128 * wv;
   int* const bq = bq_all + 64 * wv;
+  int* const qk = qk_all + (EDGE ? 128 * wv : 0);
   const int t = order ? order[blockIdx.x] : tile_of_block(q, blockIdx.x);
   if (t < 0) return;  // uniform across the workgroup
   const int tx = t % q.tiles_x, ty = t / q.tiles_x;
@@ -138,6 +192,21 @@ __global__ void __launch_bounds__(64 * WAVES) k_cyl(CylParams p, const float* __
     if (J0 > J1) continue;
     HoseK hk = {};
     if (LS == FDTBX_LINESHAPE_HOSEMANN && !COUNT) hose_constants(rec, hk);
+    // the edge band (profile_tile.h) for y_i = T_R,i (R cos phi - R_D) + T_A,i R sin phi +
+    // T_Z,i (Z - Z_D) - kappa_i, with |R cos phi - R_D| <= R + |R_D| and |R sin phi| <= R
+    float elo = 0.0f, ehi = 0.0f;
+    if (EDGE) {
+      const float mX = wave_max(in ? (float)(R + fabs(RD)) : 0.0f), mY = wave_max(in ? (float)R : 0.0f);
+      const float mZ = wave_max(in ? (float)fabs(Z - ZD) : 0.0f);
+      float mag = 0.0f;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+        mag = fmaxf(mag, fabsf(tr[a]) * mX + fabsf(ta[a]) * mY + fabsf(tz[a]) * mZ + fabsf(Bv[a]) + fabsf(G1[a]) +
+                             fabsf(G2[a]));
+      const float band = fmaxf(1.0e-6f, mag * 0x1p-20f);
+      elo = q.half_m - band;
+      ehi = q.half_m + band;
+    }
     double cj = cos((double)(J0 + kJB * wv) * dphi), sj = sin((double)(J0 + kJB * wv) * dphi);
     const float fZ = (float)(Z - ZD), fz = (float)Z;
     float accp = 0.0f;
@@ -187,23 +256,33 @@ __global__ void __launch_bounds__(64 * WAVES) k_cyl(CylParams p, const float* __
       if (node_window_ranges(q, r0, sl, sh, l1, h1, l2, h2, rS, r1, r2, &w)) {
         float accr = 0.0f;
         int qlen = 0;  // uniform
-        scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int, float4 e) {
+        scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int k, float4 e) {
           const unsigned long long bal = __ballot(keep);
           if (keep) {
             const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
             qn[pos] = LS == FDTBX_LINESHAPE_LAUE ? tag_kappa4(e) : e;
+            if (EDGE) qk[pos] = k;
           }
           qlen += __popcll(bal);
           wave_sync();
           if (qlen >= 64) {
-            walk_ring<COUNT, LS>(qn, 64, al, q.half_m, hk, accr, cnt);
+            if (EDGE)
+              walk_ring_edge(q, qn, qk, 64, al, elo, ehi, hk, rec, R, Z, jb, dphi, accr);
+            else
+              walk_ring<COUNT, LS>(qn, 64, al, q.half_m, hk, accr, cnt);
             qlen -= 64;
             wave_sync();
-            if (lane < qlen) qn[lane] = qn[64 + lane];
+            if (lane < qlen) {
+              qn[lane] = qn[64 + lane];
+              if (EDGE) qk[lane] = qk[64 + lane];
+            }
             wave_sync();
           }
         });
-        walk_ring<COUNT, LS>(qn, qlen, al, q.half_m, hk, accr, cnt);
+        if (EDGE)
+          walk_ring_edge(q, qn, qk, qlen, al, elo, ehi, hk, rec, R, Z, jb, dphi, accr);
+        else
+          walk_ring<COUNT, LS>(qn, qlen, al, q.half_m, hk, accr, cnt);
         wave_sync();
         accp += accr;
       }

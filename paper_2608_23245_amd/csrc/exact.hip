@@ -403,13 +403,14 @@ __device__ static void profile_record(const PrepParams& p, const double* hh, con
     o[RS_TA + i] = (float)(sc[i] * dotv(&p.f.a[3 * i], az));
   }
   o[RS_F2] = (float)f2;
-  o[RS_K + 1] = o[RS_AH + 3] = o[FDTBX_REFL_FLOATS - 1] = 0.0f;  // the spare slots
   for (int i = 0; i < 3; ++i) o[RS_AH + i] = (float)AH[i];
   for (int i = 0; i < 3; ++i) {
     const double* ai = &p.f.a[3 * i];
     const double x[5] = {sc[i] * r0 * dotv(ai, S), sc[i] * r0 * dotv(ai, e1), sc[i] * r0 * dotv(ai, e2),
                          sc[i] * dotv(ai, ep), sc[i] * ai[2]};
     for (int c = 0; c < 5; ++c) o[RS_LO + 3 * c + i] = (float)(x[c] - (double)o[RS_B + 3 * c + i]);
+    const double az[3] = {-ep[1], ep[0], 0.0};
+    o[RS_LO_TA + i] = (float)(sc[i] * dotv(ai, az) - (double)o[RS_TA + i]);
   }
 }
 

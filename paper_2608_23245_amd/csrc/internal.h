@@ -178,13 +178,14 @@ enum ReflSlot {
   RS_F2 = 37,      // |F|^2
   RS_K = 38,       // r0^2 C with C the lineshape's constant (Laue prod N/(2 pi)^6, Gaussian
                    // prod N, Hosemann prod (1 - A'^2)), so that RS_WK = W * RS_K
+  RS_W = 39,       // |F|^2 I_para
   RS_AH = 40,      // Hosemann lineshape: A'_i = max(0, (N_i - 1)/(N_i + 1)) (40..42)
-  RS_W = 44,       // |F|^2 I_para
-  RS_N = 45,       // N_eff a, b, c (45..47)
-  RS_LO = 48,      // float32 residuals x - (float)x of the binary64 values x of B, G1, G2, TR, TZ
-                   // (48..62, that order): hi + lo holds x to 2^-48 relative, for the Hosemann
-                   // walk's support-edge decisions
-};  // slots 39, 43 and 63 are 0
+  RS_N = 43,       // N_eff a, b, c (43..45)
+  RS_LO = 46,      // float32 residuals x - (float)x of the binary64 values x of B, G1, G2, TR, TZ
+                   // (46..60, that order, as slots RS_B..RS_TZ) and of TA (61..63): hi + lo
+                   // holds x to 2^-48 relative, for the Hosemann support-edge decisions
+  RS_LO_TA = 61,
+};
 
 // Per-axis scale of the lattice offsets y_i in the record (y_i = scale_i a_i.(p - s)) and
 // the support half-width in y: N_i/2 and m/2 for the Laue and Gaussian lineshapes (the

@@ -124,14 +124,15 @@ __device__ __forceinline__ EdgeCtx edge_ctx(const float* __restrict__ rec, const
   return ec;
 }
 
-// Whether node k is inside the support (every |u_i| <= half_m) in binary64 at the pixel (R, Z).
-// The node's offsets are formed as the node table defines them, with c = 1/sqrt(1 + rho^2)
-// from the binary64 reciprocal square root (within a few units in the last place) and c - 1
-// formed directly: its absolute error, about 1e-16, is all that enters u.
-__device__ __forceinline__ bool hose_inside64(const ProfParams& q, const float* rec, double R, double Z, int k) {
-  // coefficient c of axis a (c = 0..4: B, G1, G2, TR, TZ) as hi + lo
+// Whether node k is inside the support (every |u_i| <= half_m) in binary64 at the query point
+// p = D + dR e_perp + dY e_az + dZ z (a pixel: dY = 0; a ring point of the cylindrical
+// average: dY = R sin(phi)).  The node's offsets are formed as the node table defines them, with
+// c = 1/sqrt(1 + rho^2) from the binary64 reciprocal square root (within a few units in the
+// last place) and c - 1 formed directly: its absolute error, about 1e-16, is all that enters u.
+__device__ __forceinline__ bool hose_inside64(const ProfParams& q, const float* rec, int k, double dR, double dY,
+                                              double dZ) {
+  // coefficient c of axis a (c = 0..4: B, G1, G2, TR, TZ) as hi + lo; TA likewise
   auto x64 = [&](int ca) { return (double)rec[RS_B + ca] + (double)rec[RS_LO + ca]; };
-  const double dR = R - *(const double*)(rec + RS_RD), dZ = Z - *(const double*)(rec + RS_ZD);
   int i1, i2;
   window_node(k, q.n, __builtin_amdgcn_rcpf((float)q.n), &i1, &i2);
   const double d1 = -q.T64 + ((double)i1 + 0.5) * q.h64, d2 = -q.T64 + ((double)i2 + 0.5) * q.h64;
@@ -141,10 +142,16 @@ __device__ __forceinline__ bool hose_inside64(const ProfParams& q, const float* 
 #pragma unroll 1
   for (int a = 0; a < 3; ++a) {
     const double kap = fma(x64(a), cm1, fma(x64(3 + a), cd1, x64(6 + a) * cd2));
-    const double al = fma(x64(9 + a), dR, x64(12 + a) * dZ);
+    const double ta = dY != 0.0 ? ((double)rec[RS_TA + a] + (double)rec[RS_LO_TA + a]) * dY : 0.0;
+    const double al = fma(x64(9 + a), dR, fma(x64(12 + a), dZ, ta));
     in = in && fabs(al - kap) <= (double)q.half_m;
   }
   return in;
+}
+
+// hose_inside64 at the pixel (R, Z).
+__device__ __forceinline__ bool hose_inside64_px(const ProfParams& q, const float* rec, int k, double R, double Z) {
+  return hose_inside64(q, rec, k, R - *(const double*)(rec + RS_RD), 0.0, Z - *(const double*)(rec + RS_ZD));
 }
 
 // The Hosemann profile product at offsets (ya, yb, yc), before the node weight, as eval_node
@@ -185,7 +192,7 @@ __device__ __forceinline__ void hose_edge_pass(const ProfParams& q, const float4
     const float4 nd = qn[jj];
     const float ya = al[0] - nd.x, yb = al[1] - nd.y, yc = al[2] - nd.z;
     const float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
-    if (hose_band(mx, ec.lo, ec.hi) && hose_inside64(q, ec.rec, R, Z, ec.qk[jj]))
+    if (hose_band(mx, ec.lo, ec.hi) && hose_inside64_px(q, ec.rec, ec.qk[jj], R, Z))
       part = fmaf(nd.w, hose_prod(ya, yb, yc, hk), part);
   }
   accr += part;

@@ -240,10 +240,9 @@ def test_reflection_records(name):
     P = O.prepare(wl, hkl=hkl, F=np.sqrt(F2.astype(np.float64)).astype(complex), cull_extinct=False)
     raw = refl.cpu().numpy()
     assert raw.shape[1] == 64
-    np.testing.assert_allclose(raw[:, 44].astype(np.float64), P.W, rtol=2e-6)
-    np.testing.assert_allclose(raw[:, 45:48].astype(np.float64), P.N, rtol=2e-6)
+    np.testing.assert_allclose(raw[:, 39].astype(np.float64), P.W, rtol=2e-6)
+    np.testing.assert_allclose(raw[:, 43:46].astype(np.float64), P.N, rtol=2e-6)
     np.testing.assert_allclose(raw[:, 0].astype(np.float64), P.r0, rtol=2e-7)
-    assert np.all(raw[:, [39, 43, 63]] == 0.0)
     # the two binary64 fields behind the kernels' cancellation-free offsets R - R_D and Z - Z_D
     # (record floats 18..19: D.e_perp, 20..21: D_z, each a little-endian float64), bit for bit:
     # D = h a* + k b* + l c* and e_perp (reading R6) in the oracle's operation order
@@ -255,20 +254,21 @@ def test_reflection_records(name):
 
 
 def check_offset_coefficients(raw, P, lineshape):
-    """The float32 residuals (record floats 48..62) of the offset coefficients B, G1, G2, T_R,
-    T_Z (floats 2..16): each is within half a float32 unit of its coefficient's last place (a
-    residual, not a second copy), float 63 is 0, and for the Hosemann lineshape (offsets
-    y_i = u_i = a_i.(p - s)) hi + lo is the oracle's r0 a_i.S, r0 a_i.e1, r0 a_i.e2, a_i.e_perp
-    and a_i,z to 2^-47 relative."""
-    hi = raw[:, 2:17].astype(np.float64)
-    lo = raw[:, 48:63].astype(np.float64)
-    assert np.all(np.abs(lo) <= 0.5 * np.spacing(np.abs(raw[:, 2:17])).astype(np.float64))
-    assert np.all(raw[:, 63] == 0.0)
+    """The float32 residuals (record floats 46..63) of the offset coefficients B, G1, G2, T_R,
+    T_Z (floats 2..16) and T_A (floats 34..36): each is within half a float32 unit of its
+    coefficient's last place (a residual, not a second copy), and for the Hosemann lineshape
+    (offsets y_i = u_i = a_i.(p - s)) hi + lo is the oracle's r0 a_i.S, r0 a_i.e1, r0 a_i.e2,
+    a_i.e_perp, a_i,z and a_i.e_az (e_az = z x e_perp) to 2^-47 relative."""
+    hi = np.concatenate([raw[:, 2:17], raw[:, 34:37]], axis=1)
+    lo = raw[:, 46:64].astype(np.float64)
+    assert np.all(np.abs(lo) <= 0.5 * np.spacing(np.abs(hi)).astype(np.float64))
+    hi = hi.astype(np.float64)
     if lineshape != 2:
         return
     a = P.avec
+    eaz = np.stack([-P.ep[:, 1], P.ep[:, 0], np.zeros_like(P.r0)], axis=1)
     want = np.concatenate([P.r0[:, None] * (P.S @ a.T), P.r0[:, None] * (P.e1 @ a.T), P.r0[:, None] * (P.e2 @ a.T),
-                           P.ep @ a.T, np.broadcast_to(a[:, 2], (P.r0.shape[0], 3))], axis=1)
+                           P.ep @ a.T, np.broadcast_to(a[:, 2], (P.r0.shape[0], 3)), eaz @ a.T], axis=1)
     scale = np.abs(want).max(axis=1, keepdims=True)
     err = np.abs(hi + lo - want)
     assert np.all(err <= 2.0 ** -47 * scale), float((err / scale).max())
