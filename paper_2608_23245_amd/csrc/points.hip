@@ -23,6 +23,8 @@ struct PointParams {
 // out[k] = W_h r0^2 sum_nodes omega Z(p_k - s_node) for reflection h = ridx[k] (the term of
 // reflection h in the pattern's sum at p_k, before the Lorentz factor).  The lattice
 // offsets alpha_i = scale_i a_i.(p - D) are formed in binary64 from the reflection's frame.
+// For the Hosemann lineshape a node within the edge band of its support (profile_tile.h) is
+// decided in binary64 from those offsets (hose_inside64_al).
 template <int LS>
 __global__ void __launch_bounds__(256) k_profile_points(PointParams p, const int32_t* __restrict__ hkl,
                                                         const float* __restrict__ refl, const float* __restrict__ nodes,
@@ -39,9 +41,11 @@ __global__ void __launch_bounds__(256) k_profile_points(PointParams p, const int
   const double P[3] = {pts[3 * k + 0], pts[3 * k + 1], pts[3 * k + 2]};
   const double x[3] = {P[0] - F.D[0], P[1] - F.D[1], P[2] - F.D[2]};
   float al[3], Bv[3], G1[3], G2[3];
+  double al64[3];
   for (int i = 0; i < 3; ++i) {
     const double sc = LS == FDTBX_LINESHAPE_HOSEMANN ? 1.0 : 0.5 * (double)rec[RS_N + i];
-    al[i] = (float)(sc * dotv(&p.f.a[3 * i], x));
+    al64[i] = sc * dotv(&p.f.a[3 * i], x);
+    al[i] = (float)al64[i];
     if (LS == FDTBX_LINESHAPE_LAUE) al[i] = tag_alpha(al[i]);
     Bv[i] = rec[RS_B + i];
     G1[i] = rec[RS_G1 + i];
@@ -54,7 +58,15 @@ __global__ void __launch_bounds__(256) k_profile_points(PointParams p, const int
     return;
   }
   HoseK hk = {};
-  if (LS == FDTBX_LINESHAPE_HOSEMANN) hose_constants(rec, hk);
+  float elo = 0.0f, ehi = 0.0f;  // the Hosemann edge band's bounds on max|y_i|
+  if (LS == FDTBX_LINESHAPE_HOSEMANN) {
+    hose_constants(rec, hk);
+    float mag = 0.0f;
+    for (int i = 0; i < 3; ++i) mag = fmaxf(mag, fabsf(al[i]) + fabsf(Bv[i]) + fabsf(G1[i]) + fabsf(G2[i]));
+    const float band = fmaxf(1.0e-6f, mag * 0x1p-20f);
+    elo = q.half_m - band;
+    ehi = q.half_m + band;
+  }
   float acc = 0.0f;
   unsigned long long cnt = 0;
   for (int i2 = w.i2lo; i2 <= w.i2hi; ++i2) {
@@ -66,7 +78,14 @@ __global__ void __launch_bounds__(256) k_profile_points(PointParams p, const int
       e.z = fmaf(nd.x, Bv[2], fmaf(nd.y, G1[2], nd.z * G2[2]));
       e.w = nd.w;
       if (LS == FDTBX_LINESHAPE_LAUE) e = tag_kappa4(e);
-      eval_node<false, LS>(e, al[0], al[1], al[2], q.half_m, hk, acc, cnt);
+      if (LS == FDTBX_LINESHAPE_HOSEMANN) {
+        const float ya = al[0] - e.x, yb = al[1] - e.y, yc = al[2] - e.z;
+        const float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
+        if (mx <= elo || (hose_band(mx, elo, ehi) && hose_inside64_al(q, rec, i2 * q.n + i1, al64)))
+          acc = fmaf(e.w, hose_prod(ya, yb, yc, hk), acc);
+      } else {
+        eval_node<false, LS>(e, al[0], al[1], al[2], q.half_m, hk, acc, cnt);
+      }
     }
   }
   out[k] = rec[RS_WK] * acc;

@@ -67,12 +67,46 @@ __device__ static inline void splat_pixels(const SplatParams& p, const double* S
 }
 
 
+// walk_queue for the Hosemann lineshape with its support edge decided in binary64, in the two
+// passes of the pattern walks (profile_tile.h): the walk adds the nodes with max|y_i| <= lo and
+// marks the queue entries where some lane's sample falls in the band (lo, hi); the second pass
+// decides those from the sample's binary64 lattice offsets al64, node index qk[jj].
+__device__ __forceinline__ void walk_queue_edge_al(const ProfParams& q, const float4* qn, const int* qk, int cnt,
+                                                   const float* al, float lo, float hi, const HoseK& hk,
+                                                   const float* rec, const double* al64, float& accr) {
+  const float4* const q0 = qn;
+  qn += threadIdx.y;
+  float4 nxt = qn[0];
+  float part = 0.0f;
+  unsigned long long um = 0;
+  for (int jj = 0; jj < cnt; ++jj) {
+    const float4 cur = nxt;
+    nxt = qn[jj + 1];
+    eval_node_hose_main(cur, al, lo, hi, hk, part, jj, um);
+  }
+  accr += part;
+  float fix = 0.0f;
+  while (um) {  // uniform
+    const int jj = (int)__builtin_ctzll(um);
+    um &= um - 1;
+    const float4 nd = q0[jj];
+    const float ya = al[0] - nd.x, yb = al[1] - nd.y, yc = al[2] - nd.z;
+    const float mx = fmaxf(fmaxf(fabsf(ya), fabsf(yb)), fabsf(yc));
+    if (hose_band(mx, lo, hi) && hose_inside64_al(q, rec, qk[jj], al64)) fix = fmaf(nd.w, hose_prod(ya, yb, yc, hk), fix);
+  }
+  accr += fix;
+}
+
 template <bool COUNT, int LS>
 __global__ void __launch_bounds__(64) k_splat(SplatParams p, const int32_t* __restrict__ hkl, const float* __restrict__ refl,
                                               const float* __restrict__ nodes, float* __restrict__ image,
                                               unsigned long long* __restrict__ counts) {
+  // the Hosemann support edge is decided in binary64 (walk_queue_edge_al): the queue then
+  // carries its node indices in qk
+  constexpr bool EDGE = LS == FDTBX_LINESHAPE_HOSEMANN && !COUNT;
   __shared__ float4 qn[128];
   __shared__ int bq[64];
+  __shared__ int qk[EDGE ? 128 : 1];
   const int lane = threadIdx.x & 63;
   const int64_t h = (int64_t)blockIdx.x / p.n_r;
   const int a = (int)((int64_t)blockIdx.x % p.n_r);
@@ -118,6 +152,21 @@ __global__ void __launch_bounds__(64) k_splat(SplatParams p, const int32_t* __re
     // lattice offsets of the sample relative to D, and its coordinates along S0, e1, e2
     const double X[3] = {S[0] - F.D[0], S[1] - F.D[1], S[2] - F.D[2]};
     float al[3], lo[3], hi[3];
+    // the Hosemann lattice offsets in binary64 (scale 1) and the edge band (profile_tile.h):
+    // the float32 y_i rounds al64_i once and forms kappa_i as the pattern walks do
+    double al64[3] = {0.0, 0.0, 0.0};
+    float elo = 0.0f, ehi = 0.0f;
+    if (EDGE) {
+      float mag = 0.0f;
+#pragma unroll
+      for (int i = 0; i < 3; ++i) {
+        al64[i] = dotv(&p.f.a[3 * i], X);
+        mag = fmaxf(mag, wave_max(in ? fabsf((float)al64[i]) : 0.0f) + fabsf(Bv[i]) + fabsf(G1[i]) + fabsf(G2[i]));
+      }
+      const float band = fmaxf(1.0e-6f, mag * 0x1p-20f);
+      elo = q.half_m - band;
+      ehi = q.half_m + band;
+    }
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
       al[i] = in ? (float)dotv(&p.f.a[3 * i], X) * sc[i] : 1.0e30f;
@@ -134,23 +183,33 @@ __global__ void __launch_bounds__(64) k_splat(SplatParams p, const int32_t* __re
     if (node_window_ranges(q, f.at(RS_R0), sl, sh, l1, h1, l2, h2, f.at(RS_RHO), f.at(RS_RHO + 1), f.at(RS_RHO + 2),
                            &w)) {
       int qlen = 0;  // uniform
-      scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int, float4 e) {
+      scan_window(q, nodes, w, Bv, G1, G2, lo, hi, bq, [&](bool keep, int k, float4 e) {
         const unsigned long long bal = __ballot(keep);
         if (keep) {
           const int pos = qlen + (int)__builtin_amdgcn_mbcnt_hi((unsigned)(bal >> 32), __builtin_amdgcn_mbcnt_lo((unsigned)bal, 0u));
           qn[pos] = LS == FDTBX_LINESHAPE_LAUE ? tag_kappa4(e) : e;
+          if (EDGE) qk[pos] = k;
         }
         qlen += __popcll(bal);
         wave_sync();
         if (qlen >= 64) {
-          walk_queue<COUNT, LS>(qn, 64, al, q.half_m, hk, accr, cnt);
+          if (EDGE)
+            walk_queue_edge_al(q, qn, qk, 64, al, elo, ehi, hk, rec, al64, accr);
+          else
+            walk_queue<COUNT, LS>(qn, 64, al, q.half_m, hk, accr, cnt);
           qlen -= 64;
           wave_sync();
-          if (lane < qlen) qn[lane] = qn[64 + lane];
+          if (lane < qlen) {
+            qn[lane] = qn[64 + lane];
+            if (EDGE) qk[lane] = qk[64 + lane];
+          }
           wave_sync();
         }
       });
-      walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, hk, accr, cnt);
+      if (EDGE)
+        walk_queue_edge_al(q, qn, qk, qlen, al, elo, ehi, hk, rec, al64, accr);
+      else
+        walk_queue<COUNT, LS>(qn, qlen, al, q.half_m, hk, accr, cnt);
       wave_sync();
     }
     if (!COUNT && in && accr != 0.0f) {

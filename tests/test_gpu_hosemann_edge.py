@@ -115,3 +115,17 @@ def test_hosemann_support_edge_cylindrical_average():
     ref, n_ref = O.cyl_at(P, R, Z, arc, count=True)
     C.check(img, ref.reshape(img.shape), "cylindrical average, seed 315")
     assert abs(cnt - n_ref) <= 1e-4 * n_ref + 2
+
+
+def test_hosemann_forward_splat():
+    """The forward splat decides the support edge at its samples from their binary64 lattice
+    offsets (seed 740 of the generator, a Hosemann workload, against the oracle's splat)."""
+    import test_gpu_splat as S
+    wl, _ = random_case(740)
+    assert wl.dis.lineshape == 2
+    hkl = O.enumerate_hkl(wl.cell, wl.quad.d_min, wl.quad.d_max)
+    hkl = np.ascontiguousarray(hkl[~O.extinct_mask(hkl, wl.dis, wl.quad.extinction)])
+    say("Hosemann forward splat, seed 740, n_r 4, n_s 16")
+    img, _, F = S.gpu_splat(wl, hkl, 4, 16)
+    ref = O.splat(wl, O.prepare(wl, hkl=hkl, F=F, cull_extinct=False), 4, 16)
+    S.check(img, ref, "forward splat, seed 740")
