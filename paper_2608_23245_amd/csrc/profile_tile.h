@@ -124,12 +124,14 @@ __device__ __forceinline__ EdgeCtx edge_ctx(const float* __restrict__ rec, const
   return ec;
 }
 
-// Whether node k is inside the support (every |u_i| <= half_m) in binary64 for the query
-// point's binary64 lattice offsets al64_i = scale_i a_i.(p - D).  The node's offsets are formed
-// as the node table defines them, with c = 1/sqrt(1 + rho^2) from the binary64 reciprocal
-// square root (within a few units in the last place) and c - 1 formed directly: its absolute
-// error, about 1e-16, is all that enters u.
-__device__ __forceinline__ bool hose_inside64_al(const ProfParams& q, const float* rec, int k, const double* al64) {
+// Whether node k is inside the support (every |u_i| <= half_m) in binary64, for the query
+// point's binary64 lattice offsets al_of(i) = scale_i a_i.(p - D) (formed axis by axis, inside
+// the loop, which keeps this rare path's registers few).  The node's offsets are formed as the
+// node table defines them, with c = 1/sqrt(1 + rho^2) from the binary64 reciprocal square root
+// (within a few units in the last place) and c - 1 formed directly: its absolute error, about
+// 1e-16, is all that enters u.
+template <class AlOf>
+__device__ __forceinline__ bool hose_inside64_f(const ProfParams& q, const float* rec, int k, AlOf&& al_of) {
   // coefficient c of axis a (c = 0..2: B, G1, G2) as hi + lo
   auto x64 = [&](int ca) { return (double)rec[RS_B + ca] + (double)rec[RS_LO + ca]; };
   int i1, i2;
@@ -141,23 +143,26 @@ __device__ __forceinline__ bool hose_inside64_al(const ProfParams& q, const floa
 #pragma unroll 1
   for (int a = 0; a < 3; ++a) {
     const double kap = fma(x64(a), cm1, fma(x64(3 + a), cd1, x64(6 + a) * cd2));
-    in = in && fabs(al64[a] - kap) <= (double)q.half_m;
+    in = in && fabs(al_of(a) - kap) <= (double)q.half_m;
   }
   return in;
 }
 
-// hose_inside64_al at the query point p = D + dR e_perp + dY e_az + dZ z (a pixel: dY = 0; a
+// hose_inside64_f for offsets already formed in binary64 (the splat's samples, the points).
+__device__ __forceinline__ bool hose_inside64_al(const ProfParams& q, const float* rec, int k, const double* al64) {
+  return hose_inside64_f(q, rec, k, [&](int a) { return al64[a]; });
+}
+
+// hose_inside64_f at the query point p = D + dR e_perp + dY e_az + dZ z (a pixel: dY = 0; a
 // ring point of the cylindrical average: dY = R sin(phi)), its offsets from the record's
 // T_R, T_A, T_Z as hi + lo.
 __device__ __forceinline__ bool hose_inside64(const ProfParams& q, const float* rec, int k, double dR, double dY,
                                               double dZ) {
   auto x64 = [&](int slot, int lo) { return (double)rec[slot] + (double)rec[lo]; };
-  double al64[3];
-  for (int a = 0; a < 3; ++a) {
+  return hose_inside64_f(q, rec, k, [&](int a) {
     const double ta = dY != 0.0 ? x64(RS_TA + a, RS_LO_TA + a) * dY : 0.0;
-    al64[a] = fma(x64(RS_TR + a, RS_LO + 9 + a), dR, fma(x64(RS_TZ + a, RS_LO + 12 + a), dZ, ta));
-  }
-  return hose_inside64_al(q, rec, k, al64);
+    return fma(x64(RS_TR + a, RS_LO + 9 + a), dR, fma(x64(RS_TZ + a, RS_LO + 12 + a), dZ, ta));
+  });
 }
 
 // hose_inside64 at the pixel (R, Z).
